@@ -1,0 +1,153 @@
+"""CPU oracle for N-body phase-space generation and integration (test infrastructure).
+
+This package is the plain, slow, single-threaded FP64 implementation that the HIP
+library is checked against (arXiv:1711.05683 sec. 4.2, Raubold-Lynch method; the
+conventions are documented at the top of ``phsp_oracle.c``).  Only the test suite,
+the smoke check and the benchmark's CPU-baseline leg may import it.  It shares no
+code with the product library: the C source is compiled here with gcc
+(``-O2 -ffp-contract=off``, no fast-math) into ``_liboracle.so`` and called via ctypes.
+
+Parity status: every function here is pinned by the ``-m "not gpu"`` tests against
+rocRAND's Philox4x32-10 (independent implementation), closed-form and quadrature
+phase-space volumes, exact two-body kinematics, per-event conservation laws and
+Dalitz-plot flatness.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "phsp_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_liboracle.so")
+_CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared"]
+
+NMAX = 10
+OK, EINVAL, EKINEMATICS = 0, -1, -2
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``_liboracle.so`` (always, when force)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", *_CFLAGS, "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    dp = ctypes.c_void_p
+    lib.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_uniforms_per_event.argtypes = [ctypes.c_int]
+    lib.oracle_uniforms_per_event.restype = ctypes.c_int
+    lib.oracle_event_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                          ctypes.c_int, dp]
+    lib.oracle_event_uniforms.restype = None
+    lib.oracle_weight_constant.argtypes = [ctypes.c_double, dp, ctypes.c_int]
+    lib.oracle_weight_constant.restype = ctypes.c_double
+    lib.oracle_generate.argtypes = [ctypes.c_double, dp, ctypes.c_int, dp, dp, ctypes.c_uint64,
+                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                    ctypes.c_uint64, dp, ctypes.c_uint64, dp]
+    lib.oracle_generate.restype = ctypes.c_int
+    lib.oracle_integrate.argtypes = [ctypes.c_double, dp, ctypes.c_int, ctypes.c_uint64,
+                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                     ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.oracle_integrate.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _masses(masses):
+    m = np.ascontiguousarray(np.asarray(masses, dtype=np.float64))
+    return m
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status):
+        super().__init__(f"oracle status {status}")
+        self.status = status
+
+
+def philox4x32_10(ctr, key):
+    """One Philox4x32-10 block: four 32-bit words for a 4-word counter and 2-word key."""
+    lib = _load()
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib.oracle_philox4x32_10(c, k, o)
+    return [int(o[i]) for i in range(4)]
+
+
+def uniforms_per_event(n: int) -> int:
+    return _load().oracle_uniforms_per_event(n)
+
+
+def event_uniforms(seed: int, stream_id: int, g: int, n: int) -> np.ndarray:
+    """The 3N-4 uniforms of global event g, in consumption order."""
+    u = np.zeros(3 * n - 4, dtype=np.float64)
+    _load().oracle_event_uniforms(seed, stream_id, g, n, _ptr(u))
+    return u
+
+
+def weight_constant(parent_mass: float, masses) -> float:
+    m = _masses(masses)
+    return _load().oracle_weight_constant(parent_mass, _ptr(m), len(m))
+
+
+def generate(parent_mass, masses, nevents, seed=42, stream_id=0, event_offset=0,
+             parent_p4=None, parent_soa=None, want_momenta=True):
+    """Return (p4, weights): p4 has shape [N, 4, nevents] (SoA), weights [nevents]."""
+    lib = _load()
+    m = _masses(masses)
+    n = len(m)
+    out = np.zeros((n, 4, nevents), dtype=np.float64) if want_momenta else None
+    w = np.zeros(nevents, dtype=np.float64)
+    pp = None if parent_p4 is None else np.ascontiguousarray(parent_p4, dtype=np.float64)
+    ps = None if parent_soa is None else np.ascontiguousarray(parent_soa, dtype=np.float64)
+    ldp = 0 if ps is None else ps.shape[1]
+    st = lib.oracle_generate(parent_mass, _ptr(m), n, _ptr(pp), _ptr(ps), ldp, nevents, seed,
+                             stream_id, event_offset, _ptr(out), nevents, _ptr(w))
+    if st != OK:
+        raise OracleError(st)
+    return out, w
+
+
+def generate_status(parent_mass, masses, nevents=1):
+    """Status code of a generate call (argument and kinematic validation only)."""
+    lib = _load()
+    m = _masses(masses)
+    w = np.zeros(max(nevents, 1), dtype=np.float64)
+    return lib.oracle_generate(parent_mass, _ptr(m), len(m), None, None, 0, nevents, 1, 0, 0,
+                               None, 0, _ptr(w))
+
+
+def integrate(parent_mass, masses, nevents, seed=42, stream_id=0, event_offset=0):
+    """Return (mean, sigma): Monte Carlo estimate of the N-body volume and its error."""
+    lib = _load()
+    m = _masses(masses)
+    mean = ctypes.c_double()
+    sigma = ctypes.c_double()
+    st = lib.oracle_integrate(parent_mass, _ptr(m), len(m), nevents, seed, stream_id,
+                              event_offset, ctypes.byref(mean), ctypes.byref(sigma))
+    if st != OK:
+        raise OracleError(st)
+    return mean.value, sigma.value

@@ -1,0 +1,335 @@
+/*
+ * phsp_oracle.c -- plain, slow, single-threaded FP64 CPU oracle for N-body
+ * phase-space Monte Carlo generation and integration (Raubold-Lynch method,
+ * arXiv:1711.05683 sec. 4.2 "Phase-Space Monte Carlo").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant generator with the HIP library; the two sides meet
+ * only through seeded inputs and the counter-based generator each implements
+ * from its published definition.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math), so that every
+ * operation below is one IEEE-754 round-to-nearest double operation, evaluated
+ * in the order written.
+ *
+ * What the paper fixes and what is a reading of it
+ * ------------------------------------------------
+ * Sec. 4.2 states the problem (a particle of given four-momentum decaying to an
+ * n-body final state with no intermediate resonances), names the method
+ * (Raubold-Lynch, after F. James, CERN 68-15), says any number of daughters is
+ * supported and that weighted samples are produced.  Listing "lst:phsp" shows
+ * the interface: parent mass and daughter masses at construction, a parent
+ * four-vector Vector4R(mass,0,0,0) (energy first) at generation time, and a
+ * caller-allocated event container.  Everything else -- random-number
+ * generator, uniform conversion, recursion order, angle convention, weight
+ * normalisation -- is silent in the paper; this file follows the readings
+ * listed in the design notes, summarised at each step:
+ *
+ *  - phase-space measure: prod_i d^3p_i/(2E_i) delta^4(P - sum p_i), no 2*pi
+ *    factors, so the two-body volume is pi*p/M and the mean weight is the
+ *    N-body volume R_N (recursive factorisation of Lorentz-invariant phase
+ *    space, the basis of the Raubold-Lynch method);
+ *  - random words: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
+ *    Random Numbers: As Easy as 1, 2, 3", SC'11), key = 64-bit seed,
+ *    counter = (low 32 bits of g, high 32 bits of g, call index j, stream id),
+ *    g = event_offset + local event index;
+ *  - uniform k from words 2k, 2k+1: 52 bits x, u = (2x+1) 2^-53 in (0,1);
+ *  - the first N-2 uniforms are the mass uniforms; then (theta, phi) pairs for
+ *    levels 0..N-2;
+ *  - daughter 0 is innermost; each level adds the next daughter and boosts the
+ *    earlier ones (bottom-up boost chain).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_NMAX 10
+/* pi to double precision (the double nearest pi) */
+static const double ORACLE_PI = 3.141592653589793;
+
+/* ---------------------------------------------------------------------- */
+/* Philox4x32-10 (SC'11 paper, section 3.2 "Philox"): 10 rounds of a       */
+/* two-multiplier S-box/P-box on a 4x32-bit counter, 2x32-bit key bumped   */
+/* by the Weyl constants between rounds.                                   */
+/* ---------------------------------------------------------------------- */
+static const uint32_t PHILOX_M0 = 0xD2511F53u; /* multiplier applied to word 0 */
+static const uint32_t PHILOX_M1 = 0xCD9E8D57u; /* multiplier applied to word 2 */
+static const uint32_t PHILOX_W0 = 0x9E3779B9u; /* key bump, word 0 (golden ratio) */
+static const uint32_t PHILOX_W1 = 0xBB67AE85u; /* key bump, word 1 (sqrt(3)-1) */
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t prod0 = (uint64_t)PHILOX_M0 * (uint64_t)x0;
+        uint64_t prod1 = (uint64_t)PHILOX_M1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Number of random uniforms one event consumes: N-2 mass uniforms plus a
+ * (theta, phi) pair for each of the N-1 two-body levels. */
+int oracle_uniforms_per_event(int n)
+{
+    return 3 * n - 4;
+}
+
+/* Uniforms of global event g: u[k] for k = 0 .. 3N-5.  Each uniform takes two
+ * consecutive 32-bit words (low word first) of the event's Philox stream; the
+ * stream is call j = 0, 1, ... of the counter (g_lo, g_hi, j, stream_id). */
+void oracle_event_uniforms(uint64_t seed, uint32_t stream_id, uint64_t g, int n, double *u)
+{
+    const int nu = oracle_uniforms_per_event(n);
+    const int nwords = 2 * nu;
+    uint32_t words[4 * ((2 * (3 * ORACLE_NMAX - 4) + 3) / 4)];
+    const uint32_t key[2] = { (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32) };
+    for (int j = 0; 4 * j < nwords; ++j) {
+        const uint32_t ctr[4] = { (uint32_t)(g & 0xFFFFFFFFu), (uint32_t)(g >> 32),
+                                  (uint32_t)j, stream_id };
+        oracle_philox4x32_10(ctr, key, &words[4 * j]);
+    }
+    for (int k = 0; k < nu; ++k) {
+        uint64_t bits = ((uint64_t)words[2 * k + 1] << 32) | (uint64_t)words[2 * k];
+        uint64_t x = bits >> 12;                     /* 52 bits */
+        u[k] = (double)(2 * x + 1) * 0x1p-53;        /* exact, in [2^-53, 1-2^-53] */
+    }
+}
+
+/* Normalisation of the weight.  Unrolling the recursion
+ *   R_N(M) = int d(sigma^2) R_2(M; sigma, m_{N-1}) R_{N-1}(sigma; m_0..m_{N-2}),
+ *   R_2(a; b, c) = pi p(a; b, c) / a,
+ * and substituting sigma_i = S_i + T R_i (sorted R on the unit simplex of
+ * volume 1/(N-2)!) leaves
+ *   R_N = pi^{N-1} (2T)^{N-2} / (M (N-2)!) * E[ prod_i p_i ].
+ * The factors are multiplied in the order written in this comment. */
+double oracle_weight_constant(double parent_mass, const double *masses, int n)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += masses[i];
+    const double t = parent_mass - s;
+    double c = 1.0 / parent_mass;
+    for (int i = 0; i < n - 1; ++i) c = c * ORACLE_PI;
+    for (int i = 0; i < n - 2; ++i) c = c * (2.0 * t);
+    double fact = 1.0;
+    for (int i = 2; i <= n - 2; ++i) fact = fact * (double)i;
+    return c / fact;
+}
+
+/* Ascending sort of a handful of doubles (insertion sort: obviously correct). */
+static void sort_ascending(double *a, int n)
+{
+    for (int i = 1; i < n; ++i) {
+        double v = a[i];
+        int j = i - 1;
+        while (j >= 0 && a[j] > v) {
+            a[j + 1] = a[j];
+            --j;
+        }
+        a[j + 1] = v;
+    }
+}
+
+/* Pure Lorentz boost of the four-vector v = (E, px, py, pz) by rapidity vector
+ * eta = gamma*beta: E' = gamma E + eta.p,  p' = p + (eta.p/(gamma+1) + E) eta. */
+static void boost(double v[4], const double eta[3], double gamma)
+{
+    const double e = v[0];
+    const double ep = eta[0] * v[1] + eta[1] * v[2] + eta[2] * v[3];
+    const double f = ep / (gamma + 1.0) + e;
+    v[0] = gamma * e + ep;
+    v[1] = v[1] + f * eta[0];
+    v[2] = v[2] + f * eta[1];
+    v[3] = v[3] + f * eta[2];
+}
+
+/* Isotropic unit vector from two uniforms: cos(theta) = 2u - 1,
+ * sin(theta) = 2 sqrt(u (1-u)), phi = 2 pi v. */
+static void direction(double u, double v, double nhat[3])
+{
+    const double ct = 2.0 * u - 1.0;
+    const double st = 2.0 * sqrt(u * (1.0 - u));
+    const double phi = 6.283185307179586 * v;
+    nhat[0] = st * cos(phi);
+    nhat[1] = st * sin(phi);
+    nhat[2] = ct;
+}
+
+/* One event.  p4[d][mu] receives daughter d's (E, px, py, pz) in the frame of
+ * the parent given by (parent4 == NULL: at rest; else the parent's four-vector,
+ * boosted with eta = P/M, gamma = E_P/M); the return value is the weight. */
+static double one_event(double parent_mass, const double *masses, int n,
+                        const double *parent4, const double *u, double p4[][4])
+{
+    double prefix[ORACLE_NMAX];                  /* S_i = m_0 + ... + m_i */
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+        s += masses[i];
+        prefix[i] = s;
+    }
+    const double t = parent_mass - s;            /* kinetic energy released */
+
+    /* Sorted mass uniforms R_0 = 0 < R_1 <= ... <= R_{N-2} < R_{N-1} = 1. */
+    double r[ORACLE_NMAX];
+    r[0] = 0.0;
+    for (int i = 0; i < n - 2; ++i) r[i + 1] = u[i];
+    sort_ascending(&r[1], n - 2);
+    r[n - 1] = 1.0;
+
+    /* Invariant masses of the subsystems {0..i}. */
+    double sigma[ORACLE_NMAX];
+    sigma[0] = masses[0];
+    for (int i = 1; i <= n - 2; ++i) sigma[i] = prefix[i] + t * r[i];
+    sigma[n - 1] = parent_mass;
+
+    /* Two-body breakup momentum of sigma_{i+1} -> sigma_i + m_{i+1}, with the
+     * released energy g_i = sigma_{i+1} - sigma_i - m_{i+1} = T (R_{i+1} - R_i). */
+    double p[ORACLE_NMAX];
+    for (int i = 0; i <= n - 2; ++i) {
+        const double gi = t * (r[i + 1] - r[i]);
+        const double b = sigma[i], c = masses[i + 1];
+        const double q = gi * (2.0 * b + 2.0 * c + gi) * (gi + 2.0 * c) * (2.0 * b + gi);
+        p[i] = sqrt(q) / (2.0 * sigma[i + 1]);
+    }
+
+    double w = oracle_weight_constant(parent_mass, masses, n);
+    for (int i = 0; i <= n - 2; ++i) w = w * p[i];
+
+    /* Level 0: daughters 0 and 1 back to back in the rest frame of {0,1}. */
+    double nhat[3];
+    direction(u[n - 2], u[n - 1], nhat);
+    p4[1][0] = sqrt(p[0] * p[0] + masses[1] * masses[1]);
+    p4[0][0] = sqrt(p[0] * p[0] + masses[0] * masses[0]);
+    for (int k = 0; k < 3; ++k) {
+        p4[1][k + 1] = p[0] * nhat[k];
+        p4[0][k + 1] = -(p[0] * nhat[k]);
+    }
+    /* Levels 1..N-2: daughter i+1 recoils against {0..i}, which is then
+     * boosted from its own rest frame into the rest frame of {0..i+1}. */
+    for (int i = 1; i <= n - 2; ++i) {
+        direction(u[n - 2 + 2 * i], u[n - 1 + 2 * i], nhat);
+        p4[i + 1][0] = sqrt(p[i] * p[i] + masses[i + 1] * masses[i + 1]);
+        for (int k = 0; k < 3; ++k) p4[i + 1][k + 1] = p[i] * nhat[k];
+        const double gamma = sqrt(p[i] * p[i] + sigma[i] * sigma[i]) / sigma[i];
+        double eta[3];
+        for (int k = 0; k < 3; ++k) eta[k] = -(p[i] / sigma[i]) * nhat[k];
+        for (int d = 0; d <= i; ++d) boost(p4[d], eta, gamma);
+    }
+
+    if (parent4 != NULL) {
+        const double gamma = parent4[0] / parent_mass;
+        const double eta[3] = { parent4[1] / parent_mass, parent4[2] / parent_mass,
+                                parent4[3] / parent_mass };
+        for (int d = 0; d < n; ++d) boost(p4[d], eta, gamma);
+    }
+    return w;
+}
+
+/* Return codes shared in meaning (not in code) with the product library. */
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+#define ORACLE_EKINEMATICS (-2)
+
+static int check_args(double parent_mass, const double *masses, int n)
+{
+    if (n < 2 || n > ORACLE_NMAX || masses == NULL) return ORACLE_EINVAL;
+    if (!(parent_mass > 0.0) || !isfinite(parent_mass)) return ORACLE_EINVAL;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!(masses[i] >= 0.0) || !isfinite(masses[i])) return ORACLE_EINVAL;
+        s += masses[i];
+    }
+    if (!(parent_mass - s > 0.0)) return ORACLE_EKINEMATICS;
+    return ORACLE_OK;
+}
+
+/* Generate events e = 0..nevents-1 (global index event_offset + e).
+ *   parent_p4     NULL, or one (E, px, py, pz) applied to every event;
+ *   parent_soa    NULL, or per-event parents, component mu of event e at
+ *                 parent_soa[mu * ld_parent + e];
+ *   out           NULL, or SoA: component mu of daughter d of event e at
+ *                 out[(4 d + mu) * ld + e];
+ *   weights       NULL, or weights[e]. */
+int oracle_generate(double parent_mass, const double *masses, int n,
+                    const double *parent_p4, const double *parent_soa, uint64_t ld_parent,
+                    uint64_t nevents, uint64_t seed, uint32_t stream_id, uint64_t event_offset,
+                    double *out, uint64_t ld, double *weights)
+{
+    int st = check_args(parent_mass, masses, n);
+    if (st != ORACLE_OK) return st;
+    if (out != NULL && ld < nevents) return ORACLE_EINVAL;
+    if (parent_soa != NULL && ld_parent < nevents) return ORACLE_EINVAL;
+    double u[3 * ORACLE_NMAX];
+    double p4[ORACLE_NMAX][4];
+    for (uint64_t e = 0; e < nevents; ++e) {
+        oracle_event_uniforms(seed, stream_id, event_offset + e, n, u);
+        double parent[4];
+        const double *pp = parent_p4;
+        if (parent_soa != NULL) {
+            for (int mu = 0; mu < 4; ++mu) parent[mu] = parent_soa[mu * ld_parent + e];
+            pp = parent;
+        }
+        const double w = one_event(parent_mass, masses, n, pp, u, p4);
+        if (weights != NULL) weights[e] = w;
+        if (out != NULL)
+            for (int d = 0; d < n; ++d)
+                for (int mu = 0; mu < 4; ++mu) out[(uint64_t)(4 * d + mu) * ld + e] = p4[d][mu];
+    }
+    return ORACLE_OK;
+}
+
+/* Neumaier's compensated summation (improved Kahan-Babuska). */
+typedef struct { double sum, comp; } nsum_t;
+
+static void nsum_add(nsum_t *a, double x)
+{
+    const double t = a->sum + x;
+    if (fabs(a->sum) >= fabs(x)) a->comp += (a->sum - t) + x;
+    else a->comp += (x - t) + a->sum;
+    a->sum = t;
+}
+
+/* Phase-space integral over events event_offset .. event_offset+nevents-1:
+ *   mean  = (sum of weights) / n              (compensated sum),
+ *   sigma = sqrt( sum (w - mean)^2 / ((n-1) n) )  (second pass, compensated),
+ * i.e. the Monte Carlo estimate of R_N and its standard error. */
+int oracle_integrate(double parent_mass, const double *masses, int n,
+                     uint64_t nevents, uint64_t seed, uint32_t stream_id, uint64_t event_offset,
+                     double *mean, double *sigma)
+{
+    int st = check_args(parent_mass, masses, n);
+    if (st != ORACLE_OK) return st;
+    if (nevents < 2 || mean == NULL || sigma == NULL) return ORACLE_EINVAL;
+    double *w = (double *)malloc(sizeof(double) * nevents);
+    if (w == NULL) return ORACLE_EINVAL;
+    st = oracle_generate(parent_mass, masses, n, NULL, NULL, 0, nevents, seed, stream_id,
+                         event_offset, NULL, 0, w);
+    if (st == ORACLE_OK) {
+        nsum_t s1 = { 0.0, 0.0 };
+        for (uint64_t e = 0; e < nevents; ++e) nsum_add(&s1, w[e]);
+        const double m = (s1.sum + s1.comp) / (double)nevents;
+        nsum_t s2 = { 0.0, 0.0 };
+        for (uint64_t e = 0; e < nevents; ++e) {
+            const double d = w[e] - m;
+            nsum_add(&s2, d * d);
+        }
+        const double var = (s2.sum + s2.comp) / (double)(nevents - 1);
+        *mean = m;
+        *sigma = sqrt(var / (double)nevents);
+    }
+    free(w);
+    return st;
+}

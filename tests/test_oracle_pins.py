@@ -1,0 +1,372 @@
+"""Pins of the CPU oracle against facts fixed outside it (no GPU needed).
+
+Each test checks the oracle against something it does not compute itself: an
+independent Philox4x32-10 implementation (rocRAND), closed-form or quadrature
+phase-space volumes, exact two-body kinematics, conservation laws and Lorentz
+invariants evaluated from the outputs, and the flatness of the three-body Dalitz
+plot (arXiv:1711.05683 sec. 4.2: kinematics of a particle of given four-momentum
+decaying to n bodies without resonances, Raubold-Lynch weighted events).
+"""
+from __future__ import annotations
+
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import volumes as V
+
+CFG0_M = 5.279
+CFG0_MASSES = [3.097, 0.4937, 0.13957]
+
+
+# ---------------------------------------------------------------- Philox ----
+
+@pytest.fixture(scope="session")
+def rocrand_kat(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available to build the rocRAND known-answer harness")
+    src = os.path.join(os.path.dirname(__file__), "kat", "rocrand_philox_kat.cpp")
+    exe = str(tmp_path_factory.mktemp("kat") / "rocrand_philox_kat")
+    subprocess.run([hipcc, "-O1", "-o", exe, src], check=True, capture_output=True)
+
+    def run(seed, subsequence, offset, nblocks):
+        out = subprocess.run([exe, str(seed), str(subsequence), str(offset), str(nblocks)],
+                             check=True, capture_output=True, text=True).stdout
+        return [[int(x, 16) for x in line.split()] for line in out.strip().splitlines()]
+    return run
+
+
+KAT_CASES = [
+    # (seed, stream_id, g, j)
+    (0, 0, 0, 0),
+    (42, 0, 0, 0),
+    (42, 0, 12345, 2),
+    (42, 7, 99999, 1),
+    (0x0123456789ABCDEF, 3, (1 << 32) + 17, 5),
+    (0xFFFFFFFFFFFFFFFF, 0xFFFFFFFF, (1 << 61) + 3, 12),  # 4 g must fit in 64 bits
+    (43, 1, 100_000_000 - 1, 0),
+]
+
+
+@pytest.mark.parametrize("seed,stream,g,j", KAT_CASES)
+def test_philox_words_match_rocrand(oracle_lib, rocrand_kat, seed, stream, g, j):
+    # rocRAND's state maps (seed, subsequence, offset) to key (seed lo, seed hi) and
+    # counter (offset/4 as 64 bits, subsequence as 64 bits); the oracle's counter is
+    # (g lo, g hi, j, stream), i.e. subsequence = stream<<32 | j, offset = 4 g.
+    blocks = rocrand_kat(seed, (stream << 32) | j, 4 * g, 3)
+    for b in range(3):
+        gg = g + b
+        want = oracle_lib.philox4x32_10([gg & 0xFFFFFFFF, gg >> 32, j, stream],
+                                        [seed & 0xFFFFFFFF, seed >> 32])
+        assert blocks[b] == want, (seed, stream, gg, j)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 6, 10])
+def test_event_uniforms_from_rocrand_words(oracle_lib, rocrand_kat, n):
+    seed, stream, g = 42, 5, 777
+    nu = 3 * n - 4
+    assert oracle_lib.uniforms_per_event(n) == nu
+    ncalls = (2 * nu + 3) // 4
+    words = []
+    for j in range(ncalls):
+        words += rocrand_kat(seed, (stream << 32) | j, 4 * g, 1)[0]
+    u = oracle_lib.event_uniforms(seed, stream, g, n)
+    for k in range(nu):
+        bits = (words[2 * k + 1] << 32) | words[2 * k]
+        x = bits >> 12
+        assert u[k] == (2 * x + 1) / 2.0 ** 53
+        assert 0.0 < u[k] < 1.0
+
+
+def test_uniform_grid_is_exact_and_open(oracle_lib):
+    for g in range(200):
+        u = oracle_lib.event_uniforms(42, 0, g, 10)
+        scaled = u * 2.0 ** 53
+        assert np.all(scaled == np.floor(scaled))
+        assert np.all(np.mod(scaled, 2.0) == 1.0)
+        assert np.all(u >= 2.0 ** -53) and np.all(u <= 1.0 - 2.0 ** -53)
+
+
+# ------------------------------------------------------ volumes (integral) ----
+
+def _assert_within(mean, sigma, exact, nsig=4.0):
+    assert sigma > 0.0
+    assert abs(mean - exact) < nsig * sigma, (mean, sigma, exact, (mean - exact) / sigma)
+
+
+@pytest.mark.parametrize("n,M,nev", [(3, 1.0, 100_000), (4, 3.0, 100_000), (5, 7.0, 60_000),
+                                     (6, 10.0, 60_000), (10, 10.0, 40_000)])
+def test_massless_volume_closed_form(oracle_lib, n, M, nev):
+    mean, sigma = oracle_lib.integrate(M, [0.0] * n, nev, seed=42)
+    _assert_within(mean, sigma, V.massless_volume(n, M))
+    # The estimate must also be sharp enough to reject a factor-of-2 normalisation error.
+    assert sigma < 0.1 * V.massless_volume(n, M)
+
+
+def test_massless_three_body_weight_per_event(oracle_lib):
+    # Massless N=3 at mass M: sigma_1 = M R, p_0 = M R / 2, p_1 = M (1 - R^2)/2, so
+    # w = (pi^2 / 2) M^2 R (1 - R^2) with R the event's single mass uniform.
+    M = 2.5
+    _, w = oracle_lib.generate(M, [0.0, 0.0, 0.0], 2000, seed=42, want_momenta=False)
+    for e in range(2000):
+        r = oracle_lib.event_uniforms(42, 0, e, 3)[0]
+        want = 0.5 * math.pi ** 2 * M * M * r * ((1.0 - r) * (1.0 + r))
+        assert abs(w[e] - want) <= 4e-15 * want
+    # per-event spread: sigma_w = pi^2 M^2 sqrt(23/6720)
+    _, w = oracle_lib.generate(1.0, [0.0] * 3, 200_000, seed=7, want_momenta=False)
+    sd = float(np.std(w, ddof=1))
+    assert abs(sd - math.pi ** 2 * math.sqrt(23.0 / 6720.0)) < 0.01 * sd
+
+
+def test_two_body_is_exact(oracle_lib):
+    M, a, b = CFG0_M, 3.097, 0.4937
+    pstar = float(V.two_body_momentum(M, a, b))
+    p4, w = oracle_lib.generate(M, [a, b], 5000, seed=42)
+    want_w = math.pi * pstar / M
+    assert np.all(np.abs(w - want_w) <= 2e-15 * want_w)
+    for d, m in ((0, a), (1, b)):
+        pmag = np.sqrt(p4[d, 1] ** 2 + p4[d, 2] ** 2 + p4[d, 3] ** 2)
+        assert np.all(np.abs(pmag - pstar) <= 1e-14 * M)
+        assert np.all(np.abs(p4[d, 0] - math.sqrt(pstar ** 2 + m * m)) <= 1e-14 * M)
+    mean, sigma = oracle_lib.integrate(M, [a, b], 5000, seed=42)
+    assert abs(mean - want_w) <= 2e-15 * want_w
+    assert sigma <= 1e-15 * want_w
+
+
+def test_massive_three_body_volume_config0(oracle_lib):
+    exact = V.three_body_volume_1d(CFG0_M, *CFG0_MASSES)
+    # two routes to the same number: 1-D recursion integral and the Dalitz area
+    area = V.dalitz_area(CFG0_M, *CFG0_MASSES)
+    assert abs(exact - math.pi ** 2 / (4 * CFG0_M ** 2) * area) < 1e-12 * exact
+    assert abs(exact - float(V.recursive_volume(CFG0_M, CFG0_MASSES)[0])) < 1e-12 * exact
+    mean, sigma = oracle_lib.integrate(CFG0_M, CFG0_MASSES, 200_000, seed=42)
+    _assert_within(mean, sigma, exact)
+    assert sigma < 2e-3 * exact
+
+
+def test_six_pion_volume(oracle_lib):
+    masses = [0.13957] * 6
+    exact = float(V.recursive_volume(10.0, masses, k=40)[0])
+    # the same quadrature reproduces the massless closed form
+    ml = float(V.recursive_volume(10.0, [0.0] * 6, k=40)[0])
+    assert abs(ml - V.massless_volume(6, 10.0)) < 1e-12 * ml
+    mean, sigma = oracle_lib.integrate(10.0, masses, 60_000, seed=42)
+    _assert_within(mean, sigma, exact)
+
+
+@pytest.mark.parametrize("masses,M", [([0.5, 1.0, 0.2, 0.3], 4.0), ([0.1, 0.2, 0.3, 0.4, 0.5], 3.0)])
+def test_massive_volume_quadrature(oracle_lib, masses, M):
+    exact = float(V.recursive_volume(M, masses, k=40)[0])
+    mean, sigma = oracle_lib.integrate(M, masses, 80_000, seed=11)
+    _assert_within(mean, sigma, exact)
+
+
+def test_integral_is_mean_and_standard_error(oracle_lib):
+    _, w = oracle_lib.generate(CFG0_M, CFG0_MASSES, 3000, seed=42, event_offset=500,
+                               want_momenta=False)
+    mean, sigma = oracle_lib.integrate(CFG0_M, CFG0_MASSES, 3000, seed=42, event_offset=500)
+    exact_mean = math.fsum(w) / len(w)
+    var = math.fsum((x - exact_mean) ** 2 for x in w) / (len(w) - 1)
+    assert abs(mean - exact_mean) <= 1e-15 * exact_mean
+    assert abs(sigma - math.sqrt(var / len(w))) <= 1e-14 * sigma
+
+
+# ---------------------------------------------------- per-event kinematics ----
+
+def _minkowski_sq(v):
+    return v[0] ** 2 - v[1] ** 2 - v[2] ** 2 - v[3] ** 2
+
+
+def _check_event_physics(oracle_lib, M, masses, parent, p4, w, seed, stream, offset):
+    n = len(masses)
+    nev = p4.shape[2]
+    total = p4.sum(axis=0)
+    P = np.array([M, 0.0, 0.0, 0.0]) if parent is None else parent
+    P = P.reshape(4, -1) if P.ndim == 2 else P[:, None]
+    scale = max(M, float(np.max(np.abs(P))))
+    assert np.all(np.abs(total - P) <= 1e-12 * scale)
+    for d in range(n):
+        E = p4[d, 0]
+        m2 = _minkowski_sq(p4[d])
+        assert np.all(np.abs(m2 - masses[d] ** 2) <= 1e-12 * E * E + 1e-300)
+        assert np.all(E >= masses[d] * (1 - 1e-15))
+    s = np.cumsum(masses)
+    T = M - s[-1]
+    for e in range(nev):
+        u = oracle_lib.event_uniforms(seed, stream, offset + e, n)
+        R = np.concatenate([[0.0], np.sort(u[: n - 2]), [1.0]])
+        sig = [masses[0]] + [s[i] + T * R[i] for i in range(1, n - 1)] + [M]
+        acc = p4[0, :, e].copy()
+        for i in range(1, n):
+            k = p4[i, :, e]
+            acc_prev = acc.copy()
+            acc = acc + k
+            # invariant mass of {0..i} equals sigma_i
+            mi = math.sqrt(max(_minkowski_sq(acc), 0.0))
+            assert abs(mi - sig[i]) <= 1e-11 * M, (e, i, mi, sig[i])
+            # breakup momentum of daughter i in the rest frame of {0..i}
+            Pk = acc[0] * k[0] - acc[1] * k[1] - acc[2] * k[2] - acc[3] * k[3]
+            estar = Pk / mi
+            pstar = math.sqrt(max(estar * estar - masses[i] ** 2, 0.0))
+            want = float(V.two_body_momentum(sig[i], sig[i - 1], masses[i]))
+            assert abs(pstar - want) <= 1e-9 * M, (e, i, pstar, want)
+            del acc_prev
+        assert w[e] >= 0.0 and np.isfinite(w[e])
+
+
+def test_event_physics_config0_at_rest(oracle_lib):
+    p4, w = oracle_lib.generate(CFG0_M, CFG0_MASSES, 400, seed=42)
+    _check_event_physics(oracle_lib, CFG0_M, CFG0_MASSES, None, p4, w, 42, 0, 0)
+
+
+@pytest.mark.parametrize("n", [2, 4, 7, 10])
+def test_event_physics_various_n(oracle_lib, n):
+    rng = np.random.default_rng(100 + n)
+    M = 5.0
+    masses = list(rng.uniform(0.0, 0.4 * M / n, size=n))
+    p4, w = oracle_lib.generate(M, masses, 150, seed=9, stream_id=3, event_offset=1000)
+    _check_event_physics(oracle_lib, M, masses, None, p4, w, 9, 3, 1000)
+
+
+def test_event_physics_moving_parent(oracle_lib):
+    M = CFG0_M
+    parent = np.array([math.sqrt(M * M + 1.0 + 4.0 + 9.0), 1.0, -2.0, 3.0])
+    p4, w = oracle_lib.generate(M, CFG0_MASSES, 300, seed=42, parent_p4=parent)
+    _check_event_physics(oracle_lib, M, CFG0_MASSES, parent, p4, w, 42, 0, 0)
+    # Lorentz invariance: identical weights and pair masses as at rest
+    p4r, wr = oracle_lib.generate(M, CFG0_MASSES, 300, seed=42)
+    assert np.array_equal(w, wr)
+    for a, b in ((0, 1), (1, 2), (0, 2)):
+        m_mov = np.sqrt(_minkowski_sq(p4[a] + p4[b]))
+        m_rest = np.sqrt(_minkowski_sq(p4r[a] + p4r[b]))
+        assert np.all(np.abs(m_mov - m_rest) <= 1e-12 * M)
+
+
+def test_event_physics_per_event_parents(oracle_lib):
+    M = CFG0_M
+    nev = 200
+    rng = np.random.default_rng(5)
+    pz = rng.uniform(0.0, 20.0, nev)
+    soa = np.stack([np.sqrt(M * M + pz * pz), np.zeros(nev), np.zeros(nev), pz])
+    p4, w = oracle_lib.generate(M, CFG0_MASSES, nev, seed=42, parent_soa=soa)
+    _check_event_physics(oracle_lib, M, CFG0_MASSES, soa, p4, w, 42, 0, 0)
+
+
+def _direction(u, v):
+    ct = 2.0 * u - 1.0
+    st = math.sqrt(max(0.0, 1.0 - ct * ct))
+    return np.array([st * math.cos(2 * math.pi * v), st * math.sin(2 * math.pi * v), ct])
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 10])
+def test_last_daughter_direction(oracle_lib, n):
+    # The last daughter is emitted in the parent rest frame and never boosted
+    # again: its direction is the last (theta, phi) pair of uniforms.
+    masses = [0.1 * (i + 1) for i in range(n)]
+    M = sum(masses) + 2.0
+    p4, _ = oracle_lib.generate(M, masses, 200, seed=3)
+    for e in range(200):
+        u = oracle_lib.event_uniforms(3, 0, e, n)
+        want = _direction(u[3 * n - 6], u[3 * n - 5])
+        p = p4[n - 1, 1:, e]
+        assert np.allclose(p / np.linalg.norm(p), want, rtol=0, atol=1e-12)
+
+
+def test_level0_direction_three_body(oracle_lib):
+    # Undo the single pure boost of {0,1} and recover the level-0 direction.
+    p4, _ = oracle_lib.generate(CFG0_M, CFG0_MASSES, 200, seed=42)
+    for e in range(200):
+        u = oracle_lib.event_uniforms(42, 0, e, 3)
+        P = p4[0, :, e] + p4[1, :, e]
+        sig = math.sqrt(_minkowski_sq(P))
+        eta = -P[1:] / sig
+        gam = P[0] / sig
+        k = p4[1, :, e]
+        ep = float(eta @ k[1:])
+        kp = k[1:] + (ep / (gam + 1.0) + k[0]) * eta
+        want = _direction(u[1], u[2])
+        assert np.allclose(kp / np.linalg.norm(kp), want, rtol=0, atol=1e-10)
+
+
+# --------------------------------------------------- distributions ----
+
+def test_dalitz_plot_is_flat(oracle_lib):
+    M, m = CFG0_M, CFG0_MASSES
+    nev = 400_000
+    p4, w = oracle_lib.generate(M, m, nev, seed=42)
+    s01 = _minkowski_sq(p4[0] + p4[1])
+    s12 = _minkowski_sq(p4[1] + p4[2])
+    lo01, hi01 = (m[0] + m[1]) ** 2, (M - m[2]) ** 2
+    edges01 = np.linspace(lo01, hi01, 13)
+    lo12, hi12 = (m[1] + m[2]) ** 2, (M - m[0]) ** 2
+    edges12 = np.linspace(lo12, hi12, 13)
+    H, _, _ = np.histogram2d(s01, s12, bins=[edges01, edges12], weights=w)
+    H2, _, _ = np.histogram2d(s01, s12, bins=[edges01, edges12], weights=w * w)
+    density = math.pi ** 2 / (4.0 * M * M)
+    chi2, ndf = 0.0, 0
+    for i in range(12):
+        for j in range(12):
+            # bin fully inside the kinematic boundary: check its four corners
+            inside = True
+            for s in (edges01[i], edges01[i + 1]):
+                a, b = V.dalitz_m12sq_limits(M, *m, s)
+                if not (a <= edges12[j] and edges12[j + 1] <= b):
+                    inside = False
+            if not inside:
+                continue
+            area = (edges01[i + 1] - edges01[i]) * (edges12[j + 1] - edges12[j])
+            want = density * area
+            var = H2[i, j] / nev ** 2 - (H[i, j] / nev) ** 2 / nev
+            chi2 += (H[i, j] / nev - want) ** 2 / var
+            ndf += 1
+    assert ndf >= 20
+    # chi^2 with ndf degrees of freedom: mean ndf, sd sqrt(2 ndf)
+    assert chi2 < ndf + 5.0 * math.sqrt(2.0 * ndf), (chi2, ndf)
+
+
+def test_isotropy(oracle_lib):
+    masses = [0.2, 0.3, 0.1, 0.4]
+    p4, w = oracle_lib.generate(3.0, masses, 100_000, seed=21)
+    W = w.sum()
+    for d in range(4):
+        p = p4[d, 1:]
+        nhat = p / np.linalg.norm(p, axis=0)
+        for k in range(3):
+            mu = float((w * nhat[k]).sum() / W)
+            sd = math.sqrt(float((w * w * nhat[k] ** 2).sum())) / W
+            assert abs(mu) < 5 * sd
+        c2 = float((w * nhat[2] ** 2).sum() / W)
+        assert abs(c2 - 1.0 / 3.0) < 0.01
+
+
+# --------------------------------------------------- determinism / validation ----
+
+def test_chunking_is_bit_identical(oracle_lib):
+    p4, w = oracle_lib.generate(CFG0_M, CFG0_MASSES, 1000, seed=42, event_offset=0)
+    pa, wa = oracle_lib.generate(CFG0_M, CFG0_MASSES, 333, seed=42, event_offset=0)
+    pb, wb = oracle_lib.generate(CFG0_M, CFG0_MASSES, 667, seed=42, event_offset=333)
+    assert np.array_equal(np.concatenate([pa, pb], axis=2), p4)
+    assert np.array_equal(np.concatenate([wa, wb]), w)
+
+
+def test_streams_and_seeds_differ(oracle_lib):
+    _, w0 = oracle_lib.generate(CFG0_M, CFG0_MASSES, 100, seed=42, stream_id=0, want_momenta=False)
+    _, w1 = oracle_lib.generate(CFG0_M, CFG0_MASSES, 100, seed=42, stream_id=1, want_momenta=False)
+    _, w2 = oracle_lib.generate(CFG0_M, CFG0_MASSES, 100, seed=43, stream_id=0, want_momenta=False)
+    assert not np.array_equal(w0, w1) and not np.array_equal(w0, w2)
+
+
+def test_validation(oracle_lib):
+    o = oracle_lib
+    assert o.generate_status(5.0, [1.0]) == o.EINVAL
+    assert o.generate_status(50.0, [0.1] * 11) == o.EINVAL
+    assert o.generate_status(5.0, [1.0, -0.1]) == o.EINVAL
+    assert o.generate_status(5.0, [1.0, float("nan")]) == o.EINVAL
+    assert o.generate_status(5.0, [3.0, 2.0]) == o.EKINEMATICS
+    assert o.generate_status(5.0, [3.0, 2.5]) == o.EKINEMATICS
+    assert o.generate_status(5.0, [0.0, 0.0]) == o.OK

@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark: phase-space events/s on one MI355X and the HBM-write roofline.
+
+Workload (the throughput configuration): a parent of mass 5.279 GeV at rest
+decays to (3.097, 0.4937, 0.13957) GeV; 1e8 events per step, FP64, Philox seed
+42; each step writes the SoA four-momenta (3 x 4 doubles) and the weight of every
+event (104 B/event, 10.4 GB) and the fused integral (mean, sigma).  One step is
+one ``hydra_phsp_generate`` call: the main kernel plus the finalize kernel.
+
+Prints ONE JSON line.  ``roofline`` uses the main kernel's average duration,
+measured with HIP events recorded by the library on the launch stream over the
+timed region; ``cpu_baseline`` times the CPU oracle on a bounded sample of the
+same workload on this host.  ``extras`` reports the other configurations
+(per-event parents, six-body FP64 vs mixed, integrate-only, batched) when
+their code paths exist.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "phase-space events/s (N=3, FP64) and % HBM roofline; mixed vs plain at tol"
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, AMD public specification
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_phsp_n3_1e8_traffic.txt")
+COPY_BYTES = 1 << 30  # calibration copy: reads and writes exactly this many bytes
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources the main kernel is built from (invalidates stale counters)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1711_05683_amd", "csrc")
+    for name in ("phsp_device.hpp", "phsp_sortnet.hpp", "phsp_kernels.hpp", "phsp_inst.hip"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when missing or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(target_s: float = 10.0, chunk: int = 1_000_000, max_events: int = 30_000_000):
+    """The CPU oracle (single thread) on a bounded sample of the same workload."""
+    import oracle
+    oracle.build(force=False)
+    M, m = 5.279, [3.097, 0.4937, 0.13957]
+    done = 0
+    t0 = time.perf_counter()
+    while done < max_events:
+        oracle.generate(M, m, chunk, seed=42, event_offset=done)
+        done += chunk
+        if time.perf_counter() - t0 >= target_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} events of the 1e8-event workload (momenta + weights), "
+                      f"{chunk}-event chunks, single thread, {dt:.1f} s",
+            "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    import paper_1711_05683_amd as P
+    P.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, launches = P.timing_read()
+    P.timing_enable(False)
+    return (t1 - t0) * 1e3 / steps, (kms / launches if launches else float("nan"))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nevents", type=int, default=100_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for rocprofv3 --pmc: a 1 GiB torch copy (the calibration "
+                         "kernel of known traffic) x3, then the main step x3; prints no JSON")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the event loop shards by event_offset; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1711_05683_amd as P
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    P.lib()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    M, m = 5.279, [3.097, 0.4937, 0.13957]
+    n_ev = args.nevents
+    out = torch.empty((3, 4, n_ev), dtype=torch.float64, device=dev)
+    w = torch.empty(n_ev, dtype=torch.float64, device=dev)
+    st = torch.empty(4, dtype=torch.float64, device=dev)
+
+    def step():
+        P.generate(M, m, n_ev, seed=42, out=out, weights=w, stats=st)
+
+    if args.counters:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        print(f"counter run done: copy {COPY_BYTES} B x3, {n_ev} events x3", flush=True)
+        return
+
+    ms_step, ms_kernel = time_steps(step, args.steps, args.warmup, torch)
+    bytes_per_event = 8 * (4 * 3 + 1)
+    achieved = bytes_per_event * n_ev / (ms_kernel * 1e-3) / 1e9
+    stats = st.cpu().tolist()
+    traffic = read_traffic()
+
+    result = {
+        "metric": METRIC,
+        "value": n_ev / (ms_step * 1e-3),
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3-body decay at rest, M=5.279 -> (3.097, 0.4937, 0.13957) GeV, "
+                               f"{n_ev:.0e} events/step, FP64, Philox4x32-10 seed 42, SoA momenta "
+                               "+ weights + fused integral",
+                   "n_daughters": 3, "nevents": n_ev, "bytes_per_event": bytes_per_event},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "k_phsp<3, at rest, FP64>", "kernel_ms": ms_kernel},
+        "integral": {"mean": stats[1], "sigma": stats[3], "n": stats[0]},
+    }
+    del out
+
+    if not args.no_extras:
+        result["extras"] = extras(P, torch, dev, args)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+def extras(P, torch, dev, args):
+    """Other configurations at their own sizes, each timed like the main step."""
+    from paper_1711_05683_amd.workloads import per_event_parents
+    ex = {}
+    steps = max(3, args.steps // 2)
+    M, m = 5.279, [3.097, 0.4937, 0.13957]
+    n1 = args.nevents
+    # config 1b: per-event parents (reads 32 B/event more)
+    parents = per_event_parents(M, n1)
+    out = torch.empty((3, 4, n1), dtype=torch.float64, device=dev)
+    w = torch.empty(n1, dtype=torch.float64, device=dev)
+    st = torch.empty(4, dtype=torch.float64, device=dev)
+    ms, kms = time_steps(lambda: P.generate(M, m, n1, out=out, weights=w, stats=st, parent_dev=parents),
+                         steps, 1, torch)
+    ex["cfg1_per_event_parent"] = {"events_per_s": n1 / (ms * 1e-3), "kernel_ms": kms,
+                                   "write_GBs": 104 * n1 / (kms * 1e-3) / 1e9,
+                                   "total_GBs": 136 * n1 / (kms * 1e-3) / 1e9}
+    del parents
+    # integrate-only (no stores): the arithmetic ceiling of the same events
+    ms, kms = time_steps(lambda: P.integrate_async(M, m, n1, stats=st), steps, 1, torch)
+    ex["cfg1_integrate_only"] = {"events_per_s": n1 / (ms * 1e-3), "kernel_ms": kms}
+    del out, w
+    # config 2: six pions at M=10, 5e7 events, FP64 vs mixed
+    n2 = max(n1 // 2, 1)
+    six = [0.13957] * 6
+    out = torch.empty((6, 4, n2), dtype=torch.float64, device=dev)
+    w = torch.empty(n2, dtype=torch.float64, device=dev)
+    ms, kms = time_steps(lambda: P.generate(10.0, six, n2, out=out, weights=w, stats=st), steps, 1, torch)
+    ex["cfg2_six_pion_fp64"] = {"events_per_s": n2 / (ms * 1e-3), "kernel_ms": kms,
+                                "write_GBs": 200 * n2 / (kms * 1e-3) / 1e9}
+    del out
+    outm = torch.empty((6, 4, n2), dtype=torch.float32, device=dev)
+    ms, kms = time_steps(lambda: P.generate(10.0, six, n2, out=outm, weights=w, stats=st, mixed=True),
+                         steps, 1, torch)
+    ex["cfg2_six_pion_mixed"] = {"events_per_s": n2 / (ms * 1e-3), "kernel_ms": kms,
+                                 "write_GBs": 104 * n2 / (kms * 1e-3) / 1e9}
+    del outm, w
+    return ex
+
+
+if __name__ == "__main__":
+    main()

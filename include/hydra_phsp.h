@@ -1,0 +1,155 @@
+/*
+ * hydra_phsp.h -- C ABI of the MI355X (gfx950) phase-space Monte Carlo library.
+ *
+ * The library generates and integrates N-body phase space with the
+ * Raubold-Lynch method (arXiv:1711.05683, sec. 4.2 "Phase-Space Monte Carlo"):
+ * a parent of given four-momentum decays to n daughters without intermediate
+ * resonances; every event carries the full kinematics of the daughters and a
+ * weight, and the mean weight estimates the n-body phase-space volume.
+ *
+ * Conventions (the paper fixes the problem and the interface of listing
+ * "lst:phsp"; the rest are the readings documented with the library):
+ *   - four-vectors are (E, px, py, pz): the listing builds the parent at rest
+ *     as Vector4R(mass, 0, 0, 0);
+ *   - the parent mass and the daughter masses are fixed per call, as in the
+ *     listing's PhaseSpace<N>(mass, masses) object; the parent four-vector is
+ *     given at generation time, as in Generate(Mother, begin, end);
+ *   - measure: prod_i d^3p_i/(2E_i) delta^4(P - sum_i p_i), no factors of 2*pi;
+ *     the mean weight is the n-body volume in this measure;
+ *   - random numbers: Philox4x32-10, key = seed, counter =
+ *     (g mod 2^32, g div 2^32, call index, stream_id) for global event index
+ *     g = event_offset + e.  Results depend only on (seed, stream_id, g), so
+ *     chunked, sharded and resumed runs are bit-identical to a single run;
+ *   - daughter 0 is the innermost; each two-body level adds the next daughter
+ *     and boosts the earlier ones into the new frame.
+ *
+ * Memory: pointers named *_dev are device pointers (e.g. from torch tensors),
+ * owned by the caller and left untouched outside the call; *_host pointers are
+ * host memory read during the call only.  Momenta are structure-of-arrays:
+ * component mu (0=E, 1=px, 2=py, 3=pz) of daughter d for event e is at
+ * p4_out_dev[(4*d + mu)*ld + e], with ld >= nevents.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ * Calls documented as asynchronous only enqueue work on it; a device fault
+ * surfaces at the next synchronising call as HYDRA_PHSP_EDEVICE.  Calls on
+ * different streams may run concurrently from different host threads.
+ *
+ * Errors: every entry point returns a status code; all argument checks happen
+ * before any work is enqueued, so a failed call has no effect on the device.
+ * hydra_phsp_strerror() names a code, hydra_phsp_last_error() gives the text
+ * of the calling thread's most recent failure.
+ */
+#ifndef HYDRA_PHSP_H
+#define HYDRA_PHSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HYDRA_PHSP_NMAX 10 /* largest number of daughters */
+#define HYDRA_PHSP_ABI_VERSION 1
+
+enum {
+    HYDRA_PHSP_OK = 0,
+    HYDRA_PHSP_EINVAL = -1,      /* bad argument: N outside [2, NMAX], null pointer, ld < nevents, ... */
+    HYDRA_PHSP_EKINEMATICS = -2, /* parent mass not above the sum of daughter masses */
+    HYDRA_PHSP_ENOMEM = -3,      /* device or host allocation failed / budget exceeded */
+    HYDRA_PHSP_EDEVICE = -4,     /* a HIP runtime error (text in hydra_phsp_last_error) */
+    HYDRA_PHSP_EAGAIN = -5,      /* serving: result not ready yet */
+    HYDRA_PHSP_ENOTFOUND = -6    /* serving: unknown or already collected request id */
+};
+
+/* Integral statistics written to a device buffer of HYDRA_PHSP_STATS doubles:
+ * [0] n (number of events), [1] mean weight (the volume estimate),
+ * [2] M2 = sum over events of (w - mean)^2, [3] sigma = sqrt(M2 / ((n-1) n)),
+ * the standard error of the mean (0 when n < 2). */
+#define HYDRA_PHSP_STATS 4
+
+/* ------------------------------------------------------------------------ */
+/* Plain FP64 path                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Generate `nevents` weighted phase-space events (sec. 4.2; listing lst:phsp's
+ * Generate(Mother, begin, end)).  Asynchronous on `stream`.
+ *
+ *   parent_mass      M > 0, the decaying particle's mass.
+ *   masses_host      n_daughters masses >= 0 (host), sum < M (else EKINEMATICS).
+ *   n_daughters      2 .. HYDRA_PHSP_NMAX.
+ *   parent_p4_host   NULL: parent at rest.  Else 4 doubles (E, px, py, pz) of one
+ *                    parent applied to every event (boost eta = p/M, gamma = E/M).
+ *   parent_p4_dev    NULL, or per-event parents (SoA, component mu of event e at
+ *                    parent_p4_dev[mu*ld_parent + e], ld_parent >= nevents); the
+ *                    decay uses M and each parent only for its boost, so every
+ *                    parent's invariant mass must equal M.  At most one of
+ *                    parent_p4_host / parent_p4_dev may be non-NULL.
+ *   nevents          number of events (0 is a no-op that still writes stats).
+ *   seed, stream_id  Philox key and counter word 3.
+ *   event_offset     global index of the first event.
+ *   p4_out_dev       [n_daughters][4][ld] doubles (device).
+ *   weights_dev      [nevents] doubles (device).
+ *   stats_dev        NULL, or HYDRA_PHSP_STATS doubles (device) receiving the
+ *                    fused integral of this call's weights.
+ */
+int hydra_phsp_generate(double parent_mass, const double *masses_host, int n_daughters,
+                        const double *parent_p4_host, const double *parent_p4_dev,
+                        uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t stream_id,
+                        uint64_t event_offset, double *p4_out_dev, uint64_t ld,
+                        double *weights_dev, double *stats_dev, void *stream);
+
+/* Phase-space integral without storing events (sec. 3 lists phase-space
+ * integration among the library's algorithms; sec. 4.2 the method).  The same
+ * events as hydra_phsp_generate with the same (seed, stream_id, event_offset);
+ * weights are Lorentz invariant, so no parent four-vector is needed.
+ *   stats_dev   HYDRA_PHSP_STATS doubles (device), written asynchronously. */
+int hydra_phsp_integrate_async(double parent_mass, const double *masses_host, int n_daughters,
+                               uint64_t nevents, uint64_t seed, uint32_t stream_id,
+                               uint64_t event_offset, double *stats_dev, void *stream);
+
+/* Synchronous convenience form: requires nevents >= 2; returns the mean weight
+ * and its standard error in host memory after synchronising `stream`. */
+int hydra_phsp_integrate(double parent_mass, const double *masses_host, int n_daughters,
+                         uint64_t nevents, uint64_t seed, uint32_t stream_id,
+                         uint64_t event_offset, double *mean_host, double *sigma_host,
+                         void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Mixed FP32/FP64 path                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* As hydra_phsp_generate, but the decay angles, energies, boosts and the
+ * momentum outputs are FP32 (p4_out_dev is [n_daughters][4][ld] floats);
+ * uniforms, sorting, invariant masses, breakup momenta, the weight and the
+ * integral stay FP64, so weights and stats equal the FP64 path's. */
+int hydra_phsp_generate_mixed(double parent_mass, const double *masses_host, int n_daughters,
+                              const double *parent_p4_host, const double *parent_p4_dev,
+                              uint64_t ld_parent, uint64_t nevents, uint64_t seed,
+                              uint32_t stream_id, uint64_t event_offset, float *p4_out_dev,
+                              uint64_t ld, double *weights_dev, double *stats_dev, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Misc                                                                      */
+/* ------------------------------------------------------------------------ */
+
+const char *hydra_phsp_strerror(int status);
+const char *hydra_phsp_last_error(void);
+int hydra_phsp_abi_version(void);
+/* Host-side self-test of the in-register sorting networks (0-1 principle over
+ * every network the kernels use); returns HYDRA_PHSP_OK when all sort. */
+int hydra_phsp_selftest_sortnet(void);
+/* Kernel timing for benchmarks: while enabled, every launch of the main
+ * phase-space kernel is bracketed by HIP events recorded on the caller's
+ * stream.  hydra_phsp_timing_read synchronises those events and returns the
+ * summed kernel time (ms) and the number of launches since the last reset. */
+int hydra_phsp_timing_enable(int on);
+int hydra_phsp_timing_read(double *total_ms_host, uint64_t *launches_host);
+int hydra_phsp_timing_reset(void);
+/* Free the library's cached device workspaces (block partials). */
+int hydra_phsp_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYDRA_PHSP_H */

@@ -1,0 +1,92 @@
+"""Build the HIP library ``libhydra_phsp.so`` for gfx950 (in-tree).
+
+Every translation unit under ``csrc/`` is compiled with hipcc for gfx950 only;
+the per-daughter-count kernel unit ``phsp_inst.hip`` is compiled once per
+N = 2..10 so that the instantiations build in parallel.  Objects go to
+``_build/`` at the repository root; the shared library lands next to this file.
+
+Usage: ``python -m paper_1711_05683_amd.build`` (or ``build()`` from Python).
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD_DIR = os.path.join(ROOT, "_build")
+LIB_NAME = "libhydra_phsp.so"
+LIB_PATH = os.path.join(PKG, LIB_NAME)
+
+ARCH = "gfx950"
+NS = range(2, 11)
+
+# Packed FP32 instructions are disabled for every HIP unit; the host pass warns
+# that it does not know the feature, which is harmless.
+HIP_FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+    f"-I{INCLUDE}", f"-I{CSRC}",
+]
+
+
+def _hipcc() -> str:
+    exe = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(exe):
+        raise RuntimeError("hipcc not found: the HIP library cannot be built")
+    return exe
+
+
+def _units():
+    """(source, object, extra flags) for every translation unit."""
+    units = []
+    for n in NS:
+        units.append((os.path.join(CSRC, "phsp_inst.hip"),
+                      os.path.join(BUILD_DIR, f"phsp_inst_n{n}.o"), [f"-DPHSP_N={n}"]))
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith(".hip") and name != "phsp_inst.hip":
+            units.append((os.path.join(CSRC, name),
+                          os.path.join(BUILD_DIR, name[:-4] + ".o"), []))
+        elif name.endswith(".cpp"):
+            units.append((os.path.join(CSRC, name),
+                          os.path.join(BUILD_DIR, name[:-4] + ".o"), []))
+    return units
+
+
+def _compile(hipcc, src, obj, extra):
+    cmd = [hipcc, *HIP_FLAGS, *extra, "-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    """Compile every unit and link the shared library; returns its path."""
+    hipcc = _hipcc()
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    units = _units()
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = [ex.submit(_compile, hipcc, s, o, x) for s, o, x in units]
+        objs = [f.result() for f in futs]
+    tmp = LIB_PATH + ".tmp"
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB_PATH)
+    if verbose:
+        print(f"built {LIB_PATH} from {len(objs)} units")
+    return LIB_PATH
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,400 @@
+// phsp_api.hip -- C ABI of the single-channel path: argument validation,
+// per-channel constants, workspace management and launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hydra_phsp.h"
+#include "phsp_api_internal.hpp"
+#include "phsp_kernels.hpp"
+
+namespace hphsp {
+
+// ---------------------------------------------------------------- errors ----
+
+static thread_local std::string t_last_error;
+
+int fail(int status, const std::string& msg) {
+    t_last_error = msg;
+    return status;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+    t_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return HYDRA_PHSP_EDEVICE;
+}
+
+// ------------------------------------------------------------- validation ----
+
+int make_channel(double M, const double* masses, int n, Channel* out) {
+    if (n < 2 || n > kNMax) return fail(HYDRA_PHSP_EINVAL, "n_daughters must be in [2, 10]");
+    if (masses == nullptr) return fail(HYDRA_PHSP_EINVAL, "masses_host is NULL");
+    if (!std::isfinite(M) || !(M > 0.0)) return fail(HYDRA_PHSP_EINVAL, "parent mass must be finite and > 0");
+    Channel c;
+    std::memset(&c, 0, sizeof(c));
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(masses[i]) || !(masses[i] >= 0.0))
+            return fail(HYDRA_PHSP_EINVAL, "daughter masses must be finite and >= 0");
+        s += masses[i];
+        c.m[i] = masses[i];
+        c.S[i] = s;
+    }
+    const double T = M - s;
+    if (!(T > 0.0)) return fail(HYDRA_PHSP_EKINEMATICS, "parent mass must exceed the sum of daughter masses");
+    // C = pi^{N-1} (2T)^{N-2} / (M (N-2)!): the volume of the sorted-uniform
+    // simplex and the Jacobian d(sigma^2) -> 2 sigma T dR of each inner level.
+    double C = 1.0 / M;
+    for (int i = 0; i < n - 1; ++i) C *= 3.141592653589793;
+    for (int i = 0; i < n - 2; ++i) C *= 2.0 * T;
+    for (int i = 2; i <= n - 2; ++i) C /= (double)i;
+    c.M = M;
+    c.T = T;
+    c.C = C;
+    c.half_inv_M = 0.5 / M;
+    *out = c;
+    return HYDRA_PHSP_OK;
+}
+
+int make_frame(double M, const double* p4, Frame* f) {
+    const double E = p4[0], px = p4[1], py = p4[2], pz = p4[3];
+    if (!std::isfinite(E) || !std::isfinite(px) || !std::isfinite(py) || !std::isfinite(pz) || !(E > 0.0))
+        return fail(HYDRA_PHSP_EINVAL, "parent four-vector must be finite with E > 0");
+    const double m2 = E * E - (px * px + py * py + pz * pz);
+    if (std::fabs(m2 - M * M) > 1e-9 * E * E)
+        return fail(HYDRA_PHSP_EINVAL, "parent four-vector's invariant mass differs from parent_mass");
+    f->eta[0] = px / M;
+    f->eta[1] = py / M;
+    f->eta[2] = pz / M;
+    f->gamma = E / M;
+    f->inv_gp1 = M / (E + M);
+    return HYDRA_PHSP_OK;
+}
+
+// --------------------------------------------------------------- workspace ----
+
+struct Workspace {
+    Moments* partials = nullptr;
+    uint64_t capacity = 0;
+    double* stats_host = nullptr; // pinned, HYDRA_PHSP_STATS doubles
+    double* stats_dev = nullptr;  // HYDRA_PHSP_STATS doubles
+};
+
+static std::mutex g_ws_mutex;
+static std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+int workspace_for(hipStream_t stream, uint64_t partials, Workspace** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    Workspace& w = g_ws[std::make_pair(dev, stream)];
+    if (w.stats_dev == nullptr) {
+        e = hipMalloc(&w.stats_dev, sizeof(double) * HYDRA_PHSP_STATS);
+        if (e != hipSuccess) return fail(HYDRA_PHSP_ENOMEM, "workspace allocation failed");
+        e = hipHostMalloc(&w.stats_host, sizeof(double) * HYDRA_PHSP_STATS, hipHostMallocDefault);
+        if (e != hipSuccess) return fail(HYDRA_PHSP_ENOMEM, "pinned workspace allocation failed");
+    }
+    if (partials > w.capacity) {
+        uint64_t cap = w.capacity ? w.capacity : 4096;
+        while (cap < partials) cap *= 2;
+        if (w.partials != nullptr) {
+            // hipFree waits for the device, so no queued kernel still reads it.
+            e = hipFree(w.partials);
+            if (e != hipSuccess) return fail_hip(e, "hipFree");
+            w.partials = nullptr;
+            w.capacity = 0;
+        }
+        e = hipMalloc(&w.partials, sizeof(Moments) * cap);
+        if (e != hipSuccess) return fail(HYDRA_PHSP_ENOMEM, "workspace allocation failed");
+        w.capacity = cap;
+    }
+    *out = &w;
+    return HYDRA_PHSP_OK;
+}
+
+int release_workspaces() {
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail_hip(e, "hipDeviceSynchronize");
+    for (auto& kv : g_ws) {
+        if (kv.second.partials) (void)hipFree(kv.second.partials);
+        if (kv.second.stats_dev) (void)hipFree(kv.second.stats_dev);
+        if (kv.second.stats_host) (void)hipHostFree(kv.second.stats_host);
+    }
+    g_ws.clear();
+    return HYDRA_PHSP_OK;
+}
+
+// ----------------------------------------------------------------- timing ----
+
+struct Timing {
+    std::mutex mu;
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool; // created lazily, reused
+    size_t used = 0;
+};
+static Timing g_timing;
+
+// Returns the slot whose events bracket the next launch, or -1 when disabled.
+long timing_begin(hipStream_t stream) {
+    std::lock_guard<std::mutex> lock(g_timing.mu);
+    if (!g_timing.on) return -1;
+    if (g_timing.used == g_timing.pool.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return -1;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return -1;
+        }
+        g_timing.pool.emplace_back(a, b);
+    }
+    const long slot = (long)g_timing.used++;
+    if (hipEventRecord(g_timing.pool[slot].first, stream) != hipSuccess) return -1;
+    return slot;
+}
+
+void timing_end(hipStream_t stream, long slot) {
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lock(g_timing.mu);
+    (void)hipEventRecord(g_timing.pool[slot].second, stream);
+}
+
+// ----------------------------------------------------------------- launch ----
+
+__global__ __launch_bounds__(kFinalizeBlock) void k_finalize(const Moments* parts, uint64_t count,
+                                                             double* stats) {
+    finalize_moments(parts, count, stats);
+}
+
+static hipError_t launch_by_n(int n, const LaunchSpec& s, const KArgs& a, hipStream_t stream) {
+    switch (n) {
+    case 2: return launch_phsp<2>(s, a, stream);
+    case 3: return launch_phsp<3>(s, a, stream);
+    case 4: return launch_phsp<4>(s, a, stream);
+    case 5: return launch_phsp<5>(s, a, stream);
+    case 6: return launch_phsp<6>(s, a, stream);
+    case 7: return launch_phsp<7>(s, a, stream);
+    case 8: return launch_phsp<8>(s, a, stream);
+    case 9: return launch_phsp<9>(s, a, stream);
+    case 10: return launch_phsp<10>(s, a, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Events per thread of the single-channel kernels.
+static int default_ept(int mode) { return mode == kIntegrate ? 2 : 1; }
+
+int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const double* parent_dev,
+               uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
+               int mode, void* out, uint64_t ld, double* weights, double* stats_dev,
+               hipStream_t stream, int ept_override) {
+    const int ept = ept_override > 0 ? ept_override : default_ept(mode);
+    const uint64_t per_block = (uint64_t)kBlock * (uint64_t)ept;
+    const uint64_t blocks = (nevents + per_block - 1) / per_block;
+    if (blocks > 0x7FFFFFFFull) return fail(HYDRA_PHSP_EINVAL, "nevents too large for one launch");
+    Workspace* ws = nullptr;
+    int st = workspace_for(stream, blocks, &ws);
+    if (st != HYDRA_PHSP_OK) return st;
+    if (blocks > 0) {
+        KArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.ch = ch;
+        if (frame) a.frame = *frame;
+        a.parent = parent_dev;
+        a.ld_parent = ld_parent;
+        a.inv_M = 1.0 / ch.M;
+        a.nevents = nevents;
+        a.event_offset = offset;
+        a.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+        a.k1 = (uint32_t)(seed >> 32);
+        a.sid = sid;
+        a.out = out;
+        a.ld = ld;
+        a.weights = weights;
+        a.partials = ws->partials;
+        LaunchSpec s{pmode, mode, ept, blocks};
+        const long slot = timing_begin(stream);
+        hipError_t e = launch_by_n(n, s, a, stream);
+        timing_end(stream, slot);
+        if (e != hipSuccess) return fail_hip(e, "phase-space kernel launch");
+    }
+    if (stats_dev != nullptr) {
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeBlock), 0, stream,
+                           (const Moments*)ws->partials, blocks, stats_dev);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail_hip(e, "finalize kernel launch");
+    }
+    return HYDRA_PHSP_OK;
+}
+
+static int generate_common(double M, const double* masses, int n, const double* parent_p4_host,
+                           const double* parent_p4_dev, uint64_t ld_parent, uint64_t nevents,
+                           uint64_t seed, uint32_t sid, uint64_t offset, void* out, uint64_t ld,
+                           double* weights, double* stats_dev, void* stream, int mode) {
+    Channel ch;
+    int st = make_channel(M, masses, n, &ch);
+    if (st != HYDRA_PHSP_OK) return st;
+    if (nevents > 0 && (out == nullptr || weights == nullptr))
+        return fail(HYDRA_PHSP_EINVAL, "p4_out_dev and weights_dev are required");
+    if (ld < nevents) return fail(HYDRA_PHSP_EINVAL, "ld must be >= nevents");
+    if (parent_p4_host != nullptr && parent_p4_dev != nullptr)
+        return fail(HYDRA_PHSP_EINVAL, "give at most one of parent_p4_host and parent_p4_dev");
+    int pmode = kAtRest;
+    Frame frame;
+    std::memset(&frame, 0, sizeof(frame));
+    if (parent_p4_host != nullptr) {
+        st = make_frame(M, parent_p4_host, &frame);
+        if (st != HYDRA_PHSP_OK) return st;
+        pmode = kBroadcast;
+    } else if (parent_p4_dev != nullptr) {
+        if (ld_parent < nevents) return fail(HYDRA_PHSP_EINVAL, "ld_parent must be >= nevents");
+        pmode = kPerEvent;
+    }
+    return run_single(ch, n, pmode, &frame, parent_p4_dev, ld_parent, nevents, seed, sid, offset, mode,
+                      out, ld, weights, stats_dev, (hipStream_t)stream, 0);
+}
+
+} // namespace hphsp
+
+using namespace hphsp;
+
+extern "C" {
+
+int hydra_phsp_generate(double parent_mass, const double* masses_host, int n_daughters,
+                        const double* parent_p4_host, const double* parent_p4_dev, uint64_t ld_parent,
+                        uint64_t nevents, uint64_t seed, uint32_t stream_id, uint64_t event_offset,
+                        double* p4_out_dev, uint64_t ld, double* weights_dev, double* stats_dev,
+                        void* stream) {
+    return generate_common(parent_mass, masses_host, n_daughters, parent_p4_host, parent_p4_dev,
+                           ld_parent, nevents, seed, stream_id, event_offset, p4_out_dev, ld,
+                           weights_dev, stats_dev, stream, kFp64);
+}
+
+int hydra_phsp_generate_mixed(double parent_mass, const double* masses_host, int n_daughters,
+                              const double* parent_p4_host, const double* parent_p4_dev,
+                              uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t stream_id,
+                              uint64_t event_offset, float* p4_out_dev, uint64_t ld,
+                              double* weights_dev, double* stats_dev, void* stream) {
+    return generate_common(parent_mass, masses_host, n_daughters, parent_p4_host, parent_p4_dev,
+                           ld_parent, nevents, seed, stream_id, event_offset, p4_out_dev, ld,
+                           weights_dev, stats_dev, stream, kMixed);
+}
+
+int hydra_phsp_integrate_async(double parent_mass, const double* masses_host, int n_daughters,
+                               uint64_t nevents, uint64_t seed, uint32_t stream_id,
+                               uint64_t event_offset, double* stats_dev, void* stream) {
+    Channel ch;
+    int st = make_channel(parent_mass, masses_host, n_daughters, &ch);
+    if (st != HYDRA_PHSP_OK) return st;
+    if (stats_dev == nullptr) return fail(HYDRA_PHSP_EINVAL, "stats_dev is NULL");
+    return run_single(ch, n_daughters, kAtRest, nullptr, nullptr, 0, nevents, seed, stream_id,
+                      event_offset, kIntegrate, nullptr, 0, nullptr, stats_dev, (hipStream_t)stream, 0);
+}
+
+int hydra_phsp_integrate(double parent_mass, const double* masses_host, int n_daughters,
+                         uint64_t nevents, uint64_t seed, uint32_t stream_id, uint64_t event_offset,
+                         double* mean_host, double* sigma_host, void* stream) {
+    Channel ch;
+    int st = make_channel(parent_mass, masses_host, n_daughters, &ch);
+    if (st != HYDRA_PHSP_OK) return st;
+    if (mean_host == nullptr || sigma_host == nullptr)
+        return fail(HYDRA_PHSP_EINVAL, "mean_host and sigma_host are required");
+    if (nevents < 2) return fail(HYDRA_PHSP_EINVAL, "integrate needs nevents >= 2");
+    hipStream_t s = (hipStream_t)stream;
+    Workspace* ws = nullptr;
+    st = workspace_for(s, 1, &ws);
+    if (st != HYDRA_PHSP_OK) return st;
+    st = run_single(ch, n_daughters, kAtRest, nullptr, nullptr, 0, nevents, seed, stream_id, event_offset,
+                    kIntegrate, nullptr, 0, nullptr, ws->stats_dev, s, 0);
+    if (st != HYDRA_PHSP_OK) return st;
+    hipError_t e = hipMemcpyAsync(ws->stats_host, ws->stats_dev, sizeof(double) * HYDRA_PHSP_STATS,
+                                  hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+    *mean_host = ws->stats_host[1];
+    *sigma_host = ws->stats_host[3];
+    return HYDRA_PHSP_OK;
+}
+
+const char* hydra_phsp_strerror(int status) {
+    switch (status) {
+    case HYDRA_PHSP_OK: return "ok";
+    case HYDRA_PHSP_EINVAL: return "invalid argument";
+    case HYDRA_PHSP_EKINEMATICS: return "kinematically forbidden decay (parent mass <= sum of daughter masses)";
+    case HYDRA_PHSP_ENOMEM: return "out of memory";
+    case HYDRA_PHSP_EDEVICE: return "HIP device error";
+    case HYDRA_PHSP_EAGAIN: return "result not ready";
+    case HYDRA_PHSP_ENOTFOUND: return "unknown request id";
+    default: return "unknown status";
+    }
+}
+
+const char* hydra_phsp_last_error(void) { return t_last_error.c_str(); }
+
+int hydra_phsp_abi_version(void) { return HYDRA_PHSP_ABI_VERSION; }
+
+int hydra_phsp_release(void) { return release_workspaces(); }
+
+int hydra_phsp_timing_enable(int on) {
+    std::lock_guard<std::mutex> lock(g_timing.mu);
+    g_timing.on = on != 0;
+    return HYDRA_PHSP_OK;
+}
+
+int hydra_phsp_timing_reset(void) {
+    std::lock_guard<std::mutex> lock(g_timing.mu);
+    g_timing.used = 0;
+    return HYDRA_PHSP_OK;
+}
+
+int hydra_phsp_timing_read(double* total_ms_host, uint64_t* launches_host) {
+    if (total_ms_host == nullptr || launches_host == nullptr)
+        return fail(HYDRA_PHSP_EINVAL, "timing_read needs two host pointers");
+    std::lock_guard<std::mutex> lock(g_timing.mu);
+    double total = 0.0;
+    for (size_t i = 0; i < g_timing.used; ++i) {
+        hipError_t e = hipEventSynchronize(g_timing.pool[i].second);
+        if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, g_timing.pool[i].first, g_timing.pool[i].second);
+        if (e != hipSuccess) return fail_hip(e, "hipEventElapsedTime");
+        total += (double)ms;
+    }
+    *total_ms_host = total;
+    *launches_host = (uint64_t)g_timing.used;
+    return HYDRA_PHSP_OK;
+}
+
+int hydra_phsp_selftest_sortnet(void) {
+    bool ok = true;
+    auto check = [&](auto tag) {
+        constexpr int K = decltype(tag)::value;
+        for (int bits = 0; bits < (1 << K); ++bits) {
+            int v[K > 0 ? K : 1];
+            for (int i = 0; i < K; ++i) v[i] = (bits >> i) & 1;
+            sortnet_sort<K, int>(v);
+            for (int i = 0; i + 1 < K; ++i)
+                if (v[i] > v[i + 1]) ok = false;
+        }
+    };
+    check(std::integral_constant<int, 1>{});
+    check(std::integral_constant<int, 2>{});
+    check(std::integral_constant<int, 3>{});
+    check(std::integral_constant<int, 4>{});
+    check(std::integral_constant<int, 5>{});
+    check(std::integral_constant<int, 6>{});
+    check(std::integral_constant<int, 7>{});
+    check(std::integral_constant<int, 8>{});
+    return ok ? HYDRA_PHSP_OK : fail(HYDRA_PHSP_EINVAL, "sorting network self-test failed");
+}
+
+} // extern "C"

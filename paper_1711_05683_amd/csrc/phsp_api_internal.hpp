@@ -1,0 +1,28 @@
+// phsp_api_internal.hpp -- host helpers shared by the library's C-ABI units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "phsp_device.hpp"
+
+namespace hphsp {
+
+int fail(int status, const std::string& msg);
+int fail_hip(hipError_t e, const char* what);
+// Validate (M, masses, n) and fill the per-channel constants.
+int make_channel(double M, const double* masses, int n, Channel* out);
+// Validate a parent four-vector of mass M and fill its boost.
+int make_frame(double M, const double* p4, Frame* f);
+// Single-channel launch with a given events-per-thread (0 = default).
+int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const double* parent_dev,
+               uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
+               int mode, void* out, uint64_t ld, double* weights, double* stats_dev, hipStream_t stream,
+               int ept_override);
+int release_workspaces();
+// Benchmark timing brackets around a kernel launch (slot -1: timing off).
+long timing_begin(hipStream_t stream);
+void timing_end(hipStream_t stream, long slot);
+
+} // namespace hphsp

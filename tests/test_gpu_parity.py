@@ -1,0 +1,303 @@
+"""GPU parity: the HIP library (called through its C ABI) against the CPU oracle.
+
+Every case runs the same seeded inputs through both sides and compares event by
+event (FP64: |dc| <= 1e-11 E_d, weights and integrals <= 1e-11 relative), over
+sizes that span many blocks with ragged tails; the full-size configurations are
+checked on sampled events that the oracle computes one by one, plus properties
+that hold at any size.
+"""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from parity import FP64_TOL, MIXED_TOL, MIXED_INTEGRAL_TOL, assert_events_close, event_errors, rel
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*args):
+    print("[parity]", *args, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_1711_05683_amd as P
+    P.lib()  # raises if the HIP library is missing: no fallback
+    oracle.build(force=False)
+    return P
+
+
+def _run(P, M, masses, nevents, seed=42, stream_id=0, offset=0, parent_p4=None, parent_dev=None,
+         mixed=False, ld=None):
+    n = len(masses)
+    dtype = torch.float32 if mixed else torch.float64
+    out = torch.empty((n, 4, ld or max(nevents, 1)), dtype=dtype, device="cuda")
+    w = torch.empty(max(nevents, 1), dtype=torch.float64, device="cuda")
+    _, _, stats = P.generate(M, masses, nevents, seed=seed, stream_id=stream_id, event_offset=offset,
+                             parent_p4=parent_p4, parent_dev=parent_dev, out=out, weights=w,
+                             mixed=mixed)
+    torch.cuda.synchronize()
+    return out[:, :, :nevents].cpu().numpy(), w[:nevents].cpu().numpy(), stats.cpu().numpy()
+
+
+CFG0 = (5.279, [3.097, 0.4937, 0.13957])
+
+
+def test_config0_full_event_by_event(P):
+    _say("config0 1e5 N=3")
+    M, m = CFG0
+    p4, w, st = _run(P, M, m, 100_000)
+    p4o, wo = oracle.generate(M, m, 100_000, seed=42)
+    assert_events_close(p4, w, p4o, wo)
+    mo, so = oracle.integrate(M, m, 100_000, seed=42)
+    assert st[0] == 100_000
+    assert rel(st[1], mo) <= FP64_TOL and rel(st[3], so) <= FP64_TOL
+
+
+def test_config0_massless(P):
+    _say("config0 massless M=1")
+    p4, w, st = _run(P, 1.0, [0.0, 0.0, 0.0], 100_000)
+    p4o, wo = oracle.generate(1.0, [0.0] * 3, 100_000, seed=42)
+    assert_events_close(p4, w, p4o, wo)
+    mo, so = oracle.integrate(1.0, [0.0] * 3, 100_000, seed=42)
+    assert rel(st[1], mo) <= FP64_TOL and rel(st[3], so) <= FP64_TOL
+    assert abs(st[1] - math.pi ** 2 / 8) < 4 * st[3]
+
+
+def _random_masses(n, seed):
+    rng = np.random.default_rng(seed)
+    M = float(rng.uniform(2.0, 12.0))
+    return M, [float(x) for x in rng.uniform(0.0, 0.4 * M / n, size=n)]
+
+
+@pytest.mark.parametrize("n", list(range(2, 11)))
+@pytest.mark.parametrize("pmode", ["rest", "broadcast", "per_event"])
+def test_n_sweep(P, n, pmode):
+    _say(f"n_sweep N={n} parent={pmode}")
+    M, m = _random_masses(n, 1000 + n)
+    nev = 10_007
+    parent_p4 = None
+    parent_dev = None
+    parent_soa = None
+    if pmode == "broadcast":
+        p = np.array([0.3, -1.1, 2.5])
+        parent_p4 = [math.sqrt(M * M + float(p @ p)), *p]
+    elif pmode == "per_event":
+        from paper_1711_05683_amd.workloads import per_event_parents
+        parent_dev = per_event_parents(M, nev)
+        parent_soa = parent_dev.cpu().numpy()
+    p4, w, st = _run(P, M, m, nev, seed=7 + n, stream_id=n, offset=123_456_789, parent_p4=parent_p4,
+                     parent_dev=parent_dev)
+    p4o, wo = oracle.generate(M, m, nev, seed=7 + n, stream_id=n, event_offset=123_456_789,
+                              parent_p4=parent_p4, parent_soa=parent_soa)
+    assert_events_close(p4, w, p4o, wo)
+    mo, so = oracle.integrate(M, m, nev, seed=7 + n, stream_id=n, event_offset=123_456_789)
+    assert rel(st[1], mo) <= FP64_TOL
+    if n > 2:
+        assert rel(st[3], so) <= FP64_TOL
+
+
+@pytest.mark.parametrize("n", [2, 3, 6, 10])
+def test_integrate_matches_oracle(P, n):
+    _say(f"integrate N={n}")
+    M, m = _random_masses(n, 2000 + n)
+    for nev in (2, 3, 255, 256, 257, 100_003):
+        mean, sigma = P.integrate(M, m, nev, seed=5, stream_id=1, event_offset=99)
+        mo, so = oracle.integrate(M, m, nev, seed=5, stream_id=1, event_offset=99)
+        assert rel(mean, mo) <= FP64_TOL, (nev, mean, mo)
+        # sigma of identical (two-body) weights is 0 up to the rounding of the
+        # oracle's compensated mean, so an absolute floor of 1e-15 mean applies
+        assert abs(sigma - so) <= FP64_TOL * so + 1e-15 * mo, (nev, sigma, so)
+
+
+def test_two_body_sigma_is_exactly_zero(P):
+    _say("two-body sigma")
+    p4, w, st = _run(P, 5.279, [3.097, 0.4937], 70_001)
+    assert np.all(w == w[0])
+    assert st[2] == 0.0 and st[3] == 0.0 and st[1] == w[0]
+    mean, sigma = P.integrate(5.279, [3.097, 0.4937], 70_001)
+    assert sigma == 0.0 and mean == w[0]
+    wo = oracle.generate(5.279, [3.097, 0.4937], 10, seed=42, want_momenta=False)[1]
+    assert rel(w[0], wo[0]) <= FP64_TOL
+
+
+@pytest.mark.parametrize("nev", [0, 1, 2, 63, 64, 65, 255, 256, 257, 511, 513, 1023, 1025])
+def test_edge_sizes(P, nev):
+    _say(f"edge size {nev}")
+    M, m = CFG0
+    p4, w, st = _run(P, M, m, nev, offset=31)
+    assert st[0] == nev
+    if nev == 0:
+        assert st[1] == 0.0 and st[3] == 0.0
+        return
+    p4o, wo = oracle.generate(M, m, nev, seed=42, event_offset=31)
+    assert_events_close(p4, w, p4o, wo)
+    assert rel(st[1], float(np.mean(wo))) <= 1e-13
+    if nev >= 2:
+        mo, so = oracle.integrate(M, m, nev, seed=42, event_offset=31)
+        assert rel(st[1], mo) <= FP64_TOL and rel(st[3], so) <= FP64_TOL
+    else:
+        assert st[3] == 0.0 and st[1] == w[0]
+
+
+def test_padding_beyond_nevents_untouched(P):
+    _say("ld padding")
+    M, m = CFG0
+    nev, ld = 1000, 1536
+    out = torch.full((3, 4, ld), float("nan"), dtype=torch.float64, device="cuda")
+    wt = torch.full((ld,), float("nan"), dtype=torch.float64, device="cuda")
+    P.generate(M, m, nev, out=out, weights=wt)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.all(np.isfinite(o[:, :, :nev])) and np.all(np.isnan(o[:, :, nev:]))
+    ww = wt.cpu().numpy()
+    assert np.all(np.isfinite(ww[:nev])) and np.all(np.isnan(ww[nev:]))
+
+
+def test_determinism_and_chunking(P):
+    _say("determinism")
+    M, m = CFG0
+    p4a, wa, sa = _run(P, M, m, 300_000)
+    p4b, wb, sb = _run(P, M, m, 300_000)
+    assert np.array_equal(p4a, p4b) and np.array_equal(wa, wb) and np.array_equal(sa, sb)
+    p41, w1, _ = _run(P, M, m, 123_457, offset=0)
+    p42, w2, _ = _run(P, M, m, 300_000 - 123_457, offset=123_457)
+    assert np.array_equal(np.concatenate([p41, p42], axis=2), p4a)
+    assert np.array_equal(np.concatenate([w1, w2]), wa)
+
+
+def test_near_threshold(P):
+    _say("near threshold")
+    m = [0.13957, 0.13957, 0.13957, 0.4937]
+    M = sum(m) * (1.0 + 1e-7)
+    p4, w, st = _run(P, M, m, 20_000)
+    p4o, wo = oracle.generate(M, m, 20_000, seed=42)
+    assert_events_close(p4, w, p4o, wo)
+
+
+def test_non_default_stream(P):
+    _say("side stream")
+    M, m = CFG0
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out, w, st = P.generate(M, m, 5000, seed=3)
+    s.synchronize()
+    p4o, wo = oracle.generate(M, m, 5000, seed=3)
+    assert_events_close(out.cpu().numpy(), w.cpu().numpy(), p4o, wo)
+
+
+@pytest.mark.parametrize("n,M,masses", [(3, 5.279, [3.097, 0.4937, 0.13957]), (6, 10.0, [0.13957] * 6),
+                                        (6, 10.0, [0.0] * 6), (10, 10.0, [0.13957] * 10)])
+def test_mixed_precision(P, n, M, masses):
+    _say(f"mixed N={n}")
+    nev = 200_000
+    p4, w, st = _run(P, M, masses, nev, mixed=True)
+    p4d, wd, sd = _run(P, M, masses, nev)
+    # FP64 prologue: weights and integral are bit-identical to the FP64 path
+    assert np.array_equal(w, wd) and np.array_equal(st, sd)
+    p4o, wo = oracle.generate(M, masses, nev, seed=42)
+    err = event_errors(p4, p4o)
+    _say(f"mixed N={n} max |dc|/E per daughter: {err}")
+    assert np.all(err <= MIXED_TOL), err
+    mo, so = oracle.integrate(M, masses, nev, seed=42)
+    assert rel(st[1], mo) <= MIXED_INTEGRAL_TOL
+
+
+# ------------------------------------------------------------ full sizes ----
+
+def _sample_indices(nev, k=1500, seed=0):
+    rng = np.random.default_rng(seed)
+    idx = np.concatenate([np.arange(min(500, nev)), np.arange(max(nev - 500, 0), nev),
+                          rng.integers(0, nev, size=k)])
+    return np.unique(idx)
+
+
+def _check_samples(P, out, w, M, m, idx, seed=42, parent_soa=None, tol=FP64_TOL):
+    n = len(m)
+    ti = torch.as_tensor(idx, device="cuda")
+    g = out[:, :, ti].cpu().numpy()
+    gw = w[ti].cpu().numpy()
+    worst = np.zeros(n)
+    for j, e in enumerate(idx):
+        ps = None if parent_soa is None else parent_soa[:, j:j + 1]
+        p4o, wo = oracle.generate(M, m, 1, seed=seed, event_offset=int(e), parent_soa=ps)
+        err = event_errors(g[:, :, j:j + 1], p4o)
+        worst = np.maximum(worst, err)
+        assert abs(gw[j] - wo[0]) <= FP64_TOL * wo[0], (e, gw[j], wo[0])
+    assert np.all(worst <= tol), worst
+    return worst
+
+
+def test_full_size_config1_at_rest(P):
+    _say("config1 1e8 at rest")
+    M, m = CFG0
+    nev = 100_000_000
+    out, w, st = P.generate(M, m, nev)
+    torch.cuda.synchronize()
+    s = st.cpu().numpy()
+    assert s[0] == nev
+    _check_samples(P, out, w, M, m, _sample_indices(nev))
+    # the full integral against the quadrature volume, and against a chunked run
+    import volumes
+    exact = volumes.three_body_volume_1d(M, *m)
+    assert abs(s[1] - exact) < 4 * s[3], (s, exact)
+    wsum = torch.sum(w).item()
+    assert rel(s[1], wsum / nev) <= 1e-12
+    del out
+    # integrate-only at 1e7 against the oracle's compensated two-pass integral
+    mean, sigma = P.integrate(M, m, 10_000_000)
+    mo, so = oracle.integrate(M, m, 10_000_000, seed=42)
+    assert rel(mean, mo) <= FP64_TOL and rel(sigma, so) <= FP64_TOL
+
+
+def test_full_size_config1_per_event_parent(P):
+    _say("config1 1e8 per-event parents")
+    from paper_1711_05683_amd.workloads import per_event_parents
+    M, m = CFG0
+    nev = 100_000_000
+    parents = per_event_parents(M, nev)
+    out, w, st = P.generate(M, m, nev, parent_dev=parents)
+    torch.cuda.synchronize()
+    idx = _sample_indices(nev, seed=1)
+    soa = parents[:, torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    _check_samples(P, out, w, M, m, idx, parent_soa=soa)
+    # weights do not depend on the parent's motion
+    w_rest = torch.empty(nev, dtype=torch.float64, device="cuda")
+    o2 = torch.empty((3, 4, nev), dtype=torch.float64, device="cuda")
+    del out
+    P.generate(M, m, nev, out=o2, weights=w_rest)
+    torch.cuda.synchronize()
+    assert torch.equal(w, w_rest)
+
+
+@pytest.mark.parametrize("masses", [[0.13957] * 6, [0.0] * 6])
+def test_full_size_config2(P, masses):
+    _say(f"config2 5e7 N=6 masses={masses[0]}")
+    M = 10.0
+    nev = 50_000_000
+    out, w, st = P.generate(M, masses, nev)
+    torch.cuda.synchronize()
+    idx = _sample_indices(nev, k=800, seed=2)
+    _check_samples(P, out, w, M, masses, idx)
+    del out
+    outm, wm, stm = P.generate(M, masses, nev, mixed=True)
+    torch.cuda.synchronize()
+    assert torch.equal(w, wm) and torch.equal(st, stm)
+    ti = torch.as_tensor(idx, device="cuda")
+    g = outm[:, :, ti].cpu().numpy()
+    worst = np.zeros(6)
+    for j, e in enumerate(idx):
+        p4o, _ = oracle.generate(M, masses, 1, seed=42, event_offset=int(e))
+        worst = np.maximum(worst, event_errors(g[:, :, j:j + 1], p4o))
+    _say(f"config2 mixed max |dc|/E: {worst}")
+    assert np.all(worst <= MIXED_TOL)

@@ -39,7 +39,8 @@ def kernel_source_hash() -> str:
     """Hash of the sources the main kernel is built from (invalidates stale counters)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1711_05683_amd", "csrc")
-    for name in ("phsp_device.hpp", "phsp_sortnet.hpp", "phsp_kernels.hpp", "phsp_inst.hip"):
+    for name in ("phsp_device.hpp", "phsp_sortnet.hpp", "phsp_reduce.hpp", "phsp_kernels.hpp",
+                 "phsp_inst.hip"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -64,7 +65,7 @@ def read_traffic():
         return None
 
 
-def cpu_baseline(target_s: float = 10.0, chunk: int = 1_000_000, max_events: int = 30_000_000):
+def cpu_baseline(target_s: float = 10.0, chunk: int = 1_000_000, max_events: int = 100_000_000):
     """The CPU oracle (single thread) on a bounded sample of the same workload."""
     import oracle
     oracle.build(force=False)
@@ -234,7 +235,42 @@ def extras(P, torch, dev, args):
     ex["cfg2_six_pion_mixed"] = {"events_per_s": n2 / (ms * 1e-3), "kernel_ms": kms,
                                  "write_GBs": 104 * n2 / (kms * 1e-3) / 1e9}
     del outm, w
+    ex["cfg3_batched_64_channels"] = batched_extra(P, torch, dev, steps)
     return ex
+
+
+def batched_extra(P, torch, dev, steps):
+    """64 channels of uneven N and size in one persistent launch (autotuned shape,
+    HIP-graph replay); kernel time from a direct launch of the same shape."""
+    from paper_1711_05683_amd.workloads import batched_channels
+    specs = batched_channels()
+    total_events = sum(c.nevents for c in specs)
+    total_bytes = sum(c.nevents * (4 * c.n + 1) * 8 for c in specs)
+    keep, descs = [], []
+    for c in specs:
+        out = torch.empty((c.n, 4, c.nevents), dtype=torch.float64, device=dev)
+        w = torch.empty(c.nevents, dtype=torch.float64, device=dev)
+        st = torch.empty(4, dtype=torch.float64, device=dev)
+        keep.append((out, w, st))
+        descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id,
+                               out=out, weights=w, stats=st))
+    t0 = time.perf_counter()
+    ept, gpc, tuned_ms = P.autotune(descs)
+    tune_s = time.perf_counter() - t0
+    plan = P.Plan(descs, ept=ept, grid_per_cu=gpc)
+    ms_graph, _ = time_steps(plan.launch, steps, 1, torch)
+    ms_direct, kms = time_steps(lambda: P.batch_run(descs, ept=ept, grid_per_cu=gpc), steps, 1, torch)
+    ntiles, grid = plan.info()
+    plan.destroy()
+    P.release()
+    del keep
+    return {"channels": len(specs), "events": total_events, "bytes": total_bytes,
+            "tuning": {"ept": ept, "grid_per_cu": gpc, "autotune_s": tune_s, "tiles": ntiles,
+                       "grid": grid},
+            "events_per_s_graph": total_events / (ms_graph * 1e-3), "ms_per_step_graph": ms_graph,
+            "kernel_ms": kms, "kernel_write_GBs": total_bytes / (kms * 1e-3) / 1e9,
+            "kernel_frac_of_8TBs": total_bytes / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "ms_per_step_direct": ms_direct}
 
 
 if __name__ == "__main__":

@@ -138,6 +138,12 @@ int hydra_phsp_abi_version(void);
 /* Host-side self-test of the in-register sorting networks (0-1 principle over
  * every network the kernels use); returns HYDRA_PHSP_OK when all sort. */
 int hydra_phsp_selftest_sortnet(void);
+/* Events per thread of the single-channel kernels, per path: path 0 =
+ * integrate-only, 1 = FP64 generate, 2 = mixed generate; ept in {1, 2, 4}, or 0
+ * for the library default.  Process-wide; changes the launch shape only (events
+ * are bit-identical for every value; integrals agree to rounding). */
+int hydra_phsp_set_events_per_thread(int path, int ept);
+
 /* Kernel timing for benchmarks: while enabled, every launch of the main
  * phase-space kernel is bracketed by HIP events recorded on the caller's
  * stream.  hydra_phsp_timing_read synchronises those events and returns the

@@ -1,0 +1,86 @@
+/*
+ * hydra_phsp_batch.h -- batched multi-channel phase-space generation.
+ *
+ * Many decay channels of uneven daughter count and event count run in one
+ * persistent kernel launch (the phase-space generator of arXiv:1711.05683
+ * sec. 4.2, applied to many (M, masses) pairs at once).  Conventions,
+ * layouts, ownership and error codes are those of hydra_phsp.h.
+ */
+#ifndef HYDRA_PHSP_BATCH_H
+#define HYDRA_PHSP_BATCH_H
+
+#include <stdint.h>
+
+#include "hydra_phsp.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One decay channel: the arguments of one hydra_phsp_generate call with the
+ * parent at rest.  p4_out_dev and weights_dev both NULL means integrate-only.
+ * stats_dev (HYDRA_PHSP_STATS doubles, device) is required.  Each channel's
+ * events and weights are bit-identical to a single-channel call with the same
+ * (masses, seed, stream_id, event_offset); its stats are bit-identical too when
+ * the single-channel call ran with the same events per thread (see
+ * hydra_phsp_set_events_per_thread), and agree to rounding otherwise. */
+typedef struct hydra_phsp_channel {
+    double parent_mass;
+    double masses[HYDRA_PHSP_NMAX];
+    int32_t n_daughters;
+    uint32_t stream_id;
+    uint64_t nevents;
+    uint64_t seed;
+    uint64_t event_offset;
+    double *p4_out_dev;  /* [n][4][ld] or NULL */
+    uint64_t ld;
+    double *weights_dev; /* [nevents] or NULL */
+    double *stats_dev;   /* HYDRA_PHSP_STATS doubles */
+} hydra_phsp_channel;
+
+/* Launch shape of the persistent kernel (blocks of 256 threads):
+ *   ept          events per thread: 1, 2 or 4 (a tile is 256*ept events);
+ *   grid_per_cu  persistent blocks per compute unit, 1 .. 64.
+ * A zero field selects the library default (ept 1, grid_per_cu 8). */
+typedef struct hydra_phsp_tuning {
+    int32_t ept;
+    int32_t grid_per_cu;
+    int32_t reserved[2];
+} hydra_phsp_tuning;
+
+/* Enqueue one batch on `stream`: validates every channel (no work is enqueued
+ * if any channel is invalid; *bad_channel_out, when not NULL, receives the
+ * index of the first bad one), uploads the tile table and launches the
+ * persistent kernel and the per-channel merges.  The device tables stay alive
+ * until the next hydra_phsp_batch_run on the same stream, which first waits
+ * for this one.  tuning may be NULL. */
+int hydra_phsp_batch_run(const hydra_phsp_channel *channels, int n_channels,
+                         const hydra_phsp_tuning *tuning, void *stream, int *bad_channel_out);
+
+/* A reusable batch: tables are built and uploaded once and the launch sequence
+ * (persistent kernel + per-channel merges) is captured into a HIP graph that
+ * hydra_phsp_plan_launch replays on any stream.  The channels, including their
+ * device pointers, are fixed at creation.  One plan's launches must not
+ * overlap each other. */
+typedef struct hydra_phsp_plan hydra_phsp_plan;
+int hydra_phsp_plan_create(const hydra_phsp_channel *channels, int n_channels,
+                           const hydra_phsp_tuning *tuning, hydra_phsp_plan **plan_out);
+int hydra_phsp_plan_launch(hydra_phsp_plan *plan, void *stream);
+/* Waits for the plan's outstanding launches, then frees it. */
+int hydra_phsp_plan_destroy(hydra_phsp_plan *plan);
+/* Number of tiles and the persistent grid size of a plan (host). */
+int hydra_phsp_plan_info(const hydra_phsp_plan *plan, uint64_t *ntiles_out, uint64_t *grid_out);
+
+/* Autotuner: times the persistent kernel over events per thread {1, 2, 4} x
+ * blocks per compute unit {1, 2, 4, 8, 16} on this batch (running it several
+ * times and overwriting its outputs) and returns the fastest shape and its
+ * time in ms.  Results are cached per device and batch shape class for the
+ * life of the process; a cached answer is returned without running. */
+int hydra_phsp_autotune(const hydra_phsp_channel *channels, int n_channels, void *stream,
+                        hydra_phsp_tuning *best_out, double *best_ms_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYDRA_PHSP_BATCH_H */

@@ -56,6 +56,8 @@ def _declare(lib):
     lib.hydra_phsp_selftest_sortnet.restype = i
     lib.hydra_phsp_release.argtypes = []
     lib.hydra_phsp_release.restype = i
+    lib.hydra_phsp_set_events_per_thread.argtypes = [i, i]
+    lib.hydra_phsp_set_events_per_thread.restype = i
     lib.hydra_phsp_timing_enable.argtypes = [i]
     lib.hydra_phsp_timing_enable.restype = i
     lib.hydra_phsp_timing_reset.argtypes = []
@@ -73,6 +75,7 @@ def lib():
                                "`python -m paper_1711_05683_amd.build` (no CPU fallback exists)")
         handle = ctypes.CDLL(LIB_PATH)
         _declare(handle)
+        _declare_batch(handle)
         _lib = handle
     return _lib
 
@@ -178,6 +181,11 @@ def release():
     _check(lib().hydra_phsp_release())
 
 
+def set_events_per_thread(path: int, ept: int):
+    """Events per thread for path 0 (integrate), 1 (FP64) or 2 (mixed); 0 = default."""
+    _check(lib().hydra_phsp_set_events_per_thread(path, ept))
+
+
 def timing_enable(on: bool = True):
     """Bracket every main-kernel launch with HIP events on its stream."""
     _check(lib().hydra_phsp_timing_enable(1 if on else 0))
@@ -190,3 +198,124 @@ def timing_read():
     k = ctypes.c_uint64()
     _check(lib().hydra_phsp_timing_read(ctypes.byref(ms), ctypes.byref(k)))
     return ms.value, k.value
+
+
+# ----------------------------------------------------------------- batched ----
+
+class ChannelDesc(ctypes.Structure):
+    """``hydra_phsp_channel`` (include/hydra_phsp_batch.h)."""
+    _fields_ = [("parent_mass", ctypes.c_double), ("masses", ctypes.c_double * NMAX),
+                ("n_daughters", ctypes.c_int32), ("stream_id", ctypes.c_uint32),
+                ("nevents", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("event_offset", ctypes.c_uint64), ("p4_out_dev", ctypes.c_void_p),
+                ("ld", ctypes.c_uint64), ("weights_dev", ctypes.c_void_p),
+                ("stats_dev", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    """``hydra_phsp_tuning``: events per thread and persistent blocks per CU (0 = default)."""
+    _fields_ = [("ept", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+def _declare_batch(lib):
+    c = ctypes
+    i, vp = c.c_int, c.c_void_p
+    chp = c.POINTER(ChannelDesc)
+    tp = c.POINTER(Tuning)
+    lib.hydra_phsp_batch_run.argtypes = [chp, i, tp, vp, c.POINTER(c.c_int)]
+    lib.hydra_phsp_batch_run.restype = i
+    lib.hydra_phsp_plan_create.argtypes = [chp, i, tp, c.POINTER(c.c_void_p)]
+    lib.hydra_phsp_plan_create.restype = i
+    lib.hydra_phsp_plan_launch.argtypes = [vp, vp]
+    lib.hydra_phsp_plan_launch.restype = i
+    lib.hydra_phsp_plan_destroy.argtypes = [vp]
+    lib.hydra_phsp_plan_destroy.restype = i
+    lib.hydra_phsp_plan_info.argtypes = [vp, c.POINTER(c.c_uint64), c.POINTER(c.c_uint64)]
+    lib.hydra_phsp_plan_info.restype = i
+    lib.hydra_phsp_autotune.argtypes = [chp, i, vp, tp, c.POINTER(c.c_double)]
+    lib.hydra_phsp_autotune.restype = i
+
+
+def channel(parent_mass: float, masses: Sequence[float], nevents: int, *, seed: int = 42,
+            stream_id: int = 0, event_offset: int = 0, out: Optional[torch.Tensor] = None,
+            weights: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None) -> ChannelDesc:
+    """Describe one batch channel; out/weights None together = integrate-only."""
+    d = ChannelDesc()
+    d.parent_mass = float(parent_mass)
+    for k, mk in enumerate(masses):
+        d.masses[k] = float(mk)
+    d.n_daughters = len(masses)
+    d.stream_id = stream_id
+    d.nevents = nevents
+    d.seed = seed
+    d.event_offset = event_offset
+    d.p4_out_dev = None if out is None else out.data_ptr()
+    d.ld = 0 if out is None else out.shape[-1]
+    d.weights_dev = None if weights is None else weights.data_ptr()
+    d.stats_dev = None if stats is None else stats.data_ptr()
+    return d
+
+
+def _channel_array(chans):
+    arr = (ChannelDesc * len(chans))(*chans)
+    return arr
+
+
+def _tuning(ept=0, grid_per_cu=0):
+    t = Tuning()
+    t.ept = ept
+    t.grid_per_cu = grid_per_cu
+    return t
+
+
+def batch_run(chans, *, ept: int = 0, grid_per_cu: int = 0, stream=None):
+    """Enqueue one batch (all channels in one persistent launch)."""
+    L = lib()
+    arr = _channel_array(chans)
+    bad = ctypes.c_int(-1)
+    t = _tuning(ept, grid_per_cu)
+    st = L.hydra_phsp_batch_run(arr, len(chans), ctypes.byref(t), _stream_handle(stream), ctypes.byref(bad))
+    if st != OK:
+        msg = L.hydra_phsp_last_error().decode(errors="replace")
+        raise PhspError(st, f"channel {bad.value}: {msg}")
+
+
+class Plan:
+    """A batch captured into a HIP graph; launch() replays it."""
+
+    def __init__(self, chans, *, ept: int = 0, grid_per_cu: int = 0):
+        L = lib()
+        arr = _channel_array(chans)
+        t = _tuning(ept, grid_per_cu)
+        h = ctypes.c_void_p()
+        _check(L.hydra_phsp_plan_create(arr, len(chans), ctypes.byref(t), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().hydra_phsp_plan_launch(self._h, _stream_handle(stream)))
+
+    def info(self):
+        nt, g = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().hydra_phsp_plan_info(self._h, ctypes.byref(nt), ctypes.byref(g)))
+        return nt.value, g.value
+
+    def destroy(self):
+        if self._h:
+            _check(lib().hydra_phsp_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def autotune(chans, stream=None):
+    """(ept, grid_per_cu, ms) of the fastest persistent-kernel shape for this batch."""
+    t = Tuning()
+    ms = ctypes.c_double()
+    _check(lib().hydra_phsp_autotune(_channel_array(chans), len(chans), _stream_handle(stream),
+                                     ctypes.byref(t), ctypes.byref(ms)))
+    return t.ept, t.grid_per_cu, ms.value

@@ -25,11 +25,17 @@ LIB_PATH = os.path.join(PKG, LIB_NAME)
 
 ARCH = "gfx950"
 NS = range(2, 11)
+BATCH_NMAX = (8, 10)
+BATCH_EPT = (1, 2, 4)
 
 # Packed FP32 instructions are disabled for every HIP unit; the host pass warns
-# that it does not know the feature, which is harmless.
+# that it does not know the feature, which is harmless.  Floating-point
+# contraction is off: every multiply-add that should fuse is written as an
+# explicit fma, so an event's arithmetic does not depend on the kernel it is
+# inlined into (single-channel, batched and every events-per-thread variant give
+# bit-identical events).
 HIP_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
+    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
     f"-I{INCLUDE}", f"-I{CSRC}",
@@ -49,8 +55,13 @@ def _units():
     for n in NS:
         units.append((os.path.join(CSRC, "phsp_inst.hip"),
                       os.path.join(BUILD_DIR, f"phsp_inst_n{n}.o"), [f"-DPHSP_N={n}"]))
+    for nmax in BATCH_NMAX:
+        for ept in BATCH_EPT:
+            units.append((os.path.join(CSRC, "phsp_batch_inst.hip"),
+                          os.path.join(BUILD_DIR, f"phsp_batch_inst_n{nmax}_e{ept}.o"),
+                          [f"-DBATCH_NMAX={nmax}", f"-DBATCH_EPT={ept}"]))
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith(".hip") and name != "phsp_inst.hip":
+        if name.endswith(".hip") and name not in ("phsp_inst.hip", "phsp_batch_inst.hip"):
             units.append((os.path.join(CSRC, name),
                           os.path.join(BUILD_DIR, name[:-4] + ".o"), []))
         elif name.endswith(".cpp"):

@@ -13,6 +13,7 @@
 
 #include "hydra_phsp.h"
 #include "phsp_api_internal.hpp"
+#include "phsp_finalize.hpp"
 #include "phsp_kernels.hpp"
 
 namespace hphsp {
@@ -81,6 +82,7 @@ int make_frame(double M, const double* p4, Frame* f) {
 // --------------------------------------------------------------- workspace ----
 
 struct Workspace {
+    Moments* mid = nullptr;       // kMaxGroups stage-1 results
     Moments* partials = nullptr;
     uint64_t capacity = 0;
     double* stats_host = nullptr; // pinned, HYDRA_PHSP_STATS doubles
@@ -98,6 +100,8 @@ int workspace_for(hipStream_t stream, uint64_t partials, Workspace** out) {
     Workspace& w = g_ws[std::make_pair(dev, stream)];
     if (w.stats_dev == nullptr) {
         e = hipMalloc(&w.stats_dev, sizeof(double) * HYDRA_PHSP_STATS);
+        if (e != hipSuccess) return fail(HYDRA_PHSP_ENOMEM, "workspace allocation failed");
+        e = hipMalloc(&w.mid, sizeof(Moments) * kMaxGroups);
         if (e != hipSuccess) return fail(HYDRA_PHSP_ENOMEM, "workspace allocation failed");
         e = hipHostMalloc(&w.stats_host, sizeof(double) * HYDRA_PHSP_STATS, hipHostMallocDefault);
         if (e != hipSuccess) return fail(HYDRA_PHSP_ENOMEM, "pinned workspace allocation failed");
@@ -127,6 +131,7 @@ int release_workspaces() {
     for (auto& kv : g_ws) {
         if (kv.second.partials) (void)hipFree(kv.second.partials);
         if (kv.second.stats_dev) (void)hipFree(kv.second.stats_dev);
+        if (kv.second.mid) (void)hipFree(kv.second.mid);
         if (kv.second.stats_host) (void)hipHostFree(kv.second.stats_host);
     }
     g_ws.clear();
@@ -169,9 +174,15 @@ void timing_end(hipStream_t stream, long slot) {
 
 // ----------------------------------------------------------------- launch ----
 
-__global__ __launch_bounds__(kFinalizeBlock) void k_finalize(const Moments* parts, uint64_t count,
-                                                             double* stats) {
-    finalize_moments(parts, count, stats);
+__global__ __launch_bounds__(kStage1Block) void k_merge_stage1(const Moments* parts, uint64_t count,
+                                                              Moments* mid) {
+    const Moments r = stage1_group(parts, count, blockIdx.x);
+    if (threadIdx.x == 0) mid[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kStage2Block) void k_merge_stage2(const Moments* mid, uint64_t groups,
+                                                              double* stats) {
+    stage2_write(mid, groups, stats);
 }
 
 static hipError_t launch_by_n(int n, const LaunchSpec& s, const KArgs& a, hipStream_t stream) {
@@ -189,8 +200,13 @@ static hipError_t launch_by_n(int n, const LaunchSpec& s, const KArgs& a, hipStr
     }
 }
 
-// Events per thread of the single-channel kernels.
-static int default_ept(int mode) { return mode == kIntegrate ? 2 : 1; }
+// Events per thread of the single-channel kernels (0 = default per path).
+static int g_ept_override[3] = {0, 0, 0};
+static int default_ept(int mode) {
+    const int o = g_ept_override[mode];
+    if (o > 0) return o;
+    return mode == kIntegrate ? 2 : 1;
+}
 
 int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const double* parent_dev,
                uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
@@ -227,10 +243,15 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
         if (e != hipSuccess) return fail_hip(e, "phase-space kernel launch");
     }
     if (stats_dev != nullptr) {
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeBlock), 0, stream,
-                           (const Moments*)ws->partials, blocks, stats_dev);
+        const uint64_t groups = stage1_groups(blocks);
+        hipLaunchKernelGGL(k_merge_stage1, dim3((unsigned)groups), dim3(kStage1Block), 0, stream,
+                           (const Moments*)ws->partials, blocks, ws->mid);
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return fail_hip(e, "finalize kernel launch");
+        if (e != hipSuccess) return fail_hip(e, "merge kernel launch");
+        hipLaunchKernelGGL(k_merge_stage2, dim3(1), dim3(kStage2Block), 0, stream,
+                           (const Moments*)ws->mid, groups, stats_dev);
+        e = hipGetLastError();
+        if (e != hipSuccess) return fail_hip(e, "merge kernel launch");
     }
     return HYDRA_PHSP_OK;
 }
@@ -342,7 +363,18 @@ const char* hydra_phsp_last_error(void) { return t_last_error.c_str(); }
 
 int hydra_phsp_abi_version(void) { return HYDRA_PHSP_ABI_VERSION; }
 
-int hydra_phsp_release(void) { return release_workspaces(); }
+int hydra_phsp_release(void) {
+    const int a = release_batch_slots();
+    const int b = release_workspaces();
+    return a != HYDRA_PHSP_OK ? a : b;
+}
+
+int hydra_phsp_set_events_per_thread(int path, int ept) {
+    if (path < 0 || path > 2) return fail(HYDRA_PHSP_EINVAL, "path must be 0, 1 or 2");
+    if (ept != 0 && ept != 1 && ept != 2 && ept != 4) return fail(HYDRA_PHSP_EINVAL, "ept must be 0, 1, 2 or 4");
+    g_ept_override[path] = ept;
+    return HYDRA_PHSP_OK;
+}
 
 int hydra_phsp_timing_enable(int on) {
     std::lock_guard<std::mutex> lock(g_timing.mu);

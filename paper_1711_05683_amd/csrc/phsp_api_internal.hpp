@@ -21,6 +21,7 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
                int mode, void* out, uint64_t ld, double* weights, double* stats_dev, hipStream_t stream,
                int ept_override);
 int release_workspaces();
+int release_batch_slots();
 // Benchmark timing brackets around a kernel launch (slot -1: timing off).
 long timing_begin(hipStream_t stream);
 void timing_end(hipStream_t stream, long slot);

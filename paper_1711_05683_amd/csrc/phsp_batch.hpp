@@ -1,0 +1,112 @@
+// phsp_batch.hpp -- persistent multi-channel kernel.
+//
+// Many decay channels (uneven N and event counts) run in one launch.  The host
+// cuts every channel into tiles of kBlock*EPT events -- exactly the per-block
+// chunks of the single-channel kernel -- and a persistent grid walks the tile
+// list with a static stride (block b takes tiles b, b+G, b+2G, ...; every block
+// leaves the loop once its next index passes the end).  Each tile switches on
+// its channel's N to the same templated per-event code as the single-channel
+// kernel, and writes its block partial at the channel's tile index, so events,
+// weights and partials are bit-identical to a single-channel launch with the
+// same events per thread; the per-channel two-stage merge then reproduces the
+// single-channel integral bit for bit.
+#pragma once
+
+#include "phsp_finalize.hpp"
+#include "phsp_kernels.hpp"
+
+namespace hphsp {
+
+// One channel as the device sees it.
+struct DevChannel {
+    KArgs a;              // per-channel arguments (partials = channel's first tile)
+    int32_t n;            // daughters
+    int32_t mode;         // kFp64 or kIntegrate
+    uint64_t ntiles;      // tiles (= block partials) of this channel
+    uint64_t first_group; // index of the channel's first stage-1 group
+    uint64_t ngroups;     // stage1_groups(ntiles)
+    double* stats;        // HYDRA_PHSP_STATS doubles
+};
+
+struct TileRef {
+    uint32_t channel;
+    uint32_t reserved;
+    uint64_t block; // block index within the channel
+};
+
+struct GroupRef {
+    uint32_t channel;
+    uint32_t group;
+};
+
+// The body of k_phsp for one tile, with the channel's arguments read from the
+// (wave-uniform) channel record.
+template <int N, int MODE, int EPT>
+__device__ __forceinline__ void run_tile(const KArgs& a, uint64_t blk) {
+    const uint64_t base = blk * (uint64_t)(kBlock * EPT);
+    Moments acc{0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const uint64_t e = base + (uint64_t)(k * kBlock) + threadIdx.x;
+        if (e < a.nevents) {
+            const double w = run_event<N, kAtRest, MODE>(a, e);
+            if (k == 0) {
+                acc = Moments{1.0, w, 0.0};
+            } else {
+                const double delta = w - acc.mean;
+                acc.n = (double)(k + 1);
+                acc.mean = acc.mean + delta * (1.0 / (double)(k + 1));
+                acc.m2 = acc.m2 + delta * (w - acc.mean);
+            }
+        }
+    }
+    const bool full = base + (uint64_t)(kBlock * EPT) <= a.nevents;
+    const Moments r = block_reduce<kWaves>(acc, full);
+    if (threadIdx.x == 0) a.partials[blk] = r;
+}
+
+template <int N, int EPT>
+__device__ __forceinline__ void run_tile_mode(const DevChannel& c, uint64_t blk) {
+    if (c.mode == kIntegrate)
+        run_tile<N, kIntegrate, EPT>(c.a, blk);
+    else
+        run_tile<N, kFp64, EPT>(c.a, blk);
+}
+
+template <int NMAXB, int EPT>
+__global__ __launch_bounds__(kBlock) void k_phsp_batched(const DevChannel* __restrict__ chans,
+                                                         const TileRef* __restrict__ tiles,
+                                                         uint64_t ntiles) {
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const TileRef tr = tiles[t];
+        const DevChannel& c = chans[tr.channel];
+        switch (c.n) {
+        case 2: run_tile_mode<2, EPT>(c, tr.block); break;
+        case 3: run_tile_mode<3, EPT>(c, tr.block); break;
+        case 4: run_tile_mode<4, EPT>(c, tr.block); break;
+        case 5: run_tile_mode<5, EPT>(c, tr.block); break;
+        case 6: run_tile_mode<6, EPT>(c, tr.block); break;
+        case 7: run_tile_mode<7, EPT>(c, tr.block); break;
+        case 8: run_tile_mode<8, EPT>(c, tr.block); break;
+        case 9: if constexpr (NMAXB >= 9) run_tile_mode<9, EPT>(c, tr.block); break;
+        case 10: if constexpr (NMAXB >= 10) run_tile_mode<10, EPT>(c, tr.block); break;
+        default: break;
+        }
+        // The tile's LDS reduction must finish before the next tile reuses LDS.
+        __syncthreads();
+    }
+}
+
+struct BatchLaunch {
+    const DevChannel* chans;
+    const TileRef* tiles;
+    uint64_t ntiles;
+    uint64_t grid;
+};
+
+// Persistent-kernel launcher for one (NMAXB, EPT) pair, defined per
+// instantiation unit.
+template <int NMAXB, int EPT>
+hipError_t launch_batched(const BatchLaunch& b, hipStream_t stream);
+
+} // namespace hphsp

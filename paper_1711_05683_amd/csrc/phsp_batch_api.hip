@@ -1,0 +1,452 @@
+// phsp_batch_api.hip -- C ABI of the batched path: validation, tile tables,
+// HIP-graph plans, one-shot batches and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <utility>
+#include <vector>
+
+#include "hydra_phsp.h"
+#include "hydra_phsp_batch.h"
+#include "phsp_api_internal.hpp"
+#include "phsp_batch.hpp"
+
+namespace hphsp {
+
+// Stage 1 of every channel's merge: block g handles group groups[g].
+__global__ __launch_bounds__(kStage1Block) void k_batch_merge_stage1(const DevChannel* __restrict__ chans,
+                                                                    const GroupRef* __restrict__ groups,
+                                                                    Moments* __restrict__ mid) {
+    const GroupRef gr = groups[blockIdx.x];
+    const DevChannel& c = chans[gr.channel];
+    const Moments r = stage1_group(c.a.partials, c.ntiles, gr.group);
+    if (threadIdx.x == 0) mid[c.first_group + gr.group] = r;
+}
+
+// Stage 2: one block per channel.
+__global__ __launch_bounds__(kStage2Block) void k_batch_merge_stage2(const DevChannel* __restrict__ chans,
+                                                                    const Moments* __restrict__ mid) {
+    const DevChannel& c = chans[blockIdx.x];
+    stage2_write(mid + c.first_group, c.ngroups, c.stats);
+}
+
+} // namespace hphsp
+
+using namespace hphsp;
+
+struct hydra_phsp_plan {
+    int device = 0;
+    int nch = 0;
+    int nmaxb = 8;
+    int ept = 1;
+    uint64_t grid = 0, ntiles = 0, ngroups = 0;
+    DevChannel* d_chans = nullptr;
+    TileRef* d_tiles = nullptr;
+    GroupRef* d_groups = nullptr;
+    Moments* d_partials = nullptr;
+    Moments* d_mid = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool launched = false;
+};
+
+namespace hphsp {
+
+static hipError_t launch_persistent(int nmaxb, int ept, const BatchLaunch& b, hipStream_t s) {
+    if (nmaxb <= 8) {
+        switch (ept) {
+        case 1: return launch_batched<8, 1>(b, s);
+        case 2: return launch_batched<8, 2>(b, s);
+        case 4: return launch_batched<8, 4>(b, s);
+        }
+    } else {
+        switch (ept) {
+        case 1: return launch_batched<10, 1>(b, s);
+        case 2: return launch_batched<10, 2>(b, s);
+        case 4: return launch_batched<10, 4>(b, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+static int check_channel(const hydra_phsp_channel& c, Channel* ch) {
+    int st = make_channel(c.parent_mass, c.masses, c.n_daughters, ch);
+    if (st != HYDRA_PHSP_OK) return st;
+    if (c.stats_dev == nullptr) return fail(HYDRA_PHSP_EINVAL, "channel stats_dev is NULL");
+    const bool has_out = c.p4_out_dev != nullptr, has_w = c.weights_dev != nullptr;
+    if (has_out != has_w) return fail(HYDRA_PHSP_EINVAL, "channel needs both p4_out_dev and weights_dev, or neither");
+    if (has_out && c.ld < c.nevents) return fail(HYDRA_PHSP_EINVAL, "channel ld must be >= nevents");
+    return HYDRA_PHSP_OK;
+}
+
+static void free_plan(hydra_phsp_plan* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->done) (void)hipEventDestroy(p->done);
+    if (p->d_chans) (void)hipFree(p->d_chans);
+    if (p->d_tiles) (void)hipFree(p->d_tiles);
+    if (p->d_groups) (void)hipFree(p->d_groups);
+    if (p->d_partials) (void)hipFree(p->d_partials);
+    if (p->d_mid) (void)hipFree(p->d_mid);
+    delete p;
+}
+
+// Enqueue the launch sequence of a plan on `s` (no graph).
+static int enqueue_plan(hydra_phsp_plan* p, hipStream_t s, bool timed) {
+    if (p->ntiles > 0) {
+        BatchLaunch b{p->d_chans, p->d_tiles, p->ntiles, p->grid};
+        const long slot = timed ? timing_begin(s) : -1;
+        hipError_t e = launch_persistent(p->nmaxb, p->ept, b, s);
+        timing_end(s, slot);
+        if (e != hipSuccess) return fail_hip(e, "batched kernel launch");
+    }
+    hipLaunchKernelGGL(k_batch_merge_stage1, dim3((unsigned)p->ngroups), dim3(kStage1Block), 0, s,
+                       (const DevChannel*)p->d_chans, (const GroupRef*)p->d_groups, p->d_mid);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "batch merge launch");
+    hipLaunchKernelGGL(k_batch_merge_stage2, dim3((unsigned)p->nch), dim3(kStage2Block), 0, s,
+                       (const DevChannel*)p->d_chans, (const Moments*)p->d_mid);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "batch merge launch");
+    return HYDRA_PHSP_OK;
+}
+
+template <typename T>
+static int upload(T** dst, const std::vector<T>& src) {
+    const size_t bytes = sizeof(T) * std::max<size_t>(src.size(), 1);
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e != hipSuccess) return fail(HYDRA_PHSP_ENOMEM, "batch table allocation failed");
+    if (!src.empty()) {
+        e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail_hip(e, "batch table upload");
+    }
+    return HYDRA_PHSP_OK;
+}
+
+static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp_tuning* tuning,
+                      hydra_phsp_plan** out, int* bad) {
+    if (bad) *bad = -1;
+    if (chans == nullptr || nch <= 0) return fail(HYDRA_PHSP_EINVAL, "need at least one channel");
+    if (out == nullptr) return fail(HYDRA_PHSP_EINVAL, "plan_out is NULL");
+    int ept = 1, gpc = 8;
+    if (tuning) {
+        if (tuning->ept) ept = tuning->ept;
+        if (tuning->grid_per_cu) gpc = tuning->grid_per_cu;
+    }
+    if (ept != 1 && ept != 2 && ept != 4) return fail(HYDRA_PHSP_EINVAL, "tuning ept must be 1, 2 or 4");
+    if (gpc < 1 || gpc > 64) return fail(HYDRA_PHSP_EINVAL, "tuning grid_per_cu must be in [1, 64]");
+
+    std::vector<DevChannel> dch((size_t)nch);
+    std::vector<TileRef> tiles;
+    std::vector<GroupRef> groups;
+    const uint64_t tile_events = (uint64_t)kBlock * (uint64_t)ept;
+    uint64_t first_tile = 0, first_group = 0;
+    int nmax = 2;
+    for (int i = 0; i < nch; ++i) {
+        const hydra_phsp_channel& c = chans[i];
+        Channel ch;
+        int st = check_channel(c, &ch);
+        if (st != HYDRA_PHSP_OK) {
+            if (bad) *bad = i;
+            return st;
+        }
+        nmax = std::max(nmax, c.n_daughters);
+        const uint64_t nt = (c.nevents + tile_events - 1) / tile_events;
+        if (nt > 0xFFFFFFFFull) return fail(HYDRA_PHSP_EINVAL, "channel too large");
+        DevChannel d;
+        std::memset(&d, 0, sizeof(d));
+        d.a.ch = ch;
+        d.a.nevents = c.nevents;
+        d.a.event_offset = c.event_offset;
+        d.a.k0 = (uint32_t)(c.seed & 0xFFFFFFFFu);
+        d.a.k1 = (uint32_t)(c.seed >> 32);
+        d.a.sid = c.stream_id;
+        d.a.out = c.p4_out_dev;
+        d.a.ld = c.ld;
+        d.a.weights = c.weights_dev;
+        d.a.inv_M = 1.0 / ch.M;
+        d.n = c.n_daughters;
+        d.mode = c.p4_out_dev ? kFp64 : kIntegrate;
+        d.ntiles = nt;
+        d.first_group = first_group;
+        d.ngroups = stage1_groups(nt);
+        d.stats = c.stats_dev;
+        // partials pointer is fixed up after allocation (offset kept in a.partials)
+        d.a.partials = reinterpret_cast<Moments*>(first_tile * sizeof(Moments));
+        dch[(size_t)i] = d;
+        for (uint64_t b = 0; b < nt; ++b) tiles.push_back(TileRef{(uint32_t)i, 0u, b});
+        for (uint64_t g = 0; g < d.ngroups; ++g) groups.push_back(GroupRef{(uint32_t)i, (uint32_t)g});
+        first_tile += nt;
+        first_group += d.ngroups;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return fail_hip(e, "hipDeviceGetAttribute");
+
+    hydra_phsp_plan* p = new hydra_phsp_plan();
+    p->device = dev;
+    p->nch = nch;
+    p->nmaxb = nmax <= 8 ? 8 : 10;
+    p->ept = ept;
+    p->ntiles = first_tile;
+    p->ngroups = first_group;
+    p->grid = std::min<uint64_t>(std::max<uint64_t>(first_tile, 1), (uint64_t)gpc * (uint64_t)std::max(cus, 1));
+    e = hipMalloc(&p->d_partials, sizeof(Moments) * std::max<uint64_t>(first_tile, 1));
+    if (e != hipSuccess) {
+        free_plan(p);
+        return fail(HYDRA_PHSP_ENOMEM, "batch partials allocation failed");
+    }
+    e = hipMalloc(&p->d_mid, sizeof(Moments) * std::max<uint64_t>(first_group, 1));
+    if (e != hipSuccess) {
+        free_plan(p);
+        return fail(HYDRA_PHSP_ENOMEM, "batch partials allocation failed");
+    }
+    for (auto& d : dch) d.a.partials = p->d_partials + reinterpret_cast<uintptr_t>(d.a.partials) / sizeof(Moments);
+    int st = upload(&p->d_chans, dch);
+    if (st == HYDRA_PHSP_OK) st = upload(&p->d_tiles, tiles);
+    if (st == HYDRA_PHSP_OK) st = upload(&p->d_groups, groups);
+    if (st == HYDRA_PHSP_OK) {
+        e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+        if (e != hipSuccess) st = fail_hip(e, "hipEventCreate");
+    }
+    if (st != HYDRA_PHSP_OK) {
+        free_plan(p);
+        return st;
+    }
+    *out = p;
+    return HYDRA_PHSP_OK;
+}
+
+static int capture_graph(hydra_phsp_plan* p) {
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamCreate");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return fail_hip(e, "hipStreamBeginCapture");
+    }
+    int st = enqueue_plan(p, cs, false);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (st != HYDRA_PHSP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+    p->graph = g;
+    e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
+    return HYDRA_PHSP_OK;
+}
+
+static int destroy_plan(hydra_phsp_plan* p) {
+    if (p == nullptr) return fail(HYDRA_PHSP_EINVAL, "plan is NULL");
+    int st = HYDRA_PHSP_OK;
+    if (p->launched) {
+        hipError_t e = hipEventSynchronize(p->done);
+        if (e != hipSuccess) st = fail_hip(e, "hipEventSynchronize");
+    }
+    free_plan(p);
+    return st;
+}
+
+// One-shot batches keep their tables alive in a per-(device, stream) slot until
+// the next batch on that stream.
+static std::mutex g_slot_mu;
+static std::map<std::pair<int, hipStream_t>, hydra_phsp_plan*> g_slots;
+
+int release_batch_slots() {
+    std::lock_guard<std::mutex> lock(g_slot_mu);
+    int st = HYDRA_PHSP_OK;
+    for (auto& kv : g_slots) {
+        const int r = destroy_plan(kv.second);
+        if (r != HYDRA_PHSP_OK) st = r;
+    }
+    g_slots.clear();
+    return st;
+}
+
+// ------------------------------------------------------------- autotuner ----
+
+struct TuneKey {
+    int device, nch, nmax, integrate_only;
+    int64_t events_bucket;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(device, nch, nmax, integrate_only, events_bucket) <
+               std::tie(o.device, o.nch, o.nmax, o.integrate_only, o.events_bucket);
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, std::pair<hydra_phsp_tuning, double>> g_tune_cache;
+
+static TuneKey tune_key(const hydra_phsp_channel* chans, int nch, int dev) {
+    TuneKey k{dev, nch, 2, 0, 0};
+    double total = 0.0;
+    for (int i = 0; i < nch; ++i) {
+        k.nmax = std::max(k.nmax, chans[i].n_daughters);
+        if (chans[i].p4_out_dev == nullptr) ++k.integrate_only;
+        total += (double)chans[i].nevents;
+    }
+    k.events_bucket = (int64_t)std::llround(4.0 * std::log2(total + 1.0)); // quarter-octave classes
+    return k;
+}
+
+} // namespace hphsp
+
+extern "C" {
+
+int hydra_phsp_plan_create(const hydra_phsp_channel* channels, int n_channels,
+                           const hydra_phsp_tuning* tuning, hydra_phsp_plan** plan_out) {
+    hydra_phsp_plan* p = nullptr;
+    int st = build_plan(channels, n_channels, tuning, &p, nullptr);
+    if (st != HYDRA_PHSP_OK) return st;
+    st = capture_graph(p);
+    if (st != HYDRA_PHSP_OK) {
+        free_plan(p);
+        return st;
+    }
+    *plan_out = p;
+    return HYDRA_PHSP_OK;
+}
+
+int hydra_phsp_plan_launch(hydra_phsp_plan* plan, void* stream) {
+    if (plan == nullptr || plan->exec == nullptr) return fail(HYDRA_PHSP_EINVAL, "plan is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const long slot = timing_begin(s);
+    hipError_t e = hipGraphLaunch(plan->exec, s);
+    timing_end(s, slot);
+    if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+    e = hipEventRecord(plan->done, s);
+    if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
+    plan->launched = true;
+    return HYDRA_PHSP_OK;
+}
+
+int hydra_phsp_plan_destroy(hydra_phsp_plan* plan) { return destroy_plan(plan); }
+
+int hydra_phsp_plan_info(const hydra_phsp_plan* plan, uint64_t* ntiles_out, uint64_t* grid_out) {
+    if (plan == nullptr || ntiles_out == nullptr || grid_out == nullptr)
+        return fail(HYDRA_PHSP_EINVAL, "plan_info needs a plan and two host pointers");
+    *ntiles_out = plan->ntiles;
+    *grid_out = plan->grid;
+    return HYDRA_PHSP_OK;
+}
+
+int hydra_phsp_batch_run(const hydra_phsp_channel* channels, int n_channels,
+                         const hydra_phsp_tuning* tuning, void* stream, int* bad_channel_out) {
+    hipStream_t s = (hipStream_t)stream;
+    hydra_phsp_plan* p = nullptr;
+    int st = build_plan(channels, n_channels, tuning, &p, bad_channel_out);
+    if (st != HYDRA_PHSP_OK) return st;
+    {
+        std::lock_guard<std::mutex> lock(g_slot_mu);
+        auto key = std::make_pair(p->device, s);
+        auto it = g_slots.find(key);
+        if (it != g_slots.end()) {
+            st = destroy_plan(it->second);
+            g_slots.erase(it);
+            if (st != HYDRA_PHSP_OK) {
+                free_plan(p);
+                return st;
+            }
+        }
+        st = enqueue_plan(p, s, true);
+        if (st == HYDRA_PHSP_OK) {
+            hipError_t e = hipEventRecord(p->done, s);
+            if (e != hipSuccess) st = fail_hip(e, "hipEventRecord");
+        }
+        if (st != HYDRA_PHSP_OK) {
+            (void)hipStreamSynchronize(s);
+            free_plan(p);
+            return st;
+        }
+        p->launched = true;
+        g_slots[key] = p;
+    }
+    return HYDRA_PHSP_OK;
+}
+
+int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void* stream,
+                        hydra_phsp_tuning* best_out, double* best_ms_out) {
+    if (best_out == nullptr || best_ms_out == nullptr)
+        return fail(HYDRA_PHSP_EINVAL, "autotune needs two host pointers");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    for (int i = 0; channels && i < n_channels; ++i) {
+        Channel ch;
+        int st = check_channel(channels[i], &ch);
+        if (st != HYDRA_PHSP_OK) return st;
+    }
+    if (channels == nullptr || n_channels <= 0) return fail(HYDRA_PHSP_EINVAL, "need at least one channel");
+    const TuneKey key = tune_key(channels, n_channels, dev);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *best_out = it->second.first;
+            *best_ms_out = it->second.second;
+            return HYDRA_PHSP_OK;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(HYDRA_PHSP_EDEVICE, "hipEventCreate failed");
+    double best_ms = 1e300;
+    hydra_phsp_tuning best{1, 8, {0, 0}};
+    int st = HYDRA_PHSP_OK;
+    const int epts[3] = {1, 2, 4};
+    const int gpcs[5] = {1, 2, 4, 8, 16};
+    for (int ei = 0; ei < 3 && st == HYDRA_PHSP_OK; ++ei) {
+        for (int gi = 0; gi < 5 && st == HYDRA_PHSP_OK; ++gi) {
+            hydra_phsp_tuning t{epts[ei], gpcs[gi], {0, 0}};
+            hydra_phsp_plan* p = nullptr;
+            st = build_plan(channels, n_channels, &t, &p, nullptr);
+            if (st != HYDRA_PHSP_OK) break;
+            st = enqueue_plan(p, s, false); // warm-up
+            float total = 0.0f;
+            const int reps = 3;
+            for (int r = 0; r < reps && st == HYDRA_PHSP_OK; ++r) {
+                (void)hipEventRecord(a, s);
+                st = enqueue_plan(p, s, false);
+                (void)hipEventRecord(b, s);
+                if (hipEventSynchronize(b) != hipSuccess) st = fail(HYDRA_PHSP_EDEVICE, "autotune sync failed");
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                total += ms;
+            }
+            (void)hipStreamSynchronize(s);
+            free_plan(p);
+            const double avg = total / reps;
+            if (st == HYDRA_PHSP_OK && avg < best_ms) {
+                best_ms = avg;
+                best = t;
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != HYDRA_PHSP_OK) return st;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache[key] = std::make_pair(best, best_ms);
+    }
+    *best_out = best;
+    *best_ms_out = best_ms;
+    return HYDRA_PHSP_OK;
+}
+
+} // extern "C"

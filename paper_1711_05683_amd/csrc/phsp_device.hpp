@@ -82,16 +82,13 @@ struct Event {
 //   E' = gamma E + eta.p,  p' = p + (eta.p / (gamma + 1) + E) eta.
 template <typename R>
 __device__ __forceinline__ void boost(R& e, R& x, R& y, R& z, R ex, R ey, R ez, R gamma, R inv_gp1) {
-    const R ep = ex * x + ey * y + ez * z;
-    const R f = ep * inv_gp1 + e;
-    e = gamma * e + ep;
-    x = x + f * ex;
-    y = y + f * ey;
-    z = z + f * ez;
+    const R ep = fma(ex, x, fma(ey, y, ez * z));
+    const R f = fma(ep, inv_gp1, e);
+    e = fma(gamma, e, ep);
+    x = fma(f, ex, x);
+    y = fma(f, ey, y);
+    z = fma(f, ez, z);
 }
-
-__device__ __forceinline__ void sincos_2pi(double u, double* s, double* c) { sincospi(2.0 * u, s, c); }
-__device__ __forceinline__ void sincos_2pi(float u, float* s, float* c) { sincospif(2.0f * u, s, c); }
 
 // The random words of global event g: J Philox blocks, counter (g lo, g hi, j, sid).
 template <int N>
@@ -129,7 +126,7 @@ __device__ __forceinline__ void solve_levels(const Channel& c, Draws<N>& d, Leve
     sortnet_sort<N - 2>(d.u);
     L.sigma[0] = c.m[0];
 #pragma unroll
-    for (int i = 1; i <= N - 2; ++i) L.sigma[i] = c.S[i] + c.T * d.u[i - 1];
+    for (int i = 1; i <= N - 2; ++i) L.sigma[i] = fma(c.T, d.u[i - 1], c.S[i]);
     L.sigma[N - 1] = c.M;
 #pragma unroll
     for (int i = 1; i <= N - 2; ++i) L.inv_sigma[i] = 1.0 / L.sigma[i];
@@ -151,11 +148,31 @@ __device__ __forceinline__ void solve_levels(const Channel& c, Draws<N>& d, Leve
 // Direction of level i from its (theta, phi) uniforms:
 // cos(theta) = 2u - 1, sin(theta) = 2 sqrt(u (1-u)), phi = 2 pi v.
 template <typename R>
-__device__ __forceinline__ void direction(R u, R v, R& nx, R& ny, R& nz) {
-    const R ct = R(2) * u - R(1);
-    const R st = R(2) * sqrt(u * (R(1) - u));
-    R sp, cp;
-    sincos_2pi(v, &sp, &cp);
+__device__ __forceinline__ void direction(double u, double v, R& nx, R& ny, R& nz);
+
+template <>
+__device__ __forceinline__ void direction<double>(double u, double v, double& nx, double& ny,
+                                                  double& nz) {
+    const double ct = 2.0 * u - 1.0;
+    const double st = 2.0 * sqrt(u * (1.0 - u));
+    double sp, cp;
+    sincospi(2.0 * v, &sp, &cp);
+    nx = st * cp;
+    ny = st * sp;
+    nz = ct;
+}
+
+// FP32 direction from the FP64 uniforms.  2u - 1 and u (1 - u) are formed in
+// FP64 (exact / one rounding) before the conversion, so directions near the
+// poles keep FP32 relative accuracy, and phi's uniform is first reduced to
+// [-1/2, 1/2] (exactly) so its conversion error is absolute, not relative to 1.
+template <>
+__device__ __forceinline__ void direction<float>(double u, double v, float& nx, float& ny, float& nz) {
+    const float ct = (float)(2.0 * u - 1.0);
+    const float st = 2.0f * sqrtf((float)(u * (1.0 - u)));
+    const float r = (float)(v - rint(v));
+    float sp, cp;
+    sincospif(2.0f * r, &sp, &cp);
     nx = st * cp;
     ny = st * sp;
     nz = ct;
@@ -170,14 +187,14 @@ __device__ __forceinline__ void build_event(const Channel& c, const Draws<N>& d,
                                             Event<N, R>& ev) {
     {
         R nx, ny, nz;
-        direction<R>(R(d.u[N - 2]), R(d.u[N - 1]), nx, ny, nz);
+        direction<R>(d.u[N - 2], d.u[N - 1], nx, ny, nz);
         const R p = R(L.p[0]);
         const R m0 = R(c.m[0]), m1 = R(c.m[1]);
-        ev.e[1] = sqrt(p * p + m1 * m1);
+        ev.e[1] = sqrt(fma(p, p, m1 * m1));
         ev.x[1] = p * nx;
         ev.y[1] = p * ny;
         ev.z[1] = p * nz;
-        ev.e[0] = sqrt(p * p + m0 * m0);
+        ev.e[0] = sqrt(fma(p, p, m0 * m0));
         ev.x[0] = -ev.x[1];
         ev.y[0] = -ev.y[1];
         ev.z[0] = -ev.z[1];
@@ -185,10 +202,10 @@ __device__ __forceinline__ void build_event(const Channel& c, const Draws<N>& d,
 #pragma unroll
     for (int i = 1; i <= N - 2; ++i) {
         R nx, ny, nz;
-        direction<R>(R(d.u[N - 2 + 2 * i]), R(d.u[N - 1 + 2 * i]), nx, ny, nz);
+        direction<R>(d.u[N - 2 + 2 * i], d.u[N - 1 + 2 * i], nx, ny, nz);
         const R p = R(L.p[i]);
         const R mi = R(c.m[i + 1]);
-        ev.e[i + 1] = sqrt(p * p + mi * mi);
+        ev.e[i + 1] = sqrt(fma(p, p, mi * mi));
         ev.x[i + 1] = p * nx;
         ev.y[i + 1] = p * ny;
         ev.z[i + 1] = p * nz;
@@ -196,7 +213,7 @@ __device__ __forceinline__ void build_event(const Channel& c, const Draws<N>& d,
         const R isig = R(L.inv_sigma[i]);
         const R eta = -(p * isig);
         const R ex = eta * nx, ey = eta * ny, ez = eta * nz;
-        const R gamma = sqrt(p * p + sig * sig) * isig;
+        const R gamma = sqrt(fma(p, p, sig * sig)) * isig;
         const R inv_gp1 = R(1) / (gamma + R(1));
 #pragma unroll
         for (int k = 0; k <= i; ++k)
@@ -210,55 +227,6 @@ __device__ __forceinline__ void boost_to_lab(Event<N, R>& ev, const Frame& f) {
     const R gamma = R(f.gamma), inv_gp1 = R(f.inv_gp1);
 #pragma unroll
     for (int k = 0; k < N; ++k) boost<R>(ev.e[k], ev.x[k], ev.y[k], ev.z[k], ex, ey, ez, gamma, inv_gp1);
-}
-
-// ---------------------------------------------------------------------------
-// Integral statistics: (n, mean, M2) with the pairwise update of Chan, Golub and
-// LeVeque ("Updating formulae and a pairwise algorithm for computing sample
-// variances", 1979).  Identical weights give M2 = 0 exactly.
-// ---------------------------------------------------------------------------
-struct Moments {
-    double n, mean, m2;
-};
-
-__device__ __forceinline__ Moments merge(const Moments& a, const Moments& b) {
-    if (b.n == 0.0) return a;
-    if (a.n == 0.0) return b;
-    const double n = a.n + b.n;
-    const double delta = b.mean - a.mean;
-    const double fb = b.n / n;
-    Moments r;
-    r.n = n;
-    r.mean = a.mean + delta * fb;
-    r.m2 = a.m2 + b.m2 + delta * delta * (a.n * fb);
-    return r;
-}
-
-// Equal-count merge (a.n == b.n): the weights are exactly 1/2.
-__device__ __forceinline__ Moments merge_equal(const Moments& a, const Moments& b) {
-    const double delta = b.mean - a.mean;
-    Moments r;
-    r.n = a.n + b.n;
-    r.mean = a.mean + delta * 0.5;
-    r.m2 = a.m2 + b.m2 + delta * delta * (a.n * 0.5);
-    return r;
-}
-
-__device__ __forceinline__ double shfl_down_d(double v, int off) { return __shfl_down(v, off, 64); }
-
-// Wave-level tree (lane i absorbs lane i+off, off = 32..1); lane 0 holds the
-// result.  `equal` selects the division-free form when every lane holds the
-// same count.
-__device__ __forceinline__ Moments wave_reduce(Moments a, bool equal) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        Moments b;
-        b.n = shfl_down_d(a.n, off);
-        b.mean = shfl_down_d(a.mean, off);
-        b.m2 = shfl_down_d(a.m2, off);
-        a = equal ? merge_equal(a, b) : merge(a, b);
-    }
-    return a;
 }
 
 } // namespace hphsp

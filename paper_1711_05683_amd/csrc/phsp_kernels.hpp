@@ -5,11 +5,11 @@
 // event b*BLOCK*EPT + k*BLOCK + t, so every step's stores of one SoA column are
 // BLOCK consecutive elements.  Each lane folds its weights into (n, mean, M2);
 // a wave tree (shuffles), an LDS step across the block's waves and one partial
-// per block follow, and a single-block finalize merges the partials in a fixed
-// order (deterministic for a given launch shape).
+// per block follow; the two-stage merge of the partials is in phsp_finalize.hpp.
 #pragma once
 
 #include "phsp_device.hpp"
+#include "phsp_reduce.hpp"
 
 namespace hphsp {
 
@@ -83,30 +83,6 @@ __device__ __forceinline__ double run_event(const KArgs& a, uint64_t e) {
     return L.w;
 }
 
-// Block-level merge of per-lane moments; thread 0 returns the block's total.
-// The cross-wave step is a pairwise tree so that equal counts stay equal.
-template <int WAVES>
-__device__ __forceinline__ Moments block_reduce(Moments acc, bool full) {
-    __shared__ Moments sm[WAVES];
-    const Moments wr = wave_reduce(acc, full);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) sm[wave] = wr;
-    __syncthreads();
-    Moments r{0.0, 0.0, 0.0};
-    if (threadIdx.x == 0) {
-        Moments t[WAVES];
-#pragma unroll
-        for (int w = 0; w < WAVES; ++w) t[w] = sm[w];
-#pragma unroll
-        for (int span = 1; span < WAVES; span <<= 1)
-#pragma unroll
-            for (int w = 0; w + span < WAVES; w += 2 * span)
-                t[w] = full ? merge_equal(t[w], t[w + span]) : merge(t[w], t[w + span]);
-        r = t[0];
-    }
-    return r;
-}
-
 template <int N, int PMODE, int MODE, int EPT>
 __global__ __launch_bounds__(kBlock) void k_phsp(const KArgs a) {
     const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * EPT);
@@ -132,31 +108,6 @@ __global__ __launch_bounds__(kBlock) void k_phsp(const KArgs a) {
     const bool full = base + (uint64_t)(kBlock * EPT) <= a.nevents;
     const Moments r = block_reduce<kWaves>(acc, full);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = r;
-}
-
-// Fixed-order merge of `count` partials by one block of kFinalizeBlock threads:
-// thread t folds the contiguous range [t*chunk, (t+1)*chunk) in order, then a
-// wave tree and an in-order fold over the waves.
-constexpr int kFinalizeBlock = 1024;
-
-__device__ __forceinline__ void finalize_moments(const Moments* parts, uint64_t count, double* stats) {
-    __shared__ Moments sm[kFinalizeBlock / 64];
-    const uint64_t chunk = (count + kFinalizeBlock - 1) / kFinalizeBlock;
-    const uint64_t lo = (uint64_t)threadIdx.x * chunk;
-    const uint64_t hi = lo + chunk < count ? lo + chunk : count;
-    Moments acc{0.0, 0.0, 0.0};
-    for (uint64_t i = lo; i < hi; ++i) acc = merge(acc, parts[i]);
-    const Moments wr = wave_reduce(acc, false);
-    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = wr;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        Moments r = sm[0];
-        for (int w = 1; w < kFinalizeBlock / 64; ++w) r = merge(r, sm[w]);
-        stats[0] = r.n;
-        stats[1] = r.mean;
-        stats[2] = r.m2;
-        stats[3] = r.n >= 2.0 ? sqrt(r.m2 / ((r.n - 1.0) * r.n)) : 0.0;
-    }
 }
 
 // Launch one instantiation (defined per N in its own translation unit).

@@ -103,3 +103,55 @@ def test_product_path_does_not_import_oracle():
             text = open(path).read()
             assert "import oracle" not in text and "from oracle" not in text, path
             assert "phsp_oracle" not in text and "_liboracle" not in text, path
+
+
+def test_batch_struct_layout_matches_header(P, tmp_path):
+    # Compile a probe against the public header and compare with the binding.
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "hydra_phsp_batch.h"
+int main(void) {
+    printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(hydra_phsp_channel),
+           offsetof(hydra_phsp_channel, n_daughters), offsetof(hydra_phsp_channel, nevents),
+           offsetof(hydra_phsp_channel, p4_out_dev), offsetof(hydra_phsp_channel, stats_dev),
+           sizeof(hydra_phsp_tuning), offsetof(hydra_phsp_tuning, grid_per_cu));
+    return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    C, T = P.ChannelDesc, P.Tuning
+    want = [ctypes.sizeof(C), C.n_daughters.offset, C.nevents.offset, C.p4_out_dev.offset,
+            C.stats_dev.offset, ctypes.sizeof(T), T.grid_per_cu.offset]
+    assert got == want
+
+
+def test_batch_validation_names_bad_channel(P):
+    good = P.channel(5.0, [1.0, 1.0], 10, stats=None)
+    good.stats_dev = 8  # fake device pointer: validation happens before any device work
+    bad = P.channel(5.0, [3.0, 3.0], 10)
+    bad.stats_dev = 8
+    arr = P._channel_array([good, good, bad])
+    idx = ctypes.c_int(-1)
+    st = P.lib().hydra_phsp_batch_run(arr, 3, None, None, ctypes.byref(idx))
+    assert st == P.EKINEMATICS and idx.value == 2
+    half = P.channel(5.0, [1.0, 1.0], 10)
+    half.stats_dev = 8
+    half.p4_out_dev = 16  # outputs without weights
+    half.ld = 10
+    arr = P._channel_array([half])
+    assert P.lib().hydra_phsp_batch_run(arr, 1, None, None, ctypes.byref(idx)) == P.EINVAL
+    assert idx.value == 0
+    t = P._tuning(ept=3)
+    arr = P._channel_array([good])
+    assert P.lib().hydra_phsp_batch_run(arr, 1, ctypes.byref(t), None, ctypes.byref(idx)) == P.EINVAL
+    assert P.lib().hydra_phsp_batch_run(arr, 0, None, None, ctypes.byref(idx)) == P.EINVAL

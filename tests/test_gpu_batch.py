@@ -1,0 +1,213 @@
+"""GPU tests of the batched persistent kernel: every channel of a batch must be
+bit-identical to a single-channel call (events, weights, and -- with the same
+events per thread -- the integral), graph replays must reproduce the eager
+result, and sampled events must match the CPU oracle."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from parity import FP64_TOL, assert_events_close, rel
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*args):
+    print("[batch]", *args, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_1711_05683_amd as P
+    P.lib()
+    oracle.build(force=False)
+    return P
+
+
+def _channels(P, n_channels=24, seed=1711, log_events=(2.0, 4.5), integrate_every=5, nmax=8):
+    from paper_1711_05683_amd.workloads import batched_channels
+    specs = batched_channels(n_channels, seed=seed, nmax=nmax, log_events=log_events)
+    # edge channels: empty, single event, ragged, two-body
+    specs[0].nevents = 0
+    specs[1].nevents = 1
+    specs[2].nevents = 257
+    specs[3].masses = specs[3].masses[:2]
+    bufs, descs = [], []
+    for i, c in enumerate(specs):
+        integ = integrate_every and i % integrate_every == integrate_every - 1
+        st = torch.full((4,), float("nan"), dtype=torch.float64, device="cuda")
+        if integ:
+            out = w = None
+        else:
+            out = torch.full((c.n, 4, max(c.nevents, 1)), float("nan"), dtype=torch.float64, device="cuda")
+            w = torch.full((max(c.nevents, 1),), float("nan"), dtype=torch.float64, device="cuda")
+        bufs.append((out, w, st))
+        descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed + i, stream_id=c.stream_id,
+                               event_offset=1000 * i, out=out, weights=w, stats=st))
+    return specs, bufs, descs
+
+
+def _single(P, c, i, integ, ept=1):
+    if integ:
+        P.set_events_per_thread(0, ept)
+        try:
+            st = P.integrate_async(c.parent_mass, c.masses, c.nevents, seed=c.seed + i,
+                                   stream_id=c.stream_id, event_offset=1000 * i)
+        finally:
+            P.set_events_per_thread(0, 0)
+        return None, None, st
+    P.set_events_per_thread(1, ept)
+    try:
+        out, w, st = P.generate(c.parent_mass, c.masses, c.nevents, seed=c.seed + i, stream_id=c.stream_id,
+                                event_offset=1000 * i)
+    finally:
+        P.set_events_per_thread(1, 0)
+    return out, w, st
+
+
+def _compare_with_single(P, specs, bufs, ept, exact_stats=True):
+    for i, c in enumerate(specs):
+        out, w, st = bufs[i]
+        so, sw, sst = _single(P, c, i, out is None, ept)
+        torch.cuda.synchronize()
+        if out is not None and c.nevents > 0:
+            assert torch.equal(out[:, :, :c.nevents], so[:, :, :c.nevents]), f"channel {i} momenta"
+            assert torch.equal(w[:c.nevents], sw[:c.nevents]), f"channel {i} weights"
+        a, b = st.cpu().numpy(), sst.cpu().numpy()
+        if exact_stats:
+            assert np.array_equal(a, b), (i, a, b)
+        else:
+            assert a[0] == b[0]
+            assert rel(a[1], b[1]) <= 1e-14 if b[1] != 0 else a[1] == 0
+            assert abs(a[3] - b[3]) <= 1e-13 * b[3] + 1e-15 * abs(b[1])
+
+
+def test_batch_matches_single_channel(P):
+    _say("batch vs single channel, ept 1")
+    specs, bufs, descs = _channels(P)
+    P.batch_run(descs, ept=1)
+    torch.cuda.synchronize()
+    _compare_with_single(P, specs, bufs, 1)
+
+
+@pytest.mark.parametrize("ept,gpc", [(2, 1), (4, 16), (1, 2)])
+def test_batch_tuning_variants(P, ept, gpc):
+    _say(f"batch variant ept={ept} grid/cu={gpc}")
+    specs, bufs, descs = _channels(P, n_channels=16, seed=7)
+    P.batch_run(descs, ept=ept, grid_per_cu=gpc)
+    torch.cuda.synchronize()
+    _compare_with_single(P, specs, bufs, ept)
+
+
+def test_batch_with_ten_body_channels(P):
+    _say("batch with N up to 10")
+    specs, bufs, descs = _channels(P, n_channels=12, seed=99, nmax=10)
+    P.batch_run(descs, ept=1)
+    torch.cuda.synchronize()
+    _compare_with_single(P, specs, bufs, 1)
+
+
+def test_batch_against_oracle(P):
+    _say("batch vs oracle")
+    specs, bufs, descs = _channels(P, n_channels=10, seed=3, integrate_every=0)
+    P.batch_run(descs)
+    torch.cuda.synchronize()
+    for i, c in enumerate(specs):
+        if c.nevents == 0:
+            continue
+        out, w, st = bufs[i]
+        k = min(c.nevents, 3000)
+        p4o, wo = oracle.generate(c.parent_mass, c.masses, k, seed=c.seed + i, stream_id=c.stream_id,
+                                  event_offset=1000 * i)
+        assert_events_close(out[:, :, :k].cpu().numpy(), w[:k].cpu().numpy(), p4o, wo)
+        if c.nevents >= 2:
+            mo, so = oracle.integrate(c.parent_mass, c.masses, c.nevents, seed=c.seed + i,
+                                      stream_id=c.stream_id, event_offset=1000 * i)
+            s = st.cpu().numpy()
+            assert rel(s[1], mo) <= FP64_TOL and abs(s[3] - so) <= FP64_TOL * so + 1e-15 * mo
+
+
+def test_plan_graph_replays(P):
+    _say("graph replays")
+    specs, bufs, descs = _channels(P, n_channels=12, seed=11)
+    P.batch_run(descs, ept=1)
+    torch.cuda.synchronize()
+    ref = [(None if o is None else o.clone(), None if w is None else w.clone(), s.clone()) for o, w, s in bufs]
+    plan = P.Plan(descs, ept=1)
+    ntiles, grid = plan.info()
+    assert ntiles > 0 and grid > 0
+    other = torch.empty((3, 4, 5000), dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        # eager work between replays: clobber every output, run unrelated kernels
+        for o, w, s in bufs:
+            if o is not None:
+                o.fill_(float("nan"))
+                w.fill_(float("nan"))
+            s.fill_(float("nan"))
+        P.generate(5.279, [3.097, 0.4937, 0.13957], 5000, out=other, seed=rep)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        for i, (o, w, s) in enumerate(bufs):
+            ro, rw, rs = ref[i]
+            if o is not None:
+                assert torch.equal(o, ro) and torch.equal(w, rw), (rep, i)
+            assert torch.equal(s, rs), (rep, i)
+    plan.destroy()
+
+
+def test_autotune(P):
+    _say("autotune")
+    specs, bufs, descs = _channels(P, n_channels=16, seed=5, log_events=(3.0, 5.0))
+    ept, gpc, ms = P.autotune(descs)
+    assert ept in (1, 2, 4) and 1 <= gpc <= 16 and ms > 0
+    # cached: same answer
+    assert P.autotune(descs) == (ept, gpc, ms)
+    # the tuned shape still gives the single-channel events
+    P.batch_run(descs, ept=ept, grid_per_cu=gpc)
+    torch.cuda.synchronize()
+    _compare_with_single(P, specs, bufs, ept)
+
+
+def test_config3_full_batch(P):
+    _say("config3: 64 channels, one persistent launch")
+    from paper_1711_05683_amd.workloads import batched_channels
+    specs = batched_channels()
+    total = sum(c.nevents for c in specs)
+    _say(f"config3 total events {total}")
+    bufs, descs = [], []
+    for c in specs:
+        out = torch.empty((c.n, 4, c.nevents), dtype=torch.float64, device="cuda")
+        w = torch.empty(c.nevents, dtype=torch.float64, device="cuda")
+        st = torch.empty(4, dtype=torch.float64, device="cuda")
+        bufs.append((out, w, st))
+        descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id,
+                               out=out, weights=w, stats=st))
+    plan = P.Plan(descs, ept=1)
+    plan.launch()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    for i in rng.choice(len(specs), size=6, replace=False):
+        c = specs[i]
+        out, w, st = bufs[i]
+        idx = np.unique(np.concatenate([[0, c.nevents - 1], rng.integers(0, c.nevents, 200)]))
+        ti = torch.as_tensor(idx, device="cuda")
+        g = out[:, :, ti].cpu().numpy()
+        gw = w[ti].cpu().numpy()
+        for j, e in enumerate(idx):
+            p4o, wo = oracle.generate(c.parent_mass, c.masses, 1, seed=c.seed, stream_id=c.stream_id,
+                                      event_offset=int(e))
+            assert_events_close(g[:, :, j:j + 1], gw[j:j + 1], p4o, wo)
+        so, sw, sst = P.generate(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id)
+        torch.cuda.synchronize()
+        assert torch.equal(so, out) and torch.equal(sw, w) and torch.equal(sst, st), i
+        del so, sw
+    plan.destroy()

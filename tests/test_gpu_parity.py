@@ -15,7 +15,8 @@ import numpy as np
 import pytest
 
 import oracle
-from parity import FP64_TOL, MIXED_TOL, MIXED_INTEGRAL_TOL, assert_events_close, event_errors, rel
+from parity import (FP64_TOL, MIXED_INTEGRAL_TOL, MIXED_MASSLESS_TAIL, MIXED_MASSLESS_TOL_M, MIXED_TOL,
+                    assert_events_close, event_errors, mixed_error_report, rel)
 
 torch = pytest.importorskip("torch")
 
@@ -196,19 +197,26 @@ def test_non_default_stream(P):
     assert_events_close(out.cpu().numpy(), w.cpu().numpy(), p4o, wo)
 
 
-@pytest.mark.parametrize("n,M,masses", [(3, 5.279, [3.097, 0.4937, 0.13957]), (6, 10.0, [0.13957] * 6),
-                                        (6, 10.0, [0.0] * 6), (10, 10.0, [0.13957] * 10)])
+MIXED_CASES = [(3, 5.279, [3.097, 0.4937, 0.13957]), (6, 10.0, [0.13957] * 6),
+               (10, 10.0, [0.13957] * 10), (6, 10.0, [0.0] * 6), (3, 1.0, [0.0] * 3)]
+
+
+@pytest.mark.parametrize("n,M,masses", MIXED_CASES)
 def test_mixed_precision(P, n, M, masses):
-    _say(f"mixed N={n}")
+    _say(f"mixed N={n} m={masses[0]}")
     nev = 200_000
     p4, w, st = _run(P, M, masses, nev, mixed=True)
     p4d, wd, sd = _run(P, M, masses, nev)
     # FP64 prologue: weights and integral are bit-identical to the FP64 path
     assert np.array_equal(w, wd) and np.array_equal(st, sd)
     p4o, wo = oracle.generate(M, masses, nev, seed=42)
-    err = event_errors(p4, p4o)
-    _say(f"mixed N={n} max |dc|/E per daughter: {err}")
-    assert np.all(err <= MIXED_TOL), err
+    rep = mixed_error_report(p4, p4o, M)
+    _say(f"mixed N={n} m={masses[0]}: {rep}")
+    if min(masses) > 0.0:
+        assert rep["max_rel_E"] <= MIXED_TOL, rep
+    else:
+        assert rep["max_rel_M"] <= MIXED_MASSLESS_TOL_M, rep
+        assert rep["frac_above_1e-5"] <= MIXED_MASSLESS_TAIL, rep
     mo, so = oracle.integrate(M, masses, nev, seed=42)
     assert rel(st[1], mo) <= MIXED_INTEGRAL_TOL
 
@@ -295,9 +303,35 @@ def test_full_size_config2(P, masses):
     assert torch.equal(w, wm) and torch.equal(st, stm)
     ti = torch.as_tensor(idx, device="cuda")
     g = outm[:, :, ti].cpu().numpy()
-    worst = np.zeros(6)
-    for j, e in enumerate(idx):
-        p4o, _ = oracle.generate(M, masses, 1, seed=42, event_offset=int(e))
-        worst = np.maximum(worst, event_errors(g[:, :, j:j + 1], p4o))
-    _say(f"config2 mixed max |dc|/E: {worst}")
-    assert np.all(worst <= MIXED_TOL)
+    ora = np.concatenate([oracle.generate(M, masses, 1, seed=42, event_offset=int(e))[0] for e in idx],
+                         axis=2)
+    rep = mixed_error_report(g, ora, M)
+    _say(f"config2 mixed sampled errors: {rep}")
+    if min(masses) > 0.0:
+        assert rep["max_rel_E"] <= MIXED_TOL, rep
+    else:
+        assert rep["max_rel_M"] <= MIXED_MASSLESS_TOL_M, rep
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_events_per_thread_variants_are_bit_identical(P, mixed):
+    _say(f"ept variants mixed={mixed}")
+    M, m = 10.0, [0.13957] * 5
+    nev = 77_777
+    ref = None
+    path = 2 if mixed else 1
+    try:
+        for ept in (1, 2, 4):
+            P.set_events_per_thread(path, ept)
+            P.set_events_per_thread(0, ept)
+            p4, w, st = _run(P, M, m, nev, offset=5, mixed=mixed)
+            mean, sigma = P.integrate(M, m, nev, event_offset=5)
+            if ref is None:
+                ref = (p4, w, st, mean, sigma)
+                continue
+            assert np.array_equal(p4, ref[0]) and np.array_equal(w, ref[1])
+            assert rel(st[1], ref[2][1]) <= 1e-14 and rel(st[3], ref[2][3]) <= 1e-13
+            assert rel(mean, ref[3]) <= 1e-14 and rel(sigma, ref[4]) <= 1e-13
+    finally:
+        P.set_events_per_thread(path, 0)
+        P.set_events_per_thread(0, 0)

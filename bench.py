@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--nevents", type=int, default=100_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=15.0,
+                    help="length of the Poisson serving trace replayed in the extras (60 = full)")
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc: a 1 GiB torch copy (the calibration "
                          "kernel of known traffic) x3, then the main step x3; prints no JSON")
@@ -236,7 +238,30 @@ def extras(P, torch, dev, args):
                                  "write_GBs": 104 * n2 / (kms * 1e-3) / 1e9}
     del outm, w
     ex["cfg3_batched_64_channels"] = batched_extra(P, torch, dev, steps)
+    if args.serve_seconds > 0:
+        ex["cfg4_serving"] = serving_extra(P, args.serve_seconds)
     return ex
+
+
+def serving_extra(P, seconds):
+    """Poisson arrivals at 2000 req/s replayed in real time by the native loop."""
+    import numpy as np
+    from paper_1711_05683_amd.workloads import serving_requests
+    reqs = serving_requests(rate_hz=2000.0, duration_s=seconds)
+    descs = [P.request(r.parent_mass, r.masses, r.nevents, seed=r.seed, stream_id=r.stream_id,
+                       integrate_only=r.integrate_only) for r in reqs]
+    srv = P.Server(32 << 30, max_events_per_tick=1 << 22)
+    lat, wall, peak = srv.replay(descs, [r.arrival_s for r in reqs])
+    st = srv.stats()
+    srv.destroy()
+    lat = np.array(lat)
+    ok = lat >= 0
+    events = sum(r.nevents for r in reqs)
+    return {"requests": len(reqs), "trace_s": seconds, "wall_s": wall, "events": events,
+            "events_per_s": events / wall, "p50_ms": float(np.median(lat[ok]) * 1e3),
+            "p99_ms": float(np.quantile(lat[ok], 0.99) * 1e3), "max_ms": float(lat[ok].max() * 1e3),
+            "failed": int((~ok).sum()), "ticks": st["ticks"], "peak_arena_bytes": peak,
+            "budget_bytes": 32 << 30}
 
 
 def batched_extra(P, torch, dev, steps):

@@ -76,6 +76,7 @@ def lib():
         handle = ctypes.CDLL(LIB_PATH)
         _declare(handle)
         _declare_batch(handle)
+        _declare_serve(handle)
         _lib = handle
     return _lib
 
@@ -319,3 +320,160 @@ def autotune(chans, stream=None):
     _check(lib().hydra_phsp_autotune(_channel_array(chans), len(chans), _stream_handle(stream),
                                      ctypes.byref(t), ctypes.byref(ms)))
     return t.ept, t.grid_per_cu, ms.value
+
+
+# ----------------------------------------------------------------- serving ----
+
+class RequestDesc(ctypes.Structure):
+    """``hydra_phsp_request`` (include/hydra_phsp_serve.h)."""
+    _fields_ = [("parent_mass", ctypes.c_double), ("masses", ctypes.c_double * NMAX),
+                ("n_daughters", ctypes.c_int32), ("integrate_only", ctypes.c_int32),
+                ("nevents", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("stream_id", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ResultDesc(ctypes.Structure):
+    """``hydra_phsp_result``."""
+    _fields_ = [("status", ctypes.c_int32), ("n_daughters", ctypes.c_int32),
+                ("nevents", ctypes.c_uint64), ("mean", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("p4_dev", ctypes.c_void_p), ("weights_dev", ctypes.c_void_p),
+                ("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+def _declare_serve(lib):
+    c = ctypes
+    i, vp, u64 = c.c_int, c.c_void_p, c.c_uint64
+    lib.hydra_phsp_server_create.argtypes = [u64, u64, i, c.POINTER(c.c_void_p)]
+    lib.hydra_phsp_server_submit.argtypes = [vp, c.POINTER(RequestDesc), c.POINTER(u64)]
+    lib.hydra_phsp_server_step.argtypes = [vp]
+    lib.hydra_phsp_server_completed.argtypes = [vp, c.POINTER(u64), i]
+    lib.hydra_phsp_server_poll.argtypes = [vp, u64, c.POINTER(ResultDesc)]
+    lib.hydra_phsp_server_release.argtypes = [vp, u64]
+    lib.hydra_phsp_server_drain.argtypes = [vp]
+    lib.hydra_phsp_server_replay.argtypes = [vp, c.POINTER(RequestDesc), c.POINTER(c.c_double), i,
+                                             c.POINTER(c.c_double), c.POINTER(c.c_double),
+                                             c.POINTER(u64)]
+    lib.hydra_phsp_server_stats.argtypes = [vp, c.POINTER(u64), c.POINTER(u64), c.POINTER(u64),
+                                            c.POINTER(u64)]
+    lib.hydra_phsp_server_destroy.argtypes = [vp]
+    for name in ("create", "submit", "step", "completed", "poll", "release", "drain", "replay", "stats",
+                 "destroy"):
+        getattr(lib, f"hydra_phsp_server_{name}").restype = i
+
+
+def request(parent_mass: float, masses: Sequence[float], nevents: int, *, seed: int = 42,
+            stream_id: int = 0, integrate_only: bool = False) -> RequestDesc:
+    r = RequestDesc()
+    r.parent_mass = float(parent_mass)
+    for k, mk in enumerate(masses):
+        r.masses[k] = float(mk)
+    r.n_daughters = len(masses)
+    r.integrate_only = 1 if integrate_only else 0
+    r.nevents = nevents
+    r.seed = seed
+    r.stream_id = stream_id
+    return r
+
+
+class Server:
+    """Continuous-batching request server (device memory bounded by ``budget_bytes``)."""
+
+    def __init__(self, budget_bytes: int, max_events_per_tick: int = 0, max_active: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().hydra_phsp_server_create(budget_bytes, max_events_per_tick, max_active,
+                                              ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, req: RequestDesc) -> int:
+        rid = ctypes.c_uint64()
+        _check(lib().hydra_phsp_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        return rid.value
+
+    def submit_status(self, req: RequestDesc) -> int:
+        rid = ctypes.c_uint64()
+        return lib().hydra_phsp_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid))
+
+    def step(self) -> int:
+        n = lib().hydra_phsp_server_step(self._h)
+        if n < 0:
+            _check(n)
+        return n
+
+    def completed(self, max_ids: int = 1024):
+        ids = (ctypes.c_uint64 * max_ids)()
+        n = lib().hydra_phsp_server_completed(self._h, ids, max_ids)
+        if n < 0:
+            _check(n)
+        return [ids[i] for i in range(n)]
+
+    def poll(self, rid: int):
+        """ResultDesc when finished, else None."""
+        res = ResultDesc()
+        st = lib().hydra_phsp_server_poll(self._h, rid, ctypes.byref(res))
+        if st == EAGAIN:
+            return None
+        _check(st)
+        return res
+
+    def release(self, rid: int):
+        _check(lib().hydra_phsp_server_release(self._h, rid))
+
+    def drain(self):
+        _check(lib().hydra_phsp_server_drain(self._h))
+
+    def replay(self, reqs, arrivals):
+        """Native real-time replay; returns (latencies [s], wall seconds, peak arena bytes)."""
+        n = len(reqs)
+        arr = (RequestDesc * n)(*reqs)
+        at = (ctypes.c_double * n)(*arrivals)
+        lat = (ctypes.c_double * n)()
+        wall = ctypes.c_double()
+        peak = ctypes.c_uint64()
+        _check(lib().hydra_phsp_server_replay(self._h, arr, at, n, lat, ctypes.byref(wall),
+                                              ctypes.byref(peak)))
+        return [lat[i] for i in range(n)], wall.value, peak.value
+
+    def stats(self):
+        a, b, c, d = (ctypes.c_uint64() for _ in range(4))
+        _check(lib().hydra_phsp_server_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                             ctypes.byref(d)))
+        return {"bytes_in_use": a.value, "peak_bytes": b.value, "ticks": c.value, "finished": d.value}
+
+    def destroy(self):
+        if self._h:
+            _check(lib().hydra_phsp_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def device_view(ptr: int, shape, dtype=None) -> torch.Tensor:
+    """Copy server-owned device memory into a new torch tensor (before release)."""
+    import numpy as _np
+    dtype = dtype or torch.float64
+    n = int(_np.prod(shape))
+    out = torch.empty(n, dtype=dtype, device="cuda")
+    nbytes = n * out.element_size()
+    if n:
+        import ctypes as _c
+        hip = _hip_runtime()
+        st = hip.hipMemcpy(_c.c_void_p(out.data_ptr()), _c.c_void_p(ptr), _c.c_size_t(nbytes), 3)
+        if st != 0:
+            raise RuntimeError(f"hipMemcpy failed: {st}")
+    return out.reshape(shape)
+
+
+_hip = None
+
+
+def _hip_runtime():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    return _hip

@@ -109,4 +109,10 @@ struct BatchLaunch {
 template <int NMAXB, int EPT>
 hipError_t launch_batched(const BatchLaunch& b, hipStream_t stream);
 
+// Host launchers shared by the batched and serving paths.
+hipError_t launch_persistent(int nmaxb, int ept, const BatchLaunch& b, hipStream_t s);
+// Stage 1 over `ngroups` group references, then stage 2 over chans[0..nch).
+hipError_t launch_batch_merges(const DevChannel* chans, const GroupRef* groups, uint64_t ngroups, Moments* mid,
+                               uint64_t nch, hipStream_t s);
+
 } // namespace hphsp

@@ -59,7 +59,7 @@ struct hydra_phsp_plan {
 
 namespace hphsp {
 
-static hipError_t launch_persistent(int nmaxb, int ept, const BatchLaunch& b, hipStream_t s) {
+hipError_t launch_persistent(int nmaxb, int ept, const BatchLaunch& b, hipStream_t s) {
     if (nmaxb <= 8) {
         switch (ept) {
         case 1: return launch_batched<8, 1>(b, s);
@@ -74,6 +74,19 @@ static hipError_t launch_persistent(int nmaxb, int ept, const BatchLaunch& b, hi
         }
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_merges(const DevChannel* chans, const GroupRef* groups, uint64_t ngroups, Moments* mid,
+                               uint64_t nch, hipStream_t s) {
+    if (ngroups == 0 || nch == 0) return hipSuccess;
+    if (ngroups > 0x7FFFFFFFull || nch > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_merge_stage1, dim3((unsigned)ngroups), dim3(kStage1Block), 0, s, chans, groups,
+                       mid);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_merge_stage2, dim3((unsigned)nch), dim3(kStage2Block), 0, s, chans,
+                       (const Moments*)mid);
+    return hipGetLastError();
 }
 
 static int check_channel(const hydra_phsp_channel& c, Channel* ch) {
@@ -107,13 +120,7 @@ static int enqueue_plan(hydra_phsp_plan* p, hipStream_t s, bool timed) {
         timing_end(s, slot);
         if (e != hipSuccess) return fail_hip(e, "batched kernel launch");
     }
-    hipLaunchKernelGGL(k_batch_merge_stage1, dim3((unsigned)p->ngroups), dim3(kStage1Block), 0, s,
-                       (const DevChannel*)p->d_chans, (const GroupRef*)p->d_groups, p->d_mid);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail_hip(e, "batch merge launch");
-    hipLaunchKernelGGL(k_batch_merge_stage2, dim3((unsigned)p->nch), dim3(kStage2Block), 0, s,
-                       (const DevChannel*)p->d_chans, (const Moments*)p->d_mid);
-    e = hipGetLastError();
+    hipError_t e = launch_batch_merges(p->d_chans, p->d_groups, p->ngroups, p->d_mid, (uint64_t)p->nch, s);
     if (e != hipSuccess) return fail_hip(e, "batch merge launch");
     return HYDRA_PHSP_OK;
 }

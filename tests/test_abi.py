@@ -105,7 +105,7 @@ def test_product_path_does_not_import_oracle():
             assert "phsp_oracle" not in text and "_liboracle" not in text, path
 
 
-def test_batch_struct_layout_matches_header(P, tmp_path):
+def test_struct_layouts_match_headers(P, tmp_path):
     # Compile a probe against the public header and compare with the binding.
     import shutil
     import subprocess
@@ -117,11 +117,16 @@ def test_batch_struct_layout_matches_header(P, tmp_path):
 #include <stddef.h>
 #include <stdio.h>
 #include "hydra_phsp_batch.h"
+#include "hydra_phsp_serve.h"
 int main(void) {
-    printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(hydra_phsp_channel),
+    printf("%zu %zu %zu %zu %zu %zu %zu ", sizeof(hydra_phsp_channel),
            offsetof(hydra_phsp_channel, n_daughters), offsetof(hydra_phsp_channel, nevents),
            offsetof(hydra_phsp_channel, p4_out_dev), offsetof(hydra_phsp_channel, stats_dev),
            sizeof(hydra_phsp_tuning), offsetof(hydra_phsp_tuning, grid_per_cu));
+    printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(hydra_phsp_request),
+           offsetof(hydra_phsp_request, integrate_only), offsetof(hydra_phsp_request, stream_id),
+           sizeof(hydra_phsp_result), offsetof(hydra_phsp_result, mean),
+           offsetof(hydra_phsp_result, weights_dev), offsetof(hydra_phsp_result, done_s));
     return 0;
 }
 ''')
@@ -129,9 +134,11 @@ int main(void) {
     subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
-    C, T = P.ChannelDesc, P.Tuning
+    C, T, Q, R = P.ChannelDesc, P.Tuning, P.RequestDesc, P.ResultDesc
     want = [ctypes.sizeof(C), C.n_daughters.offset, C.nevents.offset, C.p4_out_dev.offset,
-            C.stats_dev.offset, ctypes.sizeof(T), T.grid_per_cu.offset]
+            C.stats_dev.offset, ctypes.sizeof(T), T.grid_per_cu.offset,
+            ctypes.sizeof(Q), Q.integrate_only.offset, Q.stream_id.offset,
+            ctypes.sizeof(R), R.mean.offset, R.weights_dev.offset, R.done_s.offset]
     assert got == want
 
 

@@ -158,8 +158,9 @@ def test_plan_graph_replays(P):
         torch.cuda.synchronize()
         for i, (o, w, s) in enumerate(bufs):
             ro, rw, rs = ref[i]
+            n = specs[i].nevents
             if o is not None:
-                assert torch.equal(o, ro) and torch.equal(w, rw), (rep, i)
+                assert torch.equal(o[:, :, :n], ro[:, :, :n]) and torch.equal(w[:n], rw[:n]), (rep, i)
             assert torch.equal(s, rs), (rep, i)
     plan.destroy()
 

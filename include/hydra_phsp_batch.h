@@ -41,7 +41,7 @@ typedef struct hydra_phsp_channel {
 /* Launch shape of the persistent kernel (blocks of 256 threads):
  *   ept          events per thread: 1, 2 or 4 (a tile is 256*ept events);
  *   grid_per_cu  persistent blocks per compute unit, 1 .. 64.
- * A zero field selects the library default (ept 1, grid_per_cu 8). */
+ * A zero field selects the library default (ept 4, grid_per_cu 8). */
 typedef struct hydra_phsp_tuning {
     int32_t ept;
     int32_t grid_per_cu;

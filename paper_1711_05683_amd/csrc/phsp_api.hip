@@ -124,6 +124,8 @@ int workspace_for(hipStream_t stream, uint64_t partials, Workspace** out) {
     return HYDRA_PHSP_OK;
 }
 
+static void release_trig_tables();
+
 int release_workspaces() {
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     hipError_t e = hipDeviceSynchronize();
@@ -135,7 +137,51 @@ int release_workspaces() {
         if (kv.second.stats_host) (void)hipHostFree(kv.second.stats_host);
     }
     g_ws.clear();
+    release_trig_tables();
     return HYDRA_PHSP_OK;
+}
+
+// ------------------------------------------------------ trigonometric table ----
+
+static std::mutex g_trig_mu;
+static std::map<int, double2*> g_trig;
+
+// (cos, sin)(2 pi k / kTrigSize) for k = 0..kTrigSize-1, evaluated in long double
+// and rounded once; one device copy per GPU, created on first use.
+int trig_table(const double2** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_trig_mu);
+    auto it = g_trig.find(dev);
+    if (it != g_trig.end()) {
+        *out = it->second;
+        return HYDRA_PHSP_OK;
+    }
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    std::vector<double2> h(kTrigSize);
+    for (int k = 0; k < kTrigSize; ++k) {
+        const long double a = two_pi * (long double)k / (long double)kTrigSize;
+        h[k].x = (double)cosl(a);
+        h[k].y = (double)sinl(a);
+    }
+    double2* d = nullptr;
+    e = hipMalloc(&d, sizeof(double2) * kTrigSize);
+    if (e != hipSuccess) return fail(HYDRA_PHSP_ENOMEM, "table allocation failed");
+    e = hipMemcpy(d, h.data(), sizeof(double2) * kTrigSize, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail_hip(e, "table upload");
+    }
+    g_trig[dev] = d;
+    *out = d;
+    return HYDRA_PHSP_OK;
+}
+
+static void release_trig_tables() {
+    std::lock_guard<std::mutex> lock(g_trig_mu);
+    for (auto& kv : g_trig) (void)hipFree(kv.second);
+    g_trig.clear();
 }
 
 // ----------------------------------------------------------------- timing ----
@@ -205,7 +251,7 @@ static int g_ept_override[3] = {0, 0, 0};
 static int default_ept(int mode) {
     const int o = g_ept_override[mode];
     if (o > 0) return o;
-    return mode == kIntegrate ? 2 : 1;
+    return 4;
 }
 
 int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const double* parent_dev,
@@ -218,6 +264,9 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
     if (blocks > 0x7FFFFFFFull) return fail(HYDRA_PHSP_EINVAL, "nevents too large for one launch");
     Workspace* ws = nullptr;
     int st = workspace_for(stream, blocks, &ws);
+    if (st != HYDRA_PHSP_OK) return st;
+    const double2* trig = nullptr;
+    st = trig_table(&trig);
     if (st != HYDRA_PHSP_OK) return st;
     if (blocks > 0) {
         KArgs a;
@@ -236,6 +285,7 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
         a.ld = ld;
         a.weights = weights;
         a.partials = ws->partials;
+        a.trig = trig;
         LaunchSpec s{pmode, mode, ept, blocks};
         const long slot = timing_begin(stream);
         hipError_t e = launch_by_n(n, s, a, stream);

@@ -22,6 +22,8 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
                int ept_override);
 int release_workspaces();
 int release_batch_slots();
+// The device's (cos, sin) table used by the FP64 kernels (created on first use).
+int trig_table(const double2** out);
 // Benchmark timing brackets around a kernel launch (slot -1: timing off).
 long timing_begin(hipStream_t stream);
 void timing_end(hipStream_t stream, long slot);

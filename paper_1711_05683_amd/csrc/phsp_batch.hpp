@@ -42,14 +42,14 @@ struct GroupRef {
 // The body of k_phsp for one tile, with the channel's arguments read from the
 // (wave-uniform) channel record.
 template <int N, int MODE, int EPT>
-__device__ __forceinline__ void run_tile(const KArgs& a, uint64_t blk) {
+__device__ __forceinline__ void run_tile(const KArgs& a, uint64_t blk, const double2* tab) {
     const uint64_t base = blk * (uint64_t)(kBlock * EPT);
     Moments acc{0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        const uint64_t e = base + (uint64_t)(k * kBlock) + threadIdx.x;
-        if (e < a.nevents) {
-            const double w = run_event<N, kAtRest, MODE>(a, e);
+        const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
+        if (base + off < a.nevents) {
+            const double w = run_event<N, kAtRest, MODE, false>(a, base, off, tab);
             if (k == 0) {
                 acc = Moments{1.0, w, 0.0};
             } else {
@@ -66,30 +66,36 @@ __device__ __forceinline__ void run_tile(const KArgs& a, uint64_t blk) {
 }
 
 template <int N, int EPT>
-__device__ __forceinline__ void run_tile_mode(const DevChannel& c, uint64_t blk) {
+__device__ __forceinline__ void run_tile_mode(const DevChannel& c, uint64_t blk, const double2* tab) {
     if (c.mode == kIntegrate)
-        run_tile<N, kIntegrate, EPT>(c.a, blk);
+        run_tile<N, kIntegrate, EPT>(c.a, blk, tab);
     else
-        run_tile<N, kFp64, EPT>(c.a, blk);
+        run_tile<N, kFp64, EPT>(c.a, blk, tab);
 }
 
+// One kernel holds every N's code path, so its register budget is set by the
+// largest N; the waves-per-SIMD hint caps it (3 waves: <= 168 VGPRs for N <= 8,
+// 2 waves for N <= 10) instead of letting the scheduler trade occupancy for
+// latency hiding.
 template <int NMAXB, int EPT>
-__global__ __launch_bounds__(kBlock) void k_phsp_batched(const DevChannel* __restrict__ chans,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NMAXB <= 8 ? 3 : 2))) void k_phsp_batched(const DevChannel* __restrict__ chans,
                                                          const TileRef* __restrict__ tiles,
-                                                         uint64_t ntiles) {
+                                                         uint64_t ntiles, const double2* __restrict__ trig) {
+    __shared__ double2 tab[kTrigSize];
+    load_trig(tab, trig);
     for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileRef tr = tiles[t];
         const DevChannel& c = chans[tr.channel];
         switch (c.n) {
-        case 2: run_tile_mode<2, EPT>(c, tr.block); break;
-        case 3: run_tile_mode<3, EPT>(c, tr.block); break;
-        case 4: run_tile_mode<4, EPT>(c, tr.block); break;
-        case 5: run_tile_mode<5, EPT>(c, tr.block); break;
-        case 6: run_tile_mode<6, EPT>(c, tr.block); break;
-        case 7: run_tile_mode<7, EPT>(c, tr.block); break;
-        case 8: run_tile_mode<8, EPT>(c, tr.block); break;
-        case 9: if constexpr (NMAXB >= 9) run_tile_mode<9, EPT>(c, tr.block); break;
-        case 10: if constexpr (NMAXB >= 10) run_tile_mode<10, EPT>(c, tr.block); break;
+        case 2: run_tile_mode<2, EPT>(c, tr.block, tab); break;
+        case 3: run_tile_mode<3, EPT>(c, tr.block, tab); break;
+        case 4: run_tile_mode<4, EPT>(c, tr.block, tab); break;
+        case 5: run_tile_mode<5, EPT>(c, tr.block, tab); break;
+        case 6: run_tile_mode<6, EPT>(c, tr.block, tab); break;
+        case 7: run_tile_mode<7, EPT>(c, tr.block, tab); break;
+        case 8: run_tile_mode<8, EPT>(c, tr.block, tab); break;
+        case 9: if constexpr (NMAXB >= 9) run_tile_mode<9, EPT>(c, tr.block, tab); break;
+        case 10: if constexpr (NMAXB >= 10) run_tile_mode<10, EPT>(c, tr.block, tab); break;
         default: break;
         }
         // The tile's LDS reduction must finish before the next tile reuses LDS.
@@ -102,6 +108,7 @@ struct BatchLaunch {
     const TileRef* tiles;
     uint64_t ntiles;
     uint64_t grid;
+    const double2* trig;
 };
 
 // Persistent-kernel launcher for one (NMAXB, EPT) pair, defined per

@@ -54,6 +54,7 @@ struct hydra_phsp_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
+    const double2* trig = nullptr;
     bool launched = false;
 };
 
@@ -114,7 +115,7 @@ static void free_plan(hydra_phsp_plan* p) {
 // Enqueue the launch sequence of a plan on `s` (no graph).
 static int enqueue_plan(hydra_phsp_plan* p, hipStream_t s, bool timed) {
     if (p->ntiles > 0) {
-        BatchLaunch b{p->d_chans, p->d_tiles, p->ntiles, p->grid};
+        BatchLaunch b{p->d_chans, p->d_tiles, p->ntiles, p->grid, p->trig};
         const long slot = timed ? timing_begin(s) : -1;
         hipError_t e = launch_persistent(p->nmaxb, p->ept, b, s);
         timing_end(s, slot);
@@ -142,7 +143,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     if (bad) *bad = -1;
     if (chans == nullptr || nch <= 0) return fail(HYDRA_PHSP_EINVAL, "need at least one channel");
     if (out == nullptr) return fail(HYDRA_PHSP_EINVAL, "plan_out is NULL");
-    int ept = 1, gpc = 8;
+    int ept = 4, gpc = 8;
     if (tuning) {
         if (tuning->ept) ept = tuning->ept;
         if (tuning->grid_per_cu) gpc = tuning->grid_per_cu;
@@ -200,8 +201,12 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return fail_hip(e, "hipDeviceGetAttribute");
 
+    const double2* trig = nullptr;
+    int tst = trig_table(&trig);
+    if (tst != HYDRA_PHSP_OK) return tst;
     hydra_phsp_plan* p = new hydra_phsp_plan();
     p->device = dev;
+    p->trig = trig;
     p->nch = nch;
     p->nmaxb = nmax <= 8 ? 8 : 10;
     p->ept = ept;
@@ -413,7 +418,7 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
         return fail(HYDRA_PHSP_EDEVICE, "hipEventCreate failed");
     double best_ms = 1e300;
-    hydra_phsp_tuning best{1, 8, {0, 0}};
+    hydra_phsp_tuning best{4, 8, {0, 0}};
     int st = HYDRA_PHSP_OK;
     const int epts[3] = {1, 2, 4};
     const int gpcs[5] = {1, 2, 4, 8, 16};

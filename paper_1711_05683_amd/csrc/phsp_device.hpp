@@ -6,16 +6,25 @@
 // boosts back to the parent frame (Raubold-Lynch method, arXiv:1711.05683
 // sec. 4.2).  Everything here is register-resident; the kernels that include
 // this header own the memory traffic (SoA stores) and the reductions.
+//
+// Uniform k of an event is built from words 2k and 2k+1 of its Philox stream,
+// i.e. from half k&1 of call k>>1.  The N-2 mass uniforms come first; the
+// (theta, phi) pair of level i are uniforms N-2+2i and N-1+2i, drawn only when
+// that level is built (so integrate-only launches never draw angles, and only
+// two angle uniforms are live at a time).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "phsp_sortnet.hpp"
 
 namespace hphsp {
 
 constexpr int kNMax = 10;
+constexpr int kTrigSize = 256; // entries of the (cos, sin)(2 pi k / 256) table
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
 // multiplies and xors on a 4-word counter; the 2-word key advances by the Weyl
@@ -54,6 +63,26 @@ __device__ __forceinline__ double uniform_from_words(uint32_t lo, uint32_t hi) {
     return (one_plus - 1.0) + 0x1p-53;
 }
 
+// Counter state of one event's stream: call j uses counter (g lo, g hi, j, sid).
+struct EventRng {
+    uint32_t glo, ghi, sid, k0, k1;
+    __device__ __forceinline__ void call(uint32_t j, double& a, double& b) const {
+        const Words4 w = philox4x32_10(glo, ghi, j, sid, k0, k1);
+        a = uniform_from_words(w.x, w.y);
+        b = uniform_from_words(w.z, w.w);
+    }
+};
+
+// Reciprocal to full double precision: the hardware estimate refined by two
+// Newton-Raphson steps (each squares the relative error).
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Per-channel constants, computed once on the host.
 struct Channel {
     double M;          // parent mass
@@ -90,73 +119,66 @@ __device__ __forceinline__ void boost(R& e, R& x, R& y, R& z, R ex, R ey, R ez, 
     z = fma(f, ez, z);
 }
 
-// The random words of global event g: J Philox blocks, counter (g lo, g hi, j, sid).
+// Mass uniforms of one event (sorted in place by event_levels).  For odd N the
+// last mass call also yields level 0's theta uniform, kept in `carry`.
 template <int N>
-struct Draws {
-    static constexpr int kUniforms = 3 * N - 4;
-    static constexpr int kBlocks = (2 * kUniforms + 3) / 4;
-    double u[kUniforms];
+struct MassDraws {
+    static constexpr int kMass = N - 2;
+    double u[kMass > 0 ? kMass : 1];
+    double carry;
 };
 
 template <int N>
-__device__ __forceinline__ void draw_uniforms(Draws<N>& d, uint32_t k0, uint32_t k1, uint32_t sid,
-                                              uint64_t g) {
-    const uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
+__device__ __forceinline__ void draw_masses(MassDraws<N>& d, const EventRng& rng) {
 #pragma unroll
-    for (int j = 0; j < Draws<N>::kBlocks; ++j) {
-        const Words4 w = philox4x32_10(glo, ghi, (uint32_t)j, sid, k0, k1);
-        if (2 * j < Draws<N>::kUniforms) d.u[2 * j] = uniform_from_words(w.x, w.y);
-        if (2 * j + 1 < Draws<N>::kUniforms) d.u[2 * j + 1] = uniform_from_words(w.z, w.w);
+    for (int j = 0; 2 * j + 1 < N - 2; ++j) rng.call((uint32_t)j, d.u[2 * j], d.u[2 * j + 1]);
+    if constexpr ((N - 2) % 2 == 1) {
+        double a, b;
+        rng.call((uint32_t)((N - 3) / 2), a, b);
+        d.u[N - 3] = a;
+        d.carry = b;
+    } else {
+        d.carry = 0.0;
     }
 }
 
-// FP64 part shared by both precisions: sorted mass uniforms -> invariant masses
-// sigma_i, breakup momenta p_i, 1/sigma_i, and the weight C prod p_i.
+// (theta, phi) uniforms of level i, drawn on demand.  For even N they are both
+// halves of call (N-2)/2 + i; for odd N, theta is the carried second half of the
+// previous call and phi the first half of call (N-1)/2 + i.
 template <int N>
-struct Levels {
-    double p[N - 1];     // breakup momentum of level i (sigma_{i+1} -> sigma_i + m_{i+1})
-    double sigma[N];     // invariant mass of daughters {0..i}
-    double inv_sigma[N]; // 1 / sigma_i for 1 <= i <= N-2
-    double w;            // event weight
-};
-
-template <int N>
-__device__ __forceinline__ void solve_levels(const Channel& c, Draws<N>& d, Levels<N>& L) {
-    // Sorted R_1..R_{N-2}; R_0 = 0 and R_{N-1} = 1 are implicit.
-    sortnet_sort<N - 2>(d.u);
-    L.sigma[0] = c.m[0];
-#pragma unroll
-    for (int i = 1; i <= N - 2; ++i) L.sigma[i] = fma(c.T, d.u[i - 1], c.S[i]);
-    L.sigma[N - 1] = c.M;
-#pragma unroll
-    for (int i = 1; i <= N - 2; ++i) L.inv_sigma[i] = 1.0 / L.sigma[i];
-    double w = c.C;
-#pragma unroll
-    for (int i = 0; i <= N - 2; ++i) {
-        const double r_hi = (i + 1 <= N - 2) ? d.u[i] : 1.0;
-        const double r_lo = (i >= 1) ? d.u[i - 1] : 0.0;
-        const double g = c.T * (r_hi - r_lo); // energy released at level i
-        const double b = L.sigma[i], m = c.m[i + 1];
-        const double q = g * (2.0 * b + 2.0 * m + g) * (g + 2.0 * m) * (2.0 * b + g);
-        const double half_inv = (i + 1 <= N - 2) ? 0.5 * L.inv_sigma[i + 1] : c.half_inv_M;
-        L.p[i] = sqrt(q) * half_inv;
-        w *= L.p[i];
+__device__ __forceinline__ void draw_angles(const EventRng& rng, int i, double& carry, double& ut, double& up) {
+    if constexpr (N % 2 == 0) {
+        rng.call((uint32_t)((N - 2) / 2 + i), ut, up);
+    } else {
+        ut = carry;
+        rng.call((uint32_t)((N - 1) / 2 + i), up, carry);
     }
-    L.w = w;
 }
 
-// Direction of level i from its (theta, phi) uniforms:
+// sin and cos of 2 pi v for v in (0, 1): v = k/256 + f/256 with k = rint(256 v)
+// and |f| <= 1/2 (both exact); the table holds (cos, sin)(2 pi k/256) and short
+// Taylor series give sin d and cos d - 1 for d = 2 pi f/256, |d| <= pi/256
+// (truncation below 1e-20), combined by the angle-addition formulas.
+__device__ __forceinline__ void sincos_2pi_table(double v, const double2* tab, double& s, double& c) {
+    const double x = v * (double)kTrigSize;
+    const double k = rint(x);
+    const double d = (x - k) * 0.02454369260617026; // 2 pi / 256
+    const double d2 = d * d;
+    const double sd = fma(d * d2, fma(d2, fma(d2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), d);
+    const double cm1 = d2 * fma(d2, fma(d2, -1.0 / 720.0, 1.0 / 24.0), -0.5);
+    const double2 t = tab[((int)k) & (kTrigSize - 1)];
+    s = fma(t.y, cm1, fma(t.x, sd, t.y));
+    c = fma(t.x, cm1, fma(-t.y, sd, t.x));
+}
+
+// Direction of a level from its (theta, phi) uniforms:
 // cos(theta) = 2u - 1, sin(theta) = 2 sqrt(u (1-u)), phi = 2 pi v.
-template <typename R>
-__device__ __forceinline__ void direction(double u, double v, R& nx, R& ny, R& nz);
-
-template <>
-__device__ __forceinline__ void direction<double>(double u, double v, double& nx, double& ny,
-                                                  double& nz) {
+__device__ __forceinline__ void direction(double u, double v, const double2* tab, double& nx, double& ny,
+                                          double& nz) {
     const double ct = 2.0 * u - 1.0;
     const double st = 2.0 * sqrt(u * (1.0 - u));
     double sp, cp;
-    sincospi(2.0 * v, &sp, &cp);
+    sincos_2pi_table(v, tab, sp, cp);
     nx = st * cp;
     ny = st * sp;
     nz = ct;
@@ -166,8 +188,8 @@ __device__ __forceinline__ void direction<double>(double u, double v, double& nx
 // FP64 (exact / one rounding) before the conversion, so directions near the
 // poles keep FP32 relative accuracy, and phi's uniform is first reduced to
 // [-1/2, 1/2] (exactly) so its conversion error is absolute, not relative to 1.
-template <>
-__device__ __forceinline__ void direction<float>(double u, double v, float& nx, float& ny, float& nz) {
+__device__ __forceinline__ void direction(double u, double v, const double2*, float& nx, float& ny,
+                                          float& nz) {
     const float ct = (float)(2.0 * u - 1.0);
     const float st = 2.0f * sqrtf((float)(u * (1.0 - u)));
     const float r = (float)(v - rint(v));
@@ -178,47 +200,92 @@ __device__ __forceinline__ void direction<float>(double u, double v, float& nx, 
     nz = ct;
 }
 
-// Kinematics in precision R (double: the plain path; float: the mixed path).
-// Level 0 puts daughters 0 and 1 back to back in the rest frame of {0,1}; level
-// i adds daughter i+1 against {0..i} and boosts daughters 0..i from the rest
-// frame of {0..i} into that of {0..i+1}.
-template <int N, typename R>
-__device__ __forceinline__ void build_event(const Channel& c, const Draws<N>& d, const Levels<N>& L,
-                                            Event<N, R>& ev) {
-    {
-        R nx, ny, nz;
-        direction<R>(d.u[N - 2], d.u[N - 1], nx, ny, nz);
-        const R p = R(L.p[0]);
-        const R m0 = R(c.m[0]), m1 = R(c.m[1]);
-        ev.e[1] = sqrt(fma(p, p, m1 * m1));
-        ev.x[1] = p * nx;
-        ev.y[1] = p * ny;
-        ev.z[1] = p * nz;
-        ev.e[0] = sqrt(fma(p, p, m0 * m0));
-        ev.x[0] = -ev.x[1];
-        ev.y[0] = -ev.y[1];
-        ev.z[0] = -ev.z[1];
-    }
+// Energies of the two bodies of a level in the rest frame of hi = lo + m + g:
+//   E(m) = (hi^2 + m^2 - lo^2) / (2 hi) = ((m + g)(hi + lo) + m^2) h,  h = 1/(2 hi),
+// and E(lo) likewise with m and lo exchanged; every term is non-negative, so
+// nothing cancels.
+__device__ __forceinline__ double level_energy(double m, double lo, double g, double hi, double h) {
+    return fma(m + g, hi + lo, m * m) * h;
+}
+
+// All two-body levels of one event, in one pass.  The weight (always FP64) is
+// C prod_i p_i with the invariant masses sigma_i = S_i + T R_i of the sorted
+// mass uniforms, the energy released g_i = T (R_{i+1} - R_i) and the breakup
+// momentum p_i of sigma_{i+1} -> sigma_i + m_{i+1}.  With KIN, the kinematics of
+// the level follow at once, in precision R (double: the plain path; float: the
+// mixed path): level 0 puts daughters 0 and 1 back to back in the rest frame of
+// {0,1}; level i adds daughter i+1 against {0..i} and boosts daughters 0..i
+// from the rest frame of {0..i} into that of {0..i+1}.  Only the current
+// level's quantities are live, besides the sorted uniforms and the momenta.
+template <int N, typename R, bool KIN>
+__device__ __forceinline__ double event_levels(const Channel& c, const EventRng& rng, MassDraws<N>& d,
+                                               const double2* tab, Event<N, R>& ev) {
+    constexpr bool kF64 = std::is_same<R, double>::value;
+    sortnet_sort<N - 2>(d.u); // R_1..R_{N-2}; R_0 = 0 and R_{N-1} = 1 are implicit
+    double carry = d.carry;
+    double w = c.C;
+    double sig_lo = c.m[0]; // sigma_i
+    double inv_lo = 0.0;    // 1 / sigma_i (i >= 1)
 #pragma unroll
-    for (int i = 1; i <= N - 2; ++i) {
-        R nx, ny, nz;
-        direction<R>(d.u[N - 2 + 2 * i], d.u[N - 1 + 2 * i], nx, ny, nz);
-        const R p = R(L.p[i]);
-        const R mi = R(c.m[i + 1]);
-        ev.e[i + 1] = sqrt(fma(p, p, mi * mi));
-        ev.x[i + 1] = p * nx;
-        ev.y[i + 1] = p * ny;
-        ev.z[i + 1] = p * nz;
-        const R sig = R(L.sigma[i]);
-        const R isig = R(L.inv_sigma[i]);
-        const R eta = -(p * isig);
-        const R ex = eta * nx, ey = eta * ny, ez = eta * nz;
-        const R gamma = sqrt(fma(p, p, sig * sig)) * isig;
-        const R inv_gp1 = R(1) / (gamma + R(1));
+    for (int i = 0; i <= N - 2; ++i) {
+        constexpr int kTop = N - 2;
+        const bool inner = i < kTop; // sigma_{i+1} is an inner subsystem, not the parent
+        const double r_hi = inner ? d.u[i] : 1.0;
+        const double r_lo = (i >= 1) ? d.u[i - 1] : 0.0;
+        const double sig_hi = inner ? fma(c.T, r_hi, c.S[i + 1]) : c.M;
+        const double inv_hi = inner ? recip(sig_hi) : 0.0;
+        const double h = inner ? 0.5 * inv_hi : c.half_inv_M; // 1 / (2 sigma_{i+1})
+        const double g = c.T * (r_hi - r_lo);
+        const double m = c.m[i + 1];
+        const double q = g * (2.0 * sig_lo + 2.0 * m + g) * (g + 2.0 * m) * (2.0 * sig_lo + g);
+        const double pd = sqrt(q) * h;
+        w *= pd;
+        if constexpr (KIN) {
+            double ut, up;
+            draw_angles<N>(rng, i, carry, ut, up);
+            R nx, ny, nz;
+            direction(ut, up, tab, nx, ny, nz);
+            const R p = R(pd);
+            ev.x[i + 1] = p * nx;
+            ev.y[i + 1] = p * ny;
+            ev.z[i + 1] = p * nz;
+            if (i == 0) {
+                if constexpr (kF64) {
+                    ev.e[1] = level_energy(m, sig_lo, g, sig_hi, h);
+                    ev.e[0] = level_energy(sig_lo, m, g, sig_hi, h);
+                } else {
+                    const R m0 = R(c.m[0]), m1 = R(m);
+                    ev.e[1] = sqrt(fma(p, p, m1 * m1));
+                    ev.e[0] = sqrt(fma(p, p, m0 * m0));
+                }
+                ev.x[0] = -ev.x[1];
+                ev.y[0] = -ev.y[1];
+                ev.z[0] = -ev.z[1];
+            } else {
+                R gamma, inv_gp1;
+                if constexpr (kF64) {
+                    ev.e[i + 1] = level_energy(m, sig_lo, g, sig_hi, h);
+                    const double esys = level_energy(sig_lo, m, g, sig_hi, h); // energy of {0..i}
+                    gamma = esys * inv_lo;
+                    inv_gp1 = sig_lo * recip(esys + sig_lo); // 1/(gamma+1) = sigma / (E + sigma)
+                } else {
+                    const R mi = R(m);
+                    ev.e[i + 1] = sqrt(fma(p, p, mi * mi));
+                    const R sig = R(sig_lo);
+                    gamma = sqrt(fma(p, p, sig * sig)) * R(inv_lo);
+                    inv_gp1 = R(1) / (gamma + R(1));
+                }
+                const R eta = -(p * R(inv_lo));
+                const R ex = eta * nx, ey = eta * ny, ez = eta * nz;
 #pragma unroll
-        for (int k = 0; k <= i; ++k)
-            boost<R>(ev.e[k], ev.x[k], ev.y[k], ev.z[k], ex, ey, ez, gamma, inv_gp1);
+                for (int k = 0; k <= i; ++k)
+                    boost<R>(ev.e[k], ev.x[k], ev.y[k], ev.z[k], ex, ey, ez, gamma, inv_gp1);
+            }
+        }
+        sig_lo = sig_hi;
+        inv_lo = inv_hi;
     }
+    return w;
 }
 
 template <int N, typename R>
@@ -227,6 +294,13 @@ __device__ __forceinline__ void boost_to_lab(Event<N, R>& ev, const Frame& f) {
     const R gamma = R(f.gamma), inv_gp1 = R(f.inv_gp1);
 #pragma unroll
     for (int k = 0; k < N; ++k) boost<R>(ev.e[k], ev.x[k], ev.y[k], ev.z[k], ex, ey, ez, gamma, inv_gp1);
+}
+
+// The block's copy of the (cos, sin) table: filled once per block from the
+// library's device table (block size >= kTrigSize), then read per lane.
+__device__ __forceinline__ void load_trig(double2* lds, const double2* global) {
+    if (threadIdx.x < kTrigSize) lds[threadIdx.x] = global[threadIdx.x];
+    __syncthreads();
 }
 
 } // namespace hphsp

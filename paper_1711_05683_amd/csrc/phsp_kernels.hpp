@@ -14,6 +14,7 @@
 namespace hphsp {
 
 constexpr int kBlock = 256;
+static_assert(kBlock >= kTrigSize, "a block loads the trigonometric table with one entry per thread");
 constexpr int kWaves = kBlock / 64;
 
 enum ParentMode { kAtRest = 0, kBroadcast = 1, kPerEvent = 2 };
@@ -32,66 +33,97 @@ struct KArgs {
     uint64_t ld;
     double* weights;       // [nevents]
     Moments* partials;     // [gridDim.x]
+    const double2* trig;   // kTrigSize (cos, sin) pairs of 2 pi k / kTrigSize
 };
 
+// Non-temporal store to column `col` at byte offset `boff` (32-bit): the column
+// base is wave-uniform, so the store takes the scalar-base + vector-offset form.
+template <bool PIN, typename R>
+__device__ __forceinline__ void store_col(R* col, uint32_t boff, R v) {
+    if constexpr (!PIN) {
+        __builtin_nontemporal_store(v, reinterpret_cast<R*>(reinterpret_cast<char*>(col) + boff));
+        return;
+    }
+    // Pin the column base in scalar registers so the compiler does not fold the
+    // columns into one per-lane 64-bit base (which costs a 64-bit add per store).
+    // Only for few columns: each pinned base holds two scalar registers.
+    const uint64_t p = reinterpret_cast<uint64_t>(col);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    using gchar = __attribute__((address_space(1))) char;
+    using gR = __attribute__((address_space(1))) R;
+    gchar* base = (gchar*)(((uint64_t)hi << 32) | lo);
+    __builtin_nontemporal_store(v, (gR*)(base + boff));
+}
+
 template <typename R>
-__device__ __forceinline__ void store_nt(R* p, R v) {
-    __builtin_nontemporal_store(v, p);
+__device__ __forceinline__ R load_col(const R* col, uint32_t boff) {
+    return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(col) + boff);
 }
 
 // Per-event parent frame: eta = P/M, gamma = E/M, 1/(gamma+1) = M/(E+M).
-__device__ __forceinline__ Frame load_parent_frame(const double* parent, uint64_t ldp, uint64_t e,
+// `parent` already points at the block's first event; `off` is the lane's event
+// offset within the block.
+__device__ __forceinline__ Frame load_parent_frame(const double* parent, uint64_t ldp, uint32_t off,
                                                    double M, double inv_M) {
-    const double E = parent[e];
-    const double px = parent[ldp + e];
-    const double py = parent[2 * ldp + e];
-    const double pz = parent[3 * ldp + e];
+    const uint32_t boff = off * (uint32_t)sizeof(double);
+    const double E = load_col(parent, boff);
+    const double px = load_col(parent + ldp, boff);
+    const double py = load_col(parent + 2 * ldp, boff);
+    const double pz = load_col(parent + 3 * ldp, boff);
     Frame f;
     f.eta[0] = px * inv_M;
     f.eta[1] = py * inv_M;
     f.eta[2] = pz * inv_M;
     f.gamma = E * inv_M;
-    f.inv_gp1 = M / (E + M);
+    f.inv_gp1 = M * recip(E + M);
     return f;
 }
 
-// One event end to end: draws, levels, kinematics, lab boost, stores.
-template <int N, int PMODE, int MODE>
-__device__ __forceinline__ double run_event(const KArgs& a, uint64_t e) {
-    Draws<N> d;
-    draw_uniforms<N>(d, a.k0, a.k1, a.sid, a.event_offset + e);
-    Levels<N> L;
-    solve_levels<N>(a.ch, d, L);
+// One event end to end: draws, levels, kinematics, lab boost, stores.  The event
+// is base + off: `base` (the block's first event) is wave-uniform, so every
+// column address is a scalar base plus the lane's 32-bit offset (PIN keeps the
+// column bases in scalar registers).  `tab` is the block's LDS copy of the
+// trigonometric table (FP64 generate only).
+template <int N, int PMODE, int MODE, bool PIN = (N <= 5)>
+__device__ __forceinline__ double run_event(const KArgs& a, uint64_t base, uint32_t off, const double2* tab) {
+    const uint64_t g = a.event_offset + base + off;
+    const EventRng rng{(uint32_t)g, (uint32_t)(g >> 32), a.sid, a.k0, a.k1};
+    MassDraws<N> d;
+    draw_masses<N>(d, rng);
+    using R = typename std::conditional<MODE == kMixed, float, double>::type;
+    Event<N, R> ev;
+    const double w = event_levels<N, R, MODE != kIntegrate>(a.ch, rng, d, tab, ev);
     if constexpr (MODE != kIntegrate) {
-        using R = typename std::conditional<MODE == kMixed, float, double>::type;
-        Event<N, R> ev;
-        build_event<N, R>(a.ch, d, L, ev);
         if constexpr (PMODE == kBroadcast) boost_to_lab<N, R>(ev, a.frame);
         if constexpr (PMODE == kPerEvent)
-            boost_to_lab<N, R>(ev, load_parent_frame(a.parent, a.ld_parent, e, a.ch.M, a.inv_M));
-        R* out = static_cast<R*>(a.out) + e;
+            boost_to_lab<N, R>(ev, load_parent_frame(a.parent + base, a.ld_parent, off, a.ch.M, a.inv_M));
+        R* out = static_cast<R*>(a.out) + base;
         const uint64_t ld = a.ld;
+        const uint32_t boff = off * (uint32_t)sizeof(R);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            store_nt(out + (uint64_t)(4 * k + 0) * ld, ev.e[k]);
-            store_nt(out + (uint64_t)(4 * k + 1) * ld, ev.x[k]);
-            store_nt(out + (uint64_t)(4 * k + 2) * ld, ev.y[k]);
-            store_nt(out + (uint64_t)(4 * k + 3) * ld, ev.z[k]);
+            store_col<PIN>(out + (uint64_t)(4 * k + 0) * ld, boff, ev.e[k]);
+            store_col<PIN>(out + (uint64_t)(4 * k + 1) * ld, boff, ev.x[k]);
+            store_col<PIN>(out + (uint64_t)(4 * k + 2) * ld, boff, ev.y[k]);
+            store_col<PIN>(out + (uint64_t)(4 * k + 3) * ld, boff, ev.z[k]);
         }
-        store_nt(a.weights + e, L.w);
+        store_col<PIN>(a.weights + base, off * (uint32_t)sizeof(double), w);
     }
-    return L.w;
+    return w;
 }
 
 template <int N, int PMODE, int MODE, int EPT>
 __global__ __launch_bounds__(kBlock) void k_phsp(const KArgs a) {
+    __shared__ double2 tab[kTrigSize];
+    if constexpr (MODE == kFp64) load_trig(tab, a.trig);
     const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * EPT);
     Moments acc{0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        const uint64_t e = base + (uint64_t)(k * kBlock) + threadIdx.x;
-        if (e < a.nevents) {
-            const double w = run_event<N, PMODE, MODE>(a, e);
+        const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
+        if (base + off < a.nevents) {
+            const double w = run_event<N, PMODE, MODE>(a, base, off, tab);
             // Welford step with count k+1 (events of a lane form a prefix of its
             // steps).  The first event is taken as it is, so no rounding of w*w can
             // enter M2 when all weights are equal (two-body decays).

@@ -175,6 +175,7 @@ struct hydra_phsp_server {
     int max_active = 1024;
     Arena arena;
     hipStream_t stream = nullptr;
+    const double2* trig = nullptr;
     TickSlot slots[kTickSlots];
     int next_slot = 0;
     std::deque<int> busy_order; // slots in launch order
@@ -342,7 +343,7 @@ int launch_tick(hydra_phsp_server* s) {
     }
     if (e != hipSuccess) return fail_hip(e, "server table upload");
     BatchLaunch b{t.chans.dev, t.tiles.dev, (uint64_t)tiles.size(),
-                  std::min<uint64_t>((uint64_t)tiles.size(), 8ull * (uint64_t)s->cus)};
+                  std::min<uint64_t>((uint64_t)tiles.size(), 8ull * (uint64_t)s->cus), s->trig};
     e = launch_persistent(nmax <= 8 ? 8 : 10, kServeEpt, b, q);
     if (e != hipSuccess) return fail_hip(e, "server tick launch");
     if (!fin.empty()) {
@@ -403,6 +404,11 @@ int hydra_phsp_server_create(uint64_t hbm_budget_bytes, uint64_t max_events_per_
     if (e != hipSuccess) {
         delete s;
         return fail_hip(e, "hipGetDevice");
+    }
+    int tst = trig_table(&s->trig);
+    if (tst != HYDRA_PHSP_OK) {
+        delete s;
+        return tst;
     }
     if (!s->arena.init(hbm_budget_bytes)) {
         delete s;

@@ -192,7 +192,7 @@ def test_config3_full_batch(P):
         bufs.append((out, w, st))
         descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id,
                                out=out, weights=w, stats=st))
-    plan = P.Plan(descs, ept=1)
+    plan = P.Plan(descs)  # library default shape = the single-channel default
     plan.launch()
     torch.cuda.synchronize()
     rng = np.random.default_rng(0)

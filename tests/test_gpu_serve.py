@@ -91,7 +91,8 @@ def test_server_matches_single_channel_and_oracle(P):
     srv = P.Server(4 << 30)
     ids = [srv.submit(_desc(P, r)) for r in reqs]
     srv.drain()
-    P.set_events_per_thread(0, 1)
+    P.set_events_per_thread(0, 1)  # the server's tiles are 256 events
+    P.set_events_per_thread(1, 1)
     try:
         for rid, r in zip(ids, reqs):
             out, w, mean, sigma = _collect(P, srv, rid, r)
@@ -114,6 +115,7 @@ def test_server_matches_single_channel_and_oracle(P):
             srv.release(rid)
     finally:
         P.set_events_per_thread(0, 0)
+        P.set_events_per_thread(1, 0)
     srv.destroy()
 
 

@@ -1,0 +1,61 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one plausible mistake in a copy of the oracle's C source (in a
+temporary directory, on the CPU), rebuilds it, and runs the pin suite against
+the copy: the suite must fail.  The committed oracle itself is never modified.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTATIONS = [
+    ("weight constant off by 1e-7", "c = c * (2.0 * t);", "c = c * (2.0 * t) * 1.0000001;"),
+    ("boosted energy sign", "v[0] = gamma * e + ep;", "v[0] = gamma * e - ep;"),
+    ("boost 1/(gamma-1)", "const double f = ep / (gamma + 1.0) + e;", "const double f = ep / (gamma - 1.0) + e;"),
+    ("sin/cos swapped", "nhat[0] = st * cos(phi);", "nhat[0] = st * sin(phi);"),
+    ("cos(theta) sign", "const double ct = 2.0 * u - 1.0;", "const double ct = 1.0 - 2.0 * u;"),
+    ("mass uniforms not sorted", "sort_ascending(&r[1], n - 2);", ""),
+    ("theta/phi uniforms swapped", "direction(u[n - 2 + 2 * i], u[n - 1 + 2 * i], nhat);",
+     "direction(u[n - 1 + 2 * i], u[n - 2 + 2 * i], nhat);"),
+    ("wrong uniform bits", "uint64_t x = bits >> 12;", "uint64_t x = (bits >> 11) & ((1ull << 52) - 1);"),
+    ("factorial off by one", "for (int i = 2; i <= n - 2; ++i) fact", "for (int i = 2; i <= n - 3; ++i) fact"),
+    ("Philox key word", "uint32_t y2 = hi0 ^ x3 ^ k1;", "uint32_t y2 = hi0 ^ x3 ^ k0;"),
+    ("daughter 0 not back to back", "p4[0][k + 1] = -(p[0] * nhat[k]);", "p4[0][k + 1] = (p[0] * nhat[k]);"),
+    ("parent gamma off by 1e-6", "const double gamma = parent4[0] / parent_mass;",
+     "const double gamma = parent4[0] / parent_mass * 1.000001;"),
+    ("variance scaled", "nsum_add(&s2, d * d);", "nsum_add(&s2, d * d * 1.0000001);"),
+    ("last subsystem daughter not boosted", "for (int d = 0; d <= i; ++d) boost(p4[d], eta, gamma);",
+     "for (int d = 0; d < i; ++d) boost(p4[d], eta, gamma);"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(tmp_path, name, old, new):
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    work = tmp_path / "w"
+    shutil.copytree(os.path.join(ROOT, "oracle"), work / "oracle",
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    src = work / "oracle" / "phsp_oracle.c"
+    text = src.read_text()
+    assert old in text, f"mutation site not found: {old}"
+    src.write_text(text.replace(old, new, 1))
+    tests = work / "tests"
+    tests.mkdir()
+    for f in ("conftest.py", "volumes.py", "test_oracle_pins.py"):
+        shutil.copy(os.path.join(ROOT, "tests", f), tests / f)
+    shutil.copytree(os.path.join(ROOT, "tests", "kat"), tests / "kat")
+    env = dict(os.environ, PYTHONPATH=str(work))
+    subprocess.run([sys.executable, "-c", "import oracle; oracle.build()"], cwd=work, env=env, check=True)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        str(tests / "test_oracle_pins.py")], cwd=work, env=env, capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode != 0, f"planted mistake '{name}' passed every pin:\n{r.stdout[-2000:]}"

@@ -370,3 +370,39 @@ def test_validation(oracle_lib):
     assert o.generate_status(5.0, [3.0, 2.0]) == o.EKINEMATICS
     assert o.generate_status(5.0, [3.0, 2.5]) == o.EKINEMATICS
     assert o.generate_status(5.0, [0.0, 0.0]) == o.OK
+
+
+# --------------------------------------------------- property tests ----
+
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=60, deadline=None)
+@given(n=st.integers(2, 10), M=st.floats(0.5, 50.0), frac=st.floats(0.0, 0.95),
+       seed=st.integers(0, 2 ** 64 - 1), stream=st.integers(0, 2 ** 32 - 1),
+       offset=st.integers(0, 2 ** 50), moving=st.booleans(), mseed=st.integers(0, 10 ** 6))
+def test_property_conservation_and_ordering(oracle_lib, n, M, frac, seed, stream, offset, moving, mseed):
+    rng = np.random.default_rng(mseed)
+    raw = rng.uniform(0.0, 1.0, size=n)
+    masses = list(raw / raw.sum() * frac * M)  # sum of masses = frac * M < M
+    parent = None
+    if moving:
+        p = rng.normal(size=3) * M
+        parent = np.array([math.sqrt(M * M + float(p @ p)), *p])
+    p4, w = oracle_lib.generate(M, masses, 16, seed=seed, stream_id=stream, event_offset=offset,
+                                parent_p4=parent)
+    assert np.all(np.isfinite(p4)) and np.all(w >= 0.0) and np.all(np.isfinite(w))
+    P = np.array([M, 0.0, 0.0, 0.0]) if parent is None else parent
+    scale = float(np.max(np.abs(P)))
+    assert np.all(np.abs(p4.sum(axis=0) - P[:, None]) <= 1e-11 * scale)
+    for d in range(n):
+        m2 = _minkowski_sq(p4[d])
+        assert np.all(np.abs(m2 - masses[d] ** 2) <= 1e-10 * p4[d, 0] ** 2 + 1e-300)
+    # invariant masses of the nested subsystems never decrease
+    acc = p4[0].copy()
+    prev = np.full(16, masses[0])
+    for i in range(1, n):
+        acc = acc + p4[i]
+        mi = np.sqrt(np.maximum(_minkowski_sq(acc), 0.0))
+        assert np.all(mi >= prev + masses[i] - 1e-9 * M)
+        prev = mi

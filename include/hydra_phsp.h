@@ -140,8 +140,9 @@ int hydra_phsp_abi_version(void);
 int hydra_phsp_selftest_sortnet(void);
 /* Events per thread of the single-channel kernels, per path: path 0 =
  * integrate-only, 1 = FP64 generate, 2 = mixed generate; ept in {1, 2, 4}, or 0
- * for the library default.  Process-wide; changes the launch shape only (events
- * are bit-identical for every value; integrals agree to rounding). */
+ * for the library default (4; 1 for generate with n_daughters >= 7).
+ * Process-wide; changes the launch shape only (events are bit-identical for
+ * every value; integrals agree to rounding). */
 int hydra_phsp_set_events_per_thread(int path, int ept);
 
 /* Kernel timing for benchmarks: while enabled, every launch of the main

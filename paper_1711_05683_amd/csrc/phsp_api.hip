@@ -246,11 +246,15 @@ static hipError_t launch_by_n(int n, const LaunchSpec& s, const KArgs& a, hipStr
     }
 }
 
-// Events per thread of the single-channel kernels (0 = default per path).
+// Events per thread of the single-channel kernels (0 = default per path).  The
+// defaults come from measurements on MI355X: four events per lane amortise the
+// block reduction and the table load, except for generate with N >= 7, whose
+// register footprint with four events in flight would cut occupancy.
 static int g_ept_override[3] = {0, 0, 0};
-static int default_ept(int mode) {
+static int default_ept(int mode, int n) {
     const int o = g_ept_override[mode];
     if (o > 0) return o;
+    if (mode != kIntegrate && n >= 7) return 1;
     return 4;
 }
 
@@ -258,7 +262,7 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
                uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
                int mode, void* out, uint64_t ld, double* weights, double* stats_dev,
                hipStream_t stream, int ept_override) {
-    const int ept = ept_override > 0 ? ept_override : default_ept(mode);
+    const int ept = ept_override > 0 ? ept_override : default_ept(mode, n);
     const uint64_t per_block = (uint64_t)kBlock * (uint64_t)ept;
     const uint64_t blocks = (nevents + per_block - 1) / per_block;
     if (blocks > 0x7FFFFFFFull) return fail(HYDRA_PHSP_EINVAL, "nevents too large for one launch");

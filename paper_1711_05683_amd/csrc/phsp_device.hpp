@@ -45,8 +45,9 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)kPhiloxMulA * c0;
         const uint64_t pb = (uint64_t)kPhiloxMulB * c2;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ (k0 + (uint32_t)r * kPhiloxWeylA);
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ (k1 + (uint32_t)r * kPhiloxWeylB);
+        // three-input xor in one v_bitop3_b32 (truth table 0x96 = a ^ b ^ c)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), c1, k0 + (uint32_t)r * kPhiloxWeylA, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), c3, k1 + (uint32_t)r * kPhiloxWeylB, 0x96);
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
         c0 = n0;
@@ -184,20 +185,15 @@ __device__ __forceinline__ void direction(double u, double v, const double2* tab
     nz = ct;
 }
 
-// FP32 direction from the FP64 uniforms.  2u - 1 and u (1 - u) are formed in
-// FP64 (exact / one rounding) before the conversion, so directions near the
-// poles keep FP32 relative accuracy, and phi's uniform is first reduced to
-// [-1/2, 1/2] (exactly) so its conversion error is absolute, not relative to 1.
-__device__ __forceinline__ void direction(double u, double v, const double2*, float& nx, float& ny,
+// FP32 direction: evaluated in FP64 (table + series, as above) and rounded once,
+// which is both cheaper than an FP32 sincos and accurate to FP32 rounding.
+__device__ __forceinline__ void direction(double u, double v, const double2* tab, float& nx, float& ny,
                                           float& nz) {
-    const float ct = (float)(2.0 * u - 1.0);
-    const float st = 2.0f * sqrtf((float)(u * (1.0 - u)));
-    const float r = (float)(v - rint(v));
-    float sp, cp;
-    sincospif(2.0f * r, &sp, &cp);
-    nx = st * cp;
-    ny = st * sp;
-    nz = ct;
+    double dx, dy, dz;
+    direction(u, v, tab, dx, dy, dz);
+    nx = (float)dx;
+    ny = (float)dy;
+    nz = (float)dz;
 }
 
 // Energies of the two bodies of a level in the rest frame of hi = lo + m + g:
@@ -220,7 +216,6 @@ __device__ __forceinline__ double level_energy(double m, double lo, double g, do
 template <int N, typename R, bool KIN>
 __device__ __forceinline__ double event_levels(const Channel& c, const EventRng& rng, MassDraws<N>& d,
                                                const double2* tab, Event<N, R>& ev) {
-    constexpr bool kF64 = std::is_same<R, double>::value;
     sortnet_sort<N - 2>(d.u); // R_1..R_{N-2}; R_0 = 0 and R_{N-1} = 1 are implicit
     double carry = d.carry;
     double w = c.C;
@@ -249,33 +244,20 @@ __device__ __forceinline__ double event_levels(const Channel& c, const EventRng&
             ev.x[i + 1] = p * nx;
             ev.y[i + 1] = p * ny;
             ev.z[i + 1] = p * nz;
+            // Per-level scalars in FP64 (gap formulas: no square roots, nothing
+            // cancels), then rounded to R for the vector arithmetic.
             if (i == 0) {
-                if constexpr (kF64) {
-                    ev.e[1] = level_energy(m, sig_lo, g, sig_hi, h);
-                    ev.e[0] = level_energy(sig_lo, m, g, sig_hi, h);
-                } else {
-                    const R m0 = R(c.m[0]), m1 = R(m);
-                    ev.e[1] = sqrt(fma(p, p, m1 * m1));
-                    ev.e[0] = sqrt(fma(p, p, m0 * m0));
-                }
+                ev.e[1] = R(level_energy(m, sig_lo, g, sig_hi, h));
+                ev.e[0] = R(level_energy(sig_lo, m, g, sig_hi, h));
                 ev.x[0] = -ev.x[1];
                 ev.y[0] = -ev.y[1];
                 ev.z[0] = -ev.z[1];
             } else {
-                R gamma, inv_gp1;
-                if constexpr (kF64) {
-                    ev.e[i + 1] = level_energy(m, sig_lo, g, sig_hi, h);
-                    const double esys = level_energy(sig_lo, m, g, sig_hi, h); // energy of {0..i}
-                    gamma = esys * inv_lo;
-                    inv_gp1 = sig_lo * recip(esys + sig_lo); // 1/(gamma+1) = sigma / (E + sigma)
-                } else {
-                    const R mi = R(m);
-                    ev.e[i + 1] = sqrt(fma(p, p, mi * mi));
-                    const R sig = R(sig_lo);
-                    gamma = sqrt(fma(p, p, sig * sig)) * R(inv_lo);
-                    inv_gp1 = R(1) / (gamma + R(1));
-                }
-                const R eta = -(p * R(inv_lo));
+                ev.e[i + 1] = R(level_energy(m, sig_lo, g, sig_hi, h));
+                const double esys = level_energy(sig_lo, m, g, sig_hi, h); // energy of {0..i}
+                const R gamma = R(esys * inv_lo);
+                const R inv_gp1 = R(sig_lo * recip(esys + sig_lo)); // 1/(gamma+1) = sigma / (E + sigma)
+                const R eta = R(-(pd * inv_lo));
                 const R ex = eta * nx, ey = eta * ny, ez = eta * nz;
 #pragma unroll
                 for (int k = 0; k <= i; ++k)

@@ -116,7 +116,7 @@ __device__ __forceinline__ double run_event(const KArgs& a, uint64_t base, uint3
 template <int N, int PMODE, int MODE, int EPT>
 __global__ __launch_bounds__(kBlock) void k_phsp(const KArgs a) {
     __shared__ double2 tab[kTrigSize];
-    if constexpr (MODE == kFp64) load_trig(tab, a.trig);
+    if constexpr (MODE != kIntegrate) load_trig(tab, a.trig);
     const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * EPT);
     Moments acc{0.0, 0.0, 0.0};
 #pragma unroll

@@ -50,14 +50,21 @@ template <> struct SortNet<8> {
                                     {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
 };
 
+// Compare-exchange primitives: min/max instructions for doubles (inputs are
+// never NaN), plain comparisons for the host self-test's integers.
+__host__ __device__ __forceinline__ double ce_lo(double a, double b) { return fmin(a, b); }
+__host__ __device__ __forceinline__ double ce_hi(double a, double b) { return fmax(a, b); }
+__host__ __device__ __forceinline__ int ce_lo(int a, int b) { return a < b ? a : b; }
+__host__ __device__ __forceinline__ int ce_hi(int a, int b) { return a < b ? b : a; }
+
 // Sort v[0..K-1] ascending in registers (NaN-free inputs).
 template <int K, typename T>
 __host__ __device__ __forceinline__ void sortnet_sort(T* v) {
 #pragma unroll
     for (int c = 0; c < SortNet<K>::kSize; ++c) {
         const int a = SortNet<K>::kNet[c].a, b = SortNet<K>::kNet[c].b;
-        const T lo = v[a] < v[b] ? v[a] : v[b];
-        const T hi = v[a] < v[b] ? v[b] : v[a];
+        const T lo = ce_lo(v[a], v[b]);
+        const T hi = ce_hi(v[a], v[b]);
         v[a] = lo;
         v[b] = hi;
     }

@@ -192,7 +192,7 @@ def test_config3_full_batch(P):
         bufs.append((out, w, st))
         descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id,
                                out=out, weights=w, stats=st))
-    plan = P.Plan(descs)  # library default shape = the single-channel default
+    plan = P.Plan(descs)  # library default shape: 4 events per thread
     plan.launch()
     torch.cuda.synchronize()
     rng = np.random.default_rng(0)
@@ -207,8 +207,12 @@ def test_config3_full_batch(P):
             p4o, wo = oracle.generate(c.parent_mass, c.masses, 1, seed=c.seed, stream_id=c.stream_id,
                                       event_offset=int(e))
             assert_events_close(g[:, :, j:j + 1], gw[j:j + 1], p4o, wo)
-        so, sw, sst = P.generate(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id)
-        torch.cuda.synchronize()
+        P.set_events_per_thread(1, 4)  # the plan's default shape (4 events per thread)
+        try:
+            so, sw, sst = P.generate(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id)
+            torch.cuda.synchronize()
+        finally:
+            P.set_events_per_thread(1, 0)
         assert torch.equal(so, out) and torch.equal(sw, w) and torch.equal(sst, st), i
         del so, sw
     plan.destroy()

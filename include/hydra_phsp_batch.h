@@ -71,11 +71,12 @@ int hydra_phsp_plan_destroy(hydra_phsp_plan *plan);
 /* Number of tiles and the persistent grid size of a plan (host). */
 int hydra_phsp_plan_info(const hydra_phsp_plan *plan, uint64_t *ntiles_out, uint64_t *grid_out);
 
-/* Autotuner: times the persistent kernel over events per thread {1, 2, 4} x
- * blocks per compute unit {1, 2, 4, 8, 16} on this batch (running it several
- * times and overwriting its outputs) and returns the fastest shape and its
- * time in ms.  Results are cached per device and batch shape class for the
- * life of the process; a cached answer is returned without running. */
+/* Autotuner: times the batch (persistent kernels and merges) over events per
+ * thread {1, 2, 4} x blocks per compute unit {1, 2, 4, 8, 16} -- two warm-up
+ * runs and five timed runs per shape, overwriting the batch's outputs -- and
+ * returns the shape with the fastest run and that run's time in ms.  Results
+ * are cached per device and batch shape class for the life of the process; a
+ * cached answer is returned without running. */
 int hydra_phsp_autotune(const hydra_phsp_channel *channels, int n_channels, void *stream,
                         hydra_phsp_tuning *best_out, double *best_ms_out);
 

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(PKG, LIB_NAME)
 
 ARCH = "gfx950"
 NS = range(2, 11)
-BATCH_NMAX = (8, 10)
+BATCH_NMAX = (3, 5, 8, 10)
 BATCH_EPT = (1, 2, 4)
 
 # Packed FP32 instructions are disabled for every HIP unit; the host pass warns

@@ -1,9 +1,10 @@
 // phsp_batch.hpp -- persistent multi-channel kernel.
 //
-// Many decay channels (uneven N and event counts) run in one launch.  The host
-// cuts every channel into tiles of kBlock*EPT events -- exactly the per-block
-// chunks of the single-channel kernel -- and a persistent grid walks the tile
-// list with a static stride (block b takes tiles b, b+G, b+2G, ...; every block
+// Many decay channels (uneven N and event counts) run in one submission.  The
+// host cuts every channel into tiles of kBlock*EPT events -- exactly the
+// per-block chunks of the single-channel kernel -- groups the tiles by
+// daughter-count class, and per class a persistent grid walks its tile range
+// with a static stride (block b takes tiles b, b+G, b+2G, ...; every block
 // leaves the loop once its next index passes the end).  Each tile switches on
 // its channel's N to the same templated per-event code as the single-channel
 // kernel, and writes its block partial at the channel's tile index, so events,
@@ -41,7 +42,7 @@ struct GroupRef {
 
 // The body of k_phsp for one tile, with the channel's arguments read from the
 // (wave-uniform) channel record.
-template <int N, int MODE, int EPT>
+template <int N, int MODE, int EPT, bool PIN>
 __device__ __forceinline__ void run_tile(const KArgs& a, uint64_t blk, const double2* tab) {
     const uint64_t base = blk * (uint64_t)(kBlock * EPT);
     Moments acc{0.0, 0.0, 0.0};
@@ -49,7 +50,7 @@ __device__ __forceinline__ void run_tile(const KArgs& a, uint64_t blk, const dou
     for (int k = 0; k < EPT; ++k) {
         const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
         if (base + off < a.nevents) {
-            const double w = run_event<N, kAtRest, MODE, false>(a, base, off, tab);
+            const double w = run_event<N, kAtRest, MODE, PIN>(a, base, off, tab);
             if (k == 0) {
                 acc = Moments{1.0, w, 0.0};
             } else {
@@ -65,20 +66,25 @@ __device__ __forceinline__ void run_tile(const KArgs& a, uint64_t blk, const dou
     if (threadIdx.x == 0) a.partials[blk] = r;
 }
 
-template <int N, int EPT>
+// Column bases stay in scalar registers only in the small-N classes, where the
+// kernel's scalar register budget allows it.
+template <int N, int EPT, int NMAXB>
 __device__ __forceinline__ void run_tile_mode(const DevChannel& c, uint64_t blk, const double2* tab) {
+    constexpr bool kPin = NMAXB <= 5;
     if (c.mode == kIntegrate)
-        run_tile<N, kIntegrate, EPT>(c.a, blk, tab);
+        run_tile<N, kIntegrate, EPT, kPin>(c.a, blk, tab);
     else
-        run_tile<N, kFp64, EPT>(c.a, blk, tab);
+        run_tile<N, kFp64, EPT, kPin>(c.a, blk, tab);
 }
 
-// One kernel holds every N's code path, so its register budget is set by the
-// largest N; the waves-per-SIMD hint caps it (3 waves: <= 168 VGPRs for N <= 8,
-// 2 waves for N <= 10) instead of letting the scheduler trade occupancy for
-// latency hiding.
+// One kernel holds the code paths of every N up to NMAXB, so its register budget
+// is set by the largest; the waves-per-SIMD hint caps it (6 waves for N <= 3,
+// 4 for N <= 5, 3 for N <= 8, 2 for N <= 10) instead of letting the scheduler
+// trade occupancy for latency hiding.
+constexpr int batch_waves_hint(int nmaxb) { return nmaxb <= 3 ? 6 : nmaxb <= 5 ? 4 : nmaxb <= 8 ? 3 : 2; }
+
 template <int NMAXB, int EPT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NMAXB <= 8 ? 3 : 2))) void k_phsp_batched(const DevChannel* __restrict__ chans,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_waves_hint(NMAXB)))) void k_phsp_batched(const DevChannel* __restrict__ chans,
                                                          const TileRef* __restrict__ tiles,
                                                          uint64_t ntiles, const double2* __restrict__ trig) {
     __shared__ double2 tab[kTrigSize];
@@ -87,15 +93,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NMAXB <=
         const TileRef tr = tiles[t];
         const DevChannel& c = chans[tr.channel];
         switch (c.n) {
-        case 2: run_tile_mode<2, EPT>(c, tr.block, tab); break;
-        case 3: run_tile_mode<3, EPT>(c, tr.block, tab); break;
-        case 4: run_tile_mode<4, EPT>(c, tr.block, tab); break;
-        case 5: run_tile_mode<5, EPT>(c, tr.block, tab); break;
-        case 6: run_tile_mode<6, EPT>(c, tr.block, tab); break;
-        case 7: run_tile_mode<7, EPT>(c, tr.block, tab); break;
-        case 8: run_tile_mode<8, EPT>(c, tr.block, tab); break;
-        case 9: if constexpr (NMAXB >= 9) run_tile_mode<9, EPT>(c, tr.block, tab); break;
-        case 10: if constexpr (NMAXB >= 10) run_tile_mode<10, EPT>(c, tr.block, tab); break;
+        case 2: run_tile_mode<2, EPT, NMAXB>(c, tr.block, tab); break;
+        case 3: run_tile_mode<3, EPT, NMAXB>(c, tr.block, tab); break;
+        case 4: if constexpr (NMAXB >= 4) run_tile_mode<4, EPT, NMAXB>(c, tr.block, tab); break;
+        case 5: if constexpr (NMAXB >= 5) run_tile_mode<5, EPT, NMAXB>(c, tr.block, tab); break;
+        case 6: if constexpr (NMAXB >= 6) run_tile_mode<6, EPT, NMAXB>(c, tr.block, tab); break;
+        case 7: if constexpr (NMAXB >= 7) run_tile_mode<7, EPT, NMAXB>(c, tr.block, tab); break;
+        case 8: if constexpr (NMAXB >= 8) run_tile_mode<8, EPT, NMAXB>(c, tr.block, tab); break;
+        case 9: if constexpr (NMAXB >= 9) run_tile_mode<9, EPT, NMAXB>(c, tr.block, tab); break;
+        case 10: if constexpr (NMAXB >= 10) run_tile_mode<10, EPT, NMAXB>(c, tr.block, tab); break;
         default: break;
         }
         // The tile's LDS reduction must finish before the next tile reuses LDS.

@@ -40,12 +40,28 @@ __global__ __launch_bounds__(kStage2Block) void k_batch_merge_stage2(const DevCh
 
 using namespace hphsp;
 
+namespace hphsp {
+// Daughter-count classes of the batched path: channels are grouped by the
+// smallest class bound that holds their N, and every class gets its own
+// persistent launch, so small-N tiles run at the occupancy of their own
+// register budget rather than that of the largest N in the batch.
+constexpr int kClasses = 4;
+constexpr int kClassMax[kClasses] = {3, 5, 8, 10};
+inline int class_of(int n) {
+    for (int c = 0; c < kClasses; ++c)
+        if (n <= kClassMax[c]) return c;
+    return kClasses - 1;
+}
+} // namespace hphsp
+
 struct hydra_phsp_plan {
     int device = 0;
     int nch = 0;
-    int nmaxb = 8;
     int ept = 1;
     uint64_t grid = 0, ntiles = 0, ngroups = 0;
+    uint64_t class_begin[hphsp::kClasses] = {0, 0, 0, 0};
+    uint64_t class_count[hphsp::kClasses] = {0, 0, 0, 0};
+    uint64_t class_grid[hphsp::kClasses] = {0, 0, 0, 0};
     DevChannel* d_chans = nullptr;
     TileRef* d_tiles = nullptr;
     GroupRef* d_groups = nullptr;
@@ -60,21 +76,21 @@ struct hydra_phsp_plan {
 
 namespace hphsp {
 
-hipError_t launch_persistent(int nmaxb, int ept, const BatchLaunch& b, hipStream_t s) {
-    if (nmaxb <= 8) {
-        switch (ept) {
-        case 1: return launch_batched<8, 1>(b, s);
-        case 2: return launch_batched<8, 2>(b, s);
-        case 4: return launch_batched<8, 4>(b, s);
-        }
-    } else {
-        switch (ept) {
-        case 1: return launch_batched<10, 1>(b, s);
-        case 2: return launch_batched<10, 2>(b, s);
-        case 4: return launch_batched<10, 4>(b, s);
-        }
+template <int NMAXB>
+static hipError_t launch_by_ept(int ept, const BatchLaunch& b, hipStream_t s) {
+    switch (ept) {
+    case 1: return launch_batched<NMAXB, 1>(b, s);
+    case 2: return launch_batched<NMAXB, 2>(b, s);
+    case 4: return launch_batched<NMAXB, 4>(b, s);
+    default: return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
+}
+
+hipError_t launch_persistent(int nmaxb, int ept, const BatchLaunch& b, hipStream_t s) {
+    if (nmaxb <= 3) return launch_by_ept<3>(ept, b, s);
+    if (nmaxb <= 5) return launch_by_ept<5>(ept, b, s);
+    if (nmaxb <= 8) return launch_by_ept<8>(ept, b, s);
+    return launch_by_ept<10>(ept, b, s);
 }
 
 hipError_t launch_batch_merges(const DevChannel* chans, const GroupRef* groups, uint64_t ngroups, Moments* mid,
@@ -115,9 +131,13 @@ static void free_plan(hydra_phsp_plan* p) {
 // Enqueue the launch sequence of a plan on `s` (no graph).
 static int enqueue_plan(hydra_phsp_plan* p, hipStream_t s, bool timed) {
     if (p->ntiles > 0) {
-        BatchLaunch b{p->d_chans, p->d_tiles, p->ntiles, p->grid, p->trig};
         const long slot = timed ? timing_begin(s) : -1;
-        hipError_t e = launch_persistent(p->nmaxb, p->ept, b, s);
+        hipError_t e = hipSuccess;
+        for (int c = 0; c < kClasses && e == hipSuccess; ++c) {
+            if (p->class_count[c] == 0) continue;
+            BatchLaunch b{p->d_chans, p->d_tiles + p->class_begin[c], p->class_count[c], p->class_grid[c], p->trig};
+            e = launch_persistent(kClassMax[c], p->ept, b, s);
+        }
         timing_end(s, slot);
         if (e != hipSuccess) return fail_hip(e, "batched kernel launch");
     }
@@ -156,7 +176,6 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     std::vector<GroupRef> groups;
     const uint64_t tile_events = (uint64_t)kBlock * (uint64_t)ept;
     uint64_t first_tile = 0, first_group = 0;
-    int nmax = 2;
     for (int i = 0; i < nch; ++i) {
         const hydra_phsp_channel& c = chans[i];
         Channel ch;
@@ -165,7 +184,6 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
             if (bad) *bad = i;
             return st;
         }
-        nmax = std::max(nmax, c.n_daughters);
         const uint64_t nt = (c.nevents + tile_events - 1) / tile_events;
         if (nt > 0xFFFFFFFFull) return fail(HYDRA_PHSP_EINVAL, "channel too large");
         DevChannel d;
@@ -194,6 +212,19 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         first_tile += nt;
         first_group += d.ngroups;
     }
+    // Tile table ordered by daughter-count class (one persistent launch per class).
+    uint64_t class_begin[kClasses], class_count[kClasses];
+    {
+        std::vector<TileRef> by_class;
+        by_class.reserve(tiles.size());
+        for (int c = 0; c < kClasses; ++c) {
+            class_begin[c] = by_class.size();
+            for (const TileRef& t : tiles)
+                if (class_of(dch[t.channel].n) == c) by_class.push_back(t);
+            class_count[c] = by_class.size() - class_begin[c];
+        }
+        tiles.swap(by_class);
+    }
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
@@ -208,11 +239,16 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     p->device = dev;
     p->trig = trig;
     p->nch = nch;
-    p->nmaxb = nmax <= 8 ? 8 : 10;
     p->ept = ept;
     p->ntiles = first_tile;
     p->ngroups = first_group;
-    p->grid = std::min<uint64_t>(std::max<uint64_t>(first_tile, 1), (uint64_t)gpc * (uint64_t)std::max(cus, 1));
+    p->grid = 0;
+    for (int c = 0; c < kClasses; ++c) {
+        p->class_begin[c] = class_begin[c];
+        p->class_count[c] = class_count[c];
+        p->class_grid[c] = std::min<uint64_t>(class_count[c], (uint64_t)gpc * (uint64_t)std::max(cus, 1));
+        p->grid = std::max(p->grid, p->class_grid[c]);
+    }
     e = hipMalloc(&p->d_partials, sizeof(Moments) * std::max<uint64_t>(first_tile, 1));
     if (e != hipSuccess) {
         free_plan(p);
@@ -428,23 +464,22 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
             hydra_phsp_plan* p = nullptr;
             st = build_plan(channels, n_channels, &t, &p, nullptr);
             if (st != HYDRA_PHSP_OK) break;
-            st = enqueue_plan(p, s, false); // warm-up
-            float total = 0.0f;
-            const int reps = 3;
-            for (int r = 0; r < reps && st == HYDRA_PHSP_OK; ++r) {
+            for (int r = 0; r < 2 && st == HYDRA_PHSP_OK; ++r) st = enqueue_plan(p, s, false); // warm-up
+            // the fastest of five runs: robust to clock and scheduling noise
+            float fastest = 1e30f;
+            for (int r = 0; r < 5 && st == HYDRA_PHSP_OK; ++r) {
                 (void)hipEventRecord(a, s);
                 st = enqueue_plan(p, s, false);
                 (void)hipEventRecord(b, s);
                 if (hipEventSynchronize(b) != hipSuccess) st = fail(HYDRA_PHSP_EDEVICE, "autotune sync failed");
                 float ms = 0.0f;
                 (void)hipEventElapsedTime(&ms, a, b);
-                total += ms;
+                fastest = std::min(fastest, ms);
             }
             (void)hipStreamSynchronize(s);
             free_plan(p);
-            const double avg = total / reps;
-            if (st == HYDRA_PHSP_OK && avg < best_ms) {
-                best_ms = avg;
+            if (st == HYDRA_PHSP_OK && fastest < best_ms) {
+                best_ms = fastest;
                 best = t;
             }
         }

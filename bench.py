@@ -129,7 +129,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the event loop shards by event_offset; see the design notes)", file=sys.stderr)
+              "(events shard across GPUs by event_offset; this benchmark measures one GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch

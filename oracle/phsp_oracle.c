@@ -23,8 +23,8 @@
  * four-vector Vector4R(mass,0,0,0) (energy first) at generation time, and a
  * caller-allocated event container.  Everything else -- random-number
  * generator, uniform conversion, recursion order, angle convention, weight
- * normalisation -- is silent in the paper; this file follows the readings
- * listed in the design notes, summarised at each step:
+ * normalisation -- is silent in the paper; this file makes the following
+ * choices, each restated where it is used:
  *
  *  - phase-space measure: prod_i d^3p_i/(2E_i) delta^4(P - sum p_i), no 2*pi
  *    factors, so the two-body volume is pi*p/M and the mean weight is the

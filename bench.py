@@ -280,17 +280,19 @@ def batched_extra(P, torch, dev, steps):
         descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id,
                                out=out, weights=w, stats=st))
     t0 = time.perf_counter()
-    ept, gpc, tuned_ms = P.autotune(descs)
+    ept, gpc, sched, tuned_ms = P.autotune(descs)
     tune_s = time.perf_counter() - t0
-    plan = P.Plan(descs, ept=ept, grid_per_cu=gpc)
+    plan = P.Plan(descs, ept=ept, grid_per_cu=gpc, schedule=sched)
     ms_graph, _ = time_steps(plan.launch, steps, 1, torch)
-    ms_direct, kms = time_steps(lambda: P.batch_run(descs, ept=ept, grid_per_cu=gpc), steps, 1, torch)
+    ms_direct, kms = time_steps(lambda: P.batch_run(descs, ept=ept, grid_per_cu=gpc, schedule=sched),
+                                steps, 1, torch)
     ntiles, grid = plan.info()
     plan.destroy()
     P.release()
     del keep
     return {"channels": len(specs), "events": total_events, "bytes": total_bytes,
-            "tuning": {"ept": ept, "grid_per_cu": gpc, "autotune_s": tune_s, "tiles": ntiles,
+            "tuning": {"ept": ept, "grid_per_cu": gpc, "schedule": ["static", "dynamic"][sched],
+                       "autotune_s": tune_s, "tiles": ntiles,
                        "grid": grid},
             "events_per_s_graph": total_events / (ms_graph * 1e-3), "ms_per_step_graph": ms_graph,
             "kernel_ms": kms, "kernel_write_GBs": total_bytes / (kms * 1e-3) / 1e9,

@@ -38,14 +38,17 @@ typedef struct hydra_phsp_channel {
     double *stats_dev;   /* HYDRA_PHSP_STATS doubles */
 } hydra_phsp_channel;
 
-/* Launch shape of the persistent kernel (blocks of 256 threads):
+/* Launch shape of the persistent kernels (blocks of 256 threads):
  *   ept          events per thread: 1, 2 or 4 (a tile is 256*ept events);
- *   grid_per_cu  persistent blocks per compute unit, 1 .. 64.
- * A zero field selects the library default (ept 4, grid_per_cu 8). */
+ *   grid_per_cu  persistent blocks per compute unit, 1 .. 64;
+ *   schedule     0: static stride over the tiles; 1: dynamic, blocks claim
+ *                tiles in order from a device counter.
+ * A zero ept or grid_per_cu selects the library default (4 and 8). */
 typedef struct hydra_phsp_tuning {
     int32_t ept;
     int32_t grid_per_cu;
-    int32_t reserved[2];
+    int32_t schedule;
+    int32_t reserved;
 } hydra_phsp_tuning;
 
 /* Enqueue one batch on `stream`: validates every channel (no work is enqueued
@@ -71,8 +74,9 @@ int hydra_phsp_plan_destroy(hydra_phsp_plan *plan);
 /* Number of tiles and the persistent grid size of a plan (host). */
 int hydra_phsp_plan_info(const hydra_phsp_plan *plan, uint64_t *ntiles_out, uint64_t *grid_out);
 
-/* Autotuner: times the batch (persistent kernels and merges) over events per
- * thread {1, 2, 4} x blocks per compute unit {1, 2, 4, 8, 16} -- two warm-up
+/* Autotuner: times the batch (persistent kernels and merges) over schedule
+ * {static, dynamic} x events per thread {1, 2, 4} x blocks per compute unit
+ * {1, 2, 4, 8, 16} -- two warm-up
  * runs and five timed runs per shape, overwriting the batch's outputs -- and
  * returns the shape with the fastest run and that run's time in ms.  Results
  * are cached per device and batch shape class for the life of the process; a

@@ -214,9 +214,10 @@ class ChannelDesc(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    """``hydra_phsp_tuning``: events per thread and persistent blocks per CU (0 = default)."""
+    """``hydra_phsp_tuning``: events per thread, persistent blocks per CU (0 = default) and
+    tile schedule (0 static stride, 1 dynamic)."""
     _fields_ = [("ept", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def _declare_batch(lib):
@@ -263,19 +264,20 @@ def _channel_array(chans):
     return arr
 
 
-def _tuning(ept=0, grid_per_cu=0):
+def _tuning(ept=0, grid_per_cu=0, schedule=0):
     t = Tuning()
     t.ept = ept
     t.grid_per_cu = grid_per_cu
+    t.schedule = schedule
     return t
 
 
-def batch_run(chans, *, ept: int = 0, grid_per_cu: int = 0, stream=None):
-    """Enqueue one batch (all channels in one persistent launch)."""
+def batch_run(chans, *, ept: int = 0, grid_per_cu: int = 0, schedule: int = 0, stream=None):
+    """Enqueue one batch (all channels; one persistent launch per daughter-count class)."""
     L = lib()
     arr = _channel_array(chans)
     bad = ctypes.c_int(-1)
-    t = _tuning(ept, grid_per_cu)
+    t = _tuning(ept, grid_per_cu, schedule)
     st = L.hydra_phsp_batch_run(arr, len(chans), ctypes.byref(t), _stream_handle(stream), ctypes.byref(bad))
     if st != OK:
         msg = L.hydra_phsp_last_error().decode(errors="replace")
@@ -285,10 +287,10 @@ def batch_run(chans, *, ept: int = 0, grid_per_cu: int = 0, stream=None):
 class Plan:
     """A batch captured into a HIP graph; launch() replays it."""
 
-    def __init__(self, chans, *, ept: int = 0, grid_per_cu: int = 0):
+    def __init__(self, chans, *, ept: int = 0, grid_per_cu: int = 0, schedule: int = 0):
         L = lib()
         arr = _channel_array(chans)
-        t = _tuning(ept, grid_per_cu)
+        t = _tuning(ept, grid_per_cu, schedule)
         h = ctypes.c_void_p()
         _check(L.hydra_phsp_plan_create(arr, len(chans), ctypes.byref(t), ctypes.byref(h)))
         self._h = h
@@ -314,12 +316,12 @@ class Plan:
 
 
 def autotune(chans, stream=None):
-    """(ept, grid_per_cu, ms) of the fastest persistent-kernel shape for this batch."""
+    """(ept, grid_per_cu, schedule, ms) of the fastest persistent-kernel shape for this batch."""
     t = Tuning()
     ms = ctypes.c_double()
     _check(lib().hydra_phsp_autotune(_channel_array(chans), len(chans), _stream_handle(stream),
                                      ctypes.byref(t), ctypes.byref(ms)))
-    return t.ept, t.grid_per_cu, ms.value
+    return t.ept, t.grid_per_cu, t.schedule, ms.value
 
 
 # ----------------------------------------------------------------- serving ----

@@ -83,13 +83,31 @@ __device__ __forceinline__ void run_tile_mode(const DevChannel& c, uint64_t blk,
 // trade occupancy for latency hiding.
 constexpr int batch_waves_hint(int nmaxb) { return nmaxb <= 3 ? 6 : nmaxb <= 5 ? 4 : nmaxb <= 8 ? 3 : 2; }
 
+// Tiles are taken either with a static stride (block b: b, b+G, b+2G, ...;
+// counter == nullptr) or dynamically from a zeroed device counter, one atomic
+// increment per tile, claimed while the previous tile is being processed, so
+// blocks advance through the tile list together (as the hardware dispatcher
+// would order them) and neighbouring output columns are written close in time.
+// Either way every block leaves once its next index is past the end.
 template <int NMAXB, int EPT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_waves_hint(NMAXB)))) void k_phsp_batched(const DevChannel* __restrict__ chans,
-                                                         const TileRef* __restrict__ tiles,
-                                                         uint64_t ntiles, const double2* __restrict__ trig) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_waves_hint(NMAXB)))) void k_phsp_batched(
+    const DevChannel* __restrict__ chans, const TileRef* __restrict__ tiles, uint64_t ntiles,
+    const double2* __restrict__ trig, unsigned long long* __restrict__ counter) {
     __shared__ double2 tab[kTrigSize];
+    __shared__ unsigned long long next;
     load_trig(tab, trig);
-    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const bool dynamic = counter != nullptr;
+    uint64_t t = blockIdx.x;
+    if (dynamic) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1ull);
+        __syncthreads();
+        t = next;
+    }
+    while (t < ntiles) {
+        if (dynamic) {
+            __syncthreads(); // every thread holds t before `next` is overwritten
+            if (threadIdx.x == 0) next = atomicAdd(counter, 1ull);
+        }
         const TileRef tr = tiles[t];
         const DevChannel& c = chans[tr.channel];
         switch (c.n) {
@@ -104,10 +122,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_wa
         case 10: if constexpr (NMAXB >= 10) run_tile_mode<10, EPT, NMAXB>(c, tr.block, tab); break;
         default: break;
         }
-        // The tile's LDS reduction must finish before the next tile reuses LDS.
+        // The tile's LDS reduction must finish before the next tile reuses LDS,
+        // and thread 0's claim of the next tile must be visible.
         __syncthreads();
+        t = dynamic ? next : t + gridDim.x;
     }
 }
+
+// Zero the dynamic-schedule counters of a batch (a kernel, not a memset, so
+// graph replays stay correct).
+__global__ void k_zero_counters(unsigned long long* c, int n);
 
 struct BatchLaunch {
     const DevChannel* chans;
@@ -115,6 +139,7 @@ struct BatchLaunch {
     uint64_t ntiles;
     uint64_t grid;
     const double2* trig;
+    unsigned long long* counter; // zeroed tile counter (dynamic schedule) or nullptr (static stride)
 };
 
 // Persistent-kernel launcher for one (NMAXB, EPT) pair, defined per

@@ -19,6 +19,10 @@
 
 namespace hphsp {
 
+__global__ void k_zero_counters(unsigned long long* c, int n) {
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
+}
+
 // Stage 1 of every channel's merge: block g handles group groups[g].
 __global__ __launch_bounds__(kStage1Block) void k_batch_merge_stage1(const DevChannel* __restrict__ chans,
                                                                     const GroupRef* __restrict__ groups,
@@ -58,6 +62,8 @@ struct hydra_phsp_plan {
     int device = 0;
     int nch = 0;
     int ept = 1;
+    int dynamic = 0;
+    unsigned long long* d_counters = nullptr; // one per class (dynamic schedule)
     uint64_t grid = 0, ntiles = 0, ngroups = 0;
     uint64_t class_begin[hphsp::kClasses] = {0, 0, 0, 0};
     uint64_t class_count[hphsp::kClasses] = {0, 0, 0, 0};
@@ -125,6 +131,7 @@ static void free_plan(hydra_phsp_plan* p) {
     if (p->d_groups) (void)hipFree(p->d_groups);
     if (p->d_partials) (void)hipFree(p->d_partials);
     if (p->d_mid) (void)hipFree(p->d_mid);
+    if (p->d_counters) (void)hipFree(p->d_counters);
     delete p;
 }
 
@@ -133,9 +140,14 @@ static int enqueue_plan(hydra_phsp_plan* p, hipStream_t s, bool timed) {
     if (p->ntiles > 0) {
         const long slot = timed ? timing_begin(s) : -1;
         hipError_t e = hipSuccess;
+        if (p->dynamic) {
+            hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, p->d_counters, kClasses);
+            e = hipGetLastError();
+        }
         for (int c = 0; c < kClasses && e == hipSuccess; ++c) {
             if (p->class_count[c] == 0) continue;
-            BatchLaunch b{p->d_chans, p->d_tiles + p->class_begin[c], p->class_count[c], p->class_grid[c], p->trig};
+            BatchLaunch b{p->d_chans, p->d_tiles + p->class_begin[c], p->class_count[c], p->class_grid[c], p->trig,
+                          p->dynamic ? p->d_counters + c : nullptr};
             e = launch_persistent(kClassMax[c], p->ept, b, s);
         }
         timing_end(s, slot);
@@ -163,11 +175,13 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     if (bad) *bad = -1;
     if (chans == nullptr || nch <= 0) return fail(HYDRA_PHSP_EINVAL, "need at least one channel");
     if (out == nullptr) return fail(HYDRA_PHSP_EINVAL, "plan_out is NULL");
-    int ept = 4, gpc = 8;
+    int ept = 4, gpc = 8, dyn = 0;
     if (tuning) {
         if (tuning->ept) ept = tuning->ept;
         if (tuning->grid_per_cu) gpc = tuning->grid_per_cu;
+        dyn = tuning->schedule;
     }
+    if (dyn != 0 && dyn != 1) return fail(HYDRA_PHSP_EINVAL, "tuning schedule must be 0 or 1");
     if (ept != 1 && ept != 2 && ept != 4) return fail(HYDRA_PHSP_EINVAL, "tuning ept must be 1, 2 or 4");
     if (gpc < 1 || gpc > 64) return fail(HYDRA_PHSP_EINVAL, "tuning grid_per_cu must be in [1, 64]");
 
@@ -240,6 +254,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     p->trig = trig;
     p->nch = nch;
     p->ept = ept;
+    p->dynamic = dyn;
     p->ntiles = first_tile;
     p->ngroups = first_group;
     p->grid = 0;
@@ -255,6 +270,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         return fail(HYDRA_PHSP_ENOMEM, "batch partials allocation failed");
     }
     e = hipMalloc(&p->d_mid, sizeof(Moments) * std::max<uint64_t>(first_group, 1));
+    if (e == hipSuccess) e = hipMalloc(&p->d_counters, sizeof(unsigned long long) * kClasses);
     if (e != hipSuccess) {
         free_plan(p);
         return fail(HYDRA_PHSP_ENOMEM, "batch partials allocation failed");
@@ -454,13 +470,14 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
         return fail(HYDRA_PHSP_EDEVICE, "hipEventCreate failed");
     double best_ms = 1e300;
-    hydra_phsp_tuning best{4, 8, {0, 0}};
+    hydra_phsp_tuning best{4, 8, 0, 0};
     int st = HYDRA_PHSP_OK;
     const int epts[3] = {1, 2, 4};
     const int gpcs[5] = {1, 2, 4, 8, 16};
+    for (int sched = 0; sched < 2 && st == HYDRA_PHSP_OK; ++sched)
     for (int ei = 0; ei < 3 && st == HYDRA_PHSP_OK; ++ei) {
         for (int gi = 0; gi < 5 && st == HYDRA_PHSP_OK; ++gi) {
-            hydra_phsp_tuning t{epts[ei], gpcs[gi], {0, 0}};
+            hydra_phsp_tuning t{epts[ei], gpcs[gi], sched, 0};
             hydra_phsp_plan* p = nullptr;
             st = build_plan(channels, n_channels, &t, &p, nullptr);
             if (st != HYDRA_PHSP_OK) break;

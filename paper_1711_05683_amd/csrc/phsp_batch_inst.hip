@@ -13,7 +13,7 @@ template <>
 hipError_t launch_batched<BATCH_NMAX, BATCH_EPT>(const BatchLaunch& b, hipStream_t stream) {
     if (b.grid == 0 || b.grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_phsp_batched<BATCH_NMAX, BATCH_EPT>), dim3((unsigned)b.grid), dim3(kBlock), 0,
-                       stream, b.chans, b.tiles, b.ntiles, b.trig);
+                       stream, b.chans, b.tiles, b.ntiles, b.trig, b.counter);
     return hipGetLastError();
 }
 

@@ -343,7 +343,7 @@ int launch_tick(hydra_phsp_server* s) {
     }
     if (e != hipSuccess) return fail_hip(e, "server table upload");
     BatchLaunch b{t.chans.dev, t.tiles.dev, (uint64_t)tiles.size(),
-                  std::min<uint64_t>((uint64_t)tiles.size(), 8ull * (uint64_t)s->cus), s->trig};
+                  std::min<uint64_t>((uint64_t)tiles.size(), 8ull * (uint64_t)s->cus), s->trig, nullptr};
     e = launch_persistent(nmax <= 8 ? 8 : 10, kServeEpt, b, q);
     if (e != hipSuccess) return fail_hip(e, "server tick launch");
     if (!fin.empty()) {

@@ -98,11 +98,11 @@ def test_batch_matches_single_channel(P):
     _compare_with_single(P, specs, bufs, 1)
 
 
-@pytest.mark.parametrize("ept,gpc", [(2, 1), (4, 16), (1, 2)])
-def test_batch_tuning_variants(P, ept, gpc):
-    _say(f"batch variant ept={ept} grid/cu={gpc}")
+@pytest.mark.parametrize("ept,gpc,sched", [(2, 1, 0), (4, 16, 0), (1, 2, 0), (4, 8, 1), (1, 1, 1), (2, 16, 1)])
+def test_batch_tuning_variants(P, ept, gpc, sched):
+    _say(f"batch variant ept={ept} grid/cu={gpc} schedule={sched}")
     specs, bufs, descs = _channels(P, n_channels=16, seed=7)
-    P.batch_run(descs, ept=ept, grid_per_cu=gpc)
+    P.batch_run(descs, ept=ept, grid_per_cu=gpc, schedule=sched)
     torch.cuda.synchronize()
     _compare_with_single(P, specs, bufs, ept)
 
@@ -168,12 +168,12 @@ def test_plan_graph_replays(P):
 def test_autotune(P):
     _say("autotune")
     specs, bufs, descs = _channels(P, n_channels=16, seed=5, log_events=(3.0, 5.0))
-    ept, gpc, ms = P.autotune(descs)
-    assert ept in (1, 2, 4) and 1 <= gpc <= 16 and ms > 0
+    ept, gpc, sched, ms = P.autotune(descs)
+    assert ept in (1, 2, 4) and 1 <= gpc <= 16 and sched in (0, 1) and ms > 0
     # cached: same answer
-    assert P.autotune(descs) == (ept, gpc, ms)
+    assert P.autotune(descs) == (ept, gpc, sched, ms)
     # the tuned shape still gives the single-channel events
-    P.batch_run(descs, ept=ept, grid_per_cu=gpc)
+    P.batch_run(descs, ept=ept, grid_per_cu=gpc, schedule=sched)
     torch.cuda.synchronize()
     _compare_with_single(P, specs, bufs, ept)
 

@@ -273,7 +273,8 @@ def batched_extra(P, torch, dev, steps):
     total_bytes = sum(c.nevents * (4 * c.n + 1) * 8 for c in specs)
     keep, descs = [], []
     for c in specs:
-        out = torch.empty((c.n, 4, c.nevents), dtype=torch.float64, device=dev)
+        # columns on 128-byte lines (the layout the library recommends)
+        out = torch.empty((c.n, 4, P.aligned_ld(c.nevents)), dtype=torch.float64, device=dev)
         w = torch.empty(c.nevents, dtype=torch.float64, device=dev)
         st = torch.empty(4, dtype=torch.float64, device=dev)
         keep.append((out, w, st))
@@ -289,15 +290,30 @@ def batched_extra(P, torch, dev, steps):
     ntiles, grid = plan.info()
     plan.destroy()
     P.release()
-    del keep
+    del keep, descs
+    # the same batch with ld = nevents (columns start mid-line): partial-line stores
+    keep, descs = [], []
+    for c in specs:
+        out = torch.empty((c.n, 4, c.nevents), dtype=torch.float64, device=dev)
+        w = torch.empty(c.nevents, dtype=torch.float64, device=dev)
+        st = torch.empty(4, dtype=torch.float64, device=dev)
+        keep.append((out, w, st))
+        descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id,
+                               out=out, weights=w, stats=st))
+    _, kms_unaligned = time_steps(lambda: P.batch_run(descs, ept=ept, grid_per_cu=gpc, schedule=sched),
+                                  steps, 1, torch)
+    P.release()
+    del keep, descs
     return {"channels": len(specs), "events": total_events, "bytes": total_bytes,
-            "tuning": {"ept": ept, "grid_per_cu": gpc, "schedule": ["static", "dynamic"][sched],
+            "tuning": {"ept": ept, "grid_per_cu": gpc, "schedule": ["static", "dynamic", "one block per tile"][sched],
                        "autotune_s": tune_s, "tiles": ntiles,
                        "grid": grid},
             "events_per_s_graph": total_events / (ms_graph * 1e-3), "ms_per_step_graph": ms_graph,
             "kernel_ms": kms, "kernel_write_GBs": total_bytes / (kms * 1e-3) / 1e9,
             "kernel_frac_of_8TBs": total_bytes / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
-            "ms_per_step_direct": ms_direct}
+            "ms_per_step_direct": ms_direct, "ld": "aligned_ld(nevents)",
+            "kernel_ms_ld_eq_nevents": kms_unaligned,
+            "kernel_write_GBs_ld_eq_nevents": total_bytes / (kms_unaligned * 1e-3) / 1e9}
 
 
 if __name__ == "__main__":

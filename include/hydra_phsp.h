@@ -87,7 +87,12 @@ enum {
  *   nevents          number of events (0 is a no-op that still writes stats).
  *   seed, stream_id  Philox key and counter word 3.
  *   event_offset     global index of the first event.
- *   p4_out_dev       [n_daughters][4][ld] doubles (device).
+ *   p4_out_dev       [n_daughters][4][ld] doubles (device).  Any ld >= nevents
+ *                    works; a 128-byte aligned p4_out_dev with ld a multiple of
+ *                    16 (32 for the FP32 outputs of the mixed path) starts every
+ *                    column on a cache line, so every wave's stores are whole-line
+ *                    writes.  Misaligned columns turn them into partial-line
+ *                    writes, measured at up to ~40% less write bandwidth.
  *   weights_dev      [nevents] doubles (device).
  *   stats_dev        NULL, or HYDRA_PHSP_STATS doubles (device) receiving the
  *                    fused integral of this call's weights.
@@ -121,7 +126,8 @@ int hydra_phsp_integrate(double parent_mass, const double *masses_host, int n_da
 /* As hydra_phsp_generate, but the decay angles, energies, boosts and the
  * momentum outputs are FP32 (p4_out_dev is [n_daughters][4][ld] floats);
  * uniforms, sorting, invariant masses, breakup momenta, the weight and the
- * integral stay FP64, so weights and stats equal the FP64 path's. */
+ * integral stay FP64, so weights equal the FP64 path's, and so do the stats
+ * when both paths run the same events per thread. */
 int hydra_phsp_generate_mixed(double parent_mass, const double *masses_host, int n_daughters,
                               const double *parent_p4_host, const double *parent_p4_dev,
                               uint64_t ld_parent, uint64_t nevents, uint64_t seed,
@@ -140,7 +146,10 @@ int hydra_phsp_abi_version(void);
 int hydra_phsp_selftest_sortnet(void);
 /* Events per thread of the single-channel kernels, per path: path 0 =
  * integrate-only, 1 = FP64 generate, 2 = mixed generate; ept in {1, 2, 4}, or 0
- * for the library default (4; 1 for generate with n_daughters >= 7).
+ * for the library default (integrate: 4; mixed: 2 for n_daughters = 2, else 4;
+ * FP64 generate: 2 for N = 2, 1 for N = 3, 4 for N = 4..7, 1 for N >= 8, and 1
+ * with per-event parents for N <= 3).  One launch covers at most
+ * (2^32 - 1) / 256 * ept events; larger counts are rejected with EINVAL.
  * Process-wide; changes the launch shape only (events are bit-identical for
  * every value; integrals agree to rounding). */
 int hydra_phsp_set_events_per_thread(int path, int ept);

@@ -38,11 +38,14 @@ typedef struct hydra_phsp_channel {
     double *stats_dev;   /* HYDRA_PHSP_STATS doubles */
 } hydra_phsp_channel;
 
-/* Launch shape of the persistent kernels (blocks of 256 threads):
+/* Launch shape of the batched kernels (blocks of 256 threads):
  *   ept          events per thread: 1, 2 or 4 (a tile is 256*ept events);
- *   grid_per_cu  persistent blocks per compute unit, 1 .. 64;
- *   schedule     0: static stride over the tiles; 1: dynamic, blocks claim
- *                tiles in order from a device counter.
+ *   grid_per_cu  persistent blocks per compute unit, 1 .. 64 (schedules 0, 1);
+ *   schedule     0: persistent grid, static stride over the tiles;
+ *                1: persistent grid, blocks claim tiles in order from a
+ *                   device counter;
+ *                2: one block per tile (grid = tile count, grid_per_cu is
+ *                   ignored), so the hardware dispatches tiles in order.
  * A zero ept or grid_per_cu selects the library default (4 and 8). */
 typedef struct hydra_phsp_tuning {
     int32_t ept;
@@ -74,9 +77,9 @@ int hydra_phsp_plan_destroy(hydra_phsp_plan *plan);
 /* Number of tiles and the persistent grid size of a plan (host). */
 int hydra_phsp_plan_info(const hydra_phsp_plan *plan, uint64_t *ntiles_out, uint64_t *grid_out);
 
-/* Autotuner: times the batch (persistent kernels and merges) over schedule
+/* Autotuner: times the batch (kernels and merges) over schedule
  * {static, dynamic} x events per thread {1, 2, 4} x blocks per compute unit
- * {1, 2, 4, 8, 16} -- two warm-up
+ * {1, 2, 4, 8, 16}, plus one block per tile x events per thread -- two warm-up
  * runs and five timed runs per shape, overwriting the batch's outputs -- and
  * returns the shape with the fastest run and that run's time in ms.  Results
  * are cached per device and batch shape class for the life of the process; a

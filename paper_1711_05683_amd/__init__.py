@@ -102,6 +102,14 @@ def _dptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def aligned_ld(nevents: int) -> int:
+    """Leading dimension for an SoA output of ``nevents`` events: a multiple of 32
+    elements, so every column starts on a 128-byte line (FP64 and FP32) and each
+    wave's stores cover whole lines.  Columns that start mid-line make the stores
+    partial-line writes, which cost up to ~40% of the write bandwidth on MI355X."""
+    return (max(nevents, 1) + 31) // 32 * 32
+
+
 def generate(parent_mass: float, masses: Sequence[float], nevents: int, *, seed: int = 42,
              stream_id: int = 0, event_offset: int = 0, parent_p4: Optional[Sequence[float]] = None,
              parent_dev: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
@@ -111,15 +119,17 @@ def generate(parent_mass: float, masses: Sequence[float], nevents: int, *, seed:
     """Generate events on the GPU (asynchronous on the current stream).
 
     Returns ``(p4, weights, stats)``: ``p4`` is ``[N, 4, ld]`` (float64, or float32
-    when ``mixed``), ``weights`` is ``[nevents]`` float64 and ``stats`` holds
+    when ``mixed``; when ``out`` is not given, a ``[N, 4, nevents]`` view of a buffer
+    with ``aligned_ld(nevents)`` columns), ``weights`` is ``[nevents]`` float64 and ``stats`` holds
     ``(n, mean, M2, sigma)`` of the weights (None unless ``want_stats``).
     ``parent_p4`` is one (E, px, py, pz) applied to all events; ``parent_dev`` a
     ``[4, ld_parent]`` float64 device tensor of per-event parents."""
     m, n = _masses(masses)
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     dtype = torch.float32 if mixed else torch.float64
-    if out is None:
-        out = torch.empty((n, 4, max(nevents, 1)), dtype=dtype, device=dev)
+    own_out = out is None
+    if own_out:
+        out = torch.empty((n, 4, aligned_ld(nevents)), dtype=dtype, device=dev)
     if weights is None:
         weights = torch.empty(max(nevents, 1), dtype=torch.float64, device=dev)
     if stats is None and want_stats:
@@ -141,6 +151,8 @@ def generate(parent_mass: float, masses: Sequence[float], nevents: int, *, seed:
     fn = lib().hydra_phsp_generate_mixed if mixed else lib().hydra_phsp_generate
     _check(fn(parent_mass, m, n, p4h, _dptr(parent_dev), ldp, nevents, seed, stream_id, event_offset,
               _dptr(out), ld, _dptr(weights), _dptr(stats), _stream_handle(stream)))
+    if own_out:
+        out = out[:, :, :max(nevents, 1)]
     return out, weights, stats
 
 
@@ -215,7 +227,7 @@ class ChannelDesc(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     """``hydra_phsp_tuning``: events per thread, persistent blocks per CU (0 = default) and
-    tile schedule (0 static stride, 1 dynamic)."""
+    tile schedule (0 static stride, 1 dynamic, 2 one block per tile)."""
     _fields_ = [("ept", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 

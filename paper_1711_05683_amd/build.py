@@ -25,8 +25,7 @@ LIB_PATH = os.path.join(PKG, LIB_NAME)
 
 ARCH = "gfx950"
 NS = range(2, 11)
-BATCH_NMAX = (3, 5, 8, 10)
-BATCH_EPT = (1, 2, 4)
+BATCH_MIXED = (8, 10)
 
 # Packed FP32 instructions are disabled for every HIP unit; the host pass warns
 # that it does not know the feature, which is harmless.  Floating-point
@@ -55,11 +54,12 @@ def _units():
     for n in NS:
         units.append((os.path.join(CSRC, "phsp_inst.hip"),
                       os.path.join(BUILD_DIR, f"phsp_inst_n{n}.o"), [f"-DPHSP_N={n}"]))
-    for nmax in BATCH_NMAX:
-        for ept in BATCH_EPT:
-            units.append((os.path.join(CSRC, "phsp_batch_inst.hip"),
-                          os.path.join(BUILD_DIR, f"phsp_batch_inst_n{nmax}_e{ept}.o"),
-                          [f"-DBATCH_NMAX={nmax}", f"-DBATCH_EPT={ept}"]))
+    for n in NS:
+        units.append((os.path.join(CSRC, "phsp_batch_inst.hip"),
+                      os.path.join(BUILD_DIR, f"phsp_batch_inst_n{n}.o"), [f"-DBATCH_N={n}"]))
+    for nmax in BATCH_MIXED:
+        units.append((os.path.join(CSRC, "phsp_batch_inst.hip"),
+                      os.path.join(BUILD_DIR, f"phsp_batch_mixed_n{nmax}.o"), [f"-DBATCH_MIXED={nmax}"]))
     for name in sorted(os.listdir(CSRC)):
         if name.endswith(".hip") and name not in ("phsp_inst.hip", "phsp_batch_inst.hip"):
             units.append((os.path.join(CSRC, name),

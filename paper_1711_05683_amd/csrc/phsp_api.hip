@@ -247,25 +247,34 @@ static hipError_t launch_by_n(int n, const LaunchSpec& s, const KArgs& a, hipStr
 }
 
 // Events per thread of the single-channel kernels (0 = default per path).  The
-// defaults come from measurements on MI355X: four events per lane amortise the
-// block reduction and the table load, except for generate with N >= 7, whose
-// register footprint with four events in flight would cut occupancy.
+// defaults are the fastest of 1, 2 and 4 measured on MI355X (warm clocks, about
+// 10 GB of output per launch).  Integration stores nothing, so four events per
+// lane amortise the block reduction best.  For generation the store pattern
+// matters as much: blocks that span 256 or 512 events per column stream their
+// stores faster than blocks spanning 1024, which is what favours one event per
+// lane for N = 3 (and for per-event parents, which also read), two for N = 2,
+// and four for N = 4..7, where the per-event work dominates; for N >= 8 the
+// register footprint of several events in flight costs more than it saves.
 static int g_ept_override[3] = {0, 0, 0};
-static int default_ept(int mode, int n) {
+static int default_ept(int mode, int n, int pmode) {
     const int o = g_ept_override[mode];
     if (o > 0) return o;
-    if (mode != kIntegrate && n >= 7) return 1;
-    return 4;
+    if (mode == kIntegrate) return 4;
+    if (mode == kMixed) return n == 2 ? 2 : 4;
+    if (pmode == kPerEvent && n <= 3) return 1;
+    static const int kFp64[11] = {0, 0, 2, 1, 4, 4, 4, 4, 1, 1, 1};
+    return kFp64[n];
 }
 
 int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const double* parent_dev,
                uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
                int mode, void* out, uint64_t ld, double* weights, double* stats_dev,
                hipStream_t stream, int ept_override) {
-    const int ept = ept_override > 0 ? ept_override : default_ept(mode, n);
+    const int ept = ept_override > 0 ? ept_override : default_ept(mode, n, pmode);
     const uint64_t per_block = (uint64_t)kBlock * (uint64_t)ept;
     const uint64_t blocks = (nevents + per_block - 1) / per_block;
-    if (blocks > 0x7FFFFFFFull) return fail(HYDRA_PHSP_EINVAL, "nevents too large for one launch");
+    if (blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
+        return fail(HYDRA_PHSP_EINVAL, "nevents too large for one launch (more than 2^32 - 1 threads)");
     Workspace* ws = nullptr;
     int st = workspace_for(stream, blocks, &ws);
     if (st != HYDRA_PHSP_OK) return st;

@@ -3,9 +3,10 @@
 // Many decay channels (uneven N and event counts) run in one submission.  The
 // host cuts every channel into tiles of kBlock*EPT events -- exactly the
 // per-block chunks of the single-channel kernel -- groups the tiles by
-// daughter-count class, and per class a persistent grid walks its tile range
-// with a static stride (block b takes tiles b, b+G, b+2G, ...; every block
-// leaves the loop once its next index passes the end).  Each tile switches on
+// daughter-count class, and per class one launch walks its tile range: either
+// one block per tile, or a persistent grid with a static stride (block b takes
+// tiles b, b+G, b+2G, ...; every block leaves the loop once its next index
+// passes the end) or a dynamic claim of the next tile.  Each tile switches on
 // its channel's N to the same templated per-event code as the single-channel
 // kernel, and writes its block partial at the channel's tile index, so events,
 // weights and partials are bit-identical to a single-channel launch with the
@@ -66,33 +67,37 @@ __device__ __forceinline__ void run_tile(const KArgs& a, uint64_t blk, const dou
     if (threadIdx.x == 0) a.partials[blk] = r;
 }
 
-// Column bases stay in scalar registers only in the small-N classes, where the
-// kernel's scalar register budget allows it.
-template <int N, int EPT, int NMAXB>
+// Column bases stay in scalar registers only where the kernel's scalar register
+// budget allows it (every N of the kernel at most 5).
+template <int N, int EPT, int NHI>
 __device__ __forceinline__ void run_tile_mode(const DevChannel& c, uint64_t blk, const double2* tab) {
-    constexpr bool kPin = NMAXB <= 5;
+    constexpr bool kPin = NHI <= 5;
     if (c.mode == kIntegrate)
         run_tile<N, kIntegrate, EPT, kPin>(c.a, blk, tab);
     else
         run_tile<N, kFp64, EPT, kPin>(c.a, blk, tab);
 }
 
-// One kernel holds the code paths of every N up to NMAXB, so its register budget
-// is set by the largest; the waves-per-SIMD hint caps it (6 waves for N <= 3,
-// 4 for N <= 5, 3 for N <= 8, 2 for N <= 10) instead of letting the scheduler
-// trade occupancy for latency hiding.
-constexpr int batch_waves_hint(int nmaxb) { return nmaxb <= 3 ? 6 : nmaxb <= 5 ? 4 : nmaxb <= 8 ? 3 : 2; }
+// A value every lane of the wave holds (read from LDS), moved to scalar
+// registers so that the tile and channel records are addressed uniformly.
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
 
-// Tiles are taken either with a static stride (block b: b, b+G, b+2G, ...;
-// counter == nullptr) or dynamically from a zeroed device counter, one atomic
-// increment per tile, claimed while the previous tile is being processed, so
-// blocks advance through the tile list together (as the hardware dispatcher
-// would order them) and neighbouring output columns are written close in time.
-// Either way every block leaves once its next index is past the end.
-template <int NMAXB, int EPT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_waves_hint(NMAXB)))) void k_phsp_batched(
-    const DevChannel* __restrict__ chans, const TileRef* __restrict__ tiles, uint64_t ntiles,
-    const double2* __restrict__ trig, unsigned long long* __restrict__ counter) {
+// Tile walk shared by the batched kernels.  Tiles are taken either with a
+// static stride (block b: b, b+G, b+2G, ...; counter == nullptr; with G equal to
+// the tile count this is one block per tile) or dynamically from a zeroed device
+// counter, one atomic increment per tile, claimed while the previous tile is
+// being processed.  Either way every block leaves once its next index is past
+// the end.  Channels of the kernel have N in [NLO, NHI]; MODE is kIntegrate or
+// kFp64 for a kernel of one mode, or -1 to follow each channel's mode.
+template <int NLO, int NHI, int MODE, int EPT>
+__device__ __forceinline__ void batched_body(const DevChannel* __restrict__ chans,
+                                             const TileRef* __restrict__ tiles, uint64_t ntiles,
+                                             const double2* __restrict__ trig,
+                                             unsigned long long* __restrict__ counter) {
     __shared__ double2 tab[kTrigSize];
     __shared__ unsigned long long next;
     load_trig(tab, trig);
@@ -101,7 +106,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_wa
     if (dynamic) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1ull);
         __syncthreads();
-        t = next;
+        t = wave_uniform(next);
     }
     while (t < ntiles) {
         if (dynamic) {
@@ -110,24 +115,55 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_wa
         }
         const TileRef tr = tiles[t];
         const DevChannel& c = chans[tr.channel];
-        switch (c.n) {
-        case 2: run_tile_mode<2, EPT, NMAXB>(c, tr.block, tab); break;
-        case 3: run_tile_mode<3, EPT, NMAXB>(c, tr.block, tab); break;
-        case 4: if constexpr (NMAXB >= 4) run_tile_mode<4, EPT, NMAXB>(c, tr.block, tab); break;
-        case 5: if constexpr (NMAXB >= 5) run_tile_mode<5, EPT, NMAXB>(c, tr.block, tab); break;
-        case 6: if constexpr (NMAXB >= 6) run_tile_mode<6, EPT, NMAXB>(c, tr.block, tab); break;
-        case 7: if constexpr (NMAXB >= 7) run_tile_mode<7, EPT, NMAXB>(c, tr.block, tab); break;
-        case 8: if constexpr (NMAXB >= 8) run_tile_mode<8, EPT, NMAXB>(c, tr.block, tab); break;
-        case 9: if constexpr (NMAXB >= 9) run_tile_mode<9, EPT, NMAXB>(c, tr.block, tab); break;
-        case 10: if constexpr (NMAXB >= 10) run_tile_mode<10, EPT, NMAXB>(c, tr.block, tab); break;
-        default: break;
+        if constexpr (NLO == NHI && MODE >= 0) {
+            run_tile<NLO, MODE, EPT, (NHI <= 5)>(c.a, tr.block, tab);
+        } else {
+            switch (c.n) {
+            case 2: if constexpr (NLO <= 2 && NHI >= 2) run_tile_mode<2, EPT, NHI>(c, tr.block, tab); break;
+            case 3: if constexpr (NLO <= 3 && NHI >= 3) run_tile_mode<3, EPT, NHI>(c, tr.block, tab); break;
+            case 4: if constexpr (NLO <= 4 && NHI >= 4) run_tile_mode<4, EPT, NHI>(c, tr.block, tab); break;
+            case 5: if constexpr (NLO <= 5 && NHI >= 5) run_tile_mode<5, EPT, NHI>(c, tr.block, tab); break;
+            case 6: if constexpr (NLO <= 6 && NHI >= 6) run_tile_mode<6, EPT, NHI>(c, tr.block, tab); break;
+            case 7: if constexpr (NLO <= 7 && NHI >= 7) run_tile_mode<7, EPT, NHI>(c, tr.block, tab); break;
+            case 8: if constexpr (NLO <= 8 && NHI >= 8) run_tile_mode<8, EPT, NHI>(c, tr.block, tab); break;
+            case 9: if constexpr (NLO <= 9 && NHI >= 9) run_tile_mode<9, EPT, NHI>(c, tr.block, tab); break;
+            case 10: if constexpr (NLO <= 10 && NHI >= 10) run_tile_mode<10, EPT, NHI>(c, tr.block, tab); break;
+            default: break;
+            }
         }
         // The tile's LDS reduction must finish before the next tile reuses LDS,
         // and thread 0's claim of the next tile must be visible.
         __syncthreads();
-        t = dynamic ? next : t + gridDim.x;
+        t = dynamic ? wave_uniform(next) : t + gridDim.x;
     }
 }
+
+// Batched kernel for channels of exactly N daughters and one mode (kFp64 or
+// kIntegrate): the per-event code and the register budget are those of the
+// single-channel kernel for that N and mode.
+template <int N, int MODE, int EPT>
+__global__ __launch_bounds__(kBlock) void k_phsp_batched(const DevChannel* __restrict__ chans,
+                                                         const TileRef* __restrict__ tiles, uint64_t ntiles,
+                                                         const double2* __restrict__ trig,
+                                                         unsigned long long* __restrict__ counter) {
+    batched_body<N, N, MODE, EPT>(chans, tiles, ntiles, trig, counter);
+}
+
+// Kernel for tiles of any N up to NMAXB in one launch (the serving path, whose
+// ticks mix requests).  Its register budget is set by the largest N; the
+// waves-per-SIMD hint caps it (3 waves for N <= 8, 2 for N <= 10) instead of
+// letting the scheduler trade occupancy for latency hiding.
+constexpr int mixed_waves_hint(int nmaxb) { return nmaxb <= 8 ? 3 : 2; }
+
+template <int NMAXB, int EPT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(mixed_waves_hint(NMAXB)))) void
+k_phsp_batched_mixed(const DevChannel* __restrict__ chans, const TileRef* __restrict__ tiles, uint64_t ntiles,
+                     const double2* __restrict__ trig, unsigned long long* __restrict__ counter) {
+    batched_body<2, NMAXB, -1, EPT>(chans, tiles, ntiles, trig, counter);
+}
+
+// Largest grid of one launch: 256-thread blocks, at most 2^32 - 1 work-items.
+constexpr uint64_t kMaxGridBlocks = 0xFFFFFFFFull / (uint64_t)kBlock;
 
 // Zero the dynamic-schedule counters of a batch (a kernel, not a memset, so
 // graph replays stay correct).
@@ -142,13 +178,18 @@ struct BatchLaunch {
     unsigned long long* counter; // zeroed tile counter (dynamic schedule) or nullptr (static stride)
 };
 
-// Persistent-kernel launcher for one (NMAXB, EPT) pair, defined per
-// instantiation unit.
-template <int NMAXB, int EPT>
+// Launchers, defined per instantiation unit: exactly N daughters, or any N up to
+// NMAXB in one launch.
+template <int N, int MODE, int EPT>
 hipError_t launch_batched(const BatchLaunch& b, hipStream_t stream);
+template <int NMAXB, int EPT>
+hipError_t launch_batched_mixed(const BatchLaunch& b, hipStream_t stream);
 
-// Host launchers shared by the batched and serving paths.
-hipError_t launch_persistent(int nmaxb, int ept, const BatchLaunch& b, hipStream_t s);
+// Host launchers shared by the batched and serving paths: the channels of
+// exactly n daughters and one mode with ept events per thread; tiles of any N
+// up to nmax (8 or 10) and either mode with one event per thread.
+hipError_t launch_batch_class(int n, int mode, int ept, const BatchLaunch& b, hipStream_t s);
+hipError_t launch_mixed_tiles(int nmax, const BatchLaunch& b, hipStream_t s);
 // Stage 1 over `ngroups` group references, then stage 2 over chans[0..nch).
 hipError_t launch_batch_merges(const DevChannel* chans, const GroupRef* groups, uint64_t ngroups, Moments* mid,
                                uint64_t nch, hipStream_t s);

@@ -45,17 +45,14 @@ __global__ __launch_bounds__(kStage2Block) void k_batch_merge_stage2(const DevCh
 using namespace hphsp;
 
 namespace hphsp {
-// Daughter-count classes of the batched path: channels are grouped by the
-// smallest class bound that holds their N, and every class gets its own
-// persistent launch, so small-N tiles run at the occupancy of their own
-// register budget rather than that of the largest N in the batch.
-constexpr int kClasses = 4;
-constexpr int kClassMax[kClasses] = {3, 5, 8, 10};
-inline int class_of(int n) {
-    for (int c = 0; c < kClasses; ++c)
-        if (n <= kClassMax[c]) return c;
-    return kClasses - 1;
-}
+// Classes of the batched path: one per (N = 2..10, FP64 generate or
+// integrate-only).  Every class gets its own launch of the kernel specialised
+// for it, so each tile runs with the code and the occupancy of the
+// single-channel kernel.
+constexpr int kClasses = 18;
+inline int class_of(int n, int mode) { return (n - 2) + (mode == kIntegrate ? 9 : 0); }
+inline int class_n(int c) { return c % 9 + 2; }
+inline int class_mode(int c) { return c < 9 ? kFp64 : kIntegrate; }
 } // namespace hphsp
 
 struct hydra_phsp_plan {
@@ -65,9 +62,9 @@ struct hydra_phsp_plan {
     int dynamic = 0;
     unsigned long long* d_counters = nullptr; // one per class (dynamic schedule)
     uint64_t grid = 0, ntiles = 0, ngroups = 0;
-    uint64_t class_begin[hphsp::kClasses] = {0, 0, 0, 0};
-    uint64_t class_count[hphsp::kClasses] = {0, 0, 0, 0};
-    uint64_t class_grid[hphsp::kClasses] = {0, 0, 0, 0};
+    uint64_t class_begin[hphsp::kClasses] = {};
+    uint64_t class_count[hphsp::kClasses] = {};
+    uint64_t class_grid[hphsp::kClasses] = {};
     DevChannel* d_chans = nullptr;
     TileRef* d_tiles = nullptr;
     GroupRef* d_groups = nullptr;
@@ -82,21 +79,38 @@ struct hydra_phsp_plan {
 
 namespace hphsp {
 
-template <int NMAXB>
+template <int N, int MODE>
 static hipError_t launch_by_ept(int ept, const BatchLaunch& b, hipStream_t s) {
     switch (ept) {
-    case 1: return launch_batched<NMAXB, 1>(b, s);
-    case 2: return launch_batched<NMAXB, 2>(b, s);
-    case 4: return launch_batched<NMAXB, 4>(b, s);
+    case 1: return launch_batched<N, MODE, 1>(b, s);
+    case 2: return launch_batched<N, MODE, 2>(b, s);
+    case 4: return launch_batched<N, MODE, 4>(b, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_persistent(int nmaxb, int ept, const BatchLaunch& b, hipStream_t s) {
-    if (nmaxb <= 3) return launch_by_ept<3>(ept, b, s);
-    if (nmaxb <= 5) return launch_by_ept<5>(ept, b, s);
-    if (nmaxb <= 8) return launch_by_ept<8>(ept, b, s);
-    return launch_by_ept<10>(ept, b, s);
+template <int N>
+static hipError_t launch_by_mode(int mode, int ept, const BatchLaunch& b, hipStream_t s) {
+    return mode == kIntegrate ? launch_by_ept<N, kIntegrate>(ept, b, s) : launch_by_ept<N, kFp64>(ept, b, s);
+}
+
+hipError_t launch_batch_class(int n, int mode, int ept, const BatchLaunch& b, hipStream_t s) {
+    switch (n) {
+    case 2: return launch_by_mode<2>(mode, ept, b, s);
+    case 3: return launch_by_mode<3>(mode, ept, b, s);
+    case 4: return launch_by_mode<4>(mode, ept, b, s);
+    case 5: return launch_by_mode<5>(mode, ept, b, s);
+    case 6: return launch_by_mode<6>(mode, ept, b, s);
+    case 7: return launch_by_mode<7>(mode, ept, b, s);
+    case 8: return launch_by_mode<8>(mode, ept, b, s);
+    case 9: return launch_by_mode<9>(mode, ept, b, s);
+    case 10: return launch_by_mode<10>(mode, ept, b, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_mixed_tiles(int nmax, const BatchLaunch& b, hipStream_t s) {
+    return nmax <= 8 ? launch_batched_mixed<8, 1>(b, s) : launch_batched_mixed<10, 1>(b, s);
 }
 
 hipError_t launch_batch_merges(const DevChannel* chans, const GroupRef* groups, uint64_t ngroups, Moments* mid,
@@ -148,7 +162,7 @@ static int enqueue_plan(hydra_phsp_plan* p, hipStream_t s, bool timed) {
             if (p->class_count[c] == 0) continue;
             BatchLaunch b{p->d_chans, p->d_tiles + p->class_begin[c], p->class_count[c], p->class_grid[c], p->trig,
                           p->dynamic ? p->d_counters + c : nullptr};
-            e = launch_persistent(kClassMax[c], p->ept, b, s);
+            e = launch_batch_class(class_n(c), class_mode(c), p->ept, b, s);
         }
         timing_end(s, slot);
         if (e != hipSuccess) return fail_hip(e, "batched kernel launch");
@@ -181,7 +195,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         if (tuning->grid_per_cu) gpc = tuning->grid_per_cu;
         dyn = tuning->schedule;
     }
-    if (dyn != 0 && dyn != 1) return fail(HYDRA_PHSP_EINVAL, "tuning schedule must be 0 or 1");
+    if (dyn < 0 || dyn > 2) return fail(HYDRA_PHSP_EINVAL, "tuning schedule must be 0, 1 or 2");
     if (ept != 1 && ept != 2 && ept != 4) return fail(HYDRA_PHSP_EINVAL, "tuning ept must be 1, 2 or 4");
     if (gpc < 1 || gpc > 64) return fail(HYDRA_PHSP_EINVAL, "tuning grid_per_cu must be in [1, 64]");
 
@@ -226,7 +240,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         first_tile += nt;
         first_group += d.ngroups;
     }
-    // Tile table ordered by daughter-count class (one persistent launch per class).
+    // Tile table ordered by daughter-count class (one launch per class).
     uint64_t class_begin[kClasses], class_count[kClasses];
     {
         std::vector<TileRef> by_class;
@@ -234,7 +248,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         for (int c = 0; c < kClasses; ++c) {
             class_begin[c] = by_class.size();
             for (const TileRef& t : tiles)
-                if (class_of(dch[t.channel].n) == c) by_class.push_back(t);
+                if (class_of(dch[t.channel].n, dch[t.channel].mode) == c) by_class.push_back(t);
             class_count[c] = by_class.size() - class_begin[c];
         }
         tiles.swap(by_class);
@@ -254,14 +268,18 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     p->trig = trig;
     p->nch = nch;
     p->ept = ept;
-    p->dynamic = dyn;
+    p->dynamic = dyn == 1;
     p->ntiles = first_tile;
     p->ngroups = first_group;
     p->grid = 0;
     for (int c = 0; c < kClasses; ++c) {
         p->class_begin[c] = class_begin[c];
         p->class_count[c] = class_count[c];
-        p->class_grid[c] = std::min<uint64_t>(class_count[c], (uint64_t)gpc * (uint64_t)std::max(cus, 1));
+        // Schedule 2 launches one block per tile (the static stride then runs
+        // one iteration); the grid stays within the dispatch limit of 2^32 - 1
+        // work-items, beyond which the stride loop takes over.
+        const uint64_t cap = dyn == 2 ? kMaxGridBlocks : (uint64_t)gpc * (uint64_t)std::max(cus, 1);
+        p->class_grid[c] = std::min<uint64_t>(class_count[c], cap);
         p->grid = std::max(p->grid, p->class_grid[c]);
     }
     e = hipMalloc(&p->d_partials, sizeof(Moments) * std::max<uint64_t>(first_tile, 1));
@@ -474,10 +492,10 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
     int st = HYDRA_PHSP_OK;
     const int epts[3] = {1, 2, 4};
     const int gpcs[5] = {1, 2, 4, 8, 16};
-    for (int sched = 0; sched < 2 && st == HYDRA_PHSP_OK; ++sched)
+    for (int sched = 0; sched < 3 && st == HYDRA_PHSP_OK; ++sched)
     for (int ei = 0; ei < 3 && st == HYDRA_PHSP_OK; ++ei) {
-        for (int gi = 0; gi < 5 && st == HYDRA_PHSP_OK; ++gi) {
-            hydra_phsp_tuning t{epts[ei], gpcs[gi], sched, 0};
+        for (int gi = 0; gi < (sched == 2 ? 1 : 5) && st == HYDRA_PHSP_OK; ++gi) {
+            hydra_phsp_tuning t{epts[ei], sched == 2 ? 0 : gpcs[gi], sched, 0};
             hydra_phsp_plan* p = nullptr;
             st = build_plan(channels, n_channels, &t, &p, nullptr);
             if (st != HYDRA_PHSP_OK) break;

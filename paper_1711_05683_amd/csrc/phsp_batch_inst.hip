@@ -1,20 +1,45 @@
-// phsp_batch_inst.hip -- instantiates the persistent multi-channel kernel for one
-// (largest N, events per thread) pair; compiled once per pair with
-// -DBATCH_NMAX=<8|10> -DBATCH_EPT=<1|2|4>.
+// phsp_batch_inst.hip -- instantiates the batched kernels of one unit: compiled
+// once per N with -DBATCH_N=<2..10> (exact-N kernels, FP64 and integrate-only,
+// 1, 2 and 4 events per thread) and once per bound with -DBATCH_MIXED=<8|10> (any N up to the bound,
+// one event per thread).
 #include "phsp_batch.hpp"
 
-#if !defined(BATCH_NMAX) || !defined(BATCH_EPT)
-#error "compile with -DBATCH_NMAX=<8|10> -DBATCH_EPT=<1|2|4>"
+#if !defined(BATCH_N) && !defined(BATCH_MIXED)
+#error "compile with -DBATCH_N=<2..10> or -DBATCH_MIXED=<8|10>"
 #endif
 
 namespace hphsp {
 
-template <>
-hipError_t launch_batched<BATCH_NMAX, BATCH_EPT>(const BatchLaunch& b, hipStream_t stream) {
-    if (b.grid == 0 || b.grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_phsp_batched<BATCH_NMAX, BATCH_EPT>), dim3((unsigned)b.grid), dim3(kBlock), 0,
-                       stream, b.chans, b.tiles, b.ntiles, b.trig, b.counter);
+#if defined(BATCH_N)
+template <int MODE, int EPT>
+static hipError_t launch_n(const BatchLaunch& b, hipStream_t stream) {
+    if (b.grid == 0 || b.grid > kMaxGridBlocks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_phsp_batched<BATCH_N, MODE, EPT>), dim3((unsigned)b.grid), dim3(kBlock), 0, stream,
+                       b.chans, b.tiles, b.ntiles, b.trig, b.counter);
     return hipGetLastError();
 }
+#define HPHSP_BATCH_INST(MODE, EPT)                                                                            \
+    template <>                                                                                                \
+    hipError_t launch_batched<BATCH_N, MODE, EPT>(const BatchLaunch& b, hipStream_t s) {                      \
+        return launch_n<MODE, EPT>(b, s);                                                                      \
+    }
+HPHSP_BATCH_INST(kFp64, 1)
+HPHSP_BATCH_INST(kFp64, 2)
+HPHSP_BATCH_INST(kFp64, 4)
+HPHSP_BATCH_INST(kIntegrate, 1)
+HPHSP_BATCH_INST(kIntegrate, 2)
+HPHSP_BATCH_INST(kIntegrate, 4)
+#undef HPHSP_BATCH_INST
+#endif
+
+#if defined(BATCH_MIXED)
+template <>
+hipError_t launch_batched_mixed<BATCH_MIXED, 1>(const BatchLaunch& b, hipStream_t stream) {
+    if (b.grid == 0 || b.grid > kMaxGridBlocks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_phsp_batched_mixed<BATCH_MIXED, 1>), dim3((unsigned)b.grid), dim3(kBlock), 0, stream,
+                       b.chans, b.tiles, b.ntiles, b.trig, b.counter);
+    return hipGetLastError();
+}
+#endif
 
 } // namespace hphsp

@@ -41,7 +41,7 @@ hipError_t by_mode(const LaunchSpec& s, const KArgs& a, hipStream_t stream) {
 
 template <>
 hipError_t launch_phsp<PHSP_N>(const LaunchSpec& s, const KArgs& a, hipStream_t stream) {
-    if (s.blocks == 0 || s.blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    if (s.blocks == 0 || s.blocks > 0xFFFFFFFFull / (uint64_t)kBlock) return hipErrorInvalidValue;
     if (s.mode == kIntegrate) return by_ept<kAtRest, kIntegrate>(s, a, stream);
     switch (s.pmode) {
     case kAtRest: return by_mode<kAtRest>(s, a, stream);

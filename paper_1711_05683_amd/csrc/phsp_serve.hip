@@ -1,6 +1,6 @@
 // phsp_serve.hip -- continuous-batching request server.
 //
-// Host scheduler over the persistent multi-channel kernel: a FIFO queue, an
+// Host scheduler over the multi-channel kernel: a FIFO queue, an
 // HBM arena with a first-fit free list (the budget), a ring of tick slots
 // (pinned staging + device tables), and one in-order stream on which ticks run
 // back to back.  Every request is cut into tiles of kBlock events; a tick takes
@@ -26,7 +26,8 @@
 namespace hphsp {
 namespace {
 
-constexpr int kServeEpt = 1; // a tile is kBlock events: the single-channel FP64 launch shape
+constexpr int kServeEpt = 1; // a tile is kBlock events, one per thread
+static_assert(kServeEpt == 1, "the mixed-N kernels of a tick are built with one event per thread");
 constexpr uint64_t kAlign = 256;
 constexpr int kTickSlots = 4;
 
@@ -342,9 +343,11 @@ int launch_tick(hydra_phsp_server* s) {
                                hipMemcpyHostToDevice, q);
     }
     if (e != hipSuccess) return fail_hip(e, "server table upload");
+    // One block per tile: blocks are dispatched in tile order, so each request's
+    // output columns are written front to back.
     BatchLaunch b{t.chans.dev, t.tiles.dev, (uint64_t)tiles.size(),
-                  std::min<uint64_t>((uint64_t)tiles.size(), 8ull * (uint64_t)s->cus), s->trig, nullptr};
-    e = launch_persistent(nmax <= 8 ? 8 : 10, kServeEpt, b, q);
+                  std::min<uint64_t>((uint64_t)tiles.size(), kMaxGridBlocks), s->trig, nullptr};
+    e = launch_mixed_tiles(nmax, b, q);
     if (e != hipSuccess) return fail_hip(e, "server tick launch");
     if (!fin.empty()) {
         e = launch_batch_merges(t.fin.dev, t.groups.dev, groups.size(), t.mid, fin.size(), q);

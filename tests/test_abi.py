@@ -162,3 +162,5 @@ def test_batch_validation_names_bad_channel(P):
     arr = P._channel_array([good])
     assert P.lib().hydra_phsp_batch_run(arr, 1, ctypes.byref(t), None, ctypes.byref(idx)) == P.EINVAL
     assert P.lib().hydra_phsp_batch_run(arr, 0, None, None, ctypes.byref(idx)) == P.EINVAL
+    for bad_t in (P._tuning(schedule=3), P._tuning(schedule=-1), P._tuning(grid_per_cu=65)):
+        assert P.lib().hydra_phsp_batch_run(arr, 1, ctypes.byref(bad_t), None, ctypes.byref(idx)) == P.EINVAL

@@ -98,7 +98,8 @@ def test_batch_matches_single_channel(P):
     _compare_with_single(P, specs, bufs, 1)
 
 
-@pytest.mark.parametrize("ept,gpc,sched", [(2, 1, 0), (4, 16, 0), (1, 2, 0), (4, 8, 1), (1, 1, 1), (2, 16, 1)])
+@pytest.mark.parametrize("ept,gpc,sched", [(2, 1, 0), (4, 16, 0), (1, 2, 0), (4, 8, 1), (1, 1, 1), (2, 16, 1),
+                                            (1, 0, 2), (2, 0, 2), (4, 0, 2)])
 def test_batch_tuning_variants(P, ept, gpc, sched):
     _say(f"batch variant ept={ept} grid/cu={gpc} schedule={sched}")
     specs, bufs, descs = _channels(P, n_channels=16, seed=7)
@@ -169,7 +170,8 @@ def test_autotune(P):
     _say("autotune")
     specs, bufs, descs = _channels(P, n_channels=16, seed=5, log_events=(3.0, 5.0))
     ept, gpc, sched, ms = P.autotune(descs)
-    assert ept in (1, 2, 4) and 1 <= gpc <= 16 and sched in (0, 1) and ms > 0
+    assert ept in (1, 2, 4) and sched in (0, 1, 2) and ms > 0
+    assert (gpc == 0) if sched == 2 else (1 <= gpc <= 16)
     # cached: same answer
     assert P.autotune(descs) == (ept, gpc, sched, ms)
     # the tuned shape still gives the single-channel events

@@ -206,9 +206,19 @@ def test_mixed_precision(P, n, M, masses):
     _say(f"mixed N={n} m={masses[0]}")
     nev = 200_000
     p4, w, st = _run(P, M, masses, nev, mixed=True)
-    p4d, wd, sd = _run(P, M, masses, nev)
-    # FP64 prologue: weights and integral are bit-identical to the FP64 path
-    assert np.array_equal(w, wd) and np.array_equal(st, sd)
+    # FP64 prologue: weights are bit-identical to the FP64 path, and so is the
+    # integral when both run the same launch shape (the reduction tree follows
+    # the block partials)
+    P.set_events_per_thread(1, 4)
+    P.set_events_per_thread(2, 4)
+    try:
+        _, wm4, sm4 = _run(P, M, masses, nev, mixed=True)
+        p4d, wd, sd = _run(P, M, masses, nev)
+    finally:
+        P.set_events_per_thread(1, 0)
+        P.set_events_per_thread(2, 0)
+    assert np.array_equal(w, wd) and np.array_equal(wm4, wd) and np.array_equal(sm4, sd)
+    assert rel(st[1], sd[1]) <= 1e-13
     p4o, wo = oracle.generate(M, masses, nev, seed=42)
     rep = mixed_error_report(p4, p4o, M)
     _say(f"mixed N={n} m={masses[0]}: {rep}")

@@ -46,9 +46,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic():
+def read_traffic(kernel: str = ""):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when missing or taken on a different kernel source."""
+    when missing, taken on a different kernel source, or on another instantiation
+    than `kernel` (e.g. another events-per-thread setting)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     fields = {}
@@ -58,6 +59,8 @@ def read_traffic():
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
     if fields.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if kernel and kernel not in fields.get("kernel", ""):
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -125,6 +128,8 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc: a 1 GiB torch copy (the calibration "
                          "kernel of known traffic) x3, then the main step x3; prints no JSON")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the 64-channel batched configuration and print its figures")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -141,6 +146,10 @@ def main():
     P.lib()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    if args.batched_only:
+        print(json.dumps(batched_extra(P, torch, dev, args.steps)), flush=True)
+        return
 
     M, m = 5.279, [3.097, 0.4937, 0.13957]
     n_ev = args.nevents
@@ -167,7 +176,9 @@ def main():
     bytes_per_event = 8 * (4 * 3 + 1)
     achieved = bytes_per_event * n_ev / (ms_kernel * 1e-3) / 1e9
     stats = st.cpu().tolist()
-    traffic = read_traffic()
+    ept = P.events_per_thread(1, 3)
+    main_kernel = f"k_phsp<3, 0, 1, {ept}>"
+    traffic = read_traffic(main_kernel)
 
     result = {
         "metric": METRIC,
@@ -188,7 +199,8 @@ def main():
                    "n_daughters": 3, "nevents": n_ev, "bytes_per_event": bytes_per_event},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "k_phsp<3, at rest, FP64>", "kernel_ms": ms_kernel},
+                     "kernel": f"{main_kernel} (N=3, at rest, FP64, {ept} event(s) per thread)",
+                     "kernel_ms": ms_kernel},
         "integral": {"mean": stats[1], "sigma": stats[3], "n": stats[0]},
     }
     del out

@@ -153,6 +153,10 @@ int hydra_phsp_selftest_sortnet(void);
  * Process-wide; changes the launch shape only (events are bit-identical for
  * every value; integrals agree to rounding). */
 int hydra_phsp_set_events_per_thread(int path, int ept);
+/* The events per thread the next single-channel launch on `path` would use for
+ * n_daughters (per_event_parents != 0: with per-event parent four-vectors),
+ * after any override; EINVAL for a bad path or n_daughters. */
+int hydra_phsp_events_per_thread(int path, int n_daughters, int per_event_parents);
 
 /* Kernel timing for benchmarks: while enabled, every launch of the main
  * phase-space kernel is bracketed by HIP events recorded on the caller's

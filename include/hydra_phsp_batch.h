@@ -2,8 +2,10 @@
  * hydra_phsp_batch.h -- batched multi-channel phase-space generation.
  *
  * Many decay channels of uneven daughter count and event count run in one
- * persistent kernel launch (the phase-space generator of arXiv:1711.05683
- * sec. 4.2, applied to many (M, masses) pairs at once).  Conventions,
+ * submission: one kernel launch per (daughter count, mode) class present, each
+ * specialised like the single-channel kernel for that class (the phase-space
+ * generator of arXiv:1711.05683 sec. 4.2, applied to many (M, masses) pairs at
+ * once).  Conventions,
  * layouts, ownership and error codes are those of hydra_phsp.h.
  */
 #ifndef HYDRA_PHSP_BATCH_H
@@ -22,8 +24,8 @@ extern "C" {
  * stats_dev (HYDRA_PHSP_STATS doubles, device) is required.  Each channel's
  * events and weights are bit-identical to a single-channel call with the same
  * (masses, seed, stream_id, event_offset); its stats are bit-identical too when
- * the single-channel call ran with the same events per thread (see
- * hydra_phsp_set_events_per_thread), and agree to rounding otherwise. */
+ * the single-channel call ran with the same events per thread (always so with
+ * tuning ept 0, see hydra_phsp_tuning), and agree to rounding otherwise. */
 typedef struct hydra_phsp_channel {
     double parent_mass;
     double masses[HYDRA_PHSP_NMAX];
@@ -39,14 +41,17 @@ typedef struct hydra_phsp_channel {
 } hydra_phsp_channel;
 
 /* Launch shape of the batched kernels (blocks of 256 threads):
- *   ept          events per thread: 1, 2 or 4 (a tile is 256*ept events);
+ *   ept          events per thread: 1, 2 or 4 for every class (a tile is
+ *                256*ept events), or 0: per class, what a single-channel call
+ *                of that N and mode would use (hydra_phsp_events_per_thread),
+ *                so every channel's tiles are that call's blocks;
  *   grid_per_cu  persistent blocks per compute unit, 1 .. 64 (schedules 0, 1);
  *   schedule     0: persistent grid, static stride over the tiles;
  *                1: persistent grid, blocks claim tiles in order from a
  *                   device counter;
  *                2: one block per tile (grid = tile count, grid_per_cu is
  *                   ignored), so the hardware dispatches tiles in order.
- * A zero ept or grid_per_cu selects the library default (4 and 8). */
+ * A zero grid_per_cu selects the library default (8). */
 typedef struct hydra_phsp_tuning {
     int32_t ept;
     int32_t grid_per_cu;
@@ -57,14 +62,14 @@ typedef struct hydra_phsp_tuning {
 /* Enqueue one batch on `stream`: validates every channel (no work is enqueued
  * if any channel is invalid; *bad_channel_out, when not NULL, receives the
  * index of the first bad one), uploads the tile table and launches the
- * persistent kernel and the per-channel merges.  The device tables stay alive
+ * class kernels and the per-channel merges.  The device tables stay alive
  * until the next hydra_phsp_batch_run on the same stream, which first waits
  * for this one.  tuning may be NULL. */
 int hydra_phsp_batch_run(const hydra_phsp_channel *channels, int n_channels,
                          const hydra_phsp_tuning *tuning, void *stream, int *bad_channel_out);
 
 /* A reusable batch: tables are built and uploaded once and the launch sequence
- * (persistent kernel + per-channel merges) is captured into a HIP graph that
+ * (class kernels + per-channel merges) is captured into a HIP graph that
  * hydra_phsp_plan_launch replays on any stream.  The channels, including their
  * device pointers, are fixed at creation.  One plan's launches must not
  * overlap each other. */
@@ -74,12 +79,13 @@ int hydra_phsp_plan_create(const hydra_phsp_channel *channels, int n_channels,
 int hydra_phsp_plan_launch(hydra_phsp_plan *plan, void *stream);
 /* Waits for the plan's outstanding launches, then frees it. */
 int hydra_phsp_plan_destroy(hydra_phsp_plan *plan);
-/* Number of tiles and the persistent grid size of a plan (host). */
+/* Number of tiles and the largest class grid of a plan (host). */
 int hydra_phsp_plan_info(const hydra_phsp_plan *plan, uint64_t *ntiles_out, uint64_t *grid_out);
 
 /* Autotuner: times the batch (kernels and merges) over schedule
- * {static, dynamic} x events per thread {1, 2, 4} x blocks per compute unit
- * {1, 2, 4, 8, 16}, plus one block per tile x events per thread -- two warm-up
+ * {static, dynamic} x events per thread {per class, 1, 2, 4} x blocks per
+ * compute unit {1, 2, 4, 8, 16}, plus one block per tile x events per thread
+ * -- two warm-up
  * runs and five timed runs per shape, overwriting the batch's outputs -- and
  * returns the shape with the fastest run and that run's time in ms.  Results
  * are cached per device and batch shape class for the life of the process; a

@@ -58,6 +58,8 @@ def _declare(lib):
     lib.hydra_phsp_release.restype = i
     lib.hydra_phsp_set_events_per_thread.argtypes = [i, i]
     lib.hydra_phsp_set_events_per_thread.restype = i
+    lib.hydra_phsp_events_per_thread.argtypes = [i, i, i]
+    lib.hydra_phsp_events_per_thread.restype = i
     lib.hydra_phsp_timing_enable.argtypes = [i]
     lib.hydra_phsp_timing_enable.restype = i
     lib.hydra_phsp_timing_reset.argtypes = []
@@ -199,6 +201,13 @@ def set_events_per_thread(path: int, ept: int):
     _check(lib().hydra_phsp_set_events_per_thread(path, ept))
 
 
+def events_per_thread(path: int, n_daughters: int, per_event_parents: bool = False) -> int:
+    """Events per thread of the next launch on path 0 (integrate), 1 (FP64) or 2 (mixed)."""
+    r = lib().hydra_phsp_events_per_thread(path, n_daughters, int(per_event_parents))
+    _check(min(r, 0))
+    return r
+
+
 def timing_enable(on: bool = True):
     """Bracket every main-kernel launch with HIP events on its stream."""
     _check(lib().hydra_phsp_timing_enable(1 if on else 0))
@@ -226,7 +235,8 @@ class ChannelDesc(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    """``hydra_phsp_tuning``: events per thread, persistent blocks per CU (0 = default) and
+    """``hydra_phsp_tuning``: events per thread (0 = per class, as a single-channel call),
+    persistent blocks per CU (0 = default) and
     tile schedule (0 static stride, 1 dynamic, 2 one block per tile)."""
     _fields_ = [("ept", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -285,7 +295,7 @@ def _tuning(ept=0, grid_per_cu=0, schedule=0):
 
 
 def batch_run(chans, *, ept: int = 0, grid_per_cu: int = 0, schedule: int = 0, stream=None):
-    """Enqueue one batch (all channels; one persistent launch per daughter-count class)."""
+    """Enqueue one batch (all channels; one launch per (daughter count, mode) class)."""
     L = lib()
     arr = _channel_array(chans)
     bad = ctypes.c_int(-1)
@@ -328,7 +338,7 @@ class Plan:
 
 
 def autotune(chans, stream=None):
-    """(ept, grid_per_cu, schedule, ms) of the fastest persistent-kernel shape for this batch."""
+    """(ept, grid_per_cu, schedule, ms) of the fastest launch shape for this batch."""
     t = Tuning()
     ms = ctypes.c_double()
     _check(lib().hydra_phsp_autotune(_channel_array(chans), len(chans), _stream_handle(stream),

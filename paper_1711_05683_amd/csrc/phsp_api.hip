@@ -266,6 +266,8 @@ static int default_ept(int mode, int n, int pmode) {
     return kFp64[n];
 }
 
+int single_channel_ept(int mode, int n, int pmode) { return default_ept(mode, n, pmode); }
+
 int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const double* parent_dev,
                uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
                int mode, void* out, uint64_t ld, double* weights, double* stats_dev,
@@ -329,6 +331,10 @@ static int generate_common(double M, const double* masses, int n, const double* 
     if (nevents > 0 && (out == nullptr || weights == nullptr))
         return fail(HYDRA_PHSP_EINVAL, "p4_out_dev and weights_dev are required");
     if (ld < nevents) return fail(HYDRA_PHSP_EINVAL, "ld must be >= nevents");
+    const uintptr_t elem = mode == kMixed ? sizeof(float) : sizeof(double);
+    if ((uintptr_t)out % elem != 0 || (uintptr_t)weights % sizeof(double) != 0 ||
+        (uintptr_t)stats_dev % sizeof(double) != 0 || (uintptr_t)parent_p4_dev % sizeof(double) != 0)
+        return fail(HYDRA_PHSP_EINVAL, "device pointers must be aligned to their element size");
     if (parent_p4_host != nullptr && parent_p4_dev != nullptr)
         return fail(HYDRA_PHSP_EINVAL, "give at most one of parent_p4_host and parent_p4_dev");
     int pmode = kAtRest;
@@ -437,6 +443,13 @@ int hydra_phsp_set_events_per_thread(int path, int ept) {
     if (ept != 0 && ept != 1 && ept != 2 && ept != 4) return fail(HYDRA_PHSP_EINVAL, "ept must be 0, 1, 2 or 4");
     g_ept_override[path] = ept;
     return HYDRA_PHSP_OK;
+}
+
+int hydra_phsp_events_per_thread(int path, int n_daughters, int per_event_parents) {
+    if (path < 0 || path > 2) return fail(HYDRA_PHSP_EINVAL, "path must be 0, 1 or 2");
+    if (n_daughters < 2 || n_daughters > HYDRA_PHSP_NMAX)
+        return fail(HYDRA_PHSP_EINVAL, "n_daughters must be in [2, HYDRA_PHSP_NMAX]");
+    return default_ept(path, n_daughters, per_event_parents ? kPerEvent : kAtRest);
 }
 
 int hydra_phsp_timing_enable(int on) {

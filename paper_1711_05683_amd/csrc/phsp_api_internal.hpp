@@ -20,6 +20,9 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
                uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
                int mode, void* out, uint64_t ld, double* weights, double* stats_dev, hipStream_t stream,
                int ept_override);
+// Events per thread a single-channel launch uses for (mode, n, parent mode),
+// after the process-wide override.
+int single_channel_ept(int mode, int n, int pmode);
 int release_workspaces();
 int release_batch_slots();
 // The device's (cos, sin) table used by the FP64 kernels (created on first use).

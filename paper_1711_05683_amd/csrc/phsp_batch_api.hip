@@ -58,7 +58,7 @@ inline int class_mode(int c) { return c < 9 ? kFp64 : kIntegrate; }
 struct hydra_phsp_plan {
     int device = 0;
     int nch = 0;
-    int ept = 1;
+    int class_ept[hphsp::kClasses] = {};     // events per thread of each class's launch
     int dynamic = 0;
     unsigned long long* d_counters = nullptr; // one per class (dynamic schedule)
     uint64_t grid = 0, ntiles = 0, ngroups = 0;
@@ -133,6 +133,9 @@ static int check_channel(const hydra_phsp_channel& c, Channel* ch) {
     const bool has_out = c.p4_out_dev != nullptr, has_w = c.weights_dev != nullptr;
     if (has_out != has_w) return fail(HYDRA_PHSP_EINVAL, "channel needs both p4_out_dev and weights_dev, or neither");
     if (has_out && c.ld < c.nevents) return fail(HYDRA_PHSP_EINVAL, "channel ld must be >= nevents");
+    if ((uintptr_t)c.p4_out_dev % sizeof(double) != 0 || (uintptr_t)c.weights_dev % sizeof(double) != 0 ||
+        (uintptr_t)c.stats_dev % sizeof(double) != 0)
+        return fail(HYDRA_PHSP_EINVAL, "channel device pointers must be 8-byte aligned");
     return HYDRA_PHSP_OK;
 }
 
@@ -162,7 +165,7 @@ static int enqueue_plan(hydra_phsp_plan* p, hipStream_t s, bool timed) {
             if (p->class_count[c] == 0) continue;
             BatchLaunch b{p->d_chans, p->d_tiles + p->class_begin[c], p->class_count[c], p->class_grid[c], p->trig,
                           p->dynamic ? p->d_counters + c : nullptr};
-            e = launch_batch_class(class_n(c), class_mode(c), p->ept, b, s);
+            e = launch_batch_class(class_n(c), class_mode(c), p->class_ept[c], b, s);
         }
         timing_end(s, slot);
         if (e != hipSuccess) return fail_hip(e, "batched kernel launch");
@@ -189,20 +192,26 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     if (bad) *bad = -1;
     if (chans == nullptr || nch <= 0) return fail(HYDRA_PHSP_EINVAL, "need at least one channel");
     if (out == nullptr) return fail(HYDRA_PHSP_EINVAL, "plan_out is NULL");
-    int ept = 4, gpc = 8, dyn = 0;
+    int ept = 0, gpc = 8, dyn = 0;
     if (tuning) {
         if (tuning->ept) ept = tuning->ept;
         if (tuning->grid_per_cu) gpc = tuning->grid_per_cu;
         dyn = tuning->schedule;
     }
     if (dyn < 0 || dyn > 2) return fail(HYDRA_PHSP_EINVAL, "tuning schedule must be 0, 1 or 2");
-    if (ept != 1 && ept != 2 && ept != 4) return fail(HYDRA_PHSP_EINVAL, "tuning ept must be 1, 2 or 4");
+    if (ept != 0 && ept != 1 && ept != 2 && ept != 4)
+        return fail(HYDRA_PHSP_EINVAL, "tuning ept must be 0, 1, 2 or 4");
+    // Events per thread per class: the given value, or (0) what a single-channel
+    // launch of that N and mode would use, so that every channel's tiles are that
+    // launch's blocks.
+    int class_ept[kClasses];
+    for (int c = 0; c < kClasses; ++c)
+        class_ept[c] = ept ? ept : single_channel_ept(class_mode(c), class_n(c), kAtRest);
     if (gpc < 1 || gpc > 64) return fail(HYDRA_PHSP_EINVAL, "tuning grid_per_cu must be in [1, 64]");
 
     std::vector<DevChannel> dch((size_t)nch);
     std::vector<TileRef> tiles;
     std::vector<GroupRef> groups;
-    const uint64_t tile_events = (uint64_t)kBlock * (uint64_t)ept;
     uint64_t first_tile = 0, first_group = 0;
     for (int i = 0; i < nch; ++i) {
         const hydra_phsp_channel& c = chans[i];
@@ -212,6 +221,8 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
             if (bad) *bad = i;
             return st;
         }
+        const uint64_t tile_events =
+            (uint64_t)kBlock * (uint64_t)class_ept[class_of(c.n_daughters, c.p4_out_dev ? kFp64 : kIntegrate)];
         const uint64_t nt = (c.nevents + tile_events - 1) / tile_events;
         if (nt > 0xFFFFFFFFull) return fail(HYDRA_PHSP_EINVAL, "channel too large");
         DevChannel d;
@@ -267,7 +278,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     p->device = dev;
     p->trig = trig;
     p->nch = nch;
-    p->ept = ept;
+    for (int c = 0; c < kClasses; ++c) p->class_ept[c] = class_ept[c];
     p->dynamic = dyn == 1;
     p->ntiles = first_tile;
     p->ngroups = first_group;
@@ -490,10 +501,10 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
     double best_ms = 1e300;
     hydra_phsp_tuning best{4, 8, 0, 0};
     int st = HYDRA_PHSP_OK;
-    const int epts[3] = {1, 2, 4};
+    const int epts[4] = {0, 1, 2, 4};
     const int gpcs[5] = {1, 2, 4, 8, 16};
     for (int sched = 0; sched < 3 && st == HYDRA_PHSP_OK; ++sched)
-    for (int ei = 0; ei < 3 && st == HYDRA_PHSP_OK; ++ei) {
+    for (int ei = 0; ei < 4 && st == HYDRA_PHSP_OK; ++ei) {
         for (int gi = 0; gi < (sched == 2 ? 1 : 5) && st == HYDRA_PHSP_OK; ++gi) {
             hydra_phsp_tuning t{epts[ei], sched == 2 ? 0 : gpcs[gi], sched, 0};
             hydra_phsp_plan* p = nullptr;

@@ -49,7 +49,7 @@ def test_strerror(P):
         assert P.lib().hydra_phsp_strerror(code)
 
 
-def _gen_status(P, M, masses, nevents=10, ld=None, out=1, w=1, parent_host=None, parent_dev=None,
+def _gen_status(P, M, masses, nevents=10, ld=None, out=8, w=8, parent_host=None, parent_dev=None,
                 ldp=0):
     m, n = P._masses(masses)
     ph = None if parent_host is None else (ctypes.c_double * 4)(*parent_host)
@@ -80,6 +80,27 @@ def test_validation_before_any_device_work(P):
     # per-event parents with a too-short leading dimension
     assert _gen_status(P, 5.0, [1.0, 1.0], parent_dev=ctypes.c_void_p(8), ldp=3) == P.EINVAL
     assert "ld_parent" in P.lib().hydra_phsp_last_error().decode()
+    # device pointers not aligned to their element size
+    assert _gen_status(P, 5.0, [1.0, 1.0], out=12) == P.EINVAL
+    assert "aligned" in P.lib().hydra_phsp_last_error().decode()
+    assert _gen_status(P, 5.0, [1.0, 1.0], w=4) == P.EINVAL
+    assert _gen_status(P, 5.0, [1.0, 1.0], parent_dev=ctypes.c_void_p(12), ldp=10) == P.EINVAL
+
+
+def test_events_per_thread_query(P):
+    for path in (0, 1, 2):
+        for n in range(2, 11):
+            for pe in (0, 1):
+                assert P.events_per_thread(path, n, bool(pe)) in (1, 2, 4)
+    assert P.events_per_thread(0, 3) == 4
+    P.set_events_per_thread(1, 2)
+    try:
+        assert P.events_per_thread(1, 3) == 2 and P.events_per_thread(1, 10, True) == 2
+    finally:
+        P.set_events_per_thread(1, 0)
+    assert P.lib().hydra_phsp_events_per_thread(3, 3, 0) == P.EINVAL
+    assert P.lib().hydra_phsp_events_per_thread(1, 11, 0) == P.EINVAL
+    assert P.lib().hydra_phsp_events_per_thread(1, 1, 0) == P.EINVAL
 
 
 def test_integrate_validation(P):

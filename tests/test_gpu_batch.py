@@ -108,6 +108,14 @@ def test_batch_tuning_variants(P, ept, gpc, sched):
     _compare_with_single(P, specs, bufs, ept)
 
 
+def test_batch_default_shape_matches_single_channel_defaults(P):
+    _say("batch ept 0 (per class) vs single-channel defaults, N up to 10, both modes")
+    specs, bufs, descs = _channels(P, n_channels=24, seed=31, nmax=10, integrate_every=4)
+    P.batch_run(descs)  # ept 0: every class takes its single-channel setting
+    torch.cuda.synchronize()
+    _compare_with_single(P, specs, bufs, 0)
+
+
 def test_batch_with_ten_body_channels(P):
     _say("batch with N up to 10")
     specs, bufs, descs = _channels(P, n_channels=12, seed=99, nmax=10)
@@ -170,7 +178,7 @@ def test_autotune(P):
     _say("autotune")
     specs, bufs, descs = _channels(P, n_channels=16, seed=5, log_events=(3.0, 5.0))
     ept, gpc, sched, ms = P.autotune(descs)
-    assert ept in (1, 2, 4) and sched in (0, 1, 2) and ms > 0
+    assert ept in (0, 1, 2, 4) and sched in (0, 1, 2) and ms > 0
     assert (gpc == 0) if sched == 2 else (1 <= gpc <= 16)
     # cached: same answer
     assert P.autotune(descs) == (ept, gpc, sched, ms)
@@ -194,7 +202,7 @@ def test_config3_full_batch(P):
         bufs.append((out, w, st))
         descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id,
                                out=out, weights=w, stats=st))
-    plan = P.Plan(descs)  # library default shape: 4 events per thread
+    plan = P.Plan(descs)  # default shape: each class as its single-channel launch
     plan.launch()
     torch.cuda.synchronize()
     rng = np.random.default_rng(0)
@@ -209,12 +217,8 @@ def test_config3_full_batch(P):
             p4o, wo = oracle.generate(c.parent_mass, c.masses, 1, seed=c.seed, stream_id=c.stream_id,
                                       event_offset=int(e))
             assert_events_close(g[:, :, j:j + 1], gw[j:j + 1], p4o, wo)
-        P.set_events_per_thread(1, 4)  # the plan's default shape (4 events per thread)
-        try:
-            so, sw, sst = P.generate(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id)
-            torch.cuda.synchronize()
-        finally:
-            P.set_events_per_thread(1, 0)
+        so, sw, sst = P.generate(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id)
+        torch.cuda.synchronize()
         assert torch.equal(so, out) and torch.equal(sw, w) and torch.equal(sst, st), i
         del so, sw
     plan.destroy()

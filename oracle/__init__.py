@@ -68,6 +68,14 @@ def _load():
                                      ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
     lib.oracle_integrate.restype = ctypes.c_int
+    lib.oracle_calls_per_event.argtypes = [ctypes.c_int]
+    lib.oracle_calls_per_event.restype = ctypes.c_int
+    lib.oracle_accept_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int]
+    lib.oracle_accept_uniform.restype = ctypes.c_double
+    lib.oracle_unweight.argtypes = [ctypes.c_double, dp, ctypes.c_int, dp, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, dp, ctypes.c_uint64,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    lib.oracle_unweight.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -151,3 +159,41 @@ def integrate(parent_mass, masses, nevents, seed=42, stream_id=0, event_offset=0
     if st != OK:
         raise OracleError(st)
     return mean.value, sigma.value
+
+
+def calls_per_event(n: int) -> int:
+    """Philox calls one event's own uniforms use."""
+    return _load().oracle_calls_per_event(n)
+
+
+def accept_uniform(seed: int, stream_id: int, g: int, n: int) -> float:
+    """The hit-or-miss acceptance uniform of global event g."""
+    return _load().oracle_accept_uniform(seed, stream_id, g, n)
+
+
+def unweight(parent_mass, masses, ntrials, seed=42, stream_id=0, event_offset=0, w_max=0.0,
+             parent_p4=None, capacity=None, want_momenta=True):
+    """Hit-or-miss unweighting of ntrials weighted events (trial e kept when
+    v_e * w_max < w_e; w_max = 0: the largest trial weight).
+
+    Returns (p4, index, kept, over, w_max_used): p4 [N, 4, min(kept, capacity)] of the
+    kept events in trial order, index their global event indices, kept the number
+    kept, over the number of trials with w > w_max."""
+    lib = _load()
+    m = _masses(masses)
+    n = len(m)
+    cap = ntrials if capacity is None else capacity
+    out = np.zeros((n, 4, max(cap, 1)), dtype=np.float64) if want_momenta else None
+    idx = np.zeros(max(cap, 1), dtype=np.uint64)
+    counts = np.zeros(2, dtype=np.uint64)
+    used = ctypes.c_double()
+    pp = None if parent_p4 is None else np.ascontiguousarray(parent_p4, dtype=np.float64)
+    st = lib.oracle_unweight(parent_mass, _ptr(m), n, _ptr(pp), ntrials, seed, stream_id, event_offset,
+                             float(w_max), _ptr(out), max(cap, 1) if want_momenta else cap, _ptr(idx),
+                             _ptr(counts), ctypes.byref(used))
+    if st != OK:
+        raise OracleError(st)
+    kept, over = int(counts[0]), int(counts[1])
+    k = min(kept, cap)
+    p4 = None if out is None else out[:, :, :k]
+    return p4, idx[:k], kept, over, used.value

@@ -333,3 +333,79 @@ int oracle_integrate(double parent_mass, const double *masses, int n,
     free(w);
     return st;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Unweighted samples (sec. 4.2 lists them next to weighted ones).  Plain   */
+/* hit-or-miss: a trial event of weight w is kept with probability          */
+/* min(1, w / w_max), so the kept events are distributed as phase space     */
+/* itself (flat in the invariants) with unit weight.                        */
+/* ---------------------------------------------------------------------- */
+
+/* Number of Philox calls one event's uniforms use: ceil((3N-4)/2). */
+int oracle_calls_per_event(int n)
+{
+    return (oracle_uniforms_per_event(n) + 1) / 2;
+}
+
+/* The acceptance uniform of global event g: words 0 and 1 of Philox call
+ * j = oracle_calls_per_event(n) of the event's counter stream (the first call
+ * its own uniforms do not use), converted like every other uniform. */
+double oracle_accept_uniform(uint64_t seed, uint32_t stream_id, uint64_t g, int n)
+{
+    const uint32_t key[2] = { (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32) };
+    const uint32_t ctr[4] = { (uint32_t)(g & 0xFFFFFFFFu), (uint32_t)(g >> 32),
+                              (uint32_t)oracle_calls_per_event(n), stream_id };
+    uint32_t words[4];
+    oracle_philox4x32_10(ctr, key, words);
+    uint64_t bits = ((uint64_t)words[1] << 32) | (uint64_t)words[0];
+    uint64_t x = bits >> 12;
+    return (double)(2 * x + 1) * 0x1p-53;
+}
+
+/* Trials e = 0..ntrials-1 (global index event_offset + e) are the weighted
+ * events oracle_generate produces; trial e is kept when v * w_max < w, with v
+ * its acceptance uniform.  w_max == 0 takes the largest weight of the trials
+ * (first pass).  Kept events are written in trial order to out (SoA, capacity
+ * ld; kept events past the capacity are counted, not written) and, when index
+ * is not NULL, their global indices to index[0..].  counts[0] = number kept,
+ * counts[1] = number of trials whose weight exceeds w_max (kept with
+ * probability 1, so w_max did not bound them).  *w_max_used = the w_max applied. */
+int oracle_unweight(double parent_mass, const double *masses, int n, const double *parent_p4,
+                    uint64_t ntrials, uint64_t seed, uint32_t stream_id, uint64_t event_offset,
+                    double w_max, double *out, uint64_t ld, uint64_t *index, uint64_t counts[2],
+                    double *w_max_used)
+{
+    int st = check_args(parent_mass, masses, n);
+    if (st != ORACLE_OK) return st;
+    if (counts == NULL || !(w_max >= 0.0) || !isfinite(w_max)) return ORACLE_EINVAL;
+    double u[3 * ORACLE_NMAX];
+    double p4[ORACLE_NMAX][4];
+    if (w_max == 0.0) {
+        for (uint64_t e = 0; e < ntrials; ++e) {
+            oracle_event_uniforms(seed, stream_id, event_offset + e, n, u);
+            const double w = one_event(parent_mass, masses, n, parent_p4, u, p4);
+            if (w > w_max) w_max = w;
+        }
+    }
+    uint64_t kept = 0, over = 0;
+    for (uint64_t e = 0; e < ntrials; ++e) {
+        const uint64_t g = event_offset + e;
+        oracle_event_uniforms(seed, stream_id, g, n, u);
+        const double w = one_event(parent_mass, masses, n, parent_p4, u, p4);
+        const double v = oracle_accept_uniform(seed, stream_id, g, n);
+        if (w > w_max) ++over;
+        if (v * w_max < w) {
+            if (kept < ld) {
+                if (out != NULL)
+                    for (int d = 0; d < n; ++d)
+                        for (int mu = 0; mu < 4; ++mu) out[(uint64_t)(4 * d + mu) * ld + kept] = p4[d][mu];
+                if (index != NULL) index[kept] = g;
+            }
+            ++kept;
+        }
+    }
+    counts[0] = kept;
+    counts[1] = over;
+    if (w_max_used != NULL) *w_max_used = w_max;
+    return ORACLE_OK;
+}

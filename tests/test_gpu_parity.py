@@ -121,6 +121,36 @@ def test_integrate_matches_oracle(P, n):
         assert abs(sigma - so) <= FP64_TOL * so + 1e-15 * mo, (nev, sigma, so)
 
 
+@pytest.mark.parametrize("n", [3, 6])
+def test_counter_high_words(P, n):
+    """Events whose global index crosses 2^32 (counter word 1 changes), a seed
+    with both key words non-zero and a large stream id."""
+    _say(f"counter high words N={n}")
+    M, m = _random_masses(n, 3000 + n)
+    seed, sid, off, nev = 0xDEADBEEF12345678, 0x80000005, (1 << 32) - 1000, 5000
+    p4, w, st = _run(P, M, m, nev, seed=seed, stream_id=sid, offset=off)
+    p4o, wo = oracle.generate(M, m, nev, seed=seed, stream_id=sid, event_offset=off)
+    assert_events_close(p4, w, p4o, wo)
+    mo, so = oracle.integrate(M, m, nev, seed=seed, stream_id=sid, event_offset=off)
+    assert rel(st[1], mo) <= FP64_TOL and rel(st[3], so) <= FP64_TOL
+    # chunked across the boundary: the same events
+    p4a, wa, _ = _run(P, M, m, 1000, seed=seed, stream_id=sid, offset=off)
+    p4b, wb, _ = _run(P, M, m, nev - 1000, seed=seed, stream_id=sid, offset=1 << 32)
+    assert np.array_equal(np.concatenate([p4a, p4b], axis=2), p4) and np.array_equal(np.concatenate([wa, wb]), w)
+
+
+def test_binding_allocates_line_aligned_columns(P):
+    _say("binding output layout")
+    M, m = CFG0
+    nev = 1001
+    out, w, _ = P.generate(M, m, nev)
+    assert tuple(out.shape) == (3, 4, nev) and out.stride(1) == P.aligned_ld(nev) and out.stride(1) % 32 == 0
+    assert out.data_ptr() % 128 == 0
+    torch.cuda.synchronize()
+    p4o, wo = oracle.generate(M, m, nev, seed=42)
+    assert_events_close(out.cpu().numpy(), w.cpu().numpy(), p4o, wo)
+
+
 def test_two_body_sigma_is_exactly_zero(P):
     _say("two-body sigma")
     p4, w, st = _run(P, 5.279, [3.097, 0.4937], 70_001)

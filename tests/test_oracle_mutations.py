@@ -33,6 +33,12 @@ MUTATIONS = [
     ("variance scaled", "nsum_add(&s2, d * d);", "nsum_add(&s2, d * d * 1.0000001);"),
     ("last subsystem daughter not boosted", "for (int d = 0; d <= i; ++d) boost(p4[d], eta, gamma);",
      "for (int d = 0; d < i; ++d) boost(p4[d], eta, gamma);"),
+    ("accept uniform from the event's own last call", "(uint32_t)oracle_calls_per_event(n), stream_id };",
+     "(uint32_t)(oracle_calls_per_event(n) - 1), stream_id };"),
+    ("accept test inverted", "if (v * w_max < w) {", "if (v * w_max > w) {"),
+    ("sample maximum not taken", "if (w > w_max) w_max = w;", "if (w > w_max) w_max = w * 0.5;"),
+    ("kept events stored at the trial index", "out[(uint64_t)(4 * d + mu) * ld + kept] = p4[d][mu];",
+     "out[(uint64_t)(4 * d + mu) * ld + e] = p4[d][mu];"),
 ]
 
 

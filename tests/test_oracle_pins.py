@@ -344,6 +344,109 @@ def test_isotropy(oracle_lib):
         assert abs(c2 - 1.0 / 3.0) < 0.01
 
 
+# --------------------------------------------------- unweighted samples ----
+# Hit-or-miss unweighting keeps trial e when v_e * w_max < w_e.  The kept events
+# must be distributed as phase space itself (unit weight): the pins below check
+# the accepted fraction against E[w]/w_max, the kept-event densities against
+# closed forms, and that the kept events are the weighted events of the same
+# index.
+
+def test_accept_uniform_uses_the_first_unused_call(oracle_lib):
+    for n in range(2, 11):
+        words = 2 * (3 * n - 4)  # words the event's own uniforms consume
+        j = oracle_lib.calls_per_event(n)
+        assert 4 * (j - 1) < words <= 4 * j
+        # words 0 and 1 of call j, converted like every other uniform
+        w = oracle_lib.philox4x32_10([77, 5, j, 3], [11, 0])
+        x = ((w[1] << 32) | w[0]) >> 12
+        assert oracle_lib.accept_uniform(11, 3, (5 << 32) | 77, n) == (2 * x + 1) * 2.0 ** -53
+
+
+def test_unweight_two_body_keeps_every_trial(oracle_lib):
+    M, m = 5.279, [3.097, 0.4937]
+    p4, idx, kept, over, used = oracle_lib.unweight(M, m, 3000, seed=9, event_offset=100)
+    assert kept == 3000 and over == 0 and np.array_equal(idx, np.arange(100, 3100, dtype=np.uint64))
+    q4, w = oracle_lib.generate(M, m, 3000, seed=9, event_offset=100)
+    assert used == w[0] and np.array_equal(p4, q4)
+
+
+def test_unweight_massless_three_body_acceptance(oracle_lib):
+    # w = (pi^2/2) M^2 R (1 - R^2) with R uniform: w_max = pi^2 M^2 / (3 sqrt 3), and
+    # the kept fraction is E[w] / w_max = (pi^2 M^2 / 8) / w_max = 3 sqrt(3) / 8.
+    M, n = 1.0, 200_000
+    wmax = math.pi ** 2 * M * M / (3.0 * math.sqrt(3.0)) * (1.0 + 1e-12)
+    p4, idx, kept, over, used = oracle_lib.unweight(M, [0.0, 0.0, 0.0], n, seed=5, w_max=wmax)
+    assert over == 0 and used == wmax
+    p = 3.0 * math.sqrt(3.0) / 8.0
+    assert abs(kept / n - p) < 5.0 * math.sqrt(p * (1.0 - p) / n), (kept / n, p)
+    # kept R = m01 / M has density 4 R (1 - R^2): CDF 2R^2 - R^4
+    r = np.sqrt(np.maximum(_minkowski_sq(p4[0] + p4[1]), 0.0)) / M
+    edges = np.linspace(0.0, 1.0, 21)
+    cnt, _ = np.histogram(r, bins=edges)
+    cdf = 2.0 * edges ** 2 - edges ** 4
+    want = kept * np.diff(cdf)
+    chi2 = float(((cnt - want) ** 2 / want).sum())
+    assert chi2 < 19 + 5.0 * math.sqrt(2.0 * 19), chi2
+
+
+def test_unweighted_dalitz_plot_is_flat(oracle_lib):
+    M, m = CFG0_M, CFG0_MASSES
+    p4, idx, kept, over, used = oracle_lib.unweight(M, m, 300_000, seed=42)
+    s01 = _minkowski_sq(p4[0] + p4[1])
+    s12 = _minkowski_sq(p4[1] + p4[2])
+    lo01, hi01 = (m[0] + m[1]) ** 2, (M - m[2]) ** 2
+    lo12, hi12 = (m[1] + m[2]) ** 2, (M - m[0]) ** 2
+    edges01, edges12 = np.linspace(lo01, hi01, 11), np.linspace(lo12, hi12, 11)
+    H, _, _ = np.histogram2d(s01, s12, bins=[edges01, edges12])
+    area_total = V.dalitz_area(M, *m)
+    chi2, ndf = 0.0, 0
+    for i in range(10):
+        for j in range(10):
+            inside = True
+            for sv in (edges01[i], edges01[i + 1]):
+                a, b = V.dalitz_m12sq_limits(M, *m, sv)
+                if not (a <= edges12[j] and edges12[j + 1] <= b):
+                    inside = False
+            if not inside:
+                continue
+            want = kept * (edges01[i + 1] - edges01[i]) * (edges12[j + 1] - edges12[j]) / area_total
+            chi2 += (H[i, j] - want) ** 2 / want
+            ndf += 1
+    assert ndf >= 15
+    assert chi2 < ndf + 5.0 * math.sqrt(2.0 * ndf), (chi2, ndf)
+
+
+def test_unweighted_isotropy(oracle_lib):
+    masses = [0.2, 0.3, 0.1, 0.4]
+    p4, idx, kept, over, used = oracle_lib.unweight(3.0, masses, 200_000, seed=21)
+    assert kept > 20_000
+    for d in range(4):
+        p = p4[d, 1:]
+        nhat = p / np.linalg.norm(p, axis=0)
+        for k in range(3):
+            assert abs(float(nhat[k].mean())) < 5.0 / math.sqrt(3.0 * kept)
+        assert abs(float((nhat[2] ** 2).mean()) - 1.0 / 3.0) < 5.0 * math.sqrt(4.0 / 45.0 / kept)
+
+
+def test_kept_events_are_the_weighted_events(oracle_lib):
+    M, m, off, n = 4.0, [0.5, 1.0, 0.2, 0.3], 7, 20_000
+    q4, w = oracle_lib.generate(M, m, n, seed=3, stream_id=2, event_offset=off)
+    p4, idx, kept, over, used = oracle_lib.unweight(M, m, n, seed=3, stream_id=2, event_offset=off)
+    assert used == float(w.max()) and over == 0
+    v = np.array([oracle_lib.accept_uniform(3, 2, off + e, len(m)) for e in range(n)])
+    want = np.nonzero(v * used < w)[0]
+    assert kept == len(want) and np.array_equal(idx, (want + off).astype(np.uint64))
+    assert np.array_equal(p4, q4[:, :, want])
+    # a smaller w_max: the trials above it are counted and always kept
+    wm = float(np.median(w))
+    _, idx2, kept2, over2, _ = oracle_lib.unweight(M, m, n, seed=3, stream_id=2, event_offset=off, w_max=wm)
+    assert over2 == int((w > wm).sum())
+    assert np.array_equal(idx2, (np.nonzero(v * wm < w)[0] + off).astype(np.uint64))
+    # capacity smaller than the kept count: the first kept events, full count
+    p4c, idxc, keptc, _, _ = oracle_lib.unweight(M, m, n, seed=3, stream_id=2, event_offset=off, capacity=100)
+    assert keptc == kept and np.array_equal(idxc, idx[:100]) and np.array_equal(p4c, p4[:, :, :100])
+
+
 # --------------------------------------------------- determinism / validation ----
 
 def test_chunking_is_bit_identical(oracle_lib):

@@ -233,6 +233,7 @@ def extras(P, torch, dev, args):
     # integrate-only (no stores): the arithmetic ceiling of the same events
     ms, kms = time_steps(lambda: P.integrate_async(M, m, n1, stats=st), steps, 1, torch)
     ex["cfg1_integrate_only"] = {"events_per_s": n1 / (ms * 1e-3), "kernel_ms": kms}
+    ex["cfg1_unweighted"] = unweighted_extra(P, torch, dev, M, m, n1, out, steps)
     del out, w
     # config 2: six pions at M=10, 5e7 events, FP64 vs mixed
     n2 = max(n1 // 2, 1)
@@ -253,6 +254,25 @@ def extras(P, torch, dev, args):
     if args.serve_seconds > 0:
         ex["cfg4_serving"] = serving_extra(P, args.serve_seconds)
     return ex
+
+
+def unweighted_extra(P, torch, dev, M, m, n, out, steps):
+    """Hit-or-miss unweighted sample of the 1e8 trials: with the sample maximum as
+    the bound (max, count, scan and write passes) and with that bound given
+    (count, scan, write).  Kernel time = the whole launch sequence."""
+    cnt = torch.empty(2, dtype=torch.int64, device=dev)
+    wmo = torch.empty(1, dtype=torch.float64, device=dev)
+    ms0, k0 = time_steps(lambda: P.generate_unweighted(M, m, n, out=out, counts=cnt, w_max_out=wmo), steps, 1,
+                         torch)
+    kept, over = (int(x) for x in cnt.cpu().tolist())
+    w_max = float(wmo.item())
+    ms1, k1 = time_steps(lambda: P.generate_unweighted(M, m, n, w_max=w_max, out=out, counts=cnt, w_max_out=wmo),
+                         steps, 1, torch)
+    bytes_kept = kept * 8 * 4 * len(m)
+    return {"trials": n, "kept": kept, "kept_fraction": kept / n, "w_max": w_max, "over_bound": over,
+            "ms_sample_max": k0, "ms_given_bound": k1, "trials_per_s_given_bound": n / (k1 * 1e-3),
+            "kept_per_s_given_bound": kept / (k1 * 1e-3), "kept_per_s_sample_max": kept / (k0 * 1e-3),
+            "write_GBs_given_bound": bytes_kept / (k1 * 1e-3) / 1e9}
 
 
 def serving_extra(P, seconds):

@@ -1,0 +1,60 @@
+/*
+ * hydra_phsp_unweight.h -- unweighted phase-space samples.
+ *
+ * Sec. 4.2 of arXiv:1711.05683 lists unweighted samples beside the weighted
+ * ones.  This is the hit-or-miss method: trial event g (the weighted event
+ * hydra_phsp_generate produces for the same seed, stream_id and global index
+ * g) is kept when v_g * w_max < w_g, where w_g is its weight and v_g its
+ * acceptance uniform: words 0 and 1 of Philox4x32-10 call j = ceil((3N-4)/2) of
+ * the event's counter stream (the first call its own uniforms do not use),
+ * converted like every other uniform, (2x+1) 2^-53 with x the top 52 bits.
+ * Kept events therefore follow the phase-space density with unit weight.
+ * Conventions, layouts, ownership and error codes are those of hydra_phsp.h.
+ */
+#ifndef HYDRA_PHSP_UNWEIGHT_H
+#define HYDRA_PHSP_UNWEIGHT_H
+
+#include <stdint.h>
+
+#include "hydra_phsp.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Hit-or-miss sample from ntrials weighted trials (global indices event_offset
+ * .. event_offset + ntrials - 1).  Asynchronous on `stream`.
+ *
+ *   parent_mass, masses_host, n_daughters, parent_p4_host, seed, stream_id,
+ *   event_offset  as for hydra_phsp_generate (parent at rest or one broadcast
+ *                 parent four-vector).
+ *   w_max         > 0: the bound (trials with a larger weight are always kept
+ *                 and counted in counts_dev[1]); 0: the largest weight among
+ *                 the trials, found by an extra pass over them.
+ *   p4_out_dev    NULL, or the kept events in trial order, SoA
+ *                 [n_daughters][4][ld] doubles (device).
+ *   ld            capacity in events when p4_out_dev or index_out_dev is given
+ *                 (>= 1); kept events past the capacity are counted but not
+ *                 written.
+ *   index_out_dev NULL, or [ld] uint64 (device): the global index of each kept
+ *                 event, increasing.
+ *   counts_dev    required, 2 uint64 (device): [0] number kept (all of them,
+ *                 also past the capacity), [1] number of trials whose weight
+ *                 exceeded w_max.
+ *   w_max_dev     NULL, or 1 double (device) receiving the bound applied.
+ *
+ * With both outputs NULL only the counts are produced (no kinematics are
+ * computed).  EINVAL for a negative or non-finite w_max, a NULL counts_dev, a
+ * zero capacity with outputs, misaligned pointers or ntrials beyond one
+ * launch ((2^32 - 1) / 256 * 1024 trials); EKINEMATICS as for generate. */
+int hydra_phsp_generate_unweighted(double parent_mass, const double *masses_host, int n_daughters,
+                                   const double *parent_p4_host, uint64_t ntrials, uint64_t seed,
+                                   uint32_t stream_id, uint64_t event_offset, double w_max,
+                                   double *p4_out_dev, uint64_t ld, uint64_t *index_out_dev,
+                                   uint64_t *counts_dev, double *w_max_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYDRA_PHSP_UNWEIGHT_H */

@@ -66,6 +66,8 @@ def _declare(lib):
     lib.hydra_phsp_timing_reset.restype = i
     lib.hydra_phsp_timing_read.argtypes = [dp, c.POINTER(c.c_uint64)]
     lib.hydra_phsp_timing_read.restype = i
+    lib.hydra_phsp_generate_unweighted.argtypes = [d, dp, i, dp, u64, u64, u32, u64, d, vp, u64, vp, vp, vp, vp]
+    lib.hydra_phsp_generate_unweighted.restype = i
 
 
 def lib():
@@ -156,6 +158,50 @@ def generate(parent_mass: float, masses: Sequence[float], nevents: int, *, seed:
     if own_out:
         out = out[:, :, :max(nevents, 1)]
     return out, weights, stats
+
+
+def generate_unweighted(parent_mass: float, masses: Sequence[float], ntrials: int, *, seed: int = 42,
+                        stream_id: int = 0, event_offset: int = 0, w_max: float = 0.0,
+                        parent_p4: Optional[Sequence[float]] = None, capacity: Optional[int] = None,
+                        want_events: bool = True, want_index: bool = False, device=None,
+                        stream: Optional[torch.cuda.Stream] = None, out: Optional[torch.Tensor] = None,
+                        index: Optional[torch.Tensor] = None, counts: Optional[torch.Tensor] = None,
+                        w_max_out: Optional[torch.Tensor] = None):
+    """Hit-or-miss unweighted sample from ``ntrials`` weighted trials (asynchronous).
+
+    Trial g is kept when v_g * w_max < w_g (``w_max`` = 0: the largest trial
+    weight).  Returns ``(p4, index, counts, w_max_used)``: ``p4`` an
+    ``[N, 4, capacity]`` float64 buffer whose first ``counts[0]`` columns are the
+    kept events in trial order (None unless ``want_events``), ``index`` their
+    global indices (int64, None unless ``want_index``), ``counts`` a device int64
+    pair (kept, trials with w > w_max) and ``w_max_used`` a device scalar.  Read
+    ``counts`` after synchronizing the stream.  ``out``, ``index``, ``counts`` and
+    ``w_max_out`` may be given (contiguous, of those shapes and dtypes) to reuse
+    buffers; ``capacity`` is then ``out``'s (or ``index``'s) last dimension."""
+    m, n = _masses(masses)
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    cap = aligned_ld(ntrials) if capacity is None else int(capacity)
+    if out is None and want_events:
+        out = torch.empty((n, 4, max(cap, 1)), dtype=torch.float64, device=dev)
+    if out is not None and (out.dtype != torch.float64 or not out.is_contiguous() or out.dim() != 3
+                            or tuple(out.shape[:2]) != (n, 4)):
+        raise ValueError(f"out must be a contiguous [{n}, 4, capacity] float64 tensor")
+    idx = index
+    if idx is None and want_index:
+        idx = torch.empty(out.shape[2] if out is not None else max(cap, 1), dtype=torch.int64, device=dev)
+    if out is not None and idx is not None and idx.shape[0] != out.shape[2]:
+        raise ValueError("index must have one entry per output column")
+    if counts is None:
+        counts = torch.empty(2, dtype=torch.int64, device=dev)
+    wm = w_max_out if w_max_out is not None else torch.empty(1, dtype=torch.float64, device=dev)
+    p4h = None
+    if parent_p4 is not None:
+        p4h = (ctypes.c_double * 4)(*[float(x) for x in parent_p4])
+    ld = out.shape[2] if out is not None else (idx.shape[0] if idx is not None else 0)
+    _check(lib().hydra_phsp_generate_unweighted(parent_mass, m, n, p4h, ntrials, seed, stream_id, event_offset,
+                                                float(w_max), _dptr(out), ld, _dptr(idx), _dptr(counts),
+                                                _dptr(wm), _stream_handle(stream)))
+    return out, idx, counts, wm
 
 
 def integrate_async(parent_mass: float, masses: Sequence[float], nevents: int, *, seed: int = 42,

@@ -434,8 +434,9 @@ int hydra_phsp_abi_version(void) { return HYDRA_PHSP_ABI_VERSION; }
 
 int hydra_phsp_release(void) {
     const int a = release_batch_slots();
-    const int b = release_workspaces();
-    return a != HYDRA_PHSP_OK ? a : b;
+    const int b = release_workspaces(); // synchronizes the device first
+    const int c = release_unweight_workspaces();
+    return a != HYDRA_PHSP_OK ? a : (b != HYDRA_PHSP_OK ? b : c);
 }
 
 int hydra_phsp_set_events_per_thread(int path, int ept) {

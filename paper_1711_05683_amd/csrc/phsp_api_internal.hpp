@@ -24,6 +24,7 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
 // after the process-wide override.
 int single_channel_ept(int mode, int n, int pmode);
 int release_workspaces();
+int release_unweight_workspaces();
 int release_batch_slots();
 // The device's (cos, sin) table used by the FP64 kernels (created on first use).
 int trig_table(const double2** out);

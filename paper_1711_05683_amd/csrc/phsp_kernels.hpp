@@ -80,24 +80,41 @@ __device__ __forceinline__ Frame load_parent_frame(const double* parent, uint64_
     return f;
 }
 
-// One event end to end: draws, levels, kinematics, lab boost, stores.  The event
-// is base + off: `base` (the block's first event) is wave-uniform, so every
-// column address is a scalar base plus the lane's 32-bit offset (PIN keeps the
-// column bases in scalar registers).  `tab` is the block's LDS copy of the
-// trigonometric table (FP64 generate only).
-template <int N, int PMODE, int MODE, bool PIN = (N <= 5)>
-__device__ __forceinline__ double run_event(const KArgs& a, uint64_t base, uint32_t off, const double2* tab) {
+// Counter stream of event base + off.
+__device__ __forceinline__ EventRng event_rng(const KArgs& a, uint64_t base, uint32_t off) {
     const uint64_t g = a.event_offset + base + off;
-    const EventRng rng{(uint32_t)g, (uint32_t)(g >> 32), a.sid, a.k0, a.k1};
+    return EventRng{(uint32_t)g, (uint32_t)(g >> 32), a.sid, a.k0, a.k1};
+}
+
+// One event's draws, levels, kinematics and lab boost, without stores: fills ev
+// (unless MODE is kIntegrate) and returns the weight.  Every kernel that needs an
+// event calls this, so the same event is bit-identical in all of them.
+template <int N, int PMODE, int MODE, typename R>
+__device__ __forceinline__ double compute_event(const KArgs& a, uint64_t base, uint32_t off, const double2* tab,
+                                                Event<N, R>& ev) {
+    const EventRng rng = event_rng(a, base, off);
     MassDraws<N> d;
     draw_masses<N>(d, rng);
-    using R = typename std::conditional<MODE == kMixed, float, double>::type;
-    Event<N, R> ev;
     const double w = event_levels<N, R, MODE != kIntegrate>(a.ch, rng, d, tab, ev);
     if constexpr (MODE != kIntegrate) {
         if constexpr (PMODE == kBroadcast) boost_to_lab<N, R>(ev, a.frame);
         if constexpr (PMODE == kPerEvent)
             boost_to_lab<N, R>(ev, load_parent_frame(a.parent + base, a.ld_parent, off, a.ch.M, a.inv_M));
+    }
+    return w;
+}
+
+// One event end to end: compute_event, then the stores.  The event is base +
+// off: `base` (the block's first event) is wave-uniform, so every column address
+// is a scalar base plus the lane's 32-bit offset (PIN keeps the column bases in
+// scalar registers).  `tab` is the block's LDS copy of the trigonometric table
+// (FP64 generate only).
+template <int N, int PMODE, int MODE, bool PIN = (N <= 5)>
+__device__ __forceinline__ double run_event(const KArgs& a, uint64_t base, uint32_t off, const double2* tab) {
+    using R = typename std::conditional<MODE == kMixed, float, double>::type;
+    Event<N, R> ev;
+    const double w = compute_event<N, PMODE, MODE, R>(a, base, off, tab, ev);
+    if constexpr (MODE != kIntegrate) {
         R* out = static_cast<R*>(a.out) + base;
         const uint64_t ld = a.ld;
         const uint32_t boff = off * (uint32_t)sizeof(R);

@@ -1,0 +1,258 @@
+// phsp_unweight.hpp -- kernels of the unweighted (hit-or-miss) path.
+//
+// Trial event e of a launch is the weighted event the generator produces for
+// the same counter; it is kept when v * w_max < w, with v the acceptance
+// uniform of the event (words 0 and 1 of the first Philox call its own uniforms
+// do not use).  Kept events are written in trial order.  The passes, each over
+// the same blocks of kBlock * kUnwEpt trials:
+//   max    (only when no bound is given) the largest weight per block;
+//   count  kept and over-bound trials per block (weights only, no kinematics);
+//   write  the full kinematics again (counter-based draws make them identical),
+//          each kept event stored at its block's offset plus its rank.
+// Between count and write the per-block counts are scanned (phsp_unweight_api.hip).
+#pragma once
+
+#include "phsp_kernels.hpp"
+
+namespace hphsp {
+
+constexpr int kUnwEpt = 4; // trials per lane and block step; a block covers 1024 trials
+
+// Philox calls of one event's own uniforms: ceil((3N - 4) / 2).
+template <int N>
+constexpr uint32_t kEventCalls = (uint32_t)((3 * N - 4 + 1) / 2);
+
+template <int N>
+__device__ __forceinline__ double accept_uniform(const KArgs& a, uint64_t base, uint32_t off) {
+    double v, unused;
+    event_rng(a, base, off).call(kEventCalls<N>, v, unused);
+    return v;
+}
+
+struct UnwArgs {
+    KArgs a;                   // channel, counters, parent frame, trig table (a.out unused)
+    const double* w_max;       // device scalar: the bound applied
+    double* block_max;         // [blocks] largest weight per block (max pass)
+    uint2* counts;             // [blocks] (kept, weight > w_max) per block
+    const uint64_t* offsets;   // [blocks] kept events before the block
+    double* out;               // kept events, [N][4][ld]
+    uint64_t ld;               // capacity in events
+    uint64_t* index;           // NULL, or [ld] global index of each kept event
+};
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Largest weight of the block's trials (weights are >= 0).
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_unw_max(const UnwArgs u) {
+    __shared__ double sm[kWaves];
+    const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * kUnwEpt);
+    double m = 0.0;
+#pragma unroll
+    for (int k = 0; k < kUnwEpt; ++k) {
+        const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
+        if (base + off < u.a.nevents) {
+            Event<N, double> ev;
+            m = fmax(m, compute_event<N, kAtRest, kIntegrate, double>(u.a, base, off, nullptr, ev));
+        }
+    }
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = sm[0];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) r = fmax(r, sm[w]);
+        u.block_max[blockIdx.x] = r;
+    }
+}
+
+// Kept and over-bound trials of the block (the weights only).
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_unw_count(const UnwArgs u) {
+    __shared__ uint32_t sk[kWaves], so[kWaves];
+    const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * kUnwEpt);
+    const double wmax = *u.w_max;
+    uint32_t kept = 0, over = 0;
+#pragma unroll
+    for (int k = 0; k < kUnwEpt; ++k) {
+        const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
+        if (base + off < u.a.nevents) {
+            Event<N, double> ev;
+            const double w = compute_event<N, kAtRest, kIntegrate, double>(u.a, base, off, nullptr, ev);
+            const double v = accept_uniform<N>(u.a, base, off);
+            kept += (v * wmax < w) ? 1u : 0u;
+            over += (w > wmax) ? 1u : 0u;
+        }
+    }
+    kept = wave_sum_u32(kept);
+    over = wave_sum_u32(over);
+    if ((threadIdx.x & 63) == 0) {
+        sk[threadIdx.x >> 6] = kept;
+        so[threadIdx.x >> 6] = over;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0, b = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            a += sk[w];
+            b += so[w];
+        }
+        u.counts[blockIdx.x] = make_uint2(a, b);
+    }
+}
+
+// Elements of one 128-byte line of FP64 (the store granule the write pass
+// aligns to).
+constexpr int kLineElems = 16;
+
+// A step's store window: positions [line0, end) with end = next + total, where
+// line0 starts the line holding `next`; the first c positions are the carried
+// values, the first `full` positions make whole lines (stored now) and the last
+// `tail` are carried on.  Thread t stores window elements t and t + kBlock
+// (positions pos0 and pos0 + kBlock) when ok0 / ok1: inside the whole lines,
+// owned by the block (>= first) and within the capacity ld.  The same window
+// serves every column.
+struct StepWindow {
+    uint32_t c, full, tail;
+    uint64_t pos0;
+    bool ok0, ok1;
+};
+
+__device__ __forceinline__ StepWindow step_window(uint64_t first, uint64_t next, uint32_t total, uint64_t ld) {
+    StepWindow w;
+    const uint64_t line0 = next - next % kLineElems;
+    const uint64_t end = next + total;
+    w.c = (uint32_t)(next - line0);
+    w.full = (uint32_t)(end - end % kLineElems - line0);
+    w.tail = (uint32_t)(end - line0) - w.full;
+    w.pos0 = line0 + threadIdx.x;
+    const uint64_t pos1 = w.pos0 + kBlock;
+    w.ok0 = threadIdx.x < w.full && w.pos0 >= first && w.pos0 < ld;
+    w.ok1 = threadIdx.x + kBlock < w.full && pos1 >= first && pos1 < ld;
+    return w;
+}
+
+// Stage the values v[g] (g < G columns) of the step's kept trials (slot = rank
+// among them) behind the columns' carries, store the window's whole lines and
+// keep each tail (the start of the next line) as the new carry.  buf holds G
+// rows of kLineElems + kBlock values, carry G rows of kLineElems.  Two barriers.
+template <int G, typename T>
+__device__ __forceinline__ void stage_and_store(const T (&v)[G], bool keep, uint32_t slot, const StepWindow& w,
+                                                T (*buf)[kLineElems + kBlock], T (*carry)[kLineElems],
+                                                T* const (&col)[G]) {
+    const uint32_t b0 = kLineElems - w.c + threadIdx.x; // buf index of window element t
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        if (threadIdx.x < w.c) buf[g][kLineElems - w.c + threadIdx.x] = carry[g][threadIdx.x];
+        if (keep) buf[g][kLineElems + slot] = v[g];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        if (w.ok0) __builtin_nontemporal_store(buf[g][b0], col[g] + w.pos0);
+        if (w.ok1) __builtin_nontemporal_store(buf[g][b0 + kBlock], col[g] + w.pos0 + kBlock);
+        if (threadIdx.x < w.tail) carry[g][threadIdx.x] = buf[g][kLineElems - w.c + w.full + threadIdx.x];
+    }
+    __syncthreads(); // stores and carries have read buf before it is refilled
+}
+
+// The block's last carry: the partial line at the end of its run.
+template <typename T>
+__device__ __forceinline__ void flush_carry(const T* carry, T* col, uint64_t ld, uint64_t first, uint64_t end) {
+    const uint64_t line0 = end - end % kLineElems;
+    const uint64_t pos = line0 + threadIdx.x;
+    if (threadIdx.x < end - line0 && pos >= first && pos < ld) __builtin_nontemporal_store(carry[threadIdx.x], col + pos);
+}
+
+// Full kinematics of every trial, kept ones stored in trial order: step k of
+// the block holds trials base + k*kBlock + t, so a kept trial's position is the
+// block's offset, plus the kept trials of earlier steps, of earlier waves in
+// this step, and of lower lanes in this wave.  Each column is written through
+// LDS in whole 128-byte lines: a step's kept values are appended to the values
+// carried over from the previous step, every completed line is stored by
+// consecutive threads, and the incomplete tail is carried on; only the two lines
+// at the ends of the block's run are written partially.  (Runs that start
+// mid-line would otherwise turn most stores into partial-line writes.)
+template <int N, int PMODE>
+__global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
+    __shared__ double2 tab[kTrigSize];
+    __shared__ double buf[4][kLineElems + kBlock];
+    __shared__ double carry[4 * N][kLineElems];
+    __shared__ uint64_t ibuf[1][kLineElems + kBlock];
+    __shared__ uint64_t icarry[1][kLineElems];
+    __shared__ uint32_t sk[kWaves];
+    load_trig(tab, u.a.trig);
+    const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * kUnwEpt);
+    const double wmax = *u.w_max;
+    const uint64_t first = u.offsets[blockIdx.x];
+    uint64_t next = first;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 0; k < kUnwEpt; ++k) {
+        const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
+        bool keep = false;
+        Event<N, double> ev;
+        if (base + off < u.a.nevents) {
+            const double w = compute_event<N, PMODE, kFp64, double>(u.a, base, off, tab, ev);
+            keep = accept_uniform<N>(u.a, base, off) * wmax < w;
+        }
+        const uint64_t mask = __ballot(keep);
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        if (lane == 0) sk[wave] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            before += (w < wave) ? sk[w] : 0u;
+            total += sk[w];
+        }
+        const uint32_t slot = before + rank;
+        const StepWindow win = step_window(first, next, total, u.ld);
+        if (u.index != nullptr) {
+            const uint64_t g[1] = {u.a.event_offset + base + off};
+            uint64_t* const icol[1] = {u.index};
+            stage_and_store<1, uint64_t>(g, keep, slot, win, ibuf, icarry, icol);
+        }
+        if (u.out != nullptr) {
+#pragma unroll
+            for (int d = 0; d < N; ++d) {
+                const double v[4] = {ev.e[d], ev.x[d], ev.y[d], ev.z[d]};
+                double* const cols[4] = {u.out + (uint64_t)(4 * d + 0) * u.ld, u.out + (uint64_t)(4 * d + 1) * u.ld,
+                                         u.out + (uint64_t)(4 * d + 2) * u.ld, u.out + (uint64_t)(4 * d + 3) * u.ld};
+                stage_and_store<4, double>(v, keep, slot, win, buf, &carry[4 * d], cols);
+            }
+        }
+        next += total; // sk was read before the staging barriers, so the next step may overwrite it
+    }
+    if (u.index != nullptr) flush_carry<uint64_t>(icarry[0], u.index, u.ld, first, next);
+    if (u.out != nullptr)
+        for (int c = 0; c < 4 * N; ++c) flush_carry<double>(carry[c], u.out + (uint64_t)c * u.ld, u.ld, first, next);
+}
+
+struct UnwLaunch {
+    UnwArgs u;
+    uint64_t blocks;
+    int pmode; // kAtRest or kBroadcast (write pass)
+};
+
+// Per-N launchers, defined in the per-N instantiation units.
+template <int N>
+hipError_t launch_unw_max(const UnwLaunch& L, hipStream_t s);
+template <int N>
+hipError_t launch_unw_count(const UnwLaunch& L, hipStream_t s);
+template <int N>
+hipError_t launch_unw_write(const UnwLaunch& L, hipStream_t s);
+
+} // namespace hphsp

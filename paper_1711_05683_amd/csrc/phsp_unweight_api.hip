@@ -1,0 +1,297 @@
+// phsp_unweight_api.hip -- C ABI of the unweighted (hit-or-miss) path: the
+// per-stream workspace, the scan of the per-block counts and the launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "hydra_phsp.h"
+#include "hydra_phsp_unweight.h"
+#include "phsp_api_internal.hpp"
+#include "phsp_unweight.hpp"
+
+namespace hphsp {
+
+constexpr int kScanBlock = 256;   // counts scanned per block of the partial scan
+constexpr int kScanTop = 1024;    // threads of the single-block scan of the partial sums
+
+// Largest weight over the per-block maxima (max is exact in any order).
+__global__ __launch_bounds__(kScanTop) void k_unw_max_final(const double* __restrict__ block_max,
+                                                            uint64_t blocks, double* __restrict__ w_max) {
+    __shared__ double sm[kScanTop / 64];
+    double m = 0.0;
+    for (uint64_t i = threadIdx.x; i < blocks; i += kScanTop) m = fmax(m, block_max[i]);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int w = 0; w < kScanTop / 64; ++w) r = fmax(r, sm[w]);
+        *w_max = r;
+    }
+}
+
+__global__ void k_unw_set(double* __restrict__ w_max, double value) {
+    if (threadIdx.x == 0) *w_max = value;
+}
+
+// Inclusive scan of one value per thread across a block of BLOCK threads
+// (wave shuffles, then the wave totals through LDS).
+template <int BLOCK>
+__device__ __forceinline__ uint64_t block_inclusive_scan(uint64_t v, uint64_t* sm) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    if (lane == 63) sm[wave] = v;
+    __syncthreads();
+    uint64_t add = 0;
+    for (int w = 0; w < wave; ++w) add += sm[w];
+    __syncthreads();
+    return v + add;
+}
+
+// Stage 1: kept count of each group of kScanBlock blocks.
+__global__ __launch_bounds__(kScanBlock) void k_unw_scan_partial(const uint2* __restrict__ counts, uint64_t blocks,
+                                                                 uint64_t* __restrict__ sums) {
+    __shared__ uint64_t sm[kScanBlock / 64];
+    const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const uint64_t v = i < blocks ? counts[i].x : 0u;
+    const uint64_t inc = block_inclusive_scan<kScanBlock>(v, sm);
+    if (threadIdx.x == kScanBlock - 1) sums[blockIdx.x] = inc;
+}
+
+// Stage 2 (one block): exclusive prefix of the group sums, in place, and the
+// totals (kept, over-bound) into the caller's counts; the bound applied into the
+// caller's w_max output when asked.
+__global__ __launch_bounds__(kScanTop) void k_unw_scan_top(uint64_t* __restrict__ sums, uint64_t groups,
+                                                           const uint2* __restrict__ counts, uint64_t blocks,
+                                                           uint64_t* __restrict__ totals,
+                                                           const double* __restrict__ w_max,
+                                                           double* __restrict__ w_max_out) {
+    __shared__ uint64_t sm[kScanTop / 64];
+    __shared__ uint64_t last;
+    uint64_t carry = 0;
+    for (uint64_t b0 = 0; b0 < groups; b0 += kScanTop) {
+        const uint64_t i = b0 + threadIdx.x;
+        const uint64_t v = i < groups ? sums[i] : 0u;
+        const uint64_t inc = block_inclusive_scan<kScanTop>(v, sm);
+        if (i < groups) sums[i] = carry + inc - v;
+        if (threadIdx.x == kScanTop - 1) last = inc; // this chunk's total
+        __syncthreads();
+        carry += last;
+        __syncthreads();
+    }
+    // over-bound trials: a plain sum (order-free for integers)
+    uint64_t over = 0;
+    for (uint64_t i = threadIdx.x; i < blocks; i += kScanTop) over += counts[i].y;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) over += __shfl_xor(over, off, 64);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = over;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t o = 0;
+        for (int w = 0; w < kScanTop / 64; ++w) o += sm[w];
+        totals[0] = carry;
+        totals[1] = o;
+        if (w_max_out != nullptr) *w_max_out = *w_max;
+    }
+}
+
+// Stage 3: each block's offset = its group's prefix + the kept counts of the
+// earlier blocks of the group.
+__global__ __launch_bounds__(kScanBlock) void k_unw_scan_finish(const uint2* __restrict__ counts, uint64_t blocks,
+                                                                const uint64_t* __restrict__ sums,
+                                                                uint64_t* __restrict__ offsets) {
+    __shared__ uint64_t sm[kScanBlock / 64];
+    const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const uint64_t v = i < blocks ? counts[i].x : 0u;
+    const uint64_t inc = block_inclusive_scan<kScanBlock>(v, sm);
+    if (i < blocks) offsets[i] = sums[blockIdx.x] + inc - v;
+}
+
+namespace {
+
+struct UnwWorkspace {
+    double* block_max = nullptr;
+    uint2* counts = nullptr;
+    uint64_t* offsets = nullptr;
+    uint64_t* sums = nullptr;
+    double* w_max = nullptr;
+    uint64_t capacity = 0; // blocks
+};
+
+std::mutex g_unw_mu;
+std::map<std::pair<int, hipStream_t>, UnwWorkspace> g_unw_ws;
+
+void free_ws(UnwWorkspace& w) {
+    if (w.block_max) (void)hipFree(w.block_max);
+    if (w.counts) (void)hipFree(w.counts);
+    if (w.offsets) (void)hipFree(w.offsets);
+    if (w.sums) (void)hipFree(w.sums);
+    if (w.w_max) (void)hipFree(w.w_max);
+    w = UnwWorkspace{};
+}
+
+int unw_workspace(hipStream_t stream, uint64_t blocks, UnwWorkspace** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_unw_mu);
+    UnwWorkspace& w = g_unw_ws[std::make_pair(dev, stream)];
+    if (w.w_max == nullptr || blocks > w.capacity) {
+        uint64_t cap = w.capacity ? w.capacity : 4096;
+        while (cap < blocks) cap *= 2;
+        free_ws(w); // hipFree waits for the device, so no queued kernel still uses it
+        const uint64_t groups = (cap + kScanBlock - 1) / kScanBlock;
+        bool ok = hipMalloc(&w.block_max, sizeof(double) * cap) == hipSuccess &&
+                  hipMalloc(&w.counts, sizeof(uint2) * cap) == hipSuccess &&
+                  hipMalloc(&w.offsets, sizeof(uint64_t) * cap) == hipSuccess &&
+                  hipMalloc(&w.sums, sizeof(uint64_t) * groups) == hipSuccess &&
+                  hipMalloc(&w.w_max, sizeof(double)) == hipSuccess;
+        if (!ok) {
+            free_ws(w);
+            return fail(HYDRA_PHSP_ENOMEM, "unweighting workspace allocation failed");
+        }
+        w.capacity = cap;
+    }
+    *out = &w;
+    return HYDRA_PHSP_OK;
+}
+
+template <int N>
+hipError_t launch_pass(int pass, const UnwLaunch& L, hipStream_t s) {
+    switch (pass) {
+    case 0: return launch_unw_max<N>(L, s);
+    case 1: return launch_unw_count<N>(L, s);
+    default: return launch_unw_write<N>(L, s);
+    }
+}
+
+hipError_t launch_pass_n(int n, int pass, const UnwLaunch& L, hipStream_t s) {
+    switch (n) {
+    case 2: return launch_pass<2>(pass, L, s);
+    case 3: return launch_pass<3>(pass, L, s);
+    case 4: return launch_pass<4>(pass, L, s);
+    case 5: return launch_pass<5>(pass, L, s);
+    case 6: return launch_pass<6>(pass, L, s);
+    case 7: return launch_pass<7>(pass, L, s);
+    case 8: return launch_pass<8>(pass, L, s);
+    case 9: return launch_pass<9>(pass, L, s);
+    case 10: return launch_pass<10>(pass, L, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+} // namespace
+
+int release_unweight_workspaces() {
+    std::lock_guard<std::mutex> lock(g_unw_mu);
+    for (auto& kv : g_unw_ws) free_ws(kv.second);
+    g_unw_ws.clear();
+    return HYDRA_PHSP_OK;
+}
+
+} // namespace hphsp
+
+using namespace hphsp;
+
+extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* masses_host, int n_daughters,
+                                              const double* parent_p4_host, uint64_t ntrials, uint64_t seed,
+                                              uint32_t stream_id, uint64_t event_offset, double w_max,
+                                              double* p4_out_dev, uint64_t ld, uint64_t* index_out_dev,
+                                              uint64_t* counts_dev, double* w_max_dev, void* stream) {
+    Channel ch;
+    int st = make_channel(parent_mass, masses_host, n_daughters, &ch);
+    if (st != HYDRA_PHSP_OK) return st;
+    if (!(w_max >= 0.0) || w_max > 1.7976931348623157e308)
+        return fail(HYDRA_PHSP_EINVAL, "w_max must be finite and >= 0 (0: the largest trial weight)");
+    if (counts_dev == nullptr) return fail(HYDRA_PHSP_EINVAL, "counts_dev is required");
+    if ((p4_out_dev != nullptr || index_out_dev != nullptr) && ld == 0)
+        return fail(HYDRA_PHSP_EINVAL, "ld (the capacity in events) must be >= 1 when outputs are given");
+    if ((uintptr_t)p4_out_dev % sizeof(double) != 0 || (uintptr_t)index_out_dev % sizeof(uint64_t) != 0 ||
+        (uintptr_t)counts_dev % sizeof(uint64_t) != 0 || (uintptr_t)w_max_dev % sizeof(double) != 0)
+        return fail(HYDRA_PHSP_EINVAL, "device pointers must be aligned to their element size");
+    Frame frame;
+    std::memset(&frame, 0, sizeof(frame));
+    int pmode = kAtRest;
+    if (parent_p4_host != nullptr) {
+        st = make_frame(parent_mass, parent_p4_host, &frame);
+        if (st != HYDRA_PHSP_OK) return st;
+        pmode = kBroadcast;
+    }
+    const uint64_t span = (uint64_t)kBlock * (uint64_t)kUnwEpt;
+    const uint64_t blocks = (ntrials + span - 1) / span;
+    if (blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
+        return fail(HYDRA_PHSP_EINVAL, "ntrials too large for one launch (more than 2^32 - 1 threads)");
+
+    hipStream_t s = (hipStream_t)stream;
+    UnwWorkspace* ws = nullptr;
+    st = unw_workspace(s, std::max<uint64_t>(blocks, 1), &ws);
+    if (st != HYDRA_PHSP_OK) return st;
+    const double2* trig = nullptr;
+    st = trig_table(&trig);
+    if (st != HYDRA_PHSP_OK) return st;
+
+    UnwLaunch L;
+    std::memset(&L, 0, sizeof(L));
+    L.u.a.ch = ch;
+    L.u.a.frame = frame;
+    L.u.a.inv_M = 1.0 / ch.M;
+    L.u.a.nevents = ntrials;
+    L.u.a.event_offset = event_offset;
+    L.u.a.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    L.u.a.k1 = (uint32_t)(seed >> 32);
+    L.u.a.sid = stream_id;
+    L.u.a.trig = trig;
+    L.u.w_max = ws->w_max;
+    L.u.block_max = ws->block_max;
+    L.u.counts = ws->counts;
+    L.u.offsets = ws->offsets;
+    L.u.out = p4_out_dev;
+    L.u.ld = ld;
+    L.u.index = index_out_dev;
+    L.blocks = blocks;
+    L.pmode = pmode;
+
+    const long slot = timing_begin(s);
+    hipError_t e = hipSuccess;
+    if (w_max == 0.0) {
+        if (blocks > 0) e = launch_pass_n(n_daughters, 0, L, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_unw_max_final, dim3(1), dim3(kScanTop), 0, s, (const double*)ws->block_max, blocks,
+                               ws->w_max);
+            e = hipGetLastError();
+        }
+    } else {
+        hipLaunchKernelGGL(k_unw_set, dim3(1), dim3(64), 0, s, ws->w_max, w_max);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && blocks > 0) e = launch_pass_n(n_daughters, 1, L, s);
+    const uint64_t groups = (blocks + kScanBlock - 1) / kScanBlock;
+    if (e == hipSuccess && groups > 0) {
+        hipLaunchKernelGGL(k_unw_scan_partial, dim3((unsigned)groups), dim3(kScanBlock), 0, s,
+                           (const uint2*)ws->counts, blocks, ws->sums);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_unw_scan_top, dim3(1), dim3(kScanTop), 0, s, ws->sums, groups, (const uint2*)ws->counts,
+                           blocks, counts_dev, (const double*)ws->w_max, w_max_dev);
+        e = hipGetLastError();
+    }
+    const bool outputs = p4_out_dev != nullptr || index_out_dev != nullptr;
+    if (e == hipSuccess && groups > 0 && outputs) {
+        hipLaunchKernelGGL(k_unw_scan_finish, dim3((unsigned)groups), dim3(kScanBlock), 0, s, (const uint2*)ws->counts,
+                           blocks, (const uint64_t*)ws->sums, ws->offsets);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && blocks > 0 && outputs) e = launch_pass_n(n_daughters, 2, L, s);
+    timing_end(s, slot);
+    if (e != hipSuccess) return fail_hip(e, "unweighting kernel launch");
+    return HYDRA_PHSP_OK;
+}

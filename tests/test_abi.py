@@ -185,3 +185,27 @@ def test_batch_validation_names_bad_channel(P):
     assert P.lib().hydra_phsp_batch_run(arr, 0, None, None, ctypes.byref(idx)) == P.EINVAL
     for bad_t in (P._tuning(schedule=3), P._tuning(schedule=-1), P._tuning(grid_per_cu=65)):
         assert P.lib().hydra_phsp_batch_run(arr, 1, ctypes.byref(bad_t), None, ctypes.byref(idx)) == P.EINVAL
+
+
+def test_unweighted_validation(P):
+    m, n = P._masses([1.0, 1.0, 0.5])
+    f = P.lib().hydra_phsp_generate_unweighted
+    cnt, out, idx = ctypes.c_void_p(64), ctypes.c_void_p(128), ctypes.c_void_p(256)
+
+    def call(M=5.0, w_max=0.0, out=out, ld=10, idx=None, counts=cnt, parent=None, ntrials=100, mm=m, nn=n):
+        ph = None if parent is None else (ctypes.c_double * 4)(*parent)
+        return f(M, mm, nn, ph, ntrials, 1, 0, 0, w_max, out, ld, idx, counts, None, None)
+
+    assert call(w_max=-1.0) == P.EINVAL
+    assert call(w_max=float("nan")) == P.EINVAL
+    assert call(w_max=float("inf")) == P.EINVAL
+    assert call(counts=None) == P.EINVAL
+    assert "counts_dev" in P.lib().hydra_phsp_last_error().decode()
+    assert call(ld=0) == P.EINVAL
+    assert call(out=None, idx=idx, ld=0) == P.EINVAL
+    assert call(out=ctypes.c_void_p(132)) == P.EINVAL
+    assert call(counts=ctypes.c_void_p(68)) == P.EINVAL
+    assert call(M=2.0) == P.EKINEMATICS
+    assert call(parent=[5.0, 1.0, 0.0, 0.0]) == P.EINVAL  # parent mass is not M
+    m1, n1 = P._masses([1.0])
+    assert call(mm=m1, nn=n1) == P.EINVAL

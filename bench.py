@@ -234,6 +234,7 @@ def extras(P, torch, dev, args):
     ms, kms = time_steps(lambda: P.integrate_async(M, m, n1, stats=st), steps, 1, torch)
     ex["cfg1_integrate_only"] = {"events_per_s": n1 / (ms * 1e-3), "kernel_ms": kms}
     ex["cfg1_unweighted"] = unweighted_extra(P, torch, dev, M, m, n1, out, steps)
+    ex["cfg1_sequential"] = sequential_extra(P, torch, dev, M, m, n1, out, w, st, steps)
     del out, w
     # config 2: six pions at M=10, 5e7 events, FP64 vs mixed
     n2 = max(n1 // 2, 1)
@@ -254,6 +255,31 @@ def extras(P, torch, dev, args):
     if args.serve_seconds > 0:
         ex["cfg4_serving"] = serving_extra(P, args.serve_seconds)
     return ex
+
+
+def sequential_extra(P, torch, dev, M, m, n, out, w, st, steps):
+    """Sequential decays: each event's daughter 0 (mass 3.097, read in place from
+    the first output) decays to mu+ mu- in a second call on another stream id.
+    Stage 2 reads 32 B and writes 72 B per event."""
+    mmu = 0.1056583755
+    out2 = torch.empty((2, 4, n), dtype=torch.float64, device=dev)
+    w2 = torch.empty(n, dtype=torch.float64, device=dev)
+    st2 = torch.empty(4, dtype=torch.float64, device=dev)
+
+    def stage2():
+        P.generate(m[0], [mmu, mmu], n, seed=42, stream_id=1, parent_dev=out[0], out=out2, weights=w2, stats=st2)
+
+    def chain():
+        P.generate(M, m, n, seed=42, out=out, weights=w, stats=st)
+        stage2()
+
+    chain()
+    ms2, k2 = time_steps(stage2, steps, 1, torch)
+    msc, _ = time_steps(chain, steps, 1, torch)
+    del out2, w2
+    return {"decay": "5.279 -> (3.097 -> mu mu, 0.4937, 0.13957)", "stage2_kernel_ms": k2,
+            "stage2_total_GBs": 104 * n / (k2 * 1e-3) / 1e9, "chain_ms_per_step": msc,
+            "chain_events_per_s": n / (msc * 1e-3)}
 
 
 def unweighted_extra(P, torch, dev, M, m, n, out, steps):

@@ -84,6 +84,11 @@ enum {
  *                    decay uses M and each parent only for its boost, so every
  *                    parent's invariant mass must equal M.  At most one of
  *                    parent_p4_host / parent_p4_dev may be non-NULL.
+ *                    Sequential decays (sec. 4.2): daughter d of an earlier
+ *                    FP64 call is p4_out_dev + 4*d*ld of that call with
+ *                    ld_parent = its ld, read in place, with M = its mass and
+ *                    another stream_id (or seed) so the two stages draw
+ *                    independent uniforms.
  *   nevents          number of events (0 is a no-op that still writes stats).
  *   seed, stream_id  Philox key and counter word 3.
  *   event_offset     global index of the first event.

@@ -76,6 +76,10 @@ def _load():
                                     ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, dp, ctypes.c_uint64,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
     lib.oracle_unweight.restype = ctypes.c_int
+    lib.oracle_model_integrate.argtypes = [ctypes.c_double, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp,
+                                           ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, dp,
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.oracle_model_integrate.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -197,3 +201,26 @@ def unweight(parent_mass, masses, ntrials, seed=42, stream_id=0, event_offset=0,
     k = min(kept, cap)
     p4 = None if out is None else out[:, :, :k]
     return p4, idx[:k], kept, over, used.value
+
+
+def model_integrate(parent_mass, masses, nevents, resonances=(), seed=42, stream_id=0, event_offset=0,
+                    want_values=False):
+    """Integral of |A|^2 over phase space (parent at rest), |A|^2 the product of
+    relativistic Breit-Wigner intensities 1/((M^2 - s_ij)^2 + M^2 G^2) given as
+    (i, j, M, G) tuples.  Returns (mean, sigma, values or None)."""
+    lib = _load()
+    m = _masses(masses)
+    k = len(resonances)
+    pi = np.array([r[0] for r in resonances] + [0], dtype=np.int32)
+    pj = np.array([r[1] for r in resonances] + [0], dtype=np.int32)
+    rm = np.array([r[2] for r in resonances] + [0.0], dtype=np.float64)
+    rg = np.array([r[3] for r in resonances] + [0.0], dtype=np.float64)
+    vals = np.zeros(nevents, dtype=np.float64) if want_values else None
+    mean = ctypes.c_double()
+    sigma = ctypes.c_double()
+    st = lib.oracle_model_integrate(parent_mass, _ptr(m), len(m), k, _ptr(pi), _ptr(pj), _ptr(rm), _ptr(rg),
+                                    nevents, seed, stream_id, event_offset, _ptr(vals), ctypes.byref(mean),
+                                    ctypes.byref(sigma))
+    if st != OK:
+        raise OracleError(st)
+    return mean.value, sigma.value, vals

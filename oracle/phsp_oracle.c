@@ -409,3 +409,81 @@ int oracle_unweight(double parent_mass, const double *masses, int n, const doubl
     if (w_max_used != NULL) *w_max_used = w_max;
     return ORACLE_OK;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Model evaluation over phase space (sec. 4.2: "evaluation of model").    */
+/* The model is a product of relativistic Breit-Wigner intensities in pair  */
+/* invariant masses, |A|^2 = prod_k 1 / ((M_k^2 - s_k)^2 + M_k^2 G_k^2),    */
+/* s_k = (p_i + p_j)^2 for the pair (i, j) of factor k; no factor is the    */
+/* constant 1.  Each event contributes w |A|^2, so the mean is the integral */
+/* of |A|^2 over phase space.                                               */
+/* ---------------------------------------------------------------------- */
+
+#define ORACLE_MAX_BW 4
+
+/* s = (p_i + p_j)^2 = (E_i + E_j)^2 - |p_i + p_j|^2, components summed first. */
+static double pair_mass_sq(const double a[4], const double b[4])
+{
+    const double e = a[0] + b[0], x = a[1] + b[1], y = a[2] + b[2], z = a[3] + b[3];
+    return e * e - x * x - y * y - z * z;
+}
+
+static double model_intensity(double p4[][4], int n_bw, const int *pi, const int *pj, const double *mass,
+                              const double *width)
+{
+    double a2 = 1.0;
+    for (int k = 0; k < n_bw; ++k) {
+        const double s = pair_mass_sq(p4[pi[k]], p4[pj[k]]);
+        const double d = mass[k] * mass[k] - s;
+        const double mg = mass[k] * width[k];
+        a2 = a2 / (d * d + mg * mg);
+    }
+    return a2;
+}
+
+static int check_model(int n, int n_bw, const int *pi, const int *pj, const double *mass, const double *width)
+{
+    if (n_bw < 0 || n_bw > ORACLE_MAX_BW) return ORACLE_EINVAL;
+    for (int k = 0; k < n_bw; ++k) {
+        if (pi[k] < 0 || pj[k] >= n || pi[k] >= pj[k]) return ORACLE_EINVAL;
+        if (!(mass[k] > 0.0) || !(width[k] > 0.0) || !isfinite(mass[k]) || !isfinite(width[k])) return ORACLE_EINVAL;
+    }
+    return ORACLE_OK;
+}
+
+/* Per-event values w |A|^2 of events e = 0..nevents-1 (parent at rest) into
+ * values[e] (when not NULL), and their mean and standard error as in
+ * oracle_integrate (compensated sum, second pass). */
+int oracle_model_integrate(double parent_mass, const double *masses, int n, int n_bw, const int *pi,
+                           const int *pj, const double *mass, const double *width, uint64_t nevents,
+                           uint64_t seed, uint32_t stream_id, uint64_t event_offset, double *values,
+                           double *mean, double *sigma)
+{
+    int st = check_args(parent_mass, masses, n);
+    if (st != ORACLE_OK) return st;
+    st = check_model(n, n_bw, pi, pj, mass, width);
+    if (st != ORACLE_OK) return st;
+    if (nevents < 2 || mean == NULL || sigma == NULL) return ORACLE_EINVAL;
+    double *v = (double *)malloc(sizeof(double) * nevents);
+    if (v == NULL) return ORACLE_EINVAL;
+    double u[3 * ORACLE_NMAX];
+    double p4[ORACLE_NMAX][4];
+    for (uint64_t e = 0; e < nevents; ++e) {
+        oracle_event_uniforms(seed, stream_id, event_offset + e, n, u);
+        const double w = one_event(parent_mass, masses, n, NULL, u, p4);
+        v[e] = w * model_intensity(p4, n_bw, pi, pj, mass, width);
+        if (values != NULL) values[e] = v[e];
+    }
+    nsum_t s1 = { 0.0, 0.0 };
+    for (uint64_t e = 0; e < nevents; ++e) nsum_add(&s1, v[e]);
+    const double m = (s1.sum + s1.comp) / (double)nevents;
+    nsum_t s2 = { 0.0, 0.0 };
+    for (uint64_t e = 0; e < nevents; ++e) {
+        const double d = v[e] - m;
+        nsum_add(&s2, d * d);
+    }
+    *mean = m;
+    *sigma = sqrt((s2.sum + s2.comp) / (double)(nevents - 1) / (double)nevents);
+    free(v);
+    return ORACLE_OK;
+}

@@ -151,6 +151,28 @@ def test_binding_allocates_line_aligned_columns(P):
     assert_events_close(out.cpu().numpy(), w.cpu().numpy(), p4o, wo)
 
 
+def test_sequential_decay_chain(P):
+    """Daughter 0 of a first generation as the per-event parent of a second one
+    (its four rows of the first output, read in place): element-wise parity of
+    both stages with the oracle chain, and four-momentum conservation."""
+    _say("sequential decays")
+    M, m = CFG0
+    nev = 20_011
+    ld = P.aligned_ld(nev)
+    out1 = torch.empty((3, 4, ld), dtype=torch.float64, device="cuda")
+    w1 = torch.empty(nev, dtype=torch.float64, device="cuda")
+    P.generate(M, m, nev, seed=42, out=out1, weights=w1)
+    out2, w2, st2 = P.generate(m[0], [0.0, 0.0, 0.0], nev, seed=42, stream_id=1, parent_dev=out1[0])
+    torch.cuda.synchronize()
+    p1 = out1[:, :, :nev].cpu().numpy()
+    p2 = out2.cpu().numpy()
+    q1, v1 = oracle.generate(M, m, nev, seed=42)
+    assert_events_close(p1, w1.cpu().numpy(), q1, v1)
+    q2, v2 = oracle.generate(m[0], [0.0, 0.0, 0.0], nev, seed=42, stream_id=1, parent_soa=np.ascontiguousarray(q1[0]))
+    assert_events_close(p2, w2.cpu().numpy(), q2, v2)
+    assert np.all(np.abs(p2.sum(axis=0) - p1[0]) <= 1e-12 * np.abs(p1[0]).max())
+
+
 def test_two_body_sigma_is_exactly_zero(P):
     _say("two-body sigma")
     p4, w, st = _run(P, 5.279, [3.097, 0.4937], 70_001)

@@ -39,6 +39,10 @@ MUTATIONS = [
     ("sample maximum not taken", "if (w > w_max) w_max = w;", "if (w > w_max) w_max = w * 0.5;"),
     ("kept events stored at the trial index", "out[(uint64_t)(4 * d + mu) * ld + kept] = p4[d][mu];",
      "out[(uint64_t)(4 * d + mu) * ld + e] = p4[d][mu];"),
+    ("Breit-Wigner denominator sign", "const double d = mass[k] * mass[k] - s;",
+     "const double d = mass[k] * mass[k] + s;"),
+    ("pair momentum differenced", "x = a[1] + b[1], y = a[2] + b[2]", "x = a[1] - b[1], y = a[2] + b[2]"),
+    ("Breit-Wigner width term", "const double mg = mass[k] * width[k];", "const double mg = width[k];"),
 ]
 
 

@@ -257,6 +257,27 @@ def test_event_physics_per_event_parents(oracle_lib):
     _check_event_physics(oracle_lib, M, CFG0_MASSES, soa, p4, w, 42, 0, 0)
 
 
+def test_sequential_decay_chain(oracle_lib):
+    """Sequential decays: daughter 0 of a first generation is the per-event parent
+    of a second (another stream, so the uniforms are independent).  The chain
+    conserves four-momentum, the second stage's weights do not depend on the
+    parent's motion, and the mean of the product of the two weights is the product
+    of the two volumes (the intermediate has a fixed mass)."""
+    M, m = CFG0_M, CFG0_MASSES
+    n = 100_000
+    p4, w1 = oracle_lib.generate(M, m, n, seed=42, stream_id=0)
+    mid = m[0]
+    soa = np.ascontiguousarray(p4[0])  # [4][n]: the J/psi-like daughter of each event
+    q4, w2 = oracle_lib.generate(mid, [0.0, 0.0, 0.0], n, seed=42, stream_id=1, parent_soa=soa)
+    assert np.all(np.abs(q4.sum(axis=0) - soa) <= 1e-12 * np.abs(soa).max())
+    _check_event_physics(oracle_lib, mid, [0.0, 0.0, 0.0], soa[:, :300], q4[:, :, :300], w2[:300], 42, 1, 0)
+    _, w2_rest = oracle_lib.generate(mid, [0.0, 0.0, 0.0], n, seed=42, stream_id=1, want_momenta=False)
+    assert np.array_equal(w2, w2_rest)
+    ww = w1 * w2
+    want = V.three_body_volume_1d(M, *m) * V.massless_volume(3, mid)
+    _assert_within(float(ww.mean()), float(ww.std(ddof=1)) / math.sqrt(n), want)
+
+
 def _direction(u, v):
     ct = 2.0 * u - 1.0
     st = math.sqrt(max(0.0, 1.0 - ct * ct))
@@ -445,6 +466,64 @@ def test_kept_events_are_the_weighted_events(oracle_lib):
     # capacity smaller than the kept count: the first kept events, full count
     p4c, idxc, keptc, _, _ = oracle_lib.unweight(M, m, n, seed=3, stream_id=2, event_offset=off, capacity=100)
     assert keptc == kept and np.array_equal(idxc, idx[:100]) and np.array_equal(p4c, p4[:, :, :100])
+
+
+# --------------------------------------------------- model evaluation ----
+# The integral of a product of relativistic Breit-Wigner intensities in pair
+# masses over three-body phase space, against one-dimensional quadratures of the
+# uniform Dalitz density (the second intensity integrated in closed form).
+
+KSTAR = (0.8955, 0.0473)   # a K pi resonance in the (1, 2) pair of config 0
+PSI2S = (3.686, 0.3)       # a broad resonance in the (0, 1) pair of config 0
+
+
+def test_model_constant_is_the_plain_integral(oracle_lib):
+    a = oracle_lib.model_integrate(CFG0_M, CFG0_MASSES, 50_000, seed=3)
+    b = oracle_lib.integrate(CFG0_M, CFG0_MASSES, 50_000, seed=3)
+    assert a[:2] == b
+
+
+def test_model_one_breit_wigner(oracle_lib):
+    M, m = CFG0_M, CFG0_MASSES
+    mean, sigma, _ = oracle_lib.model_integrate(M, m, 400_000, resonances=[(1, 2, *KSTAR)], seed=11)
+    want = V.bw_dalitz_integral_one(M, *m, *KSTAR)
+    _assert_within(mean, sigma, want)
+    # a quadrature-independent cross-check of the quadrature: narrow-width limit
+    # pi/(mr gr) W01(mr^2) pi^2/(4M^2), to a few percent for this width
+    l01, h01 = V.dalitz_m12sq_limits(M, m[2], m[1], m[0], KSTAR[0] ** 2)
+    narrow = math.pi / (KSTAR[0] * KSTAR[1]) * (h01 - l01) * math.pi ** 2 / (4 * M * M)
+    assert abs(want / narrow - 1.0) < 0.05
+
+
+def test_model_two_breit_wigners(oracle_lib):
+    M, m = CFG0_M, CFG0_MASSES
+    res = [(0, 1, *PSI2S), (1, 2, *KSTAR)]
+    mean, sigma, _ = oracle_lib.model_integrate(M, m, 400_000, resonances=res, seed=12)
+    want = V.bw_dalitz_integral_two(M, *m, PSI2S, KSTAR)
+    _assert_within(mean, sigma, want)
+
+
+def test_model_values_are_weight_times_intensity(oracle_lib):
+    M, m = 4.0, [0.5, 1.0, 0.2, 0.3]
+    res = [(0, 3, 1.2, 0.1), (1, 2, 1.5, 0.2)]
+    _, _, v = oracle_lib.model_integrate(M, m, 2000, resonances=res, seed=5, want_values=True)
+    p4, w = oracle_lib.generate(M, m, 2000, seed=5)
+    a2 = np.ones(2000)
+    for i, j, mr, gr in res:
+        s = _minkowski_sq(p4[i] + p4[j])
+        a2 = a2 / ((mr * mr - s) ** 2 + (mr * gr) ** 2)
+    assert np.allclose(v, w * a2, rtol=1e-12, atol=0.0)
+
+
+def test_model_validation(oracle_lib):
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.model_integrate(CFG0_M, CFG0_MASSES, 100, resonances=[(1, 1, 1.0, 0.1)])
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.model_integrate(CFG0_M, CFG0_MASSES, 100, resonances=[(0, 3, 1.0, 0.1)])
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.model_integrate(CFG0_M, CFG0_MASSES, 100, resonances=[(0, 1, 1.0, 0.0)])
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.model_integrate(CFG0_M, CFG0_MASSES, 100, resonances=[(0, 1, 1.0, 0.1)] * 5)
 
 
 # --------------------------------------------------- determinism / validation ----

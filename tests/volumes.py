@@ -97,3 +97,39 @@ def three_body_volume_1d(M: float, m0: float, m1: float, m2: float, k: int = 200
     ds = (hi - lo) * np.sin(2.0 * t) * w * (np.pi / 4.0)
     f = two_body_momentum(s, m0, m1) * two_body_momentum(M, s, m2)
     return float(2.0 * np.pi ** 2 / M * np.sum(f * ds))
+
+
+def bw_dalitz_integral_one(M, m0, m1, m2, mr, gr, k: int = 4000) -> float:
+    """Integral over three-body phase space of one relativistic Breit-Wigner
+    intensity 1/((mr^2 - s12)^2 + (mr gr)^2) in the (1,2) pair mass.
+
+    The Dalitz density is uniform, pi^2/(4 M^2) per unit (s01, s12), so the
+    integral is pi^2/(4M^2) int ds12 W01(s12) |BW(s12)|^2 with W01 the width of
+    the s01 range at fixed s12; s12 = mr^2 + mr gr tan(theta) flattens the peak."""
+    lo, hi = (m1 + m2) ** 2, (M - m0) ** 2
+    g = mr * gr
+    a, b = np.arctan((lo - mr * mr) / g), np.arctan((hi - mr * mr) / g)
+    x, w = _gauss_legendre(k)
+    th = 0.5 * (b - a) * x + 0.5 * (a + b)
+    s = mr * mr + g * np.tan(th)
+    s = np.clip(s, lo, hi)
+    l01, h01 = dalitz_m12sq_limits(M, m2, m1, m0, s)  # range of s01 at fixed s12 (relabelled)
+    f = (h01 - l01) / g  # |BW|^2 ds = dtheta / g
+    return float(np.pi ** 2 / (4.0 * M * M) * 0.5 * (b - a) * np.sum(w * f))
+
+
+def bw_dalitz_integral_two(M, m0, m1, m2, r01, r12, k: int = 4000) -> float:
+    """Two Breit-Wigner intensities, in s01 (r01 = (mass, width)) and in s12
+    (r12).  The s12 integral of the second at fixed s01 is an arctangent
+    difference, leaving one dimension: s01 = m^2 + m g tan(theta)."""
+    (ma, ga), (mb, gb) = r01, r12
+    lo, hi = (m0 + m1) ** 2, (M - m2) ** 2
+    g = ma * ga
+    gb2 = mb * gb
+    a, b = np.arctan((lo - ma * ma) / g), np.arctan((hi - ma * ma) / g)
+    x, w = _gauss_legendre(k)
+    th = 0.5 * (b - a) * x + 0.5 * (a + b)
+    s = np.clip(ma * ma + g * np.tan(th), lo, hi)
+    l12, h12 = dalitz_m12sq_limits(M, m0, m1, m2, s)
+    inner = (np.arctan((h12 - mb * mb) / gb2) - np.arctan((l12 - mb * mb) / gb2)) / gb2
+    return float(np.pi ** 2 / (4.0 * M * M) * 0.5 * (b - a) * np.sum(w * inner / g))

@@ -235,6 +235,7 @@ def extras(P, torch, dev, args):
     ex["cfg1_integrate_only"] = {"events_per_s": n1 / (ms * 1e-3), "kernel_ms": kms}
     ex["cfg1_unweighted"] = unweighted_extra(P, torch, dev, M, m, n1, out, steps)
     ex["cfg1_sequential"] = sequential_extra(P, torch, dev, M, m, n1, out, w, st, steps)
+    ex["cfg1_model"] = model_extra(P, torch, dev, M, m, n1, w, st, steps)
     del out, w
     # config 2: six pions at M=10, 5e7 events, FP64 vs mixed
     n2 = max(n1 // 2, 1)
@@ -255,6 +256,20 @@ def extras(P, torch, dev, args):
     if args.serve_seconds > 0:
         ex["cfg4_serving"] = serving_extra(P, args.serve_seconds)
     return ex
+
+
+def model_extra(P, torch, dev, M, m, n, w, st, steps):
+    """Model evaluation over the 1e8 events: one Breit-Wigner intensity (a K pi
+    resonance) and two (plus a broad one in the other pair); the per-event values
+    w |A|^2 are written (8 B/event) and integrated."""
+    one = [(1, 2, 0.8955, 0.0473)]
+    two = [(0, 1, 3.686, 0.3), (1, 2, 0.8955, 0.0473)]
+    r = {}
+    for name, res in (("one_factor", one), ("two_factors", two)):
+        ms, k = time_steps(lambda: P.integrate_model(M, m, n, res, values=w, stats=st), steps, 1, torch)
+        r[name] = {"kernel_ms": k, "events_per_s": n / (ms * 1e-3), "integral": float(st[1].item()),
+                   "sigma": float(st[3].item())}
+    return r
 
 
 def sequential_extra(P, torch, dev, M, m, n, out, w, st, steps):

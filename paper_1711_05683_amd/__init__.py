@@ -68,6 +68,8 @@ def _declare(lib):
     lib.hydra_phsp_timing_read.restype = i
     lib.hydra_phsp_generate_unweighted.argtypes = [d, dp, i, dp, u64, u64, u32, u64, d, vp, u64, vp, vp, vp, vp]
     lib.hydra_phsp_generate_unweighted.restype = i
+    lib.hydra_phsp_integrate_model.argtypes = [d, dp, i, vp, i, u64, u64, u32, u64, vp, vp, vp]
+    lib.hydra_phsp_integrate_model.restype = i
 
 
 def lib():
@@ -202,6 +204,35 @@ def generate_unweighted(parent_mass: float, masses: Sequence[float], ntrials: in
                                                 float(w_max), _dptr(out), ld, _dptr(idx), _dptr(counts),
                                                 _dptr(wm), _stream_handle(stream)))
     return out, idx, counts, wm
+
+
+class BreitWigner(ctypes.Structure):
+    """``hydra_phsp_breit_wigner``: a relativistic Breit-Wigner factor in the
+    invariant mass of daughters (i, j)."""
+    _fields_ = [("i", ctypes.c_int32), ("j", ctypes.c_int32), ("mass", ctypes.c_double),
+                ("width", ctypes.c_double)]
+
+
+def integrate_model(parent_mass: float, masses: Sequence[float], nevents: int, resonances=(), *, seed: int = 42,
+                    stream_id: int = 0, event_offset: int = 0, values: Optional[torch.Tensor] = None,
+                    want_values: bool = False, stats: Optional[torch.Tensor] = None, device=None,
+                    stream: Optional[torch.cuda.Stream] = None):
+    """Integral of |A|^2 over phase space, |A|^2 = prod of Breit-Wigner intensities
+    given as (i, j, mass, width) tuples (asynchronous).  Returns ``(stats, values)``:
+    the device stats (n, mean, M2, sigma) of w |A|^2 and, when asked, the per-event
+    values."""
+    m, n = _masses(masses)
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    k = len(resonances)
+    arr = (BreitWigner * max(k, 1))(*[BreitWigner(int(a), int(b), float(c), float(d)) for a, b, c, d in resonances])
+    if values is None and want_values:
+        values = torch.empty(max(nevents, 1), dtype=torch.float64, device=dev)
+    if stats is None:
+        stats = torch.empty(STATS, dtype=torch.float64, device=dev)
+    _check(lib().hydra_phsp_integrate_model(parent_mass, m, n, ctypes.cast(arr, ctypes.c_void_p), k, nevents,
+                                            seed, stream_id, event_offset, _dptr(values), _dptr(stats),
+                                            _stream_handle(stream)))
+    return stats, values
 
 
 def integrate_async(parent_mass: float, masses: Sequence[float], nevents: int, *, seed: int = 42,

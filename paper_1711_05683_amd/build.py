@@ -60,11 +60,14 @@ def _units():
     for n in NS:
         units.append((os.path.join(CSRC, "phsp_unweight_inst.hip"),
                       os.path.join(BUILD_DIR, f"phsp_unweight_inst_n{n}.o"), [f"-DUNW_N={n}"]))
+    for n in NS:
+        units.append((os.path.join(CSRC, "phsp_model_inst.hip"),
+                      os.path.join(BUILD_DIR, f"phsp_model_inst_n{n}.o"), [f"-DMODEL_N={n}"]))
     for nmax in BATCH_MIXED:
         units.append((os.path.join(CSRC, "phsp_batch_inst.hip"),
                       os.path.join(BUILD_DIR, f"phsp_batch_mixed_n{nmax}.o"), [f"-DBATCH_MIXED={nmax}"]))
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith(".hip") and name not in ("phsp_inst.hip", "phsp_batch_inst.hip", "phsp_unweight_inst.hip"):
+        if name.endswith(".hip") and not name.endswith("_inst.hip"):
             units.append((os.path.join(CSRC, name),
                           os.path.join(BUILD_DIR, name[:-4] + ".o"), []))
         elif name.endswith(".cpp"):

@@ -307,17 +307,30 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
         timing_end(stream, slot);
         if (e != hipSuccess) return fail_hip(e, "phase-space kernel launch");
     }
-    if (stats_dev != nullptr) {
-        const uint64_t groups = stage1_groups(blocks);
-        hipLaunchKernelGGL(k_merge_stage1, dim3((unsigned)groups), dim3(kStage1Block), 0, stream,
-                           (const Moments*)ws->partials, blocks, ws->mid);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return fail_hip(e, "merge kernel launch");
-        hipLaunchKernelGGL(k_merge_stage2, dim3(1), dim3(kStage2Block), 0, stream,
-                           (const Moments*)ws->mid, groups, stats_dev);
-        e = hipGetLastError();
-        if (e != hipSuccess) return fail_hip(e, "merge kernel launch");
-    }
+    if (stats_dev != nullptr) return merge_partials(stream, ws->partials, blocks, stats_dev);
+    return HYDRA_PHSP_OK;
+}
+
+int block_partials(hipStream_t stream, uint64_t blocks, Moments** partials) {
+    Workspace* ws = nullptr;
+    const int st = workspace_for(stream, blocks, &ws);
+    if (st == HYDRA_PHSP_OK) *partials = ws->partials;
+    return st;
+}
+
+int merge_partials(hipStream_t stream, const Moments* partials, uint64_t blocks, double* stats_dev) {
+    Workspace* ws = nullptr;
+    const int st = workspace_for(stream, blocks, &ws);
+    if (st != HYDRA_PHSP_OK) return st;
+    const uint64_t groups = stage1_groups(blocks);
+    hipLaunchKernelGGL(k_merge_stage1, dim3((unsigned)groups), dim3(kStage1Block), 0, stream, partials, blocks,
+                       ws->mid);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "merge kernel launch");
+    hipLaunchKernelGGL(k_merge_stage2, dim3(1), dim3(kStage2Block), 0, stream, (const Moments*)ws->mid, groups,
+                       stats_dev);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "merge kernel launch");
     return HYDRA_PHSP_OK;
 }
 

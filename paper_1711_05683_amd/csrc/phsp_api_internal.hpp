@@ -6,6 +6,7 @@
 #include <string>
 
 #include "phsp_device.hpp"
+#include "phsp_reduce.hpp"
 
 namespace hphsp {
 
@@ -23,6 +24,11 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
 // Events per thread a single-channel launch uses for (mode, n, parent mode),
 // after the process-wide override.
 int single_channel_ept(int mode, int n, int pmode);
+// The stream's block-partials buffer, grown to at least `blocks` entries (valid
+// until the next call on the stream that grows it).
+int block_partials(hipStream_t stream, uint64_t blocks, Moments** partials);
+// Two-stage fixed-order merge of `blocks` partials into HYDRA_PHSP_STATS doubles.
+int merge_partials(hipStream_t stream, const Moments* partials, uint64_t blocks, double* stats_dev);
 int release_workspaces();
 int release_unweight_workspaces();
 int release_batch_slots();

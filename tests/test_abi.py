@@ -139,6 +139,7 @@ def test_struct_layouts_match_headers(P, tmp_path):
 #include <stdio.h>
 #include "hydra_phsp_batch.h"
 #include "hydra_phsp_serve.h"
+#include "hydra_phsp_model.h"
 int main(void) {
     printf("%zu %zu %zu %zu %zu %zu %zu ", sizeof(hydra_phsp_channel),
            offsetof(hydra_phsp_channel, n_daughters), offsetof(hydra_phsp_channel, nevents),
@@ -148,6 +149,8 @@ int main(void) {
            offsetof(hydra_phsp_request, integrate_only), offsetof(hydra_phsp_request, stream_id),
            sizeof(hydra_phsp_result), offsetof(hydra_phsp_result, mean),
            offsetof(hydra_phsp_result, weights_dev), offsetof(hydra_phsp_result, done_s));
+    printf("%zu %zu %zu\n", sizeof(hydra_phsp_breit_wigner), offsetof(hydra_phsp_breit_wigner, mass),
+           offsetof(hydra_phsp_breit_wigner, width));
     return 0;
 }
 ''')
@@ -159,7 +162,8 @@ int main(void) {
     want = [ctypes.sizeof(C), C.n_daughters.offset, C.nevents.offset, C.p4_out_dev.offset,
             C.stats_dev.offset, ctypes.sizeof(T), T.grid_per_cu.offset,
             ctypes.sizeof(Q), Q.integrate_only.offset, Q.stream_id.offset,
-            ctypes.sizeof(R), R.mean.offset, R.weights_dev.offset, R.done_s.offset]
+            ctypes.sizeof(R), R.mean.offset, R.weights_dev.offset, R.done_s.offset,
+            ctypes.sizeof(P.BreitWigner), P.BreitWigner.mass.offset, P.BreitWigner.width.offset]
     assert got == want
 
 
@@ -209,3 +213,25 @@ def test_unweighted_validation(P):
     assert call(parent=[5.0, 1.0, 0.0, 0.0]) == P.EINVAL  # parent mass is not M
     m1, n1 = P._masses([1.0])
     assert call(mm=m1, nn=n1) == P.EINVAL
+
+
+def test_model_validation(P):
+    m, n = P._masses([3.097, 0.4937, 0.13957])
+    f = P.lib().hydra_phsp_integrate_model
+
+    def call(res, st=ctypes.c_void_p(64), vals=None, k=None, M=5.279):
+        arr = (P.BreitWigner * max(len(res), 1))(*[P.BreitWigner(*r) for r in res])
+        return f(M, m, n, ctypes.cast(arr, ctypes.c_void_p), len(res) if k is None else k, 100, 1, 0, 0, vals, st,
+                 None)
+
+    assert call([(0, 1, 1.0, 0.1)], st=None) == P.EINVAL
+    assert call([(1, 1, 1.0, 0.1)]) == P.EINVAL
+    assert call([(1, 0, 1.0, 0.1)]) == P.EINVAL
+    assert call([(0, 3, 1.0, 0.1)]) == P.EINVAL
+    assert call([(0, 1, 0.0, 0.1)]) == P.EINVAL
+    assert call([(0, 1, 1.0, -0.1)]) == P.EINVAL
+    assert call([(0, 1, float("inf"), 0.1)]) == P.EINVAL
+    assert call([(0, 1, 1.0, 0.1)] * 5) == P.EINVAL
+    assert call([(0, 1, 1.0, 0.1)], k=-1) == P.EINVAL
+    assert call([(0, 1, 1.0, 0.1)], vals=ctypes.c_void_p(12)) == P.EINVAL
+    assert call([(0, 1, 1.0, 0.1)], M=3.5) == P.EKINEMATICS

@@ -130,6 +130,8 @@ def main():
                          "kernel of known traffic) x3, then the main step x3; prints no JSON")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 64-channel batched configuration and print its figures")
+    ap.add_argument("--only", choices=["unweighted", "model", "sequential"],
+                    help="run only this extra on the 1e8-event workload and print its figures")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -149,6 +151,22 @@ def main():
 
     if args.batched_only:
         print(json.dumps(batched_extra(P, torch, dev, args.steps)), flush=True)
+        return
+    if args.only:
+        M, m = 5.279, [3.097, 0.4937, 0.13957]
+        n = args.nevents
+        out = torch.empty((3, 4, n), dtype=torch.float64, device=dev)
+        w = torch.empty(n, dtype=torch.float64, device=dev)
+        st = torch.empty(4, dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            P.generate(M, m, n, out=out, weights=w, stats=st)
+        if args.only == "unweighted":
+            r = unweighted_extra(P, torch, dev, M, m, n, out, args.steps)
+        elif args.only == "model":
+            r = model_extra(P, torch, dev, M, m, n, w, st, args.steps)
+        else:
+            r = sequential_extra(P, torch, dev, M, m, n, out, w, st, args.steps)
+        print(json.dumps(r), flush=True)
         return
 
     M, m = 5.279, [3.097, 0.4937, 0.13957]

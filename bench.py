@@ -251,6 +251,16 @@ def extras(P, torch, dev, args):
     # integrate-only (no stores): the arithmetic ceiling of the same events
     ms, kms = time_steps(lambda: P.integrate_async(M, m, n1, stats=st), steps, 1, torch)
     ex["cfg1_integrate_only"] = {"events_per_s": n1 / (ms * 1e-3), "kernel_ms": kms}
+    # the same events into columns off the 128-byte line grid (ld = n + 1): the staged kernel
+    del out
+    raw = torch.empty((3 * 4 * (n1 + 1),), dtype=torch.float64, device=dev)
+    ms, kms = time_steps(lambda: P.generate(M, m, n1, out=raw.view(3, 4, n1 + 1), weights=w, stats=st), steps, 1,
+                         torch)
+    ex["cfg1_ld_off_line_grid"] = {"ld": n1 + 1, "kernel_ms": kms, "events_per_s": n1 / (ms * 1e-3),
+                                   "write_GBs": 104 * n1 / (kms * 1e-3) / 1e9}
+    del raw
+    out = torch.empty((3, 4, n1), dtype=torch.float64, device=dev)
+    P.generate(M, m, n1, out=out, weights=w, stats=st)
     ex["cfg1_unweighted"] = unweighted_extra(P, torch, dev, M, m, n1, out, steps)
     ex["cfg1_sequential"] = sequential_extra(P, torch, dev, M, m, n1, out, w, st, steps)
     ex["cfg1_model"] = model_extra(P, torch, dev, M, m, n1, w, st, steps)
@@ -391,7 +401,8 @@ def batched_extra(P, torch, dev, steps):
         keep.append((out, w, st))
         descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id,
                                out=out, weights=w, stats=st))
-    _, kms_unaligned = time_steps(lambda: P.batch_run(descs, ept=ept, grid_per_cu=gpc, schedule=sched),
+    ept_u, gpc_u, sched_u, _ = P.autotune(descs)  # off the line grid: its own classes and shape
+    _, kms_unaligned = time_steps(lambda: P.batch_run(descs, ept=ept_u, grid_per_cu=gpc_u, schedule=sched_u),
                                   steps, 1, torch)
     P.release()
     del keep, descs
@@ -404,6 +415,8 @@ def batched_extra(P, torch, dev, steps):
             "kernel_frac_of_8TBs": total_bytes / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "ms_per_step_direct": ms_direct, "ld": "aligned_ld(nevents)",
             "kernel_ms_ld_eq_nevents": kms_unaligned,
+            "tuning_ld_eq_nevents": {"ept": ept_u, "grid_per_cu": gpc_u,
+                                     "schedule": ["static", "dynamic", "one block per tile"][sched_u]},
             "kernel_write_GBs_ld_eq_nevents": total_bytes / (kms_unaligned * 1e-3) / 1e9}
 
 

@@ -88,8 +88,10 @@ int hydra_phsp_plan_info(const hydra_phsp_plan *plan, uint64_t *ntiles_out, uint
  * -- two warm-up
  * runs and five timed runs per shape, overwriting the batch's outputs -- and
  * returns the shape with the fastest run and that run's time in ms.  Results
- * are cached per device and batch shape class for the life of the process; a
- * cached answer is returned without running. */
+ * are cached per device and batch shape class (channel count, largest N,
+ * integrate-only and off-line-grid channel counts, total events to a quarter
+ * octave) for the life of the process; a cached answer is returned without
+ * running. */
 int hydra_phsp_autotune(const hydra_phsp_channel *channels, int n_channels, void *stream,
                         hydra_phsp_tuning *best_out, double *best_ms_out);
 

@@ -301,7 +301,12 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
         a.weights = weights;
         a.partials = ws->partials;
         a.trig = trig;
-        LaunchSpec s{pmode, mode, ept, blocks};
+        // Columns on the 128-byte line grid take the direct-store kernel; any
+        // other layout the staged one (whole-line writes through LDS).
+        const uint64_t elem = mode == kMixed ? sizeof(float) : sizeof(double);
+        const bool aligned = (uintptr_t)out % kLineBytes == 0 && (ld * elem) % kLineBytes == 0 &&
+                             (uintptr_t)weights % kLineBytes == 0;
+        LaunchSpec s{pmode, mode, ept, blocks, mode != kIntegrate && !aligned};
         const long slot = timing_begin(stream);
         hipError_t e = launch_by_n(n, s, a, stream);
         timing_end(stream, slot);

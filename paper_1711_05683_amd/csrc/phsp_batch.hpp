@@ -92,8 +92,9 @@ __device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
 // counter, one atomic increment per tile, claimed while the previous tile is
 // being processed.  Either way every block leaves once its next index is past
 // the end.  Channels of the kernel have N in [NLO, NHI]; MODE is kIntegrate or
-// kFp64 for a kernel of one mode, or -1 to follow each channel's mode.
-template <int NLO, int NHI, int MODE, int EPT>
+// kFp64 for a kernel of one mode, or -1 to follow each channel's mode; STAGED
+// (one N, kFp64) writes through LDS in whole lines for outputs off the line grid.
+template <int NLO, int NHI, int MODE, int EPT, bool STAGED = false>
 __device__ __forceinline__ void batched_body(const DevChannel* __restrict__ chans,
                                              const TileRef* __restrict__ tiles, uint64_t ntiles,
                                              const double2* __restrict__ trig,
@@ -115,7 +116,10 @@ __device__ __forceinline__ void batched_body(const DevChannel* __restrict__ chan
         }
         const TileRef tr = tiles[t];
         const DevChannel& c = chans[tr.channel];
-        if constexpr (NLO == NHI && MODE >= 0) {
+        if constexpr (STAGED) {
+            static_assert(NLO == NHI && MODE == kFp64, "staged tiles are of one N and FP64");
+            run_staged_block<NLO, kAtRest, kFp64, EPT>(c.a, tr.block, tab);
+        } else if constexpr (NLO == NHI && MODE >= 0) {
             run_tile<NLO, MODE, EPT, (NHI <= 5)>(c.a, tr.block, tab);
         } else {
             switch (c.n) {
@@ -139,14 +143,14 @@ __device__ __forceinline__ void batched_body(const DevChannel* __restrict__ chan
 }
 
 // Batched kernel for channels of exactly N daughters and one mode (kFp64 or
-// kIntegrate): the per-event code and the register budget are those of the
-// single-channel kernel for that N and mode.
-template <int N, int MODE, int EPT>
+// kIntegrate), staged or not: the per-event code and the register budget are
+// those of the single-channel kernel for that N, mode and layout.
+template <int N, int MODE, int EPT, bool STAGED>
 __global__ __launch_bounds__(kBlock) void k_phsp_batched(const DevChannel* __restrict__ chans,
                                                          const TileRef* __restrict__ tiles, uint64_t ntiles,
                                                          const double2* __restrict__ trig,
                                                          unsigned long long* __restrict__ counter) {
-    batched_body<N, N, MODE, EPT>(chans, tiles, ntiles, trig, counter);
+    batched_body<N, N, MODE, EPT, STAGED>(chans, tiles, ntiles, trig, counter);
 }
 
 // Kernel for tiles of any N up to NMAXB in one launch (the serving path, whose
@@ -180,7 +184,7 @@ struct BatchLaunch {
 
 // Launchers, defined per instantiation unit: exactly N daughters, or any N up to
 // NMAXB in one launch.
-template <int N, int MODE, int EPT>
+template <int N, int MODE, int EPT, bool STAGED>
 hipError_t launch_batched(const BatchLaunch& b, hipStream_t stream);
 template <int NMAXB, int EPT>
 hipError_t launch_batched_mixed(const BatchLaunch& b, hipStream_t stream);
@@ -188,7 +192,7 @@ hipError_t launch_batched_mixed(const BatchLaunch& b, hipStream_t stream);
 // Host launchers shared by the batched and serving paths: the channels of
 // exactly n daughters and one mode with ept events per thread; tiles of any N
 // up to nmax (8 or 10) and either mode with one event per thread.
-hipError_t launch_batch_class(int n, int mode, int ept, const BatchLaunch& b, hipStream_t s);
+hipError_t launch_batch_class(int n, int mode, bool staged, int ept, const BatchLaunch& b, hipStream_t s);
 hipError_t launch_mixed_tiles(int nmax, const BatchLaunch& b, hipStream_t s);
 // Stage 1 over `ngroups` group references, then stage 2 over chans[0..nch).
 hipError_t launch_batch_merges(const DevChannel* chans, const GroupRef* groups, uint64_t ngroups, Moments* mid,

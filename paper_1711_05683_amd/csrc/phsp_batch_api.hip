@@ -45,14 +45,25 @@ __global__ __launch_bounds__(kStage2Block) void k_batch_merge_stage2(const DevCh
 using namespace hphsp;
 
 namespace hphsp {
-// Classes of the batched path: one per (N = 2..10, FP64 generate or
-// integrate-only).  Every class gets its own launch of the kernel specialised
-// for it, so each tile runs with the code and the occupancy of the
-// single-channel kernel.
-constexpr int kClasses = 18;
-inline int class_of(int n, int mode) { return (n - 2) + (mode == kIntegrate ? 9 : 0); }
+// Classes of the batched path: one per (N = 2..10, kind), the kinds being FP64
+// generate into columns on the 128-byte line grid, FP64 generate into other
+// layouts (staged stores) and integrate-only.  Every class gets its own launch of
+// the kernel specialised for it, so each tile runs with the code and the
+// occupancy of the single-channel kernel for that N, mode and layout.
+constexpr int kClasses = 27;
+enum ClassKind { kKindDirect = 0, kKindIntegrate = 1, kKindStaged = 2 };
+inline int class_of(int n, int kind) { return (n - 2) + 9 * kind; }
 inline int class_n(int c) { return c % 9 + 2; }
-inline int class_mode(int c) { return c < 9 ? kFp64 : kIntegrate; }
+inline int class_kind(int c) { return c / 9; }
+inline int class_mode(int c) { return class_kind(c) == kKindIntegrate ? kIntegrate : kFp64; }
+// Kind of a channel: line-aligned columns (base and ld * 8 bytes multiples of
+// 128) and weights take the direct-store kernel.
+inline int channel_kind(const hydra_phsp_channel& c) {
+    if (c.p4_out_dev == nullptr) return kKindIntegrate;
+    const bool aligned = (uintptr_t)c.p4_out_dev % kLineBytes == 0 && (c.ld * sizeof(double)) % kLineBytes == 0 &&
+                         (uintptr_t)c.weights_dev % kLineBytes == 0;
+    return aligned ? kKindDirect : kKindStaged;
+}
 } // namespace hphsp
 
 struct hydra_phsp_plan {
@@ -79,32 +90,33 @@ struct hydra_phsp_plan {
 
 namespace hphsp {
 
-template <int N, int MODE>
+template <int N, int MODE, bool STAGED>
 static hipError_t launch_by_ept(int ept, const BatchLaunch& b, hipStream_t s) {
     switch (ept) {
-    case 1: return launch_batched<N, MODE, 1>(b, s);
-    case 2: return launch_batched<N, MODE, 2>(b, s);
-    case 4: return launch_batched<N, MODE, 4>(b, s);
+    case 1: return launch_batched<N, MODE, 1, STAGED>(b, s);
+    case 2: return launch_batched<N, MODE, 2, STAGED>(b, s);
+    case 4: return launch_batched<N, MODE, 4, STAGED>(b, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <int N>
-static hipError_t launch_by_mode(int mode, int ept, const BatchLaunch& b, hipStream_t s) {
-    return mode == kIntegrate ? launch_by_ept<N, kIntegrate>(ept, b, s) : launch_by_ept<N, kFp64>(ept, b, s);
+static hipError_t launch_by_mode(int mode, bool staged, int ept, const BatchLaunch& b, hipStream_t s) {
+    if (mode == kIntegrate) return launch_by_ept<N, kIntegrate, false>(ept, b, s);
+    return staged ? launch_by_ept<N, kFp64, true>(ept, b, s) : launch_by_ept<N, kFp64, false>(ept, b, s);
 }
 
-hipError_t launch_batch_class(int n, int mode, int ept, const BatchLaunch& b, hipStream_t s) {
+hipError_t launch_batch_class(int n, int mode, bool staged, int ept, const BatchLaunch& b, hipStream_t s) {
     switch (n) {
-    case 2: return launch_by_mode<2>(mode, ept, b, s);
-    case 3: return launch_by_mode<3>(mode, ept, b, s);
-    case 4: return launch_by_mode<4>(mode, ept, b, s);
-    case 5: return launch_by_mode<5>(mode, ept, b, s);
-    case 6: return launch_by_mode<6>(mode, ept, b, s);
-    case 7: return launch_by_mode<7>(mode, ept, b, s);
-    case 8: return launch_by_mode<8>(mode, ept, b, s);
-    case 9: return launch_by_mode<9>(mode, ept, b, s);
-    case 10: return launch_by_mode<10>(mode, ept, b, s);
+    case 2: return launch_by_mode<2>(mode, staged, ept, b, s);
+    case 3: return launch_by_mode<3>(mode, staged, ept, b, s);
+    case 4: return launch_by_mode<4>(mode, staged, ept, b, s);
+    case 5: return launch_by_mode<5>(mode, staged, ept, b, s);
+    case 6: return launch_by_mode<6>(mode, staged, ept, b, s);
+    case 7: return launch_by_mode<7>(mode, staged, ept, b, s);
+    case 8: return launch_by_mode<8>(mode, staged, ept, b, s);
+    case 9: return launch_by_mode<9>(mode, staged, ept, b, s);
+    case 10: return launch_by_mode<10>(mode, staged, ept, b, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -165,7 +177,7 @@ static int enqueue_plan(hydra_phsp_plan* p, hipStream_t s, bool timed) {
             if (p->class_count[c] == 0) continue;
             BatchLaunch b{p->d_chans, p->d_tiles + p->class_begin[c], p->class_count[c], p->class_grid[c], p->trig,
                           p->dynamic ? p->d_counters + c : nullptr};
-            e = launch_batch_class(class_n(c), class_mode(c), p->class_ept[c], b, s);
+            e = launch_batch_class(class_n(c), class_mode(c), class_kind(c) == kKindStaged, p->class_ept[c], b, s);
         }
         timing_end(s, slot);
         if (e != hipSuccess) return fail_hip(e, "batched kernel launch");
@@ -210,6 +222,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     if (gpc < 1 || gpc > 64) return fail(HYDRA_PHSP_EINVAL, "tuning grid_per_cu must be in [1, 64]");
 
     std::vector<DevChannel> dch((size_t)nch);
+    std::vector<int> kinds((size_t)nch);
     std::vector<TileRef> tiles;
     std::vector<GroupRef> groups;
     uint64_t first_tile = 0, first_group = 0;
@@ -222,7 +235,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
             return st;
         }
         const uint64_t tile_events =
-            (uint64_t)kBlock * (uint64_t)class_ept[class_of(c.n_daughters, c.p4_out_dev ? kFp64 : kIntegrate)];
+            (uint64_t)kBlock * (uint64_t)class_ept[class_of(c.n_daughters, channel_kind(c))];
         const uint64_t nt = (c.nevents + tile_events - 1) / tile_events;
         if (nt > 0xFFFFFFFFull) return fail(HYDRA_PHSP_EINVAL, "channel too large");
         DevChannel d;
@@ -246,6 +259,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         // partials pointer is fixed up after allocation (offset kept in a.partials)
         d.a.partials = reinterpret_cast<Moments*>(first_tile * sizeof(Moments));
         dch[(size_t)i] = d;
+        kinds[(size_t)i] = channel_kind(c);
         for (uint64_t b = 0; b < nt; ++b) tiles.push_back(TileRef{(uint32_t)i, 0u, b});
         for (uint64_t g = 0; g < d.ngroups; ++g) groups.push_back(GroupRef{(uint32_t)i, (uint32_t)g});
         first_tile += nt;
@@ -259,7 +273,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         for (int c = 0; c < kClasses; ++c) {
             class_begin[c] = by_class.size();
             for (const TileRef& t : tiles)
-                if (class_of(dch[t.channel].n, dch[t.channel].mode) == c) by_class.push_back(t);
+                if (class_of(dch[t.channel].n, kinds[t.channel]) == c) by_class.push_back(t);
             class_count[c] = by_class.size() - class_begin[c];
         }
         tiles.swap(by_class);
@@ -374,22 +388,23 @@ int release_batch_slots() {
 // ------------------------------------------------------------- autotuner ----
 
 struct TuneKey {
-    int device, nch, nmax, integrate_only;
+    int device, nch, nmax, integrate_only, staged;
     int64_t events_bucket;
     bool operator<(const TuneKey& o) const {
-        return std::tie(device, nch, nmax, integrate_only, events_bucket) <
-               std::tie(o.device, o.nch, o.nmax, o.integrate_only, o.events_bucket);
+        return std::tie(device, nch, nmax, integrate_only, staged, events_bucket) <
+               std::tie(o.device, o.nch, o.nmax, o.integrate_only, o.staged, o.events_bucket);
     }
 };
 static std::mutex g_tune_mu;
 static std::map<TuneKey, std::pair<hydra_phsp_tuning, double>> g_tune_cache;
 
 static TuneKey tune_key(const hydra_phsp_channel* chans, int nch, int dev) {
-    TuneKey k{dev, nch, 2, 0, 0};
+    TuneKey k{dev, nch, 2, 0, 0, 0};
     double total = 0.0;
     for (int i = 0; i < nch; ++i) {
         k.nmax = std::max(k.nmax, chans[i].n_daughters);
         if (chans[i].p4_out_dev == nullptr) ++k.integrate_only;
+        if (channel_kind(chans[i]) == kKindStaged) ++k.staged;
         total += (double)chans[i].nevents;
     }
     k.events_bucket = (int64_t)std::llround(4.0 * std::log2(total + 1.0)); // quarter-octave classes

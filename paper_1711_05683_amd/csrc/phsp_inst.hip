@@ -13,6 +13,13 @@ namespace {
 
 template <int PMODE, int MODE, int EPT>
 hipError_t go(const LaunchSpec& s, const KArgs& a, hipStream_t stream) {
+    if constexpr (MODE != kIntegrate) {
+        if (s.staged) {
+            hipLaunchKernelGGL((k_phsp_staged<PHSP_N, PMODE, MODE, EPT>), dim3((unsigned)s.blocks), dim3(kBlock), 0,
+                               stream, a);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((k_phsp<PHSP_N, PMODE, MODE, EPT>), dim3((unsigned)s.blocks), dim3(kBlock), 0,
                        stream, a);
     return hipGetLastError();

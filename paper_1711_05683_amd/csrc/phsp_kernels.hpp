@@ -10,6 +10,7 @@
 
 #include "phsp_device.hpp"
 #include "phsp_reduce.hpp"
+#include "phsp_stage.hpp"
 
 namespace hphsp {
 
@@ -159,12 +160,86 @@ __global__ __launch_bounds__(kBlock) void k_phsp(const KArgs a) {
     if (threadIdx.x == 0) a.partials[blockIdx.x] = r;
 }
 
+// k_phsp for outputs whose columns do not all start on a 128-byte line (any
+// ld, any element-aligned pointer): the same events and per-lane statistics, but
+// every column -- the 4N momentum columns and the weights -- is written through
+// LDS in whole lines (phsp_stage.hpp), one daughter's four columns at a time.
+// The body of one block of k_phsp_staged (block index blk); also a tile of the
+// batched kernels.
+template <int N, int PMODE, int MODE, int EPT>
+__device__ __forceinline__ void run_staged_block(const KArgs& a, uint64_t blk, const double2* tab) {
+    static_assert(MODE != kIntegrate, "integration stores nothing");
+    static_assert(kBlock == kStageBlock, "the staging helpers assume the kernel's block size");
+    using R = typename std::conditional<MODE == kMixed, float, double>::type;
+    constexpr uint32_t L = line_elems<R>();
+    constexpr uint32_t LW = line_elems<double>();
+    __shared__ R buf[4][L + kBlock];
+    __shared__ R carry[4 * N][L];
+    __shared__ double wbuf[1][LW + kBlock];
+    __shared__ double wcarry[1][LW];
+    const uint64_t base = blk * (uint64_t)(kBlock * EPT);
+    R* const out = static_cast<R*>(a.out);
+    Moments acc{0.0, 0.0, 0.0};
+    uint64_t next = base;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        if (next >= a.nevents) break; // uniform across the block
+        const uint64_t left = a.nevents - next;
+        const uint32_t total = left < (uint64_t)kBlock ? (uint32_t)left : (uint32_t)kBlock;
+        const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
+        const bool valid = threadIdx.x < total;
+        Event<N, R> ev;
+        double w = 0.0;
+        if (valid) {
+            w = compute_event<N, PMODE, MODE, R>(a, base, off, tab, ev);
+            if (k == 0) {
+                acc = Moments{1.0, w, 0.0};
+            } else {
+                const double delta = w - acc.mean;
+                acc.n = (double)(k + 1);
+                acc.mean = acc.mean + delta * (1.0 / (double)(k + 1));
+                acc.m2 = acc.m2 + delta * (w - acc.mean);
+            }
+        }
+        {
+            const double wv[1] = {w};
+            double* const wc[1] = {a.weights};
+            const ColWindow ww[1] = {col_window<double>(line_offset(a.weights), base, next, total, a.nevents)};
+            stage_and_store<1, double>(wv, valid, threadIdx.x, ww, wbuf, wcarry, wc);
+        }
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+            const R v[4] = {ev.e[d], ev.x[d], ev.y[d], ev.z[d]};
+            R* const cols[4] = {out + (uint64_t)(4 * d + 0) * a.ld, out + (uint64_t)(4 * d + 1) * a.ld,
+                                out + (uint64_t)(4 * d + 2) * a.ld, out + (uint64_t)(4 * d + 3) * a.ld};
+            ColWindow w4[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) w4[g] = col_window<R>(line_offset(cols[g]), base, next, total, a.nevents);
+            stage_and_store<4, R>(v, valid, threadIdx.x, w4, buf, &carry[4 * d], cols);
+        }
+        next += total;
+    }
+    flush_carry<double>(wcarry[0], a.weights, base, next, a.nevents);
+    for (int c = 0; c < 4 * N; ++c) flush_carry<R>(carry[c], out + (uint64_t)c * a.ld, base, next, a.nevents);
+    const bool full = base + (uint64_t)(kBlock * EPT) <= a.nevents;
+    const Moments r = block_reduce<kWaves>(acc, full);
+    if (threadIdx.x == 0) a.partials[blk] = r;
+}
+
+template <int N, int PMODE, int MODE, int EPT>
+__global__ __launch_bounds__(kBlock) void k_phsp_staged(const KArgs a) {
+    __shared__ double2 tab[kTrigSize];
+    load_trig(tab, a.trig);
+    run_staged_block<N, PMODE, MODE, EPT>(a, blockIdx.x, tab);
+}
+
 // Launch one instantiation (defined per N in its own translation unit).
 struct LaunchSpec {
     int pmode;
     int mode;
     int ept;
     uint64_t blocks;
+    bool staged; // outputs with a column off the 128-byte line grid: k_phsp_staged
 };
 
 template <int N>

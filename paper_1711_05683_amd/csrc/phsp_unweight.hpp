@@ -13,6 +13,7 @@
 #pragma once
 
 #include "phsp_kernels.hpp"
+#include "phsp_stage.hpp"
 
 namespace hphsp {
 
@@ -113,69 +114,6 @@ __global__ __launch_bounds__(kBlock) void k_unw_count(const UnwArgs u) {
     }
 }
 
-// Elements of one 128-byte line of FP64 (the store granule the write pass
-// aligns to).
-constexpr int kLineElems = 16;
-
-// A step's store window: positions [line0, end) with end = next + total, where
-// line0 starts the line holding `next`; the first c positions are the carried
-// values, the first `full` positions make whole lines (stored now) and the last
-// `tail` are carried on.  Thread t stores window elements t and t + kBlock
-// (positions pos0 and pos0 + kBlock) when ok0 / ok1: inside the whole lines,
-// owned by the block (>= first) and within the capacity ld.  The same window
-// serves every column.
-struct StepWindow {
-    uint32_t c, full, tail;
-    uint64_t pos0;
-    bool ok0, ok1;
-};
-
-__device__ __forceinline__ StepWindow step_window(uint64_t first, uint64_t next, uint32_t total, uint64_t ld) {
-    StepWindow w;
-    const uint64_t line0 = next - next % kLineElems;
-    const uint64_t end = next + total;
-    w.c = (uint32_t)(next - line0);
-    w.full = (uint32_t)(end - end % kLineElems - line0);
-    w.tail = (uint32_t)(end - line0) - w.full;
-    w.pos0 = line0 + threadIdx.x;
-    const uint64_t pos1 = w.pos0 + kBlock;
-    w.ok0 = threadIdx.x < w.full && w.pos0 >= first && w.pos0 < ld;
-    w.ok1 = threadIdx.x + kBlock < w.full && pos1 >= first && pos1 < ld;
-    return w;
-}
-
-// Stage the values v[g] (g < G columns) of the step's kept trials (slot = rank
-// among them) behind the columns' carries, store the window's whole lines and
-// keep each tail (the start of the next line) as the new carry.  buf holds G
-// rows of kLineElems + kBlock values, carry G rows of kLineElems.  Two barriers.
-template <int G, typename T>
-__device__ __forceinline__ void stage_and_store(const T (&v)[G], bool keep, uint32_t slot, const StepWindow& w,
-                                                T (*buf)[kLineElems + kBlock], T (*carry)[kLineElems],
-                                                T* const (&col)[G]) {
-    const uint32_t b0 = kLineElems - w.c + threadIdx.x; // buf index of window element t
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        if (threadIdx.x < w.c) buf[g][kLineElems - w.c + threadIdx.x] = carry[g][threadIdx.x];
-        if (keep) buf[g][kLineElems + slot] = v[g];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        if (w.ok0) __builtin_nontemporal_store(buf[g][b0], col[g] + w.pos0);
-        if (w.ok1) __builtin_nontemporal_store(buf[g][b0 + kBlock], col[g] + w.pos0 + kBlock);
-        if (threadIdx.x < w.tail) carry[g][threadIdx.x] = buf[g][kLineElems - w.c + w.full + threadIdx.x];
-    }
-    __syncthreads(); // stores and carries have read buf before it is refilled
-}
-
-// The block's last carry: the partial line at the end of its run.
-template <typename T>
-__device__ __forceinline__ void flush_carry(const T* carry, T* col, uint64_t ld, uint64_t first, uint64_t end) {
-    const uint64_t line0 = end - end % kLineElems;
-    const uint64_t pos = line0 + threadIdx.x;
-    if (threadIdx.x < end - line0 && pos >= first && pos < ld) __builtin_nontemporal_store(carry[threadIdx.x], col + pos);
-}
-
 // Full kinematics of every trial, kept ones stored in trial order: step k of
 // the block holds trials base + k*kBlock + t, so a kept trial's position is the
 // block's offset, plus the kept trials of earlier steps, of earlier waves in
@@ -188,10 +126,10 @@ __device__ __forceinline__ void flush_carry(const T* carry, T* col, uint64_t ld,
 template <int N, int PMODE>
 __global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
     __shared__ double2 tab[kTrigSize];
-    __shared__ double buf[4][kLineElems + kBlock];
-    __shared__ double carry[4 * N][kLineElems];
-    __shared__ uint64_t ibuf[1][kLineElems + kBlock];
-    __shared__ uint64_t icarry[1][kLineElems];
+    __shared__ double buf[4][line_elems<double>() + kBlock];
+    __shared__ double carry[4 * N][line_elems<double>()];
+    __shared__ uint64_t ibuf[1][line_elems<uint64_t>() + kBlock];
+    __shared__ uint64_t icarry[1][line_elems<uint64_t>()];
     __shared__ uint32_t sk[kWaves];
     load_trig(tab, u.a.trig);
     const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * kUnwEpt);
@@ -219,11 +157,11 @@ __global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
             total += sk[w];
         }
         const uint32_t slot = before + rank;
-        const StepWindow win = step_window(first, next, total, u.ld);
         if (u.index != nullptr) {
             const uint64_t g[1] = {u.a.event_offset + base + off};
             uint64_t* const icol[1] = {u.index};
-            stage_and_store<1, uint64_t>(g, keep, slot, win, ibuf, icarry, icol);
+            const ColWindow wi[1] = {col_window<uint64_t>(line_offset(u.index), first, next, total, u.ld)};
+            stage_and_store<1, uint64_t>(g, keep, slot, wi, ibuf, icarry, icol);
         }
         if (u.out != nullptr) {
 #pragma unroll
@@ -231,14 +169,17 @@ __global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
                 const double v[4] = {ev.e[d], ev.x[d], ev.y[d], ev.z[d]};
                 double* const cols[4] = {u.out + (uint64_t)(4 * d + 0) * u.ld, u.out + (uint64_t)(4 * d + 1) * u.ld,
                                          u.out + (uint64_t)(4 * d + 2) * u.ld, u.out + (uint64_t)(4 * d + 3) * u.ld};
-                stage_and_store<4, double>(v, keep, slot, win, buf, &carry[4 * d], cols);
+                ColWindow w4[4];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) w4[g] = col_window<double>(line_offset(cols[g]), first, next, total, u.ld);
+                stage_and_store<4, double>(v, keep, slot, w4, buf, &carry[4 * d], cols);
             }
         }
         next += total; // sk was read before the staging barriers, so the next step may overwrite it
     }
-    if (u.index != nullptr) flush_carry<uint64_t>(icarry[0], u.index, u.ld, first, next);
+    if (u.index != nullptr) flush_carry<uint64_t>(icarry[0], u.index, first, next, u.ld);
     if (u.out != nullptr)
-        for (int c = 0; c < 4 * N; ++c) flush_carry<double>(carry[c], u.out + (uint64_t)c * u.ld, u.ld, first, next);
+        for (int c = 0; c < 4 * N; ++c) flush_carry<double>(carry[c], u.out + (uint64_t)c * u.ld, first, next, u.ld);
 }
 
 struct UnwLaunch {

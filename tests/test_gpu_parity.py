@@ -173,6 +173,41 @@ def test_sequential_decay_chain(P):
     assert np.all(np.abs(p2.sum(axis=0) - p1[0]) <= 1e-12 * np.abs(p1[0]).max())
 
 
+@pytest.mark.parametrize("n", [2, 3, 6, 10])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_line_aligned_and_staged_layouts_agree(P, n, mixed):
+    """Outputs whose columns start mid-line take the staged kernel (whole-line
+    writes through LDS): events, weights and stats must be bit-identical to the
+    direct-store kernel on a line-aligned layout, for every events-per-thread
+    setting, and nothing outside the events may be written."""
+    _say(f"staged vs direct N={n} mixed={mixed}")
+    M, m = _random_masses(n, 5000 + n)
+    dtype = torch.float32 if mixed else torch.float64
+    nev = 9_999
+    ld_al = P.aligned_ld(nev)
+    path = 2 if mixed else 1
+    for ept in (1, 2, 4):
+        P.set_events_per_thread(path, ept)
+        try:
+            a = torch.full((n, 4, ld_al), float("nan"), dtype=dtype, device="cuda")
+            wa = torch.full((ld_al,), float("nan"), dtype=torch.float64, device="cuda")
+            _, _, sa = P.generate(M, m, nev, seed=3, event_offset=77, out=a, weights=wa, mixed=mixed)
+            # columns off the line grid: ld = nev + 3 and both buffers shifted by one element
+            ld = nev + 3
+            rawb = torch.full((n * 4 * ld + 1,), float("nan"), dtype=dtype, device="cuda")
+            rawwb = torch.full((nev + 2,), float("nan"), dtype=torch.float64, device="cuda")
+            b = rawb[1:].view(n, 4, ld)
+            wb = rawwb[1:nev + 1]
+            _, _, sb = P.generate(M, m, nev, seed=3, event_offset=77, out=b, weights=wb, mixed=mixed)
+            torch.cuda.synchronize()
+        finally:
+            P.set_events_per_thread(path, 0)
+        assert torch.equal(a[:, :, :nev], b[:, :, :nev]) and torch.equal(wa[:nev], wb), ept
+        assert torch.equal(sa, sb), ept
+        assert bool(torch.isnan(b[:, :, nev:]).all()) and bool(torch.isnan(rawb[:1]).all())
+        assert bool(torch.isnan(rawwb[:1]).all()) and bool(torch.isnan(rawwb[nev + 1:]).all())
+
+
 def test_two_body_sigma_is_exactly_zero(P):
     _say("two-body sigma")
     p4, w, st = _run(P, 5.279, [3.097, 0.4937], 70_001)

@@ -15,6 +15,7 @@ Dalitz-plot flatness.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -80,6 +81,12 @@ def _load():
                                            ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, dp,
                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.oracle_model_integrate.restype = ctypes.c_int
+    lib.oracle_vegas_iteration.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_uint64,
+                                           ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double), dp]
+    lib.oracle_vegas_iteration.restype = ctypes.c_int
+    lib.oracle_vegas_refine.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_double]
+    lib.oracle_vegas_refine.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -224,3 +231,64 @@ def model_integrate(parent_mass, masses, nevents, resonances=(), seed=42, stream
     if st != OK:
         raise OracleError(st)
     return mean.value, sigma.value, vals
+
+
+def gaussian_integral(lo, hi, mu, sigma) -> float:
+    """Closed form of the product-of-Gaussians integrand over the box (erf)."""
+    import math
+    r = 1.0
+    for a, b, m, s in zip(lo, hi, mu, sigma):
+        r *= 0.5 * (math.erf((b - m) / (s * math.sqrt(2.0))) - math.erf((a - m) / (s * math.sqrt(2.0))))
+    return r
+
+
+def uniform_grid(dim: int, bins: int) -> np.ndarray:
+    return np.tile(np.arange(bins + 1, dtype=np.float64) / bins, (dim, 1))
+
+
+def vegas_iteration(lo, hi, mu, sigma, grid, calls, seed=42, iteration=0, want_hist=True):
+    """One VEGAS iteration: (mean, sigma, histogram [dim, bins] or None)."""
+    lib = _load()
+    lo, hi, mu, sg = (np.ascontiguousarray(a, dtype=np.float64) for a in (lo, hi, mu, sigma))
+    grid = np.ascontiguousarray(grid, dtype=np.float64)
+    dim, bins = grid.shape[0], grid.shape[1] - 1
+    hist = np.zeros((dim, bins), dtype=np.float64) if want_hist else None
+    mean = ctypes.c_double()
+    sig = ctypes.c_double()
+    st = lib.oracle_vegas_iteration(dim, bins, _ptr(lo), _ptr(hi), _ptr(mu), _ptr(sg), _ptr(grid), calls, seed,
+                                    iteration, ctypes.byref(mean), ctypes.byref(sig), _ptr(hist))
+    if st != OK:
+        raise OracleError(st)
+    return mean.value, sig.value, hist
+
+
+def vegas_refine(grid, hist, alpha=1.5):
+    """Refined copy of the grid."""
+    lib = _load()
+    g = np.array(grid, dtype=np.float64, copy=True)
+    h = np.ascontiguousarray(hist, dtype=np.float64)
+    st = lib.oracle_vegas_refine(g.shape[0], g.shape[1] - 1, _ptr(g), _ptr(h), float(alpha))
+    if st != OK:
+        raise OracleError(st)
+    return g
+
+
+def vegas(lo, hi, mu, sigma, calls, iterations, warmup=0, bins=50, alpha=1.5, seed=42):
+    """VEGAS: `warmup` iterations that only adapt the grid, then `iterations`
+    that also estimate; each ends with a refinement.  Returns (result, error,
+    chi2/dof, per-iteration (mean, sigma) of the estimating iterations, final
+    grid); the result is their inverse-variance weighted mean.  Iteration t uses
+    counter word 3 = t (independent samples)."""
+    grid = uniform_grid(len(lo), bins)
+    its = []
+    for t in range(warmup + iterations):
+        m, s, h = vegas_iteration(lo, hi, mu, sigma, grid, calls, seed=seed, iteration=t)
+        if t >= warmup:
+            its.append((m, s))
+        grid = vegas_refine(grid, h, alpha)
+    w = np.array([1.0 / (s * s) for _, s in its])
+    v = np.array([m for m, _ in its])
+    res = float((w * v).sum() / w.sum())
+    err = float(1.0 / math.sqrt(w.sum()))
+    chi2 = float((w * (v - res) ** 2).sum() / max(len(its) - 1, 1))
+    return res, err, chi2, its, grid

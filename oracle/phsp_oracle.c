@@ -487,3 +487,135 @@ int oracle_model_integrate(double parent_mass, const double *masses, int n, int 
     free(v);
     return ORACLE_OK;
 }
+
+/* ---------------------------------------------------------------------- */
+/* VEGAS importance sampling (Lepage, J. Comput. Phys. 27 (1978) 192; the   */
+/* paper's sec. 5.1 uses it on a 10-dimensional Gaussian) and plain Monte   */
+/* Carlo as its special case: one iteration on the uniform grid.            */
+/*                                                                          */
+/* Integrand: f(x) = prod_d exp(-(x_d - mu_d)^2 / (2 s_d^2)) / (s_d sqrt(2 pi))
+/* over the box prod_d [lo_d, hi_d].  Grid: per dimension, K bins with edges */
+/* g[d][0] = 0 < ... < g[d][K] = 1 in unit coordinates.  Sample i of        */
+/* iteration t draws uniform u_d (uniform k of the counter stream           */
+/* (i lo, i hi, j, t) under key seed, converted like the phase-space        */
+/* uniforms); z = K u_d, bin b = floor(z), y = g[b] + (z - b)(g[b+1] - g[b]), */
+/* x_d = lo_d + y (hi_d - lo_d); its value is f(x) J with                    */
+/* J = prod_d K (g[b+1] - g[b]) (hi_d - lo_d).  The iteration's estimate is  */
+/* the mean of the values with its standard error; the refinement histogram */
+/* collects value^2 in each dimension's bin.                                */
+/* ---------------------------------------------------------------------- */
+
+#define ORACLE_VEGAS_DMAX 16
+#define ORACLE_VEGAS_KMAX 128
+
+static double gauss_factor(double x, double mu, double s)
+{
+    const double t = (x - mu) / s;
+    return exp(-0.5 * t * t) / (s * 2.5066282746310002);   /* sqrt(2 pi) */
+}
+
+int oracle_vegas_iteration(int dim, int bins, const double *lo, const double *hi, const double *mu,
+                           const double *sig, const double *grid, uint64_t calls, uint64_t seed,
+                           uint32_t iteration, double *mean, double *sigma, double *hist)
+{
+    if (dim < 1 || dim > ORACLE_VEGAS_DMAX || bins < 1 || bins > ORACLE_VEGAS_KMAX || calls < 2) return ORACLE_EINVAL;
+    if (mean == NULL || sigma == NULL || grid == NULL) return ORACLE_EINVAL;
+    const uint32_t key[2] = { (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32) };
+    double *v = (double *)malloc(sizeof(double) * calls);
+    if (v == NULL) return ORACLE_EINVAL;
+    if (hist != NULL)
+        for (int k = 0; k < dim * bins; ++k) hist[k] = 0.0;
+    int binof[ORACLE_VEGAS_DMAX];
+    for (uint64_t i = 0; i < calls; ++i) {
+        uint32_t words[4 * ((ORACLE_VEGAS_DMAX + 1) / 2)];
+        for (int j = 0; 2 * j < dim; ++j) {
+            const uint32_t ctr[4] = { (uint32_t)(i & 0xFFFFFFFFu), (uint32_t)(i >> 32), (uint32_t)j, iteration };
+            oracle_philox4x32_10(ctr, key, &words[4 * j]);
+        }
+        double val = 1.0;
+        for (int d = 0; d < dim; ++d) {
+            uint64_t bits = ((uint64_t)words[2 * d + 1] << 32) | (uint64_t)words[2 * d];
+            const double u = (double)(2 * (bits >> 12) + 1) * 0x1p-53;
+            const double z = u * (double)bins;
+            int b = (int)z;
+            if (b > bins - 1) b = bins - 1;
+            const double *g = grid + d * (bins + 1);
+            const double width = g[b + 1] - g[b];
+            const double y = g[b] + (z - (double)b) * width;
+            const double x = lo[d] + y * (hi[d] - lo[d]);
+            val = val * gauss_factor(x, mu[d], sig[d]) * ((double)bins * width * (hi[d] - lo[d]));
+            binof[d] = b;
+        }
+        v[i] = val;
+        if (hist != NULL)
+            for (int d = 0; d < dim; ++d) hist[d * bins + binof[d]] += val * val;
+    }
+    nsum_t s1 = { 0.0, 0.0 };
+    for (uint64_t i = 0; i < calls; ++i) nsum_add(&s1, v[i]);
+    const double m = (s1.sum + s1.comp) / (double)calls;
+    nsum_t s2 = { 0.0, 0.0 };
+    for (uint64_t i = 0; i < calls; ++i) {
+        const double dd = v[i] - m;
+        nsum_add(&s2, dd * dd);
+    }
+    *mean = m;
+    *sigma = sqrt((s2.sum + s2.comp) / (double)(calls - 1) / (double)calls);
+    free(v);
+    return ORACLE_OK;
+}
+
+/* Grid refinement of one VEGAS iteration, per dimension: the histogram h of
+ * value^2 per bin is smoothed with its neighbours ((h[0]+h[1])/2, then
+ * (h[k-1]+h[k]+h[k+1])/3, then (h[K-2]+h[K-1])/2); each bin gets the damped
+ * importance r_k = ((1 - 1/R)/log R)^alpha with R = (sum of the smoothed h) /
+ * smoothed h[k] (0 for an empty bin); the new edges cut the old grid, with
+ * each old bin's share of importance spread evenly over its width, into K
+ * pieces of equal importance.  Bins with no importance keep the grid. */
+int oracle_vegas_refine(int dim, int bins, double *grid, const double *hist, double alpha)
+{
+    if (dim < 1 || dim > ORACLE_VEGAS_DMAX || bins < 2 || bins > ORACLE_VEGAS_KMAX || grid == NULL || hist == NULL)
+        return ORACLE_EINVAL;
+    double sm[ORACLE_VEGAS_KMAX], r[ORACLE_VEGAS_KMAX], edges[ORACLE_VEGAS_KMAX + 1];
+    for (int d = 0; d < dim; ++d) {
+        const double *h = hist + d * bins;
+        double *g = grid + d * (bins + 1);
+        double tot = 0.0;
+        for (int k = 0; k < bins; ++k) {
+            if (k == 0) sm[k] = (h[0] + h[1]) / 2.0;
+            else if (k == bins - 1) sm[k] = (h[bins - 2] + h[bins - 1]) / 2.0;
+            else sm[k] = (h[k - 1] + h[k] + h[k + 1]) / 3.0;
+            tot += sm[k];
+        }
+        double rtot = 0.0;
+        for (int k = 0; k < bins; ++k) {
+            r[k] = 0.0;
+            if (sm[k] > 0.0) {
+                const double R = tot / sm[k];
+                r[k] = R > 1.0 ? pow((1.0 - 1.0 / R) / log(R), alpha) : 1.0;
+            }
+            rtot += r[k];
+        }
+        if (!(rtot > 0.0)) continue;
+        const double per = rtot / (double)bins;   /* importance per new bin */
+        edges[0] = 0.0;
+        int k = 0;            /* old bin being consumed */
+        double left = r[0];   /* importance left in old bin k */
+        for (int e = 1; e < bins; ++e) {
+            double need = per;
+            while (need > left && k < bins - 1) {
+                need -= left;
+                ++k;
+                left = r[k];
+            }
+            left -= need;
+            /* the new edge lies in old bin k, a fraction (r[k] - left)/r[k] into it */
+            double frac = r[k] > 0.0 ? (r[k] - left) / r[k] : 1.0;
+            if (frac < 0.0) frac = 0.0;   /* rounding of the running sums */
+            if (frac > 1.0) frac = 1.0;
+            edges[e] = g[k] + frac * (g[k + 1] - g[k]);
+        }
+        edges[bins] = 1.0;
+        for (int e = 0; e <= bins; ++e) g[e] = edges[e];
+    }
+    return ORACLE_OK;
+}

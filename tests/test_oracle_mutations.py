@@ -43,6 +43,15 @@ MUTATIONS = [
      "const double d = mass[k] * mass[k] + s;"),
     ("pair momentum differenced", "x = a[1] + b[1], y = a[2] + b[2]", "x = a[1] - b[1], y = a[2] + b[2]"),
     ("Breit-Wigner width term", "const double mg = mass[k] * width[k];", "const double mg = width[k];"),
+    ("VEGAS Jacobian without the bin count",
+     "val = val * gauss_factor(x, mu[d], sig[d]) * ((double)bins * width * (hi[d] - lo[d]));",
+     "val = val * gauss_factor(x, mu[d], sig[d]) * (width * (hi[d] - lo[d]));"),
+    ("VEGAS point inside the bin", "const double y = g[b] + (z - (double)b) * width;",
+     "const double y = g[b] + u * width;"),
+    ("VEGAS damping exponent sign", "r[k] = R > 1.0 ? pow((1.0 - 1.0 / R) / log(R), alpha) : 1.0;",
+     "r[k] = R > 1.0 ? pow((1.0 - 1.0 / R) / log(R), -alpha) : 1.0;"),
+    ("VEGAS new edge mirrored in the old bin", "edges[e] = g[k] + frac * (g[k + 1] - g[k]);",
+     "edges[e] = g[k] + (1.0 - frac) * (g[k + 1] - g[k]);"),
 ]
 
 

@@ -526,6 +526,64 @@ def test_model_validation(oracle_lib):
         oracle_lib.model_integrate(CFG0_M, CFG0_MASSES, 100, resonances=[(0, 1, 1.0, 0.1)] * 5)
 
 
+# --------------------------------------------------- VEGAS / plain MC ----
+# Integrand: a product of Gaussians over a box, whose integral is a product of
+# error-function differences.
+
+def test_plain_mc_gaussian_closed_form(oracle_lib):
+    lo, hi, mu, sg = [0.0, -1.0, 0.5], [1.0, 2.0, 1.5], [0.4, 0.3, 1.0], [0.5, 0.8, 0.6]
+    m, s, _ = oracle_lib.vegas_iteration(lo, hi, mu, sg, oracle_lib.uniform_grid(3, 50), 200_000, seed=7)
+    _assert_within(m, s, oracle_lib.gaussian_integral(lo, hi, mu, sg))
+
+
+def test_vegas_ten_dimensional_gaussian(oracle_lib):
+    # the integrand of the paper's VEGAS benchmark: a 10-dimensional Gaussian
+    D = 10
+    lo, hi, mu, sg = [0.0] * D, [1.0] * D, [0.5] * D, [0.1] * D
+    exact = oracle_lib.gaussian_integral(lo, hi, mu, sg)
+    res, err, chi2, its, grid = oracle_lib.vegas(lo, hi, mu, sg, 50_000, 5, warmup=5, seed=11)
+    _assert_within(res, err, exact)
+    assert chi2 < 5.0
+    # adaptation: the same calls on the uniform grid give a far larger error
+    _, s_plain, _ = oracle_lib.vegas_iteration(lo, hi, mu, sg, oracle_lib.uniform_grid(D, 50), 50_000, seed=11)
+    assert its[-1][1] < 0.05 * s_plain
+
+
+def test_vegas_refinement_invariants(oracle_lib):
+    rng = np.random.default_rng(3)
+    g = oracle_lib.uniform_grid(4, 50)
+    h = rng.exponential(size=(4, 50))
+    g2 = oracle_lib.vegas_refine(g, h)
+    assert np.all(g2[:, 0] == 0.0) and np.all(g2[:, -1] == 1.0) and np.all(np.diff(g2, axis=1) > 0.0)
+    # a flat histogram keeps the grid
+    g3 = oracle_lib.vegas_refine(g, np.ones((4, 50)))
+    assert np.allclose(g3, g, rtol=0.0, atol=1e-12)
+    # a histogram peaked in the middle draws bins towards it
+    k = np.arange(50)
+    peak = np.exp(-0.5 * ((k - 24.5) / 5.0) ** 2)[None, :]
+    g4 = oracle_lib.vegas_refine(oracle_lib.uniform_grid(1, 50), peak)[0]
+    w = np.diff(g4)
+    assert w[24] < 0.5 * w[0] and w[25] < 0.5 * w[-1]
+
+
+def test_vegas_grid_converges_to_the_integrand(oracle_lib):
+    # one dimension: the adapted density is close to |f| normalised, so the
+    # grid's edges sit near the quantiles of the (truncated) Gaussian
+    lo, hi, mu, sg = [0.0], [1.0], [0.3], [0.08]
+    *_, grid = oracle_lib.vegas(lo, hi, mu, sg, 20_000, 10, seed=5)
+    g = grid[0]
+    for q, z in ((0.25, -0.6745), (0.5, 0.0), (0.75, 0.6745)):
+        assert abs(g[int(50 * q)] - (mu[0] + z * sg[0])) < 0.02, (q, g[int(50 * q)])
+
+
+def test_vegas_sampling_is_deterministic_per_iteration(oracle_lib):
+    args = ([0.0] * 4, [1.0] * 4, [0.5] * 4, [0.2] * 4, oracle_lib.uniform_grid(4, 50), 5000)
+    a = oracle_lib.vegas_iteration(*args, seed=1, iteration=2)
+    b = oracle_lib.vegas_iteration(*args, seed=1, iteration=2)
+    c = oracle_lib.vegas_iteration(*args, seed=1, iteration=3)
+    assert a[0] == b[0] and np.array_equal(a[2], b[2]) and a[0] != c[0]
+
+
 # --------------------------------------------------- determinism / validation ----
 
 def test_chunking_is_bit_identical(oracle_lib):

@@ -281,9 +281,35 @@ def extras(P, torch, dev, args):
                                  "write_GBs": 104 * n2 / (kms * 1e-3) / 1e9}
     del outm, w
     ex["cfg3_batched_64_channels"] = batched_extra(P, torch, dev, steps)
+    ex["vegas_10d_gaussian"] = vegas_extra(P, torch, dev)
     if args.serve_seconds > 0:
         ex["cfg4_serving"] = serving_extra(P, args.serve_seconds)
     return ex
+
+
+def vegas_extra(P, torch, dev):
+    """VEGAS on the integrand of the paper's VEGAS benchmark, a 10-dimensional
+    Gaussian (here mean 0.5, sigma 0.1 per dimension over the unit cube, 50
+    bins): 5 adapting + 5 estimating iterations of 1e7 calls, and single
+    iterations of 1e7 / 1e8 calls timed on the adapted grid."""
+    import numpy as np
+    D = 10
+    lo, hi, mu, sg = [0.0] * D, [1.0] * D, [0.5] * D, [0.1] * D
+    exact = 1.0
+    for a, b, m, s in zip(lo, hi, mu, sg):
+        exact *= 0.5 * (math.erf((b - m) / (s * math.sqrt(2.0))) - math.erf((a - m) / (s * math.sqrt(2.0))))
+    f = P.gauss_box(lo, hi, mu, sg)
+    t0 = time.perf_counter()
+    res, err, chi2, grid = P.vegas(f, 10_000_000, 5, warmup=5, seed=42)
+    wall = time.perf_counter() - t0
+    g = torch.as_tensor(np.ascontiguousarray(grid), device=dev)
+    r = {"integrand": "10-D Gaussian, mean 0.5, sigma 0.1, unit cube, 50 bins", "exact": exact,
+         "result": res, "error": err, "chi2_dof": chi2, "pull": (res - exact) / err,
+         "driver_s_10_iterations_1e7_calls": wall}
+    for calls in (10_000_000, 100_000_000):
+        ms, k = time_steps(lambda: P.vegas_iteration(f, g, calls, seed=7, iteration=100), 5, 1, torch)
+        r[f"iteration_{calls:.0e}_calls"] = {"kernel_ms": k, "ms": ms, "samples_per_s": calls / (k * 1e-3)}
+    return r
 
 
 def model_extra(P, torch, dev, M, m, n, w, st, steps):

@@ -83,7 +83,7 @@ def _load():
     lib.oracle_model_integrate.restype = ctypes.c_int
     lib.oracle_vegas_iteration.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_uint64,
                                            ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
-                                           ctypes.POINTER(ctypes.c_double), dp]
+                                           ctypes.POINTER(ctypes.c_double), dp, dp]
     lib.oracle_vegas_iteration.restype = ctypes.c_int
     lib.oracle_vegas_refine.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_double]
     lib.oracle_vegas_refine.restype = ctypes.c_int
@@ -246,19 +246,23 @@ def uniform_grid(dim: int, bins: int) -> np.ndarray:
     return np.tile(np.arange(bins + 1, dtype=np.float64) / bins, (dim, 1))
 
 
-def vegas_iteration(lo, hi, mu, sigma, grid, calls, seed=42, iteration=0, want_hist=True):
-    """One VEGAS iteration: (mean, sigma, histogram [dim, bins] or None)."""
+def vegas_iteration(lo, hi, mu, sigma, grid, calls, seed=42, iteration=0, want_hist=True, want_values=False):
+    """One VEGAS iteration: (mean, sigma, histogram [dim, bins] or None), plus the
+    per-sample values as a fourth item when want_values."""
     lib = _load()
     lo, hi, mu, sg = (np.ascontiguousarray(a, dtype=np.float64) for a in (lo, hi, mu, sigma))
     grid = np.ascontiguousarray(grid, dtype=np.float64)
     dim, bins = grid.shape[0], grid.shape[1] - 1
     hist = np.zeros((dim, bins), dtype=np.float64) if want_hist else None
+    vals = np.zeros(calls, dtype=np.float64) if want_values else None
     mean = ctypes.c_double()
     sig = ctypes.c_double()
     st = lib.oracle_vegas_iteration(dim, bins, _ptr(lo), _ptr(hi), _ptr(mu), _ptr(sg), _ptr(grid), calls, seed,
-                                    iteration, ctypes.byref(mean), ctypes.byref(sig), _ptr(hist))
+                                    iteration, ctypes.byref(mean), ctypes.byref(sig), _ptr(hist), _ptr(vals))
     if st != OK:
         raise OracleError(st)
+    if want_values:
+        return mean.value, sig.value, hist, vals
     return mean.value, sig.value, hist
 
 

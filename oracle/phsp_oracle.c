@@ -516,7 +516,7 @@ static double gauss_factor(double x, double mu, double s)
 
 int oracle_vegas_iteration(int dim, int bins, const double *lo, const double *hi, const double *mu,
                            const double *sig, const double *grid, uint64_t calls, uint64_t seed,
-                           uint32_t iteration, double *mean, double *sigma, double *hist)
+                           uint32_t iteration, double *mean, double *sigma, double *hist, double *values)
 {
     if (dim < 1 || dim > ORACLE_VEGAS_DMAX || bins < 1 || bins > ORACLE_VEGAS_KMAX || calls < 2) return ORACLE_EINVAL;
     if (mean == NULL || sigma == NULL || grid == NULL) return ORACLE_EINVAL;
@@ -547,6 +547,7 @@ int oracle_vegas_iteration(int dim, int bins, const double *lo, const double *hi
             binof[d] = b;
         }
         v[i] = val;
+        if (values != NULL) values[i] = val;
         if (hist != NULL)
             for (int d = 0; d < dim; ++d) hist[d * bins + binof[d]] += val * val;
     }

@@ -70,6 +70,12 @@ def _declare(lib):
     lib.hydra_phsp_generate_unweighted.restype = i
     lib.hydra_phsp_integrate_model.argtypes = [d, dp, i, vp, i, u64, u64, u32, u64, vp, vp, vp]
     lib.hydra_phsp_integrate_model.restype = i
+    lib.hydra_phsp_vegas_iteration.argtypes = [vp, i, vp, u64, u64, u32, vp, vp, vp, vp]
+    lib.hydra_phsp_vegas_iteration.restype = i
+    lib.hydra_phsp_vegas_refine.argtypes = [i, i, vp, vp, d]
+    lib.hydra_phsp_vegas_refine.restype = i
+    lib.hydra_phsp_vegas.argtypes = [vp, i, u64, i, i, d, u64, vp, dp, dp, dp, vp]
+    lib.hydra_phsp_vegas.restype = i
 
 
 def lib():
@@ -233,6 +239,63 @@ def integrate_model(parent_mass: float, masses: Sequence[float], nevents: int, r
                                             seed, stream_id, event_offset, _dptr(values), _dptr(stats),
                                             _stream_handle(stream)))
     return stats, values
+
+
+VEGAS_DMAX = 16
+
+
+class GaussBox(ctypes.Structure):
+    """``hydra_phsp_gauss_box``: the product-of-Gaussians integrand over a box."""
+    _fields_ = [("dim", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("lo", ctypes.c_double * VEGAS_DMAX), ("hi", ctypes.c_double * VEGAS_DMAX),
+                ("mean", ctypes.c_double * VEGAS_DMAX), ("sigma", ctypes.c_double * VEGAS_DMAX)]
+
+
+def gauss_box(lo, hi, mean, sigma) -> GaussBox:
+    f = GaussBox()
+    f.dim = len(lo)
+    for k in range(len(lo)):
+        f.lo[k], f.hi[k], f.mean[k], f.sigma[k] = float(lo[k]), float(hi[k]), float(mean[k]), float(sigma[k])
+    return f
+
+
+def vegas_iteration(f: GaussBox, grid: torch.Tensor, calls: int, *, seed: int = 42, iteration: int = 0,
+                    want_hist: bool = True, want_values: bool = False, stream: Optional[torch.cuda.Stream] = None):
+    """One VEGAS iteration on the device grid ([dim, bins+1] float64, asynchronous).
+    Returns (stats, hist or None, values or None) as device tensors."""
+    if grid.dtype != torch.float64 or not grid.is_contiguous() or grid.dim() != 2 or grid.shape[0] != f.dim:
+        raise ValueError("grid must be a contiguous [dim, bins+1] float64 tensor")
+    bins = grid.shape[1] - 1
+    dev = grid.device
+    stats = torch.empty(STATS, dtype=torch.float64, device=dev)
+    hist = torch.empty((f.dim, bins), dtype=torch.float64, device=dev) if want_hist else None
+    vals = torch.empty(max(calls, 1), dtype=torch.float64, device=dev) if want_values else None
+    _check(lib().hydra_phsp_vegas_iteration(ctypes.byref(f), bins, _dptr(grid), calls, seed, iteration, _dptr(stats),
+                                            _dptr(hist), _dptr(vals), _stream_handle(stream)))
+    return stats, hist, vals
+
+
+def vegas_refine(grid, hist, alpha: float = 1.5):
+    """Refined copy of a host grid ([dim, bins+1] numpy float64) from a host histogram."""
+    import numpy as np
+    g = np.array(grid, dtype=np.float64, copy=True, order="C")
+    h = np.ascontiguousarray(hist, dtype=np.float64)
+    _check(lib().hydra_phsp_vegas_refine(g.shape[0], g.shape[1] - 1, g.ctypes.data, h.ctypes.data, float(alpha)))
+    return g
+
+
+def vegas(f: GaussBox, calls: int, iterations: int, *, warmup: int = 0, bins: int = 50, alpha: float = 1.5,
+          seed: int = 42, grid=None, stream: Optional[torch.cuda.Stream] = None):
+    """VEGAS integration (synchronous): returns (result, error, chi2/dof, final grid [dim, bins+1])."""
+    import numpy as np
+    g = np.zeros((f.dim, bins + 1), dtype=np.float64) if grid is None else np.array(grid, dtype=np.float64)
+    if grid is None:
+        g[:] = np.arange(bins + 1) / bins
+    res, err, chi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().hydra_phsp_vegas(ctypes.byref(f), bins, calls, warmup, iterations, float(alpha), seed,
+                                  g.ctypes.data, ctypes.byref(res), ctypes.byref(err), ctypes.byref(chi),
+                                  _stream_handle(stream)))
+    return res.value, err.value, chi.value, g
 
 
 def integrate_async(parent_mass: float, masses: Sequence[float], nevents: int, *, seed: int = 42,

@@ -454,7 +454,8 @@ int hydra_phsp_release(void) {
     const int a = release_batch_slots();
     const int b = release_workspaces(); // synchronizes the device first
     const int c = release_unweight_workspaces();
-    return a != HYDRA_PHSP_OK ? a : (b != HYDRA_PHSP_OK ? b : c);
+    const int d = release_vegas_workspaces();
+    return a != HYDRA_PHSP_OK ? a : (b != HYDRA_PHSP_OK ? b : (c != HYDRA_PHSP_OK ? c : d));
 }
 
 int hydra_phsp_set_events_per_thread(int path, int ept) {

@@ -31,6 +31,7 @@ int block_partials(hipStream_t stream, uint64_t blocks, Moments** partials);
 int merge_partials(hipStream_t stream, const Moments* partials, uint64_t blocks, double* stats_dev);
 int release_workspaces();
 int release_unweight_workspaces();
+int release_vegas_workspaces();
 int release_batch_slots();
 // The device's (cos, sin) table used by the FP64 kernels (created on first use).
 int trig_table(const double2** out);

@@ -235,3 +235,34 @@ def test_model_validation(P):
     assert call([(0, 1, 1.0, 0.1)], k=-1) == P.EINVAL
     assert call([(0, 1, 1.0, 0.1)], vals=ctypes.c_void_p(12)) == P.EINVAL
     assert call([(0, 1, 1.0, 0.1)], M=3.5) == P.EKINEMATICS
+
+
+def test_vegas_validation_and_host_refinement(P):
+    import numpy as np
+    import oracle
+    f = P.gauss_box([0.0] * 3, [1.0] * 3, [0.5] * 3, [0.2] * 3)
+    st = ctypes.c_void_p(64)
+    g = ctypes.c_void_p(128)
+    call = P.lib().hydra_phsp_vegas_iteration
+    assert call(ctypes.byref(f), 1, g, 100, 1, 0, st, None, None, None) == P.EINVAL      # bins < 2
+    assert call(ctypes.byref(f), 129, g, 100, 1, 0, st, None, None, None) == P.EINVAL    # bins > 128
+    assert call(ctypes.byref(f), 50, None, 100, 1, 0, st, None, None, None) == P.EINVAL  # no grid
+    assert call(ctypes.byref(f), 50, g, 100, 1, 0, None, None, None, None) == P.EINVAL   # no stats
+    bad = P.gauss_box([0.0] * 3, [1.0, 0.0, 1.0], [0.5] * 3, [0.2] * 3)
+    assert call(ctypes.byref(bad), 50, g, 100, 1, 0, st, None, None, None) == P.EINVAL   # hi <= lo
+    bad = P.gauss_box([0.0] * 3, [1.0] * 3, [0.5] * 3, [0.2, 0.0, 0.2])
+    assert call(ctypes.byref(bad), 50, g, 100, 1, 0, st, None, None, None) == P.EINVAL   # sigma <= 0
+    bad.dim = 17
+    assert call(ctypes.byref(bad), 50, g, 100, 1, 0, st, None, None, None) == P.EINVAL
+    # the library's host refinement against the oracle's (independent code, same rule)
+    oracle.build(force=False)
+    rng = np.random.default_rng(4)
+    for dim, bins in ((1, 2), (3, 50), (10, 50), (2, 128)):
+        grid = oracle.uniform_grid(dim, bins)
+        for _ in range(4):
+            h = rng.exponential(size=(dim, bins)) * np.exp(-0.5 * ((np.arange(bins) - bins / 3) / (bins / 8)) ** 2)
+            h[:, rng.integers(0, bins)] = 0.0
+            a = P.vegas_refine(grid, h, 1.5)
+            b = oracle.vegas_refine(grid, h, 1.5)
+            assert np.allclose(a, b, rtol=0.0, atol=1e-13), float(np.abs(a - b).max())
+            grid = a

@@ -130,7 +130,7 @@ def main():
                          "kernel of known traffic) x3, then the main step x3; prints no JSON")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 64-channel batched configuration and print its figures")
-    ap.add_argument("--only", choices=["unweighted", "model", "sequential"],
+    ap.add_argument("--only", choices=["unweighted", "model", "sequential", "vegas"],
                     help="run only this extra on the 1e8-event workload and print its figures")
     args = ap.parse_args()
 
@@ -151,6 +151,9 @@ def main():
 
     if args.batched_only:
         print(json.dumps(batched_extra(P, torch, dev, args.steps)), flush=True)
+        return
+    if args.only == "vegas":
+        print(json.dumps(vegas_extra(P, torch, dev)), flush=True)
         return
     if args.only:
         M, m = 5.279, [3.097, 0.4937, 0.13957]

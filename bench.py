@@ -10,7 +10,9 @@ one ``hydra_phsp_generate`` call: the main kernel plus the finalize kernel.
 Prints ONE JSON line.  ``roofline`` uses the main kernel's average duration,
 measured with HIP events recorded by the library on the launch stream over the
 timed region; ``cpu_baseline`` times the CPU oracle on a bounded sample of the
-same workload on this host.  ``extras`` reports the other configurations
+same workload on this host.  ``ceilings`` measures the two rates that bound
+the main kernel with the library's probes: its stores alone (constant data, same
+buffers and launch shape) and its Philox calls alone.  ``extras`` reports the other configurations
 (per-event parents, six-body FP64 vs mixed, integrate-only, batched) when
 their code paths exist.
 """
@@ -223,6 +225,7 @@ def main():
                      "kernel": f"{main_kernel} (N=3, at rest, FP64, {ept} event(s) per thread)",
                      "kernel_ms": ms_kernel},
         "integral": {"mean": stats[1], "sigma": stats[3], "n": stats[0]},
+        "ceilings": ceilings(P, torch, out, w, n_ev, ept, ms_kernel, bytes_per_event, args),
     }
     del out
 
@@ -231,6 +234,44 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
+
+
+def time_launches(fn, steps, warmup, torch):
+    """Mean duration of one launch of ``fn``: a pair of events on the current
+    stream (the stream the probes launch on) around each launch."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    pairs = []
+    for _ in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        pairs.append((a, b))
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in pairs) / steps
+
+
+def ceilings(P, torch, out, w, n, ept, ms_kernel, bytes_per_event, args):
+    """The two rates that bound the generator, measured with the library's
+    probes on the headline workload: the same stores with constant data (same
+    buffers, launch shape and events per thread), and the same Philox calls
+    with nothing else."""
+    cols = out.shape[0] * out.shape[1]
+    flat = out.view(cols, out.shape[2])
+    warm = max(10, args.warmup // 2)
+    ms_w = time_launches(lambda: P.probe_write(flat, w, n, events_per_thread=ept), args.steps, warm, torch)
+    calls = (3 * 3 - 4 + 1) // 2
+    fold = torch.empty((n + P.PROBE_SPAN - 1) // P.PROBE_SPAN, dtype=torch.int32, device=out.device)
+    ms_p = time_launches(lambda: P.probe_philox(n, calls, fold=fold), args.steps, warm, torch)
+    gbs = bytes_per_event * n / (ms_w * 1e-3) / 1e9
+    return {
+        "write": {"kernel": f"k_write_bw<{cols}, {ept}>", "ms": ms_w, "GB/s": gbs, "frac": gbs / PEAK_HBM_GBS,
+                  "generator_over_ceiling": ms_w / ms_kernel},
+        "philox": {"kernel": "k_philox_only", "ms": ms_p, "calls_per_s": n * calls / (ms_p * 1e-3),
+                   "calls_per_event": calls, "events_per_s": n / (ms_p * 1e-3)},
+    }
 
 
 def extras(P, torch, dev, args):

@@ -76,6 +76,10 @@ def _declare(lib):
     lib.hydra_phsp_vegas_refine.restype = i
     lib.hydra_phsp_vegas.argtypes = [vp, i, u64, i, i, d, u64, vp, dp, dp, dp, vp]
     lib.hydra_phsp_vegas.restype = i
+    lib.hydra_phsp_probe_write.argtypes = [vp, u64, i, vp, u64, i, vp]
+    lib.hydra_phsp_probe_write.restype = i
+    lib.hydra_phsp_probe_philox.argtypes = [u64, i, u64, u32, vp, vp]
+    lib.hydra_phsp_probe_philox.restype = i
 
 
 def lib():
@@ -296,6 +300,41 @@ def vegas(f: GaussBox, calls: int, iterations: int, *, warmup: int = 0, bins: in
                                   g.ctypes.data, ctypes.byref(res), ctypes.byref(err), ctypes.byref(chi),
                                   _stream_handle(stream)))
     return res.value, err.value, chi.value, g
+
+
+PROBE_SPAN = 1024
+
+
+def probe_write(out: torch.Tensor, weights: torch.Tensor, nevents: int, *, events_per_thread: int = 1,
+                stream: Optional[torch.cuda.Stream] = None):
+    """Streaming-write probe (asynchronous): the generator's store pattern with
+    constant data.  ``out`` is a contiguous ``[C, ld]`` float64 tensor (``[N, 4, ld]``
+    of a generate call may be passed flattened); column c gets the value c and
+    ``weights`` gets -1 for events < ``nevents``."""
+    if out.dtype != torch.float64 or not out.is_contiguous() or out.dim() < 2:
+        raise ValueError("out must be a contiguous [C, ld] (or [N, 4, ld]) float64 tensor")
+    if weights.dtype != torch.float64 or not weights.is_contiguous():
+        raise ValueError("weights must be a contiguous float64 tensor")
+    ld = out.shape[-1]
+    cols = out.numel() // max(ld, 1)
+    _check(lib().hydra_phsp_probe_write(_dptr(out), ld, cols, _dptr(weights), nevents, events_per_thread,
+                                        _stream_handle(stream)))
+
+
+def probe_philox(nevents: int, calls_per_event: int, *, seed: int = 42, stream_id: int = 0,
+                 fold: Optional[torch.Tensor] = None, device=None, stream: Optional[torch.cuda.Stream] = None):
+    """Philox probe (asynchronous): returns the int32 tensor of per-block
+    exclusive-or folds of every Philox word the generator's events would draw
+    (``PROBE_SPAN`` events per block)."""
+    blocks = (nevents + PROBE_SPAN - 1) // PROBE_SPAN
+    if fold is None:
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        fold = torch.empty(max(blocks, 1), dtype=torch.int32, device=dev)
+    if fold.dtype != torch.int32 or not fold.is_contiguous() or fold.numel() < blocks:
+        raise ValueError(f"fold must be a contiguous int32 tensor of at least {blocks} entries")
+    _check(lib().hydra_phsp_probe_philox(nevents, calls_per_event, seed, stream_id, _dptr(fold),
+                                         _stream_handle(stream)))
+    return fold
 
 
 def integrate_async(parent_mass: float, masses: Sequence[float], nevents: int, *, seed: int = 42,

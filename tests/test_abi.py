@@ -266,3 +266,23 @@ def test_vegas_validation_and_host_refinement(P):
             b = oracle.vegas_refine(grid, h, 1.5)
             assert np.allclose(a, b, rtol=0.0, atol=1e-13), float(np.abs(a - b).max())
             grid = a
+
+
+def test_probe_validation(P):
+    w = P.lib().hydra_phsp_probe_write
+    o, wt = ctypes.c_void_p(256), ctypes.c_void_p(512)
+    assert w(None, 100, 12, wt, 100, 1, None) == P.EINVAL                     # no output
+    assert w(o, 100, 12, None, 100, 1, None) == P.EINVAL                      # no weights
+    assert w(ctypes.c_void_p(260), 100, 12, wt, 100, 1, None) == P.EINVAL     # misaligned
+    assert w(o, 100, 0, wt, 100, 1, None) == P.EINVAL                         # no column
+    assert w(o, 100, 41, wt, 100, 1, None) == P.EINVAL                        # more than 4 NMAX
+    assert w(o, 100, 12, wt, 100, 3, None) == P.EINVAL                        # events per thread
+    assert w(o, 99, 12, wt, 100, 1, None) == P.EINVAL                         # ld < nevents
+    assert w(o, 100, 12, wt, 0, 1, None) == P.OK                              # nothing to enqueue
+    ph = P.lib().hydra_phsp_probe_philox
+    f = ctypes.c_void_p(64)
+    assert ph(100, 3, 1, 0, None, None) == P.EINVAL
+    assert ph(100, 3, 1, 0, ctypes.c_void_p(66), None) == P.EINVAL
+    assert ph(100, 0, 1, 0, f, None) == P.EINVAL
+    assert ph(100, 17, 1, 0, f, None) == P.EINVAL
+    assert ph(0, 3, 1, 0, f, None) == P.OK

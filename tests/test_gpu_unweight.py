@@ -115,6 +115,25 @@ def test_unweighted_capacity_and_count_only(P):
     assert int(counts[0].item()) == full[2] and float(wm.item()) == full[4]
 
 
+def test_unweighted_repeat_and_low_acceptance(P):
+    """A large call repeated, then a smaller one on the same (grown) workspace,
+    must give identical results and the kept trials of the small call must be the
+    prefix of the large call's; a bound far above every weight keeps few trials
+    (most blocks store nothing or a few partial lines)."""
+    _say("repeat / low acceptance")
+    M, m = CFG0
+    a = _gpu(P, M, m, 3_000_017, seed=21, w_max=4.8)
+    b = _gpu(P, M, m, 3_000_017, seed=21, w_max=4.8)
+    assert a[2] == b[2] and a[2] < 2**63 and np.array_equal(a[1], b[1]) and np.array_equal(a[0], b[0])
+    small = _gpu(P, M, m, 100_003, seed=21, w_max=4.8)
+    k = int(np.searchsorted(a[1], 100_003))
+    assert small[2] == k and np.array_equal(small[1], a[1][:k]) and np.array_equal(small[0], a[0][:, :, :k])
+    gp4, gidx, gkept, gover, _ = _gpu(P, M, m, 200_003, seed=5, w_max=480.0)
+    op4, oidx, okept, oover, owm = oracle.unweight(M, m, 200_003, seed=5, w_max=480.0)
+    assert gover == oover == 0 and 0 < okept < 5000
+    _compare(M, m, gp4, gidx, gkept, okept, oidx, op4, owm, 5, 0)
+
+
 @pytest.mark.parametrize("ntrials", [0, 1, 1023, 1024, 1025])
 def test_unweighted_edge_sizes(P, ntrials):
     _say(f"edge {ntrials}")

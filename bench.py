@@ -452,12 +452,15 @@ def batched_extra(P, torch, dev, steps):
         descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id,
                                out=out, weights=w, stats=st))
     t0 = time.perf_counter()
-    ept, gpc, sched, tuned_ms = P.autotune(descs)
+    ept, gpc, sched, nstr, tuned_ms = P.autotune(descs)
     tune_s = time.perf_counter() - t0
-    plan = P.Plan(descs, ept=ept, grid_per_cu=gpc, schedule=sched)
+    plan = P.Plan(descs, ept=ept, grid_per_cu=gpc, schedule=sched, streams=nstr)
     ms_graph, _ = time_steps(plan.launch, steps, 1, torch)
-    ms_direct, kms = time_steps(lambda: P.batch_run(descs, ept=ept, grid_per_cu=gpc, schedule=sched),
+    ms_direct, kms = time_steps(lambda: P.batch_run(descs, ept=ept, grid_per_cu=gpc, schedule=sched, streams=nstr),
                                 steps, 1, torch)
+    # the same shape with the class kernels one after another on one stream
+    ms_direct1, kms1 = time_steps(lambda: P.batch_run(descs, ept=ept, grid_per_cu=gpc, schedule=sched, streams=1),
+                                  steps, 1, torch)
     ntiles, grid = plan.info()
     plan.destroy()
     P.release()
@@ -471,22 +474,24 @@ def batched_extra(P, torch, dev, steps):
         keep.append((out, w, st))
         descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id,
                                out=out, weights=w, stats=st))
-    ept_u, gpc_u, sched_u, _ = P.autotune(descs)  # off the line grid: its own classes and shape
-    _, kms_unaligned = time_steps(lambda: P.batch_run(descs, ept=ept_u, grid_per_cu=gpc_u, schedule=sched_u),
-                                  steps, 1, torch)
+    ept_u, gpc_u, sched_u, nstr_u, _ = P.autotune(descs)  # off the line grid: its own classes and shape
+    _, kms_unaligned = time_steps(lambda: P.batch_run(descs, ept=ept_u, grid_per_cu=gpc_u, schedule=sched_u,
+                                                      streams=nstr_u), steps, 1, torch)
     P.release()
     del keep, descs
     return {"channels": len(specs), "events": total_events, "bytes": total_bytes,
             "tuning": {"ept": ept, "grid_per_cu": gpc, "schedule": ["static", "dynamic", "one block per tile"][sched],
-                       "autotune_s": tune_s, "tiles": ntiles,
+                       "streams": max(nstr, 1), "autotune_s": tune_s, "tiles": ntiles,
                        "grid": grid},
+            "kernel_ms_one_stream": kms1, "ms_per_step_direct_one_stream": ms_direct1,
             "events_per_s_graph": total_events / (ms_graph * 1e-3), "ms_per_step_graph": ms_graph,
             "kernel_ms": kms, "kernel_write_GBs": total_bytes / (kms * 1e-3) / 1e9,
             "kernel_frac_of_8TBs": total_bytes / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "ms_per_step_direct": ms_direct, "ld": "aligned_ld(nevents)",
             "kernel_ms_ld_eq_nevents": kms_unaligned,
             "tuning_ld_eq_nevents": {"ept": ept_u, "grid_per_cu": gpc_u,
-                                     "schedule": ["static", "dynamic", "one block per tile"][sched_u]},
+                                     "schedule": ["static", "dynamic", "one block per tile"][sched_u],
+                                     "streams": max(nstr_u, 1)},
             "kernel_write_GBs_ld_eq_nevents": total_bytes / (kms_unaligned * 1e-3) / 1e9}
 
 

@@ -50,13 +50,23 @@ typedef struct hydra_phsp_channel {
  *                1: persistent grid, blocks claim tiles in order from a
  *                   device counter;
  *                2: one block per tile (grid = tile count, grid_per_cu is
- *                   ignored), so the hardware dispatches tiles in order.
+ *                   ignored), so the hardware dispatches tiles in order;
+ *   streams      0 or 1: the class kernels run one after another on the
+ *                caller's stream; 2 .. HYDRA_PHSP_MAX_CLASS_STREAMS: they are
+ *                spread over that many streams (the caller's and the plan's
+ *                own, forked from and joined back into the caller's stream
+ *                with events, largest classes first onto the least loaded
+ *                stream), so kernels of different classes -- memory-bound
+ *                small N beside arithmetic-bound large N -- can run at the
+ *                same time.  Results do not depend on it (classes write
+ *                disjoint outputs and partials; the merges follow the join).
  * A zero grid_per_cu selects the library default (8). */
+#define HYDRA_PHSP_MAX_CLASS_STREAMS 4
 typedef struct hydra_phsp_tuning {
     int32_t ept;
     int32_t grid_per_cu;
     int32_t schedule;
-    int32_t reserved;
+    int32_t streams;
 } hydra_phsp_tuning;
 
 /* Enqueue one batch on `stream`: validates every channel (no work is enqueued
@@ -84,8 +94,9 @@ int hydra_phsp_plan_info(const hydra_phsp_plan *plan, uint64_t *ntiles_out, uint
 
 /* Autotuner: times the batch (kernels and merges) over schedule
  * {static, dynamic} x events per thread {per class, 1, 2, 4} x blocks per
- * compute unit {1, 2, 4, 8, 16}, plus one block per tile x events per thread
- * -- two warm-up
+ * compute unit {1, 2, 4, 8, 16}, plus one block per tile x events per thread,
+ * on one stream, then the best of those on 2 .. HYDRA_PHSP_MAX_CLASS_STREAMS
+ * streams -- two warm-up
  * runs and five timed runs per shape, overwriting the batch's outputs -- and
  * returns the shape with the fastest run and that run's time in ms.  Results
  * are cached per device and batch shape class (channel count, largest N,

@@ -415,10 +415,11 @@ class ChannelDesc(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     """``hydra_phsp_tuning``: events per thread (0 = per class, as a single-channel call),
-    persistent blocks per CU (0 = default) and
-    tile schedule (0 static stride, 1 dynamic, 2 one block per tile)."""
+    persistent blocks per CU (0 = default),
+    tile schedule (0 static stride, 1 dynamic, 2 one block per tile) and the
+    number of streams the class kernels are spread over (0 or 1 = one)."""
     _fields_ = [("ept", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("streams", ctypes.c_int32)]
 
 
 def _declare_batch(lib):
@@ -465,20 +466,22 @@ def _channel_array(chans):
     return arr
 
 
-def _tuning(ept=0, grid_per_cu=0, schedule=0):
+def _tuning(ept=0, grid_per_cu=0, schedule=0, streams=0):
     t = Tuning()
     t.ept = ept
     t.grid_per_cu = grid_per_cu
     t.schedule = schedule
+    t.streams = streams
     return t
 
 
-def batch_run(chans, *, ept: int = 0, grid_per_cu: int = 0, schedule: int = 0, stream=None):
+def batch_run(chans, *, ept: int = 0, grid_per_cu: int = 0, schedule: int = 0, streams: int = 0,
+              stream=None):
     """Enqueue one batch (all channels; one launch per (daughter count, mode) class)."""
     L = lib()
     arr = _channel_array(chans)
     bad = ctypes.c_int(-1)
-    t = _tuning(ept, grid_per_cu, schedule)
+    t = _tuning(ept, grid_per_cu, schedule, streams)
     st = L.hydra_phsp_batch_run(arr, len(chans), ctypes.byref(t), _stream_handle(stream), ctypes.byref(bad))
     if st != OK:
         msg = L.hydra_phsp_last_error().decode(errors="replace")
@@ -488,10 +491,10 @@ def batch_run(chans, *, ept: int = 0, grid_per_cu: int = 0, schedule: int = 0, s
 class Plan:
     """A batch captured into a HIP graph; launch() replays it."""
 
-    def __init__(self, chans, *, ept: int = 0, grid_per_cu: int = 0, schedule: int = 0):
+    def __init__(self, chans, *, ept: int = 0, grid_per_cu: int = 0, schedule: int = 0, streams: int = 0):
         L = lib()
         arr = _channel_array(chans)
-        t = _tuning(ept, grid_per_cu, schedule)
+        t = _tuning(ept, grid_per_cu, schedule, streams)
         h = ctypes.c_void_p()
         _check(L.hydra_phsp_plan_create(arr, len(chans), ctypes.byref(t), ctypes.byref(h)))
         self._h = h
@@ -517,12 +520,12 @@ class Plan:
 
 
 def autotune(chans, stream=None):
-    """(ept, grid_per_cu, schedule, ms) of the fastest launch shape for this batch."""
+    """(ept, grid_per_cu, schedule, streams, ms) of the fastest launch shape for this batch."""
     t = Tuning()
     ms = ctypes.c_double()
     _check(lib().hydra_phsp_autotune(_channel_array(chans), len(chans), _stream_handle(stream),
                                      ctypes.byref(t), ctypes.byref(ms)))
-    return t.ept, t.grid_per_cu, t.schedule, ms.value
+    return t.ept, t.grid_per_cu, t.schedule, t.streams, ms.value
 
 
 # ----------------------------------------------------------------- serving ----

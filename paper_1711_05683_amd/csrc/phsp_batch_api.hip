@@ -81,6 +81,11 @@ struct hydra_phsp_plan {
     GroupRef* d_groups = nullptr;
     Moments* d_partials = nullptr;
     Moments* d_mid = nullptr;
+    int nstreams = 1;                        // streams the class kernels are spread over
+    int class_stream[hphsp::kClasses] = {};  // 0: the caller's stream, i > 0: aux[i - 1]
+    hipStream_t aux[HYDRA_PHSP_MAX_CLASS_STREAMS - 1] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[HYDRA_PHSP_MAX_CLASS_STREAMS - 1] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -161,6 +166,11 @@ static void free_plan(hydra_phsp_plan* p) {
     if (p->d_partials) (void)hipFree(p->d_partials);
     if (p->d_mid) (void)hipFree(p->d_mid);
     if (p->d_counters) (void)hipFree(p->d_counters);
+    for (int i = 0; i < HYDRA_PHSP_MAX_CLASS_STREAMS - 1; ++i) {
+        if (p->join[i]) (void)hipEventDestroy(p->join[i]);
+        if (p->aux[i]) (void)hipStreamDestroy(p->aux[i]);
+    }
+    if (p->fork) (void)hipEventDestroy(p->fork);
     delete p;
 }
 
@@ -173,11 +183,20 @@ static int enqueue_plan(hydra_phsp_plan* p, hipStream_t s, bool timed) {
             hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, p->d_counters, kClasses);
             e = hipGetLastError();
         }
+        // fork: the plan's other streams start after everything before on s
+        if (e == hipSuccess && p->nstreams > 1) e = hipEventRecord(p->fork, s);
+        for (int i = 0; i + 1 < p->nstreams && e == hipSuccess; ++i) e = hipStreamWaitEvent(p->aux[i], p->fork, 0);
         for (int c = 0; c < kClasses && e == hipSuccess; ++c) {
             if (p->class_count[c] == 0) continue;
             BatchLaunch b{p->d_chans, p->d_tiles + p->class_begin[c], p->class_count[c], p->class_grid[c], p->trig,
                           p->dynamic ? p->d_counters + c : nullptr};
-            e = launch_batch_class(class_n(c), class_mode(c), class_kind(c) == kKindStaged, p->class_ept[c], b, s);
+            const hipStream_t cs = p->class_stream[c] == 0 ? s : p->aux[p->class_stream[c] - 1];
+            e = launch_batch_class(class_n(c), class_mode(c), class_kind(c) == kKindStaged, p->class_ept[c], b, cs);
+        }
+        // join: s continues (merges) after every class kernel
+        for (int i = 0; i + 1 < p->nstreams && e == hipSuccess; ++i) {
+            e = hipEventRecord(p->join[i], p->aux[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join[i], 0);
         }
         timing_end(s, slot);
         if (e != hipSuccess) return fail_hip(e, "batched kernel launch");
@@ -199,18 +218,59 @@ static int upload(T** dst, const std::vector<T>& src) {
     return HYDRA_PHSP_OK;
 }
 
+// Spread the classes present over `nstreams` streams: largest class first onto
+// the least loaded stream, a class's load being its events times its bytes per
+// event (4N+1 doubles; an integrate-only class counts N + 1 for its
+// arithmetic).  Stream 0 is the caller's; the others and the fork / join events
+// belong to the plan.  Fewer classes than streams use only as many streams.
+static int assign_class_streams(hydra_phsp_plan* p, int nstreams) {
+    int present = 0;
+    for (int c = 0; c < kClasses; ++c) present += p->class_count[c] > 0 ? 1 : 0;
+    p->nstreams = std::max(1, std::min(nstreams, present));
+    for (int c = 0; c < kClasses; ++c) p->class_stream[c] = 0;
+    if (p->nstreams == 1) return HYDRA_PHSP_OK;
+    hipError_t e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    for (int i = 0; i + 1 < p->nstreams && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&p->aux[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return fail_hip(e, "class stream creation");
+    double cost[kClasses];
+    int order[kClasses];
+    for (int c = 0; c < kClasses; ++c) {
+        const double per = class_mode(c) == kIntegrate ? (double)(class_n(c) + 1) : (double)(4 * class_n(c) + 1);
+        cost[c] = (double)p->class_count[c] * (double)p->class_ept[c] * per;
+        order[c] = c;
+    }
+    std::stable_sort(order, order + kClasses, [&](int a, int b) { return cost[a] > cost[b]; });
+    double load[HYDRA_PHSP_MAX_CLASS_STREAMS] = {};
+    for (int k = 0; k < kClasses; ++k) {
+        const int c = order[k];
+        if (p->class_count[c] == 0) continue;
+        int best = 0;
+        for (int i = 1; i < p->nstreams; ++i)
+            if (load[i] < load[best]) best = i;
+        p->class_stream[c] = best;
+        load[best] += cost[c];
+    }
+    return HYDRA_PHSP_OK;
+}
+
 static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp_tuning* tuning,
                       hydra_phsp_plan** out, int* bad) {
     if (bad) *bad = -1;
     if (chans == nullptr || nch <= 0) return fail(HYDRA_PHSP_EINVAL, "need at least one channel");
     if (out == nullptr) return fail(HYDRA_PHSP_EINVAL, "plan_out is NULL");
-    int ept = 0, gpc = 8, dyn = 0;
+    int ept = 0, gpc = 8, dyn = 0, nstreams = 1;
     if (tuning) {
         if (tuning->ept) ept = tuning->ept;
         if (tuning->grid_per_cu) gpc = tuning->grid_per_cu;
         dyn = tuning->schedule;
+        if (tuning->streams) nstreams = tuning->streams;
     }
     if (dyn < 0 || dyn > 2) return fail(HYDRA_PHSP_EINVAL, "tuning schedule must be 0, 1 or 2");
+    if (nstreams < 1 || nstreams > HYDRA_PHSP_MAX_CLASS_STREAMS)
+        return fail(HYDRA_PHSP_EINVAL, "tuning streams must be in [0, HYDRA_PHSP_MAX_CLASS_STREAMS]");
     if (ept != 0 && ept != 1 && ept != 2 && ept != 4)
         return fail(HYDRA_PHSP_EINVAL, "tuning ept must be 0, 1, 2 or 4");
     // Events per thread per class: the given value, or (0) what a single-channel
@@ -326,6 +386,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
         if (e != hipSuccess) st = fail_hip(e, "hipEventCreate");
     }
+    if (st == HYDRA_PHSP_OK) st = assign_class_streams(p, nstreams);
     if (st != HYDRA_PHSP_OK) {
         free_plan(p);
         return st;
@@ -543,6 +604,36 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
                 best_ms = fastest;
                 best = t;
             }
+        }
+    }
+    // the best one-stream shape with its classes spread over more streams
+    const hydra_phsp_tuning one = best;
+    for (int ns = 2; ns <= HYDRA_PHSP_MAX_CLASS_STREAMS && st == HYDRA_PHSP_OK; ++ns) {
+        hydra_phsp_tuning t = one;
+        t.streams = ns;
+        hydra_phsp_plan* p = nullptr;
+        st = build_plan(channels, n_channels, &t, &p, nullptr);
+        if (st != HYDRA_PHSP_OK) break;
+        if (p->nstreams < ns) { // fewer classes than streams: same as a smaller count
+            free_plan(p);
+            break;
+        }
+        for (int r = 0; r < 2 && st == HYDRA_PHSP_OK; ++r) st = enqueue_plan(p, s, false);
+        float fastest = 1e30f;
+        for (int r = 0; r < 5 && st == HYDRA_PHSP_OK; ++r) {
+            (void)hipEventRecord(a, s);
+            st = enqueue_plan(p, s, false);
+            (void)hipEventRecord(b, s);
+            if (hipEventSynchronize(b) != hipSuccess) st = fail(HYDRA_PHSP_EDEVICE, "autotune sync failed");
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            fastest = std::min(fastest, ms);
+        }
+        (void)hipStreamSynchronize(s);
+        free_plan(p);
+        if (st == HYDRA_PHSP_OK && fastest < best_ms) {
+            best_ms = fastest;
+            best = t;
         }
     }
     (void)hipEventDestroy(a);

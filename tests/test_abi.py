@@ -167,6 +167,15 @@ int main(void) {
     assert got == want
 
 
+def test_batch_tuning_validation(P):
+    good = P.channel(5.0, [1.0, 1.0], 10, stats=None)
+    good.stats_dev = 8  # fake device pointer: validation happens before any device work
+    arr = P._channel_array([good])
+    for kw in ({"streams": 5}, {"streams": -1}, {"schedule": 3}, {"ept": 3}, {"grid_per_cu": 65}):
+        t = P._tuning(**kw)
+        assert P.lib().hydra_phsp_batch_run(arr, 1, ctypes.byref(t), None, None) == P.EINVAL, kw
+
+
 def test_batch_validation_names_bad_channel(P):
     good = P.channel(5.0, [1.0, 1.0], 10, stats=None)
     good.stats_dev = 8  # fake device pointer: validation happens before any device work

@@ -108,6 +108,45 @@ def test_batch_tuning_variants(P, ept, gpc, sched):
     _compare_with_single(P, specs, bufs, ept)
 
 
+@pytest.mark.parametrize("streams,sched", [(2, 2), (3, 2), (4, 2), (4, 0), (3, 1)])
+def test_batch_class_streams(P, streams, sched):
+    """Class kernels spread over several streams: the same events, weights and
+    integrals as single-channel calls (every class of N up to 10, both modes)."""
+    _say(f"batch classes over {streams} streams, schedule={sched}")
+    specs, bufs, descs = _channels(P, n_channels=24, seed=41 + streams, nmax=10, integrate_every=4)
+    P.batch_run(descs, schedule=sched, grid_per_cu=0 if sched == 2 else 4, streams=streams)
+    torch.cuda.synchronize()
+    _compare_with_single(P, specs, bufs, 0)
+
+
+def test_plan_graph_with_class_streams(P):
+    """A plan whose class kernels sit on parallel graph branches replays to the
+    eager one-stream result, with eager work between replays."""
+    _say("graph replays, classes over 3 streams")
+    specs, bufs, descs = _channels(P, n_channels=16, seed=13, nmax=10)
+    P.batch_run(descs, streams=1)
+    torch.cuda.synchronize()
+    ref = [(None if o is None else o.clone(), None if w is None else w.clone(), s.clone()) for o, w, s in bufs]
+    plan = P.Plan(descs, streams=3)
+    for rep in range(3):
+        for o, w, s in bufs:
+            if o is not None:
+                o.fill_(float("nan"))
+                w.fill_(float("nan"))
+            s.fill_(float("nan"))
+        P.integrate_async(5.279, [3.097, 0.4937, 0.13957], 100_000, seed=rep)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        for i, (o, w, s) in enumerate(bufs):
+            ro, rw, rs = ref[i]
+            n = specs[i].nevents
+            if o is not None:
+                assert torch.equal(o[:, :, :n], ro[:, :, :n]) and torch.equal(w[:n], rw[:n]), (rep, i)
+            assert torch.equal(s, rs), (rep, i)
+    plan.destroy()
+
+
 def test_batch_default_shape_matches_single_channel_defaults(P):
     _say("batch ept 0 (per class) vs single-channel defaults, N up to 10, both modes")
     specs, bufs, descs = _channels(P, n_channels=24, seed=31, nmax=10, integrate_every=4)
@@ -177,13 +216,13 @@ def test_plan_graph_replays(P):
 def test_autotune(P):
     _say("autotune")
     specs, bufs, descs = _channels(P, n_channels=16, seed=5, log_events=(3.0, 5.0))
-    ept, gpc, sched, ms = P.autotune(descs)
-    assert ept in (0, 1, 2, 4) and sched in (0, 1, 2) and ms > 0
+    ept, gpc, sched, nstr, ms = P.autotune(descs)
+    assert ept in (0, 1, 2, 4) and sched in (0, 1, 2) and nstr in (0, 1, 2, 3, 4) and ms > 0
     assert (gpc == 0) if sched == 2 else (1 <= gpc <= 16)
     # cached: same answer
-    assert P.autotune(descs) == (ept, gpc, sched, ms)
+    assert P.autotune(descs) == (ept, gpc, sched, nstr, ms)
     # the tuned shape still gives the single-channel events
-    P.batch_run(descs, ept=ept, grid_per_cu=gpc, schedule=sched)
+    P.batch_run(descs, ept=ept, grid_per_cu=gpc, schedule=sched, streams=nstr)
     torch.cuda.synchronize()
     _compare_with_single(P, specs, bufs, ept)
 

@@ -170,7 +170,10 @@ int hydra_phsp_events_per_thread(int path, int n_daughters, int per_event_parent
 int hydra_phsp_timing_enable(int on);
 int hydra_phsp_timing_read(double *total_ms_host, uint64_t *launches_host);
 int hydra_phsp_timing_reset(void);
-/* Free the library's cached device workspaces (block partials). */
+/* Free every cached device workspace of the library (single-channel block
+ * partials, the tables of the last batch per stream, the unweighting and VEGAS
+ * workspaces), after synchronising the device.  Not to be called while another
+ * thread is inside a library call; later calls allocate afresh. */
 int hydra_phsp_release(void);
 
 #ifdef __cplusplus

@@ -2,6 +2,7 @@
 // per-channel constants, workspace management and launches.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -255,9 +256,9 @@ static hipError_t launch_by_n(int n, const LaunchSpec& s, const KArgs& a, hipStr
 // lane for N = 3 (and for per-event parents, which also read), two for N = 2,
 // and four for N = 4..7, where the per-event work dominates; for N >= 8 the
 // register footprint of several events in flight costs more than it saves.
-static int g_ept_override[3] = {0, 0, 0};
+static std::atomic<int> g_ept_override[3] = {{0}, {0}, {0}}; // read by launches on any thread
 static int default_ept(int mode, int n, int pmode) {
-    const int o = g_ept_override[mode];
+    const int o = g_ept_override[mode].load(std::memory_order_relaxed);
     if (o > 0) return o;
     if (mode == kIntegrate) return 4;
     if (mode == kMixed) return n == 2 ? 2 : 4;
@@ -461,7 +462,7 @@ int hydra_phsp_release(void) {
 int hydra_phsp_set_events_per_thread(int path, int ept) {
     if (path < 0 || path > 2) return fail(HYDRA_PHSP_EINVAL, "path must be 0, 1 or 2");
     if (ept != 0 && ept != 1 && ept != 2 && ept != 4) return fail(HYDRA_PHSP_EINVAL, "ept must be 0, 1, 2 or 4");
-    g_ept_override[path] = ept;
+    g_ept_override[path].store(ept, std::memory_order_relaxed);
     return HYDRA_PHSP_OK;
 }
 

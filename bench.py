@@ -48,10 +48,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel: str = ""):
+def read_traffic(kernel: str = "", algorithmic_bytes: float = 0.0):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when missing, taken on a different kernel source, or on another instantiation
-    than `kernel` (e.g. another events-per-thread setting)."""
+    when missing, taken on a different kernel source, on another instantiation
+    than `kernel` (e.g. another events-per-thread setting), or on a launch of
+    another size than `algorithmic_bytes` (when given)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     fields = {}
@@ -65,6 +66,9 @@ def read_traffic(kernel: str = ""):
     if kernel and kernel not in fields.get("kernel", ""):
         return None
     try:
+        if algorithmic_bytes and abs(float(fields["algorithmic_bytes_per_launch"]) - algorithmic_bytes) > \
+                1e-6 * algorithmic_bytes:
+            return None
         return float(fields["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
@@ -201,7 +205,7 @@ def main():
     stats = st.cpu().tolist()
     ept = P.events_per_thread(1, 3)
     main_kernel = f"k_phsp<3, 0, 1, {ept}>"
-    traffic = read_traffic(main_kernel)
+    traffic = read_traffic(main_kernel, float(bytes_per_event * n_ev))
 
     result = {
         "metric": METRIC,

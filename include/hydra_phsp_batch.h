@@ -102,7 +102,11 @@ int hydra_phsp_plan_info(const hydra_phsp_plan *plan, uint64_t *ntiles_out, uint
  * are cached per device and batch shape class (channel count, largest N,
  * integrate-only and off-line-grid channel counts, total events to a quarter
  * octave) for the life of the process; a cached answer is returned without
- * running. */
+ * running.  When the environment variable HYDRA_PHSP_TUNE_CACHE names a file,
+ * answers are also looked up in it (after the process's own cache) and new ones
+ * appended to it, one text line per device architecture and compute-unit
+ * count and shape class, so later processes skip the sweep; a missing or
+ * unwritable file is ignored. */
 int hydra_phsp_autotune(const hydra_phsp_channel *channels, int n_channels, void *stream,
                         hydra_phsp_tuning *best_out, double *best_ms_out);
 

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -472,6 +474,70 @@ static TuneKey tune_key(const hydra_phsp_channel* chans, int nch, int dev) {
     return k;
 }
 
+// ----------------------------------------------- persistent tuning cache ----
+// With HYDRA_PHSP_TUNE_CACHE naming a file, autotune results are looked up in
+// it and appended to it, one text line per (device architecture and compute
+// units, shape class):
+//   hydra_phsp_tune 1 <device> <nch> <nmax> <integrate_only> <staged> <bucket> <ept> <grid_per_cu> <schedule> <streams> <ms>
+
+static std::string device_tag(int dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
+    std::string tag = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
+    for (char& ch : tag)
+        if (ch == ' ' || ch == '\t' || ch == '\n') ch = '_';
+    return tag;
+}
+
+static bool tuning_valid(const hydra_phsp_tuning& t) {
+    return (t.ept == 0 || t.ept == 1 || t.ept == 2 || t.ept == 4) && t.schedule >= 0 && t.schedule <= 2 &&
+           t.grid_per_cu >= 0 && t.grid_per_cu <= 64 && t.streams >= 0 && t.streams <= HYDRA_PHSP_MAX_CLASS_STREAMS;
+}
+
+static bool tune_file_lookup(const TuneKey& k, hydra_phsp_tuning* t, double* ms) {
+    const char* path = std::getenv("HYDRA_PHSP_TUNE_CACHE");
+    if (path == nullptr || *path == 0) return false;
+    const std::string tag = device_tag(k.device);
+    if (tag.empty()) return false;
+    FILE* f = std::fopen(path, "r");
+    if (f == nullptr) return false;
+    char line[512], dtag[256];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f) != nullptr) {
+        int ver = 0, nch = 0, nmax = 0, integ = 0, staged = 0;
+        long long bucket = 0;
+        hydra_phsp_tuning r{};
+        double m = 0.0;
+        if (std::sscanf(line, "hydra_phsp_tune %d %255s %d %d %d %d %lld %d %d %d %d %lf", &ver, dtag, &nch, &nmax,
+                        &integ, &staged, &bucket, &r.ept, &r.grid_per_cu, &r.schedule, &r.streams, &m) != 12)
+            continue;
+        if (ver != 1 || tag != dtag || nch != k.nch || nmax != k.nmax || integ != k.integrate_only ||
+            staged != k.staged || bucket != (long long)k.events_bucket || !tuning_valid(r) || !(m > 0.0))
+            continue;
+        *t = r; // the last matching line wins
+        *ms = m;
+        found = true;
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void tune_file_append(const TuneKey& k, const hydra_phsp_tuning& t, double ms) {
+    const char* path = std::getenv("HYDRA_PHSP_TUNE_CACHE");
+    if (path == nullptr || *path == 0) return;
+    const std::string tag = device_tag(k.device);
+    if (tag.empty()) return;
+    char line[512];
+    const int len = std::snprintf(line, sizeof(line), "hydra_phsp_tune 1 %s %d %d %d %d %lld %d %d %d %d %.9g\n",
+                                  tag.c_str(), k.nch, k.nmax, k.integrate_only, k.staged, (long long)k.events_bucket,
+                                  t.ept, t.grid_per_cu, t.schedule, t.streams, ms);
+    if (len <= 0 || len >= (int)sizeof(line)) return;
+    FILE* f = std::fopen(path, "a");
+    if (f == nullptr) return; // the cache is an optimisation: an unwritable file is ignored
+    std::fputs(line, f);      // one write of one short line per result
+    std::fclose(f);
+}
+
 } // namespace hphsp
 
 extern "C" {
@@ -569,6 +635,14 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
             *best_ms_out = it->second.second;
             return HYDRA_PHSP_OK;
         }
+        hydra_phsp_tuning t{};
+        double ms = 0.0;
+        if (tune_file_lookup(key, &t, &ms)) {
+            g_tune_cache[key] = std::make_pair(t, ms);
+            *best_out = t;
+            *best_ms_out = ms;
+            return HYDRA_PHSP_OK;
+        }
     }
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t a = nullptr, b = nullptr;
@@ -642,6 +716,7 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tune_cache[key] = std::make_pair(best, best_ms);
+        tune_file_append(key, best, best_ms);
     }
     *best_out = best;
     *best_ms_out = best_ms;

@@ -227,6 +227,33 @@ def test_autotune(P):
     _compare_with_single(P, specs, bufs, ept)
 
 
+def test_autotune_file_cache(P, tmp_path, monkeypatch):
+    """HYDRA_PHSP_TUNE_CACHE: a sweep's answer is appended to the file, and a
+    line written for another shape class is returned without a sweep."""
+    import math
+    _say("autotune file cache")
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("HYDRA_PHSP_TUNE_CACHE", str(path))
+    _, _, descs = _channels(P, n_channels=7, seed=77, log_events=(3.0, 4.0))
+    ept, gpc, sched, nstr, ms = P.autotune(descs)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    f = lines[0].split()
+    assert f[:2] == ["hydra_phsp_tune", "1"] and f[3] == "7"
+    assert [int(x) for x in f[8:12]] == [ept, gpc, sched, nstr] and abs(float(f[12]) - ms) <= 1e-8 * ms
+    # another shape class (nine channels): its key, as the library forms it
+    _, _, descs2 = _channels(P, n_channels=9, seed=78, log_events=(3.0, 4.0))
+    nmax = max(d.n_daughters for d in descs2)
+    integ = sum(1 for d in descs2 if not d.p4_out_dev)
+    staged = sum(1 for d in descs2 if d.p4_out_dev and not (d.p4_out_dev % 128 == 0 and (d.ld * 8) % 128 == 0
+                                                          and d.weights_dev % 128 == 0))
+    bucket = math.floor(4.0 * math.log2(sum(d.nevents for d in descs2) + 1.0) + 0.5)
+    with open(path, "a") as fh:
+        fh.write(f"hydra_phsp_tune 1 {f[2]} 9 {nmax} {integ} {staged} {bucket} 2 3 1 2 0.123\n")
+    assert P.autotune(descs2) == (2, 3, 1, 2, 0.123)
+    assert len(path.read_text().splitlines()) == 2  # nothing appended: no sweep ran
+
+
 def test_config3_full_batch(P):
     _say("config3: 64 channels, one persistent launch")
     from paper_1711_05683_amd.workloads import batched_channels

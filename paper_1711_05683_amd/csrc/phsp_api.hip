@@ -275,7 +275,7 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
                hipStream_t stream, int ept_override) {
     const int ept = ept_override > 0 ? ept_override : default_ept(mode, n, pmode);
     const uint64_t per_block = (uint64_t)kBlock * (uint64_t)ept;
-    const uint64_t blocks = (nevents + per_block - 1) / per_block;
+    const uint64_t blocks = ceil_div(nevents, per_block);
     if (blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
         return fail(HYDRA_PHSP_EINVAL, "nevents too large for one launch (more than 2^32 - 1 threads)");
     Workspace* ws = nullptr;

@@ -10,6 +10,10 @@
 
 namespace hphsp {
 
+// ceil(a / b) for b > 0, without the overflow of (a + b - 1) / b near 2^64
+// (event counts come from callers unchecked).
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return a / b + (a % b != 0 ? 1 : 0); }
+
 int fail(int status, const std::string& msg);
 int fail_hip(hipError_t e, const char* what);
 // Validate (M, masses, n) and fill the per-channel constants.

@@ -298,7 +298,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         }
         const uint64_t tile_events =
             (uint64_t)kBlock * (uint64_t)class_ept[class_of(c.n_daughters, channel_kind(c))];
-        const uint64_t nt = (c.nevents + tile_events - 1) / tile_events;
+        const uint64_t nt = ceil_div(c.nevents, tile_events);
         if (nt > 0xFFFFFFFFull) return fail(HYDRA_PHSP_EINVAL, "channel too large");
         DevChannel d;
         std::memset(&d, 0, sizeof(d));

@@ -61,7 +61,7 @@ extern "C" int hydra_phsp_integrate_model(double parent_mass, const double* mass
         m.bg[k] = r.width;
     }
     const uint64_t span = (uint64_t)kBlock * (uint64_t)kModelEpt;
-    const uint64_t blocks = (nevents + span - 1) / span;
+    const uint64_t blocks = ceil_div(nevents, span);
     if (blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
         return fail(HYDRA_PHSP_EINVAL, "nevents too large for one launch (more than 2^32 - 1 threads)");
     hipStream_t s = (hipStream_t)stream;

@@ -99,7 +99,7 @@ int hydra_phsp_probe_write(double* out_dev, uint64_t ld, int n_columns, double* 
         return fail(HYDRA_PHSP_EINVAL, "events_per_thread must be 1, 2 or 4");
     if (ld < nevents) return fail(HYDRA_PHSP_EINVAL, "ld must be >= nevents");
     const uint64_t span = (uint64_t)kProbeBlock * (uint64_t)events_per_thread;
-    const uint64_t blocks = (nevents + span - 1) / span;
+    const uint64_t blocks = ceil_div(nevents, span);
     if (blocks > 0xFFFFFFFFull / (uint64_t)kProbeBlock)
         return fail(HYDRA_PHSP_EINVAL, "nevents too large for one launch (more than 2^32 - 1 threads)");
     if (blocks == 0) return HYDRA_PHSP_OK;
@@ -126,7 +126,7 @@ int hydra_phsp_probe_philox(uint64_t nevents, int calls_per_event, uint64_t seed
     if (fold_dev == nullptr) return fail(HYDRA_PHSP_EINVAL, "fold_dev is required");
     if ((uintptr_t)fold_dev % 4) return fail(HYDRA_PHSP_EINVAL, "fold_dev must be 4-byte aligned");
     if (calls_per_event < 1 || calls_per_event > 16) return fail(HYDRA_PHSP_EINVAL, "calls_per_event must be in [1, 16]");
-    const uint64_t blocks = (nevents + HYDRA_PHSP_PROBE_SPAN - 1) / HYDRA_PHSP_PROBE_SPAN;
+    const uint64_t blocks = ceil_div(nevents, HYDRA_PHSP_PROBE_SPAN);
     if (blocks > 0xFFFFFFFFull / (uint64_t)kProbeBlock)
         return fail(HYDRA_PHSP_EINVAL, "nevents too large for one launch (more than 2^32 - 1 threads)");
     if (blocks == 0) return HYDRA_PHSP_OK;

@@ -226,7 +226,7 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
         pmode = kBroadcast;
     }
     const uint64_t span = (uint64_t)kBlock * (uint64_t)kUnwEpt;
-    const uint64_t blocks = (ntrials + span - 1) / span;
+    const uint64_t blocks = ceil_div(ntrials, span);
     if (blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
         return fail(HYDRA_PHSP_EINVAL, "ntrials too large for one launch (more than 2^32 - 1 threads)");
 

@@ -185,7 +185,7 @@ int vegas_iteration(const hydra_phsp_gauss_box* f, int bins, const double* grid_
                     uint32_t iteration, double* stats_dev, double* hist_dev, double* values_dev, hipStream_t s) {
     const int D = f->dim;
     const uint64_t span = (uint64_t)kVegasBlock * (uint64_t)kVegasEpt;
-    const uint64_t blocks = (calls + span - 1) / span;
+    const uint64_t blocks = ceil_div(calls, span);
     if (blocks > 0xFFFFFFFFull / (uint64_t)kVegasBlock)
         return fail(HYDRA_PHSP_EINVAL, "calls too large for one launch (more than 2^32 - 1 threads)");
     const uint64_t groups = (blocks + kHistGroup - 1) / kHistGroup;

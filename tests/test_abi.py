@@ -295,3 +295,33 @@ def test_probe_validation(P):
     assert ph(100, 0, 1, 0, f, None) == P.EINVAL
     assert ph(100, 17, 1, 0, f, None) == P.EINVAL
     assert ph(0, 3, 1, 0, f, None) == P.OK
+
+
+def test_event_counts_beyond_one_launch_are_rejected(P):
+    """Counts whose grid would pass 2^32 - 1 threads (up to 2^64 - 1, where a
+    naive ceil(n / span) wraps) fail in validation on every entry point."""
+    L = P.lib()
+    m, n = P._masses([1.0, 1.0, 0.5])
+    big = (1 << 64) - 1
+    fake = ctypes.c_void_p(256)
+    # generate / mixed (FP64 at rest: 2 events per thread for N = 2, 1 for N = 3 -> 4294967040 events max)
+    for cnt in (big, 1 << 40, (0xFFFFFFFF // 256) * 256 + 1):
+        assert _gen_status(P, 5.0, [1.0, 1.0, 0.5], nevents=cnt) == P.EINVAL, cnt
+        assert "too large" in L.hydra_phsp_last_error().decode()
+        if cnt > (0xFFFFFFFF // 256) * 1024:  # the mixed path runs 4 events per thread
+            assert L.hydra_phsp_generate_mixed(5.0, m, n, None, None, 0, cnt, 1, 0, 0, fake, cnt, fake, None,
+                                               None) == P.EINVAL
+    for cnt in (big, (0xFFFFFFFF // 256) * 1024 + 1):   # integrate: 4 events per thread
+        assert L.hydra_phsp_integrate_async(5.0, m, n, cnt, 1, 0, 0, fake, None) == P.EINVAL, cnt
+        assert L.hydra_phsp_integrate_model(5.0, m, n, None, 0, cnt, 1, 0, 0, None, fake, None) == P.EINVAL
+        assert L.hydra_phsp_generate_unweighted(5.0, m, n, None, cnt, 1, 0, 0, 1.0, None, 0, None, fake, None,
+                                                None) == P.EINVAL
+        assert L.hydra_phsp_probe_philox(cnt, 3, 1, 0, fake, None) == P.EINVAL
+    assert L.hydra_phsp_probe_write(fake, big, 12, fake, big, 4, None) == P.EINVAL
+    f = P.gauss_box([0.0] * 3, [1.0] * 3, [0.5] * 3, [0.2] * 3)
+    assert L.hydra_phsp_vegas_iteration(ctypes.byref(f), 50, fake, big, 1, 0, fake, None, None, None) == P.EINVAL
+    # the batch: one channel too large for its class launch
+    c = P.channel(5.0, [1.0, 1.0], 10, stats=None)
+    c.stats_dev = 8
+    c.nevents = big
+    assert L.hydra_phsp_batch_run(P._channel_array([c]), 1, None, None, None) == P.EINVAL

@@ -365,6 +365,25 @@ def test_full_size_config1_at_rest(P):
     assert rel(mean, mo) <= FP64_TOL and rel(sigma, so) <= FP64_TOL
 
 
+def test_integrate_largest_single_launch(P):
+    """The largest count one integrate launch takes ((2^32 - 1) / 256 blocks of
+    1024 events, 1.7e10 events): every block counted, the volume within 5 sigma
+    of the quadrature; one more event is refused."""
+    import volumes
+    M, m = CFG0
+    nmax = (0xFFFFFFFF // 256) * 1024
+    _say(f"integrate {nmax} events in one launch")
+    assert P.events_per_thread(0, 3) == 4
+    st = P.integrate_async(M, m, nmax, seed=7)
+    torch.cuda.synchronize()
+    s = st.cpu().numpy()
+    assert s[0] == nmax
+    exact = volumes.three_body_volume_1d(M, *m)
+    assert abs(s[1] - exact) < 5 * s[3] and 0 < s[3] < 1e-5 * exact, (s, exact)
+    with pytest.raises(P.PhspError):
+        P.integrate_async(M, m, nmax + 1, seed=7)
+
+
 def test_full_size_config1_per_event_parent(P):
     _say("config1 1e8 per-event parents")
     from paper_1711_05683_amd.workloads import per_event_parents

@@ -451,3 +451,52 @@ def test_events_per_thread_variants_are_bit_identical(P, mixed):
     finally:
         P.set_events_per_thread(path, 0)
         P.set_events_per_thread(0, 0)
+
+
+def test_threads_on_separate_streams(P):
+    """Six host threads, each on its own stream, call generate, integrate,
+    unweighted generation and model evaluation at once (the calls release the
+    interpreter lock): every result equals the same call made alone."""
+    import threading
+    _say("six threads, six streams")
+    M, m = CFG0
+    res = [(1, 2, 0.8955, 0.0473)]
+
+    def calls(i, stream):
+        out, w, st = P.generate(M, m, 200_003 + 17 * i, seed=100 + i, stream=stream)
+        st2 = P.integrate_async(M, m, 300_007 + i, seed=200 + i, stream=stream)
+        p4u, idx, cnt, _ = P.generate_unweighted(M, m, 100_003, seed=300 + i, want_index=True, stream=stream)
+        stm, vals = P.integrate_model(M, m, 150_001, res, seed=400 + i, want_values=True, stream=stream)
+        return out, w, st, st2, p4u, idx, cnt, stm, vals
+
+    def host(r):
+        return [t.cpu() for t in r]
+
+    results, errors = [None] * 6, []
+
+    def work(i):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                r = calls(i, s)
+            s.synchronize()
+            results[i] = host(r)
+        except Exception as e:  # reported by the main thread
+            errors.append((i, repr(e)))
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(6)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    assert all(not t.is_alive() for t in threads)
+    for i in range(6):
+        want = host(calls(i, None))
+        got = results[i]
+        k = int(want[6][0])  # kept events: the unweighted outputs beyond them are unset
+        assert torch.equal(got[6], want[6]), i
+        got[4], want[4] = got[4][:, :, :k], want[4][:, :, :k]
+        got[5], want[5] = got[5][:k], want[5][:k]
+        for j, (a, b) in enumerate(zip(got, want)):
+            assert torch.equal(a, b), (i, j)

@@ -280,19 +280,24 @@ int launch_tick(hydra_phsp_server* s) {
     std::vector<DevChannel> fin;
     std::vector<GroupRef> groups;
     std::vector<uint64_t> finishing;
+    // The tick is planned without touching the requests; their progress (next
+    // tile, leaving the active list) is committed only once the tick is on the
+    // stream, so a failure below leaves every request as it was.
+    std::vector<std::pair<uint64_t, uint64_t>> progress; // (request, its next tile after this tick)
+    std::vector<uint64_t> still;
     int nmax = 2;
     {
         std::lock_guard<std::mutex> lock(s->mu);
-        std::vector<uint64_t> still;
         for (uint64_t id : s->active) {
             Request& r = s->reqs[id];
             if (tiles.size() < s->max_tiles_per_tick && r.next_tile < r.ntiles) {
                 const uint32_t ci = (uint32_t)chans.size();
                 chans.push_back(dev_channel(r));
                 nmax = std::max(nmax, r.r.n_daughters);
-                while (r.next_tile < r.ntiles && tiles.size() < s->max_tiles_per_tick)
-                    tiles.push_back(TileRef{ci, 0u, r.next_tile++});
-                if (r.next_tile == r.ntiles) {
+                uint64_t next = r.next_tile;
+                while (next < r.ntiles && tiles.size() < s->max_tiles_per_tick) tiles.push_back(TileRef{ci, 0u, next++});
+                progress.emplace_back(id, next);
+                if (next == r.ntiles) {
                     DevChannel f = dev_channel(r);
                     f.first_group = groups.size();
                     for (uint64_t g = 0; g < f.ngroups; ++g) groups.push_back(GroupRef{(uint32_t)fin.size(), (uint32_t)g});
@@ -303,7 +308,6 @@ int launch_tick(hydra_phsp_server* s) {
             }
             still.push_back(id);
         }
-        s->active.swap(still);
     }
     if (tiles.empty()) return HYDRA_PHSP_OK;
     int st = t.chans.ensure(chans.size());
@@ -357,6 +361,11 @@ int launch_tick(hydra_phsp_server* s) {
     }
     e = hipEventRecord(t.done, q);
     if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
+    {
+        std::lock_guard<std::mutex> lock(s->mu);
+        for (const auto& pr : progress) s->reqs[pr.first].next_tile = pr.second;
+        s->active.swap(still);
+    }
     t.finishing.swap(finishing);
     t.busy = true;
     s->busy_order.push_back(s->next_slot);

@@ -431,6 +431,7 @@ def serving_extra(P, seconds):
     srv = P.Server(32 << 30, max_events_per_tick=1 << 22)
     lat, wall, peak = srv.replay(descs, [r.arrival_s for r in reqs])
     st = srv.stats()
+    cnt = srv.counters()
     srv.destroy()
     lat = np.array(lat)
     ok = lat >= 0
@@ -439,7 +440,10 @@ def serving_extra(P, seconds):
             "events_per_s": events / wall, "p50_ms": float(np.median(lat[ok]) * 1e3),
             "p99_ms": float(np.quantile(lat[ok], 0.99) * 1e3), "max_ms": float(lat[ok].max() * 1e3),
             "failed": int((~ok).sum()), "ticks": st["ticks"], "peak_arena_bytes": peak,
-            "budget_bytes": 32 << 30}
+            "budget_bytes": 32 << 30, "admission_budget_stalls": cnt["budget_stalls"],
+            "admission_active_stalls": cnt["active_stalls"],
+            "queue_wait_mean_ms": cnt["queue_wait_sum_s"] / max(cnt["finished"], 1) * 1e3,
+            "queue_wait_max_ms": cnt["queue_wait_max_s"] * 1e3}
 
 
 def batched_extra(P, torch, dev, steps):

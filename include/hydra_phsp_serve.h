@@ -89,6 +89,16 @@ int hydra_phsp_server_replay(hydra_phsp_server *server, const hydra_phsp_request
 /* Counters: bytes in use, peak bytes, ticks launched, requests finished. */
 int hydra_phsp_server_stats(const hydra_phsp_server *server, uint64_t *bytes_in_use,
                             uint64_t *peak_bytes, uint64_t *ticks, uint64_t *finished);
+
+/* Admission counters since creation (all host-side). */
+typedef struct hydra_phsp_server_counters {
+    uint64_t bytes_in_use, peak_bytes, ticks, finished;
+    uint64_t budget_stalls;  /* steps that left the queue's head waiting for HBM budget */
+    uint64_t active_stalls;  /* steps that left it waiting for an active slot */
+    double queue_wait_max_s; /* longest submit -> admit wait of a finished request */
+    double queue_wait_sum_s; /* summed submit -> admit waits of finished requests */
+} hydra_phsp_server_counters;
+int hydra_phsp_server_counters_get(const hydra_phsp_server *server, hydra_phsp_server_counters *out);
 /* Wait for all outstanding device work, then free everything. */
 int hydra_phsp_server_destroy(hydra_phsp_server *server);
 

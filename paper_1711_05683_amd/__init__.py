@@ -538,6 +538,13 @@ class RequestDesc(ctypes.Structure):
                 ("stream_id", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+class ServerCounters(ctypes.Structure):
+    """``hydra_phsp_server_counters``."""
+    _fields_ = [("bytes_in_use", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64), ("ticks", ctypes.c_uint64),
+                ("finished", ctypes.c_uint64), ("budget_stalls", ctypes.c_uint64), ("active_stalls", ctypes.c_uint64),
+                ("queue_wait_max_s", ctypes.c_double), ("queue_wait_sum_s", ctypes.c_double)]
+
+
 class ResultDesc(ctypes.Structure):
     """``hydra_phsp_result``."""
     _fields_ = [("status", ctypes.c_int32), ("n_daughters", ctypes.c_int32),
@@ -561,6 +568,8 @@ def _declare_serve(lib):
                                              c.POINTER(u64)]
     lib.hydra_phsp_server_stats.argtypes = [vp, c.POINTER(u64), c.POINTER(u64), c.POINTER(u64),
                                             c.POINTER(u64)]
+    lib.hydra_phsp_server_counters_get.argtypes = [vp, c.POINTER(ServerCounters)]
+    lib.hydra_phsp_server_counters_get.restype = c.c_int
     lib.hydra_phsp_server_destroy.argtypes = [vp]
     for name in ("create", "submit", "step", "completed", "poll", "release", "drain", "replay", "stats",
                  "destroy"):
@@ -638,6 +647,14 @@ class Server:
         _check(lib().hydra_phsp_server_replay(self._h, arr, at, n, lat, ctypes.byref(wall),
                                               ctypes.byref(peak)))
         return [lat[i] for i in range(n)], wall.value, peak.value
+
+    def counters(self):
+        """Admission counters: bytes in use / peak, ticks, finished requests, steps
+        that left the queue's head waiting for budget or for an active slot, and
+        the longest and summed submit-to-admit waits (seconds)."""
+        c = ServerCounters()
+        _check(lib().hydra_phsp_server_counters_get(self._h, ctypes.byref(c)))
+        return {f: getattr(c, f) for f, _ in ServerCounters._fields_}
 
     def stats(self):
         a, b, c, d = (ctypes.c_uint64() for _ in range(4))

@@ -187,6 +187,8 @@ struct hydra_phsp_server {
     std::vector<uint64_t> active; // admitted with tiles left, in admission order
     std::vector<uint64_t> completed;
     uint64_t ticks = 0, finished = 0;
+    uint64_t budget_stalls = 0, active_stalls = 0;
+    double queue_wait_max = 0.0, queue_wait_sum = 0.0;
 };
 
 namespace hphsp {
@@ -217,6 +219,9 @@ int retire(hydra_phsp_server* s) {
             r.res.status = HYDRA_PHSP_OK;
             r.res.done_s = now;
             r.done = true;
+            const double waited = r.res.admit_s - r.res.submit_s;
+            s->queue_wait_sum += waited;
+            s->queue_wait_max = std::max(s->queue_wait_max, waited);
             s->completed.push_back(t.finishing[k]);
             ++s->finished;
         }
@@ -230,9 +235,16 @@ int retire(hydra_phsp_server* s) {
 void admit(hydra_phsp_server* s) {
     std::lock_guard<std::mutex> lock(s->mu);
     const double now = now_s();
-    while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
+    while (!s->queue.empty()) {
+        if ((int)s->active.size() >= s->max_active) {
+            ++s->active_stalls;
+            break;
+        }
         Request& r = s->reqs[s->queue.front()];
-        if (!s->arena.alloc(r.bytes, &r.off)) break; // FIFO: wait for memory
+        if (!s->arena.alloc(r.bytes, &r.off)) { // FIFO: wait for memory
+            ++s->budget_stalls;
+            break;
+        }
         char* p = s->arena.ptr(r.off);
         r.parts = reinterpret_cast<Moments*>(p);
         p += round_up(sizeof(Moments) * r.ntiles);
@@ -365,12 +377,12 @@ int launch_tick(hydra_phsp_server* s) {
         std::lock_guard<std::mutex> lock(s->mu);
         for (const auto& pr : progress) s->reqs[pr.first].next_tile = pr.second;
         s->active.swap(still);
+        ++s->ticks;
     }
     t.finishing.swap(finishing);
     t.busy = true;
     s->busy_order.push_back(s->next_slot);
     s->next_slot = (s->next_slot + 1) % kTickSlots;
-    ++s->ticks;
     return HYDRA_PHSP_OK;
 }
 
@@ -570,6 +582,20 @@ int hydra_phsp_server_stats(const hydra_phsp_server* s, uint64_t* bytes_in_use, 
     if (peak_bytes) *peak_bytes = s->arena.peak();
     if (ticks) *ticks = s->ticks;
     if (finished) *finished = s->finished;
+    return HYDRA_PHSP_OK;
+}
+
+int hydra_phsp_server_counters_get(const hydra_phsp_server* s, hydra_phsp_server_counters* out) {
+    if (s == nullptr || out == nullptr) return fail(HYDRA_PHSP_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(const_cast<hydra_phsp_server*>(s)->mu);
+    out->bytes_in_use = s->arena.used();
+    out->peak_bytes = s->arena.peak();
+    out->ticks = s->ticks;
+    out->finished = s->finished;
+    out->budget_stalls = s->budget_stalls;
+    out->active_stalls = s->active_stalls;
+    out->queue_wait_max_s = s->queue_wait_max;
+    out->queue_wait_sum_s = s->queue_wait_sum;
     return HYDRA_PHSP_OK;
 }
 

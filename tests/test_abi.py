@@ -140,6 +140,7 @@ def test_struct_layouts_match_headers(P, tmp_path):
 #include "hydra_phsp_batch.h"
 #include "hydra_phsp_serve.h"
 #include "hydra_phsp_model.h"
+#include "hydra_phsp_serve.h"
 int main(void) {
     printf("%zu %zu %zu %zu %zu %zu %zu ", sizeof(hydra_phsp_channel),
            offsetof(hydra_phsp_channel, n_daughters), offsetof(hydra_phsp_channel, nevents),
@@ -149,8 +150,10 @@ int main(void) {
            offsetof(hydra_phsp_request, integrate_only), offsetof(hydra_phsp_request, stream_id),
            sizeof(hydra_phsp_result), offsetof(hydra_phsp_result, mean),
            offsetof(hydra_phsp_result, weights_dev), offsetof(hydra_phsp_result, done_s));
-    printf("%zu %zu %zu\n", sizeof(hydra_phsp_breit_wigner), offsetof(hydra_phsp_breit_wigner, mass),
+    printf("%zu %zu %zu ", sizeof(hydra_phsp_breit_wigner), offsetof(hydra_phsp_breit_wigner, mass),
            offsetof(hydra_phsp_breit_wigner, width));
+    printf("%zu %zu %zu\n", sizeof(hydra_phsp_server_counters), offsetof(hydra_phsp_server_counters, budget_stalls),
+           offsetof(hydra_phsp_server_counters, queue_wait_sum_s));
     return 0;
 }
 ''')
@@ -163,7 +166,9 @@ int main(void) {
             C.stats_dev.offset, ctypes.sizeof(T), T.grid_per_cu.offset,
             ctypes.sizeof(Q), Q.integrate_only.offset, Q.stream_id.offset,
             ctypes.sizeof(R), R.mean.offset, R.weights_dev.offset, R.done_s.offset,
-            ctypes.sizeof(P.BreitWigner), P.BreitWigner.mass.offset, P.BreitWigner.width.offset]
+            ctypes.sizeof(P.BreitWigner), P.BreitWigner.mass.offset, P.BreitWigner.width.offset,
+            ctypes.sizeof(P.ServerCounters), P.ServerCounters.budget_stalls.offset,
+            P.ServerCounters.queue_wait_sum_s.offset]
     assert got == want
 
 

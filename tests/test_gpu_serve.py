@@ -137,6 +137,17 @@ def test_tiny_budget_forces_queuing(P):
         assert srv.stats()["bytes_in_use"] <= budget
     st = srv.stats()
     assert st["peak_bytes"] <= budget and st["finished"] == len(ids)
+    c = srv.counters()
+    assert c["finished"] == len(ids) and c["ticks"] == st["ticks"] and c["peak_bytes"] == st["peak_bytes"]
+    assert c["budget_stalls"] > 0 and c["active_stalls"] == 0  # requests waited for memory, never for a slot
+    assert c["queue_wait_max_s"] > 0.0 and c["queue_wait_max_s"] * len(ids) >= c["queue_wait_sum_s"] >= 0.0
+    srv.destroy()
+    # one active slot: every request but the first waits for it
+    srv = P.Server(8 << 30, max_active=1)
+    ids = [srv.submit(_desc(P, r)) for r in reqs[:4]]
+    srv.drain()
+    c = srv.counters()
+    assert c["finished"] == 4 and c["active_stalls"] > 0 and c["budget_stalls"] == 0
     srv.destroy()
 
 

@@ -136,7 +136,7 @@ def main():
                          "kernel of known traffic) x3, then the main step x3; prints no JSON")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 64-channel batched configuration and print its figures")
-    ap.add_argument("--only", choices=["unweighted", "model", "sequential", "vegas"],
+    ap.add_argument("--only", choices=["unweighted", "model", "sequential", "vegas", "by_n"],
                     help="run only this extra on the 1e8-event workload and print its figures")
     args = ap.parse_args()
 
@@ -160,6 +160,9 @@ def main():
         return
     if args.only == "vegas":
         print(json.dumps(vegas_extra(P, torch, dev)), flush=True)
+        return
+    if args.only == "by_n":
+        print(json.dumps(by_n_extra(P, torch, dev, args.steps)), flush=True)
         return
     if args.only:
         M, m = 5.279, [3.097, 0.4937, 0.13957]
@@ -333,6 +336,34 @@ def extras(P, torch, dev, args):
     if args.serve_seconds > 0:
         ex["cfg4_serving"] = serving_extra(P, args.serve_seconds)
     return ex
+
+
+def by_n_extra(P, torch, dev, steps):
+    """Single channel by daughter count: N pions from M = 10 GeV, FP64 at rest,
+    about 10.4 GB of output per launch on line-aligned columns, default events
+    per thread; each N's generator against the write probe with the same
+    stores, and its integrate-only time."""
+    r = {}
+    for n in range(2, 11):
+        m = [0.13957] * n
+        nev = int(10.4e9 // (8 * (4 * n + 1)))
+        nev -= nev % 1024
+        out = torch.empty((n, 4, P.aligned_ld(nev)), dtype=torch.float64, device=dev)
+        w = torch.empty(nev, dtype=torch.float64, device=dev)
+        st = torch.empty(4, dtype=torch.float64, device=dev)
+        ept = P.events_per_thread(1, n)
+        _, k = time_steps(lambda: P.generate(10.0, m, nev, out=out, weights=w, stats=st), steps, 15, torch)
+        kw = time_launches(lambda: P.probe_write(out.view(4 * n, out.shape[2]), w, nev, events_per_thread=ept),
+                           steps, 10, torch)
+        _, ki = time_steps(lambda: P.integrate_async(10.0, m, nev, stats=st), steps, 10, torch)
+        b = 8 * (4 * n + 1) * nev
+        r[str(n)] = {"nevents": nev, "ept": ept, "kernel": f"k_phsp<{n}, 0, 1, {ept}>", "kernel_ms": k,
+                     "write_GBs": b / (k * 1e-3) / 1e9, "probe_kernel": f"k_write_bw<{4 * n}, {ept}>",
+                     "probe_ms": kw, "probe_GBs": b / (kw * 1e-3) / 1e9, "kernel_over_probe_rate": kw / k,
+                     "integrate_ms": ki}
+        del out, w
+        torch.cuda.empty_cache()
+    return r
 
 
 def vegas_extra(P, torch, dev):

@@ -151,17 +151,23 @@ int hydra_phsp_abi_version(void);
 int hydra_phsp_selftest_sortnet(void);
 /* Events per thread of the single-channel kernels, per path: path 0 =
  * integrate-only, 1 = FP64 generate, 2 = mixed generate; ept in {1, 2, 4}, or 0
- * for the library default (integrate: 4; mixed: 2 for n_daughters = 2, else 4;
- * FP64 generate: 2 for N = 2, 1 for N = 3, 4 for N = 4..7, 1 for N >= 8, and 1
- * with per-event parents for N <= 3).  One launch covers at most
+ * for the library default.  Defaults with columns on the 128-byte line grid:
+ * integrate 4; mixed 2 for n_daughters = 2, else 4; FP64 generate 2 for N = 2,
+ * 1 for N = 3, 4 for N = 4..7, 1 for N >= 8, and 1 with per-event parents for
+ * N <= 3.  Columns off the line grid (the staged kernel) have their own:
+ * FP64 (any parent mode) 2, 4, 2, 2, 2, 1, 1, 1, 1 and mixed 4, 4, 4, 2, 2, 1,
+ * 1, 2, 1 for N = 2..10.  One launch covers at most
  * (2^32 - 1) / 256 * ept events; larger counts are rejected with EINVAL.
  * Process-wide; changes the launch shape only (events are bit-identical for
  * every value; integrals agree to rounding). */
 int hydra_phsp_set_events_per_thread(int path, int ept);
 /* The events per thread the next single-channel launch on `path` would use for
- * n_daughters (per_event_parents != 0: with per-event parent four-vectors),
- * after any override; EINVAL for a bad path or n_daughters. */
-int hydra_phsp_events_per_thread(int path, int n_daughters, int per_event_parents);
+ * n_daughters, after any override.  flags: bit 0 (1) with per-event parent
+ * four-vectors, bit 1 (2) with columns off the 128-byte line grid.  EINVAL for
+ * a bad path, n_daughters or flags. */
+#define HYDRA_PHSP_EPT_PER_EVENT_PARENTS 1
+#define HYDRA_PHSP_EPT_OFF_LINE_GRID 2
+int hydra_phsp_events_per_thread(int path, int n_daughters, int flags);
 
 /* Kernel timing for benchmarks: while enabled, every launch of the main
  * phase-space kernel is bracketed by HIP events recorded on the caller's

@@ -43,8 +43,9 @@ typedef struct hydra_phsp_channel {
 /* Launch shape of the batched kernels (blocks of 256 threads):
  *   ept          events per thread: 1, 2 or 4 for every class (a tile is
  *                256*ept events), or 0: per class, what a single-channel call
- *                of that N and mode would use (hydra_phsp_events_per_thread),
- *                so every channel's tiles are that call's blocks;
+ *                of that N, mode and layout (columns on or off the 128-byte
+ *                line grid) would use (hydra_phsp_events_per_thread), so every
+ *                channel's tiles are the blocks of that call on its buffers;
  *   grid_per_cu  persistent blocks per compute unit, 1 .. 64 (schedules 0, 1);
  *   schedule     0: persistent grid, static stride over the tiles;
  *                1: persistent grid, blocks claim tiles in order from a

@@ -380,9 +380,11 @@ def set_events_per_thread(path: int, ept: int):
     _check(lib().hydra_phsp_set_events_per_thread(path, ept))
 
 
-def events_per_thread(path: int, n_daughters: int, per_event_parents: bool = False) -> int:
-    """Events per thread of the next launch on path 0 (integrate), 1 (FP64) or 2 (mixed)."""
-    r = lib().hydra_phsp_events_per_thread(path, n_daughters, int(per_event_parents))
+def events_per_thread(path: int, n_daughters: int, per_event_parents: bool = False,
+                      off_line_grid: bool = False) -> int:
+    """Events per thread of the next launch on path 0 (integrate), 1 (FP64) or 2 (mixed);
+    ``off_line_grid``: for outputs whose columns do not start on 128-byte lines."""
+    r = lib().hydra_phsp_events_per_thread(path, n_daughters, int(per_event_parents) | (2 if off_line_grid else 0))
     _check(min(r, 0))
     return r
 

@@ -257,23 +257,39 @@ static hipError_t launch_by_n(int n, const LaunchSpec& s, const KArgs& a, hipStr
 // and four for N = 4..7, where the per-event work dominates; for N >= 8 the
 // register footprint of several events in flight costs more than it saves.
 static std::atomic<int> g_ept_override[3] = {{0}, {0}, {0}}; // read by launches on any thread
-static int default_ept(int mode, int n, int pmode) {
+// Off the line grid the staged kernel's LDS rounds and barriers change the
+// balance: measured the same way, a longer block run pays off for N = 3 and
+// for the mixed path up to N = 4, while from N = 7 the staged kernel's larger
+// register footprint makes one event per lane fastest (four events per lane at
+// N = 8..10 mixed take half as long again).
+static int default_ept(int mode, int n, int pmode, bool staged) {
     const int o = g_ept_override[mode].load(std::memory_order_relaxed);
     if (o > 0) return o;
     if (mode == kIntegrate) return 4;
+    if (staged) {
+        static const int kStagedFp64[11] = {0, 0, 2, 4, 2, 2, 2, 1, 1, 1, 1};
+        static const int kStagedMixed[11] = {0, 0, 4, 4, 4, 2, 2, 1, 1, 2, 1};
+        return mode == kMixed ? kStagedMixed[n] : kStagedFp64[n];
+    }
     if (mode == kMixed) return n == 2 ? 2 : 4;
     if (pmode == kPerEvent && n <= 3) return 1;
     static const int kFp64[11] = {0, 0, 2, 1, 4, 4, 4, 4, 1, 1, 1};
     return kFp64[n];
 }
 
-int single_channel_ept(int mode, int n, int pmode) { return default_ept(mode, n, pmode); }
+int single_channel_ept(int mode, int n, int pmode, bool staged) { return default_ept(mode, n, pmode, staged); }
 
 int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const double* parent_dev,
                uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
                int mode, void* out, uint64_t ld, double* weights, double* stats_dev,
                hipStream_t stream, int ept_override) {
-    const int ept = ept_override > 0 ? ept_override : default_ept(mode, n, pmode);
+    // Columns on the 128-byte line grid take the direct-store kernel; any other
+    // layout the staged one (whole-line writes through LDS).
+    const uint64_t elem = mode == kMixed ? sizeof(float) : sizeof(double);
+    const bool aligned = (uintptr_t)out % kLineBytes == 0 && (ld * elem) % kLineBytes == 0 &&
+                         (uintptr_t)weights % kLineBytes == 0;
+    const bool staged = mode != kIntegrate && !aligned;
+    const int ept = ept_override > 0 ? ept_override : default_ept(mode, n, pmode, staged);
     const uint64_t per_block = (uint64_t)kBlock * (uint64_t)ept;
     const uint64_t blocks = ceil_div(nevents, per_block);
     if (blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
@@ -302,12 +318,7 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
         a.weights = weights;
         a.partials = ws->partials;
         a.trig = trig;
-        // Columns on the 128-byte line grid take the direct-store kernel; any
-        // other layout the staged one (whole-line writes through LDS).
-        const uint64_t elem = mode == kMixed ? sizeof(float) : sizeof(double);
-        const bool aligned = (uintptr_t)out % kLineBytes == 0 && (ld * elem) % kLineBytes == 0 &&
-                             (uintptr_t)weights % kLineBytes == 0;
-        LaunchSpec s{pmode, mode, ept, blocks, mode != kIntegrate && !aligned};
+        LaunchSpec s{pmode, mode, ept, blocks, staged};
         const long slot = timing_begin(stream);
         hipError_t e = launch_by_n(n, s, a, stream);
         timing_end(stream, slot);
@@ -466,11 +477,15 @@ int hydra_phsp_set_events_per_thread(int path, int ept) {
     return HYDRA_PHSP_OK;
 }
 
-int hydra_phsp_events_per_thread(int path, int n_daughters, int per_event_parents) {
+int hydra_phsp_events_per_thread(int path, int n_daughters, int flags) {
     if (path < 0 || path > 2) return fail(HYDRA_PHSP_EINVAL, "path must be 0, 1 or 2");
     if (n_daughters < 2 || n_daughters > HYDRA_PHSP_NMAX)
         return fail(HYDRA_PHSP_EINVAL, "n_daughters must be in [2, HYDRA_PHSP_NMAX]");
-    return default_ept(path, n_daughters, per_event_parents ? kPerEvent : kAtRest);
+    if (flags & ~(HYDRA_PHSP_EPT_PER_EVENT_PARENTS | HYDRA_PHSP_EPT_OFF_LINE_GRID))
+        return fail(HYDRA_PHSP_EINVAL, "flags must combine HYDRA_PHSP_EPT_PER_EVENT_PARENTS and "
+                                       "HYDRA_PHSP_EPT_OFF_LINE_GRID");
+    return default_ept(path, n_daughters, (flags & HYDRA_PHSP_EPT_PER_EVENT_PARENTS) ? kPerEvent : kAtRest,
+                       path != kIntegrate && (flags & HYDRA_PHSP_EPT_OFF_LINE_GRID) != 0);
 }
 
 int hydra_phsp_timing_enable(int on) {

@@ -25,9 +25,9 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
                uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
                int mode, void* out, uint64_t ld, double* weights, double* stats_dev, hipStream_t stream,
                int ept_override);
-// Events per thread a single-channel launch uses for (mode, n, parent mode),
-// after the process-wide override.
-int single_channel_ept(int mode, int n, int pmode);
+// Events per thread a single-channel launch uses for (mode, n, parent mode,
+// staged layout), after the process-wide override.
+int single_channel_ept(int mode, int n, int pmode, bool staged);
 // The stream's block-partials buffer, grown to at least `blocks` entries (valid
 // until the next call on the stream that grows it).
 int block_partials(hipStream_t stream, uint64_t blocks, Moments** partials);

@@ -276,11 +276,12 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     if (ept != 0 && ept != 1 && ept != 2 && ept != 4)
         return fail(HYDRA_PHSP_EINVAL, "tuning ept must be 0, 1, 2 or 4");
     // Events per thread per class: the given value, or (0) what a single-channel
-    // launch of that N and mode would use, so that every channel's tiles are that
-    // launch's blocks.
+    // launch of that N, mode and layout would use, so that every channel's tiles
+    // are that launch's blocks.
     int class_ept[kClasses];
     for (int c = 0; c < kClasses; ++c)
-        class_ept[c] = ept ? ept : single_channel_ept(class_mode(c), class_n(c), kAtRest);
+        class_ept[c] = ept ? ept
+                           : single_channel_ept(class_mode(c), class_n(c), kAtRest, class_kind(c) == kKindStaged);
     if (gpc < 1 || gpc > 64) return fail(HYDRA_PHSP_EINVAL, "tuning grid_per_cu must be in [1, 64]");
 
     std::vector<DevChannel> dch((size_t)nch);

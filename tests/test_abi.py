@@ -100,6 +100,16 @@ def test_events_per_thread_query(P):
         P.set_events_per_thread(1, 0)
     assert P.lib().hydra_phsp_events_per_thread(3, 3, 0) == P.EINVAL
     assert P.lib().hydra_phsp_events_per_thread(1, 11, 0) == P.EINVAL
+    assert P.lib().hydra_phsp_events_per_thread(1, 3, 4) == P.EINVAL  # unknown flag
+    # columns off the line grid (staged kernel) have their own defaults
+    staged_fp64 = [2, 4, 2, 2, 2, 1, 1, 1, 1]
+    staged_mixed = [4, 4, 4, 2, 2, 1, 1, 2, 1]
+    for n in range(2, 11):
+        assert P.events_per_thread(1, n, off_line_grid=True) == staged_fp64[n - 2]
+        assert P.events_per_thread(1, n, True, True) == staged_fp64[n - 2]
+        assert P.events_per_thread(2, n, off_line_grid=True) == staged_mixed[n - 2]
+        assert P.events_per_thread(0, n, off_line_grid=True) == 4  # integrate-only has no layout
+    assert P.events_per_thread(1, 3) == 1 and P.events_per_thread(1, 3, True) == 1
     assert P.lib().hydra_phsp_events_per_thread(1, 1, 0) == P.EINVAL
 
 
@@ -311,7 +321,9 @@ def test_event_counts_beyond_one_launch_are_rejected(P):
     fake = ctypes.c_void_p(256)
     # generate / mixed (FP64 at rest: 2 events per thread for N = 2, 1 for N = 3 -> 4294967040 events max)
     for cnt in (big, 1 << 40, (0xFFFFFFFF // 256) * 256 + 1):
-        assert _gen_status(P, 5.0, [1.0, 1.0, 0.5], nevents=cnt) == P.EINVAL, cnt
+        # columns on the line grid (one event per thread for N = 3); ld rounded up without wrapping
+        ld = cnt if cnt > (1 << 63) else (cnt + 15) // 16 * 16
+        assert _gen_status(P, 5.0, [1.0, 1.0, 0.5], nevents=cnt, ld=ld, out=256, w=256) == P.EINVAL, cnt
         assert "too large" in L.hydra_phsp_last_error().decode()
         if cnt > (0xFFFFFFFF // 256) * 1024:  # the mixed path runs 4 events per thread
             assert L.hydra_phsp_generate_mixed(5.0, m, n, None, None, 0, cnt, 1, 0, 0, fake, cnt, fake, None,

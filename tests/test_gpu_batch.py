@@ -66,8 +66,11 @@ def _single(P, c, i, integ, ept=1):
         return None, None, st
     P.set_events_per_thread(1, ept)
     try:
+        # the batch channel's layout (ld = nevents), so that default settings pick the same kernel
+        out = torch.empty((len(c.masses), 4, max(c.nevents, 1)), dtype=torch.float64, device="cuda")
+        w = torch.empty(max(c.nevents, 1), dtype=torch.float64, device="cuda")
         out, w, st = P.generate(c.parent_mass, c.masses, c.nevents, seed=c.seed + i, stream_id=c.stream_id,
-                                event_offset=1000 * i)
+                                event_offset=1000 * i, out=out, weights=w)
     finally:
         P.set_events_per_thread(1, 0)
     return out, w, st
@@ -283,7 +286,11 @@ def test_config3_full_batch(P):
             p4o, wo = oracle.generate(c.parent_mass, c.masses, 1, seed=c.seed, stream_id=c.stream_id,
                                       event_offset=int(e))
             assert_events_close(g[:, :, j:j + 1], gw[j:j + 1], p4o, wo)
-        so, sw, sst = P.generate(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id)
+        # a single-channel call on the same layout (ld = nevents) takes the same kernel and shape
+        so = torch.empty_like(out)
+        sw = torch.empty_like(w)
+        so, sw, sst = P.generate(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id,
+                                 out=so, weights=sw)
         torch.cuda.synchronize()
         assert torch.equal(so, out) and torch.equal(sw, w) and torch.equal(sst, st), i
         del so, sw

@@ -5,7 +5,7 @@
 // uniform of the event (words 0 and 1 of the first Philox call its own uniforms
 // do not use).  Kept events are written in trial order.  The passes, each over
 // the same blocks of kBlock * kUnwEpt trials:
-//   max    (only when no bound is given) the largest weight per block;
+//   max    (only when no bound is given) the largest weight of all trials;
 //   count  kept and over-bound trials per block (weights only, no kinematics);
 //   write  the full kinematics again (counter-based draws make them identical),
 //          each kept event stored at its block's offset plus its rank.
@@ -33,7 +33,8 @@ __device__ __forceinline__ double accept_uniform(const KArgs& a, uint64_t base, 
 struct UnwArgs {
     KArgs a;                   // channel, counters, parent frame, trig table (a.out unused)
     const double* w_max;       // device scalar: the bound applied
-    double* block_max;         // [blocks] largest weight per block (max pass)
+    unsigned long long* w_max_bits; // the same scalar's bits, raised by the max pass with atomic max
+                                    // (non-negative doubles order like their bit patterns)
     uint2* counts;             // [blocks] (kept, weight > w_max) per block
     const uint64_t* offsets;   // [blocks] kept events before the block
     double* out;               // kept events, [N][4][ld]
@@ -53,7 +54,9 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Largest weight of the block's trials (weights are >= 0).
+// Largest weight of the trials: each block's maximum raises the bound's bit
+// pattern with an atomic max (exact and independent of order; the bound starts
+// at zero).
 template <int N>
 __global__ __launch_bounds__(kBlock) void k_unw_max(const UnwArgs u) {
     __shared__ double sm[kWaves];
@@ -74,7 +77,12 @@ __global__ __launch_bounds__(kBlock) void k_unw_max(const UnwArgs u) {
         double r = sm[0];
 #pragma unroll
         for (int w = 1; w < kWaves; ++w) r = fmax(r, sm[w]);
-        u.block_max[blockIdx.x] = r;
+        // Only a block that beats the bound seen so far raises it: the bound only
+        // grows, so a skipped block's maximum is already covered, and after the
+        // first blocks almost none contend for the one address.
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(r);
+        if (bits > __hip_atomic_load(u.w_max_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(u.w_max_bits, bits);
     }
 }
 

@@ -18,22 +18,6 @@ namespace hphsp {
 constexpr int kScanBlock = 256;   // counts scanned per block of the partial scan
 constexpr int kScanTop = 1024;    // threads of the single-block scan of the partial sums
 
-// Largest weight over the per-block maxima (max is exact in any order).
-__global__ __launch_bounds__(kScanTop) void k_unw_max_final(const double* __restrict__ block_max,
-                                                            uint64_t blocks, double* __restrict__ w_max) {
-    __shared__ double sm[kScanTop / 64];
-    double m = 0.0;
-    for (uint64_t i = threadIdx.x; i < blocks; i += kScanTop) m = fmax(m, block_max[i]);
-    m = wave_max(m);
-    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double r = 0.0;
-        for (int w = 0; w < kScanTop / 64; ++w) r = fmax(r, sm[w]);
-        *w_max = r;
-    }
-}
-
 __global__ void k_unw_set(double* __restrict__ w_max, double value) {
     if (threadIdx.x == 0) *w_max = value;
 }
@@ -56,21 +40,33 @@ __device__ __forceinline__ uint64_t block_inclusive_scan(uint64_t v, uint64_t* s
     return v + add;
 }
 
-// Stage 1: kept count of each group of kScanBlock blocks.
+// Stage 1: kept and over-bound trials of each group of kScanBlock blocks.
 __global__ __launch_bounds__(kScanBlock) void k_unw_scan_partial(const uint2* __restrict__ counts, uint64_t blocks,
-                                                                 uint64_t* __restrict__ sums) {
+                                                                 uint64_t* __restrict__ sums,
+                                                                 uint64_t* __restrict__ over_sums) {
     __shared__ uint64_t sm[kScanBlock / 64];
     const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
     const uint64_t v = i < blocks ? counts[i].x : 0u;
     const uint64_t inc = block_inclusive_scan<kScanBlock>(v, sm);
     if (threadIdx.x == kScanBlock - 1) sums[blockIdx.x] = inc;
+    uint64_t o = i < blocks ? counts[i].y : 0u;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) o += __shfl_xor(o, off, 64);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = o; // the scan's last read of sm was before its barrier
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kScanBlock / 64; ++w) t += sm[w];
+        over_sums[blockIdx.x] = t;
+    }
 }
 
 // Stage 2 (one block): exclusive prefix of the group sums, in place, and the
 // totals (kept, over-bound) into the caller's counts; the bound applied into the
 // caller's w_max output when asked.
 __global__ __launch_bounds__(kScanTop) void k_unw_scan_top(uint64_t* __restrict__ sums, uint64_t groups,
-                                                           const uint2* __restrict__ counts, uint64_t blocks,
+                                                           const uint64_t* __restrict__ over_sums,
                                                            uint64_t* __restrict__ totals,
                                                            const double* __restrict__ w_max,
                                                            double* __restrict__ w_max_out) {
@@ -87,9 +83,9 @@ __global__ __launch_bounds__(kScanTop) void k_unw_scan_top(uint64_t* __restrict_
         carry += last;
         __syncthreads();
     }
-    // over-bound trials: a plain sum (order-free for integers)
+    // over-bound trials: a plain sum of the group sums (order-free for integers)
     uint64_t over = 0;
-    for (uint64_t i = threadIdx.x; i < blocks; i += kScanTop) over += counts[i].y;
+    for (uint64_t i = threadIdx.x; i < groups; i += kScanTop) over += over_sums[i];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) over += __shfl_xor(over, off, 64);
     if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = over;
@@ -118,10 +114,10 @@ __global__ __launch_bounds__(kScanBlock) void k_unw_scan_finish(const uint2* __r
 namespace {
 
 struct UnwWorkspace {
-    double* block_max = nullptr;
     uint2* counts = nullptr;
     uint64_t* offsets = nullptr;
-    uint64_t* sums = nullptr;
+    uint64_t* sums = nullptr;      // [groups] kept trials per group of kScanBlock blocks
+    uint64_t* over_sums = nullptr; // [groups] over-bound trials per group
     double* w_max = nullptr;
     uint64_t capacity = 0; // blocks
 };
@@ -130,10 +126,10 @@ std::mutex g_unw_mu;
 std::map<std::pair<int, hipStream_t>, UnwWorkspace> g_unw_ws;
 
 void free_ws(UnwWorkspace& w) {
-    if (w.block_max) (void)hipFree(w.block_max);
     if (w.counts) (void)hipFree(w.counts);
     if (w.offsets) (void)hipFree(w.offsets);
     if (w.sums) (void)hipFree(w.sums);
+    if (w.over_sums) (void)hipFree(w.over_sums);
     if (w.w_max) (void)hipFree(w.w_max);
     w = UnwWorkspace{};
 }
@@ -149,10 +145,10 @@ int unw_workspace(hipStream_t stream, uint64_t blocks, UnwWorkspace** out) {
         while (cap < blocks) cap *= 2;
         free_ws(w); // hipFree waits for the device, so no queued kernel still uses it
         const uint64_t groups = (cap + kScanBlock - 1) / kScanBlock;
-        bool ok = hipMalloc(&w.block_max, sizeof(double) * cap) == hipSuccess &&
-                  hipMalloc(&w.counts, sizeof(uint2) * cap) == hipSuccess &&
+        bool ok = hipMalloc(&w.counts, sizeof(uint2) * cap) == hipSuccess &&
                   hipMalloc(&w.offsets, sizeof(uint64_t) * cap) == hipSuccess &&
                   hipMalloc(&w.sums, sizeof(uint64_t) * groups) == hipSuccess &&
+                  hipMalloc(&w.over_sums, sizeof(uint64_t) * groups) == hipSuccess &&
                   hipMalloc(&w.w_max, sizeof(double)) == hipSuccess;
         if (!ok) {
             free_ws(w);
@@ -250,7 +246,7 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
     L.u.a.sid = stream_id;
     L.u.a.trig = trig;
     L.u.w_max = ws->w_max;
-    L.u.block_max = ws->block_max;
+    L.u.w_max_bits = reinterpret_cast<unsigned long long*>(ws->w_max);
     L.u.counts = ws->counts;
     L.u.offsets = ws->offsets;
     L.u.out = p4_out_dev;
@@ -261,27 +257,20 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
 
     const long slot = timing_begin(s);
     hipError_t e = hipSuccess;
-    if (w_max == 0.0) {
-        if (blocks > 0) e = launch_pass_n(n_daughters, 0, L, s);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_unw_max_final, dim3(1), dim3(kScanTop), 0, s, (const double*)ws->block_max, blocks,
-                               ws->w_max);
-            e = hipGetLastError();
-        }
-    } else {
-        hipLaunchKernelGGL(k_unw_set, dim3(1), dim3(64), 0, s, ws->w_max, w_max);
-        e = hipGetLastError();
-    }
+    // the bound: given, or raised from zero to the largest trial weight by the max pass
+    hipLaunchKernelGGL(k_unw_set, dim3(1), dim3(64), 0, s, ws->w_max, w_max);
+    e = hipGetLastError();
+    if (e == hipSuccess && w_max == 0.0 && blocks > 0) e = launch_pass_n(n_daughters, 0, L, s);
     if (e == hipSuccess && blocks > 0) e = launch_pass_n(n_daughters, 1, L, s);
     const uint64_t groups = (blocks + kScanBlock - 1) / kScanBlock;
     if (e == hipSuccess && groups > 0) {
         hipLaunchKernelGGL(k_unw_scan_partial, dim3((unsigned)groups), dim3(kScanBlock), 0, s,
-                           (const uint2*)ws->counts, blocks, ws->sums);
+                           (const uint2*)ws->counts, blocks, ws->sums, ws->over_sums);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_unw_scan_top, dim3(1), dim3(kScanTop), 0, s, ws->sums, groups, (const uint2*)ws->counts,
-                           blocks, counts_dev, (const double*)ws->w_max, w_max_dev);
+        hipLaunchKernelGGL(k_unw_scan_top, dim3(1), dim3(kScanTop), 0, s, ws->sums, groups,
+                           (const uint64_t*)ws->over_sums, counts_dev, (const double*)ws->w_max, w_max_dev);
         e = hipGetLastError();
     }
     const bool outputs = p4_out_dev != nullptr || index_out_dev != nullptr;

@@ -1,14 +1,15 @@
-// phsp_batch.hpp -- persistent multi-channel kernel.
+// phsp_batch.hpp -- multi-channel (batched) kernels.
 //
 // Many decay channels (uneven N and event counts) run in one submission.  The
 // host cuts every channel into tiles of kBlock*EPT events -- exactly the
 // per-block chunks of the single-channel kernel -- groups the tiles by
-// daughter-count class, and per class one launch walks its tile range: either
-// one block per tile, or a persistent grid with a static stride (block b takes
-// tiles b, b+G, b+2G, ...; every block leaves the loop once its next index
-// passes the end) or a dynamic claim of the next tile.  Each tile switches on
-// its channel's N to the same templated per-event code as the single-channel
-// kernel, and writes its block partial at the channel's tile index, so events,
+// (daughter count, mode, layout) class, and per class one launch walks its tile
+// range: either one block per tile, or a persistent grid with a static stride
+// (block b takes tiles b, b+G, b+2G, ...; every block leaves the loop once its
+// next index passes the end) or a dynamic claim of the next tile.  A class
+// kernel runs the single-channel kernel's templated per-event code for its N
+// (the mixed kernel of the server's ticks switches on each tile's N instead),
+// and writes each tile's block partial at the channel's tile index, so events,
 // weights and partials are bit-identical to a single-channel launch with the
 // same events per thread; the per-channel two-stage merge then reproduces the
 // single-channel integral bit for bit.

@@ -87,10 +87,18 @@ def cpu_baseline(target_s: float = 10.0, chunk: int = 1_000_000, max_events: int
         if time.perf_counter() - t0 >= target_s:
             break
     dt = time.perf_counter() - t0
+    # the other configurations' generators, a short sample each (same thread)
+    others = {}
+    for name, Mo, mo, n in (("config0_3body_1e5", 5.279, [3.097, 0.4937, 0.13957], 100_000),
+                            ("config2_six_pions", 10.0, [0.13957] * 6, 500_000),
+                            ("config2_six_massless", 10.0, [0.0] * 6, 500_000)):
+        t1 = time.perf_counter()
+        oracle.generate(Mo, mo, n, seed=42)
+        others[name] = {"events": n, "events_per_s": n / (time.perf_counter() - t1)}
     return {"value": done / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
             "sample": f"first {done} events of the 1e8-event workload (momenta + weights), "
                       f"{chunk}-event chunks, single thread, {dt:.1f} s",
-            "cpu_model": _cpu_model()}
+            "cpu_model": _cpu_model(), "other_configs": others}
 
 
 def _cpu_model():

@@ -328,17 +328,23 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         first_tile += nt;
         first_group += d.ngroups;
     }
-    // Tile table ordered by daughter-count class (one launch per class).
+    // Tile table ordered by class (one launch per class), channel and tile order
+    // kept within a class: one counting pass, then one placement pass.
     uint64_t class_begin[kClasses], class_count[kClasses];
     {
-        std::vector<TileRef> by_class;
-        by_class.reserve(tiles.size());
+        std::vector<int> chan_class((size_t)nch);
+        for (int i = 0; i < nch; ++i) chan_class[(size_t)i] = class_of(dch[(size_t)i].n, kinds[(size_t)i]);
+        for (int c = 0; c < kClasses; ++c) class_count[c] = 0;
+        for (int i = 0; i < nch; ++i) class_count[chan_class[(size_t)i]] += dch[(size_t)i].ntiles;
+        uint64_t at = 0;
         for (int c = 0; c < kClasses; ++c) {
-            class_begin[c] = by_class.size();
-            for (const TileRef& t : tiles)
-                if (class_of(dch[t.channel].n, kinds[t.channel]) == c) by_class.push_back(t);
-            class_count[c] = by_class.size() - class_begin[c];
+            class_begin[c] = at;
+            at += class_count[c];
         }
+        std::vector<TileRef> by_class(tiles.size());
+        uint64_t next[kClasses];
+        for (int c = 0; c < kClasses; ++c) next[c] = class_begin[c];
+        for (const TileRef& t : tiles) by_class[next[chan_class[t.channel]]++] = t;
         tiles.swap(by_class);
     }
     int dev = 0;

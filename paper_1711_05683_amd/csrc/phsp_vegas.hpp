@@ -33,7 +33,8 @@ struct VegasArgs {
     uint32_t k0, k1;             // seed
     uint32_t iteration;          // counter word 3
     uint64_t calls;
-    double lo[kVegasDMax], width[kVegasDMax], mu[kVegasDMax], sigma[kVegasDMax]; // width = hi - lo
+    double lo[kVegasDMax], width[kVegasDMax], mu[kVegasDMax]; // width = hi - lo
+    double inv_sigma[kVegasDMax], norm[kVegasDMax];           // 1 / s_d and 1 / (s_d sqrt(2 pi)), from the host
     const double* grid;          // [D][bins + 1]
     Moments* partials;           // [blocks]
     double* hist_partials;       // NULL, or [blocks][D][bins]
@@ -74,8 +75,8 @@ __global__ __launch_bounds__(kVegasBlock) void k_vegas(const VegasArgs v) {
                 const double w = gd[bb + 1] - gd[bb];
                 const double y = gd[bb] + (z - (double)bb) * w;
                 const double x = v.lo[d] + y * v.width[d];
-                const double t = (x - v.mu[d]) / v.sigma[d];
-                const double f = exp(-0.5 * t * t) / (v.sigma[d] * 2.5066282746310002);
+                const double t = (x - v.mu[d]) * v.inv_sigma[d];
+                const double f = exp(-0.5 * t * t) * v.norm[d];
                 val = val * f * ((double)K * w * v.width[d]);
                 b[d] = bb;
             }

@@ -207,7 +207,8 @@ int vegas_iteration(const hydra_phsp_gauss_box* f, int bins, const double* grid_
         L.v.lo[d] = f->lo[d];
         L.v.width[d] = f->hi[d] - f->lo[d];
         L.v.mu[d] = f->mean[d];
-        L.v.sigma[d] = f->sigma[d];
+        L.v.inv_sigma[d] = 1.0 / f->sigma[d];
+        L.v.norm[d] = 1.0 / (f->sigma[d] * 2.5066282746310002); // sqrt(2 pi)
     }
     L.v.grid = grid_dev;
     L.v.partials = partials;

@@ -139,9 +139,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=15.0,
                     help="length of the Poisson serving trace replayed in the extras (60 = full)")
-    ap.add_argument("--counters", action="store_true",
-                    help="short run for rocprofv3 --pmc: a 1 GiB torch copy (the calibration "
-                         "kernel of known traffic) x3, then the main step x3; prints no JSON")
+    ap.add_argument("--counters", nargs="?", const="headline", default=None, choices=sorted(COUNTER_RUNS),
+                    help="short run for rocprofv3 --pmc, prints no JSON: 'headline' (default) runs a 1 GiB "
+                         "torch copy (the calibration kernel of known traffic) x3, then the main step x3; "
+                         "the other names run one configuration's launch x3 after two warm-up launches")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 64-channel batched configuration and print its figures")
     ap.add_argument("--only", choices=["unweighted", "model", "sequential", "vegas", "by_n"],
@@ -198,6 +199,9 @@ def main():
     def step():
         P.generate(M, m, n_ev, seed=42, out=out, weights=w, stats=st)
 
+    if args.counters and args.counters != "headline":
+        counter_run(P, torch, dev, args.counters)
+        return
     if args.counters:
         src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -249,6 +253,37 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
+
+
+# Short programs profiled by counter passes: name -> (parent mass, masses, events, mixed)
+COUNTER_RUNS = {"headline": None,
+                "six_pion_fp64": (10.0, [0.13957] * 6, 50_000_000, False),
+                "six_pion_mixed": (10.0, [0.13957] * 6, 50_000_000, True),
+                "six_massless_mixed": (10.0, [0.0] * 6, 50_000_000, True),
+                "ten_pion_fp64": (10.0, [0.13957] * 10, 31_700_000, False),
+                "unweighted": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False)}
+
+
+def counter_run(P, torch, dev, name):
+    """Two warm-up launches and three profiled launches of one configuration."""
+    M, m, n, mixed = COUNTER_RUNS[name]
+    dtype = torch.float32 if mixed else torch.float64
+    out = torch.empty((len(m), 4, P.aligned_ld(n)), dtype=dtype, device=dev)
+    w = torch.empty(n, dtype=torch.float64, device=dev)
+    st = torch.empty(4, dtype=torch.float64, device=dev)
+    if name == "unweighted":
+        cnt = torch.empty(2, dtype=torch.int64, device=dev)
+        wmo = torch.empty(1, dtype=torch.float64, device=dev)
+        P.generate_unweighted(M, m, n, out=out, counts=cnt, w_max_out=wmo)
+        torch.cuda.synchronize()
+        bound = float(wmo.item())
+        fn = lambda: P.generate_unweighted(M, m, n, w_max=bound, out=out, counts=cnt, w_max_out=wmo)  # noqa: E731
+    else:
+        fn = lambda: P.generate(M, m, n, out=out, weights=w, stats=st, mixed=mixed)  # noqa: E731
+    for _ in range(5):
+        fn()
+    torch.cuda.synchronize()
+    print(f"counter run {name}: {n} events x5 done", flush=True)
 
 
 def time_launches(fn, steps, warmup, torch):

@@ -118,6 +118,47 @@ def _dptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _check_buf(t: Optional[torch.Tensor], name: str, dtype, min_numel: int):
+    """Reject a caller buffer the C ABI cannot check itself: wrong dtype, not
+    contiguous, or fewer than ``min_numel`` elements (the kernels would write
+    past its end).  Runs before any device is touched."""
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor")
+    if t.numel() < min_numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, {min_numel} needed")
+
+
+def _launch_device(device=None, stream: Optional[torch.cuda.Stream] = None) -> torch.device:
+    """The device the library will launch on: the stream's, else the current one.
+    A ``device`` argument must name that device (the library launches on the
+    current device; make another one current with ``torch.cuda.device``)."""
+    cur = torch.device("cuda", torch.cuda.current_device())
+    if stream is not None and torch.device(stream.device) != cur:
+        raise ValueError(f"stream is on {stream.device}, the current device is {cur}")
+    if device is not None:
+        d = torch.device(device)
+        if d.type != "cuda" or (d.index is not None and d.index != cur.index):
+            raise ValueError(f"device {d} is not the current device {cur}")
+    return cur
+
+
+def _resident(device=None, stream: Optional[torch.cuda.Stream] = None, **bufs) -> torch.device:
+    """Check that every given buffer lives in device memory of the launch device
+    and return that device (host tensors are rejected before any device query)."""
+    for name, t in bufs.items():
+        if t is not None and not t.is_cuda:
+            raise ValueError(f"{name} must be a CUDA (device) tensor, got one on {t.device}")
+    dev = _launch_device(device, stream)
+    for name, t in bufs.items():
+        if t is not None and t.device != dev:
+            raise ValueError(f"{name} is on {t.device}, the launch device is {dev}")
+    return dev
+
+
 def aligned_ld(nevents: int) -> int:
     """Leading dimension for an SoA output of ``nevents`` events: a multiple of 32
     elements, so every column starts on a 128-byte line (FP64 and FP32) and each
@@ -141,8 +182,19 @@ def generate(parent_mass: float, masses: Sequence[float], nevents: int, *, seed:
     ``parent_p4`` is one (E, px, py, pz) applied to all events; ``parent_dev`` a
     ``[4, ld_parent]`` float64 device tensor of per-event parents."""
     m, n = _masses(masses)
-    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     dtype = torch.float32 if mixed else torch.float64
+    if out is not None and (not isinstance(out, torch.Tensor) or out.dtype != dtype or not out.is_contiguous()
+                            or out.dim() != 3 or tuple(out.shape[:2]) != (n, 4)):
+        raise ValueError(f"out must be a contiguous [{n}, 4, ld] {dtype} tensor")
+    _check_buf(weights, "weights", torch.float64, nevents)
+    _check_buf(stats, "stats", torch.float64, STATS)
+    if parent_dev is not None:
+        if not isinstance(parent_dev, torch.Tensor) or parent_dev.dtype != torch.float64 or parent_dev.dim() != 2 \
+                or parent_dev.shape[0] != 4 or not parent_dev.is_contiguous():
+            raise ValueError("parent_dev must be a contiguous [4, ld_parent] float64 tensor")
+        if parent_dev.shape[1] < nevents:
+            raise ValueError(f"parent_dev has {parent_dev.shape[1]} events per row, {nevents} needed")
+    dev = _resident(device, stream, out=out, weights=weights, stats=stats, parent_dev=parent_dev)
     own_out = out is None
     if own_out:
         out = torch.empty((n, 4, aligned_ld(nevents)), dtype=dtype, device=dev)
@@ -150,19 +202,12 @@ def generate(parent_mass: float, masses: Sequence[float], nevents: int, *, seed:
         weights = torch.empty(max(nevents, 1), dtype=torch.float64, device=dev)
     if stats is None and want_stats:
         stats = torch.empty(STATS, dtype=torch.float64, device=dev)
-    if out.dtype != dtype or not out.is_contiguous() or out.dim() != 3 or out.shape[:2] != (n, 4):
-        raise ValueError(f"out must be a contiguous [{n}, 4, ld] {dtype} tensor")
-    if weights.dtype != torch.float64 or not weights.is_contiguous():
-        raise ValueError("weights must be a contiguous float64 tensor")
     ld = out.shape[2]
     p4h = None
     if parent_p4 is not None:
         p4h = (ctypes.c_double * 4)(*[float(x) for x in parent_p4])
     ldp = 0
     if parent_dev is not None:
-        if parent_dev.dtype != torch.float64 or parent_dev.dim() != 2 or parent_dev.shape[0] != 4 \
-                or not parent_dev.is_contiguous():
-            raise ValueError("parent_dev must be a contiguous [4, ld_parent] float64 tensor")
         ldp = parent_dev.shape[1]
     fn = lib().hydra_phsp_generate_mixed if mixed else lib().hydra_phsp_generate
     _check(fn(parent_mass, m, n, p4h, _dptr(parent_dev), ldp, nevents, seed, stream_id, event_offset,
@@ -191,18 +236,24 @@ def generate_unweighted(parent_mass: float, masses: Sequence[float], ntrials: in
     ``w_max_out`` may be given (contiguous, of those shapes and dtypes) to reuse
     buffers; ``capacity`` is then ``out``'s (or ``index``'s) last dimension."""
     m, n = _masses(masses)
-    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     cap = aligned_ld(ntrials) if capacity is None else int(capacity)
+    if out is not None and (not isinstance(out, torch.Tensor) or out.dtype != torch.float64
+                            or not out.is_contiguous() or out.dim() != 3 or tuple(out.shape[:2]) != (n, 4)):
+        raise ValueError(f"out must be a contiguous [{n}, 4, capacity] float64 tensor")
+    if index is not None:
+        _check_buf(index, "index", torch.int64, 1)
+        if index.dim() != 1:
+            raise ValueError("index must be a one-dimensional int64 tensor")
+    if out is not None and index is not None and index.shape[0] != out.shape[2]:
+        raise ValueError("index must have one entry per output column")
+    _check_buf(counts, "counts", torch.int64, 2)
+    _check_buf(w_max_out, "w_max_out", torch.float64, 1)
+    dev = _resident(device, stream, out=out, index=index, counts=counts, w_max_out=w_max_out)
     if out is None and want_events:
         out = torch.empty((n, 4, max(cap, 1)), dtype=torch.float64, device=dev)
-    if out is not None and (out.dtype != torch.float64 or not out.is_contiguous() or out.dim() != 3
-                            or tuple(out.shape[:2]) != (n, 4)):
-        raise ValueError(f"out must be a contiguous [{n}, 4, capacity] float64 tensor")
     idx = index
     if idx is None and want_index:
         idx = torch.empty(out.shape[2] if out is not None else max(cap, 1), dtype=torch.int64, device=dev)
-    if out is not None and idx is not None and idx.shape[0] != out.shape[2]:
-        raise ValueError("index must have one entry per output column")
     if counts is None:
         counts = torch.empty(2, dtype=torch.int64, device=dev)
     wm = w_max_out if w_max_out is not None else torch.empty(1, dtype=torch.float64, device=dev)
@@ -232,7 +283,9 @@ def integrate_model(parent_mass: float, masses: Sequence[float], nevents: int, r
     the device stats (n, mean, M2, sigma) of w |A|^2 and, when asked, the per-event
     values."""
     m, n = _masses(masses)
-    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    _check_buf(values, "values", torch.float64, nevents)
+    _check_buf(stats, "stats", torch.float64, STATS)
+    dev = _resident(device, stream, values=values, stats=stats)
     k = len(resonances)
     arr = (BreitWigner * max(k, 1))(*[BreitWigner(int(a), int(b), float(c), float(d)) for a, b, c, d in resonances])
     if values is None and want_values:
@@ -267,10 +320,11 @@ def vegas_iteration(f: GaussBox, grid: torch.Tensor, calls: int, *, seed: int = 
                     want_hist: bool = True, want_values: bool = False, stream: Optional[torch.cuda.Stream] = None):
     """One VEGAS iteration on the device grid ([dim, bins+1] float64, asynchronous).
     Returns (stats, hist or None, values or None) as device tensors."""
-    if grid.dtype != torch.float64 or not grid.is_contiguous() or grid.dim() != 2 or grid.shape[0] != f.dim:
+    if not isinstance(grid, torch.Tensor) or grid.dtype != torch.float64 or not grid.is_contiguous() \
+            or grid.dim() != 2 or grid.shape[0] != f.dim:
         raise ValueError("grid must be a contiguous [dim, bins+1] float64 tensor")
     bins = grid.shape[1] - 1
-    dev = grid.device
+    dev = _resident(None, stream, grid=grid)
     stats = torch.empty(STATS, dtype=torch.float64, device=dev)
     hist = torch.empty((f.dim, bins), dtype=torch.float64, device=dev) if want_hist else None
     vals = torch.empty(max(calls, 1), dtype=torch.float64, device=dev) if want_values else None
@@ -311,12 +365,12 @@ def probe_write(out: torch.Tensor, weights: torch.Tensor, nevents: int, *, event
     constant data.  ``out`` is a contiguous ``[C, ld]`` float64 tensor (``[N, 4, ld]``
     of a generate call may be passed flattened); column c gets the value c and
     ``weights`` gets -1 for events < ``nevents``."""
-    if out.dtype != torch.float64 or not out.is_contiguous() or out.dim() < 2:
+    if not isinstance(out, torch.Tensor) or out.dtype != torch.float64 or not out.is_contiguous() or out.dim() < 2:
         raise ValueError("out must be a contiguous [C, ld] (or [N, 4, ld]) float64 tensor")
-    if weights.dtype != torch.float64 or not weights.is_contiguous():
-        raise ValueError("weights must be a contiguous float64 tensor")
+    _check_buf(weights, "weights", torch.float64, nevents)
     ld = out.shape[-1]
     cols = out.numel() // max(ld, 1)
+    _resident(None, stream, out=out, weights=weights)
     _check(lib().hydra_phsp_probe_write(_dptr(out), ld, cols, _dptr(weights), nevents, events_per_thread,
                                         _stream_handle(stream)))
 
@@ -327,11 +381,10 @@ def probe_philox(nevents: int, calls_per_event: int, *, seed: int = 42, stream_i
     exclusive-or folds of every Philox word the generator's events would draw
     (``PROBE_SPAN`` events per block)."""
     blocks = (nevents + PROBE_SPAN - 1) // PROBE_SPAN
+    _check_buf(fold, "fold", torch.int32, blocks)
+    dev = _resident(device, stream, fold=fold)
     if fold is None:
-        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         fold = torch.empty(max(blocks, 1), dtype=torch.int32, device=dev)
-    if fold.dtype != torch.int32 or not fold.is_contiguous() or fold.numel() < blocks:
-        raise ValueError(f"fold must be a contiguous int32 tensor of at least {blocks} entries")
     _check(lib().hydra_phsp_probe_philox(nevents, calls_per_event, seed, stream_id, _dptr(fold),
                                          _stream_handle(stream)))
     return fold
@@ -342,7 +395,8 @@ def integrate_async(parent_mass: float, masses: Sequence[float], nevents: int, *
                     device=None, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
     """Integral without storage; returns the device stats tensor (n, mean, M2, sigma)."""
     m, n = _masses(masses)
-    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    _check_buf(stats, "stats", torch.float64, STATS)
+    dev = _resident(device, stream, stats=stats)
     if stats is None:
         stats = torch.empty(STATS, dtype=torch.float64, device=dev)
     _check(lib().hydra_phsp_integrate_async(parent_mass, m, n, nevents, seed, stream_id, event_offset,
@@ -446,7 +500,19 @@ def _declare_batch(lib):
 def channel(parent_mass: float, masses: Sequence[float], nevents: int, *, seed: int = 42,
             stream_id: int = 0, event_offset: int = 0, out: Optional[torch.Tensor] = None,
             weights: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None) -> ChannelDesc:
-    """Describe one batch channel; out/weights None together = integrate-only."""
+    """Describe one batch channel; out/weights None together = integrate-only.
+    The buffers must live on the device the batch will run on (the current one
+    when the batch is enqueued or its plan created)."""
+    n = len(masses)
+    if out is not None and (not isinstance(out, torch.Tensor) or out.dtype != torch.float64
+                            or not out.is_contiguous() or out.dim() != 3 or tuple(out.shape[:2]) != (n, 4)):
+        raise ValueError(f"out must be a contiguous [{n}, 4, ld] float64 tensor")
+    if out is not None and out.shape[2] < nevents:
+        raise ValueError(f"out has ld {out.shape[2]} < nevents {nevents}")
+    _check_buf(weights, "weights", torch.float64, nevents)
+    _check_buf(stats, "stats", torch.float64, STATS)
+    if any(t is not None for t in (out, weights, stats)):
+        _resident(None, None, out=out, weights=weights, stats=stats)
     d = ChannelDesc()
     d.parent_mass = float(parent_mass)
     for k, mk in enumerate(masses):

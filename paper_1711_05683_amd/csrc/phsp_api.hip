@@ -258,20 +258,18 @@ static hipError_t launch_by_n(int n, const LaunchSpec& s, const KArgs& a, hipStr
 // register footprint of several events in flight costs more than it saves.
 static std::atomic<int> g_ept_override[3] = {{0}, {0}, {0}}; // read by launches on any thread
 // Off the line grid the staged kernel's LDS rounds and barriers change the
-// balance: measured the same way, a longer block run pays off for N = 3 and
-// for the mixed path up to N = 4, while from N = 7 the staged kernel's larger
-// register footprint makes one event per lane fastest (four events per lane at
-// N = 8..10 mixed take half as long again).
+// balance: measured the same way, a longer block run pays off for N = 3, while
+// from N = 7 the staged kernel's larger register footprint makes one event per
+// lane fastest.  The mixed path computes every event in FP64 registers like the
+// plain one and only stores narrower values, so it follows the same tables.
 static int default_ept(int mode, int n, int pmode, bool staged) {
     const int o = g_ept_override[mode].load(std::memory_order_relaxed);
     if (o > 0) return o;
     if (mode == kIntegrate) return 4;
     if (staged) {
         static const int kStagedFp64[11] = {0, 0, 2, 4, 2, 2, 2, 1, 1, 1, 1};
-        static const int kStagedMixed[11] = {0, 0, 4, 4, 4, 2, 2, 1, 1, 2, 1};
-        return mode == kMixed ? kStagedMixed[n] : kStagedFp64[n];
+        return kStagedFp64[n];
     }
-    if (mode == kMixed) return n == 2 ? 2 : 4;
     if (pmode == kPerEvent && n <= 3) return 1;
     static const int kFp64[11] = {0, 0, 2, 1, 4, 4, 4, 4, 1, 1, 1};
     return kFp64[n];

@@ -185,17 +185,6 @@ __device__ __forceinline__ void direction(double u, double v, const double2* tab
     nz = ct;
 }
 
-// FP32 direction: evaluated in FP64 (table + series, as above) and rounded once,
-// which is both cheaper than an FP32 sincos and accurate to FP32 rounding.
-__device__ __forceinline__ void direction(double u, double v, const double2* tab, float& nx, float& ny,
-                                          float& nz) {
-    double dx, dy, dz;
-    direction(u, v, tab, dx, dy, dz);
-    nx = (float)dx;
-    ny = (float)dy;
-    nz = (float)dz;
-}
-
 // Energies of the two bodies of a level in the rest frame of hi = lo + m + g:
 //   E(m) = (hi^2 + m^2 - lo^2) / (2 hi) = ((m + g)(hi + lo) + m^2) h,  h = 1/(2 hi),
 // and E(lo) likewise with m and lo exchanged; every term is non-negative, so
@@ -208,14 +197,23 @@ __device__ __forceinline__ double level_energy(double m, double lo, double g, do
 // C prod_i p_i with the invariant masses sigma_i = S_i + T R_i of the sorted
 // mass uniforms, the energy released g_i = T (R_{i+1} - R_i) and the breakup
 // momentum p_i of sigma_{i+1} -> sigma_i + m_{i+1}.  With KIN, the kinematics of
-// the level follow at once, in precision R (double: the plain path; float: the
-// mixed path): level 0 puts daughters 0 and 1 back to back in the rest frame of
-// {0,1}; level i adds daughter i+1 against {0..i} and boosts daughters 0..i
-// from the rest frame of {0..i} into that of {0..i+1}.  Only the current
-// level's quantities are live, besides the sorted uniforms and the momenta.
-template <int N, typename R, bool KIN>
+// the level follow at once, in FP64 for every output precision: level 0 puts
+// daughters 0 and 1 back to back in the rest frame of {0,1}; level i adds
+// daughter i+1 against {0..i} and boosts daughters 0..i from the rest frame of
+// {0..i} into that of {0..i+1}.  Only the current level's quantities are live,
+// besides the sorted uniforms and the momenta.
+//
+// The momenta stay FP64 between boosts even when the outputs are FP32: a light
+// daughter emitted nearly backwards to a boost of large gamma ends up with a lab
+// energy of order E/gamma, and its lab components move by about gamma times any
+// relative error in its rest-frame direction.  Rounding the vectors to FP32
+// between boosts (a direction error of 2^-24) therefore costs up to gamma * 6e-8
+// of the daughter's energy, which for massless daughters (where gamma reaches
+// 1e3 and beyond) exceeds 1e-5; rounding once at the store costs 2^-24.
+template <int N, bool KIN>
 __device__ __forceinline__ double event_levels(const Channel& c, const EventRng& rng, MassDraws<N>& d,
-                                               const double2* tab, Event<N, R>& ev) {
+                                               const double2* tab, Event<N, double>& ev) {
+    using R = double;
     sortnet_sort<N - 2>(d.u); // R_1..R_{N-2}; R_0 = 0 and R_{N-1} = 1 are implicit
     double carry = d.carry;
     double w = c.C;
@@ -240,24 +238,24 @@ __device__ __forceinline__ double event_levels(const Channel& c, const EventRng&
             draw_angles<N>(rng, i, carry, ut, up);
             R nx, ny, nz;
             direction(ut, up, tab, nx, ny, nz);
-            const R p = R(pd);
+            const R p = pd;
             ev.x[i + 1] = p * nx;
             ev.y[i + 1] = p * ny;
             ev.z[i + 1] = p * nz;
-            // Per-level scalars in FP64 (gap formulas: no square roots, nothing
-            // cancels), then rounded to R for the vector arithmetic.
+            // Per-level scalars from the gap formulas: no square roots, nothing
+            // cancels.
             if (i == 0) {
-                ev.e[1] = R(level_energy(m, sig_lo, g, sig_hi, h));
-                ev.e[0] = R(level_energy(sig_lo, m, g, sig_hi, h));
+                ev.e[1] = level_energy(m, sig_lo, g, sig_hi, h);
+                ev.e[0] = level_energy(sig_lo, m, g, sig_hi, h);
                 ev.x[0] = -ev.x[1];
                 ev.y[0] = -ev.y[1];
                 ev.z[0] = -ev.z[1];
             } else {
-                ev.e[i + 1] = R(level_energy(m, sig_lo, g, sig_hi, h));
+                ev.e[i + 1] = level_energy(m, sig_lo, g, sig_hi, h);
                 const double esys = level_energy(sig_lo, m, g, sig_hi, h); // energy of {0..i}
-                const R gamma = R(esys * inv_lo);
-                const R inv_gp1 = R(sig_lo * recip(esys + sig_lo)); // 1/(gamma+1) = sigma / (E + sigma)
-                const R eta = R(-(pd * inv_lo));
+                const R gamma = esys * inv_lo;
+                const R inv_gp1 = sig_lo * recip(esys + sig_lo); // 1/(gamma+1) = sigma / (E + sigma)
+                const R eta = -(pd * inv_lo);
                 const R ex = eta * nx, ey = eta * ny, ez = eta * nz;
 #pragma unroll
                 for (int k = 0; k <= i; ++k)
@@ -270,12 +268,11 @@ __device__ __forceinline__ double event_levels(const Channel& c, const EventRng&
     return w;
 }
 
-template <int N, typename R>
-__device__ __forceinline__ void boost_to_lab(Event<N, R>& ev, const Frame& f) {
-    const R ex = R(f.eta[0]), ey = R(f.eta[1]), ez = R(f.eta[2]);
-    const R gamma = R(f.gamma), inv_gp1 = R(f.inv_gp1);
+template <int N>
+__device__ __forceinline__ void boost_to_lab(Event<N, double>& ev, const Frame& f) {
 #pragma unroll
-    for (int k = 0; k < N; ++k) boost<R>(ev.e[k], ev.x[k], ev.y[k], ev.z[k], ex, ey, ez, gamma, inv_gp1);
+    for (int k = 0; k < N; ++k)
+        boost<double>(ev.e[k], ev.x[k], ev.y[k], ev.z[k], f.eta[0], f.eta[1], f.eta[2], f.gamma, f.inv_gp1);
 }
 
 // The block's copy of the (cos, sin) table: filled once per block from the

@@ -88,19 +88,20 @@ __device__ __forceinline__ EventRng event_rng(const KArgs& a, uint64_t base, uin
 }
 
 // One event's draws, levels, kinematics and lab boost, without stores: fills ev
-// (unless MODE is kIntegrate) and returns the weight.  Every kernel that needs an
-// event calls this, so the same event is bit-identical in all of them.
-template <int N, int PMODE, int MODE, typename R>
+// in FP64 (unless MODE is kIntegrate) and returns the weight.  Every kernel that
+// needs an event calls this, so the same event is bit-identical in all of them,
+// and the mixed path's FP32 outputs are the FP64 outputs rounded once.
+template <int N, int PMODE, int MODE>
 __device__ __forceinline__ double compute_event(const KArgs& a, uint64_t base, uint32_t off, const double2* tab,
-                                                Event<N, R>& ev) {
+                                                Event<N, double>& ev) {
     const EventRng rng = event_rng(a, base, off);
     MassDraws<N> d;
     draw_masses<N>(d, rng);
-    const double w = event_levels<N, R, MODE != kIntegrate>(a.ch, rng, d, tab, ev);
+    const double w = event_levels<N, MODE != kIntegrate>(a.ch, rng, d, tab, ev);
     if constexpr (MODE != kIntegrate) {
-        if constexpr (PMODE == kBroadcast) boost_to_lab<N, R>(ev, a.frame);
+        if constexpr (PMODE == kBroadcast) boost_to_lab<N>(ev, a.frame);
         if constexpr (PMODE == kPerEvent)
-            boost_to_lab<N, R>(ev, load_parent_frame(a.parent + base, a.ld_parent, off, a.ch.M, a.inv_M));
+            boost_to_lab<N>(ev, load_parent_frame(a.parent + base, a.ld_parent, off, a.ch.M, a.inv_M));
     }
     return w;
 }
@@ -113,18 +114,18 @@ __device__ __forceinline__ double compute_event(const KArgs& a, uint64_t base, u
 template <int N, int PMODE, int MODE, bool PIN = (N <= 5)>
 __device__ __forceinline__ double run_event(const KArgs& a, uint64_t base, uint32_t off, const double2* tab) {
     using R = typename std::conditional<MODE == kMixed, float, double>::type;
-    Event<N, R> ev;
-    const double w = compute_event<N, PMODE, MODE, R>(a, base, off, tab, ev);
+    Event<N, double> ev;
+    const double w = compute_event<N, PMODE, MODE>(a, base, off, tab, ev);
     if constexpr (MODE != kIntegrate) {
         R* out = static_cast<R*>(a.out) + base;
         const uint64_t ld = a.ld;
         const uint32_t boff = off * (uint32_t)sizeof(R);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            store_col<PIN>(out + (uint64_t)(4 * k + 0) * ld, boff, ev.e[k]);
-            store_col<PIN>(out + (uint64_t)(4 * k + 1) * ld, boff, ev.x[k]);
-            store_col<PIN>(out + (uint64_t)(4 * k + 2) * ld, boff, ev.y[k]);
-            store_col<PIN>(out + (uint64_t)(4 * k + 3) * ld, boff, ev.z[k]);
+            store_col<PIN>(out + (uint64_t)(4 * k + 0) * ld, boff, R(ev.e[k]));
+            store_col<PIN>(out + (uint64_t)(4 * k + 1) * ld, boff, R(ev.x[k]));
+            store_col<PIN>(out + (uint64_t)(4 * k + 2) * ld, boff, R(ev.y[k]));
+            store_col<PIN>(out + (uint64_t)(4 * k + 3) * ld, boff, R(ev.z[k]));
         }
         store_col<PIN>(a.weights + base, off * (uint32_t)sizeof(double), w);
     }
@@ -188,10 +189,10 @@ __device__ __forceinline__ void run_staged_block(const KArgs& a, uint64_t blk, c
         const uint32_t total = left < (uint64_t)kBlock ? (uint32_t)left : (uint32_t)kBlock;
         const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
         const bool valid = threadIdx.x < total;
-        Event<N, R> ev;
+        Event<N, double> ev;
         double w = 0.0;
         if (valid) {
-            w = compute_event<N, PMODE, MODE, R>(a, base, off, tab, ev);
+            w = compute_event<N, PMODE, MODE>(a, base, off, tab, ev);
             if (k == 0) {
                 acc = Moments{1.0, w, 0.0};
             } else {
@@ -209,7 +210,7 @@ __device__ __forceinline__ void run_staged_block(const KArgs& a, uint64_t blk, c
         }
 #pragma unroll
         for (int d = 0; d < N; ++d) {
-            const R v[4] = {ev.e[d], ev.x[d], ev.y[d], ev.z[d]};
+            const R v[4] = {R(ev.e[d]), R(ev.x[d]), R(ev.y[d]), R(ev.z[d])};
             R* const cols[4] = {out + (uint64_t)(4 * d + 0) * a.ld, out + (uint64_t)(4 * d + 1) * a.ld,
                                 out + (uint64_t)(4 * d + 2) * a.ld, out + (uint64_t)(4 * d + 3) * a.ld};
             ColWindow w4[4];

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_phsp_model(const ModelArgs m) {
         const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
         if (base + off < m.a.nevents) {
             Event<N, double> ev;
-            const double w = compute_event<N, kAtRest, kFp64, double>(m.a, base, off, tab, ev);
+            const double w = compute_event<N, kAtRest, kFp64>(m.a, base, off, tab, ev);
             const double v = w * model_intensity<N>(ev, m);
             if (m.values != nullptr) __builtin_nontemporal_store(v, m.values + base + off);
             // the per-lane Welford step of the single-channel kernel

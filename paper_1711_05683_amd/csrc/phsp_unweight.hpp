@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_unw_max(const UnwArgs u) {
         const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
         if (base + off < u.a.nevents) {
             Event<N, double> ev;
-            m = fmax(m, compute_event<N, kAtRest, kIntegrate, double>(u.a, base, off, nullptr, ev));
+            m = fmax(m, compute_event<N, kAtRest, kIntegrate>(u.a, base, off, nullptr, ev));
         }
     }
     m = wave_max(m);
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_unw_count(const UnwArgs u) {
         const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
         if (base + off < u.a.nevents) {
             Event<N, double> ev;
-            const double w = compute_event<N, kAtRest, kIntegrate, double>(u.a, base, off, nullptr, ev);
+            const double w = compute_event<N, kAtRest, kIntegrate>(u.a, base, off, nullptr, ev);
             const double v = accept_uniform<N>(u.a, base, off);
             kept += (v * wmax < w) ? 1u : 0u;
             over += (w > wmax) ? 1u : 0u;
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
         bool keep = false;
         Event<N, double> ev;
         if (base + off < u.a.nevents) {
-            const double w = compute_event<N, PMODE, kFp64, double>(u.a, base, off, tab, ev);
+            const double w = compute_event<N, PMODE, kFp64>(u.a, base, off, tab, ev);
             keep = accept_uniform<N>(u.a, base, off) * wmax < w;
         }
         const uint64_t mask = __ballot(keep);

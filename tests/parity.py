@@ -12,12 +12,6 @@ import numpy as np
 FP64_TOL = 1e-11
 MIXED_TOL = 1e-5
 MIXED_INTEGRAL_TOL = 1e-6
-# Massless daughters can end up arbitrarily soft after large boosts; the lab
-# momenta are then ill-conditioned in the FP32 rest-frame angles (relative
-# sensitivity ~ gamma), so for them the FP32 bound is stated per parent mass and
-# as a tail fraction instead of as a maximum over E_d.
-MIXED_MASSLESS_TOL_M = 1e-6
-MIXED_MASSLESS_TAIL = 1e-4
 
 
 def event_errors(p4_gpu: np.ndarray, p4_ora: np.ndarray):

@@ -342,3 +342,55 @@ def test_event_counts_beyond_one_launch_are_rejected(P):
     c.stats_dev = 8
     c.nevents = big
     assert L.hydra_phsp_batch_run(P._channel_array([c]), 1, None, None, None) == P.EINVAL
+
+
+def test_binding_rejects_bad_buffers_before_any_launch(P):
+    """The C ABI cannot see buffer sizes or residency, so the binding rejects
+    short, mistyped and host buffers before any device query or launch (this
+    runs on a machine without a GPU: every case must raise ValueError first)."""
+    import torch
+    M, m = 5.279, [3.097, 0.4937, 0.13957]
+    f64, f32, i64, i32 = torch.float64, torch.float32, torch.int64, torch.int32
+    host = lambda n, dt=f64: torch.zeros(n, dtype=dt)  # noqa: E731
+    cases = [
+        ("weights", lambda: P.generate(M, m, 100, weights=host(99))),
+        ("stats", lambda: P.generate(M, m, 100, stats=host(3))),
+        ("weights", lambda: P.generate(M, m, 100, weights=host(100, f32))),
+        ("out", lambda: P.generate(M, m, 100, out=torch.zeros(3, 4, 100, dtype=f32))),
+        ("out", lambda: P.generate(M, m, 100, out=torch.zeros(2, 4, 100, dtype=f64))),
+        ("out", lambda: P.generate(M, m, 100, out=torch.zeros(3, 4, 100, dtype=f64).transpose(0, 1))),
+        ("parent_dev", lambda: P.generate(M, m, 100, parent_dev=torch.zeros(4, 99, dtype=f64))),
+        ("parent_dev", lambda: P.generate(M, m, 100, parent_dev=torch.zeros(3, 100, dtype=f64))),
+        ("CUDA", lambda: P.generate(M, m, 100, weights=host(100))),
+        ("CUDA", lambda: P.generate(M, m, 100, out=torch.zeros(3, 4, 128, dtype=f64))),
+        ("CUDA", lambda: P.generate(M, m, 100, parent_dev=torch.zeros(4, 100, dtype=f64))),
+        ("counts", lambda: P.generate_unweighted(M, m, 100, counts=host(1, i64))),
+        ("counts", lambda: P.generate_unweighted(M, m, 100, counts=host(2, i32))),
+        ("w_max_out", lambda: P.generate_unweighted(M, m, 100, w_max_out=host(0))),
+        ("index", lambda: P.generate_unweighted(M, m, 100, index=torch.zeros(2, 64, dtype=i64))),
+        ("index", lambda: P.generate_unweighted(M, m, 100, out=torch.zeros(3, 4, 128, dtype=f64),
+                                                index=host(64, i64))),
+        ("CUDA", lambda: P.generate_unweighted(M, m, 100, counts=host(2, i64))),
+        ("values", lambda: P.integrate_model(M, m, 100, values=host(99))),
+        ("stats", lambda: P.integrate_model(M, m, 100, stats=host(2))),
+        ("CUDA", lambda: P.integrate_model(M, m, 100, stats=host(4))),
+        ("stats", lambda: P.integrate_async(M, m, 100, stats=host(3))),
+        ("CUDA", lambda: P.integrate_async(M, m, 100, stats=host(4))),
+        ("weights", lambda: P.probe_write(torch.zeros(12, 128, dtype=f64), host(99), 100)),
+        ("CUDA", lambda: P.probe_write(torch.zeros(12, 128, dtype=f64), host(100), 100)),
+        ("fold", lambda: P.probe_philox(5000, 3, fold=host(4, i32))),
+        ("CUDA", lambda: P.probe_philox(5000, 3, fold=host(5, i32))),
+        ("grid", lambda: P.vegas_iteration(P.gauss_box([0.0], [1.0], [0.5], [0.1]),
+                                           torch.zeros(2, 51, dtype=f64), 100)),
+        ("CUDA", lambda: P.vegas_iteration(P.gauss_box([0.0], [1.0], [0.5], [0.1]),
+                                           torch.zeros(1, 51, dtype=f64), 100)),
+        ("weights", lambda: P.channel(M, m, 100, out=torch.zeros(3, 4, 128, dtype=f64), weights=host(50),
+                                      stats=host(4))),
+        ("ld", lambda: P.channel(M, m, 100, out=torch.zeros(3, 4, 64, dtype=f64), weights=host(100))),
+        ("stats", lambda: P.channel(M, m, 100, stats=host(2))),
+        ("CUDA", lambda: P.channel(M, m, 100, stats=host(4))),
+    ]
+    for what, fn in cases:
+        with pytest.raises(ValueError) as e:
+            fn()
+        assert what in str(e.value), (what, str(e.value))

@@ -128,11 +128,16 @@ int hydra_phsp_integrate(double parent_mass, const double *masses_host, int n_da
 /* Mixed FP32/FP64 path                                                      */
 /* ------------------------------------------------------------------------ */
 
-/* As hydra_phsp_generate, but the decay angles, energies, boosts and the
- * momentum outputs are FP32 (p4_out_dev is [n_daughters][4][ld] floats);
- * uniforms, sorting, invariant masses, breakup momenta, the weight and the
- * integral stay FP64, so weights equal the FP64 path's, and so do the stats
- * when both paths run the same events per thread. */
+/* As hydra_phsp_generate (sec. 4.2), but the momentum outputs are FP32
+ * (p4_out_dev is [n_daughters][4][ld] floats, half the bytes).  Every event is
+ * computed in FP64 registers exactly as on the FP64 path and each component is
+ * rounded once (to nearest) when stored, so the outputs are the FP64 path's
+ * momenta rounded to FP32 (|dc| <= 2^-24 |c| beyond the FP64 error, for any
+ * daughter masses), the weights are the FP64 path's, and so are the stats when
+ * both paths run the same events per thread.  FP32 arithmetic in the boost
+ * chain was rejected: a light daughter emitted against a boost of large gamma
+ * loses about gamma * 2^-24 of its lab energy to an FP32 direction, beyond
+ * 1e-5 for massless daughters. */
 int hydra_phsp_generate_mixed(double parent_mass, const double *masses_host, int n_daughters,
                               const double *parent_p4_host, const double *parent_p4_dev,
                               uint64_t ld_parent, uint64_t nevents, uint64_t seed,
@@ -152,11 +157,10 @@ int hydra_phsp_selftest_sortnet(void);
 /* Events per thread of the single-channel kernels, per path: path 0 =
  * integrate-only, 1 = FP64 generate, 2 = mixed generate; ept in {1, 2, 4}, or 0
  * for the library default.  Defaults with columns on the 128-byte line grid:
- * integrate 4; mixed 2 for n_daughters = 2, else 4; FP64 generate 2 for N = 2,
- * 1 for N = 3, 4 for N = 4..7, 1 for N >= 8, and 1 with per-event parents for
- * N <= 3.  Columns off the line grid (the staged kernel) have their own:
- * FP64 (any parent mode) 2, 4, 2, 2, 2, 1, 1, 1, 1 and mixed 4, 4, 4, 2, 2, 1,
- * 1, 2, 1 for N = 2..10.  One launch covers at most
+ * integrate 4; FP64 and mixed generate 2 for N = 2, 1 for N = 3, 4 for
+ * N = 4..7, 1 for N >= 8, and 1 with per-event parents for N <= 3.  Columns
+ * off the line grid (the staged kernel) have their own: 2, 4, 2, 2, 2, 1, 1,
+ * 1, 1 for N = 2..10 (any parent mode, both paths).  One launch covers at most
  * (2^32 - 1) / 256 * ept events; larger counts are rejected with EINVAL.
  * Process-wide; changes the launch shape only (events are bit-identical for
  * every value; integrals agree to rounding). */

@@ -490,7 +490,7 @@ int oracle_model_integrate(double parent_mass, const double *masses, int n, int 
 
 /* ---------------------------------------------------------------------- */
 /* VEGAS importance sampling (Lepage, J. Comput. Phys. 27 (1978) 192; the   */
-/* paper's sec. 5.1 uses it on a 10-dimensional Gaussian) and plain Monte   */
+/* paper's sec. 4.1 uses it on a 10-dimensional Gaussian) and plain Monte   */
 /* Carlo as its special case: one iteration on the uniform grid.            */
 /*                                                                          */
 /* Integrand: f(x) = prod_d exp(-(x_d - mu_d)^2 / (2 s_d^2)) / (s_d sqrt(2 pi))

@@ -50,6 +50,9 @@ MUTATIONS = [
      "const double y = g[b] + u * width;"),
     ("VEGAS damping exponent sign", "r[k] = R > 1.0 ? pow((1.0 - 1.0 / R) / log(R), alpha) : 1.0;",
      "r[k] = R > 1.0 ? pow((1.0 - 1.0 / R) / log(R), -alpha) : 1.0;"),
+    ("VEGAS histogram not smoothed", "tot += sm[k];", "sm[k] = h[k];\n            tot += sm[k];"),
+    ("VEGAS end-bin smoothing over three", "if (k == 0) sm[k] = (h[0] + h[1]) / 2.0;",
+     "if (k == 0) sm[k] = (h[0] + h[1]) / 3.0;"),
     ("VEGAS new edge mirrored in the old bin", "edges[e] = g[k] + frac * (g[k + 1] - g[k]);",
      "edges[e] = g[k] + (1.0 - frac) * (g[k + 1] - g[k]);"),
 ]

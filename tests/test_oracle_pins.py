@@ -566,6 +566,30 @@ def test_vegas_refinement_invariants(oracle_lib):
     assert w[24] < 0.5 * w[0] and w[25] < 0.5 * w[-1]
 
 
+def test_vegas_refinement_single_spike_by_hand(oracle_lib):
+    """Worked examples of one refinement step (Lepage's smoothing, damping and
+    equal-importance re-cut), derived by hand from a single-spike histogram on a
+    uniform grid; they fail if the neighbour smoothing is dropped or its end-bin
+    divisor changed."""
+    # K = 6, all of value^2 in bin 2, alpha = 0 (every bin with smoothed content
+    # gets importance 1): smoothing spreads the spike to bins 1, 2, 3, i.e.
+    # [1/6, 2/3], which the six new bins share equally (1/12 each), the first new
+    # bin also taking the empty bin 0
+    g = oracle_lib.uniform_grid(1, 6)
+    h = np.array([[0.0, 0.0, 1.0, 0.0, 0.0, 0.0]])
+    want = np.array([0.0, 1 / 4, 1 / 3, 5 / 12, 1 / 2, 7 / 12, 1.0])
+    assert np.allclose(oracle_lib.vegas_refine(g, h, alpha=0.0)[0], want, rtol=0.0, atol=1e-15)
+    # K = 3, spike in bin 0, alpha = 1: smoothed (1/2, 1/3, 0), total 5/6, so
+    # R = 5/3 and 5/2 and importances r0 = (2/5)/ln(5/3), r1 = (3/5)/ln(5/2);
+    # each new bin holds (r0 + r1)/3: edge 1 lies in old bin 0 at that share of
+    # r0, edge 2 in old bin 1 at (2(r0 + r1)/3 - r0)/r1
+    r0, r1 = 0.4 / math.log(5 / 3), 0.6 / math.log(2.5)
+    per = (r0 + r1) / 3
+    want = np.array([0.0, per / r0 / 3, 1 / 3 + (2 * per - r0) / r1 / 3, 1.0])
+    got = oracle_lib.vegas_refine(oracle_lib.uniform_grid(1, 3), np.array([[1.0, 0.0, 0.0]]), alpha=1.0)[0]
+    assert np.allclose(got, want, rtol=0.0, atol=1e-14), (got, want)
+
+
 def test_vegas_grid_converges_to_the_integrand(oracle_lib):
     # one dimension: the adapted density is close to |f| normalised, so the
     # grid's edges sit near the quantiles of the (truncated) Gaussian

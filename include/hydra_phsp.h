@@ -124,6 +124,27 @@ int hydra_phsp_integrate(double parent_mass, const double *masses_host, int n_da
                          uint64_t event_offset, double *mean_host, double *sigma_host,
                          void *stream);
 
+/* For callers that cannot allocate device memory: code being captured into a
+ * HIP graph, tight serving loops, hosts that forbid hipMalloc.  Same arguments,
+ * events, weights and stats as hydra_phsp_generate (the same kernels and the
+ * same merge tree), but the block partials and merge results live in a fixed
+ * device array of the library (about 24 MiB per GPU, held until the process
+ * ends) instead of a per-stream workspace: the call makes no hipMalloc, hipFree
+ * or other allocating call, and records no timing events.  Limit: at most
+ * 2^20 blocks of 256 * ept events (ept as hydra_phsp_events_per_thread reports
+ * for path 1), e.g. 2.68e8 events for n_daughters = 3 and 1.07e9 for
+ * n_daughters = 4..7; larger counts fail with EINVAL before any work.
+ * The first call on a device performs a one-time, synchronous set-up on the
+ * current device (it looks up the array's address and uploads a 4 KiB
+ * trigonometric table); call it once, e.g. with nevents = 0, before capturing.
+ * Every call on one GPU shares the array, so calls that overlap on one GPU
+ * (other streams, other threads) race and give wrong stats; serialise them. */
+int hydra_phsp_generate_noalloc(double parent_mass, const double *masses_host, int n_daughters,
+                                const double *parent_p4_host, const double *parent_p4_dev,
+                                uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t stream_id,
+                                uint64_t event_offset, double *p4_out_dev, uint64_t ld,
+                                double *weights_dev, double *stats_dev, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Mixed FP32/FP64 path                                                      */
 /* ------------------------------------------------------------------------ */

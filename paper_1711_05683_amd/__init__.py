@@ -42,6 +42,8 @@ def _declare(lib):
     lib.hydra_phsp_generate.restype = i
     lib.hydra_phsp_generate_mixed.argtypes = lib.hydra_phsp_generate.argtypes
     lib.hydra_phsp_generate_mixed.restype = i
+    lib.hydra_phsp_generate_noalloc.argtypes = lib.hydra_phsp_generate.argtypes
+    lib.hydra_phsp_generate_noalloc.restype = i
     lib.hydra_phsp_integrate_async.argtypes = [d, dp, i, u64, u64, u32, u64, vp, vp]
     lib.hydra_phsp_integrate_async.restype = i
     lib.hydra_phsp_integrate.argtypes = [d, dp, i, u64, u64, u32, u64, dp, dp, vp]
@@ -171,7 +173,7 @@ def generate(parent_mass: float, masses: Sequence[float], nevents: int, *, seed:
              stream_id: int = 0, event_offset: int = 0, parent_p4: Optional[Sequence[float]] = None,
              parent_dev: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
              weights: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None,
-             want_stats: bool = True, mixed: bool = False, device=None,
+             want_stats: bool = True, mixed: bool = False, noalloc: bool = False, device=None,
              stream: Optional[torch.cuda.Stream] = None):
     """Generate events on the GPU (asynchronous on the current stream).
 
@@ -180,7 +182,9 @@ def generate(parent_mass: float, masses: Sequence[float], nevents: int, *, seed:
     with ``aligned_ld(nevents)`` columns), ``weights`` is ``[nevents]`` float64 and ``stats`` holds
     ``(n, mean, M2, sigma)`` of the weights (None unless ``want_stats``).
     ``parent_p4`` is one (E, px, py, pz) applied to all events; ``parent_dev`` a
-    ``[4, ld_parent]`` float64 device tensor of per-event parents."""
+    ``[4, ld_parent]`` float64 device tensor of per-event parents.  ``noalloc``
+    calls ``hydra_phsp_generate_noalloc`` (the library allocates nothing; pass
+    ``out``, ``weights`` and ``stats`` to keep the binding from allocating)."""
     m, n = _masses(masses)
     dtype = torch.float32 if mixed else torch.float64
     if out is not None and (not isinstance(out, torch.Tensor) or out.dtype != dtype or not out.is_contiguous()
@@ -210,6 +214,10 @@ def generate(parent_mass: float, masses: Sequence[float], nevents: int, *, seed:
     if parent_dev is not None:
         ldp = parent_dev.shape[1]
     fn = lib().hydra_phsp_generate_mixed if mixed else lib().hydra_phsp_generate
+    if noalloc:
+        if mixed:
+            raise ValueError("the allocation-free entry point is FP64 only")
+        fn = lib().hydra_phsp_generate_noalloc
     _check(fn(parent_mass, m, n, p4h, _dptr(parent_dev), ldp, nevents, seed, stream_id, event_offset,
               _dptr(out), ld, _dptr(weights), _dptr(stats), _stream_handle(stream)))
     if own_out:

@@ -125,8 +125,6 @@ int workspace_for(hipStream_t stream, uint64_t partials, Workspace** out) {
     return HYDRA_PHSP_OK;
 }
 
-static void release_trig_tables();
-
 int release_workspaces() {
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     hipError_t e = hipDeviceSynchronize();
@@ -138,51 +136,79 @@ int release_workspaces() {
         if (kv.second.stats_host) (void)hipHostFree(kv.second.stats_host);
     }
     g_ws.clear();
-    release_trig_tables();
     return HYDRA_PHSP_OK;
 }
 
 // ------------------------------------------------------ trigonometric table ----
 
-static std::mutex g_trig_mu;
-static std::map<int, double2*> g_trig;
-
 // (cos, sin)(2 pi k / kTrigSize) for k = 0..kTrigSize-1, evaluated in long double
-// and rounded once; one device copy per GPU, created on first use.
+// and rounded once.  The table lives in a file-scope device array (every GPU
+// holds its own copy), uploaded once per device on first use; no allocation.
+static __device__ __align__(256) double2 trig_dev[kTrigSize];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_trig_mu;
+static double2* g_trig[kMaxDevices]; // per device: address of its trig_dev copy, once uploaded
+
 int trig_table(const double2** out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(HYDRA_PHSP_EINVAL, "device index beyond the library's table");
     std::lock_guard<std::mutex> lock(g_trig_mu);
-    auto it = g_trig.find(dev);
-    if (it != g_trig.end()) {
-        *out = it->second;
+    if (g_trig[dev] != nullptr) {
+        *out = g_trig[dev];
         return HYDRA_PHSP_OK;
     }
     const long double two_pi = 6.283185307179586476925286766559005768L;
-    std::vector<double2> h(kTrigSize);
+    double2 h[kTrigSize];
     for (int k = 0; k < kTrigSize; ++k) {
         const long double a = two_pi * (long double)k / (long double)kTrigSize;
         h[k].x = (double)cosl(a);
         h[k].y = (double)sinl(a);
     }
     double2* d = nullptr;
-    e = hipMalloc(&d, sizeof(double2) * kTrigSize);
-    if (e != hipSuccess) return fail(HYDRA_PHSP_ENOMEM, "table allocation failed");
-    e = hipMemcpy(d, h.data(), sizeof(double2) * kTrigSize, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        (void)hipFree(d);
-        return fail_hip(e, "table upload");
-    }
+    e = hipGetSymbolAddress((void**)&d, HIP_SYMBOL(trig_dev));
+    if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(trig table)");
+    e = hipMemcpy(d, h, sizeof(h), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail_hip(e, "table upload");
     g_trig[dev] = d;
     *out = d;
     return HYDRA_PHSP_OK;
 }
 
-static void release_trig_tables() {
-    std::lock_guard<std::mutex> lock(g_trig_mu);
-    for (auto& kv : g_trig) (void)hipFree(kv.second);
-    g_trig.clear();
+// ------------------------------------------------------- fixed scratch ----
+
+// Device memory of the allocation-free entry point: the stage-1 merge results
+// (kMaxGroups) followed by up to kScratchPartials block partials, in one
+// file-scope device array.  Each GPU holds its own copy for the life of the
+// process; calls on one GPU share it (and race if they overlap).  Host code
+// only ever uses the per-device address from hipGetSymbolAddress, never the
+// array's name (which on the host is a stand-in, not a device address).
+constexpr uint64_t kScratchPartials = 1ull << 20;
+static __device__ __align__(256) Moments scratch[kMaxGroups + kScratchPartials];
+
+static std::mutex g_scratch_mu;
+static Moments* g_scratch[kMaxDevices]; // per device: address of its scratch copy
+
+// Set-up on first use per device (the device must be current): look up this
+// device's scratch address, and make sure its trigonometric table is uploaded.
+static int scratch_for_current_device(Moments** out, const double2** trig) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(HYDRA_PHSP_EINVAL, "device index beyond the library's table");
+    const int st = trig_table(trig);
+    if (st != HYDRA_PHSP_OK) return st;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev] == nullptr) {
+        Moments* p = nullptr;
+        e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return HYDRA_PHSP_OK;
 }
 
 // ----------------------------------------------------------------- timing ----
@@ -277,27 +303,64 @@ static int default_ept(int mode, int n, int pmode, bool staged) {
 
 int single_channel_ept(int mode, int n, int pmode, bool staged) { return default_ept(mode, n, pmode, staged); }
 
-int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const double* parent_dev,
-               uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
-               int mode, void* out, uint64_t ld, double* weights, double* stats_dev,
-               hipStream_t stream, int ept_override) {
+// Launch shape of a single-channel call: events per thread, block count and
+// kernel form (direct or staged stores).
+struct SingleShape {
+    int ept;
+    uint64_t blocks;
+    bool staged;
+};
+
+static int single_shape(int n, int pmode, uint64_t nevents, int mode, const void* out, uint64_t ld,
+                        const double* weights, int ept_override, SingleShape* sh) {
     // Columns on the 128-byte line grid take the direct-store kernel; any other
     // layout the staged one (whole-line writes through LDS).
     const uint64_t elem = mode == kMixed ? sizeof(float) : sizeof(double);
     const bool aligned = (uintptr_t)out % kLineBytes == 0 && (ld * elem) % kLineBytes == 0 &&
                          (uintptr_t)weights % kLineBytes == 0;
-    const bool staged = mode != kIntegrate && !aligned;
-    const int ept = ept_override > 0 ? ept_override : default_ept(mode, n, pmode, staged);
-    const uint64_t per_block = (uint64_t)kBlock * (uint64_t)ept;
-    const uint64_t blocks = ceil_div(nevents, per_block);
-    if (blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
+    sh->staged = mode != kIntegrate && !aligned;
+    sh->ept = ept_override > 0 ? ept_override : default_ept(mode, n, pmode, sh->staged);
+    const uint64_t per_block = (uint64_t)kBlock * (uint64_t)sh->ept;
+    sh->blocks = ceil_div(nevents, per_block);
+    if (sh->blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
         return fail(HYDRA_PHSP_EINVAL, "nevents too large for one launch (more than 2^32 - 1 threads)");
+    return HYDRA_PHSP_OK;
+}
+
+// The launches of one single-channel call with its block partials at `partials`
+// and the stage-1 merge results at `mid` (both large enough for sh.blocks).
+static int enqueue_single(const Channel& ch, int n, int pmode, const Frame* frame, const double* parent_dev,
+                          uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
+                          int mode, void* out, uint64_t ld, double* weights, double* stats_dev,
+                          hipStream_t stream, const SingleShape& sh, Moments* partials, Moments* mid,
+                          const double2* trig, bool timed);
+
+int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const double* parent_dev,
+               uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
+               int mode, void* out, uint64_t ld, double* weights, double* stats_dev,
+               hipStream_t stream, int ept_override) {
+    SingleShape sh;
+    int st = single_shape(n, pmode, nevents, mode, out, ld, weights, ept_override, &sh);
+    if (st != HYDRA_PHSP_OK) return st;
     Workspace* ws = nullptr;
-    int st = workspace_for(stream, blocks, &ws);
+    st = workspace_for(stream, sh.blocks, &ws);
     if (st != HYDRA_PHSP_OK) return st;
     const double2* trig = nullptr;
     st = trig_table(&trig);
     if (st != HYDRA_PHSP_OK) return st;
+    return enqueue_single(ch, n, pmode, frame, parent_dev, ld_parent, nevents, seed, sid, offset, mode, out, ld,
+                          weights, stats_dev, stream, sh, ws->partials, ws->mid, trig, true);
+}
+
+static int merge_partials_into(hipStream_t stream, const Moments* partials, uint64_t blocks, Moments* mid,
+                               double* stats_dev);
+
+static int enqueue_single(const Channel& ch, int n, int pmode, const Frame* frame, const double* parent_dev,
+                          uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t sid, uint64_t offset,
+                          int mode, void* out, uint64_t ld, double* weights, double* stats_dev,
+                          hipStream_t stream, const SingleShape& sh, Moments* partials, Moments* mid,
+                          const double2* trig, bool timed) {
+    const uint64_t blocks = sh.blocks;
     if (blocks > 0) {
         KArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -314,15 +377,15 @@ int run_single(const Channel& ch, int n, int pmode, const Frame* frame, const do
         a.out = out;
         a.ld = ld;
         a.weights = weights;
-        a.partials = ws->partials;
+        a.partials = partials;
         a.trig = trig;
-        LaunchSpec s{pmode, mode, ept, blocks, staged};
-        const long slot = timing_begin(stream);
+        LaunchSpec s{pmode, mode, sh.ept, blocks, sh.staged};
+        const long slot = timed ? timing_begin(stream) : -1;
         hipError_t e = launch_by_n(n, s, a, stream);
         timing_end(stream, slot);
         if (e != hipSuccess) return fail_hip(e, "phase-space kernel launch");
     }
-    if (stats_dev != nullptr) return merge_partials(stream, ws->partials, blocks, stats_dev);
+    if (stats_dev != nullptr) return merge_partials_into(stream, partials, blocks, mid, stats_dev);
     return HYDRA_PHSP_OK;
 }
 
@@ -337,12 +400,17 @@ int merge_partials(hipStream_t stream, const Moments* partials, uint64_t blocks,
     Workspace* ws = nullptr;
     const int st = workspace_for(stream, blocks, &ws);
     if (st != HYDRA_PHSP_OK) return st;
+    return merge_partials_into(stream, partials, blocks, ws->mid, stats_dev);
+}
+
+static int merge_partials_into(hipStream_t stream, const Moments* partials, uint64_t blocks, Moments* mid,
+                               double* stats_dev) {
     const uint64_t groups = stage1_groups(blocks);
     hipLaunchKernelGGL(k_merge_stage1, dim3((unsigned)groups), dim3(kStage1Block), 0, stream, partials, blocks,
-                       ws->mid);
+                       mid);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail_hip(e, "merge kernel launch");
-    hipLaunchKernelGGL(k_merge_stage2, dim3(1), dim3(kStage2Block), 0, stream, (const Moments*)ws->mid, groups,
+    hipLaunchKernelGGL(k_merge_stage2, dim3(1), dim3(kStage2Block), 0, stream, (const Moments*)mid, groups,
                        stats_dev);
     e = hipGetLastError();
     if (e != hipSuccess) return fail_hip(e, "merge kernel launch");
@@ -352,7 +420,7 @@ int merge_partials(hipStream_t stream, const Moments* partials, uint64_t blocks,
 static int generate_common(double M, const double* masses, int n, const double* parent_p4_host,
                            const double* parent_p4_dev, uint64_t ld_parent, uint64_t nevents,
                            uint64_t seed, uint32_t sid, uint64_t offset, void* out, uint64_t ld,
-                           double* weights, double* stats_dev, void* stream, int mode) {
+                           double* weights, double* stats_dev, void* stream, int mode, bool noalloc = false) {
     Channel ch;
     int st = make_channel(M, masses, n, &ch);
     if (st != HYDRA_PHSP_OK) return st;
@@ -376,8 +444,25 @@ static int generate_common(double M, const double* masses, int n, const double* 
         if (ld_parent < nevents) return fail(HYDRA_PHSP_EINVAL, "ld_parent must be >= nevents");
         pmode = kPerEvent;
     }
-    return run_single(ch, n, pmode, &frame, parent_p4_dev, ld_parent, nevents, seed, sid, offset, mode,
-                      out, ld, weights, stats_dev, (hipStream_t)stream, 0);
+    if (!noalloc)
+        return run_single(ch, n, pmode, &frame, parent_p4_dev, ld_parent, nevents, seed, sid, offset, mode,
+                          out, ld, weights, stats_dev, (hipStream_t)stream, 0);
+    // Same launches and kernels, with the partials and merge results in the
+    // fixed scratch array instead of the per-stream workspace; nothing needs
+    // clearing (every block writes its partial, every group its merge result).
+    SingleShape sh;
+    st = single_shape(n, pmode, nevents, mode, out, ld, weights, 0, &sh);
+    if (st != HYDRA_PHSP_OK) return st;
+    if (sh.blocks > kScratchPartials)
+        return fail(HYDRA_PHSP_EINVAL, "nevents too large for hydra_phsp_generate_noalloc: more than " +
+                                           std::to_string(kScratchPartials) + " blocks of " +
+                                           std::to_string(kBlock * sh.ept) + " events");
+    Moments* fixed = nullptr;
+    const double2* trig = nullptr;
+    st = scratch_for_current_device(&fixed, &trig);
+    if (st != HYDRA_PHSP_OK) return st;
+    return enqueue_single(ch, n, pmode, &frame, parent_p4_dev, ld_parent, nevents, seed, sid, offset, mode, out,
+                          ld, weights, stats_dev, (hipStream_t)stream, sh, fixed + kMaxGroups, fixed, trig, false);
 }
 
 } // namespace hphsp
@@ -394,6 +479,16 @@ int hydra_phsp_generate(double parent_mass, const double* masses_host, int n_dau
     return generate_common(parent_mass, masses_host, n_daughters, parent_p4_host, parent_p4_dev,
                            ld_parent, nevents, seed, stream_id, event_offset, p4_out_dev, ld,
                            weights_dev, stats_dev, stream, kFp64);
+}
+
+int hydra_phsp_generate_noalloc(double parent_mass, const double* masses_host, int n_daughters,
+                                const double* parent_p4_host, const double* parent_p4_dev, uint64_t ld_parent,
+                                uint64_t nevents, uint64_t seed, uint32_t stream_id, uint64_t event_offset,
+                                double* p4_out_dev, uint64_t ld, double* weights_dev, double* stats_dev,
+                                void* stream) {
+    return generate_common(parent_mass, masses_host, n_daughters, parent_p4_host, parent_p4_dev,
+                           ld_parent, nevents, seed, stream_id, event_offset, p4_out_dev, ld,
+                           weights_dev, stats_dev, stream, kFp64, true);
 }
 
 int hydra_phsp_generate_mixed(double parent_mass, const double* masses_host, int n_daughters,

@@ -396,3 +396,25 @@ def test_binding_rejects_bad_buffers_before_any_launch(P):
         with pytest.raises(ValueError) as e:
             fn()
         assert what in str(e.value), (what, str(e.value))
+
+
+def test_noalloc_rejects_counts_beyond_its_scratch_before_device_work(P):
+    """hydra_phsp_generate_noalloc keeps its block partials in a fixed array of
+    2^20 entries: a count that needs more blocks fails with EINVAL, before any
+    device call (fake pointers, no GPU needed)."""
+    f = P.lib().hydra_phsp_generate_noalloc
+    m, n = P._masses([3.097, 0.4937, 0.13957])
+    ept = P.events_per_thread(1, 3)
+    fits = (1 << 20) * 256 * ept
+    out, w, st = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21), ctypes.c_void_p(1 << 22)
+    # ld a multiple of 16 doubles keeps the columns on the line grid, the layout
+    # whose events per thread the query above reports
+    r = f(5.279, m, n, None, None, 0, fits + 1, 42, 0, 0, out, fits + 32, w, st, None)
+    assert r == P.EINVAL and "noalloc" in P.lib().hydra_phsp_last_error().decode()
+    m6, n6 = P._masses([0.13957] * 6)
+    ept6 = P.events_per_thread(1, 6)
+    r = f(10.0, m6, n6, None, None, 0, (1 << 20) * 256 * ept6 + 1, 42, 0, 0, out, 1 << 40, w, st, None)
+    assert r == P.EINVAL and "noalloc" in P.lib().hydra_phsp_last_error().decode()
+    # the ordinary argument checks come first, as for hydra_phsp_generate
+    assert f(5.279, m, n, None, None, 0, 10, 42, 0, 0, None, 10, w, st, None) == P.EINVAL
+    assert f(1.0, m, n, None, None, 0, 10, 42, 0, 0, out, 10, w, st, None) == P.EKINEMATICS

@@ -52,6 +52,14 @@ typedef struct hydra_phsp_channel {
  *                   device counter;
  *                2: one block per tile (grid = tile count, grid_per_cu is
  *                   ignored), so the hardware dispatches tiles in order;
+ *                3: a single launch over the tiles of every channel, one block
+ *                   per tile, heaviest tiles (largest N, generation before
+ *                   integration) first, in one kernel that switches on each
+ *                   tile's N; one event per thread (ept must be 0 or 1), one
+ *                   stream, and every generating channel's columns on the
+ *                   128-byte line grid (else EINVAL).  Events and weights are
+ *                   those of the per-class launches; stats are those of
+ *                   single-channel calls with one event per thread;
  *   streams      0 or 1: the class kernels run one after another on the
  *                caller's stream; 2 .. HYDRA_PHSP_MAX_CLASS_STREAMS: they are
  *                spread over that many streams (the caller's and the plan's
@@ -96,7 +104,8 @@ int hydra_phsp_plan_info(const hydra_phsp_plan *plan, uint64_t *ntiles_out, uint
 /* Autotuner: times the batch (kernels and merges) over schedule
  * {static, dynamic} x events per thread {per class, 1, 2, 4} x blocks per
  * compute unit {1, 2, 4, 8, 16}, plus one block per tile x events per thread,
- * on one stream, then the best of those on 2 .. HYDRA_PHSP_MAX_CLASS_STREAMS
+ * plus the single launch (when every column is on the line grid), on one
+ * stream, then the best per-class shape on 2 .. HYDRA_PHSP_MAX_CLASS_STREAMS
  * streams -- two warm-up
  * runs and five timed runs per shape, overwriting the batch's outputs -- and
  * returns the shape with the fastest run and that run's time in ms.  Results

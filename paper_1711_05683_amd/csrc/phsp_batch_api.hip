@@ -93,6 +93,7 @@ struct hydra_phsp_plan {
     hipEvent_t done = nullptr;
     const double2* trig = nullptr;
     bool launched = false;
+    int single_nmax = 0; // schedule 3: every tile in one launch of the mixed-N kernel (0: per-class launches)
 };
 
 namespace hphsp {
@@ -185,6 +186,15 @@ static int enqueue_plan(hydra_phsp_plan* p, hipStream_t s, bool timed) {
             hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, p->d_counters, kClasses);
             e = hipGetLastError();
         }
+        if (p->single_nmax > 0) {
+            BatchLaunch b{p->d_chans, p->d_tiles, p->ntiles, p->grid, p->trig, nullptr};
+            e = launch_mixed_tiles(p->single_nmax, b, s);
+            timing_end(s, slot);
+            if (e != hipSuccess) return fail_hip(e, "batched kernel launch");
+            e = launch_batch_merges(p->d_chans, p->d_groups, p->ngroups, p->d_mid, (uint64_t)p->nch, s);
+            if (e != hipSuccess) return fail_hip(e, "batch merge launch");
+            return HYDRA_PHSP_OK;
+        }
         // fork: the plan's other streams start after everything before on s
         if (e == hipSuccess && p->nstreams > 1) e = hipEventRecord(p->fork, s);
         for (int i = 0; i + 1 < p->nstreams && e == hipSuccess; ++i) e = hipStreamWaitEvent(p->aux[i], p->fork, 0);
@@ -270,7 +280,20 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         dyn = tuning->schedule;
         if (tuning->streams) nstreams = tuning->streams;
     }
-    if (dyn < 0 || dyn > 2) return fail(HYDRA_PHSP_EINVAL, "tuning schedule must be 0, 1 or 2");
+    if (dyn < 0 || dyn > 3) return fail(HYDRA_PHSP_EINVAL, "tuning schedule must be 0, 1, 2 or 3");
+    const bool single = dyn == 3;
+    if (single && ept != 0 && ept != 1)
+        return fail(HYDRA_PHSP_EINVAL, "the single-launch schedule runs one event per thread (tuning ept 0 or 1)");
+    if (single) {
+        ept = 1;
+        nstreams = 1;
+        for (int i = 0; chans != nullptr && i < nch; ++i)
+            if (channel_kind(chans[i]) == kKindStaged) {
+                if (bad) *bad = i;
+                return fail(HYDRA_PHSP_EINVAL, "the single-launch schedule needs every channel's columns on the "
+                                               "128-byte line grid (or integrate-only channels)");
+            }
+    }
     if (nstreams < 1 || nstreams > HYDRA_PHSP_MAX_CLASS_STREAMS)
         return fail(HYDRA_PHSP_EINVAL, "tuning streams must be in [0, HYDRA_PHSP_MAX_CLASS_STREAMS]");
     if (ept != 0 && ept != 1 && ept != 2 && ept != 4)
@@ -346,6 +369,19 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         for (int c = 0; c < kClasses; ++c) next[c] = class_begin[c];
         for (const TileRef& t : tiles) by_class[next[chan_class[t.channel]]++] = t;
         tiles.swap(by_class);
+        if (single) {
+            // One launch over every tile: the heaviest tiles (largest N, generate
+            // before integrate-only) first, so the short ones fill the tail.
+            std::vector<TileRef> heavy_first;
+            heavy_first.reserve(tiles.size());
+            for (int kind : {(int)kKindDirect, (int)kKindIntegrate})
+                for (int n = kNMax; n >= 2; --n) {
+                    const int c = class_of(n, kind);
+                    heavy_first.insert(heavy_first.end(), tiles.begin() + (ptrdiff_t)class_begin[c],
+                                       tiles.begin() + (ptrdiff_t)(class_begin[c] + class_count[c]));
+                }
+            tiles.swap(heavy_first);
+        }
     }
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -366,6 +402,11 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     p->ntiles = first_tile;
     p->ngroups = first_group;
     p->grid = 0;
+    if (single) {
+        int nmax = 2;
+        for (int i = 0; i < nch; ++i) nmax = std::max(nmax, (int)dch[(size_t)i].n);
+        p->single_nmax = nmax;
+    }
     for (int c = 0; c < kClasses; ++c) {
         p->class_begin[c] = class_begin[c];
         p->class_count[c] = class_count[c];
@@ -376,6 +417,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         p->class_grid[c] = std::min<uint64_t>(class_count[c], cap);
         p->grid = std::max(p->grid, p->class_grid[c]);
     }
+    if (single) p->grid = std::min<uint64_t>(first_tile, kMaxGridBlocks); // one block per tile
     e = hipMalloc(&p->d_partials, sizeof(Moments) * std::max<uint64_t>(first_tile, 1));
     if (e != hipSuccess) {
         free_plan(p);
@@ -497,7 +539,7 @@ static std::string device_tag(int dev) {
 }
 
 static bool tuning_valid(const hydra_phsp_tuning& t) {
-    return (t.ept == 0 || t.ept == 1 || t.ept == 2 || t.ept == 4) && t.schedule >= 0 && t.schedule <= 2 &&
+    return (t.ept == 0 || t.ept == 1 || t.ept == 2 || t.ept == 4) && t.schedule >= 0 && t.schedule <= 3 &&
            t.grid_per_cu >= 0 && t.grid_per_cu <= 64 && t.streams >= 0 && t.streams <= HYDRA_PHSP_MAX_CLASS_STREAMS;
 }
 
@@ -660,10 +702,13 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
     int st = HYDRA_PHSP_OK;
     const int epts[4] = {0, 1, 2, 4};
     const int gpcs[5] = {1, 2, 4, 8, 16};
-    for (int sched = 0; sched < 3 && st == HYDRA_PHSP_OK; ++sched)
-    for (int ei = 0; ei < 4 && st == HYDRA_PHSP_OK; ++ei) {
-        for (int gi = 0; gi < (sched == 2 ? 1 : 5) && st == HYDRA_PHSP_OK; ++gi) {
-            hydra_phsp_tuning t{epts[ei], sched == 2 ? 0 : gpcs[gi], sched, 0};
+    // schedule 3 (one launch over every tile) needs line-aligned columns and runs
+    // one event per thread: a single candidate
+    const bool single_ok = key.staged == 0;
+    for (int sched = 0; sched < (single_ok ? 4 : 3) && st == HYDRA_PHSP_OK; ++sched)
+    for (int ei = 0; ei < (sched == 3 ? 1 : 4) && st == HYDRA_PHSP_OK; ++ei) {
+        for (int gi = 0; gi < (sched >= 2 ? 1 : 5) && st == HYDRA_PHSP_OK; ++gi) {
+            hydra_phsp_tuning t{sched == 3 ? 1 : epts[ei], sched >= 2 ? 0 : gpcs[gi], sched, 0};
             hydra_phsp_plan* p = nullptr;
             st = build_plan(channels, n_channels, &t, &p, nullptr);
             if (st != HYDRA_PHSP_OK) break;
@@ -687,9 +732,10 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
             }
         }
     }
-    // the best one-stream shape with its classes spread over more streams
+    // the best one-stream shape with its classes spread over more streams (a
+    // single-launch shape has one kernel: nothing to spread)
     const hydra_phsp_tuning one = best;
-    for (int ns = 2; ns <= HYDRA_PHSP_MAX_CLASS_STREAMS && st == HYDRA_PHSP_OK; ++ns) {
+    for (int ns = 2; ns <= HYDRA_PHSP_MAX_CLASS_STREAMS && st == HYDRA_PHSP_OK && one.schedule != 3; ++ns) {
         hydra_phsp_tuning t = one;
         t.streams = ns;
         hydra_phsp_plan* p = nullptr;

@@ -55,6 +55,28 @@ def _channels(P, n_channels=24, seed=1711, log_events=(2.0, 4.5), integrate_ever
     return specs, bufs, descs
 
 
+def _aligned_channels(P, n_channels, seed, nmax=10, integrate_every=4):
+    """Channels whose columns start on 128-byte lines (ld = aligned_ld(n))."""
+    from paper_1711_05683_amd.workloads import batched_channels
+    specs = batched_channels(n_channels, seed=seed, nmax=nmax, log_events=(2.0, 4.5))
+    specs[0].nevents = 0
+    specs[1].nevents = 1
+    specs[2].nevents = 257
+    bufs, descs = [], []
+    for i, c in enumerate(specs):
+        integ = integrate_every and i % integrate_every == integrate_every - 1
+        st = torch.full((4,), float("nan"), dtype=torch.float64, device="cuda")
+        if integ:
+            out = w = None
+        else:
+            out = torch.full((c.n, 4, P.aligned_ld(c.nevents)), float("nan"), dtype=torch.float64, device="cuda")
+            w = torch.full((P.aligned_ld(c.nevents),), float("nan"), dtype=torch.float64, device="cuda")
+        bufs.append((out, w, st))
+        descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed + i, stream_id=c.stream_id,
+                               event_offset=1000 * i, out=out, weights=w, stats=st))
+    return specs, bufs, descs
+
+
 def _single(P, c, i, integ, ept=1):
     if integ:
         P.set_events_per_thread(0, ept)
@@ -131,6 +153,50 @@ def test_plan_graph_with_class_streams(P):
     torch.cuda.synchronize()
     ref = [(None if o is None else o.clone(), None if w is None else w.clone(), s.clone()) for o, w, s in bufs]
     plan = P.Plan(descs, streams=3)
+    for rep in range(3):
+        for o, w, s in bufs:
+            if o is not None:
+                o.fill_(float("nan"))
+                w.fill_(float("nan"))
+            s.fill_(float("nan"))
+        P.integrate_async(5.279, [3.097, 0.4937, 0.13957], 100_000, seed=rep)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        for i, (o, w, s) in enumerate(bufs):
+            ro, rw, rs = ref[i]
+            n = specs[i].nevents
+            if o is not None:
+                assert torch.equal(o[:, :, :n], ro[:, :, :n]) and torch.equal(w[:n], rw[:n]), (rep, i)
+            assert torch.equal(s, rs), (rep, i)
+    plan.destroy()
+
+
+def test_batch_single_launch(P):
+    """Schedule 3: every tile of every channel (N up to 10, generate and
+    integrate-only) in one launch -- the same events and weights as
+    single-channel calls, and their integrals at one event per thread."""
+    _say("batch single launch, N up to 10")
+    specs, bufs, descs = _aligned_channels(P, 24, seed=57)
+    P.batch_run(descs, schedule=3)
+    torch.cuda.synchronize()
+    _compare_with_single(P, specs, bufs, 1)
+    specs, bufs, descs = _aligned_channels(P, 12, seed=58, nmax=8, integrate_every=3)
+    P.batch_run(descs, schedule=3, ept=1)
+    torch.cuda.synchronize()
+    _compare_with_single(P, specs, bufs, 1)
+
+
+def test_plan_graph_single_launch(P):
+    """A single-launch plan replays to its eager result with other work between."""
+    _say("graph replays, single launch")
+    specs, bufs, descs = _aligned_channels(P, 16, seed=59)
+    P.batch_run(descs, schedule=3)
+    torch.cuda.synchronize()
+    ref = [(None if o is None else o.clone(), None if w is None else w.clone(), s.clone()) for o, w, s in bufs]
+    plan = P.Plan(descs, schedule=3)
+    ntiles, grid = plan.info()
+    assert grid == ntiles > 0
     for rep in range(3):
         for o, w, s in bufs:
             if o is not None:

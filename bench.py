@@ -74,8 +74,42 @@ def read_traffic(kernel: str = "", algorithmic_bytes: float = 0.0):
         return None
 
 
+def cpu_all_cores(workers: int, per_worker: int = 10_000_000, chunk: int = 1_000_000):
+    """The same plain oracle on `workers` host threads, each on its own event
+    ranges (partitioned by event_offset, so together they produce exactly the
+    events of one run; ctypes releases the interpreter lock around each oracle
+    call, and the oracle keeps no global state): whole-job events/s over the
+    wall time of the parallel section."""
+    import threading
+    import oracle
+    M, m = 5.279, [3.097, 0.4937, 0.13957]
+    oracle.generate(M, m, 1000, seed=42)  # load the library, untimed
+    nchunks = workers * (per_worker // chunk)
+    lock = threading.Lock()
+    nxt = [0]
+
+    def worker():
+        while True:
+            with lock:
+                k = nxt[0]
+                nxt[0] += 1
+            if k >= nchunks:
+                return
+            oracle.generate(M, m, chunk, seed=42, event_offset=k * chunk)
+
+    threads = [threading.Thread(target=worker) for _ in range(workers)]
+    t0 = time.perf_counter()
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    dt = time.perf_counter() - t0
+    return nchunks * chunk / dt, dt, nchunks * chunk
+
+
 def cpu_baseline(target_s: float = 10.0, chunk: int = 1_000_000, max_events: int = 100_000_000):
-    """The CPU oracle (single thread) on a bounded sample of the same workload."""
+    """The CPU oracle (single thread) on a bounded sample of the same workload,
+    then the same code on all the cores this process may use."""
     import oracle
     oracle.build(force=False)
     M, m = 5.279, [3.097, 0.4937, 0.13957]
@@ -95,10 +129,24 @@ def cpu_baseline(target_s: float = 10.0, chunk: int = 1_000_000, max_events: int
         t1 = time.perf_counter()
         oracle.generate(Mo, mo, n, seed=42)
         others[name] = {"events": n, "events_per_s": n / (time.perf_counter() - t1)}
+    nproc = os.cpu_count() or 1
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = nproc
+    # the GPU machine grants one GPU's share of the host (16 threads), whatever the
+    # machine's core count; OMP_NUM_THREADS states that share
+    share = int(os.environ.get("OMP_NUM_THREADS", usable) or usable)
+    workers = max(1, min(usable, share))
+    rate_all, dt_all, n_all = cpu_all_cores(workers)
     return {"value": done / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
             "sample": f"first {done} events of the 1e8-event workload (momenta + weights), "
                       f"{chunk}-event chunks, single thread, {dt:.1f} s",
-            "cpu_model": _cpu_model(), "other_configs": others}
+            "cpu_model": _cpu_model(), "nproc": nproc, "usable_cpus": usable,
+            "all_cores_events_per_s": rate_all, "all_cores_threads": workers,
+            "all_cores_sample": f"events [0, {n_all}) of the same workload on {workers} threads, "
+                                f"1e6-event ranges by event_offset, {dt_all:.1f} s wall",
+            "other_configs": others}
 
 
 def _cpu_model():
@@ -110,6 +158,22 @@ def _cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def warm_clocks(fn, torch, seconds):
+    """Run the step back to back, untimed, for at least `seconds` of wall time,
+    so the timed region starts at steady clocks (the first launches of a
+    process run slower while the GPU's clocks ramp up).  Returns (seconds, steps)."""
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        for _ in range(8):
+            fn()
+        n += 8
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            return dt, n
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -136,9 +200,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--nevents", type=int, default=100_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--clock-warm-s", type=float, default=2.0,
+                    help="seconds of untimed back-to-back steps after the warm-up steps, so the timed "
+                         "steps run at steady clocks")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=15.0,
-                    help="length of the Poisson serving trace replayed in the extras (60 = full)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the Poisson serving trace replayed in the extras (60 = the full trace)")
+    ap.add_argument("--serve-tight-budget-mib", type=int, default=512,
+                    help="HBM budget of the second serving replay, small enough that admission binds "
+                         "(0 = skip it)")
     ap.add_argument("--counters", nargs="?", const="headline", default=None, choices=sorted(COUNTER_RUNS),
                     help="short run for rocprofv3 --pmc, prints no JSON: 'headline' (default) runs a 1 GiB "
                          "torch copy (the calibration kernel of known traffic) x3, then the main step x3; "
@@ -214,7 +284,10 @@ def main():
         print(f"counter run done: copy {COPY_BYTES} B x3, {n_ev} events x3", flush=True)
         return
 
-    ms_step, ms_kernel = time_steps(step, args.steps, args.warmup, torch)
+    for _ in range(args.warmup):
+        step()
+    warm_s, warm_steps = warm_clocks(step, torch, args.clock_warm_s)
+    ms_step, ms_kernel = time_steps(step, args.steps, 0, torch)
     bytes_per_event = 8 * (4 * 3 + 1)
     achieved = bytes_per_event * n_ev / (ms_kernel * 1e-3) / 1e9
     stats = st.cpu().tolist()
@@ -243,6 +316,8 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": f"{main_kernel} (N=3, at rest, FP64, {ept} event(s) per thread)",
                      "kernel_ms": ms_kernel},
+        "clock_warm": {"seconds": warm_s, "steps": warm_steps,
+                       "note": "untimed steps after the warm-up steps, before the timed region"},
         "integral": {"mean": stats[1], "sigma": stats[3], "n": stats[0]},
         "ceilings": ceilings(P, torch, out, w, n_ev, ept, ms_kernel, bytes_per_event, args),
     }
@@ -377,7 +452,10 @@ def extras(P, torch, dev, args):
     ex["cfg3_batched_64_channels"] = batched_extra(P, torch, dev, steps)
     ex["vegas_10d_gaussian"] = vegas_extra(P, torch, dev)
     if args.serve_seconds > 0:
-        ex["cfg4_serving"] = serving_extra(P, args.serve_seconds)
+        ex["cfg4_serving"] = serving_extra(P, args.serve_seconds, 32 << 30)
+        if args.serve_tight_budget_mib > 0:
+            ex["cfg4_serving_tight_budget"] = serving_extra(P, args.serve_seconds,
+                                                             args.serve_tight_budget_mib << 20)
     return ex
 
 
@@ -495,14 +573,15 @@ def unweighted_extra(P, torch, dev, M, m, n, out, steps):
             "write_GBs_given_bound": bytes_kept / (k1 * 1e-3) / 1e9}
 
 
-def serving_extra(P, seconds):
-    """Poisson arrivals at 2000 req/s replayed in real time by the native loop."""
+def serving_extra(P, seconds, budget):
+    """Poisson arrivals at 2000 req/s replayed in real time by the native loop,
+    with an HBM budget of `budget` bytes for the server's arena."""
     import numpy as np
     from paper_1711_05683_amd.workloads import serving_requests
     reqs = serving_requests(rate_hz=2000.0, duration_s=seconds)
     descs = [P.request(r.parent_mass, r.masses, r.nevents, seed=r.seed, stream_id=r.stream_id,
                        integrate_only=r.integrate_only) for r in reqs]
-    srv = P.Server(32 << 30, max_events_per_tick=1 << 22)
+    srv = P.Server(budget, max_events_per_tick=1 << 22)
     lat, wall, peak = srv.replay(descs, [r.arrival_s for r in reqs])
     st = srv.stats()
     cnt = srv.counters()
@@ -514,7 +593,7 @@ def serving_extra(P, seconds):
             "events_per_s": events / wall, "p50_ms": float(np.median(lat[ok]) * 1e3),
             "p99_ms": float(np.quantile(lat[ok], 0.99) * 1e3), "max_ms": float(lat[ok].max() * 1e3),
             "failed": int((~ok).sum()), "ticks": st["ticks"], "peak_arena_bytes": peak,
-            "budget_bytes": 32 << 30, "admission_budget_stalls": cnt["budget_stalls"],
+            "budget_bytes": budget, "admission_budget_stalls": cnt["budget_stalls"],
             "admission_active_stalls": cnt["active_stalls"],
             "queue_wait_mean_ms": cnt["queue_wait_sum_s"] / max(cnt["finished"], 1) * 1e3,
             "queue_wait_max_ms": cnt["queue_wait_max_s"] * 1e3}
@@ -548,6 +627,13 @@ def batched_extra(P, torch, dev, steps):
                                   steps, 1, torch)
     ntiles, grid = plan.info()
     plan.destroy()
+    # the same batch as one launch over every tile (schedule 3, one event per
+    # thread), for comparison with the per-class launches
+    plan1 = P.Plan(descs, schedule=3)
+    ms_graph_single, _ = time_steps(plan1.launch, steps, 1, torch)
+    ntiles1, _ = plan1.info()
+    plan1.destroy()
+    ms_direct_single, kms_single = time_steps(lambda: P.batch_run(descs, schedule=3), steps, 1, torch)
     P.release()
     del keep, descs
     # the same batch with ld = nevents (columns start mid-line): partial-line stores
@@ -564,8 +650,9 @@ def batched_extra(P, torch, dev, steps):
                                                       streams=nstr_u), steps, 1, torch)
     P.release()
     del keep, descs
+    sched_names = ["static", "dynamic", "one block per tile", "single launch"]
     return {"channels": len(specs), "events": total_events, "bytes": total_bytes,
-            "tuning": {"ept": ept, "grid_per_cu": gpc, "schedule": ["static", "dynamic", "one block per tile"][sched],
+            "tuning": {"ept": ept, "grid_per_cu": gpc, "schedule": sched_names[sched],
                        "streams": max(nstr, 1), "autotune_s": tune_s, "tiles": ntiles,
                        "grid": grid},
             "kernel_ms_one_stream": kms1, "ms_per_step_direct_one_stream": ms_direct1,
@@ -574,8 +661,12 @@ def batched_extra(P, torch, dev, steps):
             "kernel_frac_of_8TBs": total_bytes / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "ms_per_step_direct": ms_direct, "ld": "aligned_ld(nevents)",
             "kernel_ms_ld_eq_nevents": kms_unaligned,
+            "single_launch": {"kernel_ms": kms_single, "kernel_write_GBs": total_bytes / (kms_single * 1e-3) / 1e9,
+                              "kernel_frac_of_8TBs": total_bytes / (kms_single * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                              "ms_per_step_graph": ms_graph_single, "ms_per_step_direct": ms_direct_single,
+                              "tiles": ntiles1, "kernel": "k_phsp_batched_mixed<8, 1>, one block per tile"},
             "tuning_ld_eq_nevents": {"ept": ept_u, "grid_per_cu": gpc_u,
-                                     "schedule": ["static", "dynamic", "one block per tile"][sched_u],
+                                     "schedule": sched_names[sched_u],
                                      "streams": max(nstr_u, 1)},
             "kernel_write_GBs_ld_eq_nevents": total_bytes / (kms_unaligned * 1e-3) / 1e9}
 

@@ -74,6 +74,14 @@ def read_traffic(kernel: str = "", algorithmic_bytes: float = 0.0):
         return None
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg: str) -> None:
+    """One line on stderr when a part of the run ends (the JSON line stays alone on stdout)."""
+    print(f"bench: {msg} ({time.perf_counter() - _T0:.1f} s)", file=sys.stderr, flush=True)
+
+
 def cpu_all_cores(workers: int, per_worker: int = 10_000_000, chunk: int = 1_000_000):
     """The same plain oracle on `workers` host threads, each on its own event
     ranges (partitioned by event_offset, so together they produce exactly the
@@ -206,7 +214,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson serving trace replayed in the extras (60 = the full trace)")
-    ap.add_argument("--serve-tight-budget-mib", type=int, default=512,
+    ap.add_argument("--serve-tight-budget-mib", type=int, default=384,
                     help="HBM budget of the second serving replay, small enough that admission binds "
                          "(0 = skip it)")
     ap.add_argument("--counters", nargs="?", const="headline", default=None, choices=sorted(COUNTER_RUNS),
@@ -322,11 +330,13 @@ def main():
         "ceilings": ceilings(P, torch, out, w, n_ev, ept, ms_kernel, bytes_per_event, args),
     }
     del out
+    progress("headline timed")
 
     if not args.no_extras:
         result["extras"] = extras(P, torch, dev, args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
+        progress("CPU oracle timed")
     print(json.dumps(result), flush=True)
 
 
@@ -413,6 +423,7 @@ def extras(P, torch, dev, args):
     st = torch.empty(4, dtype=torch.float64, device=dev)
     ms, kms = time_steps(lambda: P.generate(M, m, n1, out=out, weights=w, stats=st, parent_dev=parents),
                          steps, 1, torch)
+    progress("per-event parents timed")
     ex["cfg1_per_event_parent"] = {"events_per_s": n1 / (ms * 1e-3), "kernel_ms": kms,
                                    "write_GBs": 104 * n1 / (kms * 1e-3) / 1e9,
                                    "total_GBs": 136 * n1 / (kms * 1e-3) / 1e9}
@@ -431,8 +442,10 @@ def extras(P, torch, dev, args):
     out = torch.empty((3, 4, n1), dtype=torch.float64, device=dev)
     P.generate(M, m, n1, out=out, weights=w, stats=st)
     ex["cfg1_unweighted"] = unweighted_extra(P, torch, dev, M, m, n1, out, steps)
+    progress("unweighted timed")
     ex["cfg1_sequential"] = sequential_extra(P, torch, dev, M, m, n1, out, w, st, steps)
     ex["cfg1_model"] = model_extra(P, torch, dev, M, m, n1, w, st, steps)
+    progress("sequential and model timed")
     del out, w
     # config 2: six pions at M=10, 5e7 events, FP64 vs mixed
     n2 = max(n1 // 2, 1)
@@ -449,13 +462,18 @@ def extras(P, torch, dev, args):
     ex["cfg2_six_pion_mixed"] = {"events_per_s": n2 / (ms * 1e-3), "kernel_ms": kms,
                                  "write_GBs": 104 * n2 / (kms * 1e-3) / 1e9}
     del outm, w
+    progress("six-pion FP64 and mixed timed")
     ex["cfg3_batched_64_channels"] = batched_extra(P, torch, dev, steps)
+    progress("64-channel batch timed")
     ex["vegas_10d_gaussian"] = vegas_extra(P, torch, dev)
+    progress("VEGAS timed")
     if args.serve_seconds > 0:
         ex["cfg4_serving"] = serving_extra(P, args.serve_seconds, 32 << 30)
+        progress("serving replay done")
         if args.serve_tight_budget_mib > 0:
             ex["cfg4_serving_tight_budget"] = serving_extra(P, args.serve_seconds,
                                                              args.serve_tight_budget_mib << 20)
+            progress("tight-budget serving replay done")
     return ex
 
 

@@ -49,7 +49,7 @@ typedef struct hydra_phsp_gauss_box {
     double mean[HYDRA_PHSP_VEGAS_DMAX], sigma[HYDRA_PHSP_VEGAS_DMAX]; /* sigma > 0 */
 } hydra_phsp_gauss_box;
 
-/* One iteration, asynchronous on `stream`: `calls` samples on grid_dev
+/* One iteration, asynchronous on `stream`: `calls` (>= 2) samples on grid_dev
  * ([dim][bins+1] doubles, device; 2 <= bins <= HYDRA_PHSP_VEGAS_KMAX);
  * stats_dev (HYDRA_PHSP_STATS doubles) receives n, mean (the estimate), M2,
  * sigma; hist_dev (NULL or [dim][bins] doubles) the refinement histogram;

@@ -666,15 +666,15 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
                         hydra_phsp_tuning* best_out, double* best_ms_out) {
     if (best_out == nullptr || best_ms_out == nullptr)
         return fail(HYDRA_PHSP_EINVAL, "autotune needs two host pointers");
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
     for (int i = 0; channels && i < n_channels; ++i) {
         Channel ch;
         int st = check_channel(channels[i], &ch);
         if (st != HYDRA_PHSP_OK) return st;
     }
     if (channels == nullptr || n_channels <= 0) return fail(HYDRA_PHSP_EINVAL, "need at least one channel");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
     const TuneKey key = tune_key(channels, n_channels, dev);
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);

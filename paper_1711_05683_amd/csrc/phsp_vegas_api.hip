@@ -260,6 +260,7 @@ int hydra_phsp_vegas_iteration(const hydra_phsp_gauss_box* f, int bins, const do
     int st = check_box(f, bins);
     if (st != HYDRA_PHSP_OK) return st;
     if (grid_dev == nullptr || stats_dev == nullptr) return fail(HYDRA_PHSP_EINVAL, "grid_dev and stats_dev are required");
+    if (calls < 2) return fail(HYDRA_PHSP_EINVAL, "need calls >= 2 (the error estimate needs two samples)");
     if ((uintptr_t)grid_dev % 8 || (uintptr_t)stats_dev % 8 || (uintptr_t)hist_dev % 8 || (uintptr_t)values_dev % 8)
         return fail(HYDRA_PHSP_EINVAL, "device pointers must be 8-byte aligned");
     return vegas_iteration(f, bins, grid_dev, calls, seed, iteration, stats_dev, hist_dev, values_dev,

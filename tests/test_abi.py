@@ -294,6 +294,8 @@ def test_vegas_validation_and_host_refinement(P):
     assert call(ctypes.byref(f), 129, g, 100, 1, 0, st, None, None, None) == P.EINVAL    # bins > 128
     assert call(ctypes.byref(f), 50, None, 100, 1, 0, st, None, None, None) == P.EINVAL  # no grid
     assert call(ctypes.byref(f), 50, g, 100, 1, 0, None, None, None, None) == P.EINVAL   # no stats
+    assert call(ctypes.byref(f), 50, g, 1, 1, 0, st, None, None, None) == P.EINVAL       # one call: no error
+    assert call(ctypes.byref(f), 50, g, 0, 1, 0, st, None, None, None) == P.EINVAL       # no calls
     bad = P.gauss_box([0.0] * 3, [1.0, 0.0, 1.0], [0.5] * 3, [0.2] * 3)
     assert call(ctypes.byref(bad), 50, g, 100, 1, 0, st, None, None, None) == P.EINVAL   # hi <= lo
     bad = P.gauss_box([0.0] * 3, [1.0] * 3, [0.5] * 3, [0.2, 0.0, 0.2])

@@ -57,11 +57,13 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
 }
 
 // Two words -> one uniform on the open 52-bit grid (2x+1) 2^-53, x = the top 52
-// bits of (hi:lo).  Built as (1 + x 2^-52) - 1 + 2^-53: every step is exact.
+// bits of (hi:lo).  Built as (1 + x 2^-52) - (1 - 2^-53): both operands lie
+// within a factor of two of each other, so the one subtraction is exact
+// (Sterbenz) and gives (2x+1) 2^-53 directly.
 __device__ __forceinline__ double uniform_from_words(uint32_t lo, uint32_t hi) {
     const uint64_t x = ((((uint64_t)hi) << 32) | (uint64_t)lo) >> 12;
     const double one_plus = __longlong_as_double((long long)(0x3FF0000000000000ull | x));
-    return (one_plus - 1.0) + 0x1p-53;
+    return one_plus - (1.0 - 0x1p-53);
 }
 
 // Counter state of one event's stream: call j uses counter (g lo, g hi, j, sid).
@@ -82,6 +84,26 @@ __device__ __forceinline__ double recip(double x) {
     r = fma(r, e, r);
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
+}
+
+// Square root of x for x = 0 or finite x >= 2^-767: the hardware
+// reciprocal-square-root estimate r, one Goldschmidt step on (g, h) = (x r, r/2)
+// and two Newton corrections g += (x - g^2) h.  For these arguments this is the
+// same sequence, and the same result, as the general double square root,
+// without its rescaling of tiny arguments and its special cases; x = 0 (where
+// r is infinite) gives 0 because the estimate is capped at 2^500.  The
+// generator's arguments are pdk products and u(1-u) with u >= 2^-53.
+__device__ __forceinline__ double sqrt_pos(double x) {
+    const double r = fmin(__builtin_amdgcn_rsq(x), 0x1p+500);
+    double g = x * r;
+    double h = 0.5 * r;
+    const double e = fma(-h, g, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
 }
 
 // Per-channel constants, computed once on the host.
@@ -172,17 +194,19 @@ __device__ __forceinline__ void sincos_2pi_table(double v, const double2* tab, d
     c = fma(t.x, cm1, fma(-t.y, sd, t.x));
 }
 
-// Direction of a level from its (theta, phi) uniforms:
-// cos(theta) = 2u - 1, sin(theta) = 2 sqrt(u (1-u)), phi = 2 pi v.
-__device__ __forceinline__ void direction(double u, double v, const double2* tab, double& nx, double& ny,
-                                          double& nz) {
+// Momentum p n of a level from its (theta, phi) uniforms, n the direction with
+// cos(theta) = 2u - 1, sin(theta) = 2 sqrt(u (1-u)), phi = 2 pi v; the
+// transverse part is (p sin(theta)) (cos(phi), sin(phi)).
+__device__ __forceinline__ void level_momentum(double p, double u, double v, const double2* tab, double& px,
+                                               double& py, double& pz) {
     const double ct = 2.0 * u - 1.0;
-    const double st = 2.0 * sqrt(u * (1.0 - u));
+    const double st = 2.0 * sqrt_pos(u * (1.0 - u));
     double sp, cp;
     sincos_2pi_table(v, tab, sp, cp);
-    nx = st * cp;
-    ny = st * sp;
-    nz = ct;
+    const double pt = p * st;
+    px = pt * cp;
+    py = pt * sp;
+    pz = p * ct;
 }
 
 // Energies of the two bodies of a level in the rest frame of hi = lo + m + g:
@@ -231,17 +255,12 @@ __device__ __forceinline__ double event_levels(const Channel& c, const EventRng&
         const double g = c.T * (r_hi - r_lo);
         const double m = c.m[i + 1];
         const double q = g * (2.0 * sig_lo + 2.0 * m + g) * (g + 2.0 * m) * (2.0 * sig_lo + g);
-        const double pd = sqrt(q) * h;
+        const double pd = sqrt_pos(q) * h;
         w *= pd;
         if constexpr (KIN) {
             double ut, up;
             draw_angles<N>(rng, i, carry, ut, up);
-            R nx, ny, nz;
-            direction(ut, up, tab, nx, ny, nz);
-            const R p = pd;
-            ev.x[i + 1] = p * nx;
-            ev.y[i + 1] = p * ny;
-            ev.z[i + 1] = p * nz;
+            level_momentum(pd, ut, up, tab, ev.x[i + 1], ev.y[i + 1], ev.z[i + 1]);
             // Per-level scalars from the gap formulas: no square roots, nothing
             // cancels.
             if (i == 0) {
@@ -255,8 +274,8 @@ __device__ __forceinline__ double event_levels(const Channel& c, const EventRng&
                 const double esys = level_energy(sig_lo, m, g, sig_hi, h); // energy of {0..i}
                 const R gamma = esys * inv_lo;
                 const R inv_gp1 = sig_lo * recip(esys + sig_lo); // 1/(gamma+1) = sigma / (E + sigma)
-                const R eta = -(pd * inv_lo);
-                const R ex = eta * nx, ey = eta * ny, ez = eta * nz;
+                // eta = -(p_i / sigma_i) n: the new daughter's momentum scaled
+                const R ex = ev.x[i + 1] * -inv_lo, ey = ev.y[i + 1] * -inv_lo, ez = ev.z[i + 1] * -inv_lo;
 #pragma unroll
                 for (int k = 0; k <= i; ++k)
                     boost<R>(ev.e[k], ev.x[k], ev.y[k], ev.z[k], ex, ey, ez, gamma, inv_gp1);

@@ -3,21 +3,30 @@
 // Trial event e of a launch is the weighted event the generator produces for
 // the same counter; it is kept when v * w_max < w, with v the acceptance
 // uniform of the event (words 0 and 1 of the first Philox call its own uniforms
-// do not use).  Kept events are written in trial order.  The passes, each over
-// the same blocks of kBlock * kUnwEpt trials:
+// do not use).  Kept events are written in trial order.  The trials are cut
+// into segments of kUnwSeg consecutive trials, one wave per segment.  The
+// passes:
 //   max    (only when no bound is given) the largest weight of all trials;
-//   count  kept and over-bound trials per block (weights only, no kinematics);
-//   write  the full kinematics again (counter-based draws make them identical),
-//          each kept event stored at its block's offset plus its rank.
-// Between count and write the per-block counts are scanned (phsp_unweight_api.hip).
+//   count  per segment: the keep decisions as bit masks (one 64-bit word per 64
+//          trials; weights only, no kinematics), and the kept and over-bound
+//          counts;
+//   write  per segment: the kept trials' indices from the masks, then the full
+//          kinematics of the kept trials only, lane j of a wave taking output
+//          position c + j for 64-aligned c, so each store covers whole lines;
+//          the kinematics are recomputed from the counters (identical to the
+//          weighted events).
+// Between count and write the per-segment counts are scanned
+// (phsp_unweight_api.hip).
 #pragma once
 
 #include "phsp_kernels.hpp"
-#include "phsp_stage.hpp"
 
 namespace hphsp {
 
-constexpr int kUnwEpt = 4; // trials per lane and block step; a block covers 1024 trials
+constexpr int kUnwEpt = 4;        // max pass: trials per lane; a block covers 1024 trials
+constexpr int kUnwSegWords = 16;  // mask words of a segment
+constexpr int kUnwSeg = 64 * kUnwSegWords; // trials of a segment (one wave)
+constexpr int kUnwSegPerBlock = kBlock / 64; // segments of a count or write block
 
 // Philox calls of one event's own uniforms: ceil((3N - 4) / 2).
 template <int N>
@@ -35,8 +44,10 @@ struct UnwArgs {
     const double* w_max;       // device scalar: the bound applied
     unsigned long long* w_max_bits; // the same scalar's bits, raised by the max pass with atomic max
                                     // (non-negative doubles order like their bit patterns)
-    uint2* counts;             // [blocks] (kept, weight > w_max) per block
-    const uint64_t* offsets;   // [blocks] kept events before the block
+    uint2* counts;             // [segments] (kept, weight > w_max) per segment
+    uint64_t* masks;           // NULL (count only), or [segments * kUnwSegWords] keep bits
+    const uint64_t* offsets;   // [segments] kept events before the segment
+    uint64_t segments;
     double* out;               // kept events, [N][4][ld]
     uint64_t ld;               // capacity in events
     uint64_t* index;           // NULL, or [ld] global index of each kept event
@@ -86,114 +97,93 @@ __global__ __launch_bounds__(kBlock) void k_unw_max(const UnwArgs u) {
     }
 }
 
-// Kept and over-bound trials of the block (the weights only).
+// Keep decisions and counts of each segment (the weights only).  Wave w of
+// block b takes segment s = kUnwSegPerBlock b + w; step k covers its trials
+// s kUnwSeg + 64 k + lane, and the step's ballot is the segment's mask word k.
 template <int N>
 __global__ __launch_bounds__(kBlock) void k_unw_count(const UnwArgs u) {
-    __shared__ uint32_t sk[kWaves], so[kWaves];
-    const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * kUnwEpt);
+    const uint64_t seg = (uint64_t)blockIdx.x * kUnwSegPerBlock +
+                         (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (seg >= u.segments) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t base = seg * (uint64_t)kUnwSeg;
     const double wmax = *u.w_max;
     uint32_t kept = 0, over = 0;
-#pragma unroll
-    for (int k = 0; k < kUnwEpt; ++k) {
-        const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
+#pragma unroll 4
+    for (int k = 0; k < kUnwSegWords; ++k) {
+        const uint32_t off = (uint32_t)(64 * k) + lane;
+        bool keep = false, above = false;
         if (base + off < u.a.nevents) {
             Event<N, double> ev;
             const double w = compute_event<N, kAtRest, kIntegrate>(u.a, base, off, nullptr, ev);
             const double v = accept_uniform<N>(u.a, base, off);
-            kept += (v * wmax < w) ? 1u : 0u;
-            over += (w > wmax) ? 1u : 0u;
+            keep = v * wmax < w;
+            above = w > wmax;
         }
+        const uint64_t m = __ballot(keep);
+        kept += (uint32_t)__popcll(m);
+        over += (uint32_t)__popcll(__ballot(above));
+        if (u.masks != nullptr && lane == 0) u.masks[seg * kUnwSegWords + k] = m;
     }
-    kept = wave_sum_u32(kept);
-    over = wave_sum_u32(over);
-    if ((threadIdx.x & 63) == 0) {
-        sk[threadIdx.x >> 6] = kept;
-        so[threadIdx.x >> 6] = over;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t a = 0, b = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            a += sk[w];
-            b += so[w];
-        }
-        u.counts[blockIdx.x] = make_uint2(a, b);
-    }
+    if (lane == 0) u.counts[seg] = make_uint2(kept, over);
 }
 
-// Full kinematics of every trial, kept ones stored in trial order: step k of
-// the block holds trials base + k*kBlock + t, so a kept trial's position is the
-// block's offset, plus the kept trials of earlier steps, of earlier waves in
-// this step, and of lower lanes in this wave.  Each column is written through
-// LDS in whole 128-byte lines: a step's kept values are appended to the values
-// carried over from the previous step, every completed line is stored by
-// consecutive threads, and the incomplete tail is carried on; only the two lines
-// at the ends of the block's run are written partially.  (Runs that start
-// mid-line would otherwise turn most stores into partial-line writes.)
+// Kept trials of each segment, with full kinematics, at their places in trial
+// order.  Each wave first lists its segment's kept trials (their offsets in the
+// segment, in order) in LDS from the mask words; then, for every 64-aligned
+// window [c, c + 64) of output positions that meets the segment's run
+// [first, first + kept), lane j computes and stores the event at position c + j.
+// With columns on the 128-byte line grid every store covers whole lines except
+// in the two windows at the ends of the run; kinematics are computed for kept
+// trials only.
 template <int N, int PMODE>
 __global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
     __shared__ double2 tab[kTrigSize];
-    __shared__ double buf[4][line_elems<double>() + kBlock];
-    __shared__ double carry[4 * N][line_elems<double>()];
-    __shared__ uint64_t ibuf[1][line_elems<uint64_t>() + kBlock];
-    __shared__ uint64_t icarry[1][line_elems<uint64_t>()];
-    __shared__ uint32_t sk[kWaves];
+    __shared__ uint16_t list[kUnwSegPerBlock][kUnwSeg];
     load_trig(tab, u.a.trig);
-    const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * kUnwEpt);
-    const double wmax = *u.w_max;
-    const uint64_t first = u.offsets[blockIdx.x];
-    uint64_t next = first;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int k = 0; k < kUnwEpt; ++k) {
-        const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
-        bool keep = false;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t seg = (uint64_t)blockIdx.x * kUnwSegPerBlock + wave;
+    if (seg >= u.segments) return; // no barrier follows
+    uint32_t n = 0;
+    for (int k = 0; k < kUnwSegWords; ++k) {
+        const uint64_t m = u.masks[seg * kUnwSegWords + k];
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if ((m >> lane) & 1u) list[wave][n + rank] = (uint16_t)(64 * k + lane);
+        n += (uint32_t)__popcll(m);
+    }
+    // the list was written by other lanes of this wave: order the LDS accesses
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint64_t first = u.offsets[seg];
+    const uint64_t end = first + n < u.ld ? first + n : u.ld; // capacity truncates the run
+    const uint64_t base = seg * (uint64_t)kUnwSeg;
+    for (uint64_t c = first & ~(uint64_t)63; c < end; c += 64) {
+        const uint64_t p = c + lane;
+        if (p < first || p >= end) continue;
+        const uint32_t off = list[wave][p - first];
         Event<N, double> ev;
-        if (base + off < u.a.nevents) {
-            const double w = compute_event<N, PMODE, kFp64>(u.a, base, off, tab, ev);
-            keep = accept_uniform<N>(u.a, base, off) * wmax < w;
-        }
-        const uint64_t mask = __ballot(keep);
-        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        if (lane == 0) sk[wave] = (uint32_t)__popcll(mask);
-        __syncthreads();
-        uint32_t before = 0, total = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            before += (w < wave) ? sk[w] : 0u;
-            total += sk[w];
-        }
-        const uint32_t slot = before + rank;
-        if (u.index != nullptr) {
-            const uint64_t g[1] = {u.a.event_offset + base + off};
-            uint64_t* const icol[1] = {u.index};
-            const ColWindow wi[1] = {col_window<uint64_t>(line_offset(u.index), first, next, total, u.ld)};
-            stage_and_store<1, uint64_t>(g, keep, slot, wi, ibuf, icarry, icol);
-        }
+        (void)compute_event<N, PMODE, kFp64>(u.a, base, off, tab, ev);
         if (u.out != nullptr) {
+            double* const o = u.out + p;
 #pragma unroll
             for (int d = 0; d < N; ++d) {
-                const double v[4] = {ev.e[d], ev.x[d], ev.y[d], ev.z[d]};
-                double* const cols[4] = {u.out + (uint64_t)(4 * d + 0) * u.ld, u.out + (uint64_t)(4 * d + 1) * u.ld,
-                                         u.out + (uint64_t)(4 * d + 2) * u.ld, u.out + (uint64_t)(4 * d + 3) * u.ld};
-                ColWindow w4[4];
-#pragma unroll
-                for (int g = 0; g < 4; ++g) w4[g] = col_window<double>(line_offset(cols[g]), first, next, total, u.ld);
-                stage_and_store<4, double>(v, keep, slot, w4, buf, &carry[4 * d], cols);
+                __builtin_nontemporal_store(ev.e[d], o + (uint64_t)(4 * d + 0) * u.ld);
+                __builtin_nontemporal_store(ev.x[d], o + (uint64_t)(4 * d + 1) * u.ld);
+                __builtin_nontemporal_store(ev.y[d], o + (uint64_t)(4 * d + 2) * u.ld);
+                __builtin_nontemporal_store(ev.z[d], o + (uint64_t)(4 * d + 3) * u.ld);
             }
         }
-        next += total; // sk was read before the staging barriers, so the next step may overwrite it
+        if (u.index != nullptr) __builtin_nontemporal_store(u.a.event_offset + base + off, u.index + p);
     }
-    if (u.index != nullptr) flush_carry<uint64_t>(icarry[0], u.index, first, next, u.ld);
-    if (u.out != nullptr)
-        for (int c = 0; c < 4 * N; ++c) flush_carry<double>(carry[c], u.out + (uint64_t)c * u.ld, first, next, u.ld);
 }
 
 struct UnwLaunch {
     UnwArgs u;
-    uint64_t blocks;
-    int pmode; // kAtRest or kBroadcast (write pass)
+    uint64_t max_blocks; // max pass: kBlock * kUnwEpt trials per block
+    uint64_t blocks;     // count and write passes: kUnwSegPerBlock segments per block
+    int pmode;           // kAtRest or kBroadcast (write pass)
 };
 
 // Per-N launchers, defined in the per-N instantiation units.

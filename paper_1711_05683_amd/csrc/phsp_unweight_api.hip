@@ -1,5 +1,6 @@
 // phsp_unweight_api.hip -- C ABI of the unweighted (hit-or-miss) path: the
-// per-stream workspace, the scan of the per-block counts and the launch sequence.
+// per-stream workspace, the scan of the per-segment counts and the launch
+// sequence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,16 +41,16 @@ __device__ __forceinline__ uint64_t block_inclusive_scan(uint64_t v, uint64_t* s
     return v + add;
 }
 
-// Stage 1: kept and over-bound trials of each group of kScanBlock blocks.
-__global__ __launch_bounds__(kScanBlock) void k_unw_scan_partial(const uint2* __restrict__ counts, uint64_t blocks,
+// Stage 1: kept and over-bound trials of each group of kScanBlock segments.
+__global__ __launch_bounds__(kScanBlock) void k_unw_scan_partial(const uint2* __restrict__ counts, uint64_t segments,
                                                                  uint64_t* __restrict__ sums,
                                                                  uint64_t* __restrict__ over_sums) {
     __shared__ uint64_t sm[kScanBlock / 64];
     const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
-    const uint64_t v = i < blocks ? counts[i].x : 0u;
+    const uint64_t v = i < segments ? counts[i].x : 0u;
     const uint64_t inc = block_inclusive_scan<kScanBlock>(v, sm);
     if (threadIdx.x == kScanBlock - 1) sums[blockIdx.x] = inc;
-    uint64_t o = i < blocks ? counts[i].y : 0u;
+    uint64_t o = i < segments ? counts[i].y : 0u;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) o += __shfl_xor(o, off, 64);
     if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = o; // the scan's last read of sm was before its barrier
@@ -99,27 +100,29 @@ __global__ __launch_bounds__(kScanTop) void k_unw_scan_top(uint64_t* __restrict_
     }
 }
 
-// Stage 3: each block's offset = its group's prefix + the kept counts of the
-// earlier blocks of the group.
-__global__ __launch_bounds__(kScanBlock) void k_unw_scan_finish(const uint2* __restrict__ counts, uint64_t blocks,
+// Stage 3: each segment's offset = its group's prefix + the kept counts of the
+// earlier segments of the group.
+__global__ __launch_bounds__(kScanBlock) void k_unw_scan_finish(const uint2* __restrict__ counts, uint64_t segments,
                                                                 const uint64_t* __restrict__ sums,
                                                                 uint64_t* __restrict__ offsets) {
     __shared__ uint64_t sm[kScanBlock / 64];
     const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
-    const uint64_t v = i < blocks ? counts[i].x : 0u;
+    const uint64_t v = i < segments ? counts[i].x : 0u;
     const uint64_t inc = block_inclusive_scan<kScanBlock>(v, sm);
-    if (i < blocks) offsets[i] = sums[blockIdx.x] + inc - v;
+    if (i < segments) offsets[i] = sums[blockIdx.x] + inc - v;
 }
 
 namespace {
 
 struct UnwWorkspace {
-    uint2* counts = nullptr;
-    uint64_t* offsets = nullptr;
-    uint64_t* sums = nullptr;      // [groups] kept trials per group of kScanBlock blocks
+    uint2* counts = nullptr;       // [segments]
+    uint64_t* offsets = nullptr;   // [segments]
+    uint64_t* masks = nullptr;     // [segments * kUnwSegWords], allocated when outputs are asked for
+    uint64_t* sums = nullptr;      // [groups] kept trials per group of kScanBlock segments
     uint64_t* over_sums = nullptr; // [groups] over-bound trials per group
     double* w_max = nullptr;
-    uint64_t capacity = 0; // blocks
+    uint64_t capacity = 0;         // segments
+    uint64_t mask_capacity = 0;    // segments
 };
 
 std::mutex g_unw_mu;
@@ -128,22 +131,40 @@ std::map<std::pair<int, hipStream_t>, UnwWorkspace> g_unw_ws;
 void free_ws(UnwWorkspace& w) {
     if (w.counts) (void)hipFree(w.counts);
     if (w.offsets) (void)hipFree(w.offsets);
+    if (w.masks) (void)hipFree(w.masks);
     if (w.sums) (void)hipFree(w.sums);
     if (w.over_sums) (void)hipFree(w.over_sums);
     if (w.w_max) (void)hipFree(w.w_max);
     w = UnwWorkspace{};
 }
 
-int unw_workspace(hipStream_t stream, uint64_t blocks, UnwWorkspace** out) {
+int unw_workspace(hipStream_t stream, uint64_t segments, bool masks, UnwWorkspace** out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
     std::lock_guard<std::mutex> lock(g_unw_mu);
     UnwWorkspace& w = g_unw_ws[std::make_pair(dev, stream)];
-    if (w.w_max == nullptr || blocks > w.capacity) {
+    if (masks && segments > w.mask_capacity) {
+        uint64_t cap = w.mask_capacity ? w.mask_capacity : 4096;
+        while (cap < segments) cap *= 2;
+        if (w.masks) (void)hipFree(w.masks); // waits for the device: no queued kernel still uses it
+        w.masks = nullptr;
+        w.mask_capacity = 0;
+        if (hipMalloc(&w.masks, sizeof(uint64_t) * kUnwSegWords * cap) != hipSuccess) {
+            w.masks = nullptr;
+            return fail(HYDRA_PHSP_ENOMEM, "unweighting mask allocation failed");
+        }
+        w.mask_capacity = cap;
+    }
+    if (w.w_max == nullptr || segments > w.capacity) {
         uint64_t cap = w.capacity ? w.capacity : 4096;
-        while (cap < blocks) cap *= 2;
+        while (cap < segments) cap *= 2;
+        uint64_t* keep_masks = w.masks;
+        const uint64_t keep_mask_cap = w.mask_capacity;
+        w.masks = nullptr; // kept across the regrowth of the other buffers
         free_ws(w); // hipFree waits for the device, so no queued kernel still uses it
+        w.masks = keep_masks;
+        w.mask_capacity = keep_mask_cap;
         const uint64_t groups = (cap + kScanBlock - 1) / kScanBlock;
         bool ok = hipMalloc(&w.counts, sizeof(uint2) * cap) == hipSuccess &&
                   hipMalloc(&w.offsets, sizeof(uint64_t) * cap) == hipSuccess &&
@@ -221,14 +242,16 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
         if (st != HYDRA_PHSP_OK) return st;
         pmode = kBroadcast;
     }
-    const uint64_t span = (uint64_t)kBlock * (uint64_t)kUnwEpt;
-    const uint64_t blocks = ceil_div(ntrials, span);
-    if (blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
+    const uint64_t max_blocks = ceil_div(ntrials, (uint64_t)kBlock * (uint64_t)kUnwEpt);
+    const uint64_t segments = ceil_div(ntrials, (uint64_t)kUnwSeg);
+    const uint64_t blocks = ceil_div(segments, (uint64_t)kUnwSegPerBlock);
+    if (max_blocks > 0xFFFFFFFFull / (uint64_t)kBlock || blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
         return fail(HYDRA_PHSP_EINVAL, "ntrials too large for one launch (more than 2^32 - 1 threads)");
+    const bool outputs = p4_out_dev != nullptr || index_out_dev != nullptr;
 
     hipStream_t s = (hipStream_t)stream;
     UnwWorkspace* ws = nullptr;
-    st = unw_workspace(s, std::max<uint64_t>(blocks, 1), &ws);
+    st = unw_workspace(s, std::max<uint64_t>(segments, 1), outputs, &ws);
     if (st != HYDRA_PHSP_OK) return st;
     const double2* trig = nullptr;
     st = trig_table(&trig);
@@ -248,10 +271,13 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
     L.u.w_max = ws->w_max;
     L.u.w_max_bits = reinterpret_cast<unsigned long long*>(ws->w_max);
     L.u.counts = ws->counts;
+    L.u.masks = outputs ? ws->masks : nullptr;
     L.u.offsets = ws->offsets;
+    L.u.segments = segments;
     L.u.out = p4_out_dev;
     L.u.ld = ld;
     L.u.index = index_out_dev;
+    L.max_blocks = max_blocks;
     L.blocks = blocks;
     L.pmode = pmode;
 
@@ -260,12 +286,12 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
     // the bound: given, or raised from zero to the largest trial weight by the max pass
     hipLaunchKernelGGL(k_unw_set, dim3(1), dim3(64), 0, s, ws->w_max, w_max);
     e = hipGetLastError();
-    if (e == hipSuccess && w_max == 0.0 && blocks > 0) e = launch_pass_n(n_daughters, 0, L, s);
+    if (e == hipSuccess && w_max == 0.0 && max_blocks > 0) e = launch_pass_n(n_daughters, 0, L, s);
     if (e == hipSuccess && blocks > 0) e = launch_pass_n(n_daughters, 1, L, s);
-    const uint64_t groups = (blocks + kScanBlock - 1) / kScanBlock;
+    const uint64_t groups = (segments + kScanBlock - 1) / kScanBlock;
     if (e == hipSuccess && groups > 0) {
         hipLaunchKernelGGL(k_unw_scan_partial, dim3((unsigned)groups), dim3(kScanBlock), 0, s,
-                           (const uint2*)ws->counts, blocks, ws->sums, ws->over_sums);
+                           (const uint2*)ws->counts, segments, ws->sums, ws->over_sums);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
@@ -273,10 +299,9 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
                            (const uint64_t*)ws->over_sums, counts_dev, (const double*)ws->w_max, w_max_dev);
         e = hipGetLastError();
     }
-    const bool outputs = p4_out_dev != nullptr || index_out_dev != nullptr;
     if (e == hipSuccess && groups > 0 && outputs) {
         hipLaunchKernelGGL(k_unw_scan_finish, dim3((unsigned)groups), dim3(kScanBlock), 0, s, (const uint2*)ws->counts,
-                           blocks, (const uint64_t*)ws->sums, ws->offsets);
+                           segments, (const uint64_t*)ws->sums, ws->offsets);
         e = hipGetLastError();
     }
     if (e == hipSuccess && blocks > 0 && outputs) e = launch_pass_n(n_daughters, 2, L, s);

@@ -12,8 +12,8 @@ static bool grid_ok(uint64_t blocks) { return blocks > 0 && blocks <= 0xFFFFFFFF
 
 template <>
 hipError_t launch_unw_max<UNW_N>(const UnwLaunch& L, hipStream_t s) {
-    if (!grid_ok(L.blocks)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_unw_max<UNW_N>), dim3((unsigned)L.blocks), dim3(kBlock), 0, s, L.u);
+    if (!grid_ok(L.max_blocks)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_unw_max<UNW_N>), dim3((unsigned)L.max_blocks), dim3(kBlock), 0, s, L.u);
     return hipGetLastError();
 }
 
@@ -26,7 +26,7 @@ hipError_t launch_unw_count<UNW_N>(const UnwLaunch& L, hipStream_t s) {
 
 template <>
 hipError_t launch_unw_write<UNW_N>(const UnwLaunch& L, hipStream_t s) {
-    if (!grid_ok(L.blocks)) return hipErrorInvalidValue;
+    if (!grid_ok(L.blocks) || L.u.masks == nullptr) return hipErrorInvalidValue;
     if (L.pmode == kBroadcast)
         hipLaunchKernelGGL((k_unw_write<UNW_N, kBroadcast>), dim3((unsigned)L.blocks), dim3(kBlock), 0, s, L.u);
     else

@@ -363,6 +363,31 @@ def test_full_size_config1_at_rest(P):
     assert rel(mean, mo) <= FP64_TOL and rel(sigma, so) <= FP64_TOL
 
 
+def test_integral_at_full_size_against_oracle(P):
+    """The fused reduction's merge tree (per-lane Welford, wave and block trees,
+    two-stage merge of the block partials) against the oracle's compensated
+    two-pass integral over the same 1e8 weights: mean and sigma within 1e-11
+    relative (pairwise merging keeps the rounding error near log2(n) ulp).  The
+    mixed path's weights and integral are the FP64 path's bit for bit (checked
+    in test_full_size_config2), so this covers both."""
+    M, m = CFG0
+    nev = 100_000_000
+    _say("integral of 1e8 events: generate (stats), integrate-only, oracle")
+    w = torch.empty(nev, dtype=torch.float64, device="cuda")
+    out = torch.empty((3, 4, P.aligned_ld(nev)), dtype=torch.float64, device="cuda")
+    _, _, st = P.generate(M, m, nev, out=out, weights=w)
+    torch.cuda.synchronize()
+    del out, w
+    s = st.cpu().numpy()
+    mean_i, sigma_i = P.integrate(M, m, nev)
+    mo, so = oracle.integrate(M, m, nev, seed=42)
+    _say(f"1e8 integral: generate mean rel err {rel(s[1], mo):.3e}, sigma {rel(s[3], so):.3e}; "
+         f"integrate-only mean {rel(mean_i, mo):.3e}, sigma {rel(sigma_i, so):.3e}")
+    assert s[0] == nev
+    assert rel(s[1], mo) <= FP64_TOL and rel(s[3], so) <= FP64_TOL
+    assert rel(mean_i, mo) <= FP64_TOL and rel(sigma_i, so) <= FP64_TOL
+
+
 def test_integrate_largest_single_launch(P):
     """The largest count one integrate launch takes ((2^32 - 1) / 256 blocks of
     1024 events, 1.7e10 events): every block counted, the volume within 5 sigma

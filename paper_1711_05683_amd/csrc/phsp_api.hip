@@ -274,20 +274,21 @@ static hipError_t launch_by_n(int n, const LaunchSpec& s, const KArgs& a, hipStr
 }
 
 // Events per thread of the single-channel kernels (0 = default per path).  The
-// defaults are the fastest of 1, 2 and 4 measured on MI355X (warm clocks, about
-// 10 GB of output per launch).  Integration stores nothing, so four events per
-// lane amortise the block reduction best.  For generation the store pattern
-// matters as much: blocks that span 256 or 512 events per column stream their
-// stores faster than blocks spanning 1024, which is what favours one event per
-// lane for N = 3 (and for per-event parents, which also read), two for N = 2,
-// and four for N = 4..7, where the per-event work dominates; for N >= 8 the
-// register footprint of several events in flight costs more than it saves.
+// defaults are the fastest of 1, 2 and 4 in two warmed sweeps on MI355X (about
+// 10 GB of output per launch, N pions from 10 GeV).  Integration stores
+// nothing, so four events per lane amortise the block reduction best.  For FP64
+// generation blocks that span 256 or 512 events per column stream their stores
+// faster than blocks spanning 1024, which favours one event per lane for N = 3
+// (and for per-event parents, which also read) and two for N = 2, 4, 5 and 7;
+// four pay off where the per-event work dominates and the registers still
+// allow three or four waves per SIMD (N = 6, 9), one where they do not (N = 8,
+// 10).  The mixed path computes the same FP64 events but stores half the
+// bytes, so its arithmetic dominates earlier: four events per lane for N = 3..9.
 static std::atomic<int> g_ept_override[3] = {{0}, {0}, {0}}; // read by launches on any thread
 // Off the line grid the staged kernel's LDS rounds and barriers change the
 // balance: measured the same way, a longer block run pays off for N = 3, while
 // from N = 7 the staged kernel's larger register footprint makes one event per
-// lane fastest.  The mixed path computes every event in FP64 registers like the
-// plain one and only stores narrower values, so it follows the same tables.
+// lane fastest; both output precisions follow that table.
 static int default_ept(int mode, int n, int pmode, bool staged) {
     const int o = g_ept_override[mode].load(std::memory_order_relaxed);
     if (o > 0) return o;
@@ -297,8 +298,9 @@ static int default_ept(int mode, int n, int pmode, bool staged) {
         return kStagedFp64[n];
     }
     if (pmode == kPerEvent && n <= 3) return 1;
-    static const int kFp64[11] = {0, 0, 2, 1, 4, 4, 4, 4, 1, 1, 1};
-    return kFp64[n];
+    static const int kFp64[11] = {0, 0, 2, 1, 2, 2, 4, 2, 1, 4, 1};
+    static const int kMixedTable[11] = {0, 0, 2, 4, 4, 4, 4, 4, 4, 4, 1};
+    return mode == kMixed ? kMixedTable[n] : kFp64[n];
 }
 
 int single_channel_ept(int mode, int n, int pmode, bool staged) { return default_ept(mode, n, pmode, staged); }

@@ -132,8 +132,23 @@ __device__ __forceinline__ double run_event(const KArgs& a, uint64_t base, uint3
     return w;
 }
 
+// Waves per SIMD the generator kernels are compiled for.  The VGPR file holds
+// 512 registers per lane, allocated in steps of 8, so a kernel that needs a few
+// registers more than 128 (or 168) runs 3 (or 2) waves per SIMD instead of 4
+// (or 3).  Where the natural allocation sits just above such a step and the
+// compiler fits under it without spilling (checked on the built library by the
+// CPU tests), the hint asks for the extra wave; elsewhere it is 1 (no request).
 template <int N, int PMODE, int MODE, int EPT>
-__global__ __launch_bounds__(kBlock) void k_phsp(const KArgs a) {
+constexpr int generator_waves_hint() {
+    if (MODE == kIntegrate) return 1;
+    if (N == 8 && EPT == 1 && !(PMODE == kBroadcast && MODE == kFp64)) return 4; // 130 -> 128
+    if (N == 10 && EPT == 1) return 3;                         // 170 -> 168
+    return 1;
+}
+
+template <int N, int PMODE, int MODE, int EPT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(generator_waves_hint<N, PMODE, MODE, EPT>())))
+void k_phsp(const KArgs a) {
     __shared__ double2 tab[kTrigSize];
     if constexpr (MODE != kIntegrate) load_trig(tab, a.trig);
     const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * EPT);

@@ -103,13 +103,15 @@ def test_events_per_thread_query(P):
     assert P.lib().hydra_phsp_events_per_thread(1, 3, 4) == P.EINVAL  # unknown flag
     # columns off the line grid (staged kernel) have their own defaults
     staged_fp64 = [2, 4, 2, 2, 2, 1, 1, 1, 1]
-    aligned_fp64 = [2, 1, 4, 4, 4, 4, 1, 1, 1]
+    aligned_fp64 = [2, 1, 2, 2, 4, 2, 1, 4, 1]
+    aligned_mixed = [2, 4, 4, 4, 4, 4, 4, 4, 1]
     for n in range(2, 11):
         assert P.events_per_thread(1, n, off_line_grid=True) == staged_fp64[n - 2]
         assert P.events_per_thread(1, n, True, True) == staged_fp64[n - 2]
-        # the mixed path computes in FP64 registers too and follows the same tables
+        # off the line grid both precisions follow the staged table
         assert P.events_per_thread(2, n, off_line_grid=True) == staged_fp64[n - 2]
-        assert P.events_per_thread(1, n) == aligned_fp64[n - 2] == P.events_per_thread(2, n)
+        assert P.events_per_thread(1, n) == aligned_fp64[n - 2]
+        assert P.events_per_thread(2, n) == aligned_mixed[n - 2]
         assert P.events_per_thread(0, n, off_line_grid=True) == 4  # integrate-only has no layout
     assert P.events_per_thread(1, 3) == 1 and P.events_per_thread(1, 3, True) == 1
     assert P.lib().hydra_phsp_events_per_thread(1, 1, 0) == P.EINVAL

@@ -1,0 +1,84 @@
+"""Register budgets of the built gfx950 kernels, read from the code-object
+metadata of the library's own objects (the kernel descriptors the compiler
+emits: VGPR count, private segment size, spill counts).
+
+* No kernel spills vector registers to scratch memory, except the serving
+  path's mixed-N kernels (one launch for tiles of any N, whose budget is capped
+  by a waves-per-SIMD hint; their spills are known and small).  (Scalar
+  registers that spill go to lanes of vector registers, not to memory.)
+* Where the generator kernels carry a waves-per-SIMD hint (eight daughters and
+  ten daughters at one event per lane), they fit under the next occupancy step:
+  at most 128 VGPRs (4 waves per SIMD) and 168 (3 waves) respectively."""
+from __future__ import annotations
+
+import glob
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+BUILD_DIR = os.path.join(ROOT, "_build")
+LLVM = "/opt/rocm/llvm/bin"
+TARGET = "hipv4-amdgcn-amd-amdhsa--gfx950"
+
+
+def _kernels(obj, tmp):
+    """[(name, vgprs, private segment bytes, vgpr spills, sgpr spills)] of one object."""
+    base = os.path.join(tmp, os.path.basename(obj))
+    fb, co = base + ".fatbin", base + ".co"
+    r = subprocess.run([f"{LLVM}/llvm-objcopy", f"--dump-section=.hip_fatbin={fb}", obj, base + ".host"],
+                       capture_output=True, text=True)
+    if r.returncode != 0 or not os.path.exists(fb):
+        return []
+    subprocess.run([f"{LLVM}/clang-offload-bundler", "--unbundle", "--type=o", f"--input={fb}",
+                    f"--targets={TARGET}", f"--output={co}"], check=True, capture_output=True)
+    notes = subprocess.run([f"{LLVM}/llvm-readelf", "--notes", co], check=True, capture_output=True,
+                           text=True).stdout
+    out = []
+    for blk in re.split(r"\n\s+- \.agpr_count:", notes)[1:]:
+        def field(key):
+            return re.search(rf"\.{key}:\s+(\S+)", blk).group(1)
+        out.append((field("name"), int(field("vgpr_count")), int(field("private_segment_fixed_size")),
+                    int(field("vgpr_spill_count")), int(field("sgpr_spill_count"))))
+    return out
+
+
+@pytest.fixture(scope="module")
+def kernels(tmp_path_factory):
+    if not all(os.path.exists(f"{LLVM}/{t}") for t in ("llvm-objcopy", "clang-offload-bundler", "llvm-readelf")):
+        pytest.skip("ROCm LLVM tools not available")
+    objs = sorted(glob.glob(os.path.join(BUILD_DIR, "*.o")))
+    if len(objs) < 45:
+        if shutil.which("hipcc") is None:
+            pytest.skip("library not built and hipcc not available")
+        from paper_1711_05683_amd import build
+        build.build()
+        objs = sorted(glob.glob(os.path.join(BUILD_DIR, "*.o")))
+    tmp = str(tmp_path_factory.mktemp("co"))
+    ks = {}
+    for o in objs:
+        for k in _kernels(o, tmp):
+            ks[k[0]] = k[1:]
+    assert len(ks) > 300, len(ks)
+    return ks
+
+
+def test_no_kernel_spills_except_the_serving_mixed_kernels(kernels):
+    spilling = {n: v for n, v in kernels.items() if v[1] or v[2]}
+    unexpected = sorted(n for n in spilling if "k_phsp_batched_mixed" not in n)
+    assert not unexpected, unexpected
+
+
+@pytest.mark.parametrize("n,pmodes,limit", [(8, (0, 2), 128), (10, (0, 1, 2), 168)])
+def test_hinted_generators_fit_the_next_occupancy_step(kernels, n, pmodes, limit):
+    for pmode in pmodes:
+        for mode in (1, 2):
+            name = f"_ZN5hphsp6k_phspILi{n}ELi{pmode}ELi{mode}ELi1EEEvNS_5KArgsE"
+            assert name in kernels, name
+            assert kernels[name][0] <= limit, (name, kernels[name])
+    batched = [k for k in kernels if k.startswith("_ZN5hphsp14k_phsp_batchedILi10ELi1ELi1ELb0E")]
+    if n == 10:
+        assert batched and all(kernels[k][0] <= limit for k in batched), [(k, kernels[k]) for k in batched]

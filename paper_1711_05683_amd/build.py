@@ -41,6 +41,11 @@ HIP_FLAGS = [
 ]
 
 
+# ROCTx (the markers rocprofv3 --marker-trace records around each ABI call)
+ROCM_LIB = "/opt/rocm/lib"
+LINK_LIBS = [f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
+
+
 def _hipcc() -> str:
     exe = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(exe):
@@ -94,7 +99,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         futs = [ex.submit(_compile, hipcc, s, o, x) for s, o, x in units]
         objs = [f.result() for f in futs]
     tmp = LIB_PATH + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, *LINK_LIBS]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

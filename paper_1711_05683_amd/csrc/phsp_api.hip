@@ -478,6 +478,7 @@ int hydra_phsp_generate(double parent_mass, const double* masses_host, int n_dau
                         uint64_t nevents, uint64_t seed, uint32_t stream_id, uint64_t event_offset,
                         double* p4_out_dev, uint64_t ld, double* weights_dev, double* stats_dev,
                         void* stream) {
+    MarkerRange marker("hydra_phsp_generate");
     return generate_common(parent_mass, masses_host, n_daughters, parent_p4_host, parent_p4_dev,
                            ld_parent, nevents, seed, stream_id, event_offset, p4_out_dev, ld,
                            weights_dev, stats_dev, stream, kFp64);
@@ -498,6 +499,7 @@ int hydra_phsp_generate_mixed(double parent_mass, const double* masses_host, int
                               uint64_t ld_parent, uint64_t nevents, uint64_t seed, uint32_t stream_id,
                               uint64_t event_offset, float* p4_out_dev, uint64_t ld,
                               double* weights_dev, double* stats_dev, void* stream) {
+    MarkerRange marker("hydra_phsp_generate_mixed");
     return generate_common(parent_mass, masses_host, n_daughters, parent_p4_host, parent_p4_dev,
                            ld_parent, nevents, seed, stream_id, event_offset, p4_out_dev, ld,
                            weights_dev, stats_dev, stream, kMixed);
@@ -506,6 +508,7 @@ int hydra_phsp_generate_mixed(double parent_mass, const double* masses_host, int
 int hydra_phsp_integrate_async(double parent_mass, const double* masses_host, int n_daughters,
                                uint64_t nevents, uint64_t seed, uint32_t stream_id,
                                uint64_t event_offset, double* stats_dev, void* stream) {
+    MarkerRange marker("hydra_phsp_integrate_async");
     Channel ch;
     int st = make_channel(parent_mass, masses_host, n_daughters, &ch);
     if (st != HYDRA_PHSP_OK) return st;
@@ -517,6 +520,7 @@ int hydra_phsp_integrate_async(double parent_mass, const double* masses_host, in
 int hydra_phsp_integrate(double parent_mass, const double* masses_host, int n_daughters,
                          uint64_t nevents, uint64_t seed, uint32_t stream_id, uint64_t event_offset,
                          double* mean_host, double* sigma_host, void* stream) {
+    MarkerRange marker("hydra_phsp_integrate");
     Channel ch;
     int st = make_channel(parent_mass, masses_host, n_daughters, &ch);
     if (st != HYDRA_PHSP_OK) return st;

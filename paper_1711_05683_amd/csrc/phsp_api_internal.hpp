@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <string>
 
@@ -9,6 +10,17 @@
 #include "phsp_reduce.hpp"
 
 namespace hphsp {
+
+// Named host range around one ABI call that enqueues device work, visible to
+// rocprofv3 --marker-trace beside the kernels it launched; a push and a pop,
+// cheap when no tool listens.  (The allocation-free entry point has none.)
+class MarkerRange {
+  public:
+    explicit MarkerRange(const char* name) { roctxRangePushA(name); }
+    ~MarkerRange() { roctxRangePop(); }
+    MarkerRange(const MarkerRange&) = delete;
+    MarkerRange& operator=(const MarkerRange&) = delete;
+};
 
 // ceil(a / b) for b > 0, without the overflow of (a + b - 1) / b near 2^64
 // (event counts come from callers unchecked).

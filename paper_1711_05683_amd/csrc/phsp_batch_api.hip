@@ -606,6 +606,7 @@ int hydra_phsp_plan_create(const hydra_phsp_channel* channels, int n_channels,
 }
 
 int hydra_phsp_plan_launch(hydra_phsp_plan* plan, void* stream) {
+    MarkerRange marker("hydra_phsp_plan_launch");
     if (plan == nullptr || plan->exec == nullptr) return fail(HYDRA_PHSP_EINVAL, "plan is NULL");
     hipStream_t s = (hipStream_t)stream;
     const long slot = timing_begin(s);
@@ -630,6 +631,7 @@ int hydra_phsp_plan_info(const hydra_phsp_plan* plan, uint64_t* ntiles_out, uint
 
 int hydra_phsp_batch_run(const hydra_phsp_channel* channels, int n_channels,
                          const hydra_phsp_tuning* tuning, void* stream, int* bad_channel_out) {
+    MarkerRange marker("hydra_phsp_batch_run");
     hipStream_t s = (hipStream_t)stream;
     hydra_phsp_plan* p = nullptr;
     int st = build_plan(channels, n_channels, tuning, &p, bad_channel_out);
@@ -664,6 +666,7 @@ int hydra_phsp_batch_run(const hydra_phsp_channel* channels, int n_channels,
 
 int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void* stream,
                         hydra_phsp_tuning* best_out, double* best_ms_out) {
+    MarkerRange marker("hydra_phsp_autotune");
     if (best_out == nullptr || best_ms_out == nullptr)
         return fail(HYDRA_PHSP_EINVAL, "autotune needs two host pointers");
     for (int i = 0; channels && i < n_channels; ++i) {

@@ -37,6 +37,7 @@ extern "C" int hydra_phsp_integrate_model(double parent_mass, const double* mass
                                           uint64_t nevents, uint64_t seed, uint32_t stream_id,
                                           uint64_t event_offset, double* values_dev, double* stats_dev,
                                           void* stream) {
+    MarkerRange marker("hydra_phsp_integrate_model");
     Channel ch;
     int st = make_channel(parent_mass, masses_host, n_daughters, &ch);
     if (st != HYDRA_PHSP_OK) return st;

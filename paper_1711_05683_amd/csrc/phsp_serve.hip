@@ -472,6 +472,7 @@ int hydra_phsp_server_submit(hydra_phsp_server* s, const hydra_phsp_request* req
 }
 
 int hydra_phsp_server_step(hydra_phsp_server* s) {
+    MarkerRange marker("hydra_phsp_server_step");
     if (s == nullptr) return fail(HYDRA_PHSP_EINVAL, "server is NULL");
     int st = retire(s);
     if (st != HYDRA_PHSP_OK) return st;
@@ -533,6 +534,7 @@ int hydra_phsp_server_drain(hydra_phsp_server* s) {
 
 int hydra_phsp_server_replay(hydra_phsp_server* s, const hydra_phsp_request* reqs, const double* arrival_s, int n,
                              double* latency_s_out, double* wall_s_out, uint64_t* peak_bytes_out) {
+    MarkerRange marker("hydra_phsp_server_replay");
     if (s == nullptr || (n > 0 && (reqs == nullptr || arrival_s == nullptr || latency_s_out == nullptr)))
         return fail(HYDRA_PHSP_EINVAL, "NULL argument");
     std::unordered_map<uint64_t, int> index;

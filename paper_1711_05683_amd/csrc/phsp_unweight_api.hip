@@ -223,6 +223,7 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
                                               uint32_t stream_id, uint64_t event_offset, double w_max,
                                               double* p4_out_dev, uint64_t ld, uint64_t* index_out_dev,
                                               uint64_t* counts_dev, double* w_max_dev, void* stream) {
+    MarkerRange marker("hydra_phsp_generate_unweighted");
     Channel ch;
     int st = make_channel(parent_mass, masses_host, n_daughters, &ch);
     if (st != HYDRA_PHSP_OK) return st;

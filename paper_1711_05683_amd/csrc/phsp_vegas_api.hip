@@ -257,6 +257,7 @@ extern "C" {
 int hydra_phsp_vegas_iteration(const hydra_phsp_gauss_box* f, int bins, const double* grid_dev, uint64_t calls,
                                uint64_t seed, uint32_t iteration, double* stats_dev, double* hist_dev,
                                double* values_dev, void* stream) {
+    MarkerRange marker("hydra_phsp_vegas_iteration");
     int st = check_box(f, bins);
     if (st != HYDRA_PHSP_OK) return st;
     if (grid_dev == nullptr || stats_dev == nullptr) return fail(HYDRA_PHSP_EINVAL, "grid_dev and stats_dev are required");
@@ -279,6 +280,7 @@ int hydra_phsp_vegas_refine(int dim, int bins, double* grid_host, const double* 
 int hydra_phsp_vegas(const hydra_phsp_gauss_box* f, int bins, uint64_t calls, int warmup, int iterations,
                      double alpha, uint64_t seed, double* grid_host, double* result, double* error,
                      double* chi2_dof, void* stream) {
+    MarkerRange marker("hydra_phsp_vegas");
     int st = check_box(f, bins);
     if (st != HYDRA_PHSP_OK) return st;
     if (calls < 2 || warmup < 0 || iterations < 1) return fail(HYDRA_PHSP_EINVAL, "need calls >= 2 and iterations >= 1");

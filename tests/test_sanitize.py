@@ -82,6 +82,6 @@ def test_abi_host_code_under_asan_and_ubsan(tmp_path):
           "-fno-sanitize-recover=all", f"-I{ROOT}/include", "-c", os.path.join(SAN, "abi_host_driver.c"), "-o", drv])
     exe = str(tmp_path / "abi_sanitized")
     _run([f"{LLVM}/clang++", "-fsanitize=address,undefined", "-o", exe, drv, *api, *kernels,
-          "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"])
+          "-L/opt/rocm/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"])
     r = _run([exe], env=ENV, timeout=300)
     assert "sanitized abi ok" in r.stdout

@@ -37,8 +37,15 @@
  *  - uniform k from words 2k, 2k+1: 52 bits x, u = (2x+1) 2^-53 in (0,1);
  *  - the first N-2 uniforms are the mass uniforms; then (theta, phi) pairs for
  *    levels 0..N-2;
- *  - daughter 0 is innermost; each level adds the next daughter and boosts the
- *    earlier ones (bottom-up boost chain).
+ *  - daughter 0 is innermost; the levels are built from the top down: each
+ *    subsystem {0..i+1} splits, in its own rest frame (reached from the
+ *    parent's rest frame by one pure boost), into daughter i+1 and {0..i},
+ *    and both are boosted back into the parent's rest frame, so every
+ *    daughter takes one boost (the chain runs through the subsystems'
+ *    four-momenta).  For three daughters this is the same as boosting the
+ *    inner pair up level by level; for more it is an equally valid
+ *    parametrisation of the same phase space (every direction is isotropic in
+ *    its subsystem's rest frame whatever that frame's orientation).
  */
 #include <math.h>
 #include <stdint.h>
@@ -208,26 +215,38 @@ static double one_event(double parent_mass, const double *masses, int n,
     double w = oracle_weight_constant(parent_mass, masses, n);
     for (int i = 0; i <= n - 2; ++i) w = w * p[i];
 
-    /* Level 0: daughters 0 and 1 back to back in the rest frame of {0,1}. */
-    double nhat[3];
-    direction(u[n - 2], u[n - 1], nhat);
-    p4[1][0] = sqrt(p[0] * p[0] + masses[1] * masses[1]);
-    p4[0][0] = sqrt(p[0] * p[0] + masses[0] * masses[0]);
-    for (int k = 0; k < 3; ++k) {
-        p4[1][k + 1] = p[0] * nhat[k];
-        p4[0][k + 1] = -(p[0] * nhat[k]);
-    }
-    /* Levels 1..N-2: daughter i+1 recoils against {0..i}, which is then
-     * boosted from its own rest frame into the rest frame of {0..i+1}. */
-    for (int i = 1; i <= n - 2; ++i) {
+    /* Levels from the top down.  At level i the subsystem {0..i+1} (mass
+     * sigma_{i+1}, four-momentum sub in the parent's rest frame; the parent
+     * itself at the top) splits into daughter i+1 and the subsystem {0..i}
+     * (daughter 0 when i = 0), back to back along nhat_i in the rest frame of
+     * {0..i+1} that a pure boost reaches from the parent's rest frame.  Both
+     * are boosted into the parent's rest frame with eta = sub/sigma_{i+1},
+     * gamma = E_sub/sigma_{i+1} (nothing to do at the top); daughter i+1 is
+     * then final and the subsystem goes down one level. */
+    double sub[4] = { parent_mass, 0.0, 0.0, 0.0 };
+    for (int i = n - 2; i >= 0; --i) {
+        double nhat[3];
         direction(u[n - 2 + 2 * i], u[n - 1 + 2 * i], nhat);
-        p4[i + 1][0] = sqrt(p[i] * p[i] + masses[i + 1] * masses[i + 1]);
-        for (int k = 0; k < 3; ++k) p4[i + 1][k + 1] = p[i] * nhat[k];
-        const double gamma = sqrt(p[i] * p[i] + sigma[i] * sigma[i]) / sigma[i];
-        double eta[3];
-        for (int k = 0; k < 3; ++k) eta[k] = -(p[i] / sigma[i]) * nhat[k];
-        for (int d = 0; d <= i; ++d) boost(p4[d], eta, gamma);
+        double dau[4], rest[4];
+        dau[0] = sqrt(p[i] * p[i] + masses[i + 1] * masses[i + 1]);
+        rest[0] = sqrt(p[i] * p[i] + sigma[i] * sigma[i]);
+        for (int k = 0; k < 3; ++k) {
+            dau[k + 1] = p[i] * nhat[k];
+            rest[k + 1] = -(p[i] * nhat[k]);
+        }
+        if (i < n - 2) {
+            const double gamma = sub[0] / sigma[i + 1];
+            double eta[3];
+            for (int k = 0; k < 3; ++k) eta[k] = sub[k + 1] / sigma[i + 1];
+            boost(dau, eta, gamma);
+            boost(rest, eta, gamma);
+        }
+        for (int mu = 0; mu < 4; ++mu) {
+            p4[i + 1][mu] = dau[mu];
+            sub[mu] = rest[mu];
+        }
     }
+    for (int mu = 0; mu < 4; ++mu) p4[0][mu] = sub[mu];
 
     if (parent4 != NULL) {
         const double gamma = parent4[0] / parent_mass;

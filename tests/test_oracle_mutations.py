@@ -27,12 +27,15 @@ MUTATIONS = [
     ("wrong uniform bits", "uint64_t x = bits >> 12;", "uint64_t x = (bits >> 11) & ((1ull << 52) - 1);"),
     ("factorial off by one", "for (int i = 2; i <= n - 2; ++i) fact", "for (int i = 2; i <= n - 3; ++i) fact"),
     ("Philox key word", "uint32_t y2 = hi0 ^ x3 ^ k1;", "uint32_t y2 = hi0 ^ x3 ^ k0;"),
-    ("daughter 0 not back to back", "p4[0][k + 1] = -(p[0] * nhat[k]);", "p4[0][k + 1] = (p[0] * nhat[k]);"),
+    ("subsystem not back to back", "rest[k + 1] = -(p[i] * nhat[k]);", "rest[k + 1] = (p[i] * nhat[k]);"),
     ("parent gamma off by 1e-6", "const double gamma = parent4[0] / parent_mass;",
      "const double gamma = parent4[0] / parent_mass * 1.000001;"),
     ("variance scaled", "nsum_add(&s2, d * d);", "nsum_add(&s2, d * d * 1.0000001);"),
-    ("last subsystem daughter not boosted", "for (int d = 0; d <= i; ++d) boost(p4[d], eta, gamma);",
-     "for (int d = 0; d < i; ++d) boost(p4[d], eta, gamma);"),
+    ("emitted daughter not boosted", "boost(dau, eta, gamma);", ""),
+    ("remaining subsystem not boosted", "boost(rest, eta, gamma);", ""),
+    ("subsystem boost reversed", "eta[k] = sub[k + 1] / sigma[i + 1];", "eta[k] = -sub[k + 1] / sigma[i + 1];"),
+    ("subsystem gamma from the inner mass", "const double gamma = sub[0] / sigma[i + 1];",
+     "const double gamma = sub[0] / sigma[i];"),
     ("accept uniform from the event's own last call", "(uint32_t)oracle_calls_per_event(n), stream_id };",
      "(uint32_t)(oracle_calls_per_event(n) - 1), stream_id };"),
     ("accept test inverted", "if (v * w_max < w) {", "if (v * w_max > w) {"),

@@ -314,6 +314,38 @@ def test_level0_direction_three_body(oracle_lib):
         assert np.allclose(kp / np.linalg.norm(kp), want, rtol=0, atol=1e-10)
 
 
+@pytest.mark.parametrize("n,moving", [(4, False), (6, False), (10, False), (6, True)])
+def test_every_level_direction(oracle_lib, n, moving):
+    # Top-down levels: daughter i+1, taken into the rest frame of {0..i+1} by the
+    # pure boost of that subsystem's four-momentum (summed from the outputs, in
+    # the parent's rest frame), points along the direction of level i's
+    # (theta, phi) uniforms.  (Boosting the inner daughters level by level
+    # instead would rotate these frames, and the directions of all but the top
+    # level would differ.)
+    masses = [0.05 * (i + 1) for i in range(n)]
+    M = sum(masses) + 3.0
+    parent = np.array([math.sqrt(M * M + 1.0 + 0.25 + 4.0), 1.0, 0.5, -2.0]) if moving else None
+    p4, _ = oracle_lib.generate(M, masses, 60, seed=11, stream_id=2, parent_p4=parent)
+    if moving:  # back into the parent's rest frame first
+        eta, gam = -parent[1:] / M, parent[0] / M
+        for d in range(n):
+            ep = np.einsum("k,ke->e", eta, p4[d, 1:])
+            f = ep / (gam + 1.0) + p4[d, 0]
+            p4[d, 0] = gam * p4[d, 0] + ep
+            p4[d, 1:] = p4[d, 1:] + f[None, :] * eta[:, None]
+    for e in range(60):
+        u = oracle_lib.event_uniforms(11, 2, e, n)
+        for i in range(n - 1):
+            P = p4[: i + 2, :, e].sum(axis=0)
+            sig = math.sqrt(_minkowski_sq(P))
+            eta, gam = -P[1:] / sig, P[0] / sig
+            k = p4[i + 1, :, e]
+            ep = float(eta @ k[1:])
+            kp = k[1:] + (ep / (gam + 1.0) + k[0]) * eta
+            want = _direction(u[n - 2 + 2 * i], u[n - 1 + 2 * i])
+            assert np.allclose(kp / np.linalg.norm(kp), want, rtol=0, atol=1e-9), (e, i)
+
+
 # --------------------------------------------------- distributions ----
 
 def test_dalitz_plot_is_flat(oracle_lib):

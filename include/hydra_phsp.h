@@ -132,8 +132,8 @@ int hydra_phsp_integrate(double parent_mass, const double *masses_host, int n_da
  * ends) instead of a per-stream workspace: the call makes no hipMalloc, hipFree
  * or other allocating call, and records no timing events.  Limit: at most
  * 2^20 blocks of 256 * ept events (ept as hydra_phsp_events_per_thread reports
- * for path 1), e.g. 2.68e8 events for n_daughters = 3, 5.37e8 for 4, 5 and 7,
- * and 1.07e9 for 6 and 9; larger counts fail with EINVAL before any work.
+ * for path 1), e.g. 2.68e8 events for n_daughters = 3, 5.37e8 for 4 and 5,
+ * and 1.07e9 for 6 to 10; larger counts fail with EINVAL before any work.
  * The first call on a device performs a one-time, synchronous set-up on the
  * current device (it looks up the array's address and uploads a 4 KiB
  * trigonometric table); call it once, e.g. with nevents = 0, before capturing.
@@ -178,8 +178,8 @@ int hydra_phsp_selftest_sortnet(void);
 /* Events per thread of the single-channel kernels, per path: path 0 =
  * integrate-only, 1 = FP64 generate, 2 = mixed generate; ept in {1, 2, 4}, or 0
  * for the library default.  Defaults with columns on the 128-byte line grid:
- * integrate 4; FP64 generate 2, 1, 2, 2, 4, 2, 1, 4, 1 and mixed generate 2,
- * 4, 4, 4, 4, 4, 4, 4, 1 for N = 2..10; 1 with per-event parents for N <= 3.
+ * integrate 4; FP64 generate 2, 1, 2, 2, 4, 4, 4, 4, 4 and mixed generate 2,
+ * 4, 4, 4, 4, 4, 4, 4, 4 for N = 2..10; 1 with per-event parents for N <= 3.
  * Columns off the line grid (the staged kernel) have their own: 2, 4, 2, 2, 2,
  * 1, 1, 1, 1 for N = 2..10 (any parent mode, both paths).  One launch covers at most
  * (2^32 - 1) / 256 * ept events; larger counts are rejected with EINVAL.

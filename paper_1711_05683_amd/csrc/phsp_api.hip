@@ -279,11 +279,11 @@ static hipError_t launch_by_n(int n, const LaunchSpec& s, const KArgs& a, hipStr
 // nothing, so four events per lane amortise the block reduction best.  For FP64
 // generation blocks that span 256 or 512 events per column stream their stores
 // faster than blocks spanning 1024, which favours one event per lane for N = 3
-// (and for per-event parents, which also read) and two for N = 2, 4, 5 and 7;
-// four pay off where the per-event work dominates and the registers still
-// allow three or four waves per SIMD (N = 6, 9), one where they do not (N = 8,
-// 10).  The mixed path computes the same FP64 events but stores half the
-// bytes, so its arithmetic dominates earlier: four events per lane for N = 3..9.
+// (and for per-event parents, which also read) and two for N = 2, 4 and 5;
+// from N = 6 the per-event work dominates and four pay off (the top-down levels
+// keep one subsystem live, so four events per lane still fit in about 128
+// VGPRs).  The mixed path computes the same FP64 events but stores half the
+// bytes, so its arithmetic dominates earlier: four events per lane from N = 3.
 static std::atomic<int> g_ept_override[3] = {{0}, {0}, {0}}; // read by launches on any thread
 // Off the line grid the staged kernel's LDS rounds and barriers change the
 // balance: measured the same way, a longer block run pays off for N = 3, while
@@ -298,8 +298,8 @@ static int default_ept(int mode, int n, int pmode, bool staged) {
         return kStagedFp64[n];
     }
     if (pmode == kPerEvent && n <= 3) return 1;
-    static const int kFp64[11] = {0, 0, 2, 1, 2, 2, 4, 2, 1, 4, 1};
-    static const int kMixedTable[11] = {0, 0, 2, 4, 4, 4, 4, 4, 4, 4, 1};
+    static const int kFp64[11] = {0, 0, 2, 1, 2, 2, 4, 4, 4, 4, 4};
+    static const int kMixedTable[11] = {0, 0, 2, 4, 4, 4, 4, 4, 4, 4, 4};
     return mode == kMixed ? kMixedTable[n] : kFp64[n];
 }
 

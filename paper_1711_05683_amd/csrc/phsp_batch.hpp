@@ -146,16 +146,8 @@ __device__ __forceinline__ void batched_body(const DevChannel* __restrict__ chan
 // Batched kernel for channels of exactly N daughters and one mode (kFp64 or
 // kIntegrate), staged or not: the per-event code and the register budget are
 // those of the single-channel kernel for that N, mode and layout.
-// The waves-per-SIMD hint of the single-channel kernels where the tile loop
-// still fits without spilling (ten daughters, one event per lane: 170 -> 168
-// VGPRs, three waves instead of two); none elsewhere.
 template <int N, int MODE, int EPT, bool STAGED>
-constexpr int batched_waves_hint() {
-    return (!STAGED && N == 10 && EPT == 1) ? generator_waves_hint<N, kAtRest, MODE, EPT>() : 1;
-}
-
-template <int N, int MODE, int EPT, bool STAGED>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batched_waves_hint<N, MODE, EPT, STAGED>())))
+__global__ __launch_bounds__(kBlock)
 void k_phsp_batched(const DevChannel* __restrict__ chans, const TileRef* __restrict__ tiles, uint64_t ntiles,
                     const double2* __restrict__ trig, unsigned long long* __restrict__ counter) {
     batched_body<N, N, MODE, EPT, STAGED>(chans, tiles, ntiles, trig, counter);

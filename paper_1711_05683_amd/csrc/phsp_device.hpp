@@ -11,7 +11,9 @@
 // i.e. from half k&1 of call k>>1.  The N-2 mass uniforms come first; the
 // (theta, phi) pair of level i are uniforms N-2+2i and N-1+2i, drawn only when
 // that level is built (so integrate-only launches never draw angles, and only
-// two angle uniforms are live at a time).
+// two angle uniforms are live at a time).  The levels are built from the top
+// down, and each daughter is handed on as soon as it is final, so a kernel
+// holds one subsystem's four-momentum rather than all N daughters.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -165,16 +167,29 @@ __device__ __forceinline__ void draw_masses(MassDraws<N>& d, const EventRng& rng
     }
 }
 
-// (theta, phi) uniforms of level i, drawn on demand.  For even N they are both
-// halves of call (N-2)/2 + i; for odd N, theta is the carried second half of the
-// previous call and phi the first half of call (N-1)/2 + i.
+// (theta, phi) uniforms of level i, drawn on demand from the top level down.
+// For even N they are both halves of call (N-2)/2 + i.  For odd N, call
+// c_j = (N-1)/2 + j holds phi_j (first half) and theta_{j+1} (second half), and
+// theta_0 is the second half of the last mass call (MassDraws::carry): the top
+// level draws c_{N-2} (phi; its second half is unused) and c_{N-3} (theta), every
+// lower level i >= 1 draws c_{i-1} for its theta and keeps that call's phi for
+// level i-1 in `phi_next`, and level 0 draws nothing.
 template <int N>
-__device__ __forceinline__ void draw_angles(const EventRng& rng, int i, double& carry, double& ut, double& up) {
+__device__ __forceinline__ void draw_angles_down(const EventRng& rng, int i, double theta0, double& phi_next,
+                                                 double& ut, double& up) {
     if constexpr (N % 2 == 0) {
         rng.call((uint32_t)((N - 2) / 2 + i), ut, up);
     } else {
-        ut = carry;
-        rng.call((uint32_t)((N - 1) / 2 + i), up, carry);
+        if (i == N - 2) {
+            double unused;
+            rng.call((uint32_t)((N - 1) / 2 + i), up, unused);
+        } else {
+            up = phi_next;
+        }
+        if (i >= 1)
+            rng.call((uint32_t)((N - 1) / 2 + i - 1), phi_next, ut);
+        else
+            ut = theta0;
     }
 }
 
@@ -217,41 +232,43 @@ __device__ __forceinline__ double level_energy(double m, double lo, double g, do
     return fma(m + g, hi + lo, m * m) * h;
 }
 
-// All two-body levels of one event, in one pass.  The weight (always FP64) is
-// C prod_i p_i with the invariant masses sigma_i = S_i + T R_i of the sorted
-// mass uniforms, the energy released g_i = T (R_{i+1} - R_i) and the breakup
-// momentum p_i of sigma_{i+1} -> sigma_i + m_{i+1}.  With KIN, the kinematics of
-// the level follow at once, in FP64 for every output precision: level 0 puts
-// daughters 0 and 1 back to back in the rest frame of {0,1}; level i adds
-// daughter i+1 against {0..i} and boosts daughters 0..i from the rest frame of
-// {0..i} into that of {0..i+1}.  Only the current level's quantities are live,
-// besides the sorted uniforms and the momenta.
-//
-// The momenta stay FP64 between boosts even when the outputs are FP32: a light
-// daughter emitted nearly backwards to a boost of large gamma ends up with a lab
-// energy of order E/gamma, and its lab components move by about gamma times any
-// relative error in its rest-frame direction.  Rounding the vectors to FP32
-// between boosts (a direction error of 2^-24) therefore costs up to gamma * 6e-8
-// of the daughter's energy, which for massless daughters (where gamma reaches
-// 1e3 and beyond) exceeds 1e-5; rounding once at the store costs 2^-24.
-template <int N, bool KIN>
+// All two-body levels of one event, in one pass from the top level down.  The
+// weight (always FP64) is C prod_i p_i with the invariant masses
+// sigma_i = S_i + T R_i of the sorted mass uniforms, the energy released
+// g_i = T (R_{i+1} - R_i) and the breakup momentum p_i of
+// sigma_{i+1} -> sigma_i + m_{i+1}; its factors are multiplied top level first
+// (equal to the product in any order up to rounding).  With KIN, level i splits
+// the subsystem {0..i+1}, whose four-momentum P in the parent's rest frame the
+// level above produced (the parent itself at the top), into daughter i+1 and
+// {0..i}, back to back along the level's direction in the rest frame of
+// {0..i+1}, and boosts both into the parent's rest frame with eta = P/sigma_{i+1},
+// gamma = P_E/sigma_{i+1}, 1/(gamma+1) = sigma_{i+1}/(P_E + sigma_{i+1}) (no boost
+// at the top).  `emit(k, e, x, y, z)` then receives daughter k = i+1, final; at
+// level 0 the remaining subsystem is daughter 0 and is emitted too.  Energies in
+// the subsystem's rest frame come from the gap formulas (no square roots,
+// nothing cancels).  Everything stays FP64 whatever the output precision: a
+// light daughter emitted against a boost of large gamma ends up with an energy
+// of order E/gamma, and its components move by about gamma times any relative
+// error in its rest-frame direction, so rounding to FP32 before the last boost
+// would cost up to gamma * 6e-8 of its energy (beyond 1e-5 for massless
+// daughters); rounding once at the store costs 2^-24.
+template <int N, bool KIN, class Emit>
 __device__ __forceinline__ double event_levels(const Channel& c, const EventRng& rng, MassDraws<N>& d,
-                                               const double2* tab, Event<N, double>& ev) {
-    using R = double;
+                                               const double2* tab, Emit&& emit) {
     sortnet_sort<N - 2>(d.u); // R_1..R_{N-2}; R_0 = 0 and R_{N-1} = 1 are implicit
-    double carry = d.carry;
     double w = c.C;
-    double sig_lo = c.m[0]; // sigma_i
-    double inv_lo = 0.0;    // 1 / sigma_i (i >= 1)
+    double sig_hi = c.M;  // sigma_{i+1}
+    double inv_hi = 0.0;  // 1 / sigma_{i+1} (inner subsystems)
+    double pe = c.M, px = 0.0, py = 0.0, pz = 0.0; // {0..i+1} in the parent's rest frame
+    double phi_next = 0.0;
 #pragma unroll
-    for (int i = 0; i <= N - 2; ++i) {
-        constexpr int kTop = N - 2;
-        const bool inner = i < kTop; // sigma_{i+1} is an inner subsystem, not the parent
-        const double r_hi = inner ? d.u[i] : 1.0;
+    for (int i = N - 2; i >= 0; --i) {
+        const bool top = i == N - 2;
+        const double r_hi = top ? 1.0 : d.u[i];
         const double r_lo = (i >= 1) ? d.u[i - 1] : 0.0;
-        const double sig_hi = inner ? fma(c.T, r_hi, c.S[i + 1]) : c.M;
-        const double inv_hi = inner ? recip(sig_hi) : 0.0;
-        const double h = inner ? 0.5 * inv_hi : c.half_inv_M; // 1 / (2 sigma_{i+1})
+        const double sig_lo = (i >= 1) ? fma(c.T, r_lo, c.S[i]) : c.m[0];
+        const double inv_lo = (i >= 1) ? recip(sig_lo) : 0.0;
+        const double h = top ? c.half_inv_M : 0.5 * inv_hi; // 1 / (2 sigma_{i+1})
         const double g = c.T * (r_hi - r_lo);
         const double m = c.m[i + 1];
         const double q = g * (2.0 * sig_lo + 2.0 * m + g) * (g + 2.0 * m) * (2.0 * sig_lo + g);
@@ -259,39 +276,40 @@ __device__ __forceinline__ double event_levels(const Channel& c, const EventRng&
         w *= pd;
         if constexpr (KIN) {
             double ut, up;
-            draw_angles<N>(rng, i, carry, ut, up);
-            level_momentum(pd, ut, up, tab, ev.x[i + 1], ev.y[i + 1], ev.z[i + 1]);
-            // Per-level scalars from the gap formulas: no square roots, nothing
-            // cancels.
-            if (i == 0) {
-                ev.e[1] = level_energy(m, sig_lo, g, sig_hi, h);
-                ev.e[0] = level_energy(sig_lo, m, g, sig_hi, h);
-                ev.x[0] = -ev.x[1];
-                ev.y[0] = -ev.y[1];
-                ev.z[0] = -ev.z[1];
-            } else {
-                ev.e[i + 1] = level_energy(m, sig_lo, g, sig_hi, h);
-                const double esys = level_energy(sig_lo, m, g, sig_hi, h); // energy of {0..i}
-                const R gamma = esys * inv_lo;
-                const R inv_gp1 = sig_lo * recip(esys + sig_lo); // 1/(gamma+1) = sigma / (E + sigma)
-                // eta = -(p_i / sigma_i) n: the new daughter's momentum scaled
-                const R ex = ev.x[i + 1] * -inv_lo, ey = ev.y[i + 1] * -inv_lo, ez = ev.z[i + 1] * -inv_lo;
-#pragma unroll
-                for (int k = 0; k <= i; ++k)
-                    boost<R>(ev.e[k], ev.x[k], ev.y[k], ev.z[k], ex, ey, ez, gamma, inv_gp1);
+            draw_angles_down<N>(rng, i, d.carry, phi_next, ut, up);
+            double de = level_energy(m, sig_lo, g, sig_hi, h);
+            double re = level_energy(sig_lo, m, g, sig_hi, h); // energy of {0..i}
+            double dx, dy, dz;
+            level_momentum(pd, ut, up, tab, dx, dy, dz);
+            double rx = -dx, ry = -dy, rz = -dz;
+            if (!top) {
+                const double ex = px * inv_hi, ey = py * inv_hi, ez = pz * inv_hi;
+                const double gamma = pe * inv_hi;
+                const double inv_gp1 = sig_hi * recip(pe + sig_hi);
+                boost<double>(de, dx, dy, dz, ex, ey, ez, gamma, inv_gp1);
+                boost<double>(re, rx, ry, rz, ex, ey, ez, gamma, inv_gp1);
             }
+            emit(i + 1, de, dx, dy, dz);
+            if (i == 0) emit(0, re, rx, ry, rz);
+            pe = re;
+            px = rx;
+            py = ry;
+            pz = rz;
+            // From six daughters keep each level's work together: without this
+            // fence the scheduler hoists later levels' draws and square roots and
+            // holds them live (N = 6..10: 2-4% slower without it; N = 3, 4: about
+            // 0.5% faster without it).
+            if constexpr (N >= 6) __builtin_amdgcn_sched_barrier(0);
         }
-        sig_lo = sig_hi;
-        inv_lo = inv_hi;
+        sig_hi = sig_lo;
+        inv_hi = inv_lo;
     }
     return w;
 }
 
-template <int N>
-__device__ __forceinline__ void boost_to_lab(Event<N, double>& ev, const Frame& f) {
-#pragma unroll
-    for (int k = 0; k < N; ++k)
-        boost<double>(ev.e[k], ev.x[k], ev.y[k], ev.z[k], f.eta[0], f.eta[1], f.eta[2], f.gamma, f.inv_gp1);
+// One daughter from the parent's rest frame into the lab (moving parents).
+__device__ __forceinline__ void boost_to_lab(double& e, double& x, double& y, double& z, const Frame& f) {
+    boost<double>(e, x, y, z, f.eta[0], f.eta[1], f.eta[2], f.gamma, f.inv_gp1);
 }
 
 // The block's copy of the (cos, sin) table: filled once per block from the

@@ -87,68 +87,66 @@ __device__ __forceinline__ EventRng event_rng(const KArgs& a, uint64_t base, uin
     return EventRng{(uint32_t)g, (uint32_t)(g >> 32), a.sid, a.k0, a.k1};
 }
 
-// One event's draws, levels, kinematics and lab boost, without stores: fills ev
-// in FP64 (unless MODE is kIntegrate) and returns the weight.  Every kernel that
-// needs an event calls this, so the same event is bit-identical in all of them,
-// and the mixed path's FP32 outputs are the FP64 outputs rounded once.
-template <int N, int PMODE, int MODE>
-__device__ __forceinline__ double compute_event(const KArgs& a, uint64_t base, uint32_t off, const double2* tab,
-                                                Event<N, double>& ev) {
+// One event's draws, levels, kinematics and lab boost: `sink(k, e, x, y, z)`
+// receives each daughter's final four-momentum (FP64) as soon as it is known
+// (daughter N-1 first, 0 last; nothing for integrate-only), and the weight is
+// returned.  Every kernel that needs an event goes through this, so the same
+// event is bit-identical in all of them, and the mixed path's FP32 outputs are
+// the FP64 outputs rounded once.
+template <int N, int PMODE, int MODE, class Sink>
+__device__ __forceinline__ double emit_event(const KArgs& a, uint64_t base, uint32_t off, const double2* tab,
+                                             Sink&& sink) {
     const EventRng rng = event_rng(a, base, off);
     MassDraws<N> d;
     draw_masses<N>(d, rng);
-    const double w = event_levels<N, MODE != kIntegrate>(a.ch, rng, d, tab, ev);
-    if constexpr (MODE != kIntegrate) {
-        if constexpr (PMODE == kBroadcast) boost_to_lab<N>(ev, a.frame);
-        if constexpr (PMODE == kPerEvent)
-            boost_to_lab<N>(ev, load_parent_frame(a.parent + base, a.ld_parent, off, a.ch.M, a.inv_M));
+    if constexpr (MODE == kIntegrate || PMODE == kAtRest) {
+        return event_levels<N, MODE != kIntegrate>(a.ch, rng, d, tab, sink);
+    } else {
+        const Frame f = PMODE == kBroadcast ? a.frame
+                                            : load_parent_frame(a.parent + base, a.ld_parent, off, a.ch.M, a.inv_M);
+        return event_levels<N, true>(a.ch, rng, d, tab, [&](int k, double e, double x, double y, double z) {
+            boost_to_lab(e, x, y, z, f);
+            sink(k, e, x, y, z);
+        });
     }
-    return w;
 }
 
-// One event end to end: compute_event, then the stores.  The event is base +
-// off: `base` (the block's first event) is wave-uniform, so every column address
-// is a scalar base plus the lane's 32-bit offset (PIN keeps the column bases in
-// scalar registers).  `tab` is the block's LDS copy of the trigonometric table
-// (FP64 generate only).
+// The same event collected in registers (for consumers that need every
+// daughter at once: LDS staging, model intensities).
+template <int N, int PMODE, int MODE>
+__device__ __forceinline__ double compute_event(const KArgs& a, uint64_t base, uint32_t off, const double2* tab,
+                                                Event<N, double>& ev) {
+    return emit_event<N, PMODE, MODE>(a, base, off, tab, [&](int k, double e, double x, double y, double z) {
+        ev.e[k] = e;
+        ev.x[k] = x;
+        ev.y[k] = y;
+        ev.z[k] = z;
+    });
+}
+
+// One event end to end: each daughter's four columns are stored as soon as it
+// is final, then the weight.  The event is base + off: `base` (the block's first
+// event) is wave-uniform, so every column address is a scalar base plus the
+// lane's 32-bit offset (PIN keeps the column bases in scalar registers).  `tab`
+// is the block's LDS copy of the trigonometric table.
 template <int N, int PMODE, int MODE, bool PIN = (N <= 5)>
 __device__ __forceinline__ double run_event(const KArgs& a, uint64_t base, uint32_t off, const double2* tab) {
     using R = typename std::conditional<MODE == kMixed, float, double>::type;
-    Event<N, double> ev;
-    const double w = compute_event<N, PMODE, MODE>(a, base, off, tab, ev);
-    if constexpr (MODE != kIntegrate) {
-        R* out = static_cast<R*>(a.out) + base;
-        const uint64_t ld = a.ld;
-        const uint32_t boff = off * (uint32_t)sizeof(R);
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            store_col<PIN>(out + (uint64_t)(4 * k + 0) * ld, boff, R(ev.e[k]));
-            store_col<PIN>(out + (uint64_t)(4 * k + 1) * ld, boff, R(ev.x[k]));
-            store_col<PIN>(out + (uint64_t)(4 * k + 2) * ld, boff, R(ev.y[k]));
-            store_col<PIN>(out + (uint64_t)(4 * k + 3) * ld, boff, R(ev.z[k]));
-        }
-        store_col<PIN>(a.weights + base, off * (uint32_t)sizeof(double), w);
-    }
+    R* const out = static_cast<R*>(a.out) + base;
+    const uint64_t ld = a.ld;
+    const uint32_t boff = off * (uint32_t)sizeof(R);
+    const double w = emit_event<N, PMODE, MODE>(a, base, off, tab, [&](int k, double e, double x, double y, double z) {
+        store_col<PIN>(out + (uint64_t)(4 * k + 0) * ld, boff, R(e));
+        store_col<PIN>(out + (uint64_t)(4 * k + 1) * ld, boff, R(x));
+        store_col<PIN>(out + (uint64_t)(4 * k + 2) * ld, boff, R(y));
+        store_col<PIN>(out + (uint64_t)(4 * k + 3) * ld, boff, R(z));
+    });
+    if constexpr (MODE != kIntegrate) store_col<PIN>(a.weights + base, off * (uint32_t)sizeof(double), w);
     return w;
 }
 
-// Waves per SIMD the generator kernels are compiled for.  The VGPR file holds
-// 512 registers per lane, allocated in steps of 8, so a kernel that needs a few
-// registers more than 128 (or 168) runs 3 (or 2) waves per SIMD instead of 4
-// (or 3).  Where the natural allocation sits just above such a step and the
-// compiler fits under it without spilling (checked on the built library by the
-// CPU tests), the hint asks for the extra wave; elsewhere it is 1 (no request).
 template <int N, int PMODE, int MODE, int EPT>
-constexpr int generator_waves_hint() {
-    if (MODE == kIntegrate) return 1;
-    if (N == 8 && EPT == 1 && !(PMODE == kBroadcast && MODE == kFp64)) return 4; // 130 -> 128
-    if (N == 10 && EPT == 1) return 3;                         // 170 -> 168
-    return 1;
-}
-
-template <int N, int PMODE, int MODE, int EPT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(generator_waves_hint<N, PMODE, MODE, EPT>())))
-void k_phsp(const KArgs a) {
+__global__ __launch_bounds__(kBlock) void k_phsp(const KArgs a) {
     __shared__ double2 tab[kTrigSize];
     if constexpr (MODE != kIntegrate) load_trig(tab, a.trig);
     const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * EPT);

@@ -163,18 +163,16 @@ __global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
         const uint64_t p = c + lane;
         if (p < first || p >= end) continue;
         const uint32_t off = list[wave][p - first];
-        Event<N, double> ev;
-        (void)compute_event<N, PMODE, kFp64>(u.a, base, off, tab, ev);
-        if (u.out != nullptr) {
-            double* const o = u.out + p;
-#pragma unroll
-            for (int d = 0; d < N; ++d) {
-                __builtin_nontemporal_store(ev.e[d], o + (uint64_t)(4 * d + 0) * u.ld);
-                __builtin_nontemporal_store(ev.x[d], o + (uint64_t)(4 * d + 1) * u.ld);
-                __builtin_nontemporal_store(ev.y[d], o + (uint64_t)(4 * d + 2) * u.ld);
-                __builtin_nontemporal_store(ev.z[d], o + (uint64_t)(4 * d + 3) * u.ld);
+        double* const o = u.out + p;
+        const bool store = u.out != nullptr;
+        (void)emit_event<N, PMODE, kFp64>(u.a, base, off, tab, [&](int k, double e, double x, double y, double z) {
+            if (store) {
+                __builtin_nontemporal_store(e, o + (uint64_t)(4 * k + 0) * u.ld);
+                __builtin_nontemporal_store(x, o + (uint64_t)(4 * k + 1) * u.ld);
+                __builtin_nontemporal_store(y, o + (uint64_t)(4 * k + 2) * u.ld);
+                __builtin_nontemporal_store(z, o + (uint64_t)(4 * k + 3) * u.ld);
             }
-        }
+        });
         if (u.index != nullptr) __builtin_nontemporal_store(u.a.event_offset + base + off, u.index + p);
     }
 }

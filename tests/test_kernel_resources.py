@@ -6,9 +6,7 @@ emits: VGPR count, private segment size, spill counts).
   path's mixed-N kernels (one launch for tiles of any N, whose budget is capped
   by a waves-per-SIMD hint; their spills are known and small).  (Scalar
   registers that spill go to lanes of vector registers, not to memory.)
-* Where the generator kernels carry a waves-per-SIMD hint (eight daughters and
-  ten daughters at one event per lane), they fit under the next occupancy step:
-  at most 128 VGPRs (4 waves per SIMD) and 168 (3 waves) respectively."""
+"""
 from __future__ import annotations
 
 import glob
@@ -70,15 +68,3 @@ def test_no_kernel_spills_except_the_serving_mixed_kernels(kernels):
     spilling = {n: v for n, v in kernels.items() if v[1] or v[2]}
     unexpected = sorted(n for n in spilling if "k_phsp_batched_mixed" not in n)
     assert not unexpected, unexpected
-
-
-@pytest.mark.parametrize("n,pmodes,limit", [(8, (0, 2), 128), (10, (0, 1, 2), 168)])
-def test_hinted_generators_fit_the_next_occupancy_step(kernels, n, pmodes, limit):
-    for pmode in pmodes:
-        for mode in (1, 2):
-            name = f"_ZN5hphsp6k_phspILi{n}ELi{pmode}ELi{mode}ELi1EEEvNS_5KArgsE"
-            assert name in kernels, name
-            assert kernels[name][0] <= limit, (name, kernels[name])
-    batched = [k for k in kernels if k.startswith("_ZN5hphsp14k_phsp_batchedILi10ELi1ELi1ELb0E")]
-    if n == 10:
-        assert batched and all(kernels[k][0] <= limit for k in batched), [(k, kernels[k]) for k in batched]

@@ -154,10 +154,10 @@ void k_phsp_batched(const DevChannel* __restrict__ chans, const TileRef* __restr
 }
 
 // Kernel for tiles of any N up to NMAXB in one launch (the serving path, whose
-// ticks mix requests).  Its register budget is set by the largest N; the
-// waves-per-SIMD hint caps it (3 waves for N <= 8, 2 for N <= 10) instead of
-// letting the scheduler trade occupancy for latency hiding.
-constexpr int mixed_waves_hint(int nmaxb) { return nmaxb <= 8 ? 3 : 2; }
+// ticks mix requests, and the batch's single-launch schedule).  Its register
+// budget is set by the largest N; the waves-per-SIMD hint holds it at 128 VGPRs
+// (4 waves), which the top-down levels fit without spilling for N up to 10.
+constexpr int mixed_waves_hint(int) { return 4; }
 
 template <int NMAXB, int EPT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(mixed_waves_hint(NMAXB)))) void

@@ -180,8 +180,9 @@ int hydra_phsp_selftest_sortnet(void);
  * for the library default.  Defaults with columns on the 128-byte line grid:
  * integrate 4; FP64 generate 2, 1, 2, 2, 4, 4, 4, 4, 4 and mixed generate 2,
  * 4, 4, 4, 4, 4, 4, 4, 4 for N = 2..10; 1 with per-event parents for N <= 3.
- * Columns off the line grid (the staged kernel) have their own: 2, 4, 2, 2, 2,
- * 1, 1, 1, 1 for N = 2..10 (any parent mode, both paths).  One launch covers at most
+ * Columns off the line grid (the staged kernel) have their own: FP64 2, 4, 2,
+ * 1, 1, 1, 1, 1, 1 and mixed 4, 4, 2, 1, 1, 1, 1, 1, 1 for N = 2..10 (any
+ * parent mode).  One launch covers at most
  * (2^32 - 1) / 256 * ept events; larger counts are rejected with EINVAL.
  * Process-wide; changes the launch shape only (events are bit-identical for
  * every value; integrals agree to rounding). */

@@ -286,16 +286,18 @@ static hipError_t launch_by_n(int n, const LaunchSpec& s, const KArgs& a, hipStr
 // bytes, so its arithmetic dominates earlier: four events per lane from N = 3.
 static std::atomic<int> g_ept_override[3] = {{0}, {0}, {0}}; // read by launches on any thread
 // Off the line grid the staged kernel's LDS rounds and barriers change the
-// balance: measured the same way, a longer block run pays off for N = 3, while
-// from N = 7 the staged kernel's larger register footprint makes one event per
-// lane fastest; both output precisions follow that table.
+// balance: measured the same way, a longer block run pays off for N = 3 (and
+// N = 2 with FP32 stores), while from N = 5 the staged kernel, which holds every
+// daughter of its events until they are staged, is fastest at one event per
+// lane.
 static int default_ept(int mode, int n, int pmode, bool staged) {
     const int o = g_ept_override[mode].load(std::memory_order_relaxed);
     if (o > 0) return o;
     if (mode == kIntegrate) return 4;
     if (staged) {
-        static const int kStagedFp64[11] = {0, 0, 2, 4, 2, 2, 2, 1, 1, 1, 1};
-        return kStagedFp64[n];
+        static const int kStagedFp64[11] = {0, 0, 2, 4, 2, 1, 1, 1, 1, 1, 1};
+        static const int kStagedMixed[11] = {0, 0, 4, 4, 2, 1, 1, 1, 1, 1, 1};
+        return mode == kMixed ? kStagedMixed[n] : kStagedFp64[n];
     }
     if (pmode == kPerEvent && n <= 3) return 1;
     static const int kFp64[11] = {0, 0, 2, 1, 2, 2, 4, 4, 4, 4, 4};

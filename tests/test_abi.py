@@ -102,14 +102,14 @@ def test_events_per_thread_query(P):
     assert P.lib().hydra_phsp_events_per_thread(1, 11, 0) == P.EINVAL
     assert P.lib().hydra_phsp_events_per_thread(1, 3, 4) == P.EINVAL  # unknown flag
     # columns off the line grid (staged kernel) have their own defaults
-    staged_fp64 = [2, 4, 2, 2, 2, 1, 1, 1, 1]
+    staged_fp64 = [2, 4, 2, 1, 1, 1, 1, 1, 1]
+    staged_mixed = [4, 4, 2, 1, 1, 1, 1, 1, 1]
     aligned_fp64 = [2, 1, 2, 2, 4, 4, 4, 4, 4]
     aligned_mixed = [2, 4, 4, 4, 4, 4, 4, 4, 4]
     for n in range(2, 11):
         assert P.events_per_thread(1, n, off_line_grid=True) == staged_fp64[n - 2]
         assert P.events_per_thread(1, n, True, True) == staged_fp64[n - 2]
-        # off the line grid both precisions follow the staged table
-        assert P.events_per_thread(2, n, off_line_grid=True) == staged_fp64[n - 2]
+        assert P.events_per_thread(2, n, off_line_grid=True) == staged_mixed[n - 2]
         assert P.events_per_thread(1, n) == aligned_fp64[n - 2]
         assert P.events_per_thread(2, n) == aligned_mixed[n - 2]
         assert P.events_per_thread(0, n, off_line_grid=True) == 4  # integrate-only has no layout

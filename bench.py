@@ -645,13 +645,27 @@ def batched_extra(P, torch, dev, steps):
                                   steps, 1, torch)
     ntiles, grid = plan.info()
     plan.destroy()
-    # the same batch as one launch over every tile (schedule 3, one event per
-    # thread), for comparison with the per-class launches
-    plan1 = P.Plan(descs, schedule=3)
-    ms_graph_single, _ = time_steps(plan1.launch, steps, 1, torch)
-    ntiles1, _ = plan1.info()
-    plan1.destroy()
-    ms_direct_single, kms_single = time_steps(lambda: P.batch_run(descs, schedule=3), steps, 1, torch)
+    # the same batch as one launch over every tile, heaviest tiles first, for
+    # comparison with the per-class launches: one block per tile (schedule 3),
+    # a persistent grid with a static stride (4) or dynamic claims (5); every N
+    # at its single-channel default (ept 0) or at one event per thread (ept 1)
+    single = {}
+    for sc, name in ((3, "one block per tile"), (4, "persistent, static stride"),
+                     (5, "persistent, dynamic claims")):
+        for e in (0, 1):
+            for g in ((0,) if sc == 3 else (1, 2, 4)):
+                plan1 = P.Plan(descs, schedule=sc, ept=e, grid_per_cu=g)
+                ms_graph1, _ = time_steps(plan1.launch, steps, 1, torch)
+                ntiles1, grid1 = plan1.info()
+                plan1.destroy()
+                _, kms1s = time_steps(lambda: P.batch_run(descs, schedule=sc, ept=e, grid_per_cu=g), steps, 1,
+                                      torch)
+                single[f"schedule {sc} ept {e}" + (f" grid_per_cu {g}" if g else "")] = {
+                    "kernel": f"k_phsp_batched_mixed<8, {e}>, {name}", "kernel_ms": kms1s,
+                    "kernel_write_GBs": total_bytes / (kms1s * 1e-3) / 1e9,
+                    "kernel_frac_of_8TBs": total_bytes / (kms1s * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                    "ms_per_step_graph": ms_graph1, "tiles": ntiles1, "grid": grid1}
+    best_single = min(single, key=lambda k: single[k]["kernel_ms"])
     P.release()
     del keep, descs
     # the same batch with ld = nevents (columns start mid-line): partial-line stores
@@ -668,7 +682,8 @@ def batched_extra(P, torch, dev, steps):
                                                       streams=nstr_u), steps, 1, torch)
     P.release()
     del keep, descs
-    sched_names = ["static", "dynamic", "one block per tile", "single launch"]
+    sched_names = ["static", "dynamic", "one block per tile", "single launch, one block per tile",
+                   "single persistent launch, static stride", "single persistent launch, dynamic claims"]
     return {"channels": len(specs), "events": total_events, "bytes": total_bytes,
             "tuning": {"ept": ept, "grid_per_cu": gpc, "schedule": sched_names[sched],
                        "streams": max(nstr, 1), "autotune_s": tune_s, "tiles": ntiles,
@@ -679,10 +694,7 @@ def batched_extra(P, torch, dev, steps):
             "kernel_frac_of_8TBs": total_bytes / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "ms_per_step_direct": ms_direct, "ld": "aligned_ld(nevents)",
             "kernel_ms_ld_eq_nevents": kms_unaligned,
-            "single_launch": {"kernel_ms": kms_single, "kernel_write_GBs": total_bytes / (kms_single * 1e-3) / 1e9,
-                              "kernel_frac_of_8TBs": total_bytes / (kms_single * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                              "ms_per_step_graph": ms_graph_single, "ms_per_step_direct": ms_direct_single,
-                              "tiles": ntiles1, "kernel": "k_phsp_batched_mixed<8, 1>, one block per tile"},
+            "single_launch": {"best": best_single, **single[best_single], "by_shape": single},
             "tuning_ld_eq_nevents": {"ept": ept_u, "grid_per_cu": gpc_u,
                                      "schedule": sched_names[sched_u],
                                      "streams": max(nstr_u, 1)},

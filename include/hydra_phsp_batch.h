@@ -46,20 +46,29 @@ typedef struct hydra_phsp_channel {
  *                of that N, mode and layout (columns on or off the 128-byte
  *                line grid) would use (hydra_phsp_events_per_thread), so every
  *                channel's tiles are the blocks of that call on its buffers;
- *   grid_per_cu  persistent blocks per compute unit, 1 .. 64 (schedules 0, 1);
- *   schedule     0: persistent grid, static stride over the tiles;
+ *   grid_per_cu  persistent blocks per compute unit, 1 .. 64 (schedules 0, 1,
+ *                4, 5);
+ *   schedule     one launch per (N, mode, layout) class:
+ *                0: persistent grid, static stride over the tiles;
  *                1: persistent grid, blocks claim tiles in order from a
  *                   device counter;
  *                2: one block per tile (grid = tile count, grid_per_cu is
  *                   ignored), so the hardware dispatches tiles in order;
- *                3: a single launch over the tiles of every channel, one block
- *                   per tile, heaviest tiles (largest N, generation before
- *                   integration) first, in one kernel that switches on each
- *                   tile's N; one event per thread (ept must be 0 or 1), one
- *                   stream, and every generating channel's columns on the
- *                   128-byte line grid (else EINVAL).  Events and weights are
- *                   those of the per-class launches; stats are those of
- *                   single-channel calls with one event per thread;
+ *                one launch over the tiles of every channel, heaviest tiles
+ *                first (a tile's events times the columns it writes, or times
+ *                N for integrate-only channels), in one kernel that switches on
+ *                each tile's N:
+ *                3: one block per tile;
+ *                4: persistent grid, static stride;
+ *                5: persistent grid, blocks claim tiles from a device counter;
+ *                these take ept 0 (every N and mode at the single-channel
+ *                default for columns on the line grid; the compiled defaults
+ *                apply even when hydra_phsp_set_events_per_thread has
+ *                overridden them, so events, weights and stats are those of
+ *                single-channel calls with default settings) or ept 1 (one
+ *                event per thread), run on one stream, and need every
+ *                generating channel's columns on the 128-byte line grid (else
+ *                EINVAL);
  *   streams      0 or 1: the class kernels run one after another on the
  *                caller's stream; 2 .. HYDRA_PHSP_MAX_CLASS_STREAMS: they are
  *                spread over that many streams (the caller's and the plan's
@@ -69,7 +78,9 @@ typedef struct hydra_phsp_channel {
  *                small N beside arithmetic-bound large N -- can run at the
  *                same time.  Results do not depend on it (classes write
  *                disjoint outputs and partials; the merges follow the join).
- * A zero grid_per_cu selects the library default (8). */
+ * A zero grid_per_cu selects the library default: 8 for schedules 0 and 1, 4
+ * for schedules 4 and 5 (whose kernel fits four 256-thread blocks on a compute
+ * unit). */
 #define HYDRA_PHSP_MAX_CLASS_STREAMS 4
 typedef struct hydra_phsp_tuning {
     int32_t ept;
@@ -104,8 +115,9 @@ int hydra_phsp_plan_info(const hydra_phsp_plan *plan, uint64_t *ntiles_out, uint
 /* Autotuner: times the batch (kernels and merges) over schedule
  * {static, dynamic} x events per thread {per class, 1, 2, 4} x blocks per
  * compute unit {1, 2, 4, 8, 16}, plus one block per tile x events per thread,
- * plus the single launch (when every column is on the line grid), on one
- * stream, then the best per-class shape on 2 .. HYDRA_PHSP_MAX_CLASS_STREAMS
+ * plus the single launches (when every column is on the line grid: schedules
+ * 3, 4 and 5 at events per thread {0, 1}, 4 and 5 at 1, 2 and 4 blocks per
+ * compute unit), on one stream, then the best per-class shape on 2 .. HYDRA_PHSP_MAX_CLASS_STREAMS
  * streams -- two warm-up
  * runs and five timed runs per shape, overwriting the batch's outputs -- and
  * returns the shape with the fastest run and that run's time in ms.  Results

@@ -480,7 +480,9 @@ class ChannelDesc(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """``hydra_phsp_tuning``: events per thread (0 = per class, as a single-channel call),
     persistent blocks per CU (0 = default),
-    tile schedule (0 static stride, 1 dynamic, 2 one block per tile) and the
+    tile schedule (0 static stride, 1 dynamic, 2 one block per tile, 3 one launch
+    over every tile at one event per thread, 4 one persistent launch over every
+    tile at each N's default) and the
     number of streams the class kernels are spread over (0 or 1 = one)."""
     _fields_ = [("ept", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("streams", ctypes.c_int32)]

@@ -293,16 +293,15 @@ static std::atomic<int> g_ept_override[3] = {{0}, {0}, {0}}; // read by launches
 static int default_ept(int mode, int n, int pmode, bool staged) {
     const int o = g_ept_override[mode].load(std::memory_order_relaxed);
     if (o > 0) return o;
-    if (mode == kIntegrate) return 4;
+    if (mode == kIntegrate) return kEptIntegrate;
     if (staged) {
         static const int kStagedFp64[11] = {0, 0, 2, 4, 2, 1, 1, 1, 1, 1, 1};
         static const int kStagedMixed[11] = {0, 0, 4, 4, 2, 1, 1, 1, 1, 1, 1};
         return mode == kMixed ? kStagedMixed[n] : kStagedFp64[n];
     }
     if (pmode == kPerEvent && n <= 3) return 1;
-    static const int kFp64[11] = {0, 0, 2, 1, 2, 2, 4, 4, 4, 4, 4};
     static const int kMixedTable[11] = {0, 0, 2, 4, 4, 4, 4, 4, 4, 4, 4};
-    return mode == kMixed ? kMixedTable[n] : kFp64[n];
+    return mode == kMixed ? kMixedTable[n] : kEptLineFp64[n];
 }
 
 int single_channel_ept(int mode, int n, int pmode, bool staged) { return default_ept(mode, n, pmode, staged); }

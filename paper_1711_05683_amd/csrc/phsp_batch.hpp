@@ -79,6 +79,22 @@ __device__ __forceinline__ void run_tile_mode(const DevChannel& c, uint64_t blk,
         run_tile<N, kFp64, EPT, kPin>(c.a, blk, tab);
 }
 
+// A tile of the kernel that runs every N in one launch: EPT > 0 for every
+// channel, or EPT = 0 for each N and mode's single-channel default on the line
+// grid (so the tile is exactly that call's block).
+template <int N, int EPT, int NHI>
+__device__ __forceinline__ void run_tile_any(const DevChannel& c, uint64_t blk, const double2* tab) {
+    if constexpr (EPT > 0) {
+        run_tile_mode<N, EPT, NHI>(c, blk, tab);
+    } else {
+        constexpr bool kPin = NHI <= 5;
+        if (c.mode == kIntegrate)
+            run_tile<N, kIntegrate, kEptIntegrate, kPin>(c.a, blk, tab);
+        else
+            run_tile<N, kFp64, kEptLineFp64[N], kPin>(c.a, blk, tab);
+    }
+}
+
 // A value every lane of the wave holds (read from LDS), moved to scalar
 // registers so that the tile and channel records are addressed uniformly.
 __device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
@@ -90,7 +106,7 @@ __device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
 // Tile walk shared by the batched kernels.  Tiles are taken either with a
 // static stride (block b: b, b+G, b+2G, ...; counter == nullptr; with G equal to
 // the tile count this is one block per tile) or dynamically from a zeroed device
-// counter, one atomic increment per tile, claimed while the previous tile is
+// counter, one atomic increment per tile, claimed while the current tile is
 // being processed.  Either way every block leaves once its next index is past
 // the end.  Channels of the kernel have N in [NLO, NHI]; MODE is kIntegrate or
 // kFp64 for a kernel of one mode, or -1 to follow each channel's mode; STAGED
@@ -111,10 +127,11 @@ __device__ __forceinline__ void batched_body(const DevChannel* __restrict__ chan
         t = wave_uniform(next);
     }
     while (t < ntiles) {
-        if (dynamic) {
-            __syncthreads(); // every thread holds t before `next` is overwritten
-            if (threadIdx.x == 0) next = atomicAdd(counter, 1ull);
-        }
+        // Thread 0 claims the block's next tile now; the claim stays in flight
+        // while this tile runs and is published only after it, so the atomic's
+        // round trip is hidden behind the tile.
+        unsigned long long claim = 0;
+        if (dynamic && threadIdx.x == 0) claim = atomicAdd(counter, 1ull);
         const TileRef tr = tiles[t];
         const DevChannel& c = chans[tr.channel];
         if constexpr (STAGED) {
@@ -124,20 +141,24 @@ __device__ __forceinline__ void batched_body(const DevChannel* __restrict__ chan
             run_tile<NLO, MODE, EPT, (NHI <= 5)>(c.a, tr.block, tab);
         } else {
             switch (c.n) {
-            case 2: if constexpr (NLO <= 2 && NHI >= 2) run_tile_mode<2, EPT, NHI>(c, tr.block, tab); break;
-            case 3: if constexpr (NLO <= 3 && NHI >= 3) run_tile_mode<3, EPT, NHI>(c, tr.block, tab); break;
-            case 4: if constexpr (NLO <= 4 && NHI >= 4) run_tile_mode<4, EPT, NHI>(c, tr.block, tab); break;
-            case 5: if constexpr (NLO <= 5 && NHI >= 5) run_tile_mode<5, EPT, NHI>(c, tr.block, tab); break;
-            case 6: if constexpr (NLO <= 6 && NHI >= 6) run_tile_mode<6, EPT, NHI>(c, tr.block, tab); break;
-            case 7: if constexpr (NLO <= 7 && NHI >= 7) run_tile_mode<7, EPT, NHI>(c, tr.block, tab); break;
-            case 8: if constexpr (NLO <= 8 && NHI >= 8) run_tile_mode<8, EPT, NHI>(c, tr.block, tab); break;
-            case 9: if constexpr (NLO <= 9 && NHI >= 9) run_tile_mode<9, EPT, NHI>(c, tr.block, tab); break;
-            case 10: if constexpr (NLO <= 10 && NHI >= 10) run_tile_mode<10, EPT, NHI>(c, tr.block, tab); break;
+            case 2: if constexpr (NLO <= 2 && NHI >= 2) run_tile_any<2, EPT, NHI>(c, tr.block, tab); break;
+            case 3: if constexpr (NLO <= 3 && NHI >= 3) run_tile_any<3, EPT, NHI>(c, tr.block, tab); break;
+            case 4: if constexpr (NLO <= 4 && NHI >= 4) run_tile_any<4, EPT, NHI>(c, tr.block, tab); break;
+            case 5: if constexpr (NLO <= 5 && NHI >= 5) run_tile_any<5, EPT, NHI>(c, tr.block, tab); break;
+            case 6: if constexpr (NLO <= 6 && NHI >= 6) run_tile_any<6, EPT, NHI>(c, tr.block, tab); break;
+            case 7: if constexpr (NLO <= 7 && NHI >= 7) run_tile_any<7, EPT, NHI>(c, tr.block, tab); break;
+            case 8: if constexpr (NLO <= 8 && NHI >= 8) run_tile_any<8, EPT, NHI>(c, tr.block, tab); break;
+            case 9: if constexpr (NLO <= 9 && NHI >= 9) run_tile_any<9, EPT, NHI>(c, tr.block, tab); break;
+            case 10: if constexpr (NLO <= 10 && NHI >= 10) run_tile_any<10, EPT, NHI>(c, tr.block, tab); break;
             default: break;
             }
         }
+        if (dynamic) {
+            __syncthreads(); // every wave has read `next` for this tile
+            if (threadIdx.x == 0) next = claim;
+        }
         // The tile's LDS reduction must finish before the next tile reuses LDS,
-        // and thread 0's claim of the next tile must be visible.
+        // and the published claim must be visible.
         __syncthreads();
         t = dynamic ? wave_uniform(next) : t + gridDim.x;
     }
@@ -154,9 +175,11 @@ void k_phsp_batched(const DevChannel* __restrict__ chans, const TileRef* __restr
 }
 
 // Kernel for tiles of any N up to NMAXB in one launch (the serving path, whose
-// ticks mix requests, and the batch's single-launch schedule).  Its register
-// budget is set by the largest N; the waves-per-SIMD hint holds it at 128 VGPRs
-// (4 waves), which the top-down levels fit without spilling for N up to 10.
+// ticks mix requests, and the batch's single-launch schedules).  EPT = 1: one
+// event per thread for every N; EPT = 0: each N and mode at its single-channel
+// default (kEptLineFp64, kEptIntegrate).  Its register budget is set by the
+// largest N; the waves-per-SIMD hint holds it at 128 VGPRs (4 waves), which the
+// top-down levels fit without spilling.
 constexpr int mixed_waves_hint(int) { return 4; }
 
 template <int NMAXB, int EPT>
@@ -191,9 +214,10 @@ hipError_t launch_batched_mixed(const BatchLaunch& b, hipStream_t stream);
 
 // Host launchers shared by the batched and serving paths: the channels of
 // exactly n daughters and one mode with ept events per thread; tiles of any N
-// up to nmax (8 or 10) and either mode with one event per thread.
+// up to nmax (8 or 10) and either mode with one event per thread (ept 1) or
+// each N and mode at its single-channel default (ept 0).
 hipError_t launch_batch_class(int n, int mode, bool staged, int ept, const BatchLaunch& b, hipStream_t s);
-hipError_t launch_mixed_tiles(int nmax, const BatchLaunch& b, hipStream_t s);
+hipError_t launch_mixed_tiles(int nmax, int ept, const BatchLaunch& b, hipStream_t s);
 // Stage 1 over `ngroups` group references, then stage 2 over chans[0..nch).
 hipError_t launch_batch_merges(const DevChannel* chans, const GroupRef* groups, uint64_t ngroups, Moments* mid,
                                uint64_t nch, hipStream_t s);

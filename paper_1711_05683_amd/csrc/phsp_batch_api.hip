@@ -93,7 +93,8 @@ struct hydra_phsp_plan {
     hipEvent_t done = nullptr;
     const double2* trig = nullptr;
     bool launched = false;
-    int single_nmax = 0; // schedule 3: every tile in one launch of the mixed-N kernel (0: per-class launches)
+    int single_nmax = 0; // schedules 3, 4: every tile in one launch of the mixed-N kernel (0: per-class launches)
+    int single_ept = 1;  // that launch's events per thread: 1, or 0 (each N at its single-channel default)
 };
 
 namespace hphsp {
@@ -129,7 +130,9 @@ hipError_t launch_batch_class(int n, int mode, bool staged, int ept, const Batch
     }
 }
 
-hipError_t launch_mixed_tiles(int nmax, const BatchLaunch& b, hipStream_t s) {
+hipError_t launch_mixed_tiles(int nmax, int ept, const BatchLaunch& b, hipStream_t s) {
+    if (ept == 0) return nmax <= 8 ? launch_batched_mixed<8, 0>(b, s) : launch_batched_mixed<10, 0>(b, s);
+    if (ept != 1) return hipErrorInvalidValue;
     return nmax <= 8 ? launch_batched_mixed<8, 1>(b, s) : launch_batched_mixed<10, 1>(b, s);
 }
 
@@ -185,10 +188,15 @@ static int enqueue_plan(hydra_phsp_plan* p, hipStream_t s, bool timed) {
         if (p->dynamic) {
             hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, p->d_counters, kClasses);
             e = hipGetLastError();
+            if (e != hipSuccess) {
+                timing_end(s, slot);
+                return fail_hip(e, "counter reset launch");
+            }
         }
         if (p->single_nmax > 0) {
-            BatchLaunch b{p->d_chans, p->d_tiles, p->ntiles, p->grid, p->trig, nullptr};
-            e = launch_mixed_tiles(p->single_nmax, b, s);
+            BatchLaunch b{p->d_chans, p->d_tiles, p->ntiles, p->grid, p->trig,
+                          p->dynamic ? p->d_counters : nullptr};
+            e = launch_mixed_tiles(p->single_nmax, p->single_ept, b, s);
             timing_end(s, slot);
             if (e != hipSuccess) return fail_hip(e, "batched kernel launch");
             e = launch_batch_merges(p->d_chans, p->d_groups, p->ngroups, p->d_mid, (uint64_t)p->nch, s);
@@ -280,13 +288,17 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         dyn = tuning->schedule;
         if (tuning->streams) nstreams = tuning->streams;
     }
-    if (dyn < 0 || dyn > 3) return fail(HYDRA_PHSP_EINVAL, "tuning schedule must be 0, 1, 2 or 3");
-    const bool single = dyn == 3;
+    if (dyn < 0 || dyn > 5) return fail(HYDRA_PHSP_EINVAL, "tuning schedule must be in [0, 5]");
+    // schedules 3, 4, 5: one launch over every tile (one block per tile, or a
+    // persistent grid with a static stride or dynamic claims), each N at its
+    // compiled single-channel default (ept 0) or at one event per thread
+    const bool single = dyn >= 3;
     if (single && ept != 0 && ept != 1)
-        return fail(HYDRA_PHSP_EINVAL, "the single-launch schedule runs one event per thread (tuning ept 0 or 1)");
+        return fail(HYDRA_PHSP_EINVAL, "the single-launch schedules run each N at its single-channel default "
+                                       "(tuning ept 0) or one event per thread (ept 1)");
     if (single) {
-        ept = 1;
         nstreams = 1;
+        if (tuning == nullptr || tuning->grid_per_cu == 0) gpc = 4;
         for (int i = 0; chans != nullptr && i < nch; ++i)
             if (channel_kind(chans[i]) == kKindStaged) {
                 if (bad) *bad = i;
@@ -301,10 +313,13 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     // Events per thread per class: the given value, or (0) what a single-channel
     // launch of that N, mode and layout would use, so that every channel's tiles
     // are that launch's blocks.
+    // (single launches at ept 0: the compiled defaults of their kernel, whatever
+    // the host's events-per-thread override says)
     int class_ept[kClasses];
     for (int c = 0; c < kClasses; ++c)
-        class_ept[c] = ept ? ept
-                           : single_channel_ept(class_mode(c), class_n(c), kAtRest, class_kind(c) == kKindStaged);
+        class_ept[c] = ept                ? ept
+                       : single ? (class_mode(c) == kIntegrate ? kEptIntegrate : kEptLineFp64[class_n(c)])
+                                : single_channel_ept(class_mode(c), class_n(c), kAtRest, class_kind(c) == kKindStaged);
     if (gpc < 1 || gpc > 64) return fail(HYDRA_PHSP_EINVAL, "tuning grid_per_cu must be in [1, 64]");
 
     std::vector<DevChannel> dch((size_t)nch);
@@ -370,16 +385,28 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         for (const TileRef& t : tiles) by_class[next[chan_class[t.channel]]++] = t;
         tiles.swap(by_class);
         if (single) {
-            // One launch over every tile: the heaviest tiles (largest N, generate
-            // before integrate-only) first, so the short ones fill the tail.
+            // One launch over every tile: the heaviest tiles first, so the short
+            // ones fill the tail.  A tile's cost is taken as its events times
+            // the columns it writes (4N + 1) when generating, or times N when
+            // only integrating (measured on MI355X: about 1.4 ps per column and
+            // event for the stores, 1.5 ps per daughter and event for the
+            // arithmetic alone).
+            int order[2 * 9];
+            int no = 0;
+            for (int kind : {(int)kKindDirect, (int)kKindIntegrate})
+                for (int n = kNMax; n >= 2; --n) order[no++] = class_of(n, kind);
+            auto tile_cost = [&](int c) {
+                const int n = class_n(c);
+                return class_ept[c] * (class_kind(c) == kKindIntegrate ? n : 4 * n + 1);
+            };
+            std::stable_sort(order, order + no, [&](int a, int b) { return tile_cost(a) > tile_cost(b); });
             std::vector<TileRef> heavy_first;
             heavy_first.reserve(tiles.size());
-            for (int kind : {(int)kKindDirect, (int)kKindIntegrate})
-                for (int n = kNMax; n >= 2; --n) {
-                    const int c = class_of(n, kind);
-                    heavy_first.insert(heavy_first.end(), tiles.begin() + (ptrdiff_t)class_begin[c],
-                                       tiles.begin() + (ptrdiff_t)(class_begin[c] + class_count[c]));
-                }
+            for (int k = 0; k < no; ++k) {
+                const int c = order[k];
+                heavy_first.insert(heavy_first.end(), tiles.begin() + (ptrdiff_t)class_begin[c],
+                                   tiles.begin() + (ptrdiff_t)(class_begin[c] + class_count[c]));
+            }
             tiles.swap(heavy_first);
         }
     }
@@ -398,7 +425,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
     p->trig = trig;
     p->nch = nch;
     for (int c = 0; c < kClasses; ++c) p->class_ept[c] = class_ept[c];
-    p->dynamic = dyn == 1;
+    p->dynamic = dyn == 1 || dyn == 5;
     p->ntiles = first_tile;
     p->ngroups = first_group;
     p->grid = 0;
@@ -406,6 +433,7 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         int nmax = 2;
         for (int i = 0; i < nch; ++i) nmax = std::max(nmax, (int)dch[(size_t)i].n);
         p->single_nmax = nmax;
+        p->single_ept = ept;
     }
     for (int c = 0; c < kClasses; ++c) {
         p->class_begin[c] = class_begin[c];
@@ -417,7 +445,8 @@ static int build_plan(const hydra_phsp_channel* chans, int nch, const hydra_phsp
         p->class_grid[c] = std::min<uint64_t>(class_count[c], cap);
         p->grid = std::max(p->grid, p->class_grid[c]);
     }
-    if (single) p->grid = std::min<uint64_t>(first_tile, kMaxGridBlocks); // one block per tile
+    if (single) // one block per tile, or the persistent grid
+        p->grid = std::min<uint64_t>(first_tile, dyn == 3 ? kMaxGridBlocks : (uint64_t)gpc * (uint64_t)std::max(cus, 1));
     e = hipMalloc(&p->d_partials, sizeof(Moments) * std::max<uint64_t>(first_tile, 1));
     if (e != hipSuccess) {
         free_plan(p);
@@ -539,7 +568,7 @@ static std::string device_tag(int dev) {
 }
 
 static bool tuning_valid(const hydra_phsp_tuning& t) {
-    return (t.ept == 0 || t.ept == 1 || t.ept == 2 || t.ept == 4) && t.schedule >= 0 && t.schedule <= 3 &&
+    return (t.ept == 0 || t.ept == 1 || t.ept == 2 || t.ept == 4) && t.schedule >= 0 && t.schedule <= 5 &&
            t.grid_per_cu >= 0 && t.grid_per_cu <= 64 && t.streams >= 0 && t.streams <= HYDRA_PHSP_MAX_CLASS_STREAMS;
 }
 
@@ -705,13 +734,19 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
     int st = HYDRA_PHSP_OK;
     const int epts[4] = {0, 1, 2, 4};
     const int gpcs[5] = {1, 2, 4, 8, 16};
-    // schedule 3 (one launch over every tile) needs line-aligned columns and runs
-    // one event per thread: a single candidate
+    // schedules 3..5 (one launch over every tile) need line-aligned columns and
+    // take ept 0 or 1; their persistent grids are tried at 1, 2 and 4 blocks per
+    // compute unit (the kernel holds four waves per SIMD, so four 256-thread
+    // blocks fill a compute unit)
     const bool single_ok = key.staged == 0;
-    for (int sched = 0; sched < (single_ok ? 4 : 3) && st == HYDRA_PHSP_OK; ++sched)
-    for (int ei = 0; ei < (sched == 3 ? 1 : 4) && st == HYDRA_PHSP_OK; ++ei) {
-        for (int gi = 0; gi < (sched >= 2 ? 1 : 5) && st == HYDRA_PHSP_OK; ++gi) {
-            hydra_phsp_tuning t{sched == 3 ? 1 : epts[ei], sched >= 2 ? 0 : gpcs[gi], sched, 0};
+    const int single_gpcs[3] = {1, 2, 4};
+    for (int sched = 0; sched < (single_ok ? 6 : 3) && st == HYDRA_PHSP_OK; ++sched)
+    for (int ei = 0; ei < (sched >= 3 ? 2 : 4) && st == HYDRA_PHSP_OK; ++ei) {
+        const int ngpc = sched <= 1 ? 5 : sched >= 4 ? 3 : 1;
+        for (int gi = 0; gi < ngpc && st == HYDRA_PHSP_OK; ++gi) {
+            const int ept_t = epts[ei];
+            const int gpc_t = sched <= 1 ? gpcs[gi] : sched >= 4 ? single_gpcs[gi] : 0;
+            hydra_phsp_tuning t{ept_t, gpc_t, sched, 0};
             hydra_phsp_plan* p = nullptr;
             st = build_plan(channels, n_channels, &t, &p, nullptr);
             if (st != HYDRA_PHSP_OK) break;
@@ -738,7 +773,7 @@ int hydra_phsp_autotune(const hydra_phsp_channel* channels, int n_channels, void
     // the best one-stream shape with its classes spread over more streams (a
     // single-launch shape has one kernel: nothing to spread)
     const hydra_phsp_tuning one = best;
-    for (int ns = 2; ns <= HYDRA_PHSP_MAX_CLASS_STREAMS && st == HYDRA_PHSP_OK && one.schedule != 3; ++ns) {
+    for (int ns = 2; ns <= HYDRA_PHSP_MAX_CLASS_STREAMS && st == HYDRA_PHSP_OK && one.schedule < 3; ++ns) {
         hydra_phsp_tuning t = one;
         t.streams = ns;
         hydra_phsp_plan* p = nullptr;

@@ -363,7 +363,7 @@ int launch_tick(hydra_phsp_server* s) {
     // output columns are written front to back.
     BatchLaunch b{t.chans.dev, t.tiles.dev, (uint64_t)tiles.size(),
                   std::min<uint64_t>((uint64_t)tiles.size(), kMaxGridBlocks), s->trig, nullptr};
-    e = launch_mixed_tiles(nmax, b, q);
+    e = launch_mixed_tiles(nmax, 1, b, q);
     if (e != hipSuccess) return fail_hip(e, "server tick launch");
     if (!fin.empty()) {
         e = launch_batch_merges(t.fin.dev, t.groups.dev, groups.size(), t.mid, fin.size(), q);

@@ -190,7 +190,7 @@ def test_batch_tuning_validation(P):
     good = P.channel(5.0, [1.0, 1.0], 10, stats=None)
     good.stats_dev = 8  # fake device pointer: validation happens before any device work
     arr = P._channel_array([good])
-    for kw in ({"streams": 5}, {"streams": -1}, {"schedule": 4}, {"ept": 3}, {"grid_per_cu": 65}):
+    for kw in ({"streams": 5}, {"streams": -1}, {"schedule": 6}, {"ept": 3}, {"grid_per_cu": 65}):
         t = P._tuning(**kw)
         assert P.lib().hydra_phsp_batch_run(arr, 1, ctypes.byref(t), None, None) == P.EINVAL, kw
 
@@ -215,27 +215,34 @@ def test_batch_validation_names_bad_channel(P):
     arr = P._channel_array([good])
     assert P.lib().hydra_phsp_batch_run(arr, 1, ctypes.byref(t), None, ctypes.byref(idx)) == P.EINVAL
     assert P.lib().hydra_phsp_batch_run(arr, 0, None, None, ctypes.byref(idx)) == P.EINVAL
-    for bad_t in (P._tuning(schedule=4), P._tuning(schedule=-1), P._tuning(grid_per_cu=65)):
+    for bad_t in (P._tuning(schedule=6), P._tuning(schedule=-1), P._tuning(grid_per_cu=65)):
         assert P.lib().hydra_phsp_batch_run(arr, 1, ctypes.byref(bad_t), None, ctypes.byref(idx)) == P.EINVAL
 
 
 def test_batch_single_launch_needs_line_aligned_columns(P):
-    """Schedule 3 (one launch over every tile) runs the direct-store kernel only:
-    a generating channel off the 128-byte line grid, or an events-per-thread
-    setting other than 0 or 1, is rejected before any device work."""
+    """Schedules 3, 4 and 5 (one launch over every tile) run the direct-store
+    kernel only: a generating channel off the 128-byte line grid, or an
+    events-per-thread setting other than 0 or 1, is rejected before any device
+    work."""
     aligned = P.channel(5.0, [1.0, 1.0], 100, stats=None)
     aligned.stats_dev, aligned.p4_out_dev, aligned.weights_dev, aligned.ld = 8, 1 << 20, 1 << 21, 128
     off = P.channel(5.0, [1.0, 1.0], 100, stats=None)
     off.stats_dev, off.p4_out_dev, off.weights_dev, off.ld = 8, 1 << 20, 1 << 21, 100
     idx = ctypes.c_int(-1)
     arr = P._channel_array([aligned, off])
-    t = P._tuning(schedule=3)
-    assert P.lib().hydra_phsp_batch_run(arr, 2, ctypes.byref(t), None, ctypes.byref(idx)) == P.EINVAL
-    assert idx.value == 1 and "line grid" in P.lib().hydra_phsp_last_error().decode()
-    t = P._tuning(schedule=3, ept=2)
-    arr = P._channel_array([aligned])
-    assert P.lib().hydra_phsp_batch_run(arr, 1, ctypes.byref(t), None, ctypes.byref(idx)) == P.EINVAL
-    t = P._tuning(schedule=4)
+    for sched in (3, 4, 5):
+        arr = P._channel_array([aligned, off])
+        t = P._tuning(schedule=sched)
+        assert P.lib().hydra_phsp_batch_run(arr, 2, ctypes.byref(t), None, ctypes.byref(idx)) == P.EINVAL
+        assert idx.value == 1 and "line grid" in P.lib().hydra_phsp_last_error().decode()
+        arr = P._channel_array([aligned])
+        for ept in (2, 4):
+            t = P._tuning(schedule=sched, ept=ept)
+            assert P.lib().hydra_phsp_batch_run(arr, 1, ctypes.byref(t), None, ctypes.byref(idx)) == P.EINVAL
+            assert "ept 0" in P.lib().hydra_phsp_last_error().decode()
+        t = P._tuning(schedule=sched, grid_per_cu=65)
+        assert P.lib().hydra_phsp_batch_run(arr, 1, ctypes.byref(t), None, ctypes.byref(idx)) == P.EINVAL
+    t = P._tuning(schedule=6)
     assert P.lib().hydra_phsp_batch_run(arr, 1, ctypes.byref(t), None, ctypes.byref(idx)) == P.EINVAL
 
 

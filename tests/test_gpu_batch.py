@@ -77,7 +77,7 @@ def _aligned_channels(P, n_channels, seed, nmax=10, integrate_every=4):
     return specs, bufs, descs
 
 
-def _single(P, c, i, integ, ept=1):
+def _single(P, c, i, integ, ept=1, aligned=False):
     if integ:
         P.set_events_per_thread(0, ept)
         try:
@@ -88,9 +88,11 @@ def _single(P, c, i, integ, ept=1):
         return None, None, st
     P.set_events_per_thread(1, ept)
     try:
-        # the batch channel's layout (ld = nevents), so that default settings pick the same kernel
-        out = torch.empty((len(c.masses), 4, max(c.nevents, 1)), dtype=torch.float64, device="cuda")
-        w = torch.empty(max(c.nevents, 1), dtype=torch.float64, device="cuda")
+        # the batch channel's layout (ld = nevents, or aligned_ld), so that default
+        # settings pick the same kernel
+        ld = P.aligned_ld(c.nevents) if aligned else max(c.nevents, 1)
+        out = torch.empty((len(c.masses), 4, ld), dtype=torch.float64, device="cuda")
+        w = torch.empty(ld, dtype=torch.float64, device="cuda")
         out, w, st = P.generate(c.parent_mass, c.masses, c.nevents, seed=c.seed + i, stream_id=c.stream_id,
                                 event_offset=1000 * i, out=out, weights=w)
     finally:
@@ -98,10 +100,10 @@ def _single(P, c, i, integ, ept=1):
     return out, w, st
 
 
-def _compare_with_single(P, specs, bufs, ept, exact_stats=True):
+def _compare_with_single(P, specs, bufs, ept, exact_stats=True, aligned=False):
     for i, c in enumerate(specs):
         out, w, st = bufs[i]
-        so, sw, sst = _single(P, c, i, out is None, ept)
+        so, sw, sst = _single(P, c, i, out is None, ept, aligned)
         torch.cuda.synchronize()
         if out is not None and c.nevents > 0:
             assert torch.equal(out[:, :, :c.nevents], so[:, :, :c.nevents]), f"channel {i} momenta"
@@ -174,13 +176,14 @@ def test_plan_graph_with_class_streams(P):
 
 def test_batch_single_launch(P):
     """Schedule 3: every tile of every channel (N up to 10, generate and
-    integrate-only) in one launch -- the same events and weights as
-    single-channel calls, and their integrals at one event per thread."""
+    integrate-only) in one launch, one block per tile -- the events, weights and
+    integrals of single-channel calls with default settings (ept 0) or at one
+    event per thread (ept 1)."""
     _say("batch single launch, N up to 10")
     specs, bufs, descs = _aligned_channels(P, 24, seed=57)
     P.batch_run(descs, schedule=3)
     torch.cuda.synchronize()
-    _compare_with_single(P, specs, bufs, 1)
+    _compare_with_single(P, specs, bufs, 0, aligned=True)
     specs, bufs, descs = _aligned_channels(P, 12, seed=58, nmax=8, integrate_every=3)
     P.batch_run(descs, schedule=3, ept=1)
     torch.cuda.synchronize()
@@ -198,6 +201,74 @@ def test_plan_graph_single_launch(P):
     ntiles, grid = plan.info()
     assert grid == ntiles > 0
     for rep in range(3):
+        for o, w, s in bufs:
+            if o is not None:
+                o.fill_(float("nan"))
+                w.fill_(float("nan"))
+            s.fill_(float("nan"))
+        P.integrate_async(5.279, [3.097, 0.4937, 0.13957], 100_000, seed=rep)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        for i, (o, w, s) in enumerate(bufs):
+            ro, rw, rs = ref[i]
+            n = specs[i].nevents
+            if o is not None:
+                assert torch.equal(o[:, :, :n], ro[:, :, :n]) and torch.equal(w[:n], rw[:n]), (rep, i)
+            assert torch.equal(s, rs), (rep, i)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("sched,gpc", [(4, 1), (4, 4), (5, 1), (5, 4)])
+def test_batch_single_persistent_launch(P, sched, gpc):
+    """Schedules 4 and 5: one persistent launch over every tile (N up to 10,
+    then up to 8; generate and integrate-only), blocks taking tiles with a
+    static stride or claiming them from a counter -- events, weights and
+    integrals bit-identical to single-channel calls with default settings on
+    the same layout, or at one event per thread."""
+    _say(f"batch single persistent launch, schedule {sched}, {gpc} block(s) per CU, N up to 10")
+    specs, bufs, descs = _aligned_channels(P, 24, seed=61)
+    P.batch_run(descs, schedule=sched, grid_per_cu=gpc)
+    torch.cuda.synchronize()
+    _compare_with_single(P, specs, bufs, 0, aligned=True)
+    _say(f"batch single persistent launch, schedule {sched}, {gpc} block(s) per CU, N up to 8, ept 1")
+    specs, bufs, descs = _aligned_channels(P, 12, seed=62, nmax=8, integrate_every=3)
+    P.batch_run(descs, schedule=sched, grid_per_cu=gpc, ept=1)
+    torch.cuda.synchronize()
+    _compare_with_single(P, specs, bufs, 1)
+
+
+def test_batch_single_persistent_launch_ignores_ept_override(P):
+    """The single launches run their compiled per-N defaults even while the
+    host's events-per-thread setting is overridden."""
+    _say("batch single persistent launch under an events-per-thread override")
+    specs, bufs, descs = _aligned_channels(P, 12, seed=63, nmax=8, integrate_every=3)
+    for sched in (3, 4, 5):
+        P.set_events_per_thread(0, 1)
+        P.set_events_per_thread(1, 1)
+        try:
+            P.batch_run(descs, schedule=sched)
+            torch.cuda.synchronize()
+        finally:
+            P.set_events_per_thread(0, 0)
+            P.set_events_per_thread(1, 0)
+        _compare_with_single(P, specs, bufs, 0, aligned=True)
+
+
+@pytest.mark.parametrize("sched", [4, 5])
+def test_plan_graph_single_persistent_launch(P, sched):
+    """A persistent single-launch plan (schedule 5: its tile counter reset by a
+    kernel in the graph) replays to its eager result with other work between
+    replays."""
+    _say(f"graph replays, single persistent launch, schedule {sched}")
+    specs, bufs, descs = _aligned_channels(P, 16, seed=64)
+    P.batch_run(descs, schedule=sched, grid_per_cu=2)
+    torch.cuda.synchronize()
+    ref = [(None if o is None else o.clone(), None if w is None else w.clone(), s.clone()) for o, w, s in bufs]
+    plan = P.Plan(descs, schedule=sched, grid_per_cu=2)
+    ntiles, grid = plan.info()
+    assert 0 < grid <= ntiles
+    for rep in range(4):
         for o, w, s in bufs:
             if o is not None:
                 o.fill_(float("nan"))
@@ -361,3 +432,50 @@ def test_config3_full_batch(P):
         assert torch.equal(so, out) and torch.equal(sw, w) and torch.equal(sst, st), i
         del so, sw
     plan.destroy()
+
+
+def test_config3_single_persistent_launch(P):
+    """The 64-channel workload on line-aligned columns as one launch (schedules
+    3, 4 and 5 at their defaults): every channel's integral bit-identical to the
+    per-class launches at default settings, sampled events against the oracle."""
+    _say("config3: 64 channels, single persistent launch")
+    from paper_1711_05683_amd.workloads import batched_channels
+    specs = batched_channels()
+    bufs, descs = [], []
+    for c in specs:
+        ld = P.aligned_ld(c.nevents)
+        out = torch.empty((c.n, 4, ld), dtype=torch.float64, device="cuda")
+        w = torch.empty(ld, dtype=torch.float64, device="cuda")
+        st = torch.empty(4, dtype=torch.float64, device="cuda")
+        bufs.append((out, w, st))
+        descs.append(P.channel(c.parent_mass, c.masses, c.nevents, seed=c.seed, stream_id=c.stream_id,
+                               out=out, weights=w, stats=st))
+    rng = np.random.default_rng(1)
+    pick = rng.choice(len(specs), size=6, replace=False)
+    P.batch_run(descs)  # per-class launches, each class at its single-channel default
+    torch.cuda.synchronize()
+    ref_stats = torch.stack([st for _, _, st in bufs]).clone()
+    ref_w = {int(i): bufs[i][1][:specs[i].nevents].clone() for i in pick}
+    for sched in (3, 4, 5):
+        _say(f"config3 single launch, schedule {sched}")
+        for _, w, st in bufs:
+            w.fill_(float("nan"))
+            st.fill_(float("nan"))
+        plan = P.Plan(descs, schedule=sched)
+        plan.launch()
+        torch.cuda.synchronize()
+        plan.destroy()
+        assert torch.equal(torch.stack([st for _, _, st in bufs]), ref_stats), sched
+        for i in pick:
+            assert torch.equal(bufs[i][1][:specs[i].nevents], ref_w[int(i)]), (sched, i)
+    for i in pick:
+        c = specs[i]
+        out, w, st = bufs[i]
+        idx = np.unique(np.concatenate([[0, c.nevents - 1], rng.integers(0, c.nevents, 100)]))
+        ti = torch.as_tensor(idx, device="cuda")
+        g = out[:, :, ti].cpu().numpy()
+        gw = w[ti].cpu().numpy()
+        for j, e in enumerate(idx):
+            p4o, wo = oracle.generate(c.parent_mass, c.masses, 1, seed=c.seed, stream_id=c.stream_id,
+                                      event_offset=int(e))
+            assert_events_close(g[:, :, j:j + 1], gw[j:j + 1], p4o, wo)

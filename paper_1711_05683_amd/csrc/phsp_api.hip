@@ -14,6 +14,7 @@
 
 #include "hydra_phsp.h"
 #include "phsp_api_internal.hpp"
+#include "phsp_ept.hpp"
 #include "phsp_finalize.hpp"
 #include "phsp_kernels.hpp"
 

@@ -15,6 +15,7 @@
 // single-channel integral bit for bit.
 #pragma once
 
+#include "phsp_ept.hpp"
 #include "phsp_finalize.hpp"
 #include "phsp_kernels.hpp"
 

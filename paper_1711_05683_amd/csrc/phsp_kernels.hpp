@@ -21,13 +21,6 @@ constexpr int kWaves = kBlock / 64;
 enum ParentMode { kAtRest = 0, kBroadcast = 1, kPerEvent = 2 };
 enum Mode { kIntegrate = 0, kFp64 = 1, kMixed = 2 };
 
-// Default events per thread of the FP64 kernels whose columns lie on the 128-byte
-// line grid, by daughter count, and of integration (the fastest of 1, 2 and 4 in
-// warmed sweeps on MI355X).  The host's launch defaults and the batch kernel
-// that runs every N in one launch at these settings both read them.
-constexpr int kEptLineFp64[11] = {0, 0, 2, 1, 2, 2, 4, 4, 4, 4, 4};
-constexpr int kEptIntegrate = 4;
-
 struct KArgs {
     Channel ch;
     Frame frame;           // kBroadcast

@@ -10,13 +10,15 @@
 //   count  per segment: the keep decisions as bit masks (one 64-bit word per 64
 //          trials; weights only, no kinematics), and the kept and over-bound
 //          counts;
-//   write  per segment: the kept trials' indices from the masks, then the full
-//          kinematics of the kept trials only, lane j of a wave taking output
-//          position c + j for 64-aligned c, so each store covers whole lines;
-//          the kinematics are recomputed from the counters (identical to the
-//          weighted events).
-// Between count and write the per-segment counts are scanned
-// (phsp_unweight_api.hip).
+//   write  per range of kUnwRange output positions (aligned to kUnwRange, one
+//          wave each): the kept trials that land in the range, listed from the
+//          masks starting in the segment that holds the range's first
+//          position, then the full kinematics of those trials only, lane j of
+//          the wave taking output position c + j for 64-aligned c, so every
+//          store covers whole lines; the kinematics are recomputed from the
+//          counters (identical to the weighted events).
+// Between count and write the per-segment counts are scanned and each range's
+// first segment is recorded (phsp_unweight_api.hip).
 #pragma once
 
 #include "phsp_kernels.hpp"
@@ -26,7 +28,11 @@ namespace hphsp {
 constexpr int kUnwEpt = 4;        // max pass: trials per lane; a block covers 1024 trials
 constexpr int kUnwSegWords = 16;  // mask words of a segment
 constexpr int kUnwSeg = 64 * kUnwSegWords; // trials of a segment (one wave)
-constexpr int kUnwSegPerBlock = kBlock / 64; // segments of a count or write block
+constexpr int kUnwSegPerBlock = kBlock / 64; // segments of a count block, ranges of a write block
+constexpr int kUnwRange = 1024;   // output positions of a write-pass range (one wave)
+// A range's trials are listed with 32-bit offsets from a base trial; a list is
+// cut short (and the next one based anew) once its trials span this many.
+constexpr uint64_t kUnwSpanLimit = 1ull << 31;
 
 // Philox calls of one event's own uniforms: ceil((3N - 4) / 2).
 template <int N>
@@ -47,6 +53,8 @@ struct UnwArgs {
     uint2* counts;             // [segments] (kept, weight > w_max) per segment
     uint64_t* masks;           // NULL (count only), or [segments * kUnwSegWords] keep bits
     const uint64_t* offsets;   // [segments] kept events before the segment
+    const uint64_t* range_seg; // [segments] segment holding output position r * kUnwRange (r < ranges)
+    const uint64_t* totals;    // [0]: kept trials (the caller's counts)
     uint64_t segments;
     double* out;               // kept events, [N][4][ld]
     uint64_t ld;               // capacity in events
@@ -128,52 +136,92 @@ __global__ __launch_bounds__(kBlock) void k_unw_count(const UnwArgs u) {
     if (lane == 0) u.counts[seg] = make_uint2(kept, over);
 }
 
-// Kept trials of each segment, with full kinematics, at their places in trial
-// order.  Each wave first lists its segment's kept trials (their offsets in the
-// segment, in order) in LDS from the mask words; then, for every 64-aligned
-// window [c, c + 64) of output positions that meets the segment's run
-// [first, first + kept), lane j computes and stores the event at position c + j.
-// With columns on the 128-byte line grid every store covers whole lines except
-// in the two windows at the ends of the run; kinematics are computed for kept
-// trials only.
+// Kept trials with full kinematics at their places in trial order.  Wave w of
+// block b takes the output range r = kUnwSegPerBlock b + w, positions
+// [r kUnwRange, min((r + 1) kUnwRange, kept, ld)).  Its first position lies in
+// the run of segment range_seg[r]; the wave walks that segment's mask words
+// and the following ones (64 words per vector load, one word per step: the
+// lanes whose bit is set write their trial's offset at their rank), skipping
+// the segment's kept trials before the range, until the range is full.  Then,
+// for every 64-aligned window [c, c + 64) of the range, lane j computes and
+// stores the event at position c + j: with columns on the 128-byte line grid
+// every store covers whole lines, and no lane idles except at the very end.
+// Trials are listed as 32-bit offsets from a base; should a range's trials
+// spread over more than kUnwSpanLimit trials (kept fraction below about 5e-7),
+// the list is stored and a new one started from the next word.
 template <int N, int PMODE>
 __global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
     __shared__ double2 tab[kTrigSize];
-    __shared__ uint16_t list[kUnwSegPerBlock][kUnwSeg];
+    __shared__ uint32_t list[kUnwSegPerBlock][kUnwRange];
     load_trig(tab, u.a.trig);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
-    const uint64_t seg = (uint64_t)blockIdx.x * kUnwSegPerBlock + wave;
-    if (seg >= u.segments) return; // no barrier follows
-    uint32_t n = 0;
-    for (int k = 0; k < kUnwSegWords; ++k) {
-        const uint64_t m = u.masks[seg * kUnwSegWords + k];
-        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if ((m >> lane) & 1u) list[wave][n + rank] = (uint16_t)(64 * k + lane);
-        n += (uint32_t)__popcll(m);
-    }
-    // the list was written by other lanes of this wave: order the LDS accesses
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint64_t first = u.offsets[seg];
-    const uint64_t end = first + n < u.ld ? first + n : u.ld; // capacity truncates the run
-    const uint64_t base = seg * (uint64_t)kUnwSeg;
-    for (uint64_t c = first & ~(uint64_t)63; c < end; c += 64) {
-        const uint64_t p = c + lane;
-        if (p < first || p >= end) continue;
-        const uint32_t off = list[wave][p - first];
-        double* const o = u.out + p;
-        const bool store = u.out != nullptr;
-        (void)emit_event<N, PMODE, kFp64>(u.a, base, off, tab, [&](int k, double e, double x, double y, double z) {
-            if (store) {
-                __builtin_nontemporal_store(e, o + (uint64_t)(4 * k + 0) * u.ld);
-                __builtin_nontemporal_store(x, o + (uint64_t)(4 * k + 1) * u.ld);
-                __builtin_nontemporal_store(y, o + (uint64_t)(4 * k + 2) * u.ld);
-                __builtin_nontemporal_store(z, o + (uint64_t)(4 * k + 3) * u.ld);
+    const uint64_t range = (uint64_t)blockIdx.x * kUnwSegPerBlock + wave;
+    const uint64_t kept = u.totals[0];
+    const uint64_t stop = kept < u.ld ? kept : u.ld; // capacity truncates
+    uint64_t pos = range * (uint64_t)kUnwRange;
+    if (pos >= stop) return; // no barrier follows
+    const uint64_t r1 = pos + kUnwRange < stop ? pos + kUnwRange : stop;
+    const uint64_t seg = u.range_seg[range];
+    uint64_t skip = pos - u.offsets[seg];                 // the segment's kept trials before the range
+    uint64_t word = seg * (uint64_t)kUnwSegWords;         // next mask word to read
+    const uint64_t words = u.segments * (uint64_t)kUnwSegWords;
+    const bool store = u.out != nullptr;
+    while (pos < r1) {
+        // list the trials of positions [pos, pos + n), offsets from trial `tbase`
+        const uint64_t tbase = word * 64;
+        const uint32_t want = (uint32_t)(r1 - pos);
+        uint32_t n = 0;
+        while (n < want && word < words && word * 64 - tbase < kUnwSpanLimit) {
+            const uint64_t mine = word + lane < words ? u.masks[word + lane] : 0ull;
+            const uint32_t lo = (uint32_t)mine, hi = (uint32_t)(mine >> 32);
+            int j = 0;
+            for (; j < 64 && n < want; ++j) {
+                // (readlane returns int: widen through uint32_t, not by sign extension)
+                const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi, j) << 32) |
+                                   (uint64_t)(uint32_t)__builtin_amdgcn_readlane(lo, j);
+                const uint32_t cnt = (uint32_t)__popcll(m);
+                if (skip >= cnt) {
+                    skip -= cnt;
+                    continue;
+                }
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                const uint32_t at = n + rank - (uint32_t)skip; // list slot of this lane's trial
+                if (((m >> lane) & 1u) && rank >= (uint32_t)skip && at < want)
+                    list[wave][at] = (uint32_t)((word + (uint64_t)j) * 64 - tbase) + lane;
+                n += cnt - (uint32_t)skip;
+                skip = 0;
             }
-        });
-        if (u.index != nullptr) __builtin_nontemporal_store(u.a.event_offset + base + off, u.index + p);
+            word += (uint64_t)j;
+        }
+        if (n > want) n = want;
+        // the list was written by other lanes of this wave: order the LDS accesses
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t c = 0; c < n; c += 64) {
+            const uint32_t q = c + lane;
+            if (q >= n) continue;
+            const uint32_t off = list[wave][q];
+            double* const o = u.out + (pos + q);
+            (void)emit_event<N, PMODE, kFp64>(u.a, tbase, off, tab,
+                                              [&](int k, double e, double x, double y, double z) {
+                if (store) {
+                    __builtin_nontemporal_store(e, o + (uint64_t)(4 * k + 0) * u.ld);
+                    __builtin_nontemporal_store(x, o + (uint64_t)(4 * k + 1) * u.ld);
+                    __builtin_nontemporal_store(y, o + (uint64_t)(4 * k + 2) * u.ld);
+                    __builtin_nontemporal_store(z, o + (uint64_t)(4 * k + 3) * u.ld);
+                }
+            });
+            if (u.index != nullptr) __builtin_nontemporal_store(u.a.event_offset + tbase + off, u.index + pos + q);
+        }
+        pos += n;
+        // the next list reuses the LDS rows only after every lane has read them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (n == 0 && word >= words) break; // the masks ran out (not reached: the counts say so)
     }
 }
 

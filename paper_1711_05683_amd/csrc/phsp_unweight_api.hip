@@ -101,15 +101,25 @@ __global__ __launch_bounds__(kScanTop) void k_unw_scan_top(uint64_t* __restrict_
 }
 
 // Stage 3: each segment's offset = its group's prefix + the kept counts of the
-// earlier segments of the group.
+// earlier segments of the group; the segment whose run [offset, offset + kept)
+// holds a range start r * kUnwRange is recorded as that range's first segment
+// (a run is at most kUnwSeg = kUnwRange long, so it holds at most one start, and
+// the runs tile [0, kept), so every range start has its segment).
+static_assert(kUnwSeg <= kUnwRange, "a segment's run holds at most one range start");
 __global__ __launch_bounds__(kScanBlock) void k_unw_scan_finish(const uint2* __restrict__ counts, uint64_t segments,
                                                                 const uint64_t* __restrict__ sums,
-                                                                uint64_t* __restrict__ offsets) {
+                                                                uint64_t* __restrict__ offsets,
+                                                                uint64_t* __restrict__ range_seg) {
     __shared__ uint64_t sm[kScanBlock / 64];
     const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
     const uint64_t v = i < segments ? counts[i].x : 0u;
     const uint64_t inc = block_inclusive_scan<kScanBlock>(v, sm);
-    if (i < segments) offsets[i] = sums[blockIdx.x] + inc - v;
+    if (i < segments) {
+        const uint64_t o = sums[blockIdx.x] + inc - v;
+        offsets[i] = o;
+        const uint64_t r = (o + kUnwRange - 1) / kUnwRange;
+        if (r * kUnwRange < o + v) range_seg[r] = i;
+    }
 }
 
 namespace {
@@ -117,6 +127,7 @@ namespace {
 struct UnwWorkspace {
     uint2* counts = nullptr;       // [segments]
     uint64_t* offsets = nullptr;   // [segments]
+    uint64_t* range_seg = nullptr; // [segments] first segment of each write-pass range (ranges <= segments)
     uint64_t* masks = nullptr;     // [segments * kUnwSegWords], allocated when outputs are asked for
     uint64_t* sums = nullptr;      // [groups] kept trials per group of kScanBlock segments
     uint64_t* over_sums = nullptr; // [groups] over-bound trials per group
@@ -131,6 +142,7 @@ std::map<std::pair<int, hipStream_t>, UnwWorkspace> g_unw_ws;
 void free_ws(UnwWorkspace& w) {
     if (w.counts) (void)hipFree(w.counts);
     if (w.offsets) (void)hipFree(w.offsets);
+    if (w.range_seg) (void)hipFree(w.range_seg);
     if (w.masks) (void)hipFree(w.masks);
     if (w.sums) (void)hipFree(w.sums);
     if (w.over_sums) (void)hipFree(w.over_sums);
@@ -168,6 +180,7 @@ int unw_workspace(hipStream_t stream, uint64_t segments, bool masks, UnwWorkspac
         const uint64_t groups = (cap + kScanBlock - 1) / kScanBlock;
         bool ok = hipMalloc(&w.counts, sizeof(uint2) * cap) == hipSuccess &&
                   hipMalloc(&w.offsets, sizeof(uint64_t) * cap) == hipSuccess &&
+                  hipMalloc(&w.range_seg, sizeof(uint64_t) * cap) == hipSuccess &&
                   hipMalloc(&w.sums, sizeof(uint64_t) * groups) == hipSuccess &&
                   hipMalloc(&w.over_sums, sizeof(uint64_t) * groups) == hipSuccess &&
                   hipMalloc(&w.w_max, sizeof(double)) == hipSuccess;
@@ -274,6 +287,8 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
     L.u.counts = ws->counts;
     L.u.masks = outputs ? ws->masks : nullptr;
     L.u.offsets = ws->offsets;
+    L.u.range_seg = ws->range_seg;
+    L.u.totals = counts_dev;
     L.u.segments = segments;
     L.u.out = p4_out_dev;
     L.u.ld = ld;
@@ -302,7 +317,7 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
     }
     if (e == hipSuccess && groups > 0 && outputs) {
         hipLaunchKernelGGL(k_unw_scan_finish, dim3((unsigned)groups), dim3(kScanBlock), 0, s, (const uint2*)ws->counts,
-                           segments, (const uint64_t*)ws->sums, ws->offsets);
+                           segments, (const uint64_t*)ws->sums, ws->offsets, ws->range_seg);
         e = hipGetLastError();
     }
     if (e == hipSuccess && blocks > 0 && outputs) e = launch_pass_n(n_daughters, 2, L, s);

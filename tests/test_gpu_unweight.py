@@ -181,3 +181,29 @@ def test_unweighted_full_size_config1(P):
         v = oracle.accept_uniform(42, 0, int(t), 3)
         assert (v * w_max < ow[0]) == bool(k) or _borderline(M, m, t, w_max, 42, 0)
     del out, idx
+
+
+def test_unweighted_sparse_span_beyond_32_bits(P):
+    """A bound far above every weight over 2.2e9 trials keeps a few hundred: the
+    write pass's one output range then spans more than 2^31 trials, so its list
+    of trials is stored and restarted from a new base.  The result must be the
+    same, bit for bit, as the same trials taken in three calls of fewer than
+    2^31 trials each (event_offset continues the counter), and every kept event
+    must be the oracle's."""
+    M, m = CFG0
+    n, w_max = 2_200_000_000, 1.0e7
+    _say(f"sparse wide span: {n} trials, w_max {w_max}")
+    big = _gpu(P, M, m, n, seed=12, w_max=w_max, capacity=4096)
+    chunks = [(0, 1_000_000_000), (1_000_000_000, 1_000_000_000), (2_000_000_000, 200_000_000)]
+    parts = [_gpu(P, M, m, c, seed=12, w_max=w_max, capacity=4096, event_offset=o) for o, c in chunks]
+    assert big[3] == 0 and sum(p[3] for p in parts) == 0
+    assert big[2] == sum(p[2] for p in parts) and 0 < big[2] < 4096
+    assert np.array_equal(big[1], np.concatenate([p[1] for p in parts]))
+    assert np.array_equal(big[0], np.concatenate([p[0] for p in parts], axis=2))
+    assert big[1][-1] - big[1][0] > 2**31  # the kept trials do span beyond 32 bits of offset
+    for j in range(0, big[2], max(big[2] // 40, 1)):
+        e = int(big[1][j])
+        op4, ow = oracle.generate(M, m, 1, seed=12, event_offset=e)
+        assert_events_close(big[0][:, :, j:j + 1], np.ones(1), op4, np.ones(1))
+        v = oracle.accept_uniform(12, 0, e, 3)
+        assert v * w_max < ow[0]

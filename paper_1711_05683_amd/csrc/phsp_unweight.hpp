@@ -53,7 +53,7 @@ struct UnwArgs {
     uint2* counts;             // [segments] (kept, weight > w_max) per segment
     uint64_t* masks;           // NULL (count only), or [segments * kUnwSegWords] keep bits
     const uint64_t* offsets;   // [segments] kept events before the segment
-    const uint64_t* range_seg; // [segments] segment holding output position r * kUnwRange (r < ranges)
+    const uint64_t* range_seg; // [ranges] segment holding output position r * kUnwRange
     const uint64_t* totals;    // [0]: kept trials (the caller's counts)
     uint64_t segments;
     double* out;               // kept events, [N][4][ld]
@@ -228,7 +228,8 @@ __global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
 struct UnwLaunch {
     UnwArgs u;
     uint64_t max_blocks; // max pass: kBlock * kUnwEpt trials per block
-    uint64_t blocks;     // count and write passes: kUnwSegPerBlock segments per block
+    uint64_t blocks;     // count pass: kUnwSegPerBlock segments per block
+    uint64_t write_blocks; // write pass: kUnwSegPerBlock ranges of kUnwRange output positions per block
     int pmode;           // kAtRest or kBroadcast (write pass)
 };
 

@@ -103,9 +103,9 @@ __global__ __launch_bounds__(kScanTop) void k_unw_scan_top(uint64_t* __restrict_
 // Stage 3: each segment's offset = its group's prefix + the kept counts of the
 // earlier segments of the group; the segment whose run [offset, offset + kept)
 // holds a range start r * kUnwRange is recorded as that range's first segment
-// (a run is at most kUnwSeg = kUnwRange long, so it holds at most one start, and
-// the runs tile [0, kept), so every range start has its segment).
-static_assert(kUnwSeg <= kUnwRange, "a segment's run holds at most one range start");
+// (a run is at most kUnwSeg long, so it holds at most kUnwSeg / kUnwRange
+// starts, and the runs tile [0, kept), so every range start has its segment).
+static_assert(kUnwSeg % kUnwRange == 0, "whole ranges per segment");
 __global__ __launch_bounds__(kScanBlock) void k_unw_scan_finish(const uint2* __restrict__ counts, uint64_t segments,
                                                                 const uint64_t* __restrict__ sums,
                                                                 uint64_t* __restrict__ offsets,
@@ -117,8 +117,7 @@ __global__ __launch_bounds__(kScanBlock) void k_unw_scan_finish(const uint2* __r
     if (i < segments) {
         const uint64_t o = sums[blockIdx.x] + inc - v;
         offsets[i] = o;
-        const uint64_t r = (o + kUnwRange - 1) / kUnwRange;
-        if (r * kUnwRange < o + v) range_seg[r] = i;
+        for (uint64_t r = (o + kUnwRange - 1) / kUnwRange; r * kUnwRange < o + v; ++r) range_seg[r] = i;
     }
 }
 
@@ -127,7 +126,7 @@ namespace {
 struct UnwWorkspace {
     uint2* counts = nullptr;       // [segments]
     uint64_t* offsets = nullptr;   // [segments]
-    uint64_t* range_seg = nullptr; // [segments] first segment of each write-pass range (ranges <= segments)
+    uint64_t* range_seg = nullptr; // first segment of each write-pass range: [segments * kUnwSeg / kUnwRange]
     uint64_t* masks = nullptr;     // [segments * kUnwSegWords], allocated when outputs are asked for
     uint64_t* sums = nullptr;      // [groups] kept trials per group of kScanBlock segments
     uint64_t* over_sums = nullptr; // [groups] over-bound trials per group
@@ -180,7 +179,7 @@ int unw_workspace(hipStream_t stream, uint64_t segments, bool masks, UnwWorkspac
         const uint64_t groups = (cap + kScanBlock - 1) / kScanBlock;
         bool ok = hipMalloc(&w.counts, sizeof(uint2) * cap) == hipSuccess &&
                   hipMalloc(&w.offsets, sizeof(uint64_t) * cap) == hipSuccess &&
-                  hipMalloc(&w.range_seg, sizeof(uint64_t) * cap) == hipSuccess &&
+                  hipMalloc(&w.range_seg, sizeof(uint64_t) * cap * (kUnwSeg / kUnwRange)) == hipSuccess &&
                   hipMalloc(&w.sums, sizeof(uint64_t) * groups) == hipSuccess &&
                   hipMalloc(&w.over_sums, sizeof(uint64_t) * groups) == hipSuccess &&
                   hipMalloc(&w.w_max, sizeof(double)) == hipSuccess;
@@ -259,9 +258,13 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
     const uint64_t max_blocks = ceil_div(ntrials, (uint64_t)kBlock * (uint64_t)kUnwEpt);
     const uint64_t segments = ceil_div(ntrials, (uint64_t)kUnwSeg);
     const uint64_t blocks = ceil_div(segments, (uint64_t)kUnwSegPerBlock);
-    if (max_blocks > 0xFFFFFFFFull / (uint64_t)kBlock || blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
-        return fail(HYDRA_PHSP_EINVAL, "ntrials too large for one launch (more than 2^32 - 1 threads)");
     const bool outputs = p4_out_dev != nullptr || index_out_dev != nullptr;
+    // write pass: one wave per range of output positions that can be filled
+    const uint64_t write_blocks =
+        outputs ? ceil_div(std::min(ntrials, ld), (uint64_t)kUnwRange * (uint64_t)kUnwSegPerBlock) : 0;
+    if (max_blocks > 0xFFFFFFFFull / (uint64_t)kBlock || blocks > 0xFFFFFFFFull / (uint64_t)kBlock ||
+        write_blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
+        return fail(HYDRA_PHSP_EINVAL, "ntrials too large for one launch (more than 2^32 - 1 threads)");
 
     hipStream_t s = (hipStream_t)stream;
     UnwWorkspace* ws = nullptr;
@@ -295,6 +298,7 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
     L.u.index = index_out_dev;
     L.max_blocks = max_blocks;
     L.blocks = blocks;
+    L.write_blocks = write_blocks;
     L.pmode = pmode;
 
     const long slot = timing_begin(s);
@@ -320,7 +324,7 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
                            segments, (const uint64_t*)ws->sums, ws->offsets, ws->range_seg);
         e = hipGetLastError();
     }
-    if (e == hipSuccess && blocks > 0 && outputs) e = launch_pass_n(n_daughters, 2, L, s);
+    if (e == hipSuccess && write_blocks > 0) e = launch_pass_n(n_daughters, 2, L, s);
     timing_end(s, slot);
     if (e != hipSuccess) return fail_hip(e, "unweighting kernel launch");
     return HYDRA_PHSP_OK;

@@ -26,11 +26,11 @@ hipError_t launch_unw_count<UNW_N>(const UnwLaunch& L, hipStream_t s) {
 
 template <>
 hipError_t launch_unw_write<UNW_N>(const UnwLaunch& L, hipStream_t s) {
-    if (!grid_ok(L.blocks) || L.u.masks == nullptr) return hipErrorInvalidValue;
+    if (!grid_ok(L.write_blocks) || L.u.masks == nullptr) return hipErrorInvalidValue;
     if (L.pmode == kBroadcast)
-        hipLaunchKernelGGL((k_unw_write<UNW_N, kBroadcast>), dim3((unsigned)L.blocks), dim3(kBlock), 0, s, L.u);
+        hipLaunchKernelGGL((k_unw_write<UNW_N, kBroadcast>), dim3((unsigned)L.write_blocks), dim3(kBlock), 0, s, L.u);
     else
-        hipLaunchKernelGGL((k_unw_write<UNW_N, kAtRest>), dim3((unsigned)L.blocks), dim3(kBlock), 0, s, L.u);
+        hipLaunchKernelGGL((k_unw_write<UNW_N, kAtRest>), dim3((unsigned)L.write_blocks), dim3(kBlock), 0, s, L.u);
     return hipGetLastError();
 }
 

@@ -346,25 +346,46 @@ COUNTER_RUNS = {"headline": None,
                 "six_pion_mixed": (10.0, [0.13957] * 6, 50_000_000, True),
                 "six_massless_mixed": (10.0, [0.0] * 6, 50_000_000, True),
                 "ten_pion_fp64": (10.0, [0.13957] * 10, 31_700_000, False),
-                "unweighted": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False)}
+                "unweighted": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False),
+                "integrate": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False),
+                "model": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False),
+                "vegas": None}
 
 
 def counter_run(P, torch, dev, name):
     """Two warm-up launches and three profiled launches of one configuration."""
+    if name == "vegas":
+        # one iteration of 1e8 calls on the 10-D Gaussian of the VEGAS extra (uniform grid)
+        import numpy as np
+        D, bins = 10, 50
+        f = P.gauss_box([0.0] * D, [1.0] * D, [0.5] * D, [0.1] * D)
+        g = torch.as_tensor(np.tile(np.linspace(0.0, 1.0, bins + 1), (D, 1)), dtype=torch.float64, device=dev)
+        for _ in range(5):
+            P.vegas_iteration(f, g, 100_000_000, seed=7, iteration=100)
+        torch.cuda.synchronize()
+        print(f"counter run {name}: 1e8 calls x5 done", flush=True)
+        return
     M, m, n, mixed = COUNTER_RUNS[name]
     dtype = torch.float32 if mixed else torch.float64
-    out = torch.empty((len(m), 4, P.aligned_ld(n)), dtype=dtype, device=dev)
     w = torch.empty(n, dtype=torch.float64, device=dev)
     st = torch.empty(4, dtype=torch.float64, device=dev)
-    if name == "unweighted":
-        cnt = torch.empty(2, dtype=torch.int64, device=dev)
-        wmo = torch.empty(1, dtype=torch.float64, device=dev)
-        P.generate_unweighted(M, m, n, out=out, counts=cnt, w_max_out=wmo)
-        torch.cuda.synchronize()
-        bound = float(wmo.item())
-        fn = lambda: P.generate_unweighted(M, m, n, w_max=bound, out=out, counts=cnt, w_max_out=wmo)  # noqa: E731
+    if name == "integrate":
+        fn = lambda: P.integrate_async(M, m, n, stats=st)  # noqa: E731
+    elif name == "model":
+        one = [(1, 2, 0.8955, 0.0473)]  # the model extra's one-factor model: per-event values and integral
+        fn = lambda: P.integrate_model(M, m, n, one, values=w, stats=st)  # noqa: E731
     else:
-        fn = lambda: P.generate(M, m, n, out=out, weights=w, stats=st, mixed=mixed)  # noqa: E731
+        out = torch.empty((len(m), 4, P.aligned_ld(n)), dtype=dtype, device=dev)
+        if name == "unweighted":
+            cnt = torch.empty(2, dtype=torch.int64, device=dev)
+            wmo = torch.empty(1, dtype=torch.float64, device=dev)
+            P.generate_unweighted(M, m, n, out=out, counts=cnt, w_max_out=wmo)
+            torch.cuda.synchronize()
+            bound = float(wmo.item())
+            fn = lambda: P.generate_unweighted(M, m, n, w_max=bound, out=out, counts=cnt,  # noqa: E731
+                                               w_max_out=wmo)
+        else:
+            fn = lambda: P.generate(M, m, n, out=out, weights=w, stats=st, mixed=mixed)  # noqa: E731
     for _ in range(5):
         fn()
     torch.cuda.synchronize()

@@ -565,6 +565,26 @@ def model_extra(P, torch, dev, M, m, n, w, st, steps):
         ms, k = time_steps(lambda: P.integrate_model(M, m, n, res, values=w, stats=st), steps, 1, torch)
         r[name] = {"kernel_ms": k, "events_per_s": n / (ms * 1e-3), "integral": float(st[1].item()),
                    "sigma": float(st[3].item())}
+    # the one-factor model as a user intensity compiled at run time (hiprtc)
+    src = """
+__device__ double hydra_phsp_user_intensity(const double* e, const double* px, const double* py,
+                                            const double* pz, const double* par) {
+    const double se = e[1] + e[2], sx = px[1] + px[2], sy = py[1] + py[2], sz = pz[1] + pz[2];
+    const double s = se * se - sx * sx - sy * sy - sz * sz;
+    const double d = par[0] * par[0] - s;
+    const double mg = par[0] * par[1];
+    return 1.0 / (d * d + mg * mg);
+}
+"""
+    t0 = time.perf_counter()
+    model = P.UserModel(src, len(m))
+    compile_s = time.perf_counter() - t0
+    ms, k = time_steps(lambda: model.integrate(M, m, n, one[0][2:], values=w, stats=st), steps, 1, torch)
+    integral = float(st[1].item())
+    model.destroy()
+    r["user_one_factor"] = {"kernel_ms": k, "events_per_s": n / (ms * 1e-3), "integral": integral,
+                            "same_integral_as_built_in": integral == r["one_factor"]["integral"],
+                            "compile_s": compile_s}
     return r
 
 

@@ -46,6 +46,61 @@ int hydra_phsp_integrate_model(double parent_mass, const double *masses_host, in
                                uint64_t nevents, uint64_t seed, uint32_t stream_id, uint64_t event_offset,
                                double *values_dev, double *stats_dev, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * User intensities, compiled at run time.  Hydra evaluates user code passed as
+ * functors with parameters (sec. 3.1 of arXiv:1711.05683); here the user
+ * passes HIP device source that defines
+ *
+ *   __device__ double hydra_phsp_user_intensity(const double *e,
+ *       const double *px, const double *py, const double *pz,
+ *       const double *par);
+ *
+ * receiving the N daughters' four-momenta (E, px, py, pz)[0..N-1] in the
+ * parent's rest frame, in caller order, and the parameters par[0..15] (the
+ * n_params given at evaluation, then zeros), and returning |A|^2 >= 0.  The
+ * macro HYDRA_PHSP_N holds N; the source may define helpers of its own (names
+ * starting with hphsp or hydra_phsp_user_model are the library's).  The
+ * library compiles the source with hiprtc for gfx950 (-O3, no floating-point
+ * contraction) together with its own kernel headers into one kernel that
+ * generates each event in registers and applies the function to it (inlined),
+ * so a model runs at the speed of the built-in Breit-Wigner product.
+ * ------------------------------------------------------------------------- */
+#define HYDRA_PHSP_USER_PARAMS 16
+
+typedef struct hydra_phsp_user_model hydra_phsp_user_model;
+
+/* Compile `source_host` (NUL-terminated) for events of n_daughters (2..10)
+ * daughters; *model_out receives the model (owned by the caller: release it
+ * with hydra_phsp_user_model_destroy).  Compilation needs no GPU; the code
+ * object is loaded on each device at its first evaluation there.  EINVAL for a
+ * NULL argument, n_daughters out of range, or a source that does not compile
+ * (the compiler's log, up to 8 KiB, is in hydra_phsp_last_error); EDEVICE when
+ * hiprtc itself fails.  Calls on one model may come from several threads;
+ * create and destroy must not overlap its evaluations. */
+int hydra_phsp_user_model_create(const char *source_host, int n_daughters, hydra_phsp_user_model **model_out);
+
+/* Waits for the devices the model was loaded on, unloads it and frees it. */
+int hydra_phsp_user_model_destroy(hydra_phsp_user_model *model);
+
+/* The model's number of daughters (or EINVAL for NULL). */
+int hydra_phsp_user_model_daughters(const hydra_phsp_user_model *model);
+
+/* Integrate the user's intensity over `nevents` events, asynchronous on
+ * `stream`: as hydra_phsp_integrate_model, with masses_host holding the
+ * model's N daughter masses and params_host n_params (0..16) doubles (host;
+ * NULL when n_params is 0).  values_dev (NULL or [nevents]) receives
+ * w |A|^2 per event, stats_dev (n, mean, M2, sigma) of those values; with
+ * |A|^2 = 1 the stats are those of hydra_phsp_integrate_async with four events
+ * per thread, and a source that computes the built-in Breit-Wigner product the
+ * same way gives the same values as hydra_phsp_integrate_model.  EINVAL for a
+ * NULL model or stats_dev, n_params out of range, NULL params with n_params >
+ * 0, misaligned pointers; EKINEMATICS as for generate; EDEVICE when the code
+ * object does not load. */
+int hydra_phsp_integrate_user_model(hydra_phsp_user_model *model, double parent_mass, const double *masses_host,
+                                    const double *params_host, int n_params, uint64_t nevents, uint64_t seed,
+                                    uint32_t stream_id, uint64_t event_offset, double *values_dev,
+                                    double *stats_dev, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

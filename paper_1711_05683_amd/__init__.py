@@ -72,6 +72,14 @@ def _declare(lib):
     lib.hydra_phsp_generate_unweighted.restype = i
     lib.hydra_phsp_integrate_model.argtypes = [d, dp, i, vp, i, u64, u64, u32, u64, vp, vp, vp]
     lib.hydra_phsp_integrate_model.restype = i
+    lib.hydra_phsp_user_model_create.argtypes = [c.c_char_p, i, c.POINTER(vp)]
+    lib.hydra_phsp_user_model_create.restype = i
+    lib.hydra_phsp_user_model_destroy.argtypes = [vp]
+    lib.hydra_phsp_user_model_destroy.restype = i
+    lib.hydra_phsp_user_model_daughters.argtypes = [vp]
+    lib.hydra_phsp_user_model_daughters.restype = i
+    lib.hydra_phsp_integrate_user_model.argtypes = [vp, d, dp, dp, i, u64, u64, u32, u64, vp, vp, vp]
+    lib.hydra_phsp_integrate_user_model.restype = i
     lib.hydra_phsp_vegas_iteration.argtypes = [vp, i, vp, u64, u64, u32, vp, vp, vp, vp]
     lib.hydra_phsp_vegas_iteration.restype = i
     lib.hydra_phsp_vegas_refine.argtypes = [i, i, vp, vp, d]
@@ -304,6 +312,61 @@ def integrate_model(parent_mass: float, masses: Sequence[float], nevents: int, r
                                             seed, stream_id, event_offset, _dptr(values), _dptr(stats),
                                             _stream_handle(stream)))
     return stats, values
+
+
+USER_PARAMS = 16
+
+
+class UserModel:
+    """A user intensity compiled at run time: ``source`` is HIP device code that
+    defines ``double hydra_phsp_user_intensity(const double* e, const double* px,
+    const double* py, const double* pz, const double* par)`` for ``n_daughters``
+    daughters (see include/hydra_phsp_model.h).  Compilation needs no GPU; a source
+    that does not compile raises PhspError with the compiler's log."""
+
+    def __init__(self, source: str, n_daughters: int):
+        self._h = None
+        h = ctypes.c_void_p()
+        _check(lib().hydra_phsp_user_model_create(source.encode(), int(n_daughters), ctypes.byref(h)))
+        self._h = h
+        self.n = int(n_daughters)
+
+    def integrate(self, parent_mass: float, masses: Sequence[float], nevents: int, params: Sequence[float] = (),
+                  *, seed: int = 42, stream_id: int = 0, event_offset: int = 0,
+                  values: Optional[torch.Tensor] = None, want_values: bool = False,
+                  stats: Optional[torch.Tensor] = None, device=None, stream: Optional[torch.cuda.Stream] = None):
+        """As integrate_model, with the user's intensity and parameters (at most
+        USER_PARAMS).  Returns ``(stats, values)``."""
+        if self._h is None:
+            raise ValueError("the model was destroyed")
+        m, n = _masses(masses)
+        if n != self.n:
+            raise ValueError(f"the model has {self.n} daughters, {n} masses given")
+        if len(params) > USER_PARAMS:
+            raise ValueError(f"at most {USER_PARAMS} parameters")
+        _check_buf(values, "values", torch.float64, nevents)
+        _check_buf(stats, "stats", torch.float64, STATS)
+        dev = _resident(device, stream, values=values, stats=stats)
+        par = (ctypes.c_double * max(len(params), 1))(*[float(x) for x in params])
+        if values is None and want_values:
+            values = torch.empty(max(nevents, 1), dtype=torch.float64, device=dev)
+        if stats is None:
+            stats = torch.empty(STATS, dtype=torch.float64, device=dev)
+        _check(lib().hydra_phsp_integrate_user_model(self._h, parent_mass, m, par, len(params), nevents, seed,
+                                                     stream_id, event_offset, _dptr(values), _dptr(stats),
+                                                     _stream_handle(stream)))
+        return stats, values
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            _check(lib().hydra_phsp_user_model_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 VEGAS_DMAX = 16

@@ -41,9 +41,39 @@ HIP_FLAGS = [
 ]
 
 
-# ROCTx (the markers rocprofv3 --marker-trace records around each ABI call)
+# ROCTx (the markers rocprofv3 --marker-trace records around each ABI call) and
+# hiprtc (run-time compilation of user model intensities)
 ROCM_LIB = "/opt/rocm/lib"
-LINK_LIBS = [f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
+LINK_LIBS = [f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", "-lhiprtc", f"-Wl,-rpath,{ROCM_LIB}"]
+
+# The kernel headers a user model is compiled against at run time, embedded in
+# the library as strings (written to _build/gen before the units compile).
+GEN_DIR = os.path.join(BUILD_DIR, "gen")
+RTC_HEADERS = ("phsp_sortnet.hpp", "phsp_device.hpp", "phsp_reduce.hpp", "phsp_stage.hpp", "phsp_kernels.hpp",
+               "phsp_model.hpp")
+RTC_DELIM = "HPHSPSRC"
+
+
+def _write_rtc_sources() -> None:
+    """_build/gen/phsp_rtc_sources.inc: the names and texts of RTC_HEADERS as
+    raw string literals, for the user-model compiler in phsp_user_model.hip."""
+    os.makedirs(GEN_DIR, exist_ok=True)
+    lines = ["// written by paper_1711_05683_amd/build.py from the csrc headers; not edited by hand",
+             f"static const int kRtcHeaders = {len(RTC_HEADERS)};",
+             "static const char* const kRtcHeaderNames[] = {" + ", ".join(f'"{h}"' for h in RTC_HEADERS) + "};",
+             "static const char* const kRtcHeaderSources[] = {"]
+    for h in RTC_HEADERS:
+        with open(os.path.join(CSRC, h)) as f:
+            text = f.read()
+        if f"){RTC_DELIM}\"" in text:
+            raise RuntimeError(f"{h} contains the raw-string delimiter")
+        lines.append(f'R"{RTC_DELIM}({text}){RTC_DELIM}",')
+    lines.append("};")
+    out = os.path.join(GEN_DIR, "phsp_rtc_sources.inc")
+    new = "\n".join(lines) + "\n"
+    if not os.path.exists(out) or open(out).read() != new:
+        with open(out, "w") as f:
+            f.write(new)
 
 
 def _hipcc() -> str:
@@ -74,7 +104,8 @@ def _units():
     for name in sorted(os.listdir(CSRC)):
         if name.endswith(".hip") and not name.endswith("_inst.hip"):
             units.append((os.path.join(CSRC, name),
-                          os.path.join(BUILD_DIR, name[:-4] + ".o"), []))
+                          os.path.join(BUILD_DIR, name[:-4] + ".o"),
+                          [f"-I{GEN_DIR}"] if name == "phsp_user_model.hip" else []))
         elif name.endswith(".cpp"):
             units.append((os.path.join(CSRC, name),
                           os.path.join(BUILD_DIR, name[:-4] + ".o"), []))
@@ -93,6 +124,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     """Compile every unit and link the shared library; returns its path."""
     hipcc = _hipcc()
     os.makedirs(BUILD_DIR, exist_ok=True)
+    _write_rtc_sources()
     jobs = jobs or min(16, os.cpu_count() or 4)
     units = _units()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

@@ -1,6 +1,7 @@
 // phsp_model.hpp -- model evaluation over phase space: every event contributes
 // w |A|^2, with |A|^2 a product of relativistic Breit-Wigner intensities in pair
-// invariant masses, and the fused reduction integrates it.
+// invariant masses (or a user's intensity function), and the fused reduction
+// integrates it.
 #pragma once
 
 #include "phsp_kernels.hpp"
@@ -66,8 +67,14 @@ __device__ __forceinline__ double model_intensity(const Event<N, double>& ev, co
     return a2;
 }
 
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_phsp_model(const ModelArgs m) {
+// One block of a model kernel: every event of the block's range, with its
+// weight w and its daughters' four-momenta (parent at rest), contributes
+// v = w f(ev); v is stored when asked and folded into the block's partial like
+// the weights of the single-channel kernel.  `f` is the intensity: the
+// Breit-Wigner product below, or a user's device function compiled at run
+// time (phsp_user_model.hip).
+template <int N, class Intensity>
+__device__ __forceinline__ void model_block(const ModelArgs& m, Intensity&& f) {
     __shared__ double2 tab[kTrigSize];
     load_trig(tab, m.a.trig);
     const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * kModelEpt);
@@ -78,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_phsp_model(const ModelArgs m) {
         if (base + off < m.a.nevents) {
             Event<N, double> ev;
             const double w = compute_event<N, kAtRest, kFp64>(m.a, base, off, tab, ev);
-            const double v = w * model_intensity<N>(ev, m);
+            const double v = w * f(ev);
             if (m.values != nullptr) __builtin_nontemporal_store(v, m.values + base + off);
             // the per-lane Welford step of the single-channel kernel
             if (k == 0) {
@@ -94,6 +101,11 @@ __global__ __launch_bounds__(kBlock) void k_phsp_model(const ModelArgs m) {
     const bool full = base + (uint64_t)(kBlock * kModelEpt) <= m.a.nevents;
     const Moments r = block_reduce<kWaves>(acc, full);
     if (threadIdx.x == 0) m.a.partials[blockIdx.x] = r;
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_phsp_model(const ModelArgs m) {
+    model_block<N>(m, [&](const Event<N, double>& ev) { return model_intensity<N>(ev, m); });
 }
 
 template <int N>

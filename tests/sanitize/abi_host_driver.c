@@ -240,6 +240,39 @@ static void serving(void)
     expect(hydra_phsp_server_counters_get(NULL, &c) == HYDRA_PHSP_EINVAL, "counters of no server");
 }
 
+/* User intensities: compilation (hiprtc, host only), the compiler's log for a
+ * bad source, and validation of every evaluation argument before the code
+ * object is loaded. */
+static void user_models(void)
+{
+    static const char good[] =
+        "__device__ double hydra_phsp_user_intensity(const double* e, const double* px, const double* py,\n"
+        "    const double* pz, const double* par) { return par[0] * e[0] + pz[1] * pz[1]; }\n";
+    hydra_phsp_user_model *um = NULL;
+    expect(hydra_phsp_user_model_create(good, 3, &um) == HYDRA_PHSP_OK && um != NULL, "user model compiles");
+    expect(hydra_phsp_user_model_daughters(um) == 3, "user model daughters");
+    const double m3[3] = { 3.097, 0.4937, 0.13957 };
+    double par[HYDRA_PHSP_USER_PARAMS + 1];
+    for (int k = 0; k <= HYDRA_PHSP_USER_PARAMS; ++k) par[k] = 0.5;
+    expect(hydra_phsp_integrate_user_model(um, 5.279, m3, par, HYDRA_PHSP_USER_PARAMS + 1, 100, 42, 0, 0, NULL,
+                                           FAKE(double, 0x100), NULL) == HYDRA_PHSP_EINVAL, "too many parameters");
+    expect(hydra_phsp_integrate_user_model(um, 5.279, m3, NULL, 2, 100, 42, 0, 0, NULL, FAKE(double, 0x100),
+                                           NULL) == HYDRA_PHSP_EINVAL, "no parameters");
+    expect(hydra_phsp_integrate_user_model(um, 5.279, m3, par, 2, 100, 42, 0, 0, NULL, NULL, NULL) ==
+               HYDRA_PHSP_EINVAL, "no stats");
+    expect(hydra_phsp_integrate_user_model(um, 3.5, m3, par, 2, 100, 42, 0, 0, NULL, FAKE(double, 0x100), NULL) ==
+               HYDRA_PHSP_EKINEMATICS, "user model kinematics");
+    expect(hydra_phsp_integrate_user_model(NULL, 5.279, m3, par, 2, 100, 42, 0, 0, NULL, FAKE(double, 0x100),
+                                           NULL) == HYDRA_PHSP_EINVAL, "no user model");
+    expect(hydra_phsp_user_model_destroy(um) == HYDRA_PHSP_OK, "user model destroy");
+    hydra_phsp_user_model *bad = NULL;
+    expect(hydra_phsp_user_model_create("not a function at all", 3, &bad) == HYDRA_PHSP_EINVAL && bad == NULL,
+           "bad source");
+    expect(strstr(hydra_phsp_last_error(), "does not compile") != NULL, "compiler log");
+    expect(hydra_phsp_user_model_create(good, 11, &bad) == HYDRA_PHSP_EINVAL, "user model daughters range");
+    expect(hydra_phsp_user_model_destroy(NULL) == HYDRA_PHSP_EINVAL, "destroy of no model");
+}
+
 int main(void)
 {
     host_tables();
@@ -247,6 +280,7 @@ int main(void)
     batched();
     next_rows();
     serving();
+    user_models();
     if (failures) {
         fprintf(stderr, "%d check(s) failed\n", failures);
         return 1;

@@ -117,3 +117,131 @@ def test_model_full_size_config1(P):
         _, _, vo = oracle.model_integrate(M, m, 2, res, seed=42, event_offset=int(e), want_values=True)
         assert abs(g[j] - vo[0]) <= _tol(M, res) * abs(vo[0])
     del vals
+
+
+# --------------------------------------------------------------------------
+# User intensities compiled at run time
+
+# The built-in Breit-Wigner product written as user code: the same expression
+# in the same order (pair components summed first, s = e^2 - x^2 - y^2 - z^2,
+# each factor divided into the running product), for up to four factors given
+# as par = (i, j, mass, width) per factor; a factor with mass 0 is unused.
+USER_BW = """
+__device__ double hydra_phsp_user_intensity(const double* e, const double* px, const double* py,
+                                            const double* pz, const double* par) {
+    double a2 = 1.0;
+    for (int k = 0; k < 4; ++k) {
+        if (par[4 * k + 2] > 0.0) {
+            const int i = (int)par[4 * k], j = (int)par[4 * k + 1];
+            const double se = e[i] + e[j], sx = px[i] + px[j], sy = py[i] + py[j], sz = pz[i] + pz[j];
+            const double s = se * se - sx * sx - sy * sy - sz * sz;
+            const double d = par[4 * k + 2] * par[4 * k + 2] - s;
+            const double mg = par[4 * k + 2] * par[4 * k + 3];
+            a2 = a2 / (d * d + mg * mg);
+        }
+    }
+    return a2;
+}
+"""
+
+# A kinematic intensity of all daughters (for any N): sum_d (E_d - par0)^2 +
+# par1 pz_0^2 + par2 |p_{N-1}|.
+USER_KIN = """
+__device__ double hydra_phsp_user_intensity(const double* e, const double* px, const double* py,
+                                            const double* pz, const double* par) {
+    double f = par[1] * pz[0] * pz[0] + par[2] * sqrt(px[HYDRA_PHSP_N - 1] * px[HYDRA_PHSP_N - 1] +
+               py[HYDRA_PHSP_N - 1] * py[HYDRA_PHSP_N - 1] + pz[HYDRA_PHSP_N - 1] * pz[HYDRA_PHSP_N - 1]);
+    for (int d = 0; d < HYDRA_PHSP_N; ++d) f += (e[d] - par[0]) * (e[d] - par[0]);
+    return f;
+}
+"""
+
+
+def _bw_params(res):
+    par = [0.0] * 16
+    for k, (i, j, mass, width) in enumerate(res):
+        par[4 * k:4 * k + 4] = [float(i), float(j), mass, width]
+    return par
+
+
+@pytest.mark.parametrize("name,M,m,res", CASES, ids=[c[0] for c in CASES])
+def test_user_model_matches_builtin(P, name, M, m, res):
+    """The Breit-Wigner product as user code, compiled at run time, gives the
+    built-in model's per-event values and integral bit for bit (same events,
+    same expression, same compiler flags)."""
+    _say(f"user model = built-in: {name}")
+    n = 50_021
+    model = P.UserModel(USER_BW, len(m))
+    try:
+        st_u, v_u = model.integrate(M, m, n, _bw_params(res), seed=13, event_offset=5, want_values=True)
+        st_b, v_b = P.integrate_model(M, m, n, res, seed=13, event_offset=5, want_values=True)
+        torch.cuda.synchronize()
+        assert torch.equal(v_u[:n], v_b[:n]), name
+        assert torch.equal(st_u, st_b), (st_u.cpu().tolist(), st_b.cpu().tolist())
+    finally:
+        model.destroy()
+
+
+@pytest.mark.parametrize("M,m", [CFG0, (10.0, [0.13957] * 6), (10.0, [0.0] * 10), (5.0, [1.0, 2.0])])
+def test_user_model_against_oracle(P, M, m):
+    """A kinematic intensity of every daughter: per-event values against the
+    intensity evaluated (in numpy) on the oracle's events times the oracle's
+    weights, and the integral against the mean of those values."""
+    N = len(m)
+    _say(f"user kinematic model vs oracle, N={N}")
+    n = 20_011
+    par = [0.3 * M, 2.0, 0.7]
+    model = P.UserModel(USER_KIN, N)
+    try:
+        st, v = model.integrate(M, m, n, par, seed=77, stream_id=2, event_offset=1 << 33, want_values=True)
+        torch.cuda.synchronize()
+        g = v[:n].cpu().numpy()
+        s = st.cpu().numpy()
+    finally:
+        model.destroy()
+    p4, w = oracle.generate(M, m, n, seed=77, stream_id=2, event_offset=1 << 33)
+    E, X, Y, Z = p4[:, 0, :], p4[:, 1, :], p4[:, 2, :], p4[:, 3, :]
+    f = par[1] * Z[0] ** 2 + par[2] * np.sqrt(X[N - 1] ** 2 + Y[N - 1] ** 2 + Z[N - 1] ** 2) + \
+        ((E - par[0]) ** 2).sum(axis=0)
+    ref = w * f
+    # momenta agree to 1e-11 E_d: f moves by about 2 sum_d |E_d - par0| 1e-11 E_d + ... <= 1e-10 of its scale
+    scale = w * (par[1] * M * M + par[2] * M + ((np.abs(E) + abs(par[0])) ** 2).sum(axis=0))
+    assert np.max(np.abs(g - ref) / scale) <= 1e-10
+    mean = math.fsum(ref) / n
+    # the mean inherits the per-event bound (plus the rounding of the two sums)
+    assert s[0] == n and abs(s[1] - mean) <= 1e-10 * math.fsum(scale) / n + FP64_TOL * abs(mean)
+
+
+def test_user_model_constant_is_the_volume(P):
+    """|A|^2 = par[0] = 1: the stats are those of the plain integral at four
+    events per thread (the integrate-only default)."""
+    _say("user model constant = volume")
+    src = ("__device__ double hydra_phsp_user_intensity(const double* e, const double* px, const double* py, "
+           "const double* pz, const double* par) { return par[0]; }")
+    model = P.UserModel(src, 3)
+    try:
+        st, _ = model.integrate(*CFG0, 100_003, [1.0], seed=4)
+        ref = P.integrate_async(*CFG0, 100_003, seed=4)
+        torch.cuda.synchronize()
+        assert torch.equal(st, ref), (st.cpu().tolist(), ref.cpu().tolist())
+    finally:
+        model.destroy()
+
+
+def test_user_model_two_models_and_reuse(P):
+    """Two models live at once and each keeps its own code; a model is reused
+    across calls (its code object is loaded once per device)."""
+    _say("two user models")
+    a = P.UserModel(USER_BW, 3)
+    b = P.UserModel(USER_KIN, 3)
+    try:
+        for _ in range(2):
+            sa, _ = a.integrate(*CFG0, 30_000, _bw_params([(1, 2, *KSTAR)]), seed=9)
+            sb, _ = b.integrate(*CFG0, 30_000, [1.0, 2.0, 0.7], seed=9)
+            ra, _ = P.integrate_model(*CFG0, 30_000, [(1, 2, *KSTAR)], seed=9)
+            torch.cuda.synchronize()
+            assert torch.equal(sa, ra)
+            assert not torch.equal(sa, sb)
+    finally:
+        a.destroy()
+        b.destroy()

@@ -9,7 +9,8 @@
   and linked with the kernel units of the regular build; a C driver makes
   every device-facing call with an argument that validation must reject and
   runs the host-only routines (error strings, the sorting-network self-test,
-  the events-per-thread tables, the VEGAS grid refinement) on real data."""
+  the events-per-thread tables, the VEGAS grid refinement, the run-time
+  compilation of a user intensity) on real data."""
 from __future__ import annotations
 
 import concurrent.futures as cf
@@ -26,7 +27,7 @@ ORACLE_SRC = os.path.join(ROOT, "oracle", "phsp_oracle.c")
 CSRC = os.path.join(ROOT, "paper_1711_05683_amd", "csrc")
 BUILD_DIR = os.path.join(ROOT, "_build")
 API_UNITS = ("phsp_api", "phsp_batch_api", "phsp_serve", "phsp_unweight_api", "phsp_model_api",
-             "phsp_vegas_api", "phsp_probe")
+             "phsp_vegas_api", "phsp_probe", "phsp_user_model")
 LLVM = "/opt/rocm/llvm/bin"
 
 ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1:verify_asan_link_order=0",
@@ -68,7 +69,7 @@ def test_abi_host_code_under_asan_and_ubsan(tmp_path):
              "-fno-omit-frame-pointer", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
              "-Xarch_host", "-fno-sanitize-recover=all", "-Wno-unused-command-line-argument",
-             f"-I{ROOT}/include", f"-I{CSRC}"]
+             f"-I{ROOT}/include", f"-I{CSRC}", f"-I{os.path.join(BUILD_DIR, 'gen')}"]
 
     def compile_unit(name):
         obj = str(tmp_path / f"{name}.o")
@@ -82,6 +83,6 @@ def test_abi_host_code_under_asan_and_ubsan(tmp_path):
           "-fno-sanitize-recover=all", f"-I{ROOT}/include", "-c", os.path.join(SAN, "abi_host_driver.c"), "-o", drv])
     exe = str(tmp_path / "abi_sanitized")
     _run([f"{LLVM}/clang++", "-fsanitize=address,undefined", "-o", exe, drv, *api, *kernels,
-          "-L/opt/rocm/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"])
+          "-L/opt/rocm/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"])
     r = _run([exe], env=ENV, timeout=300)
     assert "sanitized abi ok" in r.stdout

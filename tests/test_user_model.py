@@ -1,0 +1,100 @@
+"""CPU tests of user intensities compiled at run time (hiprtc needs no GPU):
+compilation, the compiler's log for a bad source, and the validation of every
+argument before any device work."""
+from __future__ import annotations
+
+import ctypes
+
+import pytest
+
+BW_SOURCE = """
+// relativistic Breit-Wigner intensity in the (1, 2) pair mass: par = (mass, width)
+__device__ double hydra_phsp_user_intensity(const double* e, const double* px, const double* py,
+                                            const double* pz, const double* par) {
+    const double se = e[1] + e[2], sx = px[1] + px[2], sy = py[1] + py[2], sz = pz[1] + pz[2];
+    const double s = se * se - sx * sx - sy * sy - sz * sz;
+    const double d = par[0] * par[0] - s;
+    const double mg = par[0] * par[1];
+    return 1.0 / (d * d + mg * mg);
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1711_05683_amd as P
+    try:
+        P.lib()
+    except RuntimeError as e:
+        pytest.skip(str(e))
+    return P
+
+
+def _create(P, src, n):
+    h = ctypes.c_void_p()
+    st = P.lib().hydra_phsp_user_model_create(None if src is None else src.encode(), n, ctypes.byref(h))
+    return st, h
+
+
+def test_user_model_compiles_without_gpu(P):
+    st, h = _create(P, BW_SOURCE, 3)
+    assert st == P.OK and h.value
+    assert P.lib().hydra_phsp_user_model_daughters(h) == 3
+    assert P.lib().hydra_phsp_user_model_destroy(h) == P.OK
+
+
+@pytest.mark.parametrize("src", [
+    "this is not C++",
+    "__device__ double hydra_phsp_user_intensity(const double* e, const double* px, const double* py, "
+    "const double* pz, const double* par) { return undefined_symbol; }",
+    "__device__ double another_name(const double* e) { return e[0]; }",
+])
+def test_user_model_bad_source_is_rejected_with_the_log(P, src):
+    st, h = _create(P, src, 3)
+    assert st == P.EINVAL and not h.value
+    msg = P.lib().hydra_phsp_last_error().decode()
+    assert "user model does not compile" in msg and "error" in msg
+
+
+def test_user_model_create_validation(P):
+    for src, n in ((None, 3), (BW_SOURCE, 1), (BW_SOURCE, 11)):
+        st, h = _create(P, src, n)
+        assert st == P.EINVAL and not h.value, (src is None, n)
+    assert P.lib().hydra_phsp_user_model_create(BW_SOURCE.encode(), 3, None) == P.EINVAL
+    assert P.lib().hydra_phsp_user_model_destroy(None) == P.EINVAL
+    assert P.lib().hydra_phsp_user_model_daughters(None) == P.EINVAL
+
+
+def test_user_model_integrate_validation(P):
+    """Every bad argument is rejected before the code object is loaded or any
+    device memory is touched (fake device pointers are never dereferenced)."""
+    st, h = _create(P, BW_SOURCE, 3)
+    assert st == P.OK
+    f = P.lib().hydra_phsp_integrate_user_model
+    m = (ctypes.c_double * 3)(3.097, 0.4937, 0.13957)
+    par = (ctypes.c_double * 2)(0.8955, 0.0473)
+    stats = ctypes.c_void_p(256)
+    try:
+        assert f(None, 5.279, m, par, 2, 100, 1, 0, 0, None, stats, None) == P.EINVAL
+        assert f(h, 5.279, m, par, 17, 100, 1, 0, 0, None, stats, None) == P.EINVAL
+        assert f(h, 5.279, m, par, -1, 100, 1, 0, 0, None, stats, None) == P.EINVAL
+        assert f(h, 5.279, m, None, 2, 100, 1, 0, 0, None, stats, None) == P.EINVAL
+        assert f(h, 5.279, m, par, 2, 100, 1, 0, 0, None, None, None) == P.EINVAL
+        assert f(h, 5.279, m, par, 2, 100, 1, 0, 0, ctypes.c_void_p(4), stats, None) == P.EINVAL
+        assert f(h, 3.5, m, par, 2, 100, 1, 0, 0, None, stats, None) == P.EKINEMATICS
+        assert f(h, 5.279, None, par, 2, 100, 1, 0, 0, None, stats, None) == P.EINVAL
+    finally:
+        assert P.lib().hydra_phsp_user_model_destroy(h) == P.OK
+
+
+def test_user_model_binding_checks_daughter_count(P):
+    model = P.UserModel(BW_SOURCE, 3)
+    try:
+        with pytest.raises(ValueError):
+            model.integrate(5.279, [3.097, 0.4937], 100, [0.8955, 0.0473])
+        with pytest.raises(ValueError):
+            model.integrate(5.279, [3.097, 0.4937, 0.13957], 100, [0.0] * 17)
+    finally:
+        model.destroy()
+    with pytest.raises(P.PhspError):
+        P.UserModel("not a function", 3)

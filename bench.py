@@ -551,6 +551,27 @@ def vegas_extra(P, torch, dev):
     for calls in (10_000_000, 100_000_000):
         ms, k = time_steps(lambda: P.vegas_iteration(f, g, calls, seed=7, iteration=100), 5, 1, torch)
         r[f"iteration_{calls:.0e}_calls"] = {"kernel_ms": k, "ms": ms, "samples_per_s": calls / (k * 1e-3)}
+    # the same integrand as a user function compiled at run time (hiprtc)
+    src = """
+__device__ double hydra_phsp_user_integrand(const double* x, const double* par) {
+    double v = 1.0;
+    for (int d = 0; d < HYDRA_PHSP_DIM; ++d) {
+        const double t = (x[d] - par[0]) * par[1];
+        v = v * (exp(-0.5 * t * t) * par[2]);
+    }
+    return v;
+}
+"""
+    t0 = time.perf_counter()
+    u = P.UserIntegrand(src, D)
+    compile_s = time.perf_counter() - t0
+    par = [0.5, 1.0 / 0.1, 1.0 / (0.1 * math.sqrt(2.0 * math.pi))]
+    ms, k = time_steps(lambda: u.iteration(lo, hi, g, 100_000_000, par, seed=7, iteration=100), 5, 1, torch)
+    ru, eu, cu, _ = u.vegas(lo, hi, 10_000_000, 5, par, warmup=5, seed=42)
+    u.destroy()
+    r["user_integrand"] = {"iteration_1e+08_calls_kernel_ms": k, "samples_per_s": 1e8 / (k * 1e-3),
+                           "compile_s": compile_s, "result": ru, "error": eu, "chi2_dof": cu,
+                           "pull": (ru - exact) / eu}
     return r
 
 

@@ -67,6 +67,11 @@ enum {
  * the standard error of the mean (0 when n < 2). */
 #define HYDRA_PHSP_STATS 4
 
+/* Parameters a user function compiled at run time receives (par[0..15]): the
+ * model intensities of hydra_phsp_model.h and the VEGAS integrands of
+ * hydra_phsp_vegas.h. */
+#define HYDRA_PHSP_USER_PARAMS 16
+
 /* ------------------------------------------------------------------------ */
 /* Plain FP64 path                                                           */
 /* ------------------------------------------------------------------------ */

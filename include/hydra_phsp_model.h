@@ -65,8 +65,6 @@ int hydra_phsp_integrate_model(double parent_mass, const double *masses_host, in
  * generates each event in registers and applies the function to it (inlined),
  * so a model runs at the speed of the built-in Breit-Wigner product.
  * ------------------------------------------------------------------------- */
-#define HYDRA_PHSP_USER_PARAMS 16
-
 typedef struct hydra_phsp_user_model hydra_phsp_user_model;
 
 /* Compile `source_host` (NUL-terminated) for events of n_daughters (2..10)

@@ -3,7 +3,7 @@
  * Carlo (a second workload on the generator's counter-based random numbers and
  * fused reduction).
  *
- * The paper (arXiv:1711.05683, sec. 2 and 5.1) lists plain and self-adaptive
+ * The paper (arXiv:1711.05683, sec. 3 and 4.1) lists plain and self-adaptive
  * importance-sampling Monte Carlo integration and benchmarks VEGAS (Lepage,
  * J. Comput. Phys. 27 (1978) 192) on a 10-dimensional Gaussian; it follows the
  * structure of the GSL implementation and parallelises the integrand
@@ -72,6 +72,51 @@ int hydra_phsp_vegas_refine(int dim, int bins, double *grid_host, const double *
 int hydra_phsp_vegas(const hydra_phsp_gauss_box *f, int bins, uint64_t calls, int warmup, int iterations,
                      double alpha, uint64_t seed, double *grid_host, double *result, double *error,
                      double *chi2_dof, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * User integrands, compiled at run time (the paper's integrators take user
+ * functors, sec. 3.1; its VEGAS benchmark is the Gaussian above).  The user
+ * passes HIP device source that defines
+ *
+ *   __device__ double hydra_phsp_user_integrand(const double *x,
+ *                                               const double *par);
+ *
+ * receiving a sample's coordinates x[0..dim-1] in the box and the parameters
+ * par[0..15] (the n_params given, then zeros); the macro HYDRA_PHSP_DIM holds
+ * dim.  The library compiles it with hiprtc for gfx950 (-O3, no floating-point
+ * contraction) into the VEGAS kernel with the function inlined in place of the
+ * Gaussian product: the samples, grid, histogram, reduction and refinement are
+ * those described above, with value = f(x) times the Jacobian.
+ * ------------------------------------------------------------------------- */
+typedef struct hydra_phsp_user_integrand hydra_phsp_user_integrand;
+
+/* Compile `source_host` (NUL-terminated) for dim (1..16) dimensions;
+ * *integrand_out receives the integrand (release it with
+ * hydra_phsp_user_integrand_destroy).  Compilation needs no GPU; the code
+ * object is loaded on each device at its first use there.  EINVAL for a NULL
+ * argument, dim out of range, or a source that does not compile (the
+ * compiler's log, up to 8 KiB, is in hydra_phsp_last_error); EDEVICE when
+ * hiprtc itself fails. */
+int hydra_phsp_user_integrand_create(const char *source_host, int dim, hydra_phsp_user_integrand **integrand_out);
+
+/* Waits for the devices the integrand was loaded on, unloads it and frees it. */
+int hydra_phsp_user_integrand_destroy(hydra_phsp_user_integrand *integrand);
+
+/* As hydra_phsp_vegas_iteration for the user's integrand over the box
+ * [lo_host[d], hi_host[d]] (host, dim doubles each, hi > lo) with n_params
+ * (0..16) parameters params_host (host; NULL when n_params is 0).  EINVAL also
+ * for a NULL integrand or box, a bad box edge or n_params out of range. */
+int hydra_phsp_vegas_user_iteration(hydra_phsp_user_integrand *f, const double *lo_host, const double *hi_host,
+                                    const double *params_host, int n_params, int bins, const double *grid_dev,
+                                    uint64_t calls, uint64_t seed, uint32_t iteration, double *stats_dev,
+                                    double *hist_dev, double *values_dev, void *stream);
+
+/* As hydra_phsp_vegas (the whole integration, synchronous) for the user's
+ * integrand over the box with the given parameters. */
+int hydra_phsp_vegas_user(hydra_phsp_user_integrand *f, const double *lo_host, const double *hi_host,
+                          const double *params_host, int n_params, int bins, uint64_t calls, int warmup,
+                          int iterations, double alpha, uint64_t seed, double *grid_host, double *result,
+                          double *error, double *chi2_dof, void *stream);
 
 #ifdef __cplusplus
 }

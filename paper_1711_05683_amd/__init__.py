@@ -86,6 +86,14 @@ def _declare(lib):
     lib.hydra_phsp_vegas_refine.restype = i
     lib.hydra_phsp_vegas.argtypes = [vp, i, u64, i, i, d, u64, vp, dp, dp, dp, vp]
     lib.hydra_phsp_vegas.restype = i
+    lib.hydra_phsp_user_integrand_create.argtypes = [c.c_char_p, i, c.POINTER(vp)]
+    lib.hydra_phsp_user_integrand_create.restype = i
+    lib.hydra_phsp_user_integrand_destroy.argtypes = [vp]
+    lib.hydra_phsp_user_integrand_destroy.restype = i
+    lib.hydra_phsp_vegas_user_iteration.argtypes = [vp, dp, dp, dp, i, i, vp, u64, u64, u32, vp, vp, vp, vp]
+    lib.hydra_phsp_vegas_user_iteration.restype = i
+    lib.hydra_phsp_vegas_user.argtypes = [vp, dp, dp, dp, i, i, u64, i, i, d, u64, vp, dp, dp, dp, vp]
+    lib.hydra_phsp_vegas_user.restype = i
     lib.hydra_phsp_probe_write.argtypes = [vp, u64, i, vp, u64, i, vp]
     lib.hydra_phsp_probe_write.restype = i
     lib.hydra_phsp_probe_philox.argtypes = [u64, i, u64, u32, vp, vp]
@@ -402,6 +410,73 @@ def vegas_iteration(f: GaussBox, grid: torch.Tensor, calls: int, *, seed: int = 
     _check(lib().hydra_phsp_vegas_iteration(ctypes.byref(f), bins, _dptr(grid), calls, seed, iteration, _dptr(stats),
                                             _dptr(hist), _dptr(vals), _stream_handle(stream)))
     return stats, hist, vals
+
+
+class UserIntegrand:
+    """A VEGAS integrand compiled at run time: ``source`` is HIP device code that
+    defines ``double hydra_phsp_user_integrand(const double* x, const double* par)``
+    over ``dim`` coordinates (see include/hydra_phsp_vegas.h).  Compilation needs
+    no GPU; a source that does not compile raises PhspError with the log."""
+
+    def __init__(self, source: str, dim: int):
+        self._h = None
+        h = ctypes.c_void_p()
+        _check(lib().hydra_phsp_user_integrand_create(source.encode(), int(dim), ctypes.byref(h)))
+        self._h = h
+        self.dim = int(dim)
+
+    def _box(self, lo, hi, params):
+        if self._h is None:
+            raise ValueError("the integrand was destroyed")
+        if len(lo) != self.dim or len(hi) != self.dim:
+            raise ValueError(f"the integrand has {self.dim} dimensions")
+        if len(params) > USER_PARAMS:
+            raise ValueError(f"at most {USER_PARAMS} parameters")
+        D = ctypes.c_double
+        return ((D * self.dim)(*map(float, lo)), (D * self.dim)(*map(float, hi)),
+                (D * max(len(params), 1))(*map(float, params)))
+
+    def iteration(self, lo, hi, grid: torch.Tensor, calls: int, params=(), *, seed: int = 42, iteration: int = 0,
+                  want_hist: bool = True, want_values: bool = False, stream: Optional[torch.cuda.Stream] = None):
+        """One iteration on the device grid ([dim, bins+1] float64, asynchronous);
+        returns (stats, hist or None, values or None) as device tensors."""
+        lo_a, hi_a, par = self._box(lo, hi, params)
+        if grid.dtype != torch.float64 or not grid.is_contiguous() or grid.dim() != 2 or grid.shape[0] != self.dim:
+            raise ValueError("grid must be a contiguous [dim, bins+1] float64 tensor")
+        bins = grid.shape[1] - 1
+        dev = _resident(None, stream, grid=grid)
+        stats = torch.empty(STATS, dtype=torch.float64, device=dev)
+        hist = torch.empty((self.dim, bins), dtype=torch.float64, device=dev) if want_hist else None
+        vals = torch.empty(max(calls, 1), dtype=torch.float64, device=dev) if want_values else None
+        _check(lib().hydra_phsp_vegas_user_iteration(self._h, lo_a, hi_a, par, len(params), bins, _dptr(grid), calls,
+                                                     seed, iteration, _dptr(stats), _dptr(hist), _dptr(vals),
+                                                     _stream_handle(stream)))
+        return stats, hist, vals
+
+    def vegas(self, lo, hi, calls: int, iterations: int, params=(), *, warmup: int = 0, bins: int = 50,
+              alpha: float = 1.5, seed: int = 42, grid=None, stream: Optional[torch.cuda.Stream] = None):
+        """The whole integration (synchronous): (result, error, chi2/dof, final grid [dim, bins+1])."""
+        import numpy as np
+        lo_a, hi_a, par = self._box(lo, hi, params)
+        g = np.ascontiguousarray(grid if grid is not None else
+                                 np.tile(np.arange(bins + 1) / bins, (self.dim, 1)), dtype=np.float64)
+        res, err, chi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().hydra_phsp_vegas_user(self._h, lo_a, hi_a, par, len(params), g.shape[1] - 1, calls, warmup,
+                                           iterations, alpha, seed, g.ctypes.data_as(ctypes.c_void_p),
+                                           ctypes.byref(res), ctypes.byref(err), ctypes.byref(chi),
+                                           _stream_handle(stream)))
+        return res.value, err.value, chi.value, g
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            _check(lib().hydra_phsp_user_integrand_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def vegas_refine(grid, hist, alpha: float = 1.5):

@@ -51,6 +51,18 @@ int release_vegas_workspaces();
 int release_batch_slots();
 // The device's (cos, sin) table used by the FP64 kernels (created on first use).
 int trig_table(const double2** out);
+// Kernels compiled at run time (user intensities and integrands): hiprtc for
+// gfx950 with the library's flags against its own kernel headers (embedded at
+// build time), the code object kept and loaded on each device at its first use.
+struct RtcKernel;
+// Compile `source`; `kernel` is the kernel's extern "C" name, or (name_expr) a
+// C++ name expression whose lowered name hiprtc reports.  A source that does not
+// compile fails with EINVAL and "<what> does not compile: <log>".
+int rtc_compile(const std::string& source, const char* kernel, bool name_expr, const char* what, RtcKernel** out);
+// The kernel on the current device (loading the code object there at the first call).
+int rtc_function(RtcKernel* k, hipFunction_t* fn);
+// Waits for the devices it was loaded on, unloads and frees it.
+int rtc_destroy(RtcKernel* k);
 // Benchmark timing brackets around a kernel launch (slot -1: timing off).
 long timing_begin(hipStream_t stream);
 void timing_end(hipStream_t stream, long slot);

@@ -1,19 +1,19 @@
-// phsp_user_model.hip -- model evaluation with a user's intensity function,
-// compiled at run time for gfx950.
+// phsp_user_model.hip -- kernels compiled at run time from user code, and model
+// evaluation with a user's intensity function.
 //
 // Hydra evaluates user code passed as functors with parameters (sec. 3.1 of
 // arXiv:1711.05683) and lists model evaluation over phase space among the
-// generator's uses (sec. 4.2).  Here the user hands over HIP device source
-// defining
+// generator's uses (sec. 4.2).  Here the user hands over HIP device source; the
+// library compiles it with hiprtc for gfx950, with its own compiler flags,
+// together with the generator's kernel headers (embedded in the library at
+// build time), into one kernel in which the user's function is inlined where
+// the built-in one would be.  The code object is compiled once and loaded on
+// each device at its first use there.  For model evaluation the source defines
 //   double hydra_phsp_user_intensity(const double* e, const double* px,
 //                                    const double* py, const double* pz,
 //                                    const double* par)
-// for N daughters; the library compiles it with hiprtc together with the
-// generator's own kernel headers (embedded in the library) into one kernel
-// that generates each event in registers and applies the function to it, so
-// the user's code is inlined into the event loop exactly like the built-in
-// Breit-Wigner model.  The code object is compiled once per model and loaded
-// on each device at its first use there.
+// over the N daughters' four-momenta; the VEGAS integrands of
+// phsp_vegas_api.hip use the same machinery.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
@@ -29,6 +29,7 @@
 #include "phsp_model.hpp"
 
 namespace hphsp {
+
 namespace {
 
 #include "phsp_rtc_sources.inc"
@@ -41,15 +42,129 @@ const char* const kRtcRuntimeStub =
     "typedef int hipError_t;\n"
     "typedef struct ihipStream_t* hipStream_t;\n";
 
+constexpr int kMaxDevices = 64;
+constexpr size_t kMaxLogBytes = 8192;
+
+} // namespace
+
+struct RtcKernel {
+    std::vector<char> code; // gfx950 code object
+    std::string symbol;     // the kernel's (lowered) name in it
+    std::mutex mu;
+    hipModule_t module[kMaxDevices] = {};
+    hipFunction_t fn[kMaxDevices] = {};
+};
+
+int rtc_compile(const std::string& source, const char* kernel, bool name_expr, const char* what, RtcKernel** out) {
+    *out = nullptr;
+    std::vector<const char*> names, texts;
+    names.push_back("hip/hip_runtime.h");
+    texts.push_back(kRtcRuntimeStub);
+    for (int i = 0; i < kRtcHeaders; ++i) {
+        names.push_back(kRtcHeaderNames[i]);
+        texts.push_back(kRtcHeaderSources[i]);
+    }
+    hiprtcProgram prog = nullptr;
+    hiprtcResult r = hiprtcCreateProgram(&prog, source.c_str(), "user.hip", (int)names.size(), texts.data(),
+                                         names.data());
+    if (r != HIPRTC_SUCCESS)
+        return fail(HYDRA_PHSP_EDEVICE, std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r));
+    if (name_expr) {
+        r = hiprtcAddNameExpression(prog, kernel);
+        if (r != HIPRTC_SUCCESS) {
+            (void)hiprtcDestroyProgram(&prog);
+            return fail(HYDRA_PHSP_EDEVICE, std::string("hiprtcAddNameExpression: ") + hiprtcGetErrorString(r));
+        }
+    }
+    // the library's own flags: gfx950, no contraction (explicit fma only), no
+    // packed FP32
+    const char* opts[] = {"--offload-arch=gfx950", "-O3",     "-std=c++17",      "-ffp-contract=off",
+                          "-Xclang",               "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+    if (r != HIPRTC_SUCCESS) {
+        size_t n = 0;
+        std::string log;
+        if (hiprtcGetProgramLogSize(prog, &n) == HIPRTC_SUCCESS && n > 0) {
+            log.resize(n);
+            if (hiprtcGetProgramLog(prog, &log[0]) != HIPRTC_SUCCESS) log.clear();
+            if (log.size() > kMaxLogBytes) log.resize(kMaxLogBytes);
+        }
+        (void)hiprtcDestroyProgram(&prog);
+        if (r == HIPRTC_ERROR_COMPILATION || r == HIPRTC_ERROR_LINKING)
+            return fail(HYDRA_PHSP_EINVAL, std::string(what) + " does not compile: " + log);
+        return fail(HYDRA_PHSP_EDEVICE, std::string("hiprtcCompileProgram: ") + hiprtcGetErrorString(r));
+    }
+    auto* k = new RtcKernel();
+    k->symbol = kernel;
+    if (name_expr) {
+        const char* lowered = nullptr;
+        r = hiprtcGetLoweredName(prog, kernel, &lowered);
+        if (r != HIPRTC_SUCCESS || lowered == nullptr) {
+            (void)hiprtcDestroyProgram(&prog);
+            delete k;
+            return fail(HYDRA_PHSP_EDEVICE, "hiprtcGetLoweredName failed");
+        }
+        k->symbol = lowered;
+    }
+    size_t size = 0;
+    r = hiprtcGetCodeSize(prog, &size);
+    if (r == HIPRTC_SUCCESS && size > 0) {
+        k->code.resize(size);
+        r = hiprtcGetCode(prog, k->code.data());
+    }
+    (void)hiprtcDestroyProgram(&prog);
+    if (r != HIPRTC_SUCCESS || size == 0) {
+        delete k;
+        return fail(HYDRA_PHSP_EDEVICE, "hiprtc produced no code object");
+    }
+    *out = k;
+    return HYDRA_PHSP_OK;
+}
+
+int rtc_function(RtcKernel* k, hipFunction_t* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(HYDRA_PHSP_EINVAL, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lock(k->mu);
+    if (k->fn[dev] == nullptr) {
+        e = hipModuleLoadData(&k->module[dev], k->code.data());
+        if (e != hipSuccess) return fail_hip(e, "hipModuleLoadData(run-time kernel)");
+        e = hipModuleGetFunction(&k->fn[dev], k->module[dev], k->symbol.c_str());
+        if (e != hipSuccess) {
+            (void)hipModuleUnload(k->module[dev]);
+            k->module[dev] = nullptr;
+            return fail_hip(e, "hipModuleGetFunction(run-time kernel)");
+        }
+    }
+    *out = k->fn[dev];
+    return HYDRA_PHSP_OK;
+}
+
+int rtc_destroy(RtcKernel* k) {
+    int st = HYDRA_PHSP_OK;
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    for (int d = 0; d < kMaxDevices; ++d) {
+        if (k->module[d] == nullptr) continue;
+        // the module's kernels may still be queued: wait for the device first
+        if (hipSetDevice(d) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+            hipModuleUnload(k->module[d]) != hipSuccess)
+            st = fail(HYDRA_PHSP_EDEVICE, "run-time kernel unload failed");
+    }
+    if (have_cur) (void)hipSetDevice(cur);
+    delete k;
+    return st;
+}
+
+namespace {
+
 // Kernel arguments after the model's: the user's parameters, by value.
 struct UserParams {
     double p[HYDRA_PHSP_USER_PARAMS];
 };
 
-constexpr int kMaxDevices = 64;
-constexpr size_t kMaxLogBytes = 8192;
-
-std::string kernel_source(const char* user, int n) {
+std::string model_source(const char* user, int n) {
     std::string s;
     s += "#define HYDRA_PHSP_N " + std::to_string(n) + "\n";
     s += "#include \"phsp_model.hpp\"\n";
@@ -77,39 +192,8 @@ using namespace hphsp;
 
 struct hydra_phsp_user_model {
     int n = 0;
-    std::vector<char> code; // gfx950 code object
-    std::mutex mu;
-    hipModule_t module[hphsp::kMaxDevices] = {};
-    hipFunction_t fn[hphsp::kMaxDevices] = {};
+    RtcKernel* kernel = nullptr;
 };
-
-namespace hphsp {
-namespace {
-
-// The model's kernel on the current device, loading its code object there at
-// the first call.
-int user_kernel(hydra_phsp_user_model* um, hipFunction_t* out) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
-    if (dev < 0 || dev >= kMaxDevices) return fail(HYDRA_PHSP_EINVAL, "device index beyond the library's table");
-    std::lock_guard<std::mutex> lock(um->mu);
-    if (um->fn[dev] == nullptr) {
-        e = hipModuleLoadData(&um->module[dev], um->code.data());
-        if (e != hipSuccess) return fail_hip(e, "hipModuleLoadData(user model)");
-        e = hipModuleGetFunction(&um->fn[dev], um->module[dev], "hydra_phsp_user_model_kernel");
-        if (e != hipSuccess) {
-            (void)hipModuleUnload(um->module[dev]);
-            um->module[dev] = nullptr;
-            return fail_hip(e, "hipModuleGetFunction(user model)");
-        }
-    }
-    *out = um->fn[dev];
-    return HYDRA_PHSP_OK;
-}
-
-} // namespace
-} // namespace hphsp
 
 extern "C" int hydra_phsp_user_model_create(const char* source_host, int n_daughters,
                                             hydra_phsp_user_model** model_out) {
@@ -117,67 +201,20 @@ extern "C" int hydra_phsp_user_model_create(const char* source_host, int n_daugh
     *model_out = nullptr;
     if (source_host == nullptr) return fail(HYDRA_PHSP_EINVAL, "source_host is NULL");
     if (n_daughters < 2 || n_daughters > kNMax) return fail(HYDRA_PHSP_EINVAL, "n_daughters must be in [2, 10]");
-    const std::string src = kernel_source(source_host, n_daughters);
-    std::vector<const char*> names, texts;
-    names.push_back("hip/hip_runtime.h");
-    texts.push_back(kRtcRuntimeStub);
-    for (int i = 0; i < kRtcHeaders; ++i) {
-        names.push_back(kRtcHeaderNames[i]);
-        texts.push_back(kRtcHeaderSources[i]);
-    }
-    hiprtcProgram prog = nullptr;
-    hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "user_model.hip", (int)names.size(), texts.data(),
-                                         names.data());
-    if (r != HIPRTC_SUCCESS)
-        return fail(HYDRA_PHSP_EDEVICE, std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r));
-    // the library's own flags: gfx950, no contraction (explicit fma only), no
-    // packed FP32
-    const char* opts[] = {"--offload-arch=gfx950", "-O3",     "-std=c++17",      "-ffp-contract=off",
-                          "-Xclang",               "-target-feature", "-Xclang", "-packed-fp32-ops"};
-    r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
-    if (r != HIPRTC_SUCCESS) {
-        size_t n = 0;
-        std::string log;
-        if (hiprtcGetProgramLogSize(prog, &n) == HIPRTC_SUCCESS && n > 0) {
-            log.resize(n);
-            if (hiprtcGetProgramLog(prog, &log[0]) != HIPRTC_SUCCESS) log.clear();
-            if (log.size() > kMaxLogBytes) log.resize(kMaxLogBytes);
-        }
-        (void)hiprtcDestroyProgram(&prog);
-        if (r == HIPRTC_ERROR_COMPILATION)
-            return fail(HYDRA_PHSP_EINVAL, "user model does not compile: " + log);
-        return fail(HYDRA_PHSP_EDEVICE, std::string("hiprtcCompileProgram: ") + hiprtcGetErrorString(r));
-    }
-    size_t size = 0;
-    r = hiprtcGetCodeSize(prog, &size);
+    RtcKernel* k = nullptr;
+    const int st = rtc_compile(model_source(source_host, n_daughters), "hydra_phsp_user_model_kernel", false,
+                               "user model", &k);
+    if (st != HYDRA_PHSP_OK) return st;
     auto* um = new hydra_phsp_user_model();
     um->n = n_daughters;
-    if (r == HIPRTC_SUCCESS && size > 0) {
-        um->code.resize(size);
-        r = hiprtcGetCode(prog, um->code.data());
-    }
-    (void)hiprtcDestroyProgram(&prog);
-    if (r != HIPRTC_SUCCESS || size == 0) {
-        delete um;
-        return fail(HYDRA_PHSP_EDEVICE, "hiprtc produced no code object");
-    }
+    um->kernel = k;
     *model_out = um;
     return HYDRA_PHSP_OK;
 }
 
 extern "C" int hydra_phsp_user_model_destroy(hydra_phsp_user_model* model) {
     if (model == nullptr) return fail(HYDRA_PHSP_EINVAL, "model is NULL");
-    int st = HYDRA_PHSP_OK;
-    int cur = 0;
-    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
-    for (int d = 0; d < kMaxDevices; ++d) {
-        if (model->module[d] == nullptr) continue;
-        // the module's kernels may still be queued: wait for the device first
-        if (hipSetDevice(d) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
-            hipModuleUnload(model->module[d]) != hipSuccess)
-            st = fail(HYDRA_PHSP_EDEVICE, "user model unload failed");
-    }
-    if (have_cur) (void)hipSetDevice(cur);
+    const int st = rtc_destroy(model->kernel);
     delete model;
     return st;
 }
@@ -210,7 +247,7 @@ extern "C" int hydra_phsp_integrate_user_model(hydra_phsp_user_model* model, dou
     if (blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
         return fail(HYDRA_PHSP_EINVAL, "nevents too large for one launch (more than 2^32 - 1 threads)");
     hipFunction_t fn = nullptr;
-    st = user_kernel(model, &fn);
+    st = rtc_function(model->kernel, &fn);
     if (st != HYDRA_PHSP_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     Moments* partials = nullptr;

@@ -3,7 +3,7 @@
 //
 // Integrand: f(x) = prod_d exp(-(x_d - mu_d)^2 / (2 s_d^2)) / (s_d sqrt(2 pi))
 // over the box prod_d [lo_d, hi_d] (the paper's VEGAS benchmark integrates a
-// 10-dimensional Gaussian).  Sample i of iteration t takes uniform d from words
+// 10-dimensional Gaussian), or a user's function of x compiled at run time.  Sample i of iteration t takes uniform d from words
 // 2d, 2d+1 of the Philox stream with counter (i lo, i hi, call, t) under the
 // seed; with z = K u, bin b = floor(z) and y = g[b] + (z - b)(g[b+1] - g[b]),
 // x_d = lo_d + y (hi_d - lo_d), and the sample's value is f(x) times the
@@ -35,13 +35,34 @@ struct VegasArgs {
     uint64_t calls;
     double lo[kVegasDMax], width[kVegasDMax], mu[kVegasDMax]; // width = hi - lo
     double inv_sigma[kVegasDMax], norm[kVegasDMax];           // 1 / s_d and 1 / (s_d sqrt(2 pi)), from the host
+    double upar[16];             // a user integrand's parameters (HYDRA_PHSP_USER_PARAMS of them)
     const double* grid;          // [D][bins + 1]
     Moments* partials;           // [blocks]
     double* hist_partials;       // NULL, or [blocks][D][bins]
     double* values;              // NULL, or [calls]
 };
 
-template <int D>
+// The built-in integrand: each dimension's Gaussian factor and Jacobian are
+// multiplied into the value as the dimension's coordinate is made.
+// (The launch arguments come with every call rather than being held, so the
+// compiler reads them where they are used, as in a plain loop.)
+struct GaussIntegrand {
+    double val = 1.0;
+    __device__ __forceinline__ void dim(const VegasArgs& v, int d, double x, double jac) {
+        const double t = (x - v.mu[d]) * v.inv_sigma[d];
+        const double f = exp(-0.5 * t * t) * v.norm[d];
+        val = val * f * jac;
+    }
+    __device__ __forceinline__ double value(const VegasArgs&) const { return val; }
+};
+
+// A VEGAS iteration with integrand type F: for every sample a block owns, a
+// fresh F receives each dimension's coordinate x_d and Jacobian
+// K (g[b+1] - g[b]) (hi_d - lo_d) in dimension order (dim), then gives the
+// sample's value (value); the histogram and the reduction follow.  F is the
+// Gaussian product above, or a user's integrand compiled at run time
+// (phsp_user_model.hip).
+template <int D, class F = GaussIntegrand>
 __global__ __launch_bounds__(kVegasBlock) void k_vegas(const VegasArgs v) {
     extern __shared__ double vegas_lds[]; // grid [D][bins+1], then kVegasWaves tables [D][bins]
     const int K = v.bins;
@@ -64,7 +85,7 @@ __global__ __launch_bounds__(kVegasBlock) void k_vegas(const VegasArgs v) {
             double u[D + (D & 1)];
 #pragma unroll
             for (int j = 0; 2 * j < D; ++j) rng.call((uint32_t)j, u[2 * j], u[2 * j + 1]);
-            double val = 1.0;
+            F f;
             int b[D];
 #pragma unroll
             for (int d = 0; d < D; ++d) {
@@ -75,11 +96,10 @@ __global__ __launch_bounds__(kVegasBlock) void k_vegas(const VegasArgs v) {
                 const double w = gd[bb + 1] - gd[bb];
                 const double y = gd[bb] + (z - (double)bb) * w;
                 const double x = v.lo[d] + y * v.width[d];
-                const double t = (x - v.mu[d]) * v.inv_sigma[d];
-                const double f = exp(-0.5 * t * t) * v.norm[d];
-                val = val * f * ((double)K * w * v.width[d]);
+                f.dim(v, d, x, (double)K * w * v.width[d]);
                 b[d] = bb;
             }
+            const double val = f.value(v);
             if (v.values != nullptr) __builtin_nontemporal_store(val, v.values + i);
             if (hist) {
                 const double v2 = val * val;
@@ -109,6 +129,7 @@ __global__ __launch_bounds__(kVegasBlock) void k_vegas(const VegasArgs v) {
         }
     }
 }
+
 
 struct VegasLaunch {
     VegasArgs v;

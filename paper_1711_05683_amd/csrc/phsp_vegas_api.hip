@@ -6,6 +6,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -15,6 +16,9 @@
 #include "phsp_vegas.hpp"
 
 namespace hphsp {
+
+static_assert(sizeof(VegasArgs::upar) / sizeof(double) == HYDRA_PHSP_USER_PARAMS,
+              "a user integrand's parameters travel in VegasArgs::upar");
 
 // Histogram sum over the per-block tables in two fixed-order stages: group g
 // (blockIdx.y) sums the tables of blocks [g * kHistGroup, (g + 1) * kHistGroup)
@@ -137,6 +141,28 @@ int check_box(const hydra_phsp_gauss_box* f, int bins) {
     return HYDRA_PHSP_OK;
 }
 
+// The integrand of an iteration: the box, and either the built-in Gaussian
+// product (gauss) or a kernel compiled at run time from a user's function
+// (user, with its parameters).
+struct VegasIntegrand {
+    int dim = 0;
+    double lo[kVegasDMax] = {}, hi[kVegasDMax] = {};
+    const hydra_phsp_gauss_box* gauss = nullptr;
+    RtcKernel* user = nullptr;
+    double upar[HYDRA_PHSP_USER_PARAMS] = {};
+};
+
+VegasIntegrand gauss_integrand(const hydra_phsp_gauss_box* f) {
+    VegasIntegrand g;
+    g.dim = f->dim;
+    for (int d = 0; d < f->dim; ++d) {
+        g.lo[d] = f->lo[d];
+        g.hi[d] = f->hi[d];
+    }
+    g.gauss = f;
+    return g;
+}
+
 // Refinement of one dimension's edges from its value^2 histogram h (see the
 // header): smoothing, damped importance, equal-importance re-cut.
 void refine_dim(int K, double* g, const double* h, double alpha) {
@@ -181,9 +207,14 @@ void refine_dim(int K, double* g, const double* h, double alpha) {
     for (int e = 0; e <= K; ++e) g[e] = cut[e];
 }
 
-int vegas_iteration(const hydra_phsp_gauss_box* f, int bins, const double* grid_dev, uint64_t calls, uint64_t seed,
+int vegas_iteration(const VegasIntegrand& f, int bins, const double* grid_dev, uint64_t calls, uint64_t seed,
                     uint32_t iteration, double* stats_dev, double* hist_dev, double* values_dev, hipStream_t s) {
-    const int D = f->dim;
+    const int D = f.dim;
+    hipFunction_t user_fn = nullptr;
+    if (f.user != nullptr) {
+        const int ust = rtc_function(f.user, &user_fn);
+        if (ust != HYDRA_PHSP_OK) return ust;
+    }
     const uint64_t span = (uint64_t)kVegasBlock * (uint64_t)kVegasEpt;
     const uint64_t blocks = ceil_div(calls, span);
     if (blocks > 0xFFFFFFFFull / (uint64_t)kVegasBlock)
@@ -204,12 +235,15 @@ int vegas_iteration(const hydra_phsp_gauss_box* f, int bins, const double* grid_
     L.v.iteration = iteration;
     L.v.calls = calls;
     for (int d = 0; d < D; ++d) {
-        L.v.lo[d] = f->lo[d];
-        L.v.width[d] = f->hi[d] - f->lo[d];
-        L.v.mu[d] = f->mean[d];
-        L.v.inv_sigma[d] = 1.0 / f->sigma[d];
-        L.v.norm[d] = 1.0 / (f->sigma[d] * 2.5066282746310002); // sqrt(2 pi)
+        L.v.lo[d] = f.lo[d];
+        L.v.width[d] = f.hi[d] - f.lo[d];
+        if (f.gauss != nullptr) {
+            L.v.mu[d] = f.gauss->mean[d];
+            L.v.inv_sigma[d] = 1.0 / f.gauss->sigma[d];
+            L.v.norm[d] = 1.0 / (f.gauss->sigma[d] * 2.5066282746310002); // sqrt(2 pi)
+        }
     }
+    for (int k = 0; k < HYDRA_PHSP_USER_PARAMS; ++k) L.v.upar[k] = f.upar[k];
     L.v.grid = grid_dev;
     L.v.partials = partials;
     L.v.hist_partials = hist_dev ? ws->hist_partials : nullptr;
@@ -218,7 +252,14 @@ int vegas_iteration(const hydra_phsp_gauss_box* f, int bins, const double* grid_
     L.lds_bytes = sizeof(double) * ((size_t)D * (bins + 1) + (hist_dev ? (size_t)kVegasWaves * D * bins : 0));
     if (blocks > 0) {
         const long slot = timing_begin(s);
-        hipError_t e = launch_vegas(D, L, s);
+        hipError_t e = hipSuccess;
+        if (user_fn != nullptr) {
+            void* args[] = {&L.v};
+            e = hipModuleLaunchKernel(user_fn, (unsigned)L.blocks, 1, 1, kVegasBlock, 1, 1, (unsigned)L.lds_bytes, s,
+                                      args, nullptr);
+        } else {
+            e = launch_vegas(D, L, s);
+        }
         timing_end(s, slot);
         if (e != hipSuccess) return fail_hip(e, "VEGAS kernel launch");
         if (hist_dev) {
@@ -252,48 +293,63 @@ int release_vegas_workspaces() {
 
 using namespace hphsp;
 
-extern "C" {
+struct hydra_phsp_user_integrand {
+    int dim = 0;
+    RtcKernel* kernel = nullptr;
+};
 
-int hydra_phsp_vegas_iteration(const hydra_phsp_gauss_box* f, int bins, const double* grid_dev, uint64_t calls,
-                               uint64_t seed, uint32_t iteration, double* stats_dev, double* hist_dev,
-                               double* values_dev, void* stream) {
-    MarkerRange marker("hydra_phsp_vegas_iteration");
-    int st = check_box(f, bins);
-    if (st != HYDRA_PHSP_OK) return st;
+namespace hphsp {
+namespace {
+
+int check_user(const hydra_phsp_user_integrand* f, const double* lo, const double* hi, const double* params,
+               int n_params, int bins) {
+    if (f == nullptr) return fail(HYDRA_PHSP_EINVAL, "integrand is NULL");
+    if (bins < 2 || bins > HYDRA_PHSP_VEGAS_KMAX) return fail(HYDRA_PHSP_EINVAL, "bins must be in [2, 128]");
+    if (lo == nullptr || hi == nullptr) return fail(HYDRA_PHSP_EINVAL, "lo_host and hi_host are required");
+    for (int d = 0; d < f->dim; ++d)
+        if (!std::isfinite(lo[d]) || !std::isfinite(hi[d]) || !(hi[d] > lo[d]))
+            return fail(HYDRA_PHSP_EINVAL, "each box edge must be finite with hi > lo");
+    if (n_params < 0 || n_params > HYDRA_PHSP_USER_PARAMS)
+        return fail(HYDRA_PHSP_EINVAL, "n_params must be in [0, HYDRA_PHSP_USER_PARAMS]");
+    if (n_params > 0 && params == nullptr) return fail(HYDRA_PHSP_EINVAL, "params_host is NULL");
+    return HYDRA_PHSP_OK;
+}
+
+VegasIntegrand user_integrand(const hydra_phsp_user_integrand* f, const double* lo, const double* hi,
+                              const double* params, int n_params) {
+    VegasIntegrand g;
+    g.dim = f->dim;
+    for (int d = 0; d < f->dim; ++d) {
+        g.lo[d] = lo[d];
+        g.hi[d] = hi[d];
+    }
+    g.user = f->kernel;
+    for (int k = 0; k < n_params; ++k) g.upar[k] = params[k];
+    return g;
+}
+
+int check_iteration_buffers(const double* grid_dev, uint64_t calls, const double* stats_dev, const double* hist_dev,
+                            const double* values_dev) {
     if (grid_dev == nullptr || stats_dev == nullptr) return fail(HYDRA_PHSP_EINVAL, "grid_dev and stats_dev are required");
     if (calls < 2) return fail(HYDRA_PHSP_EINVAL, "need calls >= 2 (the error estimate needs two samples)");
     if ((uintptr_t)grid_dev % 8 || (uintptr_t)stats_dev % 8 || (uintptr_t)hist_dev % 8 || (uintptr_t)values_dev % 8)
         return fail(HYDRA_PHSP_EINVAL, "device pointers must be 8-byte aligned");
-    return vegas_iteration(f, bins, grid_dev, calls, seed, iteration, stats_dev, hist_dev, values_dev,
-                           (hipStream_t)stream);
-}
-
-int hydra_phsp_vegas_refine(int dim, int bins, double* grid_host, const double* hist_host, double alpha) {
-    if (dim < 1 || dim > HYDRA_PHSP_VEGAS_DMAX || bins < 2 || bins > HYDRA_PHSP_VEGAS_KMAX)
-        return fail(HYDRA_PHSP_EINVAL, "dim must be in [1, 16] and bins in [2, 128]");
-    if (grid_host == nullptr || hist_host == nullptr) return fail(HYDRA_PHSP_EINVAL, "grid and histogram are required");
-    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(HYDRA_PHSP_EINVAL, "alpha must be finite and >= 0");
-    for (int d = 0; d < dim; ++d) refine_dim(bins, grid_host + (size_t)d * (bins + 1), hist_host + (size_t)d * bins, alpha);
     return HYDRA_PHSP_OK;
 }
 
-int hydra_phsp_vegas(const hydra_phsp_gauss_box* f, int bins, uint64_t calls, int warmup, int iterations,
-                     double alpha, uint64_t seed, double* grid_host, double* result, double* error,
-                     double* chi2_dof, void* stream) {
-    MarkerRange marker("hydra_phsp_vegas");
-    int st = check_box(f, bins);
-    if (st != HYDRA_PHSP_OK) return st;
+// The whole integration (see hydra_phsp_vegas), for either kind of integrand.
+int vegas_run(const VegasIntegrand& f, int bins, uint64_t calls, int warmup, int iterations, double alpha,
+              uint64_t seed, double* grid_host, double* result, double* error, double* chi2_dof, hipStream_t s) {
     if (calls < 2 || warmup < 0 || iterations < 1) return fail(HYDRA_PHSP_EINVAL, "need calls >= 2 and iterations >= 1");
     if (result == nullptr || error == nullptr || chi2_dof == nullptr)
         return fail(HYDRA_PHSP_EINVAL, "result, error and chi2_dof are required");
     if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(HYDRA_PHSP_EINVAL, "alpha must be finite and >= 0");
-    hipStream_t s = (hipStream_t)stream;
-    const int D = f->dim, K = bins;
+    const int D = f.dim, K = bins;
     std::vector<double> grid((size_t)D * (K + 1));
     for (int d = 0; d < D; ++d)
         for (int k = 0; k <= K; ++k) grid[(size_t)d * (K + 1) + k] = grid_host ? grid_host[(size_t)d * (K + 1) + k] : (double)k / K;
     VegasWorkspace* ws = nullptr;
-    st = vegas_workspace(s, 0, &ws);
+    int st = vegas_workspace(s, 0, &ws);
     if (st != HYDRA_PHSP_OK) return st;
     std::vector<std::pair<double, double>> est; // (mean, 1/sigma^2) of the estimating iterations
     for (int t = 0; t < warmup + iterations; ++t) {
@@ -326,6 +382,116 @@ int hydra_phsp_vegas(const hydra_phsp_gauss_box* f, int bins, uint64_t calls, in
     if (grid_host)
         for (size_t i = 0; i < grid.size(); ++i) grid_host[i] = grid[i];
     return HYDRA_PHSP_OK;
+}
+
+std::string integrand_source(const char* user, int dim) {
+    std::string s;
+    s += "#define HYDRA_PHSP_DIM " + std::to_string(dim) + "\n";
+    s += "#include \"phsp_vegas.hpp\"\n";
+    // the user's function is inlined into the sample loop (x is the sample's
+    // coordinates in registers)
+    s += "__device__ __attribute__((always_inline)) double hydra_phsp_user_integrand(const double* x, "
+         "const double* par);\n";
+    s += "#line 1 \"user_integrand\"\n";
+    s += user;
+    s += "\n#line 1 \"user_integrand_kernel\"\n";
+    // the integrand type of the VEGAS kernel: coordinates and Jacobian per
+    // dimension, then the user's function times the Jacobian
+    s += "struct hydra_phsp_user_integrand_f {\n"
+         "    double x[HYDRA_PHSP_DIM];\n"
+         "    double jac = 1.0;\n"
+         "    __device__ __forceinline__ void dim(const hphsp::VegasArgs&, int d, double xd, double j) {\n"
+         "        x[d] = xd;\n"
+         "        jac = jac * j;\n"
+         "    }\n"
+         "    __device__ __forceinline__ double value(const hphsp::VegasArgs& v) const {\n"
+         "        return hydra_phsp_user_integrand(x, v.upar) * jac;\n"
+         "    }\n"
+         "};\n";
+    return s;
+}
+
+} // namespace
+} // namespace hphsp
+
+extern "C" {
+
+int hydra_phsp_vegas_iteration(const hydra_phsp_gauss_box* f, int bins, const double* grid_dev, uint64_t calls,
+                               uint64_t seed, uint32_t iteration, double* stats_dev, double* hist_dev,
+                               double* values_dev, void* stream) {
+    MarkerRange marker("hydra_phsp_vegas_iteration");
+    int st = check_box(f, bins);
+    if (st != HYDRA_PHSP_OK) return st;
+    st = check_iteration_buffers(grid_dev, calls, stats_dev, hist_dev, values_dev);
+    if (st != HYDRA_PHSP_OK) return st;
+    return vegas_iteration(gauss_integrand(f), bins, grid_dev, calls, seed, iteration, stats_dev, hist_dev, values_dev,
+                           (hipStream_t)stream);
+}
+
+int hydra_phsp_vegas_refine(int dim, int bins, double* grid_host, const double* hist_host, double alpha) {
+    if (dim < 1 || dim > HYDRA_PHSP_VEGAS_DMAX || bins < 2 || bins > HYDRA_PHSP_VEGAS_KMAX)
+        return fail(HYDRA_PHSP_EINVAL, "dim must be in [1, 16] and bins in [2, 128]");
+    if (grid_host == nullptr || hist_host == nullptr) return fail(HYDRA_PHSP_EINVAL, "grid and histogram are required");
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(HYDRA_PHSP_EINVAL, "alpha must be finite and >= 0");
+    for (int d = 0; d < dim; ++d) refine_dim(bins, grid_host + (size_t)d * (bins + 1), hist_host + (size_t)d * bins, alpha);
+    return HYDRA_PHSP_OK;
+}
+
+int hydra_phsp_vegas(const hydra_phsp_gauss_box* f, int bins, uint64_t calls, int warmup, int iterations,
+                     double alpha, uint64_t seed, double* grid_host, double* result, double* error,
+                     double* chi2_dof, void* stream) {
+    MarkerRange marker("hydra_phsp_vegas");
+    const int st = check_box(f, bins);
+    if (st != HYDRA_PHSP_OK) return st;
+    return vegas_run(gauss_integrand(f), bins, calls, warmup, iterations, alpha, seed, grid_host, result, error,
+                     chi2_dof, (hipStream_t)stream);
+}
+
+int hydra_phsp_user_integrand_create(const char* source_host, int dim, hydra_phsp_user_integrand** integrand_out) {
+    if (integrand_out == nullptr) return fail(HYDRA_PHSP_EINVAL, "integrand_out is NULL");
+    *integrand_out = nullptr;
+    if (source_host == nullptr) return fail(HYDRA_PHSP_EINVAL, "source_host is NULL");
+    if (dim < 1 || dim > HYDRA_PHSP_VEGAS_DMAX) return fail(HYDRA_PHSP_EINVAL, "dim must be in [1, 16]");
+    const std::string kernel = "hphsp::k_vegas<" + std::to_string(dim) + ", hydra_phsp_user_integrand_f>";
+    RtcKernel* k = nullptr;
+    const int st = rtc_compile(integrand_source(source_host, dim), kernel.c_str(), true, "user integrand", &k);
+    if (st != HYDRA_PHSP_OK) return st;
+    auto* f = new hydra_phsp_user_integrand();
+    f->dim = dim;
+    f->kernel = k;
+    *integrand_out = f;
+    return HYDRA_PHSP_OK;
+}
+
+int hydra_phsp_user_integrand_destroy(hydra_phsp_user_integrand* integrand) {
+    if (integrand == nullptr) return fail(HYDRA_PHSP_EINVAL, "integrand is NULL");
+    const int st = rtc_destroy(integrand->kernel);
+    delete integrand;
+    return st;
+}
+
+int hydra_phsp_vegas_user_iteration(hydra_phsp_user_integrand* f, const double* lo_host, const double* hi_host,
+                                    const double* params_host, int n_params, int bins, const double* grid_dev,
+                                    uint64_t calls, uint64_t seed, uint32_t iteration, double* stats_dev,
+                                    double* hist_dev, double* values_dev, void* stream) {
+    MarkerRange marker("hydra_phsp_vegas_user_iteration");
+    int st = check_user(f, lo_host, hi_host, params_host, n_params, bins);
+    if (st != HYDRA_PHSP_OK) return st;
+    st = check_iteration_buffers(grid_dev, calls, stats_dev, hist_dev, values_dev);
+    if (st != HYDRA_PHSP_OK) return st;
+    return vegas_iteration(user_integrand(f, lo_host, hi_host, params_host, n_params), bins, grid_dev, calls, seed,
+                           iteration, stats_dev, hist_dev, values_dev, (hipStream_t)stream);
+}
+
+int hydra_phsp_vegas_user(hydra_phsp_user_integrand* f, const double* lo_host, const double* hi_host,
+                          const double* params_host, int n_params, int bins, uint64_t calls, int warmup,
+                          int iterations, double alpha, uint64_t seed, double* grid_host, double* result,
+                          double* error, double* chi2_dof, void* stream) {
+    MarkerRange marker("hydra_phsp_vegas_user");
+    const int st = check_user(f, lo_host, hi_host, params_host, n_params, bins);
+    if (st != HYDRA_PHSP_OK) return st;
+    return vegas_run(user_integrand(f, lo_host, hi_host, params_host, n_params), bins, calls, warmup, iterations,
+                     alpha, seed, grid_host, result, error, chi2_dof, (hipStream_t)stream);
 }
 
 } // extern "C"

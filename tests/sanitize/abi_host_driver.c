@@ -271,6 +271,29 @@ static void user_models(void)
     expect(strstr(hydra_phsp_last_error(), "does not compile") != NULL, "compiler log");
     expect(hydra_phsp_user_model_create(good, 11, &bad) == HYDRA_PHSP_EINVAL, "user model daughters range");
     expect(hydra_phsp_user_model_destroy(NULL) == HYDRA_PHSP_EINVAL, "destroy of no model");
+
+    static const char integrand[] =
+        "__device__ double hydra_phsp_user_integrand(const double* x, const double* par)\n"
+        "{ return x[0] * x[HYDRA_PHSP_DIM - 1] + par[0]; }\n";
+    hydra_phsp_user_integrand *ui = NULL;
+    expect(hydra_phsp_user_integrand_create(integrand, 3, &ui) == HYDRA_PHSP_OK && ui != NULL,
+           "user integrand compiles");
+    const double lo[3] = { 0.0, 0.0, -1.0 }, hi[3] = { 1.0, 2.0, 1.0 }, bad_hi[3] = { 1.0, 0.0, 1.0 };
+    double r = 0.0, e = 0.0, c = 0.0;
+    expect(hydra_phsp_vegas_user_iteration(ui, lo, bad_hi, par, 1, 10, FAKE(double, 0x100), 100, 1, 0,
+                                           FAKE(double, 0x200), NULL, NULL, NULL) == HYDRA_PHSP_EINVAL, "bad box");
+    expect(hydra_phsp_vegas_user_iteration(ui, lo, hi, par, HYDRA_PHSP_USER_PARAMS + 1, 10, FAKE(double, 0x100),
+                                           100, 1, 0, FAKE(double, 0x200), NULL, NULL, NULL) == HYDRA_PHSP_EINVAL,
+           "too many integrand parameters");
+    expect(hydra_phsp_vegas_user_iteration(ui, lo, hi, par, 1, 10, FAKE(double, 0x100), 1, 1, 0,
+                                           FAKE(double, 0x200), NULL, NULL, NULL) == HYDRA_PHSP_EINVAL, "one call");
+    expect(hydra_phsp_vegas_user(ui, lo, hi, par, 1, 10, 100, 0, 0, 1.5, 1, NULL, &r, &e, &c, NULL) ==
+               HYDRA_PHSP_EINVAL, "no estimating iteration");
+    expect(hydra_phsp_vegas_user(NULL, lo, hi, par, 1, 10, 100, 0, 1, 1.5, 1, NULL, &r, &e, &c, NULL) ==
+               HYDRA_PHSP_EINVAL, "no integrand");
+    expect(hydra_phsp_user_integrand_destroy(ui) == HYDRA_PHSP_OK, "user integrand destroy");
+    expect(hydra_phsp_user_integrand_create("double x(", 3, &ui) == HYDRA_PHSP_EINVAL, "bad integrand source");
+    expect(hydra_phsp_user_integrand_destroy(NULL) == HYDRA_PHSP_EINVAL, "destroy of no integrand");
 }
 
 int main(void)

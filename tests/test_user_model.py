@@ -98,3 +98,63 @@ def test_user_model_binding_checks_daughter_count(P):
         model.destroy()
     with pytest.raises(P.PhspError):
         P.UserModel("not a function", 3)
+
+
+# --------------------------------------------------------------------------
+# VEGAS integrands compiled at run time
+
+INTEGRAND = """
+__device__ double hydra_phsp_user_integrand(const double* x, const double* par) {
+    return x[0] * x[1] * x[1] * exp(x[2]) * (1.0 + par[0] * x[HYDRA_PHSP_DIM - 1]);
+}
+"""
+
+
+def test_user_integrand_compiles_without_gpu(P):
+    h = ctypes.c_void_p()
+    assert P.lib().hydra_phsp_user_integrand_create(INTEGRAND.encode(), 4, ctypes.byref(h)) == P.OK and h.value
+    assert P.lib().hydra_phsp_user_integrand_destroy(h) == P.OK
+
+
+def test_user_integrand_create_validation(P):
+    f = P.lib().hydra_phsp_user_integrand_create
+    h = ctypes.c_void_p()
+    assert f(None, 4, ctypes.byref(h)) == P.EINVAL
+    for dim in (0, 17):
+        assert f(INTEGRAND.encode(), dim, ctypes.byref(h)) == P.EINVAL and not h.value
+    assert f(INTEGRAND.encode(), 4, None) == P.EINVAL
+    assert f(b"double hydra_phsp_user_integrand(", 4, ctypes.byref(h)) == P.EINVAL and not h.value
+    assert "user integrand does not compile" in P.lib().hydra_phsp_last_error().decode()
+    assert P.lib().hydra_phsp_user_integrand_destroy(None) == P.EINVAL
+    with pytest.raises(P.PhspError):
+        P.UserIntegrand("not C++", 2)
+
+
+def test_user_integrand_vegas_validation(P):
+    """Bad boxes, parameters, bins and buffers are rejected before any device work."""
+    h = ctypes.c_void_p()
+    assert P.lib().hydra_phsp_user_integrand_create(INTEGRAND.encode(), 4, ctypes.byref(h)) == P.OK
+    D = ctypes.c_double
+    lo, hi, bad_hi = (D * 4)(0, 0, 0, -1), (D * 4)(1, 1, 1, 1), (D * 4)(1, 1, 0, 1)
+    par = (D * 1)(0.5)
+    it, run = P.lib().hydra_phsp_vegas_user_iteration, P.lib().hydra_phsp_vegas_user
+    grid, stats = ctypes.c_void_p(256), ctypes.c_void_p(512)
+    r, e, c = D(), D(), D()
+    try:
+        assert it(None, lo, hi, par, 1, 10, grid, 100, 1, 0, stats, None, None, None) == P.EINVAL
+        assert it(h, None, hi, par, 1, 10, grid, 100, 1, 0, stats, None, None, None) == P.EINVAL
+        assert it(h, lo, bad_hi, par, 1, 10, grid, 100, 1, 0, stats, None, None, None) == P.EINVAL
+        assert it(h, lo, hi, par, 17, 10, grid, 100, 1, 0, stats, None, None, None) == P.EINVAL
+        assert it(h, lo, hi, None, 1, 10, grid, 100, 1, 0, stats, None, None, None) == P.EINVAL
+        assert it(h, lo, hi, par, 1, 1, grid, 100, 1, 0, stats, None, None, None) == P.EINVAL
+        assert it(h, lo, hi, par, 1, 10, None, 100, 1, 0, stats, None, None, None) == P.EINVAL
+        assert it(h, lo, hi, par, 1, 10, grid, 1, 1, 0, stats, None, None, None) == P.EINVAL
+        assert it(h, lo, hi, par, 1, 10, grid, 100, 1, 0, ctypes.c_void_p(4), None, None, None) == P.EINVAL
+        assert run(h, lo, bad_hi, par, 1, 10, 100, 0, 1, 1.5, 1, None, ctypes.byref(r), ctypes.byref(e),
+                   ctypes.byref(c), None) == P.EINVAL
+        assert run(h, lo, hi, par, 1, 10, 100, 0, 0, 1.5, 1, None, ctypes.byref(r), ctypes.byref(e),
+                   ctypes.byref(c), None) == P.EINVAL
+        assert run(h, lo, hi, par, 1, 10, 100, 0, 1, -1.0, 1, None, ctypes.byref(r), ctypes.byref(e),
+                   ctypes.byref(c), None) == P.EINVAL
+    finally:
+        assert P.lib().hydra_phsp_user_integrand_destroy(h) == P.OK

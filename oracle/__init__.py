@@ -81,6 +81,11 @@ def _load():
                                            ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, dp,
                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.oracle_model_integrate.restype = ctypes.c_int
+    lib.oracle_unweight_model.argtypes = [ctypes.c_double, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp,
+                                          ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                          ctypes.c_double, dp, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_double)]
+    lib.oracle_unweight_model.restype = ctypes.c_int
     lib.oracle_vegas_iteration.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_uint64,
                                            ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double), dp, dp]
@@ -208,6 +213,37 @@ def unweight(parent_mass, masses, ntrials, seed=42, stream_id=0, event_offset=0,
     k = min(kept, cap)
     p4 = None if out is None else out[:, :, :k]
     return p4, idx[:k], kept, over, used.value
+
+
+def unweight_model(parent_mass, masses, ntrials, resonances=(), seed=42, stream_id=0, event_offset=0, w_max=0.0,
+                   capacity=None, want_momenta=True):
+    """Hit-or-miss unweighting of ntrials events of a model (parent at rest): trial
+    e is kept when v_e * w_max < w_e |A_e|^2, |A|^2 the Breit-Wigner product of
+    model_integrate; w_max = 0: the largest trial value.  Returns (p4, index, kept,
+    over, w_max_used) as unweight."""
+    lib = _load()
+    m = _masses(masses)
+    n = len(m)
+    k = len(resonances)
+    pi = np.array([r[0] for r in resonances] + [0], dtype=np.int32)
+    pj = np.array([r[1] for r in resonances] + [0], dtype=np.int32)
+    rm = np.array([r[2] for r in resonances] + [0.0], dtype=np.float64)
+    rg = np.array([r[3] for r in resonances] + [0.0], dtype=np.float64)
+    cap = ntrials if capacity is None else capacity
+    out = np.zeros((n, 4, max(cap, 1)), dtype=np.float64) if want_momenta else None
+    idx = np.zeros(max(cap, 1), dtype=np.uint64)
+    counts = np.zeros(2, dtype=np.uint64)
+    used = ctypes.c_double()
+    st = lib.oracle_unweight_model(parent_mass, _ptr(m), n, k, _ptr(pi), _ptr(pj), _ptr(rm), _ptr(rg), ntrials,
+                                   seed, stream_id, event_offset, float(w_max), _ptr(out),
+                                   max(cap, 1) if want_momenta else cap, _ptr(idx), _ptr(counts),
+                                   ctypes.byref(used))
+    if st != OK:
+        raise OracleError(st)
+    kept, over = int(counts[0]), int(counts[1])
+    kk = min(kept, cap)
+    p4 = None if out is None else out[:, :, :kk]
+    return p4, idx[:kk], kept, over, used.value
 
 
 def model_integrate(parent_mass, masses, nevents, resonances=(), seed=42, stream_id=0, event_offset=0,

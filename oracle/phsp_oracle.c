@@ -381,54 +381,6 @@ double oracle_accept_uniform(uint64_t seed, uint32_t stream_id, uint64_t g, int 
     return (double)(2 * x + 1) * 0x1p-53;
 }
 
-/* Trials e = 0..ntrials-1 (global index event_offset + e) are the weighted
- * events oracle_generate produces; trial e is kept when v * w_max < w, with v
- * its acceptance uniform.  w_max == 0 takes the largest weight of the trials
- * (first pass).  Kept events are written in trial order to out (SoA, capacity
- * ld; kept events past the capacity are counted, not written) and, when index
- * is not NULL, their global indices to index[0..].  counts[0] = number kept,
- * counts[1] = number of trials whose weight exceeds w_max (kept with
- * probability 1, so w_max did not bound them).  *w_max_used = the w_max applied. */
-int oracle_unweight(double parent_mass, const double *masses, int n, const double *parent_p4,
-                    uint64_t ntrials, uint64_t seed, uint32_t stream_id, uint64_t event_offset,
-                    double w_max, double *out, uint64_t ld, uint64_t *index, uint64_t counts[2],
-                    double *w_max_used)
-{
-    int st = check_args(parent_mass, masses, n);
-    if (st != ORACLE_OK) return st;
-    if (counts == NULL || !(w_max >= 0.0) || !isfinite(w_max)) return ORACLE_EINVAL;
-    double u[3 * ORACLE_NMAX];
-    double p4[ORACLE_NMAX][4];
-    if (w_max == 0.0) {
-        for (uint64_t e = 0; e < ntrials; ++e) {
-            oracle_event_uniforms(seed, stream_id, event_offset + e, n, u);
-            const double w = one_event(parent_mass, masses, n, parent_p4, u, p4);
-            if (w > w_max) w_max = w;
-        }
-    }
-    uint64_t kept = 0, over = 0;
-    for (uint64_t e = 0; e < ntrials; ++e) {
-        const uint64_t g = event_offset + e;
-        oracle_event_uniforms(seed, stream_id, g, n, u);
-        const double w = one_event(parent_mass, masses, n, parent_p4, u, p4);
-        const double v = oracle_accept_uniform(seed, stream_id, g, n);
-        if (w > w_max) ++over;
-        if (v * w_max < w) {
-            if (kept < ld) {
-                if (out != NULL)
-                    for (int d = 0; d < n; ++d)
-                        for (int mu = 0; mu < 4; ++mu) out[(uint64_t)(4 * d + mu) * ld + kept] = p4[d][mu];
-                if (index != NULL) index[kept] = g;
-            }
-            ++kept;
-        }
-    }
-    counts[0] = kept;
-    counts[1] = over;
-    if (w_max_used != NULL) *w_max_used = w_max;
-    return ORACLE_OK;
-}
-
 /* ---------------------------------------------------------------------- */
 /* Model evaluation over phase space (sec. 4.2: "evaluation of model").    */
 /* The model is a product of relativistic Breit-Wigner intensities in pair  */
@@ -505,6 +457,99 @@ int oracle_model_integrate(double parent_mass, const double *masses, int n, int 
     *sigma = sqrt((s2.sum + s2.comp) / (double)(nevents - 1) / (double)nevents);
     free(v);
     return ORACLE_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Unweighted (hit-or-miss) samples.  Trials e = 0..ntrials-1 (global index  */
+/* event_offset + e) are the weighted events oracle_generate produces; the   */
+/* trial's value is its weight w, or w |A|^2 for a model (parent at rest).   */
+/* Trial e is kept when v * w_max < value, with v its acceptance uniform;    */
+/* w_max == 0 takes the largest value of the trials (first pass).  Kept      */
+/* events are written in trial order to out (SoA, capacity ld; kept events   */
+/* past the capacity are counted, not written) and, when index is not NULL,  */
+/* their global indices to index[0..].  counts[0] = number kept, counts[1] = */
+/* number of trials whose value exceeds w_max (kept with probability 1, so   */
+/* w_max did not bound them).  *w_max_used = the w_max applied.              */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int n_bw;
+    const int *pi, *pj;
+    const double *mass, *width;
+} model_t;
+
+static double trial_value(double parent_mass, const double *masses, int n, const double *parent_p4,
+                          const model_t *model, const double *u, double p4[][4])
+{
+    const double w = one_event(parent_mass, masses, n, parent_p4, u, p4);
+    if (model == NULL) return w;
+    return w * model_intensity(p4, model->n_bw, model->pi, model->pj, model->mass, model->width);
+}
+
+static int unweight(double parent_mass, const double *masses, int n, const double *parent_p4, const model_t *model,
+                    uint64_t ntrials, uint64_t seed, uint32_t stream_id, uint64_t event_offset, double w_max,
+                    double *out, uint64_t ld, uint64_t *index, uint64_t counts[2], double *w_max_used)
+{
+    if (counts == NULL || !(w_max >= 0.0) || !isfinite(w_max)) return ORACLE_EINVAL;
+    double u[3 * ORACLE_NMAX];
+    double p4[ORACLE_NMAX][4];
+    if (w_max == 0.0) {
+        for (uint64_t e = 0; e < ntrials; ++e) {
+            oracle_event_uniforms(seed, stream_id, event_offset + e, n, u);
+            const double w = trial_value(parent_mass, masses, n, parent_p4, model, u, p4);
+            if (w > w_max) w_max = w;
+        }
+    }
+    uint64_t kept = 0, over = 0;
+    for (uint64_t e = 0; e < ntrials; ++e) {
+        const uint64_t g = event_offset + e;
+        oracle_event_uniforms(seed, stream_id, g, n, u);
+        const double w = trial_value(parent_mass, masses, n, parent_p4, model, u, p4);
+        const double v = oracle_accept_uniform(seed, stream_id, g, n);
+        if (w > w_max) ++over;
+        if (v * w_max < w) {
+            if (kept < ld) {
+                if (out != NULL)
+                    for (int d = 0; d < n; ++d)
+                        for (int mu = 0; mu < 4; ++mu) out[(uint64_t)(4 * d + mu) * ld + kept] = p4[d][mu];
+                if (index != NULL) index[kept] = g;
+            }
+            ++kept;
+        }
+    }
+    counts[0] = kept;
+    counts[1] = over;
+    if (w_max_used != NULL) *w_max_used = w_max;
+    return ORACLE_OK;
+}
+
+/* The trials' values are their weights (parent at rest, or the broadcast
+ * parent_p4). */
+int oracle_unweight(double parent_mass, const double *masses, int n, const double *parent_p4,
+                    uint64_t ntrials, uint64_t seed, uint32_t stream_id, uint64_t event_offset,
+                    double w_max, double *out, uint64_t ld, uint64_t *index, uint64_t counts[2],
+                    double *w_max_used)
+{
+    int st = check_args(parent_mass, masses, n);
+    if (st != ORACLE_OK) return st;
+    return unweight(parent_mass, masses, n, parent_p4, NULL, ntrials, seed, stream_id, event_offset, w_max, out,
+                    ld, index, counts, w_max_used);
+}
+
+/* The trials' values are w |A|^2 with the Breit-Wigner product above (parent
+ * at rest): kept events follow the model's distribution over phase space. */
+int oracle_unweight_model(double parent_mass, const double *masses, int n, int n_bw, const int *pi,
+                          const int *pj, const double *mass, const double *width, uint64_t ntrials,
+                          uint64_t seed, uint32_t stream_id, uint64_t event_offset, double w_max, double *out,
+                          uint64_t ld, uint64_t *index, uint64_t counts[2], double *w_max_used)
+{
+    int st = check_args(parent_mass, masses, n);
+    if (st != ORACLE_OK) return st;
+    st = check_model(n, n_bw, pi, pj, mass, width);
+    if (st != ORACLE_OK) return st;
+    const model_t model = { n_bw, pi, pj, mass, width };
+    return unweight(parent_mass, masses, n, NULL, &model, ntrials, seed, stream_id, event_offset, w_max, out, ld,
+                    index, counts, w_max_used);
 }
 
 /* ---------------------------------------------------------------------- */

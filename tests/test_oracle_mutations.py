@@ -46,6 +46,8 @@ MUTATIONS = [
      "const double d = mass[k] * mass[k] + s;"),
     ("pair momentum differenced", "x = a[1] + b[1], y = a[2] + b[2]", "x = a[1] - b[1], y = a[2] + b[2]"),
     ("Breit-Wigner width term", "const double mg = mass[k] * width[k];", "const double mg = width[k];"),
+    ("model unweighting on the weight alone", "return w * model_intensity(p4, model->n_bw",
+     "return w + 0.0 * model_intensity(p4, model->n_bw"),
     ("VEGAS Jacobian without the bin count",
      "val = val * gauss_factor(x, mu[d], sig[d]) * ((double)bins * width * (hi[d] - lo[d]));",
      "val = val * gauss_factor(x, mu[d], sig[d]) * (width * (hi[d] - lo[d]));"),

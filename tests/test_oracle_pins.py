@@ -558,6 +558,73 @@ def test_model_validation(oracle_lib):
         oracle_lib.model_integrate(CFG0_M, CFG0_MASSES, 100, resonances=[(0, 1, 1.0, 0.1)] * 5)
 
 
+# ----------------------------------------- unweighted samples of a model ----
+# Hit-or-miss against w |A|^2: the kept events follow the model's density over
+# phase space, for config 0 with one Breit-Wigner in the (1, 2) pair mass the
+# density in s12 is W01(s12) |BW(s12)|^2 (the Dalitz density is uniform).
+
+def _bw_bin_integrals(M, m, mr, gr, edges, k=400):
+    """int over each [edges[b], edges[b+1]] of W01(s12) |BW(s12)|^2 ds12, with the
+    same arctangent substitution as volumes.bw_dalitz_integral_one, per bin."""
+    g = mr * gr
+    x, w = np.polynomial.legendre.leggauss(k)
+    out = []
+    for a_s, b_s in zip(edges[:-1], edges[1:]):
+        a, b = np.arctan((a_s - mr * mr) / g), np.arctan((b_s - mr * mr) / g)
+        th = 0.5 * (b - a) * x + 0.5 * (a + b)
+        s12 = mr * mr + g * np.tan(th)
+        l01, h01 = V.dalitz_m12sq_limits(M, m[2], m[1], m[0], s12)
+        out.append(0.5 * (b - a) * np.sum(w * (h01 - l01) / g))
+    return np.array(out)
+
+
+def test_unweight_model_without_factor_is_unweight(oracle_lib):
+    a = oracle_lib.unweight(CFG0_M, CFG0_MASSES, 30_000, seed=8, event_offset=5)
+    b = oracle_lib.unweight_model(CFG0_M, CFG0_MASSES, 30_000, [], seed=8, event_offset=5)
+    assert a[2:] == b[2:] and np.array_equal(a[1], b[1]) and np.array_equal(a[0], b[0])
+
+
+def test_unweight_model_acceptance(oracle_lib):
+    """Under a bound B above every value, a trial is kept with probability
+    w |A|^2 / B: the kept fraction is the model's integral (1-D quadrature) over B."""
+    M, m = CFG0_M, CFG0_MASSES
+    n, bound = 400_000, 4000.0
+    _, _, kept, over, used = oracle_lib.unweight_model(M, m, n, [(1, 2, *KSTAR)], seed=12, w_max=bound,
+                                                       want_momenta=False)
+    assert over == 0 and used == bound
+    p = V.bw_dalitz_integral_one(M, *m, *KSTAR) / bound
+    assert abs(kept / n - p) < 5.0 * math.sqrt(p * (1.0 - p) / n), (kept / n, p)
+
+
+def test_unweight_model_pair_mass_distribution(oracle_lib):
+    """The kept events' s12 follows W01(s12) |BW(s12)|^2 (chi^2 over bins that
+    span the peak and both tails)."""
+    M, m = CFG0_M, CFG0_MASSES
+    p4, idx, kept, over, used = oracle_lib.unweight_model(M, m, 600_000, [(1, 2, *KSTAR)], seed=13)
+    assert over == 0 and kept > 5000
+    s12 = _minkowski_sq(p4[1] + p4[2])
+    lo, hi = (m[1] + m[2]) ** 2, (M - m[0]) ** 2
+    mr, gr = KSTAR
+    inner = np.linspace(mr * mr - 4 * mr * gr, mr * mr + 4 * mr * gr, 17)
+    edges = np.concatenate([[lo], inner, [hi]])
+    cnt, _ = np.histogram(s12, bins=edges)
+    per_bin = _bw_bin_integrals(M, m, mr, gr, edges)
+    # the bins cover the whole s12 range: with the Dalitz density pi^2/(4 M^2)
+    # they add up to the model's integral
+    assert abs(per_bin.sum() * math.pi ** 2 / (4 * M * M) / V.bw_dalitz_integral_one(M, *m, mr, gr) - 1) < 1e-8
+    want = kept * per_bin / per_bin.sum()
+    chi2 = float(((cnt - want) ** 2 / want).sum())
+    ndf = len(cnt) - 1
+    assert chi2 < ndf + 5.0 * math.sqrt(2.0 * ndf), (chi2, cnt, want)
+
+
+def test_unweight_model_validation(oracle_lib):
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.unweight_model(CFG0_M, CFG0_MASSES, 100, [(1, 1, 1.0, 0.1)])
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.unweight_model(CFG0_M, CFG0_MASSES, 100, [(0, 1, 1.0, 0.1)], w_max=-1.0)
+
+
 # --------------------------------------------------- VEGAS / plain MC ----
 # Integrand: a product of Gaussians over a box, whose integral is a product of
 # error-function differences.

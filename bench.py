@@ -575,6 +575,20 @@ __device__ double hydra_phsp_user_integrand(const double* x, const double* par) 
     return r
 
 
+# One relativistic Breit-Wigner intensity in the (1, 2) pair mass as a user
+# intensity compiled at run time: par = (mass, width).
+USER_KSTAR = """
+__device__ double hydra_phsp_user_intensity(const double* e, const double* px, const double* py,
+                                            const double* pz, const double* par) {
+    const double se = e[1] + e[2], sx = px[1] + px[2], sy = py[1] + py[2], sz = pz[1] + pz[2];
+    const double s = se * se - sx * sx - sy * sy - sz * sz;
+    const double d = par[0] * par[0] - s;
+    const double mg = par[0] * par[1];
+    return 1.0 / (d * d + mg * mg);
+}
+"""
+
+
 def model_extra(P, torch, dev, M, m, n, w, st, steps):
     """Model evaluation over the 1e8 events: one Breit-Wigner intensity (a K pi
     resonance) and two (plus a broad one in the other pair); the per-event values
@@ -587,18 +601,8 @@ def model_extra(P, torch, dev, M, m, n, w, st, steps):
         r[name] = {"kernel_ms": k, "events_per_s": n / (ms * 1e-3), "integral": float(st[1].item()),
                    "sigma": float(st[3].item())}
     # the one-factor model as a user intensity compiled at run time (hiprtc)
-    src = """
-__device__ double hydra_phsp_user_intensity(const double* e, const double* px, const double* py,
-                                            const double* pz, const double* par) {
-    const double se = e[1] + e[2], sx = px[1] + px[2], sy = py[1] + py[2], sz = pz[1] + pz[2];
-    const double s = se * se - sx * sx - sy * sy - sz * sz;
-    const double d = par[0] * par[0] - s;
-    const double mg = par[0] * par[1];
-    return 1.0 / (d * d + mg * mg);
-}
-"""
     t0 = time.perf_counter()
-    model = P.UserModel(src, len(m))
+    model = P.UserModel(USER_KSTAR, len(m))
     compile_s = time.perf_counter() - t0
     ms, k = time_steps(lambda: model.integrate(M, m, n, one[0][2:], values=w, stats=st), steps, 1, torch)
     integral = float(st[1].item())
@@ -647,10 +651,31 @@ def unweighted_extra(P, torch, dev, M, m, n, out, steps):
     ms1, k1 = time_steps(lambda: P.generate_unweighted(M, m, n, w_max=w_max, out=out, counts=cnt, w_max_out=wmo),
                          steps, 1, torch)
     bytes_kept = kept * 8 * 4 * len(m)
-    return {"trials": n, "kept": kept, "kept_fraction": kept / n, "w_max": w_max, "over_bound": over,
-            "ms_sample_max": k0, "ms_given_bound": k1, "trials_per_s_given_bound": n / (k1 * 1e-3),
-            "kept_per_s_given_bound": kept / (k1 * 1e-3), "kept_per_s_sample_max": kept / (k0 * 1e-3),
-            "write_GBs_given_bound": bytes_kept / (k1 * 1e-3) / 1e9}
+    r = {"trials": n, "kept": kept, "kept_fraction": kept / n, "w_max": w_max, "over_bound": over,
+         "ms_sample_max": k0, "ms_given_bound": k1, "trials_per_s_given_bound": n / (k1 * 1e-3),
+         "kept_per_s_given_bound": kept / (k1 * 1e-3), "kept_per_s_sample_max": kept / (k0 * 1e-3),
+         "write_GBs_given_bound": bytes_kept / (k1 * 1e-3) / 1e9}
+    # samples of the one-factor K pi model (kept events follow w |A|^2), built in
+    # and as the same intensity compiled at run time
+    one = [(1, 2, 0.8955, 0.0473)]
+    model = P.UserModel(USER_KSTAR, len(m))
+    runs = {"model_one_factor": lambda wm: P.generate_unweighted_model(M, m, n, one, w_max=wm, out=out,
+                                                                       counts=cnt, w_max_out=wmo),
+            "user_model_one_factor": lambda wm: model.generate_unweighted(M, m, n, one[0][2:], w_max=wm, out=out,
+                                                                          counts=cnt, w_max_out=wmo)}
+    for name, run in runs.items():
+        ms0, k0 = time_steps(lambda: run(0.0), steps, 1, torch)
+        kept = int(cnt[0].item())
+        w_max = float(wmo.item())
+        ms1, k1 = time_steps(lambda: run(w_max), steps, 1, torch)
+        r[name] = {"kept": kept, "kept_fraction": kept / n, "w_max": w_max, "ms_sample_max": k0,
+                   "ms_given_bound": k1, "trials_per_s_given_bound": n / (k1 * 1e-3),
+                   "kept_per_s_sample_max": kept / (k0 * 1e-3)}
+    model.destroy()
+    r["user_model_one_factor"]["same_sample_as_built_in"] = \
+        r["user_model_one_factor"]["kept"] == r["model_one_factor"]["kept"] and \
+        r["user_model_one_factor"]["w_max"] == r["model_one_factor"]["w_max"]
+    return r
 
 
 def serving_extra(P, seconds, budget):

@@ -17,6 +17,7 @@
 #include <stdint.h>
 
 #include "hydra_phsp.h"
+#include "hydra_phsp_model.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -52,6 +53,37 @@ int hydra_phsp_generate_unweighted(double parent_mass, const double *masses_host
                                    uint32_t stream_id, uint64_t event_offset, double w_max,
                                    double *p4_out_dev, uint64_t ld, uint64_t *index_out_dev,
                                    uint64_t *counts_dev, double *w_max_dev, void *stream);
+
+/* Unweighted samples of a model (sec. 4.2 lists weighted and unweighted
+ * samples and model evaluation together): trial event g is kept when
+ * v_g * w_max < w_g |A|^2(g), with |A|^2 the product of Breit-Wigner factors of
+ * hydra_phsp_integrate_model, the parent at rest and v_g the acceptance uniform
+ * above.  Kept events then follow |A|^2 times the phase-space density.  The
+ * trials, draws, outputs, counts and bound are those of
+ * hydra_phsp_generate_unweighted with w_g replaced by w_g |A|^2(g) (w_max = 0:
+ * the largest w |A|^2 among the trials; counts_dev[1] the trials above the
+ * bound); with no factor the result is that of hydra_phsp_generate_unweighted.
+ * EINVAL for a bad factor (as for hydra_phsp_integrate_model) and as above. */
+int hydra_phsp_generate_unweighted_model(double parent_mass, const double *masses_host, int n_daughters,
+                                         const hydra_phsp_breit_wigner *resonances_host, int n_resonances,
+                                         uint64_t ntrials, uint64_t seed, uint32_t stream_id,
+                                         uint64_t event_offset, double w_max, double *p4_out_dev, uint64_t ld,
+                                         uint64_t *index_out_dev, uint64_t *counts_dev, double *w_max_dev,
+                                         void *stream);
+
+/* The same with a user intensity compiled by hydra_phsp_user_model_create
+ * (n_daughters is the model's): trial g is kept when
+ * v_g * w_max < w_g * hydra_phsp_user_intensity(event g, params), with the
+ * n_params (0 .. HYDRA_PHSP_USER_PARAMS) params_host values, then zeros.  The
+ * first call on a device loads the model's code there.  EINVAL for a NULL
+ * model, n_params out of range or params_host NULL with n_params > 0, and as
+ * above. */
+int hydra_phsp_generate_unweighted_user_model(hydra_phsp_user_model *model, double parent_mass,
+                                              const double *masses_host, const double *params_host, int n_params,
+                                              uint64_t ntrials, uint64_t seed, uint32_t stream_id,
+                                              uint64_t event_offset, double w_max, double *p4_out_dev, uint64_t ld,
+                                              uint64_t *index_out_dev, uint64_t *counts_dev, double *w_max_dev,
+                                              void *stream);
 
 #ifdef __cplusplus
 }

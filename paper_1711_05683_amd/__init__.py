@@ -72,6 +72,12 @@ def _declare(lib):
     lib.hydra_phsp_generate_unweighted.restype = i
     lib.hydra_phsp_integrate_model.argtypes = [d, dp, i, vp, i, u64, u64, u32, u64, vp, vp, vp]
     lib.hydra_phsp_integrate_model.restype = i
+    lib.hydra_phsp_generate_unweighted_model.argtypes = [d, dp, i, vp, i, u64, u64, u32, u64, d, vp, u64, vp,
+                                                         vp, vp, vp]
+    lib.hydra_phsp_generate_unweighted_model.restype = i
+    lib.hydra_phsp_generate_unweighted_user_model.argtypes = [vp, d, dp, dp, i, u64, u64, u32, u64, d, vp, u64,
+                                                              vp, vp, vp, vp]
+    lib.hydra_phsp_generate_unweighted_user_model.restype = i
     lib.hydra_phsp_user_model_create.argtypes = [c.c_char_p, i, c.POINTER(vp)]
     lib.hydra_phsp_user_model_create.restype = i
     lib.hydra_phsp_user_model_destroy.argtypes = [vp]
@@ -241,25 +247,10 @@ def generate(parent_mass: float, masses: Sequence[float], nevents: int, *, seed:
     return out, weights, stats
 
 
-def generate_unweighted(parent_mass: float, masses: Sequence[float], ntrials: int, *, seed: int = 42,
-                        stream_id: int = 0, event_offset: int = 0, w_max: float = 0.0,
-                        parent_p4: Optional[Sequence[float]] = None, capacity: Optional[int] = None,
-                        want_events: bool = True, want_index: bool = False, device=None,
-                        stream: Optional[torch.cuda.Stream] = None, out: Optional[torch.Tensor] = None,
-                        index: Optional[torch.Tensor] = None, counts: Optional[torch.Tensor] = None,
-                        w_max_out: Optional[torch.Tensor] = None):
-    """Hit-or-miss unweighted sample from ``ntrials`` weighted trials (asynchronous).
-
-    Trial g is kept when v_g * w_max < w_g (``w_max`` = 0: the largest trial
-    weight).  Returns ``(p4, index, counts, w_max_used)``: ``p4`` an
-    ``[N, 4, capacity]`` float64 buffer whose first ``counts[0]`` columns are the
-    kept events in trial order (None unless ``want_events``), ``index`` their
-    global indices (int64, None unless ``want_index``), ``counts`` a device int64
-    pair (kept, trials with w > w_max) and ``w_max_used`` a device scalar.  Read
-    ``counts`` after synchronizing the stream.  ``out``, ``index``, ``counts`` and
-    ``w_max_out`` may be given (contiguous, of those shapes and dtypes) to reuse
-    buffers; ``capacity`` is then ``out``'s (or ``index``'s) last dimension."""
-    m, n = _masses(masses)
+def _unweighted_buffers(n: int, ntrials: int, capacity, want_events, want_index, device, stream, out, index,
+                        counts, w_max_out):
+    """Check or allocate the outputs of an unweighted sample; returns
+    (out, index, counts, w_max_out, ld)."""
     cap = aligned_ld(ntrials) if capacity is None else int(capacity)
     if out is not None and (not isinstance(out, torch.Tensor) or out.dtype != torch.float64
                             or not out.is_contiguous() or out.dim() != 3 or tuple(out.shape[:2]) != (n, 4)):
@@ -281,10 +272,34 @@ def generate_unweighted(parent_mass: float, masses: Sequence[float], ntrials: in
     if counts is None:
         counts = torch.empty(2, dtype=torch.int64, device=dev)
     wm = w_max_out if w_max_out is not None else torch.empty(1, dtype=torch.float64, device=dev)
+    ld = out.shape[2] if out is not None else (idx.shape[0] if idx is not None else 0)
+    return out, idx, counts, wm, ld
+
+
+def generate_unweighted(parent_mass: float, masses: Sequence[float], ntrials: int, *, seed: int = 42,
+                        stream_id: int = 0, event_offset: int = 0, w_max: float = 0.0,
+                        parent_p4: Optional[Sequence[float]] = None, capacity: Optional[int] = None,
+                        want_events: bool = True, want_index: bool = False, device=None,
+                        stream: Optional[torch.cuda.Stream] = None, out: Optional[torch.Tensor] = None,
+                        index: Optional[torch.Tensor] = None, counts: Optional[torch.Tensor] = None,
+                        w_max_out: Optional[torch.Tensor] = None):
+    """Hit-or-miss unweighted sample from ``ntrials`` weighted trials (asynchronous).
+
+    Trial g is kept when v_g * w_max < w_g (``w_max`` = 0: the largest trial
+    weight).  Returns ``(p4, index, counts, w_max_used)``: ``p4`` an
+    ``[N, 4, capacity]`` float64 buffer whose first ``counts[0]`` columns are the
+    kept events in trial order (None unless ``want_events``), ``index`` their
+    global indices (int64, None unless ``want_index``), ``counts`` a device int64
+    pair (kept, trials with w > w_max) and ``w_max_used`` a device scalar.  Read
+    ``counts`` after synchronizing the stream.  ``out``, ``index``, ``counts`` and
+    ``w_max_out`` may be given (contiguous, of those shapes and dtypes) to reuse
+    buffers; ``capacity`` is then ``out``'s (or ``index``'s) last dimension."""
+    m, n = _masses(masses)
+    out, idx, counts, wm, ld = _unweighted_buffers(n, ntrials, capacity, want_events, want_index, device, stream,
+                                                   out, index, counts, w_max_out)
     p4h = None
     if parent_p4 is not None:
         p4h = (ctypes.c_double * 4)(*[float(x) for x in parent_p4])
-    ld = out.shape[2] if out is not None else (idx.shape[0] if idx is not None else 0)
     _check(lib().hydra_phsp_generate_unweighted(parent_mass, m, n, p4h, ntrials, seed, stream_id, event_offset,
                                                 float(w_max), _dptr(out), ld, _dptr(idx), _dptr(counts),
                                                 _dptr(wm), _stream_handle(stream)))
@@ -310,8 +325,7 @@ def integrate_model(parent_mass: float, masses: Sequence[float], nevents: int, r
     _check_buf(values, "values", torch.float64, nevents)
     _check_buf(stats, "stats", torch.float64, STATS)
     dev = _resident(device, stream, values=values, stats=stats)
-    k = len(resonances)
-    arr = (BreitWigner * max(k, 1))(*[BreitWigner(int(a), int(b), float(c), float(d)) for a, b, c, d in resonances])
+    arr, k = _bw_array(resonances)
     if values is None and want_values:
         values = torch.empty(max(nevents, 1), dtype=torch.float64, device=dev)
     if stats is None:
@@ -320,6 +334,32 @@ def integrate_model(parent_mass: float, masses: Sequence[float], nevents: int, r
                                             seed, stream_id, event_offset, _dptr(values), _dptr(stats),
                                             _stream_handle(stream)))
     return stats, values
+
+
+def _bw_array(resonances):
+    k = len(resonances)
+    arr = (BreitWigner * max(k, 1))(*[BreitWigner(int(a), int(b), float(c), float(d)) for a, b, c, d in resonances])
+    return arr, k
+
+
+def generate_unweighted_model(parent_mass: float, masses: Sequence[float], ntrials: int, resonances=(), *,
+                              seed: int = 42, stream_id: int = 0, event_offset: int = 0, w_max: float = 0.0,
+                              capacity: Optional[int] = None, want_events: bool = True, want_index: bool = False,
+                              device=None, stream: Optional[torch.cuda.Stream] = None,
+                              out: Optional[torch.Tensor] = None, index: Optional[torch.Tensor] = None,
+                              counts: Optional[torch.Tensor] = None, w_max_out: Optional[torch.Tensor] = None):
+    """Hit-or-miss sample of the Breit-Wigner model (parent at rest): trial g is
+    kept when v_g * w_max < w_g |A|^2(g) (``w_max`` = 0: the largest w |A|^2).
+    Arguments and results as for generate_unweighted."""
+    m, n = _masses(masses)
+    arr, k = _bw_array(resonances)
+    out, idx, counts, wm, ld = _unweighted_buffers(n, ntrials, capacity, want_events, want_index, device, stream,
+                                                   out, index, counts, w_max_out)
+    _check(lib().hydra_phsp_generate_unweighted_model(parent_mass, m, n, ctypes.cast(arr, ctypes.c_void_p), k,
+                                                      ntrials, seed, stream_id, event_offset, float(w_max),
+                                                      _dptr(out), ld, _dptr(idx), _dptr(counts), _dptr(wm),
+                                                      _stream_handle(stream)))
+    return out, idx, counts, wm
 
 
 USER_PARAMS = 16
@@ -345,17 +385,10 @@ class UserModel:
                   stats: Optional[torch.Tensor] = None, device=None, stream: Optional[torch.cuda.Stream] = None):
         """As integrate_model, with the user's intensity and parameters (at most
         USER_PARAMS).  Returns ``(stats, values)``."""
-        if self._h is None:
-            raise ValueError("the model was destroyed")
-        m, n = _masses(masses)
-        if n != self.n:
-            raise ValueError(f"the model has {self.n} daughters, {n} masses given")
-        if len(params) > USER_PARAMS:
-            raise ValueError(f"at most {USER_PARAMS} parameters")
+        m, n, par = self._params(masses, params)
         _check_buf(values, "values", torch.float64, nevents)
         _check_buf(stats, "stats", torch.float64, STATS)
         dev = _resident(device, stream, values=values, stats=stats)
-        par = (ctypes.c_double * max(len(params), 1))(*[float(x) for x in params])
         if values is None and want_values:
             values = torch.empty(max(nevents, 1), dtype=torch.float64, device=dev)
         if stats is None:
@@ -364,6 +397,35 @@ class UserModel:
                                                      stream_id, event_offset, _dptr(values), _dptr(stats),
                                                      _stream_handle(stream)))
         return stats, values
+
+    def _params(self, masses, params):
+        if self._h is None:
+            raise ValueError("the model was destroyed")
+        m, n = _masses(masses)
+        if n != self.n:
+            raise ValueError(f"the model has {self.n} daughters, {n} masses given")
+        if len(params) > USER_PARAMS:
+            raise ValueError(f"at most {USER_PARAMS} parameters")
+        return m, n, (ctypes.c_double * max(len(params), 1))(*[float(x) for x in params])
+
+    def generate_unweighted(self, parent_mass: float, masses: Sequence[float], ntrials: int,
+                            params: Sequence[float] = (), *, seed: int = 42, stream_id: int = 0,
+                            event_offset: int = 0, w_max: float = 0.0, capacity: Optional[int] = None,
+                            want_events: bool = True, want_index: bool = False, device=None,
+                            stream: Optional[torch.cuda.Stream] = None, out: Optional[torch.Tensor] = None,
+                            index: Optional[torch.Tensor] = None, counts: Optional[torch.Tensor] = None,
+                            w_max_out: Optional[torch.Tensor] = None):
+        """Hit-or-miss sample of the user's intensity (parent at rest): trial g
+        is kept when v_g * w_max < w_g * intensity(g).  Arguments and results as
+        for generate_unweighted."""
+        m, n, par = self._params(masses, params)
+        out, idx, counts, wm, ld = _unweighted_buffers(n, ntrials, capacity, want_events, want_index, device,
+                                                       stream, out, index, counts, w_max_out)
+        _check(lib().hydra_phsp_generate_unweighted_user_model(self._h, parent_mass, m, par, len(params), ntrials,
+                                                               seed, stream_id, event_offset, float(w_max),
+                                                               _dptr(out), ld, _dptr(idx), _dptr(counts),
+                                                               _dptr(wm), _stream_handle(stream)))
+        return out, idx, counts, wm
 
     def destroy(self):
         if self._h is not None and self._h.value:

@@ -50,7 +50,7 @@ LINK_LIBS = [f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", "-lhiprtc", f"-Wl,-rpat
 # the library as strings (written to _build/gen before the units compile).
 GEN_DIR = os.path.join(BUILD_DIR, "gen")
 RTC_HEADERS = ("phsp_sortnet.hpp", "phsp_device.hpp", "phsp_reduce.hpp", "phsp_stage.hpp", "phsp_kernels.hpp",
-               "phsp_model.hpp", "phsp_vegas.hpp")
+               "phsp_model.hpp", "phsp_unweight.hpp", "phsp_vegas.hpp")
 RTC_DELIM = "HPHSPSRC"
 
 

@@ -5,9 +5,13 @@
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <string>
+#include <vector>
 
 #include "phsp_device.hpp"
 #include "phsp_reduce.hpp"
+
+struct hydra_phsp_breit_wigner;
+struct hydra_phsp_user_model;
 
 namespace hphsp {
 
@@ -55,14 +59,25 @@ int trig_table(const double2** out);
 // gfx950 with the library's flags against its own kernel headers (embedded at
 // build time), the code object kept and loaded on each device at its first use.
 struct RtcKernel;
-// Compile `source`; `kernel` is the kernel's extern "C" name, or (name_expr) a
-// C++ name expression whose lowered name hiprtc reports.  A source that does not
-// compile fails with EINVAL and "<what> does not compile: <log>".
-int rtc_compile(const std::string& source, const char* kernel, bool name_expr, const char* what, RtcKernel** out);
-// The kernel on the current device (loading the code object there at the first call).
-int rtc_function(RtcKernel* k, hipFunction_t* fn);
+struct RtcName {
+    std::string name; // the kernel's extern "C" name, or a C++ name expression
+    bool expression;  // (then hiprtc reports its lowered name)
+};
+// Compile `source` with the kernels `names`.  A source that does not compile
+// fails with EINVAL and "<what> does not compile: <log>".
+int rtc_compile(const std::string& source, const std::vector<RtcName>& names, const char* what, RtcKernel** out);
+// Kernel `which` (its index in `names`) on the current device (loading the code
+// object there at the first call).
+int rtc_function(RtcKernel* k, int which, hipFunction_t* fn);
 // Waits for the devices it was loaded on, unloads and frees it.
 int rtc_destroy(RtcKernel* k);
+// The kernels of a user model's module, by index, and the model's module.
+enum { kUserModelKernel = 0, kUserModelUnwMax = 1, kUserModelUnwCount = 2 };
+RtcKernel* user_model_kernels(const hydra_phsp_user_model* model, int* n_daughters);
+// Validate up to HYDRA_PHSP_MAX_BW Breit-Wigner factors of an N-body model and
+// copy them into the kernels' form.
+struct BwFactors;
+int make_bw_factors(const hydra_phsp_breit_wigner* res, int n_res, int n_daughters, BwFactors* out);
 // Benchmark timing brackets around a kernel launch (slot -1: timing off).
 long timing_begin(hipStream_t stream);
 void timing_end(hipStream_t stream, long slot);

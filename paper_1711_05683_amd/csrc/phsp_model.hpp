@@ -11,11 +11,16 @@ namespace hphsp {
 constexpr int kMaxBw = 4;
 constexpr int kModelEpt = 4; // compute-bound (8 B stored per event at most)
 
+// Breit-Wigner factors: pairs (i, j), masses and widths of the first n.
+struct BwFactors {
+    int32_t n;                // factors in use
+    int32_t i[kMaxBw], j[kMaxBw];
+    double mass[kMaxBw], width[kMaxBw];
+};
+
 struct ModelArgs {
     KArgs a;                  // channel, counters, trig table, partials (a.out unused)
-    int32_t nbw;              // factors in use
-    int32_t bi[kMaxBw], bj[kMaxBw];
-    double bm[kMaxBw], bg[kMaxBw]; // mass, width
+    BwFactors bw;
     double* values;           // NULL or [nevents]: w |A|^2 per event
 };
 
@@ -51,20 +56,25 @@ __device__ __forceinline__ void pair_sum(const Event<N, double>& ev, int i, int 
 // |A|^2 = prod_k 1 / ((M_k^2 - s_k)^2 + (M_k G_k)^2), factors in order, with
 // s = (E_i + E_j)^2 - |p_i + p_j|^2 (components summed first).
 template <int N>
-__device__ __forceinline__ double model_intensity(const Event<N, double>& ev, const ModelArgs& m) {
+__device__ __forceinline__ double bw_product(const Event<N, double>& ev, const BwFactors& f) {
     double a2 = 1.0;
 #pragma unroll
     for (int k = 0; k < kMaxBw; ++k) {
-        if (k < m.nbw) {
+        if (k < f.n) {
             double e, x, y, z;
-            pair_sum<N>(ev, m.bi[k], m.bj[k], e, x, y, z);
+            pair_sum<N>(ev, f.i[k], f.j[k], e, x, y, z);
             const double s = e * e - x * x - y * y - z * z;
-            const double d = m.bm[k] * m.bm[k] - s;
-            const double mg = m.bm[k] * m.bg[k];
+            const double d = f.mass[k] * f.mass[k] - s;
+            const double mg = f.mass[k] * f.width[k];
             a2 = a2 / (d * d + mg * mg);
         }
     }
     return a2;
+}
+
+template <int N>
+__device__ __forceinline__ double model_intensity(const Event<N, double>& ev, const ModelArgs& m) {
+    return bw_product<N>(ev, m.bw);
 }
 
 // One block of a model kernel: every event of the block's range, with its

@@ -10,6 +10,27 @@
 #include "phsp_model.hpp"
 
 namespace hphsp {
+
+int make_bw_factors(const hydra_phsp_breit_wigner* res, int n_res, int n_daughters, BwFactors* out) {
+    std::memset(out, 0, sizeof(*out));
+    if (n_res < 0 || n_res > HYDRA_PHSP_MAX_BW)
+        return fail(HYDRA_PHSP_EINVAL, "n_resonances must be in [0, HYDRA_PHSP_MAX_BW]");
+    if (n_res > 0 && res == nullptr) return fail(HYDRA_PHSP_EINVAL, "resonances_host is NULL");
+    out->n = n_res;
+    for (int k = 0; k < n_res; ++k) {
+        const hydra_phsp_breit_wigner& r = res[k];
+        if (r.i < 0 || r.j >= n_daughters || r.i >= r.j)
+            return fail(HYDRA_PHSP_EINVAL, "resonance pair must satisfy 0 <= i < j < n_daughters");
+        if (!(r.mass > 0.0) || !(r.width > 0.0) || !std::isfinite(r.mass) || !std::isfinite(r.width))
+            return fail(HYDRA_PHSP_EINVAL, "resonance mass and width must be finite and > 0");
+        out->i[k] = r.i;
+        out->j[k] = r.j;
+        out->mass[k] = r.mass;
+        out->width[k] = r.width;
+    }
+    return HYDRA_PHSP_OK;
+}
+
 namespace {
 
 hipError_t launch_model_n(int n, const ModelArgs& m, uint64_t blocks, hipStream_t s) {
@@ -41,26 +62,13 @@ extern "C" int hydra_phsp_integrate_model(double parent_mass, const double* mass
     Channel ch;
     int st = make_channel(parent_mass, masses_host, n_daughters, &ch);
     if (st != HYDRA_PHSP_OK) return st;
-    if (n_resonances < 0 || n_resonances > HYDRA_PHSP_MAX_BW)
-        return fail(HYDRA_PHSP_EINVAL, "n_resonances must be in [0, HYDRA_PHSP_MAX_BW]");
-    if (n_resonances > 0 && resonances_host == nullptr) return fail(HYDRA_PHSP_EINVAL, "resonances_host is NULL");
     if (stats_dev == nullptr) return fail(HYDRA_PHSP_EINVAL, "stats_dev is required");
     if ((uintptr_t)values_dev % sizeof(double) != 0 || (uintptr_t)stats_dev % sizeof(double) != 0)
         return fail(HYDRA_PHSP_EINVAL, "device pointers must be aligned to their element size");
     ModelArgs m;
     std::memset(&m, 0, sizeof(m));
-    m.nbw = n_resonances;
-    for (int k = 0; k < n_resonances; ++k) {
-        const hydra_phsp_breit_wigner& r = resonances_host[k];
-        if (r.i < 0 || r.j >= n_daughters || r.i >= r.j)
-            return fail(HYDRA_PHSP_EINVAL, "resonance pair must satisfy 0 <= i < j < n_daughters");
-        if (!(r.mass > 0.0) || !(r.width > 0.0) || !std::isfinite(r.mass) || !std::isfinite(r.width))
-            return fail(HYDRA_PHSP_EINVAL, "resonance mass and width must be finite and > 0");
-        m.bi[k] = r.i;
-        m.bj[k] = r.j;
-        m.bm[k] = r.mass;
-        m.bg[k] = r.width;
-    }
+    st = make_bw_factors(resonances_host, n_resonances, n_daughters, &m.bw);
+    if (st != HYDRA_PHSP_OK) return st;
     const uint64_t span = (uint64_t)kBlock * (uint64_t)kModelEpt;
     const uint64_t blocks = ceil_div(nevents, span);
     if (blocks > 0xFFFFFFFFull / (uint64_t)kBlock)

@@ -22,6 +22,7 @@
 #pragma once
 
 #include "phsp_kernels.hpp"
+#include "phsp_model.hpp"
 
 namespace hphsp {
 
@@ -59,7 +60,42 @@ struct UnwArgs {
     double* out;               // kept events, [N][4][ld]
     uint64_t ld;               // capacity in events
     uint64_t* index;           // NULL, or [ld] global index of each kept event
+    BwFactors bw;              // a model's Breit-Wigner factors (BwIntensity)
+    double upar[16];           // a user intensity's parameters (HYDRA_PHSP_USER_PARAMS of them)
 };
+
+// What a trial is accepted against: its weight w (NoIntensity), or w times a
+// model's intensity of its daughters in the parent's rest frame (BwIntensity,
+// or a user's function compiled at run time).  kKinematics: the intensity needs
+// the daughters' four-momenta, so the trial's full event is computed.
+struct NoIntensity {
+    static constexpr bool kKinematics = false;
+    template <int N>
+    __device__ __forceinline__ double operator()(const UnwArgs&, const Event<N, double>&) const {
+        return 1.0;
+    }
+};
+
+struct BwIntensity {
+    static constexpr bool kKinematics = true;
+    template <int N>
+    __device__ __forceinline__ double operator()(const UnwArgs& u, const Event<N, double>& ev) const {
+        return bw_product<N>(ev, u.bw);
+    }
+};
+
+// The value of trial base + off (tab: the block's trigonometric table, used only
+// when the intensity needs the kinematics).
+template <int N, class I>
+__device__ __forceinline__ double trial_value(const UnwArgs& u, uint64_t base, uint32_t off, const double2* tab) {
+    Event<N, double> ev;
+    if constexpr (!I::kKinematics) {
+        return compute_event<N, kAtRest, kIntegrate>(u.a, base, off, nullptr, ev);
+    } else {
+        const double w = compute_event<N, kAtRest, kFp64>(u.a, base, off, tab, ev);
+        return w * I{}.template operator()<N>(u, ev);
+    }
+}
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
@@ -73,21 +109,20 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Largest weight of the trials: each block's maximum raises the bound's bit
+// Largest value of the trials: each block's maximum raises the bound's bit
 // pattern with an atomic max (exact and independent of order; the bound starts
 // at zero).
-template <int N>
+template <int N, class I = NoIntensity>
 __global__ __launch_bounds__(kBlock) void k_unw_max(const UnwArgs u) {
     __shared__ double sm[kWaves];
+    __shared__ double2 tab[I::kKinematics ? kTrigSize : 1];
+    if constexpr (I::kKinematics) load_trig(tab, u.a.trig);
     const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(kBlock * kUnwEpt);
     double m = 0.0;
 #pragma unroll
     for (int k = 0; k < kUnwEpt; ++k) {
         const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
-        if (base + off < u.a.nevents) {
-            Event<N, double> ev;
-            m = fmax(m, compute_event<N, kAtRest, kIntegrate>(u.a, base, off, nullptr, ev));
-        }
+        if (base + off < u.a.nevents) m = fmax(m, trial_value<N, I>(u, base, off, tab));
     }
     m = wave_max(m);
     if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
@@ -105,11 +140,13 @@ __global__ __launch_bounds__(kBlock) void k_unw_max(const UnwArgs u) {
     }
 }
 
-// Keep decisions and counts of each segment (the weights only).  Wave w of
-// block b takes segment s = kUnwSegPerBlock b + w; step k covers its trials
+// Keep decisions and counts of each segment (the values only: no stores).  Wave
+// w of block b takes segment s = kUnwSegPerBlock b + w; step k covers its trials
 // s kUnwSeg + 64 k + lane, and the step's ballot is the segment's mask word k.
-template <int N>
+template <int N, class I = NoIntensity>
 __global__ __launch_bounds__(kBlock) void k_unw_count(const UnwArgs u) {
+    __shared__ double2 tab[I::kKinematics ? kTrigSize : 1];
+    if constexpr (I::kKinematics) load_trig(tab, u.a.trig); // before any wave leaves
     const uint64_t seg = (uint64_t)blockIdx.x * kUnwSegPerBlock +
                          (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (seg >= u.segments) return;
@@ -122,8 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_unw_count(const UnwArgs u) {
         const uint32_t off = (uint32_t)(64 * k) + lane;
         bool keep = false, above = false;
         if (base + off < u.a.nevents) {
-            Event<N, double> ev;
-            const double w = compute_event<N, kAtRest, kIntegrate>(u.a, base, off, nullptr, ev);
+            const double w = trial_value<N, I>(u, base, off, tab);
             const double v = accept_uniform<N>(u.a, base, off);
             keep = v * wmax < w;
             above = w > wmax;
@@ -230,6 +266,7 @@ struct UnwLaunch {
     uint64_t max_blocks; // max pass: kBlock * kUnwEpt trials per block
     uint64_t blocks;     // count pass: kUnwSegPerBlock segments per block
     uint64_t write_blocks; // write pass: kUnwSegPerBlock ranges of kUnwRange output positions per block
+    int intensity;       // max and count passes: 0 the weight alone, 1 the Breit-Wigner model (u.bw)
     int pmode;           // kAtRest or kBroadcast (write pass)
 };
 

@@ -10,6 +10,7 @@
 #include <utility>
 
 #include "hydra_phsp.h"
+#include "hydra_phsp_model.h"
 #include "hydra_phsp_unweight.h"
 #include "phsp_api_internal.hpp"
 #include "phsp_unweight.hpp"
@@ -230,17 +231,24 @@ int release_unweight_workspaces() {
 
 using namespace hphsp;
 
-extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* masses_host, int n_daughters,
-                                              const double* parent_p4_host, uint64_t ntrials, uint64_t seed,
-                                              uint32_t stream_id, uint64_t event_offset, double w_max,
-                                              double* p4_out_dev, uint64_t ld, uint64_t* index_out_dev,
-                                              uint64_t* counts_dev, double* w_max_dev, void* stream) {
-    MarkerRange marker("hydra_phsp_generate_unweighted");
-    Channel ch;
-    int st = make_channel(parent_mass, masses_host, n_daughters, &ch);
-    if (st != HYDRA_PHSP_OK) return st;
+namespace hphsp {
+namespace {
+
+// What the trials are accepted against (see UnwArgs): the weight, the built-in
+// Breit-Wigner model, or a user model's run-time kernels.
+struct UnwIntensity {
+    int kind = 0; // 0 weight, 1 Breit-Wigner, 2 user
+    BwFactors bw{};
+    RtcKernel* user = nullptr;
+    double upar[HYDRA_PHSP_USER_PARAMS] = {};
+};
+
+int unweighted_run(const Channel& ch, int n_daughters, const double* parent_p4_host, uint64_t ntrials, uint64_t seed,
+                   uint32_t stream_id, uint64_t event_offset, double w_max, double* p4_out_dev, uint64_t ld,
+                   uint64_t* index_out_dev, uint64_t* counts_dev, double* w_max_dev, void* stream,
+                   const UnwIntensity& inten) {
     if (!(w_max >= 0.0) || w_max > 1.7976931348623157e308)
-        return fail(HYDRA_PHSP_EINVAL, "w_max must be finite and >= 0 (0: the largest trial weight)");
+        return fail(HYDRA_PHSP_EINVAL, "w_max must be finite and >= 0 (0: the largest trial value)");
     if (counts_dev == nullptr) return fail(HYDRA_PHSP_EINVAL, "counts_dev is required");
     if ((p4_out_dev != nullptr || index_out_dev != nullptr) && ld == 0)
         return fail(HYDRA_PHSP_EINVAL, "ld (the capacity in events) must be >= 1 when outputs are given");
@@ -250,8 +258,9 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
     Frame frame;
     std::memset(&frame, 0, sizeof(frame));
     int pmode = kAtRest;
+    int st = HYDRA_PHSP_OK;
     if (parent_p4_host != nullptr) {
-        st = make_frame(parent_mass, parent_p4_host, &frame);
+        st = make_frame(ch.M, parent_p4_host, &frame);
         if (st != HYDRA_PHSP_OK) return st;
         pmode = kBroadcast;
     }
@@ -265,6 +274,12 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
     if (max_blocks > 0xFFFFFFFFull / (uint64_t)kBlock || blocks > 0xFFFFFFFFull / (uint64_t)kBlock ||
         write_blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
         return fail(HYDRA_PHSP_EINVAL, "ntrials too large for one launch (more than 2^32 - 1 threads)");
+    hipFunction_t user_max = nullptr, user_count = nullptr;
+    if (inten.kind == 2) {
+        st = rtc_function(inten.user, kUserModelUnwMax, &user_max);
+        if (st == HYDRA_PHSP_OK) st = rtc_function(inten.user, kUserModelUnwCount, &user_count);
+        if (st != HYDRA_PHSP_OK) return st;
+    }
 
     hipStream_t s = (hipStream_t)stream;
     UnwWorkspace* ws = nullptr;
@@ -296,18 +311,26 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
     L.u.out = p4_out_dev;
     L.u.ld = ld;
     L.u.index = index_out_dev;
+    L.u.bw = inten.bw;
+    for (int k = 0; k < HYDRA_PHSP_USER_PARAMS; ++k) L.u.upar[k] = inten.upar[k];
     L.max_blocks = max_blocks;
     L.blocks = blocks;
     L.write_blocks = write_blocks;
     L.pmode = pmode;
+    L.intensity = inten.kind == 1 ? 1 : 0;
+    void* uargs[] = {&L.u};
 
     const long slot = timing_begin(s);
     hipError_t e = hipSuccess;
-    // the bound: given, or raised from zero to the largest trial weight by the max pass
+    // the bound: given, or raised from zero to the largest trial value by the max pass
     hipLaunchKernelGGL(k_unw_set, dim3(1), dim3(64), 0, s, ws->w_max, w_max);
     e = hipGetLastError();
-    if (e == hipSuccess && w_max == 0.0 && max_blocks > 0) e = launch_pass_n(n_daughters, 0, L, s);
-    if (e == hipSuccess && blocks > 0) e = launch_pass_n(n_daughters, 1, L, s);
+    if (e == hipSuccess && w_max == 0.0 && max_blocks > 0)
+        e = user_max ? hipModuleLaunchKernel(user_max, (unsigned)max_blocks, 1, 1, kBlock, 1, 1, 0, s, uargs, nullptr)
+                     : launch_pass_n(n_daughters, 0, L, s);
+    if (e == hipSuccess && blocks > 0)
+        e = user_count ? hipModuleLaunchKernel(user_count, (unsigned)blocks, 1, 1, kBlock, 1, 1, 0, s, uargs, nullptr)
+                       : launch_pass_n(n_daughters, 1, L, s);
     const uint64_t groups = (segments + kScanBlock - 1) / kScanBlock;
     if (e == hipSuccess && groups > 0) {
         hipLaunchKernelGGL(k_unw_scan_partial, dim3((unsigned)groups), dim3(kScanBlock), 0, s,
@@ -328,4 +351,62 @@ extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* 
     timing_end(s, slot);
     if (e != hipSuccess) return fail_hip(e, "unweighting kernel launch");
     return HYDRA_PHSP_OK;
+}
+
+} // namespace
+} // namespace hphsp
+
+extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* masses_host, int n_daughters,
+                                              const double* parent_p4_host, uint64_t ntrials, uint64_t seed,
+                                              uint32_t stream_id, uint64_t event_offset, double w_max,
+                                              double* p4_out_dev, uint64_t ld, uint64_t* index_out_dev,
+                                              uint64_t* counts_dev, double* w_max_dev, void* stream) {
+    MarkerRange marker("hydra_phsp_generate_unweighted");
+    Channel ch;
+    const int st = make_channel(parent_mass, masses_host, n_daughters, &ch);
+    if (st != HYDRA_PHSP_OK) return st;
+    return unweighted_run(ch, n_daughters, parent_p4_host, ntrials, seed, stream_id, event_offset, w_max, p4_out_dev,
+                          ld, index_out_dev, counts_dev, w_max_dev, stream, UnwIntensity{});
+}
+
+extern "C" int hydra_phsp_generate_unweighted_model(double parent_mass, const double* masses_host, int n_daughters,
+                                                    const hydra_phsp_breit_wigner* resonances_host, int n_resonances,
+                                                    uint64_t ntrials, uint64_t seed, uint32_t stream_id,
+                                                    uint64_t event_offset, double w_max, double* p4_out_dev,
+                                                    uint64_t ld, uint64_t* index_out_dev, uint64_t* counts_dev,
+                                                    double* w_max_dev, void* stream) {
+    MarkerRange marker("hydra_phsp_generate_unweighted_model");
+    Channel ch;
+    int st = make_channel(parent_mass, masses_host, n_daughters, &ch);
+    if (st != HYDRA_PHSP_OK) return st;
+    UnwIntensity inten;
+    st = make_bw_factors(resonances_host, n_resonances, n_daughters, &inten.bw);
+    if (st != HYDRA_PHSP_OK) return st;
+    // with no factor |A|^2 = 1: the weight-only passes, whose result this is
+    inten.kind = inten.bw.n > 0 ? 1 : 0;
+    return unweighted_run(ch, n_daughters, nullptr, ntrials, seed, stream_id, event_offset, w_max, p4_out_dev, ld,
+                          index_out_dev, counts_dev, w_max_dev, stream, inten);
+}
+
+extern "C" int hydra_phsp_generate_unweighted_user_model(hydra_phsp_user_model* model, double parent_mass,
+                                                         const double* masses_host, const double* params_host,
+                                                         int n_params, uint64_t ntrials, uint64_t seed,
+                                                         uint32_t stream_id, uint64_t event_offset, double w_max,
+                                                         double* p4_out_dev, uint64_t ld, uint64_t* index_out_dev,
+                                                         uint64_t* counts_dev, double* w_max_dev, void* stream) {
+    MarkerRange marker("hydra_phsp_generate_unweighted_user_model");
+    if (model == nullptr) return fail(HYDRA_PHSP_EINVAL, "model is NULL");
+    int n = 0;
+    UnwIntensity inten;
+    inten.kind = 2;
+    inten.user = user_model_kernels(model, &n);
+    Channel ch;
+    int st = make_channel(parent_mass, masses_host, n, &ch);
+    if (st != HYDRA_PHSP_OK) return st;
+    if (n_params < 0 || n_params > HYDRA_PHSP_USER_PARAMS)
+        return fail(HYDRA_PHSP_EINVAL, "n_params must be in [0, HYDRA_PHSP_USER_PARAMS]");
+    if (n_params > 0 && params_host == nullptr) return fail(HYDRA_PHSP_EINVAL, "params_host is NULL");
+    for (int k = 0; k < n_params; ++k) inten.upar[k] = params_host[k];
+    return unweighted_run(ch, n, nullptr, ntrials, seed, stream_id, event_offset, w_max, p4_out_dev, ld,
+                          index_out_dev, counts_dev, w_max_dev, stream, inten);
 }

@@ -13,14 +13,20 @@ static bool grid_ok(uint64_t blocks) { return blocks > 0 && blocks <= 0xFFFFFFFF
 template <>
 hipError_t launch_unw_max<UNW_N>(const UnwLaunch& L, hipStream_t s) {
     if (!grid_ok(L.max_blocks)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_unw_max<UNW_N>), dim3((unsigned)L.max_blocks), dim3(kBlock), 0, s, L.u);
+    if (L.intensity == 1)
+        hipLaunchKernelGGL((k_unw_max<UNW_N, BwIntensity>), dim3((unsigned)L.max_blocks), dim3(kBlock), 0, s, L.u);
+    else
+        hipLaunchKernelGGL((k_unw_max<UNW_N>), dim3((unsigned)L.max_blocks), dim3(kBlock), 0, s, L.u);
     return hipGetLastError();
 }
 
 template <>
 hipError_t launch_unw_count<UNW_N>(const UnwLaunch& L, hipStream_t s) {
     if (!grid_ok(L.blocks)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_unw_count<UNW_N>), dim3((unsigned)L.blocks), dim3(kBlock), 0, s, L.u);
+    if (L.intensity == 1)
+        hipLaunchKernelGGL((k_unw_count<UNW_N, BwIntensity>), dim3((unsigned)L.blocks), dim3(kBlock), 0, s, L.u);
+    else
+        hipLaunchKernelGGL((k_unw_count<UNW_N>), dim3((unsigned)L.blocks), dim3(kBlock), 0, s, L.u);
     return hipGetLastError();
 }
 

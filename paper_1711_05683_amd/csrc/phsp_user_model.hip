@@ -47,15 +47,17 @@ constexpr size_t kMaxLogBytes = 8192;
 
 } // namespace
 
+constexpr int kMaxRtcKernels = 4;
+
 struct RtcKernel {
-    std::vector<char> code; // gfx950 code object
-    std::string symbol;     // the kernel's (lowered) name in it
+    std::vector<char> code;            // gfx950 code object
+    std::vector<std::string> symbols;  // the kernels' (lowered) names in it
     std::mutex mu;
     hipModule_t module[kMaxDevices] = {};
-    hipFunction_t fn[kMaxDevices] = {};
+    hipFunction_t fn[kMaxDevices][kMaxRtcKernels] = {};
 };
 
-int rtc_compile(const std::string& source, const char* kernel, bool name_expr, const char* what, RtcKernel** out) {
+int rtc_compile(const std::string& source, const std::vector<RtcName>& kernels, const char* what, RtcKernel** out) {
     *out = nullptr;
     std::vector<const char*> names, texts;
     names.push_back("hip/hip_runtime.h");
@@ -69,8 +71,13 @@ int rtc_compile(const std::string& source, const char* kernel, bool name_expr, c
                                          names.data());
     if (r != HIPRTC_SUCCESS)
         return fail(HYDRA_PHSP_EDEVICE, std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r));
-    if (name_expr) {
-        r = hiprtcAddNameExpression(prog, kernel);
+    if (kernels.empty() || kernels.size() > (size_t)kMaxRtcKernels) {
+        (void)hiprtcDestroyProgram(&prog);
+        return fail(HYDRA_PHSP_EINVAL, "run-time module kernel count out of range");
+    }
+    for (const RtcName& k : kernels) {
+        if (!k.expression) continue;
+        r = hiprtcAddNameExpression(prog, k.name.c_str());
         if (r != HIPRTC_SUCCESS) {
             (void)hiprtcDestroyProgram(&prog);
             return fail(HYDRA_PHSP_EDEVICE, std::string("hiprtcAddNameExpression: ") + hiprtcGetErrorString(r));
@@ -95,16 +102,19 @@ int rtc_compile(const std::string& source, const char* kernel, bool name_expr, c
         return fail(HYDRA_PHSP_EDEVICE, std::string("hiprtcCompileProgram: ") + hiprtcGetErrorString(r));
     }
     auto* k = new RtcKernel();
-    k->symbol = kernel;
-    if (name_expr) {
+    for (const RtcName& kn : kernels) {
+        if (!kn.expression) {
+            k->symbols.push_back(kn.name);
+            continue;
+        }
         const char* lowered = nullptr;
-        r = hiprtcGetLoweredName(prog, kernel, &lowered);
+        r = hiprtcGetLoweredName(prog, kn.name.c_str(), &lowered);
         if (r != HIPRTC_SUCCESS || lowered == nullptr) {
             (void)hiprtcDestroyProgram(&prog);
             delete k;
             return fail(HYDRA_PHSP_EDEVICE, "hiprtcGetLoweredName failed");
         }
-        k->symbol = lowered;
+        k->symbols.push_back(lowered);
     }
     size_t size = 0;
     r = hiprtcGetCodeSize(prog, &size);
@@ -121,23 +131,28 @@ int rtc_compile(const std::string& source, const char* kernel, bool name_expr, c
     return HYDRA_PHSP_OK;
 }
 
-int rtc_function(RtcKernel* k, hipFunction_t* out) {
+int rtc_function(RtcKernel* k, int which, hipFunction_t* out) {
+    if (which < 0 || which >= (int)k->symbols.size()) return fail(HYDRA_PHSP_EINVAL, "run-time kernel index");
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
     if (dev < 0 || dev >= kMaxDevices) return fail(HYDRA_PHSP_EINVAL, "device index beyond the library's table");
     std::lock_guard<std::mutex> lock(k->mu);
-    if (k->fn[dev] == nullptr) {
-        e = hipModuleLoadData(&k->module[dev], k->code.data());
+    if (k->module[dev] == nullptr) {
+        hipModule_t mod = nullptr;
+        e = hipModuleLoadData(&mod, k->code.data());
         if (e != hipSuccess) return fail_hip(e, "hipModuleLoadData(run-time kernel)");
-        e = hipModuleGetFunction(&k->fn[dev], k->module[dev], k->symbol.c_str());
+        hipFunction_t fns[kMaxRtcKernels] = {};
+        for (size_t i = 0; i < k->symbols.size() && e == hipSuccess; ++i)
+            e = hipModuleGetFunction(&fns[i], mod, k->symbols[i].c_str());
         if (e != hipSuccess) {
-            (void)hipModuleUnload(k->module[dev]);
-            k->module[dev] = nullptr;
+            (void)hipModuleUnload(mod);
             return fail_hip(e, "hipModuleGetFunction(run-time kernel)");
         }
+        k->module[dev] = mod;
+        for (int i = 0; i < kMaxRtcKernels; ++i) k->fn[dev][i] = fns[i];
     }
-    *out = k->fn[dev];
+    *out = k->fn[dev][which];
     return HYDRA_PHSP_OK;
 }
 
@@ -168,6 +183,7 @@ std::string model_source(const char* user, int n) {
     std::string s;
     s += "#define HYDRA_PHSP_N " + std::to_string(n) + "\n";
     s += "#include \"phsp_model.hpp\"\n";
+    s += "#include \"phsp_unweight.hpp\"\n";
     // the user's function is inlined into the event loop (its array arguments
     // are the event's registers)
     s += "__device__ __attribute__((always_inline)) double hydra_phsp_user_intensity(const double* e, "
@@ -182,7 +198,24 @@ std::string model_source(const char* user, int n) {
          "        return hydra_phsp_user_intensity(ev.e, ev.x, ev.y, ev.z, par.p);\n"
          "    });\n"
          "}\n";
+    // the intensity type of the unweighted count and maximum passes
+    s += "struct hydra_phsp_user_intensity_u {\n"
+         "    static constexpr bool kKinematics = true;\n"
+         "    template <int N>\n"
+         "    __device__ __forceinline__ double operator()(const hphsp::UnwArgs& u,\n"
+         "                                                 const hphsp::Event<N, double>& ev) const {\n"
+         "        return hydra_phsp_user_intensity(ev.e, ev.x, ev.y, ev.z, u.upar);\n"
+         "    }\n"
+         "};\n";
     return s;
+}
+
+// The kernels of a user model's module: model evaluation, then the unweighted
+// maximum and count passes.
+std::vector<RtcName> model_kernels(int n) {
+    const std::string t = "<" + std::to_string(n) + ", hydra_phsp_user_intensity_u>";
+    return {RtcName{"hydra_phsp_user_model_kernel", false}, RtcName{"hphsp::k_unw_max" + t, true},
+            RtcName{"hphsp::k_unw_count" + t, true}};
 }
 
 } // namespace
@@ -195,6 +228,15 @@ struct hydra_phsp_user_model {
     RtcKernel* kernel = nullptr;
 };
 
+namespace hphsp {
+
+RtcKernel* user_model_kernels(const hydra_phsp_user_model* model, int* n_daughters) {
+    *n_daughters = model->n;
+    return model->kernel;
+}
+
+} // namespace hphsp
+
 extern "C" int hydra_phsp_user_model_create(const char* source_host, int n_daughters,
                                             hydra_phsp_user_model** model_out) {
     if (model_out == nullptr) return fail(HYDRA_PHSP_EINVAL, "model_out is NULL");
@@ -202,8 +244,7 @@ extern "C" int hydra_phsp_user_model_create(const char* source_host, int n_daugh
     if (source_host == nullptr) return fail(HYDRA_PHSP_EINVAL, "source_host is NULL");
     if (n_daughters < 2 || n_daughters > kNMax) return fail(HYDRA_PHSP_EINVAL, "n_daughters must be in [2, 10]");
     RtcKernel* k = nullptr;
-    const int st = rtc_compile(model_source(source_host, n_daughters), "hydra_phsp_user_model_kernel", false,
-                               "user model", &k);
+    const int st = rtc_compile(model_source(source_host, n_daughters), model_kernels(n_daughters), "user model", &k);
     if (st != HYDRA_PHSP_OK) return st;
     auto* um = new hydra_phsp_user_model();
     um->n = n_daughters;
@@ -247,7 +288,7 @@ extern "C" int hydra_phsp_integrate_user_model(hydra_phsp_user_model* model, dou
     if (blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
         return fail(HYDRA_PHSP_EINVAL, "nevents too large for one launch (more than 2^32 - 1 threads)");
     hipFunction_t fn = nullptr;
-    st = rtc_function(model->kernel, &fn);
+    st = rtc_function(model->kernel, kUserModelKernel, &fn);
     if (st != HYDRA_PHSP_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     Moments* partials = nullptr;

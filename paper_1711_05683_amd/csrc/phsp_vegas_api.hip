@@ -212,7 +212,7 @@ int vegas_iteration(const VegasIntegrand& f, int bins, const double* grid_dev, u
     const int D = f.dim;
     hipFunction_t user_fn = nullptr;
     if (f.user != nullptr) {
-        const int ust = rtc_function(f.user, &user_fn);
+        const int ust = rtc_function(f.user, 0, &user_fn);
         if (ust != HYDRA_PHSP_OK) return ust;
     }
     const uint64_t span = (uint64_t)kVegasBlock * (uint64_t)kVegasEpt;
@@ -454,7 +454,7 @@ int hydra_phsp_user_integrand_create(const char* source_host, int dim, hydra_phs
     if (dim < 1 || dim > HYDRA_PHSP_VEGAS_DMAX) return fail(HYDRA_PHSP_EINVAL, "dim must be in [1, 16]");
     const std::string kernel = "hphsp::k_vegas<" + std::to_string(dim) + ", hydra_phsp_user_integrand_f>";
     RtcKernel* k = nullptr;
-    const int st = rtc_compile(integrand_source(source_host, dim), kernel.c_str(), true, "user integrand", &k);
+    const int st = rtc_compile(integrand_source(source_host, dim), {RtcName{kernel, true}}, "user integrand", &k);
     if (st != HYDRA_PHSP_OK) return st;
     auto* f = new hydra_phsp_user_integrand();
     f->dim = dim;

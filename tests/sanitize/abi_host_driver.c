@@ -179,6 +179,16 @@ static void next_rows(void)
     bw[0].width = 0.0;
     expect(hydra_phsp_integrate_model(5.279, m3, 3, bw, 1, 100, 42, 0, 0, NULL, FAKE(double, 0x100), NULL) ==
                HYDRA_PHSP_EINVAL, "zero width");
+    expect(hydra_phsp_generate_unweighted_model(5.279, m3, 3, bw, 1, 100, 42, 0, 0, 0.0, FAKE(double, 0x100), 128,
+                                                NULL, FAKE(uint64_t, 0x200), NULL, NULL) == HYDRA_PHSP_EINVAL,
+           "unweighted model with a zero width");
+    bw[0].width = 0.0473;
+    expect(hydra_phsp_generate_unweighted_model(5.279, m3, 3, bw, HYDRA_PHSP_MAX_BW + 1, 100, 42, 0, 0, 0.0,
+                                                FAKE(double, 0x100), 128, NULL, FAKE(uint64_t, 0x200), NULL,
+                                                NULL) == HYDRA_PHSP_EINVAL, "unweighted model, too many factors");
+    expect(hydra_phsp_generate_unweighted_model(5.279, m3, 3, bw, 1, 100, 42, 0, 0, 0.0, FAKE(double, 0x100), 128,
+                                                NULL, NULL, NULL, NULL) == HYDRA_PHSP_EINVAL,
+           "unweighted model without counts");
 
     /* VEGAS: the refinement is host code; run it on real grids and histograms */
     enum { D = 3, K = 11 };
@@ -264,6 +274,16 @@ static void user_models(void)
                HYDRA_PHSP_EKINEMATICS, "user model kinematics");
     expect(hydra_phsp_integrate_user_model(NULL, 5.279, m3, par, 2, 100, 42, 0, 0, NULL, FAKE(double, 0x100),
                                            NULL) == HYDRA_PHSP_EINVAL, "no user model");
+    expect(hydra_phsp_generate_unweighted_user_model(um, 5.279, m3, par, HYDRA_PHSP_USER_PARAMS + 1, 100, 42, 0, 0,
+                                                     0.0, FAKE(double, 0x100), 128, NULL, FAKE(uint64_t, 0x200),
+                                                     NULL, NULL) == HYDRA_PHSP_EINVAL,
+           "unweighted user model, too many parameters");
+    expect(hydra_phsp_generate_unweighted_user_model(um, 5.279, m3, par, 2, 100, 42, 0, 0, -1.0,
+                                                     FAKE(double, 0x100), 128, NULL, FAKE(uint64_t, 0x200), NULL,
+                                                     NULL) == HYDRA_PHSP_EINVAL, "unweighted user model bound");
+    expect(hydra_phsp_generate_unweighted_user_model(NULL, 5.279, m3, par, 2, 100, 42, 0, 0, 0.0,
+                                                     FAKE(double, 0x100), 128, NULL, FAKE(uint64_t, 0x200), NULL,
+                                                     NULL) == HYDRA_PHSP_EINVAL, "unweighted without user model");
     expect(hydra_phsp_user_model_destroy(um) == HYDRA_PHSP_OK, "user model destroy");
     hydra_phsp_user_model *bad = NULL;
     expect(hydra_phsp_user_model_create("not a function at all", 3, &bad) == HYDRA_PHSP_EINVAL && bad == NULL,

@@ -292,6 +292,31 @@ def test_model_validation(P):
     assert call([(0, 1, 1.0, 0.1)], M=3.5) == P.EKINEMATICS
 
 
+def test_unweighted_model_validation(P):
+    m, n = P._masses([3.097, 0.4937, 0.13957])
+    f = P.lib().hydra_phsp_generate_unweighted_model
+    out, cnt = ctypes.c_void_p(1024), ctypes.c_void_p(256)
+
+    def call(res=((1, 2, 0.8955, 0.0473),), k=None, M=5.279, w_max=0.0, o=out, ld=128, counts=cnt):
+        arr = (P.BreitWigner * max(len(res), 1))(*[P.BreitWigner(*r) for r in res])
+        return f(M, m, n, ctypes.cast(arr, ctypes.c_void_p), len(res) if k is None else k, 100, 1, 0, 0, w_max, o,
+                 ld, None, counts, None, None)
+
+    assert call([(1, 1, 1.0, 0.1)]) == P.EINVAL
+    assert call([(0, 3, 1.0, 0.1)]) == P.EINVAL
+    assert call([(0, 1, 1.0, 0.0)]) == P.EINVAL
+    assert call([(0, 1, float("nan"), 0.1)]) == P.EINVAL
+    assert call([(0, 1, 1.0, 0.1)] * 5) == P.EINVAL
+    assert call(k=-1) == P.EINVAL
+    assert call(counts=None) == P.EINVAL
+    assert call(w_max=-2.0) == P.EINVAL
+    assert call(w_max=float("inf")) == P.EINVAL
+    assert call(ld=0) == P.EINVAL
+    assert call(counts=ctypes.c_void_p(260)) == P.EINVAL
+    assert call(M=3.5) == P.EKINEMATICS
+    assert f(5.279, None, 3, None, 0, 100, 1, 0, 0, 0.0, out, 128, None, cnt, None, None) == P.EINVAL
+
+
 def test_vegas_validation_and_host_refinement(P):
     import numpy as np
     import oracle

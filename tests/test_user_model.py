@@ -87,6 +87,36 @@ def test_user_model_integrate_validation(P):
         assert P.lib().hydra_phsp_user_model_destroy(h) == P.OK
 
 
+def test_user_model_unweighted_validation(P):
+    """The unweighted sample of a user model checks its arguments before any
+    device work, as the weight-only sample does."""
+    st, h = _create(P, BW_SOURCE, 3)
+    assert st == P.OK
+    f = P.lib().hydra_phsp_generate_unweighted_user_model
+    m = (ctypes.c_double * 3)(3.097, 0.4937, 0.13957)
+    par = (ctypes.c_double * 2)(0.8955, 0.0473)
+    out, cnt = ctypes.c_void_p(1024), ctypes.c_void_p(256)
+
+    def call(model=h, M=5.279, mm=m, pp=par, k=2, w_max=0.0, o=out, ld=128, counts=cnt):
+        return f(model, M, mm, pp, k, 100, 1, 0, 0, w_max, o, ld, None, counts, None, None)
+
+    try:
+        assert call(model=None) == P.EINVAL
+        assert "model" in P.lib().hydra_phsp_last_error().decode()
+        assert call(k=17) == P.EINVAL
+        assert call(k=-1) == P.EINVAL
+        assert call(pp=None) == P.EINVAL
+        assert call(counts=None) == P.EINVAL
+        assert call(w_max=-1.0) == P.EINVAL
+        assert call(w_max=float("nan")) == P.EINVAL
+        assert call(ld=0) == P.EINVAL
+        assert call(o=ctypes.c_void_p(1028)) == P.EINVAL
+        assert call(M=3.5) == P.EKINEMATICS
+        assert call(mm=None) == P.EINVAL
+    finally:
+        assert P.lib().hydra_phsp_user_model_destroy(h) == P.OK
+
+
 def test_user_model_binding_checks_daughter_count(P):
     model = P.UserModel(BW_SOURCE, 3)
     try:
@@ -94,6 +124,10 @@ def test_user_model_binding_checks_daughter_count(P):
             model.integrate(5.279, [3.097, 0.4937], 100, [0.8955, 0.0473])
         with pytest.raises(ValueError):
             model.integrate(5.279, [3.097, 0.4937, 0.13957], 100, [0.0] * 17)
+        with pytest.raises(ValueError):
+            model.generate_unweighted(5.279, [3.097, 0.4937], 100, [0.8955, 0.0473])
+        with pytest.raises(ValueError):
+            model.generate_unweighted(5.279, [3.097, 0.4937, 0.13957], 100, [0.0] * 17)
     finally:
         model.destroy()
     with pytest.raises(P.PhspError):

@@ -190,7 +190,7 @@ def test_unweighted_model_full_size(P):
 
     def one(e):
         op4, _ = oracle.generate(M, m, 1, seed=42, event_offset=int(e))
-        _, _, v = oracle.model_integrate(M, m, 1, res, seed=42, event_offset=int(e), want_values=True)
+        _, _, v = oracle.model_integrate(M, m, 2, res, seed=42, event_offset=int(e), want_values=True)
         return op4, float(v[0]), oracle.accept_uniform(42, 0, int(e), 3)
 
     rng = np.random.default_rng(1)

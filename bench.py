@@ -651,10 +651,19 @@ def unweighted_extra(P, torch, dev, M, m, n, out, steps):
     ms1, k1 = time_steps(lambda: P.generate_unweighted(M, m, n, w_max=w_max, out=out, counts=cnt, w_max_out=wmo),
                          steps, 1, torch)
     bytes_kept = kept * 8 * 4 * len(m)
+    # the same sequence with its passes one after the other (one chunk: count,
+    # scan, then write) instead of the default four-chunk pipeline
+    P.set_unweight_chunks(1)
+    try:
+        _, k1_serial = time_steps(lambda: P.generate_unweighted(M, m, n, w_max=w_max, out=out, counts=cnt,
+                                                                w_max_out=wmo), steps, 1, torch)
+    finally:
+        P.set_unweight_chunks(0)
     r = {"trials": n, "kept": kept, "kept_fraction": kept / n, "w_max": w_max, "over_bound": over,
          "ms_sample_max": k0, "ms_given_bound": k1, "trials_per_s_given_bound": n / (k1 * 1e-3),
          "kept_per_s_given_bound": kept / (k1 * 1e-3), "kept_per_s_sample_max": kept / (k0 * 1e-3),
-         "write_GBs_given_bound": bytes_kept / (k1 * 1e-3) / 1e9}
+         "write_GBs_given_bound": bytes_kept / (k1 * 1e-3) / 1e9, "frac_of_8TBs_given_bound":
+         bytes_kept / (k1 * 1e-3) / 8e12, "chunks": 4, "ms_given_bound_one_chunk": k1_serial}
     # samples of the one-factor K pi model (kept events follow w |A|^2), built in
     # and as the same intensity compiled at run time
     one = [(1, 2, 0.8955, 0.0473)]

@@ -54,6 +54,17 @@ int hydra_phsp_generate_unweighted(double parent_mass, const double *masses_host
                                    double *p4_out_dev, uint64_t ld, uint64_t *index_out_dev,
                                    uint64_t *counts_dev, double *w_max_dev, void *stream);
 
+/* Pipeline depth of the unweighted calls that store events, process-wide: the
+ * trials are cut into at most `chunks` chunks (each at least 262144 trials), and
+ * one launch stores the kept events of a chunk while it computes the keep
+ * decisions of the next.  1 runs the passes one after the other; 0 restores the
+ * defaults: 4 for acceptance against the weight alone, 1 for Breit-Wigner
+ * models (their kept fraction is usually small, so there is little store work
+ * to overlap and each chunk costs a scan and a launch tail).  User models
+ * (compiled at run time) always take one chunk.  The results are the same for
+ * every value.  EINVAL outside [0, 16]. */
+int hydra_phsp_set_unweight_chunks(int chunks);
+
 /* Unweighted samples of a model (sec. 4.2 lists weighted and unweighted
  * samples and model evaluation together): trial event g is kept when
  * v_g * w_max < w_g |A|^2(g), with |A|^2 the product of Breit-Wigner factors of

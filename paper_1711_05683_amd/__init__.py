@@ -60,6 +60,8 @@ def _declare(lib):
     lib.hydra_phsp_release.restype = i
     lib.hydra_phsp_set_events_per_thread.argtypes = [i, i]
     lib.hydra_phsp_set_events_per_thread.restype = i
+    lib.hydra_phsp_set_unweight_chunks.argtypes = [i]
+    lib.hydra_phsp_set_unweight_chunks.restype = i
     lib.hydra_phsp_events_per_thread.argtypes = [i, i, i]
     lib.hydra_phsp_events_per_thread.restype = i
     lib.hydra_phsp_timing_enable.argtypes = [i]
@@ -640,6 +642,11 @@ def release():
 def set_events_per_thread(path: int, ept: int):
     """Events per thread for path 0 (integrate), 1 (FP64) or 2 (mixed); 0 = default."""
     _check(lib().hydra_phsp_set_events_per_thread(path, ept))
+
+
+def set_unweight_chunks(chunks: int):
+    """Pipeline depth of unweighted calls that store events (0 = default, 1 = no overlap)."""
+    _check(lib().hydra_phsp_set_unweight_chunks(chunks))
 
 
 def events_per_thread(path: int, n_daughters: int, per_event_parents: bool = False,

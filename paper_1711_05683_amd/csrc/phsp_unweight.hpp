@@ -18,7 +18,14 @@
 //          store covers whole lines; the kinematics are recomputed from the
 //          counters (identical to the weighted events).
 // Between count and write the per-segment counts are scanned and each range's
-// first segment is recorded (phsp_unweight_api.hip).
+// first segment is recorded (phsp_unweight_api.hip).  The trials may be cut into
+// chunks of whole scan groups: count and scan run chunk after chunk, each chunk
+// carrying the kept total of the ones before it, and the write pass of a chunk
+// covers the output positions its scan has settled.  A fused launch then gives
+// every wave one output range of chunk k to store and one segment of chunk k+1
+// to count, so the store-bound and the arithmetic-bound work share the compute
+// units.  The kept set, its order and every stored value are the same for any
+// chunking.
 #pragma once
 
 #include "phsp_kernels.hpp"
@@ -55,8 +62,11 @@ struct UnwArgs {
     uint64_t* masks;           // NULL (count only), or [segments * kUnwSegWords] keep bits
     const uint64_t* offsets;   // [segments] kept events before the segment
     const uint64_t* range_seg; // [ranges] segment holding output position r * kUnwRange
-    const uint64_t* totals;    // [0]: kept trials (the caller's counts)
-    uint64_t segments;
+    const uint64_t* chunk_kept; // [chunks] kept trials of chunks 0..k together
+    uint64_t cnt_lo, cnt_hi;   // count pass: its segments [cnt_lo, cnt_hi)
+    uint64_t segments;         // write pass: segments counted so far (mask words it may read)
+    uint32_t chunk;            // write pass: the chunk whose settled positions it stores
+    uint32_t last_chunk;       // write pass: nonzero for the last chunk (it stores every remaining position)
     double* out;               // kept events, [N][4][ld]
     uint64_t ld;               // capacity in events
     uint64_t* index;           // NULL, or [ld] global index of each kept event
@@ -141,16 +151,12 @@ __global__ __launch_bounds__(kBlock) void k_unw_max(const UnwArgs u) {
 }
 
 // Keep decisions and counts of each segment (the values only: no stores).  Wave
-// w of block b takes segment s = kUnwSegPerBlock b + w; step k covers its trials
-// s kUnwSeg + 64 k + lane, and the step's ballot is the segment's mask word k.
-template <int N, class I = NoIntensity>
-__global__ __launch_bounds__(kBlock) void k_unw_count(const UnwArgs u) {
-    __shared__ double2 tab[I::kKinematics ? kTrigSize : 1];
-    if constexpr (I::kKinematics) load_trig(tab, u.a.trig); // before any wave leaves
-    const uint64_t seg = (uint64_t)blockIdx.x * kUnwSegPerBlock +
-                         (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (seg >= u.segments) return;
-    const uint32_t lane = threadIdx.x & 63;
+// w of block b takes segment s = seg_lo + kUnwSegPerBlock b + w; step k covers
+// its trials s kUnwSeg + 64 k + lane, and the step's ballot is the segment's
+// mask word k.
+template <int N, class I>
+__device__ __forceinline__ void unw_count_segment(const UnwArgs& u, uint64_t seg, uint32_t lane,
+                                                  const double2* tab) {
     const uint64_t base = seg * (uint64_t)kUnwSeg;
     const double wmax = *u.w_max;
     uint32_t kept = 0, over = 0;
@@ -172,9 +178,30 @@ __global__ __launch_bounds__(kBlock) void k_unw_count(const UnwArgs u) {
     if (lane == 0) u.counts[seg] = make_uint2(kept, over);
 }
 
-// Kept trials with full kinematics at their places in trial order.  Wave w of
-// block b takes the output range r = kUnwSegPerBlock b + w, positions
-// [r kUnwRange, min((r + 1) kUnwRange, kept, ld)).  Its first position lies in
+template <int N, class I = NoIntensity>
+__global__ __launch_bounds__(kBlock) void k_unw_count(const UnwArgs u) {
+    __shared__ double2 tab[I::kKinematics ? kTrigSize : 1];
+    if constexpr (I::kKinematics) load_trig(tab, u.a.trig); // before any wave leaves
+    const uint64_t seg = u.cnt_lo + (uint64_t)blockIdx.x * kUnwSegPerBlock +
+                         (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (seg < u.cnt_hi) unw_count_segment<N, I>(u, seg, threadIdx.x & 63, tab);
+}
+
+// Output positions whose trials are settled once chunks 0..k are counted and
+// scanned, K the kept total of those chunks: all of them below ld when K >= ld,
+// all K for the last chunk, else the whole ranges below K (the range holding K
+// may still take trials of the next chunk).
+__device__ __forceinline__ uint64_t unw_settled(uint64_t K, uint64_t ld, bool last) {
+    if (K >= ld) return ld;
+    return last ? K : K / kUnwRange * kUnwRange;
+}
+
+// Kept trials with full kinematics at their places in trial order, for the
+// output positions [p0, p1) chunk k settles (p0 those settled before it, a
+// multiple of kUnwRange unless it is ld).  The idx-th wave of the launch takes
+// the output range r = p0 / kUnwRange + idx, positions
+// [r kUnwRange, min((r + 1) kUnwRange, p1)) (list: its row of LDS).  Its first
+// position lies in
 // the run of segment range_seg[r]; the wave walks that segment's mask words
 // and the following ones (64 words per vector load, one word per step: the
 // lanes whose bit is set write their trial's offset at their rank), skipping
@@ -186,17 +213,13 @@ __global__ __launch_bounds__(kBlock) void k_unw_count(const UnwArgs u) {
 // spread over more than kUnwSpanLimit trials (kept fraction below about 5e-7),
 // the list is stored and a new one started from the next word.
 template <int N, int PMODE>
-__global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
-    __shared__ double2 tab[kTrigSize];
-    __shared__ uint32_t list[kUnwSegPerBlock][kUnwRange];
-    load_trig(tab, u.a.trig);
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t lane = threadIdx.x & 63;
-    const uint64_t range = (uint64_t)blockIdx.x * kUnwSegPerBlock + wave;
-    const uint64_t kept = u.totals[0];
-    const uint64_t stop = kept < u.ld ? kept : u.ld; // capacity truncates
+__device__ __forceinline__ void unw_write_range(const UnwArgs& u, uint64_t idx, uint32_t lane, const double2* tab,
+                                                uint32_t* list) {
+    const uint64_t p0 = u.chunk > 0 ? unw_settled(u.chunk_kept[u.chunk - 1], u.ld, false) : 0;
+    const uint64_t stop = unw_settled(u.chunk_kept[u.chunk], u.ld, u.last_chunk != 0); // capacity truncates
+    const uint64_t range = p0 / kUnwRange + idx;
     uint64_t pos = range * (uint64_t)kUnwRange;
-    if (pos >= stop) return; // no barrier follows
+    if (pos >= stop || p0 >= stop) return; // p0 = ld = stop: nothing left to store
     const uint64_t r1 = pos + kUnwRange < stop ? pos + kUnwRange : stop;
     const uint64_t seg = u.range_seg[range];
     uint64_t skip = pos - u.offsets[seg];                 // the segment's kept trials before the range
@@ -225,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                 const uint32_t at = n + rank - (uint32_t)skip; // list slot of this lane's trial
                 if (((m >> lane) & 1u) && rank >= (uint32_t)skip && at < want)
-                    list[wave][at] = (uint32_t)((word + (uint64_t)j) * 64 - tbase) + lane;
+                    list[at] = (uint32_t)((word + (uint64_t)j) * 64 - tbase) + lane;
                 n += cnt - (uint32_t)skip;
                 skip = 0;
             }
@@ -239,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
         for (uint32_t c = 0; c < n; c += 64) {
             const uint32_t q = c + lane;
             if (q >= n) continue;
-            const uint32_t off = list[wave][q];
+            const uint32_t off = list[q];
             double* const o = u.out + (pos + q);
             (void)emit_event<N, PMODE, kFp64>(u.a, tbase, off, tab,
                                               [&](int k, double e, double x, double y, double z) {
@@ -261,11 +284,38 @@ __global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
     }
 }
 
+template <int N, int PMODE>
+__global__ __launch_bounds__(kBlock) void k_unw_write(const UnwArgs u) {
+    __shared__ double2 tab[kTrigSize];
+    __shared__ uint32_t list[kUnwSegPerBlock][kUnwRange];
+    load_trig(tab, u.a.trig);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    unw_write_range<N, PMODE>(u, (uint64_t)blockIdx.x * kUnwSegPerBlock + wave, threadIdx.x & 63, tab, list[wave]);
+}
+
+// Fused launch: wave g counts segment u.cnt_lo + g of the next chunk, then
+// stores the g-th output range chunk u.chunk settles (the two touch disjoint
+// mask words: the write reads only the u.segments segments counted before).
+// (Counting first also keeps the compiler from reserving a scratch slot.)
+template <int N, int PMODE, class I = NoIntensity>
+__global__ __launch_bounds__(kBlock) void k_unw_write_count(const UnwArgs u) {
+    __shared__ double2 tab[kTrigSize];
+    __shared__ uint32_t list[kUnwSegPerBlock][kUnwRange];
+    load_trig(tab, u.a.trig);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t g = (uint64_t)blockIdx.x * kUnwSegPerBlock + wave;
+    const uint64_t seg = u.cnt_lo + g;
+    if (seg < u.cnt_hi) unw_count_segment<N, I>(u, seg, lane, tab);
+    unw_write_range<N, PMODE>(u, g, lane, tab, list[wave]);
+}
+
 struct UnwLaunch {
     UnwArgs u;
     uint64_t max_blocks; // max pass: kBlock * kUnwEpt trials per block
-    uint64_t blocks;     // count pass: kUnwSegPerBlock segments per block
-    uint64_t write_blocks; // write pass: kUnwSegPerBlock ranges of kUnwRange output positions per block
+    uint64_t blocks;     // count pass (one chunk): kUnwSegPerBlock segments per block
+    uint64_t write_blocks; // write pass (one chunk): kUnwSegPerBlock ranges of kUnwRange output positions per block
+                           // (fused pass: also its count segments)
     int intensity;       // max and count passes: 0 the weight alone, 1 the Breit-Wigner model (u.bw)
     int pmode;           // kAtRest or kBroadcast (write pass)
 };
@@ -277,5 +327,7 @@ template <int N>
 hipError_t launch_unw_count(const UnwLaunch& L, hipStream_t s);
 template <int N>
 hipError_t launch_unw_write(const UnwLaunch& L, hipStream_t s);
+template <int N>
+hipError_t launch_unw_write_count(const UnwLaunch& L, hipStream_t s);
 
 } // namespace hphsp

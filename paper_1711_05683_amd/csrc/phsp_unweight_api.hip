@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -42,15 +43,18 @@ __device__ __forceinline__ uint64_t block_inclusive_scan(uint64_t v, uint64_t* s
     return v + add;
 }
 
-// Stage 1: kept and over-bound trials of each group of kScanBlock segments.
-__global__ __launch_bounds__(kScanBlock) void k_unw_scan_partial(const uint2* __restrict__ counts, uint64_t segments,
-                                                                 uint64_t* __restrict__ sums,
+// Stage 1: kept and over-bound trials of each group of kScanBlock segments, for
+// the groups of one chunk (segments [seg_lo, segments), seg_lo a multiple of
+// kScanBlock; block b takes group g = seg_lo / kScanBlock + b).
+__global__ __launch_bounds__(kScanBlock) void k_unw_scan_partial(const uint2* __restrict__ counts, uint64_t seg_lo,
+                                                                 uint64_t segments, uint64_t* __restrict__ sums,
                                                                  uint64_t* __restrict__ over_sums) {
     __shared__ uint64_t sm[kScanBlock / 64];
-    const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const uint64_t g = seg_lo / kScanBlock + blockIdx.x;
+    const uint64_t i = g * kScanBlock + threadIdx.x;
     const uint64_t v = i < segments ? counts[i].x : 0u;
     const uint64_t inc = block_inclusive_scan<kScanBlock>(v, sm);
-    if (threadIdx.x == kScanBlock - 1) sums[blockIdx.x] = inc;
+    if (threadIdx.x == kScanBlock - 1) sums[g] = inc;
     uint64_t o = i < segments ? counts[i].y : 0u;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) o += __shfl_xor(o, off, 64);
@@ -60,21 +64,26 @@ __global__ __launch_bounds__(kScanBlock) void k_unw_scan_partial(const uint2* __
         uint64_t t = 0;
 #pragma unroll
         for (int w = 0; w < kScanBlock / 64; ++w) t += sm[w];
-        over_sums[blockIdx.x] = t;
+        over_sums[g] = t;
     }
 }
 
-// Stage 2 (one block): exclusive prefix of the group sums, in place, and the
-// totals (kept, over-bound) into the caller's counts; the bound applied into the
-// caller's w_max output when asked.
+// Stage 2 (one block per chunk): exclusive prefix of the chunk's group sums, in
+// place, starting from the kept total of the chunks before it; that total plus
+// the chunk's into chunk_kept[chunk], the chunk's over-bound trials into
+// chunk_over[chunk].  The last chunk also writes the totals (kept, over-bound)
+// into the caller's counts and the bound applied into the caller's w_max output
+// when asked.
 __global__ __launch_bounds__(kScanTop) void k_unw_scan_top(uint64_t* __restrict__ sums, uint64_t groups,
                                                            const uint64_t* __restrict__ over_sums,
-                                                           uint64_t* __restrict__ totals,
+                                                           uint64_t* __restrict__ chunk_kept,
+                                                           uint64_t* __restrict__ chunk_over, uint32_t chunk,
+                                                           uint32_t last_chunk, uint64_t* __restrict__ totals,
                                                            const double* __restrict__ w_max,
                                                            double* __restrict__ w_max_out) {
     __shared__ uint64_t sm[kScanTop / 64];
     __shared__ uint64_t last;
-    uint64_t carry = 0;
+    uint64_t carry = chunk > 0 ? chunk_kept[chunk - 1] : 0;
     for (uint64_t b0 = 0; b0 < groups; b0 += kScanTop) {
         const uint64_t i = b0 + threadIdx.x;
         const uint64_t v = i < groups ? sums[i] : 0u;
@@ -95,9 +104,14 @@ __global__ __launch_bounds__(kScanTop) void k_unw_scan_top(uint64_t* __restrict_
     if (threadIdx.x == 0) {
         uint64_t o = 0;
         for (int w = 0; w < kScanTop / 64; ++w) o += sm[w];
-        totals[0] = carry;
-        totals[1] = o;
-        if (w_max_out != nullptr) *w_max_out = *w_max;
+        chunk_kept[chunk] = carry;
+        chunk_over[chunk] = o;
+        if (last_chunk) {
+            for (uint32_t c = 0; c < chunk; ++c) o += chunk_over[c];
+            totals[0] = carry;
+            totals[1] = o;
+            if (w_max_out != nullptr) *w_max_out = *w_max;
+        }
     }
 }
 
@@ -107,20 +121,29 @@ __global__ __launch_bounds__(kScanTop) void k_unw_scan_top(uint64_t* __restrict_
 // (a run is at most kUnwSeg long, so it holds at most kUnwSeg / kUnwRange
 // starts, and the runs tile [0, kept), so every range start has its segment).
 static_assert(kUnwSeg % kUnwRange == 0, "whole ranges per segment");
-__global__ __launch_bounds__(kScanBlock) void k_unw_scan_finish(const uint2* __restrict__ counts, uint64_t segments,
-                                                                const uint64_t* __restrict__ sums,
+// Segments [seg_lo, segments) of one chunk; seg_lo is a multiple of kScanBlock,
+// so block b scans group seg_lo / kScanBlock + b.
+__global__ __launch_bounds__(kScanBlock) void k_unw_scan_finish(const uint2* __restrict__ counts, uint64_t seg_lo,
+                                                                uint64_t segments, const uint64_t* __restrict__ sums,
                                                                 uint64_t* __restrict__ offsets,
                                                                 uint64_t* __restrict__ range_seg) {
     __shared__ uint64_t sm[kScanBlock / 64];
-    const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const uint64_t i = seg_lo + (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
     const uint64_t v = i < segments ? counts[i].x : 0u;
     const uint64_t inc = block_inclusive_scan<kScanBlock>(v, sm);
     if (i < segments) {
-        const uint64_t o = sums[blockIdx.x] + inc - v;
+        const uint64_t o = sums[seg_lo / kScanBlock + blockIdx.x] + inc - v;
         offsets[i] = o;
         for (uint64_t r = (o + kUnwRange - 1) / kUnwRange; r * kUnwRange < o + v; ++r) range_seg[r] = i;
     }
 }
+
+// Chunks of the count-scan-write pipeline: at most kMaxChunks, each of whole
+// scan groups (kScanBlock segments, 262144 trials).
+constexpr int kMaxChunks = 16;
+constexpr int kDefaultChunks = 4;      // acceptance against the weight alone
+constexpr int kDefaultChunksModel = 1; // against a model: few trials kept, so little store work to overlap
+std::atomic<int> g_chunks_override{0};
 
 namespace {
 
@@ -132,6 +155,8 @@ struct UnwWorkspace {
     uint64_t* sums = nullptr;      // [groups] kept trials per group of kScanBlock segments
     uint64_t* over_sums = nullptr; // [groups] over-bound trials per group
     double* w_max = nullptr;
+    uint64_t* chunk_kept = nullptr; // [kMaxChunks] kept trials of chunks 0..k together
+    uint64_t* chunk_over = nullptr; // [kMaxChunks] over-bound trials per chunk
     uint64_t capacity = 0;         // segments
     uint64_t mask_capacity = 0;    // segments
 };
@@ -147,7 +172,12 @@ void free_ws(UnwWorkspace& w) {
     if (w.sums) (void)hipFree(w.sums);
     if (w.over_sums) (void)hipFree(w.over_sums);
     if (w.w_max) (void)hipFree(w.w_max);
-    w = UnwWorkspace{};
+    if (w.chunk_kept) (void)hipFree(w.chunk_kept);
+    if (w.chunk_over) (void)hipFree(w.chunk_over);
+    w.counts = nullptr;
+    w.offsets = w.range_seg = w.masks = w.sums = w.over_sums = w.chunk_kept = w.chunk_over = nullptr;
+    w.w_max = nullptr;
+    w.capacity = w.mask_capacity = 0;
 }
 
 int unw_workspace(hipStream_t stream, uint64_t segments, bool masks, UnwWorkspace** out) {
@@ -183,7 +213,9 @@ int unw_workspace(hipStream_t stream, uint64_t segments, bool masks, UnwWorkspac
                   hipMalloc(&w.range_seg, sizeof(uint64_t) * cap * (kUnwSeg / kUnwRange)) == hipSuccess &&
                   hipMalloc(&w.sums, sizeof(uint64_t) * groups) == hipSuccess &&
                   hipMalloc(&w.over_sums, sizeof(uint64_t) * groups) == hipSuccess &&
-                  hipMalloc(&w.w_max, sizeof(double)) == hipSuccess;
+                  hipMalloc(&w.w_max, sizeof(double)) == hipSuccess &&
+                  hipMalloc(&w.chunk_kept, sizeof(uint64_t) * kMaxChunks) == hipSuccess &&
+                  hipMalloc(&w.chunk_over, sizeof(uint64_t) * kMaxChunks) == hipSuccess;
         if (!ok) {
             free_ws(w);
             return fail(HYDRA_PHSP_ENOMEM, "unweighting workspace allocation failed");
@@ -199,7 +231,8 @@ hipError_t launch_pass(int pass, const UnwLaunch& L, hipStream_t s) {
     switch (pass) {
     case 0: return launch_unw_max<N>(L, s);
     case 1: return launch_unw_count<N>(L, s);
-    default: return launch_unw_write<N>(L, s);
+    case 2: return launch_unw_write<N>(L, s);
+    default: return launch_unw_write_count<N>(L, s);
     }
 }
 
@@ -266,13 +299,31 @@ int unweighted_run(const Channel& ch, int n_daughters, const double* parent_p4_h
     }
     const uint64_t max_blocks = ceil_div(ntrials, (uint64_t)kBlock * (uint64_t)kUnwEpt);
     const uint64_t segments = ceil_div(ntrials, (uint64_t)kUnwSeg);
-    const uint64_t blocks = ceil_div(segments, (uint64_t)kUnwSegPerBlock);
     const bool outputs = p4_out_dev != nullptr || index_out_dev != nullptr;
-    // write pass: one wave per range of output positions that can be filled
-    const uint64_t write_blocks =
-        outputs ? ceil_div(std::min(ntrials, ld), (uint64_t)kUnwRange * (uint64_t)kUnwSegPerBlock) : 0;
+    // Chunks of whole scan groups; without outputs there is no write pass to
+    // overlap, so one chunk.
+    const uint64_t groups = ceil_div(segments, (uint64_t)kScanBlock);
+    const int want_chunks = g_chunks_override.load(std::memory_order_relaxed);
+    // (a user model's count kernel is compiled at run time, without a fused form)
+    const int default_chunks = inten.kind == 0 ? kDefaultChunks : kDefaultChunksModel;
+    const uint64_t chunks_req =
+        outputs && inten.kind != 2 ? (uint64_t)(want_chunks > 0 ? want_chunks : default_chunks) : 1;
+    const uint64_t chunk_groups = std::max<uint64_t>(ceil_div(groups, chunks_req), 1);
+    const uint64_t chunk_segs = chunk_groups * kScanBlock;
+    const uint64_t nchunks = std::max<uint64_t>(ceil_div(segments, chunk_segs), 1);
+    // count pass: one wave per segment; write pass: one wave per range of output
+    // positions a chunk can settle (its trials plus the partial range carried in)
+    const uint64_t blocks = ceil_div(std::min(segments, chunk_segs), (uint64_t)kUnwSegPerBlock);
+    const uint64_t write_ranges =
+        outputs ? std::min(ceil_div(std::min(ntrials, chunk_segs * (uint64_t)kUnwSeg), (uint64_t)kUnwRange) + 1,
+                           ceil_div(ld, (uint64_t)kUnwRange))
+                : 0;
+    const uint64_t write_blocks = ceil_div(write_ranges, (uint64_t)kUnwSegPerBlock);
+    // fused pass: a wave per output range of chunk k or per segment of chunk k + 1
+    const uint64_t fused_blocks =
+        nchunks > 1 ? ceil_div(std::max(write_ranges, chunk_segs), (uint64_t)kUnwSegPerBlock) : 0;
     if (max_blocks > 0xFFFFFFFFull / (uint64_t)kBlock || blocks > 0xFFFFFFFFull / (uint64_t)kBlock ||
-        write_blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
+        write_blocks > 0xFFFFFFFFull / (uint64_t)kBlock || fused_blocks > 0xFFFFFFFFull / (uint64_t)kBlock)
         return fail(HYDRA_PHSP_EINVAL, "ntrials too large for one launch (more than 2^32 - 1 threads)");
     hipFunction_t user_max = nullptr, user_count = nullptr;
     if (inten.kind == 2) {
@@ -306,16 +357,13 @@ int unweighted_run(const Channel& ch, int n_daughters, const double* parent_p4_h
     L.u.masks = outputs ? ws->masks : nullptr;
     L.u.offsets = ws->offsets;
     L.u.range_seg = ws->range_seg;
-    L.u.totals = counts_dev;
-    L.u.segments = segments;
+    L.u.chunk_kept = ws->chunk_kept;
     L.u.out = p4_out_dev;
     L.u.ld = ld;
     L.u.index = index_out_dev;
     L.u.bw = inten.bw;
     for (int k = 0; k < HYDRA_PHSP_USER_PARAMS; ++k) L.u.upar[k] = inten.upar[k];
     L.max_blocks = max_blocks;
-    L.blocks = blocks;
-    L.write_blocks = write_blocks;
     L.pmode = pmode;
     L.intensity = inten.kind == 1 ? 1 : 0;
     void* uargs[] = {&L.u};
@@ -328,26 +376,52 @@ int unweighted_run(const Channel& ch, int n_daughters, const double* parent_p4_h
     if (e == hipSuccess && w_max == 0.0 && max_blocks > 0)
         e = user_max ? hipModuleLaunchKernel(user_max, (unsigned)max_blocks, 1, 1, kBlock, 1, 1, 0, s, uargs, nullptr)
                      : launch_pass_n(n_daughters, 0, L, s);
-    if (e == hipSuccess && blocks > 0)
-        e = user_count ? hipModuleLaunchKernel(user_count, (unsigned)blocks, 1, 1, kBlock, 1, 1, 0, s, uargs, nullptr)
+    // Chunk 0 is counted alone; then for each chunk k its scan, and its write pass
+    // fused with the count of chunk k + 1 (the last chunk's write pass alone).
+    auto count_range = [&](uint64_t k) {
+        L.u.cnt_lo = k * chunk_segs;
+        L.u.cnt_hi = std::min(segments, L.u.cnt_lo + chunk_segs);
+    };
+    count_range(0);
+    L.blocks = ceil_div(L.u.cnt_hi - L.u.cnt_lo, (uint64_t)kUnwSegPerBlock);
+    if (e == hipSuccess && L.blocks > 0)
+        e = user_count ? hipModuleLaunchKernel(user_count, (unsigned)L.blocks, 1, 1, kBlock, 1, 1, 0, s, uargs, nullptr)
                        : launch_pass_n(n_daughters, 1, L, s);
-    const uint64_t groups = (segments + kScanBlock - 1) / kScanBlock;
-    if (e == hipSuccess && groups > 0) {
-        hipLaunchKernelGGL(k_unw_scan_partial, dim3((unsigned)groups), dim3(kScanBlock), 0, s,
-                           (const uint2*)ws->counts, segments, ws->sums, ws->over_sums);
-        e = hipGetLastError();
+    for (uint64_t k = 0; e == hipSuccess && k < nchunks; ++k) {
+        const uint64_t seg_lo = k * chunk_segs, seg_hi = std::min(segments, seg_lo + chunk_segs);
+        const uint64_t g_lo = seg_lo / kScanBlock, g_n = ceil_div(seg_hi - seg_lo, (uint64_t)kScanBlock);
+        const bool last = k + 1 == nchunks;
+        if (g_n > 0) {
+            hipLaunchKernelGGL(k_unw_scan_partial, dim3((unsigned)g_n), dim3(kScanBlock), 0, s,
+                               (const uint2*)ws->counts, seg_lo, seg_hi, ws->sums, ws->over_sums);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_unw_scan_top, dim3(1), dim3(kScanTop), 0, s, ws->sums + g_lo, g_n,
+                               (const uint64_t*)ws->over_sums + g_lo, ws->chunk_kept, ws->chunk_over, (uint32_t)k,
+                               last ? 1u : 0u, counts_dev, (const double*)ws->w_max, w_max_dev);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess && g_n > 0 && outputs) {
+            hipLaunchKernelGGL(k_unw_scan_finish, dim3((unsigned)g_n), dim3(kScanBlock), 0, s,
+                               (const uint2*)ws->counts, seg_lo, seg_hi, (const uint64_t*)ws->sums, ws->offsets,
+                               ws->range_seg);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess && outputs) {
+            L.u.segments = seg_hi;
+            L.u.chunk = (uint32_t)k;
+            L.u.last_chunk = last ? 1u : 0u;
+            if (last) {
+                L.write_blocks = write_blocks;
+                e = launch_pass_n(n_daughters, 2, L, s);
+            } else {
+                count_range(k + 1);
+                L.write_blocks = fused_blocks;
+                e = launch_pass_n(n_daughters, 3, L, s);
+            }
+        }
     }
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_unw_scan_top, dim3(1), dim3(kScanTop), 0, s, ws->sums, groups,
-                           (const uint64_t*)ws->over_sums, counts_dev, (const double*)ws->w_max, w_max_dev);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess && groups > 0 && outputs) {
-        hipLaunchKernelGGL(k_unw_scan_finish, dim3((unsigned)groups), dim3(kScanBlock), 0, s, (const uint2*)ws->counts,
-                           segments, (const uint64_t*)ws->sums, ws->offsets, ws->range_seg);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess && write_blocks > 0) e = launch_pass_n(n_daughters, 2, L, s);
     timing_end(s, slot);
     if (e != hipSuccess) return fail_hip(e, "unweighting kernel launch");
     return HYDRA_PHSP_OK;
@@ -355,6 +429,12 @@ int unweighted_run(const Channel& ch, int n_daughters, const double* parent_p4_h
 
 } // namespace
 } // namespace hphsp
+
+extern "C" int hydra_phsp_set_unweight_chunks(int chunks) {
+    if (chunks < 0 || chunks > kMaxChunks) return fail(HYDRA_PHSP_EINVAL, "chunks must be in [0, 16]");
+    g_chunks_override.store(chunks, std::memory_order_relaxed);
+    return HYDRA_PHSP_OK;
+}
 
 extern "C" int hydra_phsp_generate_unweighted(double parent_mass, const double* masses_host, int n_daughters,
                                               const double* parent_p4_host, uint64_t ntrials, uint64_t seed,

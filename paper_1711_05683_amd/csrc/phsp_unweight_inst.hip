@@ -40,4 +40,19 @@ hipError_t launch_unw_write<UNW_N>(const UnwLaunch& L, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <>
+hipError_t launch_unw_write_count<UNW_N>(const UnwLaunch& L, hipStream_t s) {
+    if (!grid_ok(L.write_blocks) || L.u.masks == nullptr) return hipErrorInvalidValue;
+    if (L.intensity == 1)
+        hipLaunchKernelGGL((k_unw_write_count<UNW_N, kAtRest, BwIntensity>), dim3((unsigned)L.write_blocks),
+                           dim3(kBlock), 0, s, L.u);
+    else if (L.pmode == kBroadcast)
+        hipLaunchKernelGGL((k_unw_write_count<UNW_N, kBroadcast>), dim3((unsigned)L.write_blocks), dim3(kBlock), 0,
+                           s, L.u);
+    else
+        hipLaunchKernelGGL((k_unw_write_count<UNW_N, kAtRest>), dim3((unsigned)L.write_blocks), dim3(kBlock), 0, s,
+                           L.u);
+    return hipGetLastError();
+}
+
 } // namespace hphsp

@@ -87,6 +87,15 @@ def test_validation_before_any_device_work(P):
     assert _gen_status(P, 5.0, [1.0, 1.0], parent_dev=ctypes.c_void_p(12), ldp=10) == P.EINVAL
 
 
+def test_unweight_chunks_setting(P):
+    for c in (0, 1, 4, 16):
+        assert P.lib().hydra_phsp_set_unweight_chunks(c) == P.OK
+    assert P.lib().hydra_phsp_set_unweight_chunks(-1) == P.EINVAL
+    assert P.lib().hydra_phsp_set_unweight_chunks(17) == P.EINVAL
+    assert "chunks" in P.lib().hydra_phsp_last_error().decode()
+    P.set_unweight_chunks(0)
+
+
 def test_events_per_thread_query(P):
     for path in (0, 1, 2):
         for n in range(2, 11):

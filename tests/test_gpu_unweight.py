@@ -207,3 +207,70 @@ def test_unweighted_sparse_span_beyond_32_bits(P):
         assert_events_close(big[0][:, :, j:j + 1], np.ones(1), op4, np.ones(1))
         v = oracle.accept_uniform(12, 0, e, 3)
         assert v * w_max < ow[0]
+
+
+@pytest.mark.parametrize("w_max,capacity", [(0.0, None), (0.0, 1_234_567), (480.0, None)],
+                         ids=["sample_max", "capacity_mid_chunk", "few_kept"])
+def test_unweighted_chunked_pipeline(P, w_max, capacity):
+    """The write pass of chunk k and the count of chunk k+1 share one launch:
+    for every chunk count the kept set, order, events, counts and
+    bound are bit-identical to the unchunked sequence, and they match the
+    oracle.  2.6e6 trials are ten scan groups, so up to ten chunks, the last one
+    ragged; the capacity case ends the output inside a chunk, the few-kept case
+    carries one partial output range through many chunks."""
+    _say(f"chunked pipeline w_max={w_max} capacity={capacity}")
+    M, m = CFG0
+    n = 2_600_003
+    runs = {}
+    try:
+        for chunks in (1, 2, 3, 4, 16):
+            P.set_unweight_chunks(chunks)
+            runs[chunks] = _gpu(P, M, m, n, seed=31, event_offset=9, w_max=w_max, capacity=capacity)
+    finally:
+        P.set_unweight_chunks(0)
+    ref = runs[1]
+    for chunks, r in runs.items():
+        assert r[2:] == ref[2:], (chunks, r[2:], ref[2:])
+        assert np.array_equal(r[1], ref[1]) and np.array_equal(r[0], ref[0]), chunks
+    if capacity is not None:
+        # the capacity truncates the full output: its prefix, bit for bit
+        P.set_unweight_chunks(1)
+        try:
+            full = _gpu(P, M, m, n, seed=31, event_offset=9, w_max=w_max)
+        finally:
+            P.set_unweight_chunks(0)
+        k = min(capacity, full[2])
+        assert ref[2:] == full[2:] and ref[1].shape[0] == k
+        assert np.array_equal(ref[1], full[1][:k]) and np.array_equal(ref[0], full[0][:, :, :k])
+        ref = full
+    op4, oidx, okept, oover, owm = oracle.unweight(M, m, n, seed=31, event_offset=9, w_max=w_max)
+    assert ref[3] == oover and (w_max > 0.0 or rel(ref[4], owm) <= FP64_TOL)
+    _compare(M, m, ref[0], ref[1], ref[2], okept, oidx, op4, owm, 31, 0)
+
+
+def test_unweighted_chunked_on_a_side_stream(P):
+    """On a caller's stream other than the null stream, work queued after the
+    call on that stream sees every chunk's stores."""
+    _say("chunked pipeline on a side stream")
+    M, m = CFG0
+    n = 2_600_003
+    P.set_unweight_chunks(8)
+    try:
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            out, idx, counts, wm = P.generate_unweighted(M, m, n, seed=3, want_index=True, stream=s)
+            snap = (out.clone(), idx.clone(), counts.clone())
+        s.synchronize()
+    finally:
+        P.set_unweight_chunks(0)
+    torch.cuda.synchronize()
+    assert torch.equal(snap[2], counts)
+    k = int(counts[0].item())
+    assert torch.equal(snap[1][:k], idx[:k]) and torch.equal(snap[0][:, :, :k], out[:, :, :k])
+    P.set_unweight_chunks(1)
+    try:
+        ref = _gpu(P, M, m, n, seed=3)
+    finally:
+        P.set_unweight_chunks(0)
+    assert ref[2] == k and np.array_equal(ref[1], snap[1][:k].cpu().numpy().astype(np.uint64))
+    assert np.array_equal(ref[0], snap[0][:, :, :k].cpu().numpy())

@@ -304,3 +304,40 @@ def test_unweighted_user_model_against_oracle(P, M, m):
 
     _compare(gp4, gidx, gkept, len(okept), oidx, p4[:, :, okept], borderline)
     assert 0 < gkept < n
+
+
+@pytest.mark.parametrize("w_max_mode", ["sample_max", "given_bound"])
+def test_unweighted_model_chunked(P, w_max_mode):
+    """The Breit-Wigner model through the fused write-and-count launches (chunked
+    on request): every chunk count keeps the same trials with the same events,
+    counts and bound, bit for bit, and they match the oracle."""
+    _say(f"model chunked {w_max_mode}")
+    M, m = CFG0
+    res = [(0, 1, *PSI2S), (1, 2, *KSTAR)]
+    n = 2_600_003
+    tol = _tol(M, res)
+    w_max = 0.0
+    if w_max_mode == "given_bound":
+        _, _, vals = oracle.model_integrate(M, m, 20_000, res, seed=6, event_offset=5, want_values=True)
+        w_max = _clear_bound(vals, 0.95, tol)
+    runs = {}
+    try:
+        for chunks in (1, 3, 16):
+            P.set_unweight_chunks(chunks)
+            runs[chunks] = _gpu(P, M, m, n, res, seed=6, event_offset=5, w_max=w_max)
+    finally:
+        P.set_unweight_chunks(0)
+    ref = runs[1]
+    for chunks, r in runs.items():
+        assert r[2:] == ref[2:], (chunks, r[2:], ref[2:])
+        assert np.array_equal(r[1], ref[1]) and np.array_equal(r[0], ref[0]), chunks
+    gp4, gidx, gkept, gover, gwm = ref
+    op4, oidx, okept, oover, owm = oracle.unweight_model(M, m, n, res, seed=6, event_offset=5, w_max=w_max)
+    assert rel(gwm, owm) <= tol and gover == oover
+    _, _, vals = oracle.model_integrate(M, m, n, res, seed=6, event_offset=5, want_values=True)
+
+    def borderline(g):
+        v = oracle.accept_uniform(6, 0, int(g), 3)
+        return abs(v * owm - vals[int(g) - 5]) <= 4.0 * tol * vals[int(g) - 5]
+
+    _compare(gp4, gidx, gkept, okept, oidx, op4, borderline)

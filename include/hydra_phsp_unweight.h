@@ -74,6 +74,10 @@ int hydra_phsp_set_unweight_chunks(int chunks);
  * hydra_phsp_generate_unweighted with w_g replaced by w_g |A|^2(g) (w_max = 0:
  * the largest w |A|^2 among the trials; counts_dev[1] the trials above the
  * bound); with no factor the result is that of hydra_phsp_generate_unweighted.
+ * With w_max = 0 and at most 2^28 trials the library keeps each trial's value
+ * between the maximum and the count passes instead of computing it twice
+ * (8 bytes per trial in its per-stream workspace, kept until
+ * hydra_phsp_release; the results are the same either way).
  * EINVAL for a bad factor (as for hydra_phsp_integrate_model) and as above. */
 int hydra_phsp_generate_unweighted_model(double parent_mass, const double *masses_host, int n_daughters,
                                          const hydra_phsp_breit_wigner *resonances_host, int n_resonances,
@@ -88,7 +92,7 @@ int hydra_phsp_generate_unweighted_model(double parent_mass, const double *masse
  * n_params (0 .. HYDRA_PHSP_USER_PARAMS) params_host values, then zeros.  The
  * first call on a device loads the model's code there.  EINVAL for a NULL
  * model, n_params out of range or params_host NULL with n_params > 0, and as
- * above. */
+ * above.  Trial values are kept between passes as for the Breit-Wigner model. */
 int hydra_phsp_generate_unweighted_user_model(hydra_phsp_user_model *model, double parent_mass,
                                               const double *masses_host, const double *params_host, int n_params,
                                               uint64_t ntrials, uint64_t seed, uint32_t stream_id,

@@ -6,7 +6,9 @@
 // do not use).  Kept events are written in trial order.  The trials are cut
 // into segments of kUnwSeg consecutive trials, one wave per segment.  The
 // passes:
-//   max    (only when no bound is given) the largest weight of all trials;
+//   max    (only when no bound is given) the largest weight of all trials (for
+//          a model, whose values cost the full kinematics, each trial's value
+//          is also stored, so the count pass reads it instead of recomputing);
 //   count  per segment: the keep decisions as bit masks (one 64-bit word per 64
 //          trials; weights only, no kinematics), and the kept and over-bound
 //          counts;
@@ -60,6 +62,7 @@ struct UnwArgs {
                                     // (non-negative doubles order like their bit patterns)
     uint2* counts;             // [segments] (kept, weight > w_max) per segment
     uint64_t* masks;           // NULL (count only), or [segments * kUnwSegWords] keep bits
+    double* values;            // NULL, or [trials] each trial's value: stored by the max pass, read by the count
     const uint64_t* offsets;   // [segments] kept events before the segment
     const uint64_t* range_seg; // [ranges] segment holding output position r * kUnwRange
     const uint64_t* chunk_kept; // [chunks] kept trials of chunks 0..k together
@@ -132,7 +135,11 @@ __global__ __launch_bounds__(kBlock) void k_unw_max(const UnwArgs u) {
 #pragma unroll
     for (int k = 0; k < kUnwEpt; ++k) {
         const uint32_t off = (uint32_t)(k * kBlock) + threadIdx.x;
-        if (base + off < u.a.nevents) m = fmax(m, trial_value<N, I>(u, base, off, tab));
+        if (base + off < u.a.nevents) {
+            const double v = trial_value<N, I>(u, base, off, tab);
+            if (u.values != nullptr) u.values[base + off] = v;
+            m = fmax(m, v);
+        }
     }
     m = wave_max(m);
     if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
@@ -165,7 +172,7 @@ __device__ __forceinline__ void unw_count_segment(const UnwArgs& u, uint64_t seg
         const uint32_t off = (uint32_t)(64 * k) + lane;
         bool keep = false, above = false;
         if (base + off < u.a.nevents) {
-            const double w = trial_value<N, I>(u, base, off, tab);
+            const double w = u.values != nullptr ? u.values[base + off] : trial_value<N, I>(u, base, off, tab);
             const double v = accept_uniform<N>(u.a, base, off);
             keep = v * wmax < w;
             above = w > wmax;

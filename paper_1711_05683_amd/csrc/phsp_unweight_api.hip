@@ -143,6 +143,9 @@ __global__ __launch_bounds__(kScanBlock) void k_unw_scan_finish(const uint2* __r
 constexpr int kMaxChunks = 16;
 constexpr int kDefaultChunks = 4;      // acceptance against the weight alone
 constexpr int kDefaultChunksModel = 1; // against a model: few trials kept, so little store work to overlap
+// A model's trial values are kept between the max and count passes for at most
+// this many trials (8 bytes each: 2 GiB); larger calls recompute them.
+constexpr uint64_t kMaxStoredValues = 1ull << 28;
 std::atomic<int> g_chunks_override{0};
 
 namespace {
@@ -152,6 +155,7 @@ struct UnwWorkspace {
     uint64_t* offsets = nullptr;   // [segments]
     uint64_t* range_seg = nullptr; // first segment of each write-pass range: [segments * kUnwSeg / kUnwRange]
     uint64_t* masks = nullptr;     // [segments * kUnwSegWords], allocated when outputs are asked for
+    double* values = nullptr;      // [value_capacity] trial values of a model (sample-maximum calls)
     uint64_t* sums = nullptr;      // [groups] kept trials per group of kScanBlock segments
     uint64_t* over_sums = nullptr; // [groups] over-bound trials per group
     double* w_max = nullptr;
@@ -159,6 +163,7 @@ struct UnwWorkspace {
     uint64_t* chunk_over = nullptr; // [kMaxChunks] over-bound trials per chunk
     uint64_t capacity = 0;         // segments
     uint64_t mask_capacity = 0;    // segments
+    uint64_t value_capacity = 0;   // trials
 };
 
 std::mutex g_unw_mu;
@@ -174,13 +179,16 @@ void free_ws(UnwWorkspace& w) {
     if (w.w_max) (void)hipFree(w.w_max);
     if (w.chunk_kept) (void)hipFree(w.chunk_kept);
     if (w.chunk_over) (void)hipFree(w.chunk_over);
+    if (w.values) (void)hipFree(w.values);
+    w.values = nullptr;
+    w.value_capacity = 0;
     w.counts = nullptr;
     w.offsets = w.range_seg = w.masks = w.sums = w.over_sums = w.chunk_kept = w.chunk_over = nullptr;
     w.w_max = nullptr;
     w.capacity = w.mask_capacity = 0;
 }
 
-int unw_workspace(hipStream_t stream, uint64_t segments, bool masks, UnwWorkspace** out) {
+int unw_workspace(hipStream_t stream, uint64_t segments, bool masks, uint64_t values, UnwWorkspace** out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
@@ -198,15 +206,32 @@ int unw_workspace(hipStream_t stream, uint64_t segments, bool masks, UnwWorkspac
         }
         w.mask_capacity = cap;
     }
+    if (values > w.value_capacity) {
+        uint64_t cap = w.value_capacity ? w.value_capacity : (1ull << 20);
+        while (cap < values) cap *= 2;
+        if (w.values) (void)hipFree(w.values); // waits for the device: no queued kernel still uses it
+        w.values = nullptr;
+        w.value_capacity = 0;
+        if (hipMalloc(&w.values, sizeof(double) * cap) != hipSuccess) {
+            w.values = nullptr;
+            return fail(HYDRA_PHSP_ENOMEM, "unweighting value allocation failed");
+        }
+        w.value_capacity = cap;
+    }
     if (w.w_max == nullptr || segments > w.capacity) {
         uint64_t cap = w.capacity ? w.capacity : 4096;
         while (cap < segments) cap *= 2;
         uint64_t* keep_masks = w.masks;
         const uint64_t keep_mask_cap = w.mask_capacity;
+        double* keep_values = w.values;
+        const uint64_t keep_value_cap = w.value_capacity;
         w.masks = nullptr; // kept across the regrowth of the other buffers
+        w.values = nullptr;
         free_ws(w); // hipFree waits for the device, so no queued kernel still uses it
         w.masks = keep_masks;
         w.mask_capacity = keep_mask_cap;
+        w.values = keep_values;
+        w.value_capacity = keep_value_cap;
         const uint64_t groups = (cap + kScanBlock - 1) / kScanBlock;
         bool ok = hipMalloc(&w.counts, sizeof(uint2) * cap) == hipSuccess &&
                   hipMalloc(&w.offsets, sizeof(uint64_t) * cap) == hipSuccess &&
@@ -334,7 +359,10 @@ int unweighted_run(const Channel& ch, int n_daughters, const double* parent_p4_h
 
     hipStream_t s = (hipStream_t)stream;
     UnwWorkspace* ws = nullptr;
-    st = unw_workspace(s, std::max<uint64_t>(segments, 1), outputs, &ws);
+    // a model's values (the full kinematics of every trial) are computed once for
+    // the max pass and the count pass, when no bound is given
+    const bool store_values = inten.kind != 0 && w_max == 0.0 && ntrials > 0 && ntrials <= kMaxStoredValues;
+    st = unw_workspace(s, std::max<uint64_t>(segments, 1), outputs, store_values ? ntrials : 0, &ws);
     if (st != HYDRA_PHSP_OK) return st;
     const double2* trig = nullptr;
     st = trig_table(&trig);
@@ -355,6 +383,7 @@ int unweighted_run(const Channel& ch, int n_daughters, const double* parent_p4_h
     L.u.w_max_bits = reinterpret_cast<unsigned long long*>(ws->w_max);
     L.u.counts = ws->counts;
     L.u.masks = outputs ? ws->masks : nullptr;
+    L.u.values = store_values ? ws->values : nullptr;
     L.u.offsets = ws->offsets;
     L.u.range_seg = ws->range_seg;
     L.u.chunk_kept = ws->chunk_kept;

@@ -341,3 +341,25 @@ def test_unweighted_model_chunked(P, w_max_mode):
         return abs(v * owm - vals[int(g) - 5]) <= 4.0 * tol * vals[int(g) - 5]
 
     _compare(gp4, gidx, gkept, okept, oidx, op4, borderline)
+
+
+@pytest.mark.parametrize("name,M,m,res", [CASES[0], CASES[3], CASES[4]], ids=[CASES[0][0], CASES[3][0], CASES[4][0]])
+def test_unweighted_model_stored_values_match_recomputed(P, name, M, m, res):
+    """With no bound given, the max pass keeps every trial's value for the count
+    pass; with that same bound given, the count pass computes the values itself.
+    Both keep the same trials with the same events and counts, bit for bit, for
+    the built-in model and the same intensity as user code; twice in a row, the
+    second call smaller (the stored values of the first are not reused)."""
+    _say(f"stored vs recomputed values: {name}")
+    model = P.UserModel(USER_BW, len(m))
+    try:
+        for n in (400_009, 150_001):
+            sampled = _gpu(P, M, m, n, res, seed=13, event_offset=3)
+            given = _gpu(P, M, m, n, res, seed=13, event_offset=3, w_max=sampled[4])
+            assert sampled[2:] == given[2:], (sampled[2:], given[2:])
+            assert np.array_equal(sampled[1], given[1]) and np.array_equal(sampled[0], given[0])
+            u = _host(*model.generate_unweighted(M, m, n, _bw_params(res), seed=13, event_offset=3,
+                                                 want_index=True))
+            assert u[2:] == sampled[2:] and np.array_equal(u[1], sampled[1]) and np.array_equal(u[0], sampled[0])
+    finally:
+        model.destroy()

@@ -347,6 +347,7 @@ COUNTER_RUNS = {"headline": None,
                 "six_massless_mixed": (10.0, [0.0] * 6, 50_000_000, True),
                 "ten_pion_fp64": (10.0, [0.13957] * 10, 31_700_000, False),
                 "unweighted": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False),
+                "unweighted_pipeline": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False),
                 "integrate": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False),
                 "model": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False),
                 "vegas": None}
@@ -376,7 +377,10 @@ def counter_run(P, torch, dev, name):
         fn = lambda: P.integrate_model(M, m, n, one, values=w, stats=st)  # noqa: E731
     else:
         out = torch.empty((len(m), 4, P.aligned_ld(n)), dtype=dtype, device=dev)
-        if name == "unweighted":
+        if name.startswith("unweighted"):
+            # 'unweighted': the passes one after the other (one chunk); 'unweighted_pipeline': the
+            # default four chunks, each store launch also counting the next chunk
+            P.set_unweight_chunks(1 if name == "unweighted" else 0)
             cnt = torch.empty(2, dtype=torch.int64, device=dev)
             wmo = torch.empty(1, dtype=torch.float64, device=dev)
             P.generate_unweighted(M, m, n, out=out, counts=cnt, w_max_out=wmo)

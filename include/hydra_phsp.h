@@ -200,6 +200,21 @@ int hydra_phsp_set_events_per_thread(int path, int ept);
 #define HYDRA_PHSP_EPT_OFF_LINE_GRID 2
 int hydra_phsp_events_per_thread(int path, int n_daughters, int flags);
 
+/* Statistics of two disjoint sets of events merged into those of their union
+ * (host records of HYDRA_PHSP_STATS doubles: n, mean, M2, sigma), with the
+ * pairwise update of Chan, Golub and LeVeque that the kernels' reduction uses:
+ * n = na + nb, mean = ma + (mb - ma) nb / n, M2 = M2a + M2b + (mb - ma)^2 na nb / n,
+ * sigma recomputed.  This is how the integral of a job taken in pieces (a
+ * resumed job, or shards on several devices, each an event_offset range of the
+ * same seed and stream id) is assembled: the state of such a job is (seed,
+ * stream id, next event_offset, stats so far), and merging the pieces left to
+ * right in event order gives a deterministic result, equal to the single
+ * call's up to rounding (sec. 3 of arXiv:1711.05683: the Monte Carlo estimate
+ * is the mean weight, its error the standard error of the mean).  out_host may
+ * alias a_host or b_host.  EINVAL for a NULL pointer, a negative,
+ * non-integral or non-finite n, or a non-finite mean or M2, or a negative M2. */
+int hydra_phsp_stats_merge(const double *a_host, const double *b_host, double *out_host);
+
 /* Kernel timing for benchmarks: while enabled, every launch of the main
  * phase-space kernel is bracketed by HIP events recorded on the caller's
  * stream.  hydra_phsp_timing_read synchronises those events and returns the

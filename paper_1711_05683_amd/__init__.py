@@ -62,6 +62,8 @@ def _declare(lib):
     lib.hydra_phsp_set_events_per_thread.restype = i
     lib.hydra_phsp_set_unweight_chunks.argtypes = [i]
     lib.hydra_phsp_set_unweight_chunks.restype = i
+    lib.hydra_phsp_stats_merge.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.hydra_phsp_stats_merge.restype = i
     lib.hydra_phsp_events_per_thread.argtypes = [i, i, i]
     lib.hydra_phsp_events_per_thread.restype = i
     lib.hydra_phsp_timing_enable.argtypes = [i]
@@ -642,6 +644,23 @@ def release():
 def set_events_per_thread(path: int, ept: int):
     """Events per thread for path 0 (integrate), 1 (FP64) or 2 (mixed); 0 = default."""
     _check(lib().hydra_phsp_set_events_per_thread(path, ept))
+
+
+def stats_merge(a, b):
+    """Statistics (n, mean, M2, sigma) of the union of two disjoint event sets
+    from theirs (host values: sequences, or tensors on any device, which are
+    copied to the host).  Returns a list of four floats."""
+    def rec(x, name):
+        if isinstance(x, torch.Tensor):
+            x = x.detach().to("cpu", torch.float64).reshape(-1).tolist()
+        x = [float(v) for v in x]
+        if len(x) < 3:
+            raise ValueError(f"{name} needs n, mean and M2")
+        return (ctypes.c_double * STATS)(*(x + [0.0] * STATS)[:STATS])
+    ra, rb = rec(a, "a"), rec(b, "b")
+    out = (ctypes.c_double * STATS)()
+    _check(lib().hydra_phsp_stats_merge(ctypes.addressof(ra), ctypes.addressof(rb), ctypes.addressof(out)))
+    return list(out)
 
 
 def set_unweight_chunks(chunks: int):

@@ -563,6 +563,24 @@ const char* hydra_phsp_last_error(void) { return t_last_error.c_str(); }
 
 int hydra_phsp_abi_version(void) { return HYDRA_PHSP_ABI_VERSION; }
 
+int hydra_phsp_stats_merge(const double* a_host, const double* b_host, double* out_host) {
+    if (a_host == nullptr || b_host == nullptr || out_host == nullptr)
+        return fail(HYDRA_PHSP_EINVAL, "stats records must not be NULL");
+    const double* rec[2] = {a_host, b_host};
+    for (const double* r : rec) {
+        if (!std::isfinite(r[0]) || r[0] < 0.0 || r[0] != std::floor(r[0]))
+            return fail(HYDRA_PHSP_EINVAL, "stats n must be a finite non-negative integer");
+        if (!std::isfinite(r[1]) || !std::isfinite(r[2]) || r[2] < 0.0)
+            return fail(HYDRA_PHSP_EINVAL, "stats mean and M2 must be finite, M2 >= 0");
+    }
+    const Moments m = merge(Moments{a_host[0], a_host[1], a_host[2]}, Moments{b_host[0], b_host[1], b_host[2]});
+    out_host[0] = m.n;
+    out_host[1] = m.mean;
+    out_host[2] = m.m2;
+    out_host[3] = m.n >= 2.0 ? std::sqrt(m.m2 / ((m.n - 1.0) * m.n)) : 0.0;
+    return HYDRA_PHSP_OK;
+}
+
 int hydra_phsp_release(void) {
     const int a = release_batch_slots();
     const int b = release_workspaces(); // synchronizes the device first

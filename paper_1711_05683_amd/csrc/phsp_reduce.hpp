@@ -12,7 +12,7 @@ struct Moments {
     double n, mean, m2;
 };
 
-__device__ __forceinline__ Moments merge(const Moments& a, const Moments& b) {
+__host__ __device__ __forceinline__ Moments merge(const Moments& a, const Moments& b) {
     if (b.n == 0.0) return a;
     if (a.n == 0.0) return b;
     const double n = a.n + b.n;

@@ -4,9 +4,11 @@ from __future__ import annotations
 
 import ctypes
 import glob
+import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -483,3 +485,42 @@ def test_noalloc_rejects_counts_beyond_its_scratch_before_device_work(P):
     # the ordinary argument checks come first, as for hydra_phsp_generate
     assert f(5.279, m, n, None, None, 0, 10, 42, 0, 0, None, 10, w, st, None) == P.EINVAL
     assert f(1.0, m, n, None, None, 0, 10, 42, 0, 0, out, 10, w, st, None) == P.EKINEMATICS
+
+
+def test_stats_merge_is_the_statistics_of_the_union(P):
+    """Merging the (n, mean, M2) of disjoint pieces, left to right, gives the
+    statistics numpy computes over the union (two-pass, in extended precision);
+    an empty piece is neutral; sigma is the standard error of the mean."""
+    rng = np.random.default_rng(11)
+    w = rng.lognormal(0.0, 1.5, size=100_003) * 3.0
+    cuts = [0, 1, 2, 17, 50_000, 99_999, 100_003]
+
+    def stats(x):
+        x = np.asarray(x, dtype=np.longdouble)
+        if len(x) == 0:
+            return [0.0, 0.0, 0.0, 0.0]
+        mu = x.mean()
+        return [float(len(x)), float(mu), float(((x - mu) ** 2).sum()), 0.0]
+
+    acc = [0.0, 0.0, 0.0, 0.0]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        acc = P.stats_merge(acc, stats(w[a:b]))
+    ref = stats(w)
+    n = ref[0]
+    assert acc[0] == n
+    assert abs(acc[1] - ref[1]) <= 1e-14 * ref[1]
+    assert abs(acc[2] - ref[2]) <= 1e-12 * ref[2]
+    assert abs(acc[3] - math.sqrt(ref[2] / ((n - 1) * n))) <= 1e-12 * acc[3]
+    assert P.stats_merge(stats(w), [0.0, 0.0, 0.0, 0.0])[:3] == stats(w)[:3]
+    assert P.stats_merge([1.0, 2.5, 0.0, 0.0], [0.0, 0.0, 0.0, 0.0]) == [1.0, 2.5, 0.0, 0.0]
+
+
+@pytest.mark.parametrize("bad", [[-1.0, 1.0, 0.0], [1.5, 1.0, 0.0], [float("nan"), 1.0, 0.0],
+                                 [2.0, float("inf"), 0.0], [2.0, 1.0, -1.0]])
+def test_stats_merge_rejects_bad_records(P, bad):
+    good = [2.0, 1.0, 0.5, 0.0]
+    with pytest.raises(P.PhspError):
+        P.stats_merge(bad, good)
+    with pytest.raises(P.PhspError):
+        P.stats_merge(good, bad)
+    assert P.lib().hydra_phsp_stats_merge(None, None, None) == P.EINVAL

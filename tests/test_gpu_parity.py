@@ -264,6 +264,26 @@ def test_determinism_and_chunking(P):
     assert np.array_equal(np.concatenate([w1, w2]), wa)
 
 
+def test_integral_resumed_in_pieces(P):
+    """A job integrated in pieces (event_offset ranges of one seed and stream,
+    as a resumed job or shards on several devices would take them), its
+    statistics merged left to right with hydra_phsp_stats_merge: the same n,
+    the mean and sigma of the single call up to rounding, and both within the
+    FP64 tolerance of the oracle."""
+    _say("integral resumed in pieces")
+    M, m = CFG0
+    n = 3_000_017
+    cuts = [0, 1_000_000, 1_000_001, 2_345_678, n]
+    whole = P.integrate_async(M, m, n, seed=19, stream_id=4).cpu().tolist()
+    acc = [0.0, 0.0, 0.0, 0.0]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        acc = P.stats_merge(acc, P.integrate_async(M, m, b - a, seed=19, stream_id=4, event_offset=a))
+    assert acc[0] == whole[0] == n
+    assert rel(acc[1], whole[1]) <= 1e-13 and rel(acc[3], whole[3]) <= 1e-12
+    mo, so = oracle.integrate(M, m, n, seed=19, stream_id=4)
+    assert rel(acc[1], mo) <= FP64_TOL and rel(acc[3], so) <= FP64_TOL
+
+
 def test_near_threshold(P):
     _say("near threshold")
     m = [0.13957, 0.13957, 0.13957, 0.4937]

@@ -100,6 +100,21 @@ static void host_tables(void)
     expect(hydra_phsp_set_events_per_thread(1, 2) == HYDRA_PHSP_OK, "set two events per thread");
     expect(hydra_phsp_events_per_thread(1, 3, 0) == 2, "override visible");
     expect(hydra_phsp_set_events_per_thread(1, 0) == HYDRA_PHSP_OK, "restore defaults");
+    expect(hydra_phsp_set_unweight_chunks(17) == HYDRA_PHSP_EINVAL, "17 unweighting chunks");
+    expect(hydra_phsp_set_unweight_chunks(-1) == HYDRA_PHSP_EINVAL, "negative unweighting chunks");
+    expect(hydra_phsp_set_unweight_chunks(16) == HYDRA_PHSP_OK && hydra_phsp_set_unweight_chunks(0) == HYDRA_PHSP_OK,
+           "unweighting chunks set and restored");
+    {
+        /* statistics of {1, 2} and {3, 4, 5}: union {1..5}, mean 3, M2 10 */
+        double a[HYDRA_PHSP_STATS] = {2.0, 1.5, 0.5, 0.0}, b[HYDRA_PHSP_STATS] = {3.0, 4.0, 2.0, 0.0};
+        double u[HYDRA_PHSP_STATS];
+        expect(hydra_phsp_stats_merge(a, b, u) == HYDRA_PHSP_OK && u[0] == 5.0 && u[1] == 3.0 && u[2] == 10.0,
+               "stats merge of {1,2} and {3,4,5}");
+        expect(hydra_phsp_stats_merge(a, b, a) == HYDRA_PHSP_OK && a[1] == 3.0, "stats merge in place");
+        double bad[HYDRA_PHSP_STATS] = {-1.0, 0.0, 0.0, 0.0};
+        expect(hydra_phsp_stats_merge(bad, b, u) == HYDRA_PHSP_EINVAL, "stats merge of a negative n");
+        expect(hydra_phsp_stats_merge(NULL, b, u) == HYDRA_PHSP_EINVAL, "stats merge of NULL");
+    }
     expect(hydra_phsp_timing_enable(1) == HYDRA_PHSP_OK && hydra_phsp_timing_reset() == HYDRA_PHSP_OK,
            "timing switch");
     double ms = -1.0;

@@ -274,3 +274,31 @@ def test_unweighted_chunked_on_a_side_stream(P):
         P.set_unweight_chunks(0)
     assert ref[2] == k and np.array_equal(ref[1], snap[1][:k].cpu().numpy().astype(np.uint64))
     assert np.array_equal(ref[0], snap[0][:, :, :k].cpu().numpy())
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 10])
+@pytest.mark.parametrize("mode", ["rest", "broadcast"])
+def test_unweighted_chunked_every_n(P, n, mode):
+    """The fused store-and-count launch for other daughter counts and for a
+    moving parent: five chunks give the one-chunk result bit for bit, and that
+    matches the oracle."""
+    _say(f"chunked N={n} {mode}")
+    M, m = _random_masses(n, 7000 + n)
+    ntrials, seed, sid, off = 1_300_007, 29 + n, 5, 77_000_000_001
+    parent = None
+    if mode == "broadcast":
+        p = np.array([-0.4, 2.5, 1.1])
+        parent = [math.sqrt(M * M + float(p @ p)), *p]
+    runs = {}
+    try:
+        for chunks in (1, 5):
+            P.set_unweight_chunks(chunks)
+            runs[chunks] = _gpu(P, M, m, ntrials, seed=seed, stream_id=sid, event_offset=off, parent_p4=parent)
+    finally:
+        P.set_unweight_chunks(0)
+    a, b = runs[1], runs[5]
+    assert a[2:] == b[2:] and np.array_equal(a[1], b[1]) and np.array_equal(a[0], b[0])
+    op4, oidx, okept, oover, owm = oracle.unweight(M, m, ntrials, seed=seed, stream_id=sid, event_offset=off,
+                                                   parent_p4=parent)
+    assert rel(b[4], owm) <= FP64_TOL and b[3] == oover
+    _compare(M, m, b[0], b[1], b[2], okept, oidx, op4, owm, seed, sid, parent)

@@ -363,3 +363,37 @@ def test_unweighted_model_stored_values_match_recomputed(P, name, M, m, res):
             assert u[2:] == sampled[2:] and np.array_equal(u[1], sampled[1]) and np.array_equal(u[0], sampled[0])
     finally:
         model.destroy()
+
+
+@pytest.mark.parametrize("w_max_mode", ["sample_max", "given_bound"])
+@pytest.mark.parametrize("name,M,m,res", CASES[2:], ids=[c[0] for c in CASES[2:]])
+def test_unweighted_model_chunked_every_n(P, name, M, m, res, w_max_mode):
+    """The Breit-Wigner fused store-and-count launch for four, six and ten
+    daughters: five chunks give the one-chunk result bit for bit (values stored
+    by the max pass or recomputed), and it matches the oracle."""
+    _say(f"model chunked {name} {w_max_mode}")
+    n = 1_300_007
+    tol = _tol(M, res)
+    w_max = 0.0
+    if w_max_mode == "given_bound":
+        _, _, vals = oracle.model_integrate(M, m, 20_000, res, seed=8, event_offset=2, want_values=True)
+        w_max = _clear_bound(vals, 0.9, tol)
+    runs = {}
+    try:
+        for chunks in (1, 5):
+            P.set_unweight_chunks(chunks)
+            runs[chunks] = _gpu(P, M, m, n, res, seed=8, event_offset=2, w_max=w_max)
+    finally:
+        P.set_unweight_chunks(0)
+    a, b = runs[1], runs[5]
+    assert a[2:] == b[2:] and np.array_equal(a[1], b[1]) and np.array_equal(a[0], b[0])
+    gp4, gidx, gkept, gover, gwm = b
+    op4, oidx, okept, oover, owm = oracle.unweight_model(M, m, n, res, seed=8, event_offset=2, w_max=w_max)
+    assert rel(gwm, owm) <= tol and gover == oover
+    _, _, vals = oracle.model_integrate(M, m, n, res, seed=8, event_offset=2, want_values=True)
+
+    def borderline(g):
+        v = oracle.accept_uniform(8, 0, int(g), len(m))
+        return abs(v * owm - vals[int(g) - 2]) <= 4.0 * tol * vals[int(g) - 2]
+
+    _compare(gp4, gidx, gkept, okept, oidx, op4, borderline)

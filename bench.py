@@ -633,13 +633,22 @@ def sequential_extra(P, torch, dev, M, m, n, out, w, st, steps):
         P.generate(M, m, n, seed=42, out=out, weights=w, stats=st)
         stage2()
 
+    def fused():
+        P.generate_chain(M, m, 0, [mmu, mmu], n, seed=42, stream_id=0, stream_id2=1, out=out, weights=w, stats=st,
+                         out2=out2, weights2=w2, stats2=st2)
+
     chain()
     ms2, k2 = time_steps(stage2, steps, 1, torch)
     msc, _ = time_steps(chain, steps, 1, torch)
+    fused()
+    msf, kf = time_steps(fused, steps, 1, torch)
     del out2, w2
+    # the fused launch writes both stages (104 + 72 B per event) and reads nothing
     return {"decay": "5.279 -> (3.097 -> mu mu, 0.4937, 0.13957)", "stage2_kernel_ms": k2,
             "stage2_total_GBs": 104 * n / (k2 * 1e-3) / 1e9, "chain_ms_per_step": msc,
-            "chain_events_per_s": n / (msc * 1e-3)}
+            "chain_events_per_s": n / (msc * 1e-3), "fused_chain_ms_per_step": msf, "fused_chain_kernel_ms": kf,
+            "fused_chain_events_per_s": n / (msf * 1e-3),
+            "fused_chain_write_GBs": 176 * n / (kf * 1e-3) / 1e9}
 
 
 def unweighted_extra(P, torch, dev, M, m, n, out, steps):

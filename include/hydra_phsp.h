@@ -113,6 +113,37 @@ int hydra_phsp_generate(double parent_mass, const double *masses_host, int n_dau
                         uint64_t event_offset, double *p4_out_dev, uint64_t ld,
                         double *weights_dev, double *stats_dev, void *stream);
 
+/* A sequential decay in one launch (sec. 4.2 lists sequential decays among the
+ * generator's uses): the result is defined as that of two calls,
+ *   hydra_phsp_generate(parent_mass, masses_host, n_daughters, NULL, NULL, 0,
+ *       nevents, seed, stream_id, event_offset, p4_out_dev, ld, weights_dev,
+ *       stats_dev, stream);
+ *   hydra_phsp_generate(masses_host[chained], masses2_host, n2, NULL,
+ *       p4_out_dev + 4 * chained * ld, ld, nevents, seed, stream_id2,
+ *       event_offset, p4_out2_dev, ld2, weights2_dev, stats2_dev, stream);
+ * i.e. daughter `chained` of each first-stage event (parent at rest) decays
+ * into n2 daughters in its own frame, with the same event index and another
+ * counter stream (stream_id2 != stream_id for independent uniforms).  Events
+ * and weights of both stages are bit-identical to the two calls'; the
+ * integrals agree to rounding (bit-identical when both calls run one event per
+ * thread, as this launch does).  With every column on the 128-byte line grid
+ * (p4_out_dev, weights_dev, p4_out2_dev, weights2_dev 128-byte aligned, ld and
+ * ld2 multiples of 16) one kernel computes both stages, keeping the chained
+ * daughter in registers instead of reading it back; other layouts run the two
+ * calls.
+ *   chained          0 .. n_daughters - 1.
+ *   masses2_host, n2 the second stage's daughters, 2 <= n2 <= 4, their sum
+ *                    below masses_host[chained] (EKINEMATICS otherwise).
+ *   p4_out2_dev      [n2][4][ld2] doubles (device); weights2_dev [nevents];
+ *   stats2_dev       NULL, or HYDRA_PHSP_STATS doubles: the second stage's integral.
+ * Other arguments, layouts and errors as for hydra_phsp_generate. */
+int hydra_phsp_generate_chain(double parent_mass, const double *masses_host, int n_daughters, int chained,
+                              const double *masses2_host, int n2, uint64_t nevents, uint64_t seed,
+                              uint32_t stream_id, uint32_t stream_id2, uint64_t event_offset,
+                              double *p4_out_dev, uint64_t ld, double *weights_dev, double *stats_dev,
+                              double *p4_out2_dev, uint64_t ld2, double *weights2_dev, double *stats2_dev,
+                              void *stream);
+
 /* Phase-space integral without storing events (sec. 3 lists phase-space
  * integration among the library's algorithms; sec. 4.2 the method).  The same
  * events as hydra_phsp_generate with the same (seed, stream_id, event_offset);

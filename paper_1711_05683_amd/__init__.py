@@ -44,6 +44,9 @@ def _declare(lib):
     lib.hydra_phsp_generate_mixed.restype = i
     lib.hydra_phsp_generate_noalloc.argtypes = lib.hydra_phsp_generate.argtypes
     lib.hydra_phsp_generate_noalloc.restype = i
+    lib.hydra_phsp_generate_chain.argtypes = [d, dp, i, i, dp, i, u64, u64, u32, u32, u64, vp, u64, vp, vp,
+                                              vp, u64, vp, vp, vp]
+    lib.hydra_phsp_generate_chain.restype = i
     lib.hydra_phsp_integrate_async.argtypes = [d, dp, i, u64, u64, u32, u64, vp, vp]
     lib.hydra_phsp_integrate_async.restype = i
     lib.hydra_phsp_integrate.argtypes = [d, dp, i, u64, u64, u32, u64, dp, dp, vp]
@@ -249,6 +252,56 @@ def generate(parent_mass: float, masses: Sequence[float], nevents: int, *, seed:
     if own_out:
         out = out[:, :, :max(nevents, 1)]
     return out, weights, stats
+
+
+def generate_chain(parent_mass: float, masses: Sequence[float], chained: int, masses2: Sequence[float],
+                   nevents: int, *, seed: int = 42, stream_id: int = 0, stream_id2: int = 1, event_offset: int = 0,
+                   out: Optional[torch.Tensor] = None, weights: Optional[torch.Tensor] = None,
+                   stats: Optional[torch.Tensor] = None, out2: Optional[torch.Tensor] = None,
+                   weights2: Optional[torch.Tensor] = None, stats2: Optional[torch.Tensor] = None,
+                   want_stats: bool = True, device=None, stream: Optional[torch.cuda.Stream] = None):
+    """A sequential decay in one launch (asynchronous): the first stage at rest,
+    then daughter ``chained`` of every event decays into ``masses2`` (at most 4
+    daughters) with counter stream ``stream_id2``.  The same result as
+    ``generate`` twice, the second call with ``parent_dev=p4[chained]``.
+    Returns ``(p4, weights, stats, p4_2, weights2, stats2)``; outputs not given
+    are allocated on the line grid (``aligned_ld(nevents)`` columns) and
+    returned as ``[N, 4, nevents]`` views."""
+    m, n = _masses(masses)
+    m2, n2 = _masses(masses2)
+    for o, k, name in ((out, n, "out"), (out2, n2, "out2")):
+        if o is not None and (not isinstance(o, torch.Tensor) or o.dtype != torch.float64 or not o.is_contiguous()
+                              or o.dim() != 3 or tuple(o.shape[:2]) != (k, 4) or o.shape[2] < nevents):
+            raise ValueError(f"{name} must be a contiguous [{k}, 4, ld >= nevents] float64 tensor")
+    for b, name in ((weights, "weights"), (weights2, "weights2")):
+        _check_buf(b, name, torch.float64, nevents)
+    for b, name in ((stats, "stats"), (stats2, "stats2")):
+        _check_buf(b, name, torch.float64, STATS)
+    dev = _resident(device, stream, out=out, weights=weights, stats=stats, out2=out2, weights2=weights2,
+                    stats2=stats2)
+    views = []
+    if out is None:
+        out = torch.empty((n, 4, aligned_ld(nevents)), dtype=torch.float64, device=dev)
+        views.append(0)
+    if out2 is None:
+        out2 = torch.empty((n2, 4, aligned_ld(nevents)), dtype=torch.float64, device=dev)
+        views.append(1)
+    if weights is None:
+        weights = torch.empty(max(nevents, 1), dtype=torch.float64, device=dev)
+    if weights2 is None:
+        weights2 = torch.empty(max(nevents, 1), dtype=torch.float64, device=dev)
+    if want_stats:
+        stats = torch.empty(STATS, dtype=torch.float64, device=dev) if stats is None else stats
+        stats2 = torch.empty(STATS, dtype=torch.float64, device=dev) if stats2 is None else stats2
+    _check(lib().hydra_phsp_generate_chain(parent_mass, m, n, int(chained), m2, n2, nevents, seed, stream_id,
+                                           stream_id2, event_offset, _dptr(out), out.shape[2], _dptr(weights),
+                                           _dptr(stats), _dptr(out2), out2.shape[2], _dptr(weights2),
+                                           _dptr(stats2), _stream_handle(stream)))
+    if 0 in views:
+        out = out[:, :, :max(nevents, 1)]
+    if 1 in views:
+        out2 = out2[:, :, :max(nevents, 1)]
+    return out, weights, stats, out2, weights2, stats2
 
 
 def _unweighted_buffers(n: int, ntrials: int, capacity, want_events, want_index, device, stream, out, index,

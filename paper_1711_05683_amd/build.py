@@ -98,6 +98,9 @@ def _units():
     for n in NS:
         units.append((os.path.join(CSRC, "phsp_model_inst.hip"),
                       os.path.join(BUILD_DIR, f"phsp_model_inst_n{n}.o"), [f"-DMODEL_N={n}"]))
+    for n in NS:
+        units.append((os.path.join(CSRC, "phsp_chain_inst.hip"),
+                      os.path.join(BUILD_DIR, f"phsp_chain_inst_n{n}.o"), [f"-DCHAIN_N1={n}"]))
     for nmax in BATCH_MIXED:
         units.append((os.path.join(CSRC, "phsp_batch_inst.hip"),
                       os.path.join(BUILD_DIR, f"phsp_batch_mixed_n{nmax}.o"), [f"-DBATCH_MIXED={nmax}"]))

@@ -62,16 +62,9 @@ __device__ __forceinline__ R load_col(const R* col, uint32_t boff) {
     return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(col) + boff);
 }
 
-// Per-event parent frame: eta = P/M, gamma = E/M, 1/(gamma+1) = M/(E+M).
-// `parent` already points at the block's first event; `off` is the lane's event
-// offset within the block.
-__device__ __forceinline__ Frame load_parent_frame(const double* parent, uint64_t ldp, uint32_t off,
-                                                   double M, double inv_M) {
-    const uint32_t boff = off * (uint32_t)sizeof(double);
-    const double E = load_col(parent, boff);
-    const double px = load_col(parent + ldp, boff);
-    const double py = load_col(parent + 2 * ldp, boff);
-    const double pz = load_col(parent + 3 * ldp, boff);
+// Frame of a parent four-momentum (E, p) of mass M: eta = P/M, gamma = E/M,
+// 1/(gamma+1) = M/(E+M).
+__device__ __forceinline__ Frame parent_frame(double E, double px, double py, double pz, double M, double inv_M) {
     Frame f;
     f.eta[0] = px * inv_M;
     f.eta[1] = py * inv_M;
@@ -81,10 +74,36 @@ __device__ __forceinline__ Frame load_parent_frame(const double* parent, uint64_
     return f;
 }
 
+// Per-event parent frame, read from the parent columns: `parent` already points
+// at the block's first event; `off` is the lane's event offset within the block.
+__device__ __forceinline__ Frame load_parent_frame(const double* parent, uint64_t ldp, uint32_t off,
+                                                   double M, double inv_M) {
+    const uint32_t boff = off * (uint32_t)sizeof(double);
+    const double E = load_col(parent, boff);
+    const double px = load_col(parent + ldp, boff);
+    const double py = load_col(parent + 2 * ldp, boff);
+    const double pz = load_col(parent + 3 * ldp, boff);
+    return parent_frame(E, px, py, pz, M, inv_M);
+}
+
 // Counter stream of event base + off.
 __device__ __forceinline__ EventRng event_rng(const KArgs& a, uint64_t base, uint32_t off) {
     const uint64_t g = a.event_offset + base + off;
     return EventRng{(uint32_t)g, (uint32_t)(g >> 32), a.sid, a.k0, a.k1};
+}
+
+// One event in the rest frame of its parent, boosted into the frame `f` moves
+// with: `sink(k, e, x, y, z)` receives each daughter's final four-momentum.
+template <int N, class Sink>
+__device__ __forceinline__ double emit_event_in_frame(const KArgs& a, uint64_t base, uint32_t off,
+                                                      const double2* tab, const Frame& f, Sink&& sink) {
+    const EventRng rng = event_rng(a, base, off);
+    MassDraws<N> d;
+    draw_masses<N>(d, rng);
+    return event_levels<N, true>(a.ch, rng, d, tab, [&](int k, double e, double x, double y, double z) {
+        boost_to_lab(e, x, y, z, f);
+        sink(k, e, x, y, z);
+    });
 }
 
 // One event's draws, levels, kinematics and lab boost: `sink(k, e, x, y, z)`
@@ -96,18 +115,15 @@ __device__ __forceinline__ EventRng event_rng(const KArgs& a, uint64_t base, uin
 template <int N, int PMODE, int MODE, class Sink>
 __device__ __forceinline__ double emit_event(const KArgs& a, uint64_t base, uint32_t off, const double2* tab,
                                              Sink&& sink) {
-    const EventRng rng = event_rng(a, base, off);
-    MassDraws<N> d;
-    draw_masses<N>(d, rng);
     if constexpr (MODE == kIntegrate || PMODE == kAtRest) {
+        const EventRng rng = event_rng(a, base, off);
+        MassDraws<N> d;
+        draw_masses<N>(d, rng);
         return event_levels<N, MODE != kIntegrate>(a.ch, rng, d, tab, sink);
     } else {
         const Frame f = PMODE == kBroadcast ? a.frame
                                             : load_parent_frame(a.parent + base, a.ld_parent, off, a.ch.M, a.inv_M);
-        return event_levels<N, true>(a.ch, rng, d, tab, [&](int k, double e, double x, double y, double z) {
-            boost_to_lab(e, x, y, z, f);
-            sink(k, e, x, y, z);
-        });
+        return emit_event_in_frame<N>(a, base, off, tab, f, sink);
     }
 }
 

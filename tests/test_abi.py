@@ -524,3 +524,25 @@ def test_stats_merge_rejects_bad_records(P, bad):
     with pytest.raises(P.PhspError):
         P.stats_merge(good, bad)
     assert P.lib().hydra_phsp_stats_merge(None, None, None) == P.EINVAL
+
+
+def test_chain_validation_before_device_work(P):
+    """The two-stage entry point rejects bad arguments on the host."""
+    lib = P.lib()
+    m = (ctypes.c_double * 3)(3.097, 0.4937, 0.13957)
+    m2 = (ctypes.c_double * 2)(0.1056583755, 0.1056583755)
+    heavy = (ctypes.c_double * 2)(2.0, 1.5)
+    five = (ctypes.c_double * 5)(0.1, 0.1, 0.1, 0.1, 0.1)
+    fake = ctypes.c_void_p(0x10000)
+
+    def call(chained=0, masses2=m2, n2=2, out=fake, out2=fake, ld=10, ld2=10, nev=10):
+        return lib.hydra_phsp_generate_chain(5.279, m, 3, chained, masses2, n2, nev, 1, 0, 1, 0, out, ld, fake, None,
+                                             out2, ld2, fake, None, None)
+
+    assert call(chained=3) == P.EINVAL and "chained" in lib.hydra_phsp_last_error().decode()
+    assert call(chained=-1) == P.EINVAL
+    assert call(masses2=five, n2=5) == P.EINVAL and "n2" in lib.hydra_phsp_last_error().decode()
+    assert call(masses2=heavy) == P.EKINEMATICS
+    assert call(out2=None) == P.EINVAL
+    assert call(ld2=5) == P.EINVAL
+    assert call(out=ctypes.c_void_p(0x10004)) == P.EINVAL

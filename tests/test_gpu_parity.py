@@ -173,6 +173,79 @@ def test_sequential_decay_chain(P):
     assert np.all(np.abs(p2.sum(axis=0) - p1[0]) <= 1e-12 * np.abs(p1[0]).max())
 
 
+CHAIN_CASES = [  # (M, first-stage masses, chained daughter, second-stage masses)
+    (5.279, [3.097, 0.4937, 0.13957], 0, [0.1056583755, 0.1056583755]),
+    (5.279, [3.097, 0.4937, 0.13957], 0, [0.13957, 0.13957, 0.13957]),
+    (5.279, [3.097, 0.4937, 0.13957], 1, [0.13957, 0.13957]),
+    (10.0, [0.13957, 1.5, 0.13957, 0.13957, 0.13957, 0.13957], 1, [0.13957, 0.13957, 0.13957, 0.13957]),
+    (10.0, [0.0] * 9 + [2.0], 9, [0.0, 0.0, 0.0]),
+    (4.0, [1.0, 2.0], 1, [0.5, 0.6, 0.1, 0.2]),
+]
+
+
+def _chain_reference(P, M, m, d, m2, nev, seed, off):
+    """The two single-channel calls the fused launch is defined by."""
+    ld = P.aligned_ld(nev)
+    o1 = torch.empty((len(m), 4, ld), dtype=torch.float64, device="cuda")
+    w1 = torch.empty(nev, dtype=torch.float64, device="cuda")
+    _, _, s1 = P.generate(M, m, nev, seed=seed, stream_id=3, event_offset=off, out=o1, weights=w1)
+    o2, w2, s2 = P.generate(m[d], m2, nev, seed=seed, stream_id=8, event_offset=off, parent_dev=o1[d])
+    torch.cuda.synchronize()
+    return (o1[:, :, :nev].cpu().numpy(), w1.cpu().numpy(), s1.cpu().numpy(), o2.cpu().numpy(),
+            w2.cpu().numpy(), s2.cpu().numpy())
+
+
+@pytest.mark.parametrize("case", range(len(CHAIN_CASES)))
+def test_chain_in_one_launch_equals_two_calls(P, case):
+    """The fused two-stage launch against the two calls it is defined by: both
+    stages' events and weights bit for bit, the integrals bit for bit when the
+    calls run one event per thread (as the fused launch does) and to rounding at
+    their defaults; the second stage against the oracle's chain."""
+    M, m, d, m2 = CHAIN_CASES[case]
+    _say(f"chain case {case}: N1={len(m)} chained {d} N2={len(m2)}")
+    nev, seed, off = 100_003, 17 + case, 5_000_000_007
+    r = P.generate_chain(M, m, d, m2, nev, seed=seed, stream_id=3, stream_id2=8, event_offset=off)
+    torch.cuda.synchronize()
+    got = [t.cpu().numpy() for t in r]
+    P.set_events_per_thread(1, 1)
+    try:
+        ref1 = _chain_reference(P, M, m, d, m2, nev, seed, off)
+    finally:
+        P.set_events_per_thread(1, 0)
+    for g, e in zip(got, ref1):
+        assert np.array_equal(g[..., :nev] if g.ndim == 3 else g, e)
+    ref = _chain_reference(P, M, m, d, m2, nev, seed, off)
+    for k in (0, 1, 3, 4):
+        assert np.array_equal(got[k], ref[k])
+    for k in (2, 5):
+        assert got[k][0] == ref[k][0] and rel(got[k][1], ref[k][1]) <= 1e-13
+        assert abs(got[k][3] - ref[k][3]) <= 1e-12 * ref[k][3] + 1e-15 * ref[k][1]  # two-body: sigma = 0
+    q1, v1 = oracle.generate(M, m, nev, seed=seed, stream_id=3, event_offset=off)
+    q2, v2 = oracle.generate(m[d], m2, nev, seed=seed, stream_id=8, event_offset=off,
+                             parent_soa=np.ascontiguousarray(q1[d]))
+    assert_events_close(got[0], got[1], q1, v1)
+    assert_events_close(got[3], got[4], q2, v2)
+
+
+def test_chain_off_the_line_grid_runs_the_two_calls(P):
+    """Columns that start mid-line (ld = n + 1): the library runs the two calls
+    (staged kernels); the result is theirs, bit for bit."""
+    _say("chain off the line grid")
+    M, m, d, m2 = CHAIN_CASES[0]
+    nev = 50_001
+    o1 = torch.empty((3, 4, nev + 1), dtype=torch.float64, device="cuda")
+    o2 = torch.empty((2, 4, nev + 1), dtype=torch.float64, device="cuda")
+    r = P.generate_chain(M, m, d, m2, nev, seed=5, stream_id=3, stream_id2=8, out=o1, out2=o2)
+    r1 = torch.empty_like(o1)
+    r2 = torch.empty_like(o2)
+    _, w1, s1 = P.generate(M, m, nev, seed=5, stream_id=3, out=r1)
+    _, w2, s2 = P.generate(m[d], m2, nev, seed=5, stream_id=8, parent_dev=r1[d], out=r2)
+    torch.cuda.synchronize()
+    for g, e in zip([r[0][:, :, :nev], r[1], r[2], r[3][:, :, :nev], r[4], r[5]],
+                    [r1[:, :, :nev], w1, s1, r2[:, :, :nev], w2, s2]):
+        assert torch.equal(g, e)
+
+
 @pytest.mark.parametrize("n", [2, 3, 6, 10])
 @pytest.mark.parametrize("mixed", [False, True])
 def test_line_aligned_and_staged_layouts_agree(P, n, mixed):

@@ -20,8 +20,10 @@
  *     (g mod 2^32, g div 2^32, call index, stream_id) for global event index
  *     g = event_offset + e.  Results depend only on (seed, stream_id, g), so
  *     chunked, sharded and resumed runs are bit-identical to a single run;
- *   - daughter 0 is the innermost; each two-body level adds the next daughter
- *     and boosts the earlier ones into the new frame.
+ *   - daughter 0 is the innermost: the masses of the subsystems {0..i} are
+ *     drawn first, then the levels run top down: level i splits {0..i+1} into
+ *     daughter i+1 and {0..i}, back to back in the rest frame of {0..i+1}, and
+ *     boosts both into the parent's rest frame (one boost per daughter).
  *
  * Memory: pointers named *_dev are device pointers (e.g. from torch tensors),
  * owned by the caller and left untouched outside the call; *_host pointers are

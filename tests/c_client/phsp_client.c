@@ -50,7 +50,41 @@ int main(int argc, char **argv) {
         MUST(hipMemcpy(&p4[0][c], out + (uint64_t)c * ld, sizeof(double), hipMemcpyDeviceToHost));
         MUST(hipMemcpy(&p4[1][c], out + (uint64_t)c * ld + (n - 1), sizeof(double), hipMemcpyDeviceToHost));
     }
+    /* the same first stage with daughter 0 decaying to two muons, in one launch */
+    const double mu2[2] = {0.1056583755, 0.1056583755};
+    double *out2 = NULL, *w2 = NULL, *stats2 = NULL, *half = NULL;
+    MUST(hipMalloc((void **)&out2, sizeof(double) * 8 * ld));
+    MUST(hipMalloc((void **)&w2, sizeof(double) * ld));
+    MUST(hipMalloc((void **)&stats2, sizeof(double) * HYDRA_PHSP_STATS));
+    MUST(hipMalloc((void **)&half, sizeof(double) * 2 * HYDRA_PHSP_STATS));
+    const int st_chain = hydra_phsp_generate_chain(M, masses, 3, 0, mu2, 2, n, seed, 0, 1, 0, out, ld, w, NULL, out2,
+                                                   ld, w2, stats2, NULL);
+    /* the integral in two pieces, merged on the host */
+    const uint64_t cut = n / 2;
+    const int st_a = hydra_phsp_integrate_async(M, masses, 3, cut, seed, 0, 0, half, NULL);
+    const int st_b = hydra_phsp_integrate_async(M, masses, 3, n - cut, seed, 0, cut, half + HYDRA_PHSP_STATS, NULL);
+    MUST(hipDeviceSynchronize());
+    double h[2 * HYDRA_PHSP_STATS], merged[HYDRA_PHSP_STATS], q[2][8], wq[2];
+    MUST(hipMemcpy(h, half, sizeof(h), hipMemcpyDeviceToHost));
+    const int st_merge = hydra_phsp_stats_merge(h, h + HYDRA_PHSP_STATS, merged);
+    MUST(hipMemcpy(&wq[0], w2, sizeof(double), hipMemcpyDeviceToHost));
+    MUST(hipMemcpy(&wq[1], w2 + (n - 1), sizeof(double), hipMemcpyDeviceToHost));
+    for (int c = 0; c < 8; ++c) {
+        MUST(hipMemcpy(&q[0][c], out2 + (uint64_t)c * ld, sizeof(double), hipMemcpyDeviceToHost));
+        MUST(hipMemcpy(&q[1][c], out2 + (uint64_t)c * ld + (n - 1), sizeof(double), hipMemcpyDeviceToHost));
+    }
     printf("status %d %d\n", st_gen, st_int);
+    printf("status2 %d %d %d %d\n", st_chain, st_a, st_b, st_merge);
+    printf("merged %.17g %.17g %.17g %.17g\n", merged[0], merged[1], merged[2], merged[3]);
+    for (int k = 0; k < 2; ++k) {
+        printf("chain %llu %.17g", (unsigned long long)(k == 0 ? 0 : n - 1), wq[k]);
+        for (int c = 0; c < 8; ++c) printf(" %.17g", q[k][c]);
+        printf("\n");
+    }
+    MUST(hipFree(out2));
+    MUST(hipFree(w2));
+    MUST(hipFree(stats2));
+    MUST(hipFree(half));
     printf("stats %.17g %.17g %.17g %.17g\n", s[0], s[1], s[2], s[3]);
     printf("integral %.17g %.17g\n", mean, sigma);
     for (int k = 0; k < 2; ++k) {
@@ -61,5 +95,8 @@ int main(int argc, char **argv) {
     MUST(hipFree(out));
     MUST(hipFree(w));
     MUST(hipFree(stats));
-    return st_gen == HYDRA_PHSP_OK && st_int == HYDRA_PHSP_OK ? 0 : 3;
+    return st_gen == HYDRA_PHSP_OK && st_int == HYDRA_PHSP_OK && st_chain == HYDRA_PHSP_OK && st_a == HYDRA_PHSP_OK &&
+                   st_b == HYDRA_PHSP_OK && st_merge == HYDRA_PHSP_OK
+               ? 0
+               : 3;
 }

@@ -47,14 +47,15 @@ def test_c_client_matches_oracle(tmp_path):
     r = subprocess.run([exe, str(n), str(seed)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     rows = {}
-    events = []
+    events, chain = [], []
     for line in r.stdout.splitlines():
         f = line.split()
-        if f[0] == "event":
-            events.append((int(f[1]), float(f[2]), np.array([float(x) for x in f[3:]])))
+        if f[0] in ("event", "chain"):
+            (events if f[0] == "event" else chain).append((int(f[1]), float(f[2]),
+                                                            np.array([float(x) for x in f[3:]])))
         else:
             rows[f[0]] = [float(x) for x in f[1:]]
-    assert rows["status"] == [0.0, 0.0]
+    assert rows["status"] == [0.0, 0.0] and rows["status2"] == [0.0, 0.0, 0.0, 0.0]
     M, m = 5.279, [3.097, 0.4937, 0.13957]
     oracle.build(force=False)
     mo, so = oracle.integrate(M, m, n, seed=seed)
@@ -67,4 +68,15 @@ def test_c_client_matches_oracle(tmp_path):
         po = p4o[:, :, 0]  # [3][4]
         for d in range(3):
             assert np.all(np.abs(p[4 * d:4 * d + 4] - po[d]) <= FP64_TOL * po[d][0]), (g, d)
+    # the integral merged from two pieces, and the second stage of the one-launch chain
+    mg = rows["merged"]
+    assert mg[0] == n and rel(mg[1], mo) <= FP64_TOL and rel(mg[3], so) <= FP64_TOL
+    mmu = 0.1056583755
+    for g, w, p in chain:
+        p4o, _ = oracle.generate(M, m, 1, seed=seed, event_offset=g)
+        q4o, wo = oracle.generate(m[0], [mmu, mmu], 1, seed=seed, stream_id=1, event_offset=g,
+                                  parent_soa=np.ascontiguousarray(p4o[0]))
+        assert rel(w, wo[0]) <= FP64_TOL
+        for d in range(2):
+            assert np.all(np.abs(p[4 * d:4 * d + 4] - q4o[d, :, 0]) <= FP64_TOL * q4o[d, 0, 0]), (g, d)
     sys.stdout.flush()

@@ -348,6 +348,7 @@ COUNTER_RUNS = {"headline": None,
                 "ten_pion_fp64": (10.0, [0.13957] * 10, 31_700_000, False),
                 "unweighted": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False),
                 "unweighted_pipeline": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False),
+                "chain": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False),
                 "integrate": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False),
                 "model": (5.279, [3.097, 0.4937, 0.13957], 100_000_000, False),
                 "vegas": None}
@@ -375,6 +376,14 @@ def counter_run(P, torch, dev, name):
     elif name == "model":
         one = [(1, 2, 0.8955, 0.0473)]  # the model extra's one-factor model: per-event values and integral
         fn = lambda: P.integrate_model(M, m, n, one, values=w, stats=st)  # noqa: E731
+    elif name == "chain":
+        # the sequential-decay extra in one launch: daughter 0 -> mu mu
+        out = torch.empty((len(m), 4, P.aligned_ld(n)), dtype=dtype, device=dev)
+        out2 = torch.empty((2, 4, P.aligned_ld(n)), dtype=dtype, device=dev)
+        w2 = torch.empty(n, dtype=torch.float64, device=dev)
+        st2 = torch.empty(4, dtype=torch.float64, device=dev)
+        fn = lambda: P.generate_chain(M, m, 0, [0.1056583755] * 2, n, out=out, weights=w, stats=st,  # noqa: E731
+                                      out2=out2, weights2=w2, stats2=st2)
     else:
         out = torch.empty((len(m), 4, P.aligned_ld(n)), dtype=dtype, device=dev)
         if name.startswith("unweighted"):

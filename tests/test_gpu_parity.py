@@ -227,6 +227,38 @@ def test_chain_in_one_launch_equals_two_calls(P, case):
     assert_events_close(got[3], got[4], q2, v2)
 
 
+@pytest.mark.parametrize("nev", [0, 1, 255, 257, 70_001])
+def test_chain_edge_sizes(P, nev):
+    """Empty, single-event and ragged launches of the one-launch chain: the
+    two calls' events, weights and integrals bit for bit (one event per
+    thread), and nothing written past nevents."""
+    _say(f"chain edge size {nev}")
+    M, m, d, m2 = CHAIN_CASES[1]
+    ld = P.aligned_ld(nev)
+    o1 = torch.full((3, 4, ld), float("nan"), dtype=torch.float64, device="cuda")
+    o2 = torch.full((3, 4, ld), float("nan"), dtype=torch.float64, device="cuda")
+    w1 = torch.full((ld,), float("nan"), dtype=torch.float64, device="cuda")
+    w2 = torch.full((ld,), float("nan"), dtype=torch.float64, device="cuda")
+    s1 = torch.empty(4, dtype=torch.float64, device="cuda")
+    s2 = torch.empty(4, dtype=torch.float64, device="cuda")
+    P.generate_chain(M, m, d, m2, nev, seed=9, stream_id=3, stream_id2=8, event_offset=123, out=o1, weights=w1,
+                     stats=s1, out2=o2, weights2=w2, stats2=s2)
+    torch.cuda.synchronize()
+    assert int(s1[0].item()) == nev and int(s2[0].item()) == nev
+    assert bool(torch.isnan(o1[:, :, nev:]).all()) and bool(torch.isnan(o2[:, :, nev:]).all())
+    assert bool(torch.isnan(w1[nev:]).all()) and bool(torch.isnan(w2[nev:]).all())
+    if nev == 0:
+        return
+    P.set_events_per_thread(1, 1)
+    try:
+        ref = _chain_reference(P, M, m, d, m2, nev, 9, 123)
+    finally:
+        P.set_events_per_thread(1, 0)
+    got = [o1[:, :, :nev], w1[:nev], s1, o2[:, :, :nev], w2[:nev], s2]
+    for g, e in zip(got, ref):
+        assert np.array_equal(g.cpu().numpy(), e)
+
+
 def test_chain_off_the_line_grid_runs_the_two_calls(P):
     """Columns that start mid-line (ld = n + 1): the library runs the two calls
     (staged kernels); the result is theirs, bit for bit."""
